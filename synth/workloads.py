@@ -1,0 +1,115 @@
+"""Seeded non-rigid workloads (template, camera, ground truth, targets).
+
+Recipe (stated once here and in the design notes):
+
+* Template: an ellipsoid with semi-axes (0.15, 0.5, 0.15) m (long axis along
+  the image's +y), centred 2.5 m in front of the camera.  The small case uses
+  an icosphere of subdivision level 4 (2,562 vertices, 5,120 faces); other
+  sizes use a Fibonacci-spiral hull with exactly the requested vertex count.
+* Vertex colours: i.i.d. uniform in [0, 1]^3 per vertex.
+* Camera: pinhole, square image of side S, focal length 2S, principal point
+  ((S-1)/2, (S-1)/2); world = camera frame (the paper's static camera).
+* Ground truth: a smooth deformation field owned by this generator.  It picks
+  ``n_ctrl`` control vertices at random, draws for each an axis-angle rotation
+  with i.i.d. N(0, 0.05^2) rad components and a translation with i.i.d.
+  N(0, 0.01^2) m components, and moves every vertex by the normalised
+  Gaussian-RBF blend (over all control points) of those rigid motions.  The
+  field is *not* expressed in the solver's deformation graph, so, as with real
+  footage, the targets are not exactly reachable by the solver.
+* Targets: mask and colour image rendered from the ground-truth mesh
+  (``synth.render``), background colour 0.
+"""
+from dataclasses import dataclass
+
+import numpy as np
+from scipy.spatial.transform import Rotation
+
+from .meshes import ellipsoid_icosphere, fibonacci_ellipsoid
+from .render import render_targets
+
+SEMI_AXES = (0.15, 0.5, 0.15)
+CENTRE = (0.0, 0.0, 2.5)
+
+
+@dataclass
+class Camera:
+    width: int
+    height: int
+    fx: float
+    fy: float
+    cx: float
+    cy: float
+
+    @staticmethod
+    def square(side):
+        f = float(2 * side)
+        c = (side - 1) / 2.0
+        return Camera(int(side), int(side), f, f, c, c)
+
+    def as_array(self):
+        return np.array([self.fx, self.fy, self.cx, self.cy], dtype=np.float32)
+
+
+# name -> recipe.  Weights are (w_sil, w_photo, w_arap); schedule is (GN, PCG).
+CONFIGS = {
+    # 2,562-vertex icosphere ellipsoid, 64 nodes, 256^2, 5 GN x 10 PCG.
+    "small": dict(mesh="ico4", n_vertices=2562, n_nodes=64, side=256, gn=5, pcg=10,
+                  weights=(1.0, 0.1, 10.0)),
+    # paper-shaped non-rigid frame: 20,000 vertices, 500 nodes, 1080^2, 3 GN x 8 PCG.
+    "frame20k": dict(mesh="fib", n_vertices=20000, n_nodes=500, side=1080, gn=3, pcg=8,
+                     weights=(1.0, 0.1, 10.0)),
+    # stress capture: 200,000 vertices, 4,000 nodes, 2048^2, 3 GN x 10 PCG.
+    "stress200k": dict(mesh="fib", n_vertices=200000, n_nodes=4000, side=2048, gn=3, pcg=10,
+                       weights=(1.0, 0.1, 10.0)),
+}
+
+
+def template_mesh(mesh, n_vertices):
+    if mesh == "ico4":
+        return ellipsoid_icosphere(4, SEMI_AXES, CENTRE)
+    return fibonacci_ellipsoid(n_vertices, SEMI_AXES, CENTRE)
+
+
+def smooth_field(xyz, n_ctrl, rng, rot_sigma=0.05, trans_sigma=0.01):
+    """Ground-truth deformation: normalised Gaussian-RBF blend of random rigid motions."""
+    p = xyz.T.astype(np.float64)
+    ctrl = rng.choice(p.shape[0], size=n_ctrl, replace=False)
+    c = p[ctrl]
+    rot = Rotation.from_rotvec(rng.normal(0.0, rot_sigma, size=(n_ctrl, 3)))
+    trans = rng.normal(0.0, trans_sigma, size=(n_ctrl, 3))
+    # kernel width: mean distance from a control point to its nearest other one
+    dcc = np.linalg.norm(c[:, None, :] - c[None, :, :], axis=2)
+    np.fill_diagonal(dcc, np.inf)
+    sigma = dcc.min(axis=1).mean()
+    out = np.zeros_like(p)
+    wsum = np.zeros(p.shape[0])
+    mats = rot.as_matrix()
+    for m in range(n_ctrl):
+        d2 = ((p - c[m]) ** 2).sum(axis=1)
+        w = np.exp(-d2 / (2.0 * sigma * sigma))
+        moved = (p - c[m]) @ mats[m].T + c[m] + trans[m]
+        out += w[:, None] * moved
+        wsum += w
+    out /= wsum[:, None]
+    return np.ascontiguousarray(out.T.astype(np.float32))
+
+
+def make_nonrigid_frame(name="small", seed=0, n_vertices=None, n_nodes=None, side=None):
+    """One non-rigid frame: template, camera, ground truth and rendered targets."""
+    cfg = dict(CONFIGS[name])
+    if n_vertices is not None:
+        cfg["n_vertices"] = n_vertices
+        cfg["mesh"] = "fib"
+    if n_nodes is not None:
+        cfg["n_nodes"] = n_nodes
+    if side is not None:
+        cfg["side"] = side
+    rng = np.random.Generator(np.random.PCG64(seed))
+    xyz, tri = template_mesh(cfg["mesh"], cfg["n_vertices"])
+    rgb = rng.uniform(0.0, 1.0, size=(3, xyz.shape[1])).astype(np.float32)
+    cam = Camera.square(cfg["side"])
+    gt = smooth_field(xyz, cfg["n_nodes"], rng)
+    mask, image = render_targets(gt, tri, rgb, cam)
+    return dict(name=name, seed=seed, xyz=xyz, tri=tri, rgb=rgb, cam=cam, gt_xyz=gt,
+                mask=mask, image=image, n_nodes=cfg["n_nodes"], gn=cfg["gn"], pcg=cfg["pcg"],
+                weights=cfg["weights"])
