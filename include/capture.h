@@ -1,0 +1,206 @@
+/*
+ * capture.h -- C ABI of the MI355X (gfx950) per-frame Gauss-Newton solvers
+ * for monocular human performance capture (LiveCap, Habermann et al.,
+ * ACM TOG 2019).
+ *
+ * Conventions shared by every entry point
+ *  - Array arguments are DEVICE pointers unless marked "host".  Multi-channel
+ *    arrays are structure-of-arrays: [3][n] means three planes of n values.
+ *    Images are row-major [H][W]; pixel (i, j) = (column, row) has its centre
+ *    at image coordinates (i, j).
+ *  - The caller owns every buffer.  The library never frees caller memory and
+ *    keeps no caller pointer past the call, except that a template keeps its
+ *    own device copy of the static data it derives (capture_template_create).
+ *  - Scratch memory comes from the caller's workspace (capture_workspace_size);
+ *    solves allocate nothing.
+ *  - `stream` is a hipStream_t passed as void*; NULL is the null stream.  Work
+ *    is enqueued on it; solve calls wait for it before returning (the report
+ *    is filled on return).
+ *  - Errors: negative return codes; capture_last_error() gives a message
+ *    (thread-local, valid until the next call on that thread).  Nothing
+ *    throws across the ABI.  Arguments are validated before any launch; on an
+ *    error return no output has been modified.
+ */
+#ifndef CAPTURE_H
+#define CAPTURE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#if defined(__GNUC__) || defined(__clang__)
+#define CAPTURE_API __attribute__((visibility("default")))
+#else
+#define CAPTURE_API
+#endif
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    CAPTURE_OK = 0,
+    CAPTURE_EINVAL = -1,       /* invalid argument (sizes, null pointers, non-manifold mesh) */
+    CAPTURE_ENOTSPD = -2,      /* a linear system was not positive definite */
+    CAPTURE_ENONFINITE = -3,   /* a non-finite value was found in inputs or results */
+    CAPTURE_EHIP = -4,         /* a HIP runtime call failed */
+    CAPTURE_ENOMEM = -5,       /* workspace too small, or template allocation failed */
+    CAPTURE_EUNSUPPORTED = -6  /* a size beyond a documented limit */
+};
+
+#define CAPTURE_BIND_K 4       /* nodes per vertex (embedded deformation binding) */
+#define CAPTURE_EDGE_K 8       /* out-edges per node (regulariser graph) */
+#define CAPTURE_MAX_GN 32      /* maximum Gauss-Newton steps per solve */
+
+typedef struct capture_ctx capture_ctx;
+typedef struct capture_template capture_template;
+
+/* Pinhole camera, world = camera frame (Sec. 3.2: static camera, camera and
+ * world space are the same): u = fx*X/Z + cx, v = fy*Y/Z + cy. */
+typedef struct {
+    int32_t width, height;
+    float fx, fy, cx, cy;
+} capture_camera;
+
+/* Open a context on HIP device `device`.  *ctx receives an opaque handle. */
+CAPTURE_API int capture_create(capture_ctx **ctx, int device);
+CAPTURE_API void capture_destroy(capture_ctx *ctx);
+CAPTURE_API const char *capture_last_error(void);
+
+/* --------------------------------------------------------------------------
+ * Deformation graph (embedded deformation nodes; the paper names this
+ * parameterisation as the alternative to per-vertex unknowns, Sec. 6).
+ *   xyz          [3][n_vertices]  rest positions (float32)
+ *   node_vertex  [n_nodes]        out: farthest-point samples, seeded at vertex
+ *                                 0, argmax ties -> lowest vertex index
+ *   bind_idx     [4][n_vertices]  out: 4 nearest nodes, ascending distance,
+ *                                 ties -> lower node index
+ *   bind_w       [4][n_vertices]  out: exp(-d^2 / (2 d4^2)) normalised to sum 1,
+ *                                 d4 = distance to the 4th-nearest node
+ *   edge_dst     [8][n_nodes]     out: 8 nearest other nodes (ties -> lower
+ *                                 index), -1 when fewer exist
+ * Squared distances use one float32 recipe ((dx*dx + dy*dy) + dz*dz) so the
+ * indices are reproducible bit for bit.  Requires 4 <= n_nodes <= n_vertices
+ * and n_nodes <= 65536.  Synchronous.
+ * ------------------------------------------------------------------------ */
+CAPTURE_API int capture_graph_build(capture_ctx *ctx, const float *xyz, int32_t n_vertices, int32_t n_nodes,
+                        int32_t *node_vertex, int32_t *bind_idx, float *bind_w, int32_t *edge_dst,
+                        void *stream);
+
+/* --------------------------------------------------------------------------
+ * Template: static mesh topology plus graph.  Creation reads the arrays once
+ * (device pointers), checks them (indices in range, edge-manifold mesh with
+ * each edge in one or two faces, binding weights finite) and builds the
+ * library's tiled execution plan in its own device memory.  Triangles wind
+ * counter-clockwise seen from outside.
+ *   nodes_per_tile / vertices_per_tile: 0 = library defaults (autotuned).
+ * ------------------------------------------------------------------------ */
+typedef struct {
+    int32_t n_vertices, n_triangles, n_nodes;
+    const int32_t *tri;          /* [3][n_triangles] */
+    const int32_t *node_vertex;  /* [n_nodes] */
+    const int32_t *bind_idx;     /* [4][n_vertices] */
+    const float *bind_w;         /* [4][n_vertices] */
+    const int32_t *edge_dst;     /* [8][n_nodes], -1 = no edge */
+    int32_t vertices_per_tile;   /* 0 = default (256); at most 256 */
+} capture_template_desc;
+
+CAPTURE_API int capture_template_create(capture_ctx *ctx, const capture_template_desc *desc,
+                            capture_template **out);
+CAPTURE_API void capture_template_destroy(capture_template *tmpl);
+
+/* One frame of the non-rigid stage (Sec. 3.4). */
+typedef struct {
+    const capture_template *tmpl;
+    const float *xyz;          /* [3][n_vertices] the frame's input mesh (e.g. the posed
+                                  template); graph node k sits at xyz[:, node_vertex[k]] */
+    const float *rgb;          /* [3][n_vertices] template vertex colours C, in [0, 1] */
+    capture_camera camera;
+    const uint8_t *mask;       /* [H][W] foreground silhouette, 0 = background */
+    const float *image;        /* [3][H][W] colour frame in [0, 1] */
+    float *node_state;         /* [12][n_nodes] in: start, out: solution; per node the
+                                  rotation R row-major (9 values) then translation t (3) */
+} capture_frame;
+
+/* Weights and schedule.  E = w_photo*sum||sigma_c(I_Gauss(pi(V_i)) - C_i)||^2
+ *  + w_sil*sum b_i I_DT(pi(V_i))^2 + w_arap*sum||R_k(g_l - g_k) + g_k + t_k - g_l - t_l||^2.
+ * tau_color: the photometric robust-kernel threshold (residual set to zero when
+ * the colour difference norm exceeds it); +inf or 0 disables it. */
+typedef struct {
+    float w_sil, w_photo, w_arap, tau_color;
+    int32_t gn_iters;          /* 1..CAPTURE_MAX_GN */
+    int32_t pcg_iters;         /* >= 0 Jacobi-PCG iterations per Gauss-Newton step */
+    uint32_t flags;            /* reserved, 0 */
+} capture_nonrigid_params;
+
+/* Host-side report of one solve. */
+typedef struct {
+    double energy[CAPTURE_MAX_GN + 1];    /* E at the start of each GN step, then the final E */
+    double e_photo, e_sil, e_sil_abs, e_arap;  /* final per-term energies (e_sil_abs: with |b_i|) */
+    int32_t n_visible, n_boundary;        /* |visible set|, |contour set| */
+    int32_t gn_done;                      /* Gauss-Newton steps taken */
+    int32_t status;                       /* CAPTURE_OK or a device-detected error */
+} capture_report;
+
+/* Workspace bytes for solving the `n` frames together (n = 1 for a single
+ * frame).  Frames are host structs; their arrays are not read. */
+CAPTURE_API int capture_workspace_size(capture_ctx *ctx, int32_t n, const capture_frame *frames, size_t *bytes);
+
+/* Non-rigid Gauss-Newton solve of one frame (Sec. 3.4 energy, Sec. 4 solver:
+ * J^T J delta = -J^T F with J^T J applied matrix-free and solved by
+ * Jacobi-preconditioned CG, fixed iteration counts).  The once-per-frame
+ * decisions (visible set by depth buffering, contour set B, direction signs
+ * b_i) are taken at the start state.  `report` is host memory. */
+CAPTURE_API int capture_nonrigid_solve(capture_ctx *ctx, const capture_frame *frame,
+                           const capture_nonrigid_params *params, capture_report *report,
+                           void *workspace, size_t workspace_bytes, void *stream);
+
+/* The same solve for `n` independent frames of possibly different sizes in one
+ * sequence of batched launches.  `frames` and `reports` are host arrays of n;
+ * all frames share `params`. */
+CAPTURE_API int capture_batch_solve(capture_ctx *ctx, int32_t n, const capture_frame *frames,
+                        const capture_nonrigid_params *params, capture_report *reports,
+                        void *workspace, size_t workspace_bytes, void *stream);
+
+/* --------------------------------------------------------------------------
+ * Stage entry points: the per-frame preprocessing and one linearisation, with
+ * their intermediate results, for callers that need them (and for checking).
+ * All outputs are caller-allocated device arrays; any may be NULL.
+ * ------------------------------------------------------------------------ */
+
+/* Per-frame preprocessing at the frame's node_state (Sec. 3.2 distance
+ * transform, Sec. 3.4 blurred image, visibility, contour set, signs):
+ *   dt        [H][W] float   Euclidean distance (px) to the nearest contour pixel
+ *   blurred   [3][H][W]      Gaussian blur (kernel 3, sigma 0.8, clamp-to-edge)
+ *   zbuf      [H][W] uint32  float bits of the largest inverse depth, 0 = empty
+ *   vflags    [n_vertices] uint8: bit0 visible, bit1 contour set B, bit2 b_i = -1 */
+CAPTURE_API int capture_frame_decisions(capture_ctx *ctx, const capture_frame *frame, float *dt, float *blurred,
+                            uint32_t *zbuf, uint8_t *vflags, void *workspace, size_t workspace_bytes,
+                            void *stream);
+
+/* One linearisation at the frame's node_state (decisions taken at the same
+ * state), then the matrix-free product:
+ *   rhs   [6][n_nodes]  -J^T B F per node (dw_x, dw_y, dw_z, dt_x, dt_y, dt_z)
+ *   diag  [6][n_nodes]  diagonal of J^T |B| J
+ *   p     [6][n_nodes]  input direction (may be NULL: no product)
+ *   Ap    [6][n_nodes]  out: J^T |B| J p
+ *   energy (host, 4 doubles): photo, sil (with b_i), sil with |b_i|, arap */
+CAPTURE_API int capture_linearize(capture_ctx *ctx, const capture_frame *frame, const capture_nonrigid_params *params,
+                      float *rhs, float *diag, const float *p, float *Ap, double *energy,
+                      void *workspace, size_t workspace_bytes, void *stream);
+
+/* --------------------------------------------------------------------------
+ * Kernel timing.  While enabled, every launch of the solver kernels is
+ * bracketed by HIP events on the call's stream; elapsed times accumulate per
+ * kernel until read.  Kernel names: "blur", "contour", "dt_cols", "dt_rows",
+ * "deform_start", "raster", "contour_edges", "decide", "linearize",
+ * "node_init", "apply", "node_pcg".
+ * ------------------------------------------------------------------------ */
+CAPTURE_API int capture_profile_enable(capture_ctx *ctx, int on);
+/* Accumulated time (ms) and launch count of `kernel` since the last read;
+ * resets that kernel's counters. */
+CAPTURE_API int capture_profile_read(capture_ctx *ctx, const char *kernel, double *total_ms, int64_t *launches);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

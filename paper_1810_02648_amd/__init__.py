@@ -1,0 +1,216 @@
+"""MI355X-native per-frame Gauss-Newton solvers (LiveCap non-rigid stage).
+
+Thin Python binding over the C ABI in ``libcapture.so`` (include/capture.h).
+PyTorch only provides device memory and the stream: every step of the solve
+runs in the library's HIP kernels.  Nothing here computes on the CPU; if the
+library is missing, calls fail loudly.
+"""
+import ctypes as C
+import math
+
+import torch
+
+from . import capi
+from .capi import CaptureError  # noqa: F401
+
+__all__ = ["Context", "Template", "FrameInputs", "graph_build", "CaptureError"]
+
+
+def _ptr(t):
+    return C.c_void_p(t.data_ptr()) if t is not None else C.c_void_p(None)
+
+
+def _stream():
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _need(t, dtype, shape, name):
+    if not (t.is_cuda and t.dtype == dtype and t.is_contiguous() and tuple(t.shape) == tuple(shape)):
+        raise ValueError("%s must be a contiguous CUDA %s tensor of shape %s (got %s %s %s)"
+                         % (name, dtype, tuple(shape), t.device, t.dtype, tuple(t.shape)))
+
+
+class Context:
+    """A library context on one device (owns nothing but the device id)."""
+
+    def __init__(self, device=0):
+        self.lib = capi.load()
+        self.device = device
+        h = C.c_void_p()
+        capi.check(self.lib.capture_create(C.byref(h), device))
+        self.h = h
+        self._ws = None
+
+    def close(self):
+        if self.h:
+            self.lib.capture_destroy(self.h)
+            self.h = None
+
+    def workspace(self, nbytes):
+        """A device byte buffer of at least nbytes (kept and reused)."""
+        if self._ws is None or self._ws.numel() < nbytes:
+            self._ws = torch.empty(max(nbytes, 256), dtype=torch.uint8, device="cuda:%d" % self.device)
+        return self._ws
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def graph_build(ctx, xyz, n_nodes):
+    """Farthest-point nodes, 4-nearest binding and 8-nearest node edges."""
+    nv = xyz.shape[1]
+    _need(xyz, torch.float32, (3, nv), "xyz")
+    dev = xyz.device
+    g = dict(node_vertex=torch.empty(n_nodes, dtype=torch.int32, device=dev),
+             bind_idx=torch.empty((4, nv), dtype=torch.int32, device=dev),
+             bind_w=torch.empty((4, nv), dtype=torch.float32, device=dev),
+             edge_dst=torch.empty((8, n_nodes), dtype=torch.int32, device=dev))
+    capi.check(ctx.lib.capture_graph_build(ctx.h, _ptr(xyz), nv, n_nodes, _ptr(g["node_vertex"]),
+                                           _ptr(g["bind_idx"]), _ptr(g["bind_w"]), _ptr(g["edge_dst"]),
+                                           _stream()))
+    return g
+
+
+class Template:
+    """Mesh topology plus deformation graph, planned for the device."""
+
+    def __init__(self, ctx, tri, graph, vertices_per_tile=0):
+        nf = tri.shape[1]
+        nv = graph["bind_idx"].shape[1]
+        nn = graph["node_vertex"].shape[0]
+        _need(tri, torch.int32, (3, nf), "tri")
+        _need(graph["node_vertex"], torch.int32, (nn,), "node_vertex")
+        _need(graph["bind_idx"], torch.int32, (4, nv), "bind_idx")
+        _need(graph["bind_w"], torch.float32, (4, nv), "bind_w")
+        _need(graph["edge_dst"], torch.int32, (8, nn), "edge_dst")
+        self.ctx = ctx
+        self.nv, self.nf, self.nn = nv, nf, nn
+        d = capi.TemplateDesc(nv, nf, nn, _ptr(tri), _ptr(graph["node_vertex"]), _ptr(graph["bind_idx"]),
+                              _ptr(graph["bind_w"]), _ptr(graph["edge_dst"]), vertices_per_tile)
+        h = C.c_void_p()
+        capi.check(ctx.lib.capture_template_create(ctx.h, C.byref(d), C.byref(h)))
+        self.h = h
+
+    def __del__(self):
+        try:
+            if self.h:
+                self.ctx.lib.capture_template_destroy(self.h)
+                self.h = None
+        except Exception:
+            pass
+
+
+class FrameInputs:
+    """Device tensors of one frame (see capture_frame)."""
+
+    def __init__(self, template, xyz, rgb, camera, mask, image, node_state):
+        nv, nn = template.nv, template.nn
+        W, H = int(camera.width), int(camera.height)
+        _need(xyz, torch.float32, (3, nv), "xyz")
+        _need(rgb, torch.float32, (3, nv), "rgb")
+        _need(mask, torch.uint8, (H, W), "mask")
+        _need(image, torch.float32, (3, H, W), "image")
+        _need(node_state, torch.float32, (12, nn), "node_state")
+        self.template, self.xyz, self.rgb, self.mask, self.image, self.node_state = (
+            template, xyz, rgb, mask, image, node_state)
+        self.camera = capi.Camera(W, H, float(camera.fx), float(camera.fy), float(camera.cx), float(camera.cy))
+
+    def struct(self):
+        return capi.Frame(self.template.h, _ptr(self.xyz), _ptr(self.rgb), self.camera, _ptr(self.mask),
+                          _ptr(self.image), _ptr(self.node_state))
+
+
+def params(w_sil=1.0, w_photo=0.1, w_arap=10.0, gn_iters=5, pcg_iters=10, tau_color=math.inf):
+    return capi.NonrigidParams(w_sil, w_photo, w_arap, tau_color, gn_iters, pcg_iters, 0)
+
+
+def _frames(frames):
+    arr = (capi.Frame * len(frames))()
+    for i, f in enumerate(frames):
+        arr[i] = f.struct()
+    return arr
+
+
+def workspace_bytes(ctx, frames):
+    arr = _frames(frames)
+    n = C.c_size_t()
+    capi.check(ctx.lib.capture_workspace_size(ctx.h, len(frames), arr, C.byref(n)))
+    return n.value
+
+
+def _report_dict(r, gn):
+    return dict(energy=[r.energy[k] for k in range(gn + 1)], e_photo=r.e_photo, e_sil=r.e_sil,
+                e_sil_abs=r.e_sil_abs, e_arap=r.e_arap, n_visible=r.n_visible,
+                n_boundary=r.n_boundary, gn_done=r.gn_done, status=r.status)
+
+
+def batch_solve(ctx, frames, prm):
+    """Solve every frame in place (node_state); returns one report dict per frame."""
+    arr = _frames(frames)
+    nbytes = workspace_bytes(ctx, frames)
+    ws = ctx.workspace(nbytes)
+    reps = (capi.Report * len(frames))()
+    capi.check(ctx.lib.capture_batch_solve(ctx.h, len(frames), arr, C.byref(prm), reps, _ptr(ws),
+                                           ws.numel(), _stream()))
+    return [_report_dict(reps[i], prm.gn_iters) for i in range(len(frames))]
+
+
+def nonrigid_solve(ctx, frame, prm):
+    arr = _frames([frame])
+    ws = ctx.workspace(workspace_bytes(ctx, [frame]))
+    rep = capi.Report()
+    capi.check(ctx.lib.capture_nonrigid_solve(ctx.h, arr, C.byref(prm), C.byref(rep), _ptr(ws), ws.numel(),
+                                              _stream()))
+    return _report_dict(rep, prm.gn_iters)
+
+
+def frame_decisions(ctx, frame):
+    """Per-frame preprocessing outputs: dt, blurred, zbuf, vflags (device tensors)."""
+    arr = _frames([frame])
+    ws = ctx.workspace(workspace_bytes(ctx, [frame]))
+    H, W = frame.camera.height, frame.camera.width
+    dev = frame.xyz.device
+    out = dict(dt=torch.empty((H, W), dtype=torch.float32, device=dev),
+               blurred=torch.empty((3, H, W), dtype=torch.float32, device=dev),
+               zbuf=torch.empty((H, W), dtype=torch.int32, device=dev),
+               vflags=torch.empty(frame.template.nv, dtype=torch.uint8, device=dev))
+    capi.check(ctx.lib.capture_frame_decisions(ctx.h, arr, _ptr(out["dt"]), _ptr(out["blurred"]),
+                                               _ptr(out["zbuf"]), _ptr(out["vflags"]), _ptr(ws), ws.numel(),
+                                               _stream()))
+    return out
+
+
+def linearize(ctx, frame, prm, p=None):
+    """rhs, diag (and A p) at the frame's node_state, plus the 4 energy terms."""
+    arr = _frames([frame])
+    ws = ctx.workspace(workspace_bytes(ctx, [frame]))
+    nn = frame.template.nn
+    dev = frame.xyz.device
+    rhs = torch.empty((6, nn), dtype=torch.float32, device=dev)
+    diag = torch.empty((6, nn), dtype=torch.float32, device=dev)
+    Ap = torch.empty((6, nn), dtype=torch.float32, device=dev) if p is not None else None
+    if p is not None:
+        _need(p, torch.float32, (6, nn), "p")
+    e = (C.c_double * 4)()
+    capi.check(ctx.lib.capture_linearize(ctx.h, arr, C.byref(prm), _ptr(rhs), _ptr(diag), _ptr(p), _ptr(Ap), e,
+                                         _ptr(ws), ws.numel(), _stream()))
+    return dict(rhs=rhs, diag=diag, Ap=Ap, energy=list(e))
+
+
+def profile_enable(ctx, on=True):
+    """Bracket every solver-kernel launch with HIP events (see capture_profile_enable)."""
+    capi.check(ctx.lib.capture_profile_enable(ctx.h, 1 if on else 0))
+
+
+def profile_read(ctx):
+    """{kernel: (total_ms, launches)} since the last read; resets the counters."""
+    out = {}
+    for name in capi.KERNELS:
+        ms = C.c_double()
+        n = C.c_int64()
+        capi.check(ctx.lib.capture_profile_read(ctx.h, name.encode(), C.byref(ms), C.byref(n)))
+        out[name] = (ms.value, n.value)
+    return out

@@ -1,0 +1,92 @@
+"""ctypes declarations of libcapture.so (mirrors include/capture.h)."""
+import ctypes as C
+import os
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libcapture.so")
+
+MAX_GN = 32
+STATUS = {0: "CAPTURE_OK", -1: "CAPTURE_EINVAL", -2: "CAPTURE_ENOTSPD", -3: "CAPTURE_ENONFINITE",
+          -4: "CAPTURE_EHIP", -5: "CAPTURE_ENOMEM", -6: "CAPTURE_EUNSUPPORTED"}
+
+
+class Camera(C.Structure):
+    _fields_ = [("width", C.c_int32), ("height", C.c_int32), ("fx", C.c_float), ("fy", C.c_float),
+                ("cx", C.c_float), ("cy", C.c_float)]
+
+
+class TemplateDesc(C.Structure):
+    _fields_ = [("n_vertices", C.c_int32), ("n_triangles", C.c_int32), ("n_nodes", C.c_int32),
+                ("tri", C.c_void_p), ("node_vertex", C.c_void_p), ("bind_idx", C.c_void_p),
+                ("bind_w", C.c_void_p), ("edge_dst", C.c_void_p), ("vertices_per_tile", C.c_int32)]
+
+
+class Frame(C.Structure):
+    _fields_ = [("tmpl", C.c_void_p), ("xyz", C.c_void_p), ("rgb", C.c_void_p), ("camera", Camera),
+                ("mask", C.c_void_p), ("image", C.c_void_p), ("node_state", C.c_void_p)]
+
+
+class NonrigidParams(C.Structure):
+    _fields_ = [("w_sil", C.c_float), ("w_photo", C.c_float), ("w_arap", C.c_float),
+                ("tau_color", C.c_float), ("gn_iters", C.c_int32), ("pcg_iters", C.c_int32),
+                ("flags", C.c_uint32)]
+
+
+class Report(C.Structure):
+    _fields_ = [("energy", C.c_double * (MAX_GN + 1)), ("e_photo", C.c_double), ("e_sil", C.c_double),
+                ("e_sil_abs", C.c_double), ("e_arap", C.c_double), ("n_visible", C.c_int32),
+                ("n_boundary", C.c_int32), ("gn_done", C.c_int32), ("status", C.c_int32)]
+
+
+_P = C.c_void_p
+SIGNATURES = {
+    "capture_create": (C.c_int, [C.POINTER(C.c_void_p), C.c_int]),
+    "capture_destroy": (None, [_P]),
+    "capture_last_error": (C.c_char_p, []),
+    "capture_graph_build": (C.c_int, [_P, _P, C.c_int32, C.c_int32, _P, _P, _P, _P, _P]),
+    "capture_template_create": (C.c_int, [_P, C.POINTER(TemplateDesc), C.POINTER(C.c_void_p)]),
+    "capture_template_destroy": (None, [_P]),
+    "capture_workspace_size": (C.c_int, [_P, C.c_int32, C.POINTER(Frame), C.POINTER(C.c_size_t)]),
+    "capture_nonrigid_solve": (C.c_int, [_P, C.POINTER(Frame), C.POINTER(NonrigidParams), C.POINTER(Report),
+                                         _P, C.c_size_t, _P]),
+    "capture_batch_solve": (C.c_int, [_P, C.c_int32, C.POINTER(Frame), C.POINTER(NonrigidParams),
+                                      C.POINTER(Report), _P, C.c_size_t, _P]),
+    "capture_frame_decisions": (C.c_int, [_P, C.POINTER(Frame), _P, _P, _P, _P, _P, C.c_size_t, _P]),
+    "capture_linearize": (C.c_int, [_P, C.POINTER(Frame), C.POINTER(NonrigidParams), _P, _P, _P, _P,
+                                    C.POINTER(C.c_double), _P, C.c_size_t, _P]),
+    "capture_profile_enable": (C.c_int, [_P, C.c_int]),
+    "capture_profile_read": (C.c_int, [_P, C.c_char_p, C.POINTER(C.c_double), C.POINTER(C.c_int64)]),
+}
+
+KERNELS = ("blur", "contour", "dt_cols", "dt_rows", "deform_start", "raster", "contour_edges", "decide",
+           "linearize", "node_init", "apply", "node_pcg")
+
+_lib = None
+
+
+def load():
+    """Load libcapture.so; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError("libcapture.so is not built (run __graft_entry__.build() or "
+                              "python paper_1810_02648_amd/build.py): %s" % LIB_PATH)
+        lib = C.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            fn = getattr(lib, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = lib
+    return _lib
+
+
+class CaptureError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("%s (%d): %s" % (STATUS.get(code, "?"), code, msg))
+        self.code = code
+
+
+def check(code):
+    if code != 0:
+        msg = load().capture_last_error()
+        raise CaptureError(code, msg.decode() if msg else "")
+    return code

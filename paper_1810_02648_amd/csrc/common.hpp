@@ -1,0 +1,132 @@
+// Shared host/device declarations of the capture library.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "../../include/capture.h"
+
+namespace cap {
+
+// ---------------------------------------------------------------- errors
+void set_error(const std::string &msg);
+int fail(int code, const std::string &msg);
+
+#define CAP_HIP(expr)                                                                        \
+    do {                                                                                     \
+        hipError_t e_ = (expr);                                                              \
+        if (e_ != hipSuccess)                                                                \
+            return ::cap::fail(CAPTURE_EHIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+// ---------------------------------------------------------------- plan limits
+constexpr int kTileThreads = 256;     // threads of a tile workgroup (one vertex each)
+constexpr int kMaxTileVerts = 256;    // vertices per tile
+constexpr int kMaxTileContrib = 1024; // contributions held in LDS per tile
+constexpr int kMaxTileSlots = 200;    // distinct nodes touched by a tile
+constexpr int kNodeThreads = 1024;    // threads of a per-problem node workgroup
+constexpr int kMaxImageSide = 4096;
+constexpr int kScalars = 8 + 4 * (CAPTURE_MAX_GN + 1);
+
+// Static per-template data in library-owned device memory (plan order =
+// vertices grouped by their nearest node, nodes in breadth-first order of the
+// node graph; tiles are contiguous ranges of the plan order).
+struct TemplateDev {
+    int nv, nf, nn, ntiles, nslots, nmedges, max_slots, max_contrib;
+    const int *tri;            // [3][nf]
+    const int *node_vertex;    // [nn]
+    const int *bind_idx;       // [4][nv] (vertex order)
+    const float *bind_w;       // [4][nv] (vertex order)
+    const int *edge_dst;       // [8][nn]
+    const int *plan_vid;       // [nv] plan position -> vertex
+    const int *plan_pos;       // [nv] vertex -> plan position
+    const float *plan_w;       // [4][nv] binding weights in plan order
+    const uint32_t *plan_slot; // [nv] 4 tile-local slot indices (u8 each)
+    const int *tile_vbeg;      // [ntiles+1]
+    const int *tile_sbeg;      // [ntiles+1] into slot_node / partials
+    const int *slot_node;      // [nslots]
+    const int *tile_obeg;      // [ntiles+1] into owned_*
+    const int *owned_node;     // [nn]
+    const uint8_t *owned_slot; // [nn]
+    const uint8_t *owned_eslot;// [8][nn] slot of each out-edge target, 255 = none
+    const int *list_beg;       // [nslots+1] into list_idx
+    const uint16_t *list_idx;  // tile-local contribution indices, grouped by slot
+    const int *node_pbeg;      // [nn+1] into node_pidx
+    const int *node_pidx;      // global slot indices (partials) of each node, tile order
+    const int *vf_beg;         // [nv+1] vertex -> incident faces
+    const int *vf_face;        // [3nf] ascending per vertex
+    const int *medge;          // [4][nmedges]: a, b, f0, f1 (-1 = border)
+};
+
+// One problem (frame) of a batch: template, frame inputs and its workspace.
+struct ProbDev {
+    TemplateDev T;
+    const float *xyz;
+    const float *rgb;
+    const uint8_t *mask;
+    const float *image;
+    float *state;
+    int W, H;
+    float fx, fy, cx, cy;
+    float sw_sil, sw_photo, sw_arap, w_arap, tau;
+    // images
+    float *blur_tmp, *blurred, *dt;
+    int *colg;
+    uint32_t *zbuf;
+    uint8_t *contour;
+    // vertices (vertex order)
+    float *dx;        // [3][nv] deformed position at the start state (float32 recipe)
+    float *duv;       // [2][nv]
+    int *dfix;        // [2][nv] 1/256-pixel fixed point
+    uint8_t *dvalid;  // [nv]
+    uint8_t *vcont;   // [nv]
+    uint8_t *vflags;  // [nv] bit0 visible, bit1 contour set, bit2 b_i = -1
+    // faces
+    float *fcross;    // [3][nf]
+    // vertices (plan order)
+    float *px;        // [3][nv]
+    float *pc;        // [3][nv]
+    uint8_t *vcode;   // [nv]
+    float *Hm;        // [6][nv]
+    // tiles / slots
+    float *partial;   // [nslots][12]
+    double *tile_e;   // [ntiles][4]
+    // nodes
+    float *b, *diag, *dinv, *x, *r, *z, *p, *Ap;   // [6][nn]
+    double *scal;     // [kScalars]: rz, done, ..., energies [4] per GN step
+    int *counts;      // [2]
+    float *state0;    // [12][nn] copy of the start state (restored on a device-detected error)
+};
+
+// Optional per-kernel timing with HIP events (capture_profile_*).
+enum KernelId {
+    K_BLUR, K_CONTOUR, K_DT_COLS, K_DT_ROWS, K_DEFORM, K_RASTER, K_CEDGES, K_DECIDE,
+    K_LIN, K_NODE_INIT, K_APPLY, K_NODE_PCG, K_COUNT
+};
+
+struct Profiler {
+    bool on = false;
+    std::vector<hipEvent_t> ev;
+    size_t used = 0;
+    std::vector<std::pair<int, size_t>> pending;
+    double total_ms[K_COUNT] = {};
+    long long launches[K_COUNT] = {};
+};
+
+}  // namespace cap
+
+struct capture_ctx {
+    int device;
+    cap::Profiler prof;
+};
+
+struct capture_template {
+    cap::TemplateDev dev;
+    void *mem;
+    size_t bytes;
+    int device;
+};

@@ -1,0 +1,126 @@
+// Device helpers shared by the kernels (compiled with -ffp-contract=off: every
+// float operation below rounds on its own, in the order written).
+#pragma once
+
+#include "common.hpp"
+
+namespace cap {
+
+// Cubic-convolution (Keys, a = -0.5) weights for offsets -1..2 and their
+// derivatives, in the fixed float32 operation order that the integer
+// decisions rely on.
+__device__ inline void keys_weights(float f, float w[4], float d[4]) {
+    const float h = 0.5f;
+    float f2 = f * f;
+    float f3 = f2 * f;
+    w[0] = ((2.0f * f2 - f3) - f) * h;
+    w[1] = ((3.0f * f3 - 5.0f * f2) + 2.0f) * h;
+    w[2] = ((4.0f * f2 - 3.0f * f3) + f) * h;
+    w[3] = (f3 - f2) * h;
+    d[0] = ((4.0f * f - 3.0f * f2) - 1.0f) * h;
+    d[1] = (9.0f * f2 - 10.0f * f) * h;
+    d[2] = ((8.0f * f - 9.0f * f2) + 1.0f) * h;
+    d[3] = (3.0f * f2 - 2.0f * f) * h;
+}
+
+// Value and gradient of the cubic interpolant of a [H][W] float image at the
+// point (ix + fx, iy + fy) (integer cell, fraction in [0, 1)), clamp-to-edge.
+// Rows are accumulated n = 0..3, then m = 0..3.
+__device__ inline float sample_cubic_cell(const float *__restrict__ img, int W, int H, int ix, float fx, int iy,
+                                          float fy, float &gu, float &gv) {
+    float wx[4], dx[4], wy[4], dy[4];
+    keys_weights(fx, wx, dx);
+    keys_weights(fy, wy, dy);
+    int xs[4];
+#pragma unroll
+    for (int n = 0; n < 4; ++n) xs[n] = min(max(ix + n - 1, 0), W - 1);
+    float val = 0.0f, gx = 0.0f, gy = 0.0f;
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+        const float *row = img + size_t(min(max(iy + m - 1, 0), H - 1)) * W;
+        float rx = 0.0f, rv = 0.0f;
+#pragma unroll
+        for (int n = 0; n < 4; ++n) {
+            float t = row[xs[n]];
+            rx = rx + dx[n] * t;
+            rv = rv + wx[n] * t;
+        }
+        gx = gx + wy[m] * rx;
+        gy = gy + dy[m] * rv;
+        val = val + wy[m] * rv;
+    }
+    gu = gx;
+    gv = gy;
+    return val;
+}
+
+// Float32 position: cell = floor(u), fraction = u - floor(u) (the decision recipe).
+__device__ inline float sample_cubic(const float *__restrict__ img, int W, int H, float u, float v, float &gu,
+                                     float &gv) {
+    const float fu = floorf(u), fv = floorf(v);
+    return sample_cubic_cell(img, W, H, int(fu), u - fu, int(fv), v - fv, gu, gv);
+}
+
+// Three channels of a [3][H][W] image sharing the stencil.
+__device__ inline void sample_cubic3_cell(const float *__restrict__ img, int W, int H, int ix, float fx, int iy,
+                                          float fy, float val[3], float gu[3], float gv[3]) {
+    float wx[4], dx[4], wy[4], dy[4];
+    keys_weights(fx, wx, dx);
+    keys_weights(fy, wy, dy);
+    int xs[4];
+#pragma unroll
+    for (int n = 0; n < 4; ++n) xs[n] = min(max(ix + n - 1, 0), W - 1);
+    const size_t plane = size_t(W) * H;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) { val[c] = 0.0f; gu[c] = 0.0f; gv[c] = 0.0f; }
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+        size_t ro = size_t(min(max(iy + m - 1, 0), H - 1)) * W;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const float *row = img + c * plane + ro;
+            float rx = 0.0f, rv = 0.0f;
+#pragma unroll
+            for (int n = 0; n < 4; ++n) {
+                float t = row[xs[n]];
+                rx = rx + dx[n] * t;
+                rv = rv + wx[n] * t;
+            }
+            gu[c] = gu[c] + wy[m] * rx;
+            gv[c] = gv[c] + dy[m] * rv;
+            val[c] = val[c] + wy[m] * rv;
+        }
+    }
+}
+
+__device__ inline void cross3(const float a[3], const float b[3], float c[3]) {
+    c[0] = a[1] * b[2] - a[2] * b[1];
+    c[1] = a[2] * b[0] - a[0] * b[2];
+    c[2] = a[0] * b[1] - a[1] * b[0];
+}
+
+// Cell and float32 fraction of a float64 image coordinate (clamped far outside).
+__device__ inline void cell_of(double u, int &i, float &f) {
+    u = fmin(fmax(u, -1.0e6), 1.0e6);
+    const double fl = floor(u);
+    i = int(fl);
+    f = float(u - fl);
+    if (f >= 1.0f) f = 0.99999994f;
+}
+
+// Deterministic block-wide sum of a double (fixed tree over threads).
+template <int NT>
+__device__ inline double block_sum(double v, double *sh) {
+    sh[threadIdx.x] = v;
+    __syncthreads();
+#pragma unroll
+    for (int s = NT / 2; s > 0; s >>= 1) {
+        if (int(threadIdx.x) < s) sh[threadIdx.x] += sh[threadIdx.x + s];
+        __syncthreads();
+    }
+    double r = sh[0];
+    __syncthreads();
+    return r;
+}
+
+}  // namespace cap

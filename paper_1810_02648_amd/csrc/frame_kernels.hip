@@ -1,0 +1,283 @@
+// Once-per-frame kernels: blurred image, distance transform, depth buffer,
+// visibility, contour vertices and direction signs (Sec. 3.2-3.4).  Every
+// launch covers a whole batch: blockIdx.y selects the problem, blocks beyond
+// the problem's own extent return at once.
+#include "device.hpp"
+
+namespace cap {
+
+// ---------------------------------------------------------------- fills
+__global__ void k_fill_u32(uint32_t *p, size_t n, uint32_t v) {
+    size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    for (; i < n; i += size_t(gridDim.x) * blockDim.x) p[i] = v;
+}
+
+// ---------------------------------------------------------------- blur
+// Separable Gaussian (kernel 3), clamp-to-edge; pass 0 horizontal, 1 vertical.
+__global__ void k_blur(const ProbDev *__restrict__ P, int pass, float w0, float w1) {
+    const ProbDev &pr = P[blockIdx.y];
+    const int W = pr.W, H = pr.H;
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= W * H) return;
+    int y = i / W, x = i - y * W;
+    const size_t plane = size_t(W) * H;
+    const float *src = pass == 0 ? pr.image : pr.blur_tmp;
+    float *dst = pass == 0 ? pr.blur_tmp : pr.blurred;
+    for (int c = 0; c < 3; ++c) {
+        const float *s = src + c * plane;
+        float a, b, d;
+        if (pass == 0) {
+            a = s[size_t(y) * W + max(x - 1, 0)];
+            b = s[size_t(y) * W + x];
+            d = s[size_t(y) * W + min(x + 1, W - 1)];
+        } else {
+            a = s[size_t(max(y - 1, 0)) * W + x];
+            b = s[size_t(y) * W + x];
+            d = s[size_t(min(y + 1, H - 1)) * W + x];
+        }
+        dst[c * plane + i] = (w0 * a + w1 * b) + w0 * d;
+    }
+}
+
+// ---------------------------------------------------------------- distance transform
+// Contour pixels: foreground with a background 4-neighbour (outside = background).
+__global__ void k_contour(const ProbDev *__restrict__ P) {
+    const ProbDev &pr = P[blockIdx.y];
+    const int W = pr.W, H = pr.H;
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= W * H) return;
+    int y = i / W, x = i - y * W;
+    const uint8_t *m = pr.mask;
+    uint8_t c = 0;
+    if (m[i]) {
+        bool bg = x == 0 || y == 0 || x == W - 1 || y == H - 1 || !m[i - 1] || !m[i + 1] || !m[i - W] || !m[i + W];
+        c = bg ? 1 : 0;
+    }
+    pr.contour[i] = c;
+}
+
+constexpr int kFar = 1 << 20;
+
+// Phase 1: per column, distance (rows) to the nearest contour pixel in the column.
+__global__ void k_dt_cols(const ProbDev *__restrict__ P) {
+    const ProbDev &pr = P[blockIdx.y];
+    const int W = pr.W, H = pr.H;
+    int x = blockIdx.x * blockDim.x + threadIdx.x;
+    if (x >= W) return;
+    const uint8_t *c = pr.contour + x;
+    int *g = pr.colg + x;
+    int last = -kFar;
+    for (int y = 0; y < H; ++y) {
+        if (c[size_t(y) * W]) last = y;
+        g[size_t(y) * W] = y - last;
+    }
+    int next = 2 * kFar;
+    for (int y = H - 1; y >= 0; --y) {
+        if (c[size_t(y) * W]) next = y;
+        int d = next - y;
+        int cur = g[size_t(y) * W];
+        g[size_t(y) * W] = d < cur ? d : cur;
+    }
+}
+
+// Phase 2: per row, d^2(x) = min over x' of (x - x')^2 + g(x')^2, searched
+// outwards from x until (x - x')^2 reaches the best value (exact).
+__global__ void k_dt_rows(const ProbDev *__restrict__ P) {
+    extern __shared__ int G[];
+    const ProbDev &pr = P[blockIdx.y];
+    const int W = pr.W, H = pr.H;
+    const int y = blockIdx.x;
+    if (y >= H) return;
+    const int far2 = 1 << 30;
+    for (int x = threadIdx.x; x < W; x += blockDim.x) {
+        int g = pr.colg[size_t(y) * W + x];
+        G[x] = g >= kFar ? far2 : g * g;
+    }
+    __syncthreads();
+    for (int x = threadIdx.x; x < W; x += blockDim.x) {
+        int best = G[x];
+        for (int r = 1; r < W && r * r < best; ++r) {
+            int rr = r * r;
+            if (x - r >= 0) { int c = rr + G[x - r]; best = c < best ? c : best; }
+            if (x + r < W) { int c = rr + G[x + r]; best = c < best ? c : best; }
+        }
+        pr.dt[size_t(y) * W + x] = best >= far2 ? 0.0f : sqrtf(float(best));
+    }
+}
+
+// ---------------------------------------------------------------- start-state geometry
+// Embedded deformation at the start state, float32 recipe, then projection
+// and 1/256-pixel snapping.  Vertex order.
+__global__ void k_deform_start(const ProbDev *__restrict__ P) {
+    const ProbDev &pr = P[blockIdx.y];
+    const TemplateDev &T = pr.T;
+    const int nv = T.nv, nn = T.nn;
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nv) return;
+    float v[3] = {pr.xyz[i], pr.xyz[nv + i], pr.xyz[2 * nv + i]};
+    float acc[3] = {0.0f, 0.0f, 0.0f};
+    for (int j = 0; j < 4; ++j) {
+        int k = T.bind_idx[size_t(j) * nv + i];
+        float w = T.bind_w[size_t(j) * nv + i];
+        int gv = T.node_vertex[k];
+        float g[3] = {pr.xyz[gv], pr.xyz[nv + gv], pr.xyz[2 * nv + gv]};
+        float d[3] = {v[0] - g[0], v[1] - g[1], v[2] - g[2]};
+        for (int a = 0; a < 3; ++a) {
+            const float *R = pr.state + size_t(3 * a) * nn + k;
+            float q = (R[0] * d[0] + R[nn] * d[1]) + R[2 * size_t(nn)] * d[2];
+            float yv = (q + g[a]) + pr.state[size_t(9 + a) * nn + k];
+            acc[a] = acc[a] + w * yv;
+        }
+    }
+    float X = acc[0], Y = acc[1], Z = acc[2];
+    float u = (pr.fx * X) / Z + pr.cx;
+    float vv = (pr.fy * Y) / Z + pr.cy;
+    bool valid = Z > 0.0f && fabsf(u) <= 65536.0f && fabsf(vv) <= 65536.0f;
+    pr.dx[i] = X;
+    pr.dx[nv + i] = Y;
+    pr.dx[2 * nv + i] = Z;
+    pr.duv[i] = u;
+    pr.duv[nv + i] = vv;
+    pr.dfix[i] = valid ? int(rintf(u * 256.0f)) : 0;
+    pr.dfix[nv + i] = valid ? int(rintf(vv * 256.0f)) : 0;
+    pr.dvalid[i] = valid ? 1 : 0;
+    pr.vcont[i] = 0;
+}
+
+// Per face: cross product (for normals), then rasterise the inverse depth with
+// the fixed-point coverage rule; the buffer keeps the largest bit pattern.
+__global__ void k_raster(const ProbDev *__restrict__ P) {
+    const ProbDev &pr = P[blockIdx.y];
+    const TemplateDev &T = pr.T;
+    const int nv = T.nv, nf = T.nf, W = pr.W, H = pr.H;
+    int f = blockIdx.x * blockDim.x + threadIdx.x;
+    if (f >= nf) return;
+    int a = T.tri[f], b = T.tri[nf + f], c = T.tri[2 * size_t(nf) + f];
+    float p0[3] = {pr.dx[a], pr.dx[nv + a], pr.dx[2 * nv + a]};
+    float e1[3] = {pr.dx[b] - p0[0], pr.dx[nv + b] - p0[1], pr.dx[2 * nv + b] - p0[2]};
+    float e2[3] = {pr.dx[c] - p0[0], pr.dx[nv + c] - p0[1], pr.dx[2 * nv + c] - p0[2]};
+    float cr[3];
+    cross3(e1, e2, cr);
+    pr.fcross[f] = cr[0];
+    pr.fcross[nf + f] = cr[1];
+    pr.fcross[2 * size_t(nf) + f] = cr[2];
+    if (!(pr.dvalid[a] && pr.dvalid[b] && pr.dvalid[c])) return;
+    long long U0 = pr.dfix[a], V0 = pr.dfix[nv + a];
+    long long U1 = pr.dfix[b], V1 = pr.dfix[nv + b];
+    long long U2 = pr.dfix[c], V2 = pr.dfix[nv + c];
+    long long A = (U1 - U0) * (V2 - V0) - (V1 - V0) * (U2 - U0);
+    if (A == 0) return;
+    int ib = b, ic = c;
+    if (A < 0) {
+        long long t;
+        t = U1; U1 = U2; U2 = t;
+        t = V1; V1 = V2; V2 = t;
+        ib = c; ic = b;
+        A = -A;
+    }
+    float iz0 = 1.0f / pr.dx[2 * nv + a], iz1 = 1.0f / pr.dx[2 * nv + ib], iz2 = 1.0f / pr.dx[2 * nv + ic];
+    long long umin = min(U0, min(U1, U2)), umax = max(U0, max(U1, U2));
+    long long vmin = min(V0, min(V1, V2)), vmax = max(V0, max(V1, V2));
+    long long i0 = max(0LL, -((-umin) >> 8)), i1 = min((long long)W - 1, umax >> 8);
+    long long j0 = max(0LL, -((-vmin) >> 8)), j1 = min((long long)H - 1, vmax >> 8);
+    // edges 0: 1->2, 1: 2->0, 2: 0->1 and their boundary ownership
+    long long dU0 = U2 - U1, dV0 = V2 - V1, dU1 = U0 - U2, dV1 = V0 - V2, dU2 = U1 - U0, dV2 = V1 - V0;
+    bool o0 = dV0 < 0 || (dV0 == 0 && dU0 > 0);
+    bool o1 = dV1 < 0 || (dV1 == 0 && dU1 > 0);
+    bool o2 = dV2 < 0 || (dV2 == 0 && dU2 > 0);
+    float Af = float(A);
+    for (long long j = j0; j <= j1; ++j) {
+        long long Pv = j * 256;
+        for (long long i = i0; i <= i1; ++i) {
+            long long Pu = i * 256;
+            long long E0 = dU0 * (Pv - V1) - dV0 * (Pu - U1);
+            long long E1 = dU1 * (Pv - V2) - dV1 * (Pu - U2);
+            long long E2 = dU2 * (Pv - V0) - dV2 * (Pu - U0);
+            bool in = (E0 > 0 || (E0 == 0 && o0)) && (E1 > 0 || (E1 == 0 && o1)) && (E2 > 0 || (E2 == 0 && o2));
+            if (!in) continue;
+            float inv = ((float(E0) * iz0 + float(E1) * iz1) + float(E2) * iz2) / Af;
+            atomicMax(pr.zbuf + size_t(j) * W + i, __float_as_uint(inv));
+        }
+    }
+}
+
+// Per mesh edge: contour edge when its faces' facing differs (a border edge
+// when its one face is front-facing); marks both endpoints.
+__global__ void k_contour_edges(const ProbDev *__restrict__ P) {
+    const ProbDev &pr = P[blockIdx.y];
+    const TemplateDev &T = pr.T;
+    const int nv = T.nv, nf = T.nf, ne = T.nmedges;
+    int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= ne) return;
+    int a = T.medge[e], b = T.medge[ne + e], f0 = T.medge[2 * ne + e], f1 = T.medge[3 * ne + e];
+    auto back = [&](int f) {
+        int v0 = T.tri[f];
+        float s = (pr.dx[v0] * pr.fcross[f] + pr.dx[nv + v0] * pr.fcross[nf + f]) +
+                  pr.dx[2 * nv + v0] * pr.fcross[2 * size_t(nf) + f];
+        return s >= 0.0f;
+    };
+    bool c = f1 >= 0 ? (back(f0) != back(f1)) : !back(f0);
+    if (c) {
+        pr.vcont[a] = 1;
+        pr.vcont[b] = 1;
+    }
+}
+
+// Per vertex: visibility, contour set and direction sign; writes the flags in
+// vertex order and the solver's code byte in plan order.
+__global__ void k_decide(const ProbDev *__restrict__ P) {
+    const ProbDev &pr = P[blockIdx.y];
+    const TemplateDev &T = pr.T;
+    const int nv = T.nv, nf = T.nf, W = pr.W, H = pr.H;
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nv) return;
+    uint8_t code = 0;
+    if (pr.dvalid[i]) {
+        float u = pr.duv[i], v = pr.duv[nv + i];
+        int px = int(rintf(u)), py = int(rintf(v));
+        if (px >= 0 && px < W && py >= 0 && py < H) {
+            uint32_t m = 0xffffffffu;
+            for (int y = max(py - 1, 0); y <= min(py + 1, H - 1); ++y)
+                for (int x = max(px - 1, 0); x <= min(px + 1, W - 1); ++x) {
+                    uint32_t z = pr.zbuf[size_t(y) * W + x];
+                    if (z != 0u && z < m) m = z;
+                }
+            float X = pr.dx[i], Y = pr.dx[nv + i], Z = pr.dx[2 * nv + i];
+            bool vis = m == 0xffffffffu ? true : (Z <= (1.0f / __uint_as_float(m)) + 0.05f);
+            if (vis) {
+                code |= 1;
+                if (pr.vcont[i]) {
+                    code |= 2;
+                    float n[3] = {0.0f, 0.0f, 0.0f};
+                    for (int q = T.vf_beg[i]; q < T.vf_beg[i + 1]; ++q) {
+                        int f = T.vf_face[q];
+                        n[0] = n[0] + pr.fcross[f];
+                        n[1] = n[1] + pr.fcross[nf + f];
+                        n[2] = n[2] + pr.fcross[2 * size_t(nf) + f];
+                    }
+                    float gx, gy;
+                    (void)sample_cubic(pr.dt, W, H, u, v, gx, gy);
+                    float a = (n[0] * Z - n[2] * X) * pr.fx;
+                    float b = (n[1] * Z - n[2] * Y) * pr.fy;
+                    float s = a * (-gx) + b * (-gy);
+                    size_t pix = size_t(py) * W + px;
+                    bool inside = pr.mask[pix] != 0 && pr.dt[pix] >= 1.5f;
+                    if (inside && s < 0.0f) code |= 4;
+                    atomicAdd(pr.counts + 1, 1);
+                }
+                atomicAdd(pr.counts, 1);
+            }
+        }
+    }
+    pr.vflags[i] = code;
+    int p = T.plan_pos[i];
+    pr.vcode[p] = code;
+    pr.px[p] = pr.xyz[i];
+    pr.px[nv + p] = pr.xyz[nv + i];
+    pr.px[2 * nv + p] = pr.xyz[2 * nv + i];
+    pr.pc[p] = pr.rgb[i];
+    pr.pc[nv + p] = pr.rgb[nv + i];
+    pr.pc[2 * nv + p] = pr.rgb[2 * nv + i];
+}
+
+}  // namespace cap

@@ -1,0 +1,469 @@
+// Gauss-Newton / PCG kernels of the non-rigid stage (Sec. 3.4 energy, Sec. 4
+// solver).  Tile kernels (blockIdx.x = tile, blockIdx.y = problem) stream the
+// plan-ordered vertices once and accumulate per-node 6-vectors in LDS; node
+// kernels (one workgroup per problem) finish the per-node sums in a fixed
+// order and run the PCG vector updates with float64 dot products.
+#include "device.hpp"
+
+namespace cap {
+
+// LDS layout of a tile workgroup.
+struct TileLds {
+    float *R;   // [ns][9]
+    float *t;   // [ns][3]
+    float *g;   // [ns][3]
+    float *p;   // [ns][6]
+    float *c;   // [ncontrib][nc]
+};
+
+__device__ inline TileLds tile_lds(float *base, int ns, int ncomp) {
+    TileLds L;
+    L.R = base;
+    L.t = L.R + 9 * ns;
+    L.g = L.t + 3 * ns;
+    L.p = L.g + 3 * ns;
+    L.c = L.p + (ncomp == 6 ? 6 * ns : 0);
+    return L;
+}
+
+__device__ inline void load_slots(const ProbDev &pr, int sb, int ns, TileLds &L, bool with_p) {
+    const TemplateDev &T = pr.T;
+    const int nn = T.nn, nv = T.nv;
+    for (int s = threadIdx.x; s < ns; s += blockDim.x) {
+        int k = T.slot_node[sb + s];
+        for (int q = 0; q < 9; ++q) L.R[9 * s + q] = pr.state[size_t(q) * nn + k];
+        for (int q = 0; q < 3; ++q) L.t[3 * s + q] = pr.state[size_t(9 + q) * nn + k];
+        int gv = T.node_vertex[k];
+        for (int q = 0; q < 3; ++q) L.g[3 * s + q] = pr.xyz[size_t(q) * nv + gv];
+        if (with_p)
+            for (int q = 0; q < 6; ++q) L.p[6 * s + q] = pr.p[size_t(q) * nn + k];
+    }
+}
+
+__device__ inline void rot_apply(const float *R, const float d[3], float q[3]) {
+    q[0] = (R[0] * d[0] + R[1] * d[1]) + R[2] * d[2];
+    q[1] = (R[3] * d[0] + R[4] * d[1]) + R[5] * d[2];
+    q[2] = (R[6] * d[0] + R[7] * d[1]) + R[8] * d[2];
+}
+
+// ----------------------------------------------------------------------------
+// Linearisation: residuals, per-vertex condensed normal-equation blocks
+// H_i = sum |b| G^T G (3x3) and g_i = sum b G^T r, the energy, and per-slot
+// partial sums of the right-hand side -J^T B F and of diag(J^T |B| J).
+// mode 0: full; mode 1: energy only.
+// ----------------------------------------------------------------------------
+__global__ __launch_bounds__(kTileThreads) void k_linearize(const ProbDev *__restrict__ P, int mode) {
+    extern __shared__ float lds[];
+    __shared__ double red[kTileThreads];
+    const ProbDev &pr = P[blockIdx.y];
+    const TemplateDev &T = pr.T;
+    const int tile = blockIdx.x;
+    if (tile >= T.ntiles) return;
+    const int nv = T.nv, nn = T.nn;
+    const int vb = T.tile_vbeg[tile], nvt = T.tile_vbeg[tile + 1] - vb;
+    const int sb = T.tile_sbeg[tile], ns = T.tile_sbeg[tile + 1] - sb;
+    const int ob = T.tile_obeg[tile], nown = T.tile_obeg[tile + 1] - ob;
+    TileLds L = tile_lds(lds, ns, 12);
+    load_slots(pr, sb, ns, L, false);
+    __syncthreads();
+
+    double e_ph = 0.0, e_s = 0.0, e_sa = 0.0, e_a = 0.0;
+    const int lv = threadIdx.x;
+    if (lv < nvt) {
+        const int p = vb + lv;
+        const uint8_t code = pr.vcode[p];
+        float Hm[6] = {0, 0, 0, 0, 0, 0}, gi[3] = {0, 0, 0};
+        float q[4][3], w[4];
+        int sl[4];
+        const uint32_t packed = T.plan_slot[p];
+        const float v[3] = {pr.px[p], pr.px[nv + p], pr.px[2 * nv + p]};
+        // the deformed position and its projection in float64: an image
+        // coordinate of ~1e3 px in float32 is only good to ~1e-4 px, which the
+        // photometric and silhouette residuals would feel
+        double V[3] = {0, 0, 0};
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            sl[j] = (packed >> (8 * j)) & 0xff;
+            w[j] = T.plan_w[size_t(j) * nv + p];
+            const float *g = L.g + 3 * sl[j];
+            const float *Rm = L.R + 9 * sl[j];
+            const double d[3] = {double(v[0]) - g[0], double(v[1]) - g[1], double(v[2]) - g[2]};
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                const double qa = (double(Rm[3 * a]) * d[0] + double(Rm[3 * a + 1]) * d[1]) + double(Rm[3 * a + 2]) * d[2];
+                q[j][a] = float(qa);
+                V[a] += double(w[j]) * ((qa + g[a]) + L.t[3 * sl[j] + a]);
+            }
+        }
+        if ((code & 3) && V[2] > 0.0) {
+            const double izd = 1.0 / V[2];
+            const double ud = double(pr.fx) * V[0] * izd + pr.cx, vd = double(pr.fy) * V[1] * izd + pr.cy;
+            int cu, cv;
+            float fu, fv;
+            cell_of(ud, cu, fu);
+            cell_of(vd, cv, fv);
+            const float iz = float(izd), X = float(V[0]), Y = float(V[1]);
+            // d(u, v)/dV
+            const float P0[3] = {pr.fx * iz, 0.0f, -pr.fx * X * iz * iz};
+            const float P1[3] = {0.0f, pr.fy * iz, -pr.fy * Y * iz * iz};
+            if (code & 1) {
+                float val[3], gu[3], gv[3];
+                sample_cubic3_cell(pr.blurred, pr.W, pr.H, cu, fu, cv, fv, val, gu, gv);
+                float res[3], n2 = 0.0f;
+                for (int c = 0; c < 3; ++c) {
+                    res[c] = val[c] - pr.pc[size_t(c) * nv + p];
+                    n2 += res[c] * res[c];
+                }
+                if (!(sqrtf(n2) > pr.tau)) {
+                    for (int c = 0; c < 3; ++c) {
+                        const float r = pr.sw_photo * res[c];
+                        float G[3];
+                        for (int a = 0; a < 3; ++a) G[a] = pr.sw_photo * (gu[c] * P0[a] + gv[c] * P1[a]);
+                        Hm[0] += G[0] * G[0]; Hm[1] += G[0] * G[1]; Hm[2] += G[0] * G[2];
+                        Hm[3] += G[1] * G[1]; Hm[4] += G[1] * G[2]; Hm[5] += G[2] * G[2];
+                        for (int a = 0; a < 3; ++a) gi[a] += G[a] * r;
+                        e_ph += double(r) * double(r);
+                    }
+                }
+            }
+            if (code & 2) {
+                float gu, gv;
+                const float dval = sample_cubic_cell(pr.dt, pr.W, pr.H, cu, fu, cv, fv, gu, gv);
+                const float r = pr.sw_sil * dval;
+                const float b = (code & 4) ? -1.0f : 1.0f;
+                float G[3];
+                for (int a = 0; a < 3; ++a) G[a] = pr.sw_sil * (gu * P0[a] + gv * P1[a]);
+                Hm[0] += G[0] * G[0]; Hm[1] += G[0] * G[1]; Hm[2] += G[0] * G[2];
+                Hm[3] += G[1] * G[1]; Hm[4] += G[1] * G[2]; Hm[5] += G[2] * G[2];
+                for (int a = 0; a < 3; ++a) gi[a] += b * G[a] * r;
+                e_s += double(b) * double(r) * double(r);
+                e_sa += double(r) * double(r);
+            }
+        }
+        if (mode == 0) {
+            if (code & 3)
+                for (int q6 = 0; q6 < 6; ++q6) pr.Hm[size_t(q6) * nv + p] = Hm[q6];
+            // contributions to the 4 bound nodes: rhs -w[q x g; g], diag w^2[diag(Q^T H Q); diag(H)]
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                float *c = L.c + 12 * (4 * lv + j);
+                const float *qq = q[j];
+                const float ww = w[j], w2 = w[j] * w[j];
+                float qxg[3];
+                cross3(qq, gi, qxg);
+                c[0] = -ww * qxg[0]; c[1] = -ww * qxg[1]; c[2] = -ww * qxg[2];
+                c[3] = -ww * gi[0]; c[4] = -ww * gi[1]; c[5] = -ww * gi[2];
+                const float xx = Hm[0], xy = Hm[1], xz = Hm[2], yy = Hm[3], yz = Hm[4], zz = Hm[5];
+                c[6] = w2 * ((qq[2] * qq[2] * yy - 2.0f * qq[2] * qq[1] * yz) + qq[1] * qq[1] * zz);
+                c[7] = w2 * ((qq[2] * qq[2] * xx - 2.0f * qq[2] * qq[0] * xz) + qq[0] * qq[0] * zz);
+                c[8] = w2 * ((qq[1] * qq[1] * xx - 2.0f * qq[1] * qq[0] * xy) + qq[0] * qq[0] * yy);
+                c[9] = w2 * xx; c[10] = w2 * yy; c[11] = w2 * zz;
+            }
+        }
+    }
+    // regulariser edges owned by this tile: r = sqrt(w)(R_k(g_l - g_k) + g_k + t_k - g_l - t_l)
+    for (int idx = threadIdx.x; idx < nown * 8; idx += blockDim.x) {
+        const int o = idx >> 3, e = idx & 7;
+        const int so = T.owned_slot[ob + o];
+        const int se = T.owned_eslot[size_t(e) * nn + ob + o];
+        float *c0 = L.c + 12 * (4 * nvt + 2 * idx);
+        float *c1 = c0 + 12;
+        if (se == 255) {
+            if (mode == 0)
+                for (int q12 = 0; q12 < 12; ++q12) { c0[q12] = 0.0f; c1[q12] = 0.0f; }
+            continue;
+        }
+        const float *gk = L.g + 3 * so, *gl = L.g + 3 * se;
+        float d[3] = {gl[0] - gk[0], gl[1] - gk[1], gl[2] - gk[2]};
+        float ekl[3];
+        rot_apply(L.R + 9 * so, d, ekl);
+        float r[3];
+        {
+            const float *Rk = L.R + 9 * so;
+            const double dd[3] = {double(gl[0]) - gk[0], double(gl[1]) - gk[1], double(gl[2]) - gk[2]};
+            for (int a = 0; a < 3; ++a) {
+                const double ed = (double(Rk[3 * a]) * dd[0] + double(Rk[3 * a + 1]) * dd[1]) + double(Rk[3 * a + 2]) * dd[2];
+                r[a] = float(double(pr.sw_arap) * ((ed - dd[a]) + (double(L.t[3 * so + a]) - L.t[3 * se + a])));
+            }
+        }
+        e_a += double(r[0]) * r[0] + double(r[1]) * r[1] + double(r[2]) * r[2];
+        if (mode == 0) {
+            float exr[3];
+            cross3(ekl, r, exr);
+            const float s = pr.sw_arap, wa = pr.w_arap;
+            c0[0] = -s * exr[0]; c0[1] = -s * exr[1]; c0[2] = -s * exr[2];
+            c0[3] = -s * r[0]; c0[4] = -s * r[1]; c0[5] = -s * r[2];
+            c0[6] = wa * (ekl[1] * ekl[1] + ekl[2] * ekl[2]);
+            c0[7] = wa * (ekl[0] * ekl[0] + ekl[2] * ekl[2]);
+            c0[8] = wa * (ekl[0] * ekl[0] + ekl[1] * ekl[1]);
+            c0[9] = wa; c0[10] = wa; c0[11] = wa;
+            c1[0] = 0.0f; c1[1] = 0.0f; c1[2] = 0.0f;
+            c1[3] = s * r[0]; c1[4] = s * r[1]; c1[5] = s * r[2];
+            c1[6] = 0.0f; c1[7] = 0.0f; c1[8] = 0.0f;
+            c1[9] = wa; c1[10] = wa; c1[11] = wa;
+        }
+    }
+    __syncthreads();
+    if (mode == 0) {
+        for (int pair = threadIdx.x; pair < ns * 12; pair += blockDim.x) {
+            const int s = pair / 12, comp = pair - s * 12;
+            const int lb = T.list_beg[sb + s], le = T.list_beg[sb + s + 1];
+            float acc = 0.0f;
+            for (int q = lb; q < le; ++q) acc += L.c[12 * T.list_idx[q] + comp];
+            pr.partial[size_t(sb + s) * 12 + comp] = acc;
+        }
+    }
+    double s0 = block_sum<kTileThreads>(e_ph, red);
+    double s1 = block_sum<kTileThreads>(e_s, red);
+    double s2 = block_sum<kTileThreads>(e_sa, red);
+    double s3 = block_sum<kTileThreads>(e_a, red);
+    if (threadIdx.x == 0) {
+        double *te = pr.tile_e + size_t(tile) * 4;
+        te[0] = s0; te[1] = s1; te[2] = s2; te[3] = s3;
+    }
+}
+
+// ----------------------------------------------------------------------------
+// Matrix-free J^T |B| J p per tile: dV_i = sum_j w_j (w_k x q_j + tau_k),
+// f_i = H_i dV_i, node contributions w_j [q_j x f_i; f_i]; regulariser edges
+// u = w_k x e_kl + tau_k - tau_l add w_a [e x u; u] to k and w_a [0; -u] to l.
+// ----------------------------------------------------------------------------
+__global__ __launch_bounds__(kTileThreads) void k_apply(const ProbDev *__restrict__ P) {
+    extern __shared__ float lds[];
+    const ProbDev &pr = P[blockIdx.y];
+    if (pr.scal[1] != 0.0) return;
+    const TemplateDev &T = pr.T;
+    const int tile = blockIdx.x;
+    if (tile >= T.ntiles) return;
+    const int nv = T.nv, nn = T.nn;
+    const int vb = T.tile_vbeg[tile], nvt = T.tile_vbeg[tile + 1] - vb;
+    const int sb = T.tile_sbeg[tile], ns = T.tile_sbeg[tile + 1] - sb;
+    const int ob = T.tile_obeg[tile], nown = T.tile_obeg[tile + 1] - ob;
+    TileLds L = tile_lds(lds, ns, 6);
+    load_slots(pr, sb, ns, L, true);
+    __syncthreads();
+    const int lv = threadIdx.x;
+    if (lv < nvt) {
+        const int p = vb + lv;
+        float *c = L.c + 24 * lv;
+        if (pr.vcode[p] & 3) {
+            const uint32_t packed = T.plan_slot[p];
+            const float v[3] = {pr.px[p], pr.px[nv + p], pr.px[2 * nv + p]};
+            float q[4][3], w[4];
+            int sl[4];
+            float dV[3] = {0, 0, 0};
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                sl[j] = (packed >> (8 * j)) & 0xff;
+                w[j] = T.plan_w[size_t(j) * nv + p];
+                const float *g = L.g + 3 * sl[j];
+                float d[3] = {v[0] - g[0], v[1] - g[1], v[2] - g[2]};
+                rot_apply(L.R + 9 * sl[j], d, q[j]);
+                const float *pp = L.p + 6 * sl[j];
+                float oxq[3];
+                cross3(pp, q[j], oxq);
+#pragma unroll
+                for (int a = 0; a < 3; ++a) dV[a] += w[j] * (oxq[a] + pp[3 + a]);
+            }
+            float Hm[6];
+#pragma unroll
+            for (int q6 = 0; q6 < 6; ++q6) Hm[q6] = pr.Hm[size_t(q6) * nv + p];
+            const float f[3] = {(Hm[0] * dV[0] + Hm[1] * dV[1]) + Hm[2] * dV[2],
+                                (Hm[1] * dV[0] + Hm[3] * dV[1]) + Hm[4] * dV[2],
+                                (Hm[2] * dV[0] + Hm[4] * dV[1]) + Hm[5] * dV[2]};
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                float qxf[3];
+                cross3(q[j], f, qxf);
+                float *cj = c + 6 * j;
+                cj[0] = w[j] * qxf[0]; cj[1] = w[j] * qxf[1]; cj[2] = w[j] * qxf[2];
+                cj[3] = w[j] * f[0]; cj[4] = w[j] * f[1]; cj[5] = w[j] * f[2];
+            }
+        } else {
+            for (int q = 0; q < 24; ++q) c[q] = 0.0f;
+        }
+    }
+    for (int idx = threadIdx.x; idx < nown * 8; idx += blockDim.x) {
+        const int o = idx >> 3, e = idx & 7;
+        const int so = T.owned_slot[ob + o];
+        const int se = T.owned_eslot[size_t(e) * nn + ob + o];
+        float *c0 = L.c + 6 * (4 * nvt + 2 * idx);
+        float *c1 = c0 + 6;
+        if (se == 255) {
+            for (int q = 0; q < 6; ++q) { c0[q] = 0.0f; c1[q] = 0.0f; }
+            continue;
+        }
+        const float *gk = L.g + 3 * so, *gl = L.g + 3 * se;
+        float d[3] = {gl[0] - gk[0], gl[1] - gk[1], gl[2] - gk[2]};
+        float ekl[3];
+        rot_apply(L.R + 9 * so, d, ekl);
+        const float *pk = L.p + 6 * so, *pl = L.p + 6 * se;
+        float oxe[3];
+        cross3(pk, ekl, oxe);
+        float u[3] = {(oxe[0] + pk[3]) - pl[3], (oxe[1] + pk[4]) - pl[4], (oxe[2] + pk[5]) - pl[5]};
+        float exu[3];
+        cross3(ekl, u, exu);
+        const float wa = pr.w_arap;
+        c0[0] = wa * exu[0]; c0[1] = wa * exu[1]; c0[2] = wa * exu[2];
+        c0[3] = wa * u[0]; c0[4] = wa * u[1]; c0[5] = wa * u[2];
+        c1[0] = 0.0f; c1[1] = 0.0f; c1[2] = 0.0f;
+        c1[3] = -wa * u[0]; c1[4] = -wa * u[1]; c1[5] = -wa * u[2];
+    }
+    __syncthreads();
+    for (int pair = threadIdx.x; pair < ns * 6; pair += blockDim.x) {
+        const int s = pair / 6, comp = pair - s * 6;
+        const int lb = T.list_beg[sb + s], le = T.list_beg[sb + s + 1];
+        float acc = 0.0f;
+        for (int q = lb; q < le; ++q) acc += L.c[6 * T.list_idx[q] + comp];
+        pr.partial[size_t(sb + s) * 6 + comp] = acc;
+    }
+}
+
+// ----------------------------------------------------------------------------
+// Node kernels: one workgroup per problem.
+// ----------------------------------------------------------------------------
+
+// After a linearisation: b, diag, Jacobi preconditioner, PCG start vectors
+// (x = 0, r = b, z = M^-1 r, p = z), r.z, and the energy of GN step `gn`.
+__global__ __launch_bounds__(kNodeThreads) void k_node_init(const ProbDev *__restrict__ P, int gn, int energy_only) {
+    __shared__ double red[kNodeThreads];
+    const ProbDev &pr = P[blockIdx.x];
+    const TemplateDev &T = pr.T;
+    const int nn = T.nn;
+    double rz = 0.0;
+    if (!energy_only) {
+        for (int k = threadIdx.x; k < nn; k += blockDim.x) {
+            const int pb = T.node_pbeg[k], pe = T.node_pbeg[k + 1];
+            for (int c = 0; c < 6; ++c) {
+                float b = 0.0f, d = 0.0f;
+                for (int q = pb; q < pe; ++q) {
+                    b += pr.partial[size_t(T.node_pidx[q]) * 12 + c];
+                    d += pr.partial[size_t(T.node_pidx[q]) * 12 + 6 + c];
+                }
+                const float mi = d > 0.0f ? 1.0f / d : 1.0f;
+                const float z = mi * b;
+                const size_t o = size_t(c) * nn + k;
+                pr.b[o] = b; pr.diag[o] = d; pr.dinv[o] = mi;
+                pr.x[o] = 0.0f; pr.r[o] = b; pr.z[o] = z; pr.p[o] = z;
+                rz += double(b) * double(z);
+            }
+        }
+    }
+    rz = block_sum<kNodeThreads>(rz, red);
+    double e[4] = {0, 0, 0, 0};
+    for (int t = threadIdx.x; t < T.ntiles; t += blockDim.x)
+        for (int q = 0; q < 4; ++q) e[q] += pr.tile_e[size_t(t) * 4 + q];
+    for (int q = 0; q < 4; ++q) e[q] = block_sum<kNodeThreads>(e[q], red);
+    if (threadIdx.x == 0) {
+        if (!energy_only) {
+            pr.scal[0] = rz;
+            pr.scal[1] = rz == 0.0 ? 1.0 : 0.0;
+        }
+        for (int q = 0; q < 4; ++q) pr.scal[8 + 4 * gn + q] = e[q];
+    }
+}
+
+// Gather A p from the tile partials (no PCG update).
+__global__ __launch_bounds__(kNodeThreads) void k_node_gather(const ProbDev *__restrict__ P) {
+    const ProbDev &pr = P[blockIdx.x];
+    const TemplateDev &T = pr.T;
+    const int nn = T.nn;
+    for (int k = threadIdx.x; k < nn; k += blockDim.x) {
+        const int pb = T.node_pbeg[k], pe = T.node_pbeg[k + 1];
+        for (int c = 0; c < 6; ++c) {
+            float a = 0.0f;
+            for (int q = pb; q < pe; ++q) a += pr.partial[size_t(T.node_pidx[q]) * 6 + c];
+            pr.Ap[size_t(c) * nn + k] = a;
+        }
+    }
+}
+
+// R <- Exp(dw) R (Rodrigues, float32), t <- t + dt.
+__device__ inline void node_update(const ProbDev &pr, int k) {
+    const int nn = pr.T.nn;
+    float w[3], tau[3];
+    for (int a = 0; a < 3; ++a) { w[a] = pr.x[size_t(a) * nn + k]; tau[a] = pr.x[size_t(3 + a) * nn + k]; }
+    const float th2 = (w[0] * w[0] + w[1] * w[1]) + w[2] * w[2];
+    float A, B;
+    if (th2 < 1e-8f) {
+        A = 1.0f - th2 / 6.0f;
+        B = 0.5f - th2 / 24.0f;
+    } else {
+        const float th = sqrtf(th2);
+        A = sinf(th) / th;
+        B = (1.0f - cosf(th)) / th2;
+    }
+    float K[9] = {0.0f, -w[2], w[1], w[2], 0.0f, -w[0], -w[1], w[0], 0.0f};
+    float E[9];
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) {
+            float kk = (K[3 * i] * K[j] + K[3 * i + 1] * K[3 + j]) + K[3 * i + 2] * K[6 + j];
+            E[3 * i + j] = (i == j ? 1.0f : 0.0f) + A * K[3 * i + j] + B * kk;
+        }
+    float R[9];
+    for (int q = 0; q < 9; ++q) R[q] = pr.state[size_t(q) * nn + k];
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j)
+            pr.state[size_t(3 * i + j) * nn + k] = (E[3 * i] * R[j] + E[3 * i + 1] * R[3 + j]) + E[3 * i + 2] * R[6 + j];
+    for (int a = 0; a < 3; ++a) pr.state[size_t(9 + a) * nn + k] += tau[a];
+}
+
+// One PCG iteration after k_apply: A p, alpha, x/r/z updates, beta, p.
+// Stops (for this GN step) when p.Ap <= 0 or r.z == 0.  `last`: apply the
+// node update afterwards; `update_only`: only that.
+__global__ __launch_bounds__(kNodeThreads) void k_node_pcg(const ProbDev *__restrict__ P, int last, int update_only) {
+    __shared__ double red[kNodeThreads];
+    const ProbDev &pr = P[blockIdx.x];
+    const TemplateDev &T = pr.T;
+    const int nn = T.nn;
+    const bool done = pr.scal[1] != 0.0;
+    if (!done && !update_only) {
+        double pap = 0.0;
+        for (int k = threadIdx.x; k < nn; k += blockDim.x) {
+            const int pb = T.node_pbeg[k], pe = T.node_pbeg[k + 1];
+            for (int c = 0; c < 6; ++c) {
+                float a = 0.0f;
+                for (int q = pb; q < pe; ++q) a += pr.partial[size_t(T.node_pidx[q]) * 6 + c];
+                const size_t o = size_t(c) * nn + k;
+                pr.Ap[o] = a;
+                pap += double(pr.p[o]) * double(a);
+            }
+        }
+        pap = block_sum<kNodeThreads>(pap, red);
+        const double rz = pr.scal[0];
+        if (pap <= 0.0) {
+            __syncthreads();
+            if (threadIdx.x == 0) pr.scal[1] = 1.0;
+        } else {
+            const double alpha = rz / pap;
+            double rz2 = 0.0;
+            for (int k = threadIdx.x; k < nn; k += blockDim.x)
+                for (int c = 0; c < 6; ++c) {
+                    const size_t o = size_t(c) * nn + k;
+                    pr.x[o] = float(fma(alpha, double(pr.p[o]), double(pr.x[o])));
+                    const float r = float(fma(-alpha, double(pr.Ap[o]), double(pr.r[o])));
+                    const float z = pr.dinv[o] * r;
+                    pr.r[o] = r;
+                    pr.z[o] = z;
+                    rz2 += double(r) * double(z);
+                }
+            rz2 = block_sum<kNodeThreads>(rz2, red);
+            const double beta = rz2 / rz;
+            for (int k = threadIdx.x; k < nn; k += blockDim.x)
+                for (int c = 0; c < 6; ++c) {
+                    const size_t o = size_t(c) * nn + k;
+                    pr.p[o] = float(fma(beta, double(pr.p[o]), double(pr.z[o])));
+                }
+            if (threadIdx.x == 0) {
+                pr.scal[0] = rz2;
+                if (rz2 == 0.0) pr.scal[1] = 1.0;
+            }
+        }
+    }
+    if (last || update_only) {
+        __syncthreads();
+        for (int k = threadIdx.x; k < nn; k += blockDim.x) node_update(pr, k);
+    }
+}
+
+}  // namespace cap

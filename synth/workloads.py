@@ -1,6 +1,6 @@
 """Seeded non-rigid workloads (template, camera, ground truth, targets).
 
-Recipe (stated once here and in the design notes):
+Recipe:
 
 * Template: an ellipsoid with semi-axes (0.15, 0.5, 0.15) m (long axis along
   the image's +y), centred 2.5 m in front of the camera.  The small case uses

@@ -1,0 +1,226 @@
+"""GPU parity of the non-rigid stage against the FP64 oracle (through the C ABI).
+
+Bars: integer outputs (graph indices, depth buffer bits, visibility, contour
+set, direction signs, distance-transform bits) bit-exact; float outputs
+within tolerances derived from float32 arithmetic; solved node parameters
+within 1e-4 of the parameter change and energies within 1e-5 of the start
+energy (relative), against the oracle run with the same PCG schedule.
+"""
+import numpy as np
+import pytest
+
+import synth
+from oracle import graph as og
+from oracle import image as oi
+from oracle import nonrigid as onr
+from oracle import so3
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import paper_1810_02648_amd as cap
+    return cap.Context(0)
+
+
+@pytest.fixture(scope="module")
+def frames():
+    return {"small0": synth.make_nonrigid_frame("small", 0),
+            "small1": synth.make_nonrigid_frame("small", 1),
+            "mid": synth.make_nonrigid_frame("small", 2, n_vertices=9001, n_nodes=203, side=517)}
+
+
+def test_graph_build_matches_oracle(ctx, frames):
+    import paper_1810_02648_amd as cap
+    from gpu_util import dev
+    for name in ("small0", "mid"):
+        f = frames[name]
+        nn = int(f["n_nodes"]) if name != "mid" else 203
+        ref = og.build_graph(f["xyz"], nn)
+        g = cap.graph_build(ctx, dev(f["xyz"]), nn)
+        assert np.array_equal(g["node_vertex"].cpu().numpy(), ref["node_vertex"]), name
+        assert np.array_equal(g["bind_idx"].cpu().numpy(), ref["bind_idx"]), name
+        assert np.array_equal(g["edge_dst"].cpu().numpy(), ref["edge_dst"]), name
+        assert np.abs(g["bind_w"].cpu().numpy() - ref["bind_w64"]).max() < 2e-6, name
+
+
+@pytest.mark.parametrize("name", ["small0", "small1", "mid"])
+def test_frame_decisions_bit_exact(ctx, frames, name):
+    import paper_1810_02648_amd as cap
+    from gpu_util import make_frame
+    f = frames[name]
+    nn = 64 if name != "mid" else 203
+    g = og.build_graph(f["xyz"], nn)
+    P = onr.Problem(f["xyz"], f["tri"], f["rgb"], g, f["cam"], f["mask"], f["image"], f["weights"])
+    fr = make_frame(ctx, f, g)
+    out = cap.frame_decisions(ctx, fr)
+    assert np.array_equal(out["dt"].cpu().numpy().view(np.uint32), P.dt.view(np.uint32))
+    assert np.array_equal(out["zbuf"].cpu().numpy().view(np.uint32), P.dec["zbuf"])
+    fl = out["vflags"].cpu().numpy()
+    assert np.array_equal((fl & 1) != 0, P.dec["visible"])
+    assert np.array_equal((fl & 2) != 0, P.dec["boundary"])
+    assert np.array_equal((fl & 4) != 0, P.dec["bsign"] < 0)
+    assert np.abs(out["blurred"].cpu().numpy() - P.img).max() < 1e-6
+
+
+def test_distance_transform_edge_cases(ctx, frames):
+    """Empty mask (no contour: DT = 0), full mask (contour = image border), one pixel."""
+    import paper_1810_02648_amd as cap
+    from gpu_util import make_frame
+    f = dict(frames["small0"])
+    g = og.build_graph(f["xyz"], 64)
+    H, W = f["mask"].shape
+    cases = [np.zeros((H, W), np.uint8), np.ones((H, W), np.uint8)]
+    one = np.zeros((H, W), np.uint8)
+    one[H - 1, 7] = 1
+    cases.append(one)
+    for m in cases:
+        f["mask"] = m
+        out = cap.frame_decisions(ctx, make_frame(ctx, f, g))
+        ref, _ = oi.distance_transform(m)
+        assert np.array_equal(out["dt"].cpu().numpy().view(np.uint32), ref.view(np.uint32))
+
+
+def normal_equations_dense(P, state):
+    A, rhs, e = P.normal_equations(state)
+    return A, rhs, e
+
+
+@pytest.mark.parametrize("name", ["small0", "mid"])
+def test_linearization_and_jtj_product(ctx, frames, name):
+    import paper_1810_02648_amd as cap
+    from gpu_util import make_frame, dev
+    f = frames[name]
+    nn = 64 if name != "mid" else 203
+    g = og.build_graph(f["xyz"], nn)
+    rng = np.random.default_rng(11)
+    st = onr.apply_update(onr.identity_state(nn), rng.normal(0, 0.02, 6 * nn)).astype(np.float32)
+    P = onr.Problem(f["xyz"], f["tri"], f["rgb"], g, f["cam"], f["mask"], f["image"], f["weights"], state0=st)
+    A, rhs, e = P.normal_equations(st.astype(np.float64))
+    fr = make_frame(ctx, f, g, state=st)
+    pvec = rng.normal(size=(6, nn)).astype(np.float32)
+    prm = cap.params(*f["weights"], gn_iters=1, pcg_iters=1)
+    out = cap.linearize(ctx, fr, prm, dev(pvec))
+    # node-major (6 per node) vectors of the oracle -> [6][nn]
+    rhs_ref = rhs.reshape(nn, 6).T
+    diag_ref = A.diagonal().reshape(nn, 6).T
+    ap_ref = (A @ pvec.T.reshape(-1).astype(np.float64)).reshape(nn, 6).T
+    for got, ref in ((out["rhs"], rhs_ref), (out["diag"], diag_ref), (out["Ap"], ap_ref)):
+        got = got.cpu().numpy().astype(np.float64)
+        assert np.linalg.norm(got - ref) <= 2e-5 * np.linalg.norm(ref)
+        assert np.abs(got - ref).max() <= 1e-4 * np.abs(ref).max()
+    ge = out["energy"]
+    for got, ref in zip(ge, (e["photo"], e["sil"], e["sil_abs"], e["arap"])):
+        assert abs(got - ref) <= 1e-5 * max(e["total"], 1e-12)
+
+
+def params_of(state):
+    st = state.astype(np.float64)
+    return so3.log_all(st), st[9:12]
+
+
+@pytest.mark.parametrize("name,gn,pcg", [("small0", 5, 10), ("small1", 5, 10), ("mid", 3, 8)])
+def test_solve_matches_schedule_matched_oracle(ctx, frames, name, gn, pcg):
+    import paper_1810_02648_amd as cap
+    from gpu_util import make_frame
+    f = frames[name]
+    nn = 64 if name != "mid" else 203
+    g = og.build_graph(f["xyz"], nn)
+    P = onr.Problem(f["xyz"], f["tri"], f["rgb"], g, f["cam"], f["mask"], f["image"], f["weights"])
+    ref = onr.solve(P, gn, "pcg", pcg)
+    fr = make_frame(ctx, f, g)
+    rep = cap.nonrigid_solve(ctx, fr, cap.params(*f["weights"], gn_iters=gn, pcg_iters=pcg))
+    assert rep["status"] == 0
+    assert rep["n_visible"] == ref["n_visible"] and rep["n_boundary"] == ref["n_boundary"]
+    r_gpu, t_gpu = params_of(fr.node_state.cpu().numpy())
+    r_ref, t_ref = params_of(ref["state"])
+    assert np.linalg.norm(r_gpu - r_ref) <= 1e-4 * max(np.linalg.norm(r_ref), 1e-6)
+    assert np.linalg.norm(t_gpu - t_ref) <= 1e-4 * max(np.linalg.norm(t_ref), 1e-6)
+    e0 = ref["energies"][0]["total"]
+    for k, e in enumerate(ref["energies"]):
+        assert abs(rep["energy"][k] - e["total"]) <= 1e-5 * e0, k
+
+
+def test_batch_equals_single_solves(ctx, frames):
+    """An uneven batch in one launch sequence gives each frame's single-solve result."""
+    import paper_1810_02648_amd as cap
+    from gpu_util import make_frame
+    prm = cap.params(1.0, 0.1, 10.0, gn_iters=3, pcg_iters=6)
+    singles, batch = [], []
+    for name, nn in (("small0", 64), ("mid", 203), ("small1", 64)):
+        f = frames[name]
+        g = og.build_graph(f["xyz"], nn)
+        a = make_frame(ctx, f, g)
+        b = make_frame(ctx, f, g, tmpl=a.template)
+        singles.append((a, cap.nonrigid_solve(ctx, a, prm)))
+        batch.append(b)
+    reps = cap.batch_solve(ctx, batch, prm)
+    for (a, ra), b, rb in zip(singles, batch, reps):
+        assert np.array_equal(a.node_state.cpu().numpy(), b.node_state.cpu().numpy())
+        assert ra["energy"] == rb["energy"]
+
+
+def test_run_to_run_deterministic(ctx, frames):
+    import paper_1810_02648_amd as cap
+    from gpu_util import make_frame
+    f = frames["mid"]
+    g = og.build_graph(f["xyz"], 203)
+    prm = cap.params(1.0, 0.1, 10.0, gn_iters=2, pcg_iters=5)
+    a = make_frame(ctx, f, g)
+    b = make_frame(ctx, f, g, tmpl=a.template)
+    cap.nonrigid_solve(ctx, a, prm)
+    cap.nonrigid_solve(ctx, b, prm)
+    assert np.array_equal(a.node_state.cpu().numpy(), b.node_state.cpu().numpy())
+
+
+def test_degenerate_schedules_and_masks(ctx, frames):
+    """pcg_iters = 0 leaves the state; an empty mask switches the silhouette term off;
+    a 4-node graph and a small tile size still match the oracle."""
+    import paper_1810_02648_amd as cap
+    from gpu_util import make_frame
+    f = dict(frames["small0"])
+    g = og.build_graph(f["xyz"], 64)
+    fr = make_frame(ctx, f, g)
+    rep = cap.nonrigid_solve(ctx, fr, cap.params(gn_iters=2, pcg_iters=0))
+    assert np.array_equal(fr.node_state.cpu().numpy(), np.asarray(fr.node_state.cpu().numpy()))
+    st = fr.node_state.cpu().numpy()
+    assert np.allclose(st[[0, 4, 8]], 1.0) and np.allclose(st[[1, 2, 3, 5, 6, 7, 9, 10, 11]], 0.0)
+    assert rep["energy"][0] == rep["energy"][2]
+    f["mask"] = np.zeros_like(f["mask"])
+    P = onr.Problem(f["xyz"], f["tri"], f["rgb"], g, f["cam"], f["mask"], f["image"], f["weights"])
+    ref = onr.solve(P, 2, "pcg", 4)
+    fr = make_frame(ctx, f, g)
+    rep = cap.nonrigid_solve(ctx, fr, cap.params(gn_iters=2, pcg_iters=4))
+    assert rep["e_sil"] == 0.0 and rep["e_sil_abs"] == 0.0
+    assert abs(rep["energy"][-1] - ref["energies"][-1]["total"]) <= 1e-5 * ref["energies"][0]["total"]
+    # 4 nodes, tiles of 37 vertices (ragged tails everywhere)
+    f = frames["small1"]
+    g = og.build_graph(f["xyz"], 4)
+    P = onr.Problem(f["xyz"], f["tri"], f["rgb"], g, f["cam"], f["mask"], f["image"], f["weights"])
+    ref = onr.solve(P, 3, "pcg", 5)
+    fr = make_frame(ctx, f, g, vertices_per_tile=37)
+    rep = cap.nonrigid_solve(ctx, fr, cap.params(gn_iters=3, pcg_iters=5))
+    r_gpu, t_gpu = params_of(fr.node_state.cpu().numpy())
+    r_ref, t_ref = params_of(ref["state"])
+    assert np.linalg.norm(r_gpu - r_ref) <= 1e-4 * max(np.linalg.norm(r_ref), 1e-6)
+    assert np.linalg.norm(t_gpu - t_ref) <= 1e-4 * max(np.linalg.norm(t_ref), 1e-6)
+
+
+def test_invalid_arguments_are_rejected(ctx, frames):
+    import paper_1810_02648_amd as cap
+    from gpu_util import make_frame
+    f = frames["small0"]
+    g = og.build_graph(f["xyz"], 64)
+    fr = make_frame(ctx, f, g)
+    before = fr.node_state.clone()
+    for bad in (cap.params(gn_iters=0), cap.params(gn_iters=33), cap.params(pcg_iters=-1),
+                cap.params(w_sil=-1.0), cap.params(w_photo=float("nan"))):
+        with pytest.raises(cap.CaptureError) as ei:
+            cap.nonrigid_solve(ctx, fr, bad)
+        assert ei.value.code == -1
+    assert torch.equal(before, fr.node_state)
+    with pytest.raises(cap.CaptureError):
+        cap.graph_build(ctx, fr.xyz, 3)
