@@ -70,27 +70,99 @@ def cpu_baseline(frame_dict, n_nodes, gn, pcg, weights):
                        % (gn, dt, out["energies"][-1]["total"]))
 
 
-def main():
-    ap = argparse.ArgumentParser(description=__doc__)
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", default="frame20k", choices=["small", "frame20k", "stress200k"])
-    ap.add_argument("--batch", type=int, default=1, help="independent frames solved together per step")
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    args = ap.parse_args()
-    if args.gpus != 1:
-        print("bench.py measures one GPU only: the solver has no multi-GPU path "
-              "(independent captures would shard one per GPU with no communication)", file=sys.stderr)
-        sys.exit(2)
+def roofline_for(prof, steps, batch, n_act, nn, n_edges, W, H, nf, nv):
+    per_step_us = {k: 1000.0 * ms / steps for k, (ms, n) in prof.items() if n}
+    dom = max(per_step_us, key=per_step_us.get)
+    bytes_launch = batch * algorithmic_bytes(dom, n_act, nn, n_edges, W * H, nf, nv)
+    avg_s = prof[dom][0] / 1000.0 / prof[dom][1]
+    achieved = bytes_launch / avg_s / 1e9
+    apply_s = prof["apply"][0] / 1000.0 / max(prof["apply"][1], 1)
+    apply_bytes = batch * algorithmic_bytes("apply", n_act, nn, n_edges, W * H, 0, 0)
+    return {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS, "traffic": None, "avg_us": avg_s * 1e6,
+            "algorithmic_bytes_per_launch": bytes_launch, "apply_achieved_GBs": apply_bytes / apply_s / 1e9,
+            "apply_avg_us": apply_s * 1e6}
 
+
+def bench_sequence(args, cap, torch):
+    """Learned vs plain warm start on held-out frames of a 300-frame sequence."""
     import numpy as np
-    import torch
 
-    import paper_1810_02648_amd as cap
+    import synth.sequence
+    from paper_1810_02648_amd import sequence as sq
+
+    log("generating sequence", args.workload)
+    seq = synth.sequence.make_sequence(args.workload, 0)
+    ctx = cap.Context(0)
+    S = sq.DeviceSequence(ctx, seq)
+    log("plain tracking over %d frames" % S.n)
+    states, _ = sq.track_plain(S)
+    ntr = seq["n_train"]
+    X, Y = sq.training_set(S, states, range(1, ntr))
+    net = cap.WarmStart(ctx, S.nn, sq.init_params(0))
+    log("training the warm start on %d frames" % len(X))
+    t0 = time.perf_counter()
+    losses = sq.train(S, net, X, Y, epochs=args.epochs, lr=1e-3, log=log)
+    t_train = time.perf_counter() - t0
+    test = list(range(ntr, S.n))
+    for _ in range(args.warmup):
+        sq.evaluate(S, net, states, test)
+    log("timing %d passes over %d held-out frames" % (args.steps, len(test)))
+    tp = tl = 0.0
+    ev = None
+    for _ in range(args.steps):
+        ev = sq.evaluate(S, net, states, test)
+        tp += ev["t_plain"]
+        tl += ev["t_learned"]
+    n = len(test) * args.steps
+    # per-kernel times of one learned pass
+    cap.profile_enable(ctx, True)
+    cap.profile_read(ctx)
+    sq.evaluate(S, net, states, test)
+    prof = cap.profile_read(ctx)
+    cap.profile_enable(ctx, False)
+    W, H = seq["cam"].width, seq["cam"].height
+    n_act = cap.nonrigid_solve(ctx, S.frame(test[0], states[test[0] - 1].clone()), S.prm)["n_visible"]
+    n_edges = int((S.graph["edge_dst"] >= 0).sum().item())
+    calls = 2 * len(test)    # one evaluate pass = one plain and one learned solve per frame
+    roof = roofline_for(prof, calls, 1, n_act, S.nn, n_edges, W, H, seq["tri"].shape[1], seq["xyz"].shape[1])
+    return {
+        "metric": METRIC,
+        "value": n / tl,
+        "unit": "frames/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1000.0 * tl / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": "%s: %d-frame sequence, %d-vertex template, %d-node graph, %dx%d targets, %d GN x %d PCG; "
+                        "train frames 1-%d, held-out frames %d-%d; one step = all held-out frames solved from "
+                        "the learned start until the plain schedule's final energy"
+                        % (args.workload, S.n, seq["xyz"].shape[1], S.nn, W, H, seq["gn"], seq["pcg"], ntr - 1,
+                           ntr, S.n - 1),
+            "plain_frames_per_s": n / tp,
+            "speedup_vs_plain": tp / tl,
+            "mean_gn_steps_plain": float(np.mean(ev["plain_steps"])),
+            "mean_gn_steps_learned": float(np.mean(ev["learned_steps"])),
+            "target_reached_fraction": float(np.mean(ev["reached"])),
+            "prediction_used_fraction": float(np.mean(ev["used_prediction"])),
+            "train_epochs": args.epochs,
+            "train_seconds": t_train,
+            "train_loss_first_last": [losses[0], losses[-1]],
+        },
+        "roofline": roof,
+        "kernel_avg_us": {k: round(1000.0 * ms / c, 3) for k, (ms, c) in prof.items() if c},
+    }, seq
+
+
+def bench_frame(args, cap, torch):
+    """Single frames (or a batch of independent frames) from the rest state."""
     import synth
-
-    wl = synth.CONFIGS[args.workload]
     log("building workload", args.workload)
     f = synth.make_nonrigid_frame(args.workload, 0)
     nn, gn, pcg = f["n_nodes"], f["gn"], f["pcg"]
@@ -111,7 +183,6 @@ def main():
             fr.node_state.copy_(start)
         return cap.batch_solve(ctx, frames, prm)
 
-    log("warmup", args.warmup)
     for _ in range(args.warmup):
         reps = step()
     torch.cuda.synchronize()
@@ -121,9 +192,6 @@ def main():
         reps = step()
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
-    log("timed %.3f s" % elapsed)
-
-    # per-kernel times from events around every launch, in a second pass of the same steps
     cap.profile_enable(ctx, True)
     cap.profile_read(ctx)
     for _ in range(args.steps):
@@ -131,21 +199,12 @@ def main():
     torch.cuda.synchronize()
     prof = cap.profile_read(ctx)
     cap.profile_enable(ctx, False)
-    kernel_us = {k: round(1000.0 * ms / n, 3) for k, (ms, n) in prof.items() if n}
-    per_step_us = {k: 1000.0 * ms / args.steps for k, (ms, n) in prof.items() if n}
-    dom = max(per_step_us, key=per_step_us.get)
     r0 = reps[0]
-    n_act = r0["n_visible"]
-    n_edges = int((graph["edge_dst"] >= 0).sum().item())
     W, H = f["cam"].width, f["cam"].height
-    bytes_launch = args.batch * algorithmic_bytes(dom, n_act, nn, n_edges, W * H, f["tri"].shape[1],
-                                                  f["xyz"].shape[1])
-    avg_s = prof[dom][0] / 1000.0 / prof[dom][1]
-    achieved = bytes_launch / avg_s / 1e9
-    apply_s = prof["apply"][0] / 1000.0 / max(prof["apply"][1], 1)
-    apply_bytes = args.batch * algorithmic_bytes("apply", n_act, nn, n_edges, W * H, 0, 0)
-
-    result = {
+    n_edges = int((graph["edge_dst"] >= 0).sum().item())
+    roof = roofline_for(prof, args.steps, args.batch, r0["n_visible"], nn, n_edges, W, H, f["tri"].shape[1],
+                        f["xyz"].shape[1])
+    return {
         "metric": METRIC,
         "value": args.steps * args.batch / elapsed,
         "unit": "frames/s",
@@ -160,30 +219,54 @@ def main():
         "data": "synthetic",
         "config": {
             "workload": "%s: %d-vertex ellipsoid template, %d-node deformation graph, %dx%d silhouette/colour "
-                        "targets, %d GN x %d PCG, plain start (rest state); learned warm start not in this line"
+                        "targets, %d GN x %d PCG, plain start (rest state)"
                         % (args.workload, f["xyz"].shape[1], nn, W, H, gn, pcg),
             "batch": args.batch,
-            "visible_vertices": n_act,
+            "visible_vertices": r0["n_visible"],
             "final_energy": r0["energy"][-1],
             "start_energy": r0["energy"][0],
         },
-        "roofline": {
-            "bound": "hbm",
-            "kernel": dom,
-            "achieved": achieved,
-            "peak": HBM_PEAK_GBS,
-            "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS,
-            "traffic": None,
-            "avg_us": avg_s * 1e6,
-            "algorithmic_bytes_per_launch": bytes_launch,
-            "apply_achieved": apply_bytes / apply_s / 1e9,
-        },
-        "kernel_avg_us": kernel_us,
-    }
+        "roofline": roof,
+        "kernel_avg_us": {k: round(1000.0 * ms / n, 3) for k, (ms, n) in prof.items() if n},
+    }, f
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--mode", default="sequence", choices=["sequence", "frame"])
+    ap.add_argument("--workload", default=None,
+                    help="sequence: seq20k (default) or seq_small; frame: frame20k (default), small, stress200k")
+    ap.add_argument("--batch", type=int, default=1, help="frame mode: independent frames solved together per step")
+    ap.add_argument("--epochs", type=int, default=40, help="sequence mode: training epochs")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: the solver has no multi-GPU path "
+              "(independent captures would shard one per GPU with no communication)", file=sys.stderr)
+        sys.exit(2)
+    if args.workload is None:
+        args.workload = "seq20k" if args.mode == "sequence" else "frame20k"
+
+    import torch
+
+    import paper_1810_02648_amd as cap
+
+    if args.mode == "sequence":
+        result, data = bench_sequence(args, cap, torch)
+    else:
+        result, data = bench_frame(args, cap, torch)
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")
-        result["cpu_baseline"] = cpu_baseline(f, nn, gn, pcg, f["weights"])
+        if args.mode == "sequence":
+            t = data["n_train"]
+            fr = dict(xyz=data["posed"][t], tri=data["tri"], rgb=data["rgb"], cam=data["cam"],
+                      mask=data["masks"][t], image=data["images"][t])
+            result["cpu_baseline"] = cpu_baseline(fr, data["n_nodes"], data["gn"], data["pcg"], data["weights"])
+        else:
+            result["cpu_baseline"] = cpu_baseline(data, data["n_nodes"], data["gn"], data["pcg"], data["weights"])
     print(json.dumps(result), flush=True)
 
 

@@ -122,22 +122,35 @@ typedef struct {
 } capture_frame;
 
 /* Weights and schedule.  E = w_photo*sum||sigma_c(I_Gauss(pi(V_i)) - C_i)||^2
- *  + w_sil*sum b_i I_DT(pi(V_i))^2 + w_arap*sum||R_k(g_l - g_k) + g_k + t_k - g_l - t_l||^2.
+ *  + w_sil*sum b_i I_DT(pi(V_i))^2 + w_arap*sum||R_k(g_l - g_k) + g_k + t_k - g_l - t_l||^2
+ *  + w_vel*sum_i ||V_i - V_i^a||^2.
  * tau_color: the photometric robust-kernel threshold (residual set to zero when
- * the colour difference norm exceeds it); +inf or 0 disables it. */
+ * the colour difference norm exceeds it); +inf or 0 disables it.
+ * w_vel: the paper's temporal prior E_velocity (Sec. 3.4) over all vertices, with
+ * the previous frame's result carried to the current pose: V^a is the input
+ * mesh deformed by the start node state (the previous frame's solution);
+ * 0 disables it.
+ * CAPTURE_FLAG_EXCLUDE_CASE2: contour vertices in the paper's case 2 (inside the
+ * image silhouette with the normal opposing z, b_i = -1) get no silhouette
+ * residual instead of the literal -I_DT^2, which is unbounded below. */
+#define CAPTURE_FLAG_EXCLUDE_CASE2 1u
 typedef struct {
-    float w_sil, w_photo, w_arap, tau_color;
+    float w_sil, w_photo, w_arap, tau_color, w_vel;
     int32_t gn_iters;          /* 1..CAPTURE_MAX_GN */
     int32_t pcg_iters;         /* >= 0 Jacobi-PCG iterations per Gauss-Newton step */
-    uint32_t flags;            /* reserved, 0 */
+    uint32_t flags;            /* CAPTURE_FLAG_* */
 } capture_nonrigid_params;
 
 /* Host-side report of one solve. */
 typedef struct {
-    double energy[CAPTURE_MAX_GN + 1];    /* E at the start of each GN step, then the final E */
-    double e_photo, e_sil, e_sil_abs, e_arap;  /* final per-term energies (e_sil_abs: with |b_i|) */
+    double energy[CAPTURE_MAX_GN + 1];    /* E at the start of each GN step taken, then the final E
+                                             (entries 0..gn_done are valid) */
+    double e_photo, e_sil, e_sil_abs, e_arap, e_vel;  /* final per-term energies (e_sil_abs: with |b_i|) */
+    double energy_prev, energy_pred;      /* warm start only: E at the given state, E at the predicted start */
     int32_t n_visible, n_boundary;        /* |visible set|, |contour set| */
     int32_t gn_done;                      /* Gauss-Newton steps taken */
+    int32_t warm_start;                   /* 0 plain start; 1 predicted start used; 2 predicted start
+                                             rejected (higher energy), solve ran from the given state */
     int32_t status;                       /* CAPTURE_OK or a device-detected error */
 } capture_report;
 
@@ -183,17 +196,84 @@ CAPTURE_API int capture_frame_decisions(capture_ctx *ctx, const capture_frame *f
  *   diag  [6][n_nodes]  diagonal of J^T |B| J
  *   p     [6][n_nodes]  input direction (may be NULL: no product)
  *   Ap    [6][n_nodes]  out: J^T |B| J p
- *   energy (host, 4 doubles): photo, sil (with b_i), sil with |b_i|, arap */
+ *   energy (host, 5 doubles): photo, sil (with b_i), sil with |b_i|, arap, velocity */
 CAPTURE_API int capture_linearize(capture_ctx *ctx, const capture_frame *frame, const capture_nonrigid_params *params,
                       float *rhs, float *diag, const float *p, float *Ap, double *energy,
                       void *workspace, size_t workspace_bytes, void *stream);
+
+/* --------------------------------------------------------------------------
+ * Learned warm start.  A per-node network (shared weights) with two rounds of
+ * mean message passing over the node graph predicts the start update of a
+ * frame from the previous frame's node parameters and per-node statistics of
+ * the new frame's linearisation at those parameters; the paper's plain start
+ * (the previous frame's result, Sec. 3.4) stays the fallback.  Layers:
+ *   h1 = ReLU(W1 x + b1) (32 -> 128), m1 = mean over out-neighbours of h1,
+ *   h2 = ReLU(W2 [h1; m1] + b2) (256 -> 128), m2 = mean of h2,
+ *   y = W3 [h2; m2] + b3 (256 -> 6); update = y * (0.05, 0.05, 0.05 rad, 0.01, 0.01, 0.01 m).
+ * Parameter vector (float32, host order): W1 [128][32], b1 [128], W2 [128][256],
+ * b2 [128], W3 [6][256], b3 [6]; CAPTURE_WS_PARAMS values.  Matrix products
+ * run on BF16 MFMA with float32 accumulation; master weights and Adam state are
+ * float32 (Adam: beta 0.9 / 0.999, eps 1e-8).
+ * Features per node (32 floats, [n_nodes][32], zero-padded after 27):
+ *   axis-angle of R_k, t_k, change of both since frame t-2 (0 without it),
+ *   sign(b) log(1 + |b|) of b = -J^T B F (6), log(1 + diag(J^T |B| J)) (6),
+ *   node position minus the mean node position (3).
+ * ------------------------------------------------------------------------ */
+#define CAPTURE_WS_PARAMS 38662
+#define CAPTURE_WS_FEATURES 32
+
+typedef struct capture_warmstart capture_warmstart;
+
+/* Network with the given initial parameters (host, CAPTURE_WS_PARAMS floats),
+ * activation buffers for up to max_nodes nodes (library-owned device memory). */
+CAPTURE_API int capture_warmstart_create(capture_ctx *ctx, int32_t max_nodes, const float *params,
+                                         capture_warmstart **out);
+CAPTURE_API void capture_warmstart_destroy(capture_warmstart *net);
+/* Feature standardisation (host, 27 means and 27 standard deviations > 0). */
+CAPTURE_API int capture_warmstart_set_scaling(capture_warmstart *net, const float *mean, const float *stddev);
+/* Current float32 parameters (host, CAPTURE_WS_PARAMS) and Adam step count. */
+CAPTURE_API int capture_warmstart_get_params(capture_warmstart *net, float *params, int64_t *adam_steps);
+
+/* Fit the feature standardisation to `rows` raw feature rows (device,
+ * [rows][32], e.g. all nodes of all training frames): per-feature mean and
+ * standard deviation (floored at 1e-6). */
+CAPTURE_API int capture_warmstart_fit_scaling(capture_ctx *ctx, capture_warmstart *net, const float *features,
+                                              int64_t rows, void *stream);
+/* Training target [n_nodes][6] (device): per node (dw, dt) with
+ * R_next = Exp(dw) R_prev, t_next = t_prev + dt, divided by (0.05, 0.05, 0.05, 0.01, 0.01, 0.01). */
+CAPTURE_API int capture_warmstart_target(capture_ctx *ctx, int32_t n_nodes, const float *state_prev,
+                                         const float *state_next, float *target, void *stream);
+/* Raw (unstandardised) features [n_nodes][32] at the frame's node_state
+ * (device output); state_prev2: [12][n_nodes] node state of frame t-2, or NULL. */
+CAPTURE_API int capture_warmstart_features(capture_ctx *ctx, const capture_frame *frame, const float *state_prev2,
+                                           const capture_nonrigid_params *params, float *features,
+                                           void *workspace, size_t workspace_bytes, void *stream);
+/* Network output y [n_nodes][6] (scaled units) for raw features of a template's nodes. */
+CAPTURE_API int capture_warmstart_forward(capture_ctx *ctx, capture_warmstart *net, const capture_template *tmpl,
+                                          const float *features, float *y, void *stream);
+/* One training step on one frame: loss = mean (y - target)^2 over the n_nodes x 6
+ * outputs (target in scaled units, [n_nodes][6] device).  grads (device,
+ * CAPTURE_WS_PARAMS floats) receives the gradient if not NULL; with `update` the
+ * Adam step is applied.  *loss (host) receives the loss before the update. */
+CAPTURE_API int capture_warmstart_train_step(capture_ctx *ctx, capture_warmstart *net, const capture_template *tmpl,
+                                             const float *features, const float *target, float lr, int update,
+                                             float *grads, double *loss, void *stream);
+/* Non-rigid solve started by the network: decisions and linearisation at the
+ * frame's node_state (the previous frame's result), predicted start x',
+ * energies at both; the lower one starts Gauss-Newton, which stops at the
+ * start of the first step whose energy is <= target_energy (pass -inf for the
+ * full schedule).  report->warm_start tells which start was used. */
+CAPTURE_API int capture_nonrigid_solve_warm(capture_ctx *ctx, const capture_frame *frame,
+                                            const capture_nonrigid_params *params, capture_warmstart *net,
+                                            const float *state_prev2, double target_energy, capture_report *report,
+                                            void *workspace, size_t workspace_bytes, void *stream);
 
 /* --------------------------------------------------------------------------
  * Kernel timing.  While enabled, every launch of the solver kernels is
  * bracketed by HIP events on the call's stream; elapsed times accumulate per
  * kernel until read.  Kernel names: "blur", "contour", "dt_cols", "dt_rows",
  * "deform_start", "raster", "contour_edges", "decide", "linearize",
- * "node_init", "apply", "node_pcg".
+ * "node_init", "apply", "node_pcg", "ws_features", "ws_mlp".
  * ------------------------------------------------------------------------ */
 CAPTURE_API int capture_profile_enable(capture_ctx *ctx, int on);
 /* Accumulated time (ms) and launch count of `kernel` since the last read;

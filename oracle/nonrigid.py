@@ -14,8 +14,17 @@ possible regulariser on graph edges):
             ||I_Gauss - C_i||_2 > tau_c (tau_c = inf disables it);
     sil:    r_i = sqrt(w_sil) I_DT(pi(V_i)), i in B, direction weight b_i;
     ARAP:   r_kl = sqrt(w_arap) (R_k (g_l - g_k) + g_k + t_k - g_l - t_l), directed edges.
+    velocity (optional, w_vel > 0): r_i = sqrt(w_vel) (V_i - V_i^a) for every vertex,
+            the paper's temporal prior (Sec. 3.4, E_velocity) with V^{t-1} carried
+            to the current frame by the start state: V^a is the input mesh
+            deformed by the start node state (the float32 start positions of
+            the decision recipe), i.e. the previous frame's result displaced
+            onto the current pose;
 E = sum b r^2 with b = 1 except the silhouette rows (the paper's energy, which
-has negative terms when b_i = -1).  Gauss-Newton (Sec. 4, Eq. gaussnewton)
+has negative terms when b_i = -1).  With case2="exclude" the silhouette rows of
+b_i = -1 vertices are dropped instead (b = 0): the literal term is unbounded
+below and, with decisions frozen for the frame, Gauss-Newton doubles such a
+vertex's distance to the contour at every step.  Gauss-Newton (Sec. 4, Eq. gaussnewton)
 solves  (J^T |B| J) delta = -J^T B F  with B = diag(b): the system matrix uses
 |b| so that it stays positive semi-definite.
 
@@ -91,7 +100,7 @@ class Problem:
     """One non-rigid frame: inputs plus the frozen per-frame decisions."""
 
     def __init__(self, xyz, tri, rgb, graph, cam, mask, image, weights, tau_c=np.inf,
-                 state0=None):
+                 state0=None, w_vel=0.0, case2="push"):
         self.xyz, self.tri, self.rgb, self.graph, self.cam = xyz, tri, rgb, graph, cam
         self.w_sil, self.w_photo, self.w_arap = (float(w) for w in weights)
         self.tau_c = float(tau_c)
@@ -106,6 +115,11 @@ class Problem:
         self.vis_idx = np.nonzero(self.dec["visible"])[0]
         self.bnd_idx = np.nonzero(self.dec["boundary"])[0]
         self.bsign = self.dec["bsign"][self.bnd_idx].astype(np.float64)
+        if case2 == "exclude":
+            keep = self.bsign > 0
+            self.bnd_idx, self.bsign = self.bnd_idx[keep], self.bsign[keep]
+        self.w_vel = float(w_vel)
+        self.anchor = np.stack([self.dec["X"], self.dec["Y"], self.dec["Z"]]).astype(np.float64)
         self.nn = nn
         ed = graph["edge_dst"]
         src = np.repeat(np.arange(nn)[None, :], ed.shape[0], axis=0)
@@ -123,7 +137,7 @@ class Problem:
         P = projection_jacobian(V, cam)
         rows_F, rows_b, trip = [], [], []
         row0 = 0
-        e = dict(photo=0.0, sil=0.0, sil_abs=0.0, arap=0.0)
+        e = dict(photo=0.0, sil=0.0, sil_abs=0.0, arap=0.0, vel=0.0)
 
         # photometric rows
         vid = self.vis_idx
@@ -170,6 +184,25 @@ class Problem:
                 trip.append((np.repeat(rr, 6), cols.ravel(), vals.ravel()))
         row0 += vid.size
 
+        # velocity rows (all vertices)
+        if self.w_vel > 0:
+            sw = np.sqrt(self.w_vel)
+            r_v = sw * (V - self.anchor)
+            e["vel"] = float((r_v ** 2).sum())
+            vid = np.arange(V.shape[1])
+            if need_jacobian:
+                blocks = _vertex_cols(self.graph, q, vid)
+            for c in range(3):
+                rows_F.append(r_v[c])
+                rows_b.append(np.ones(vid.size))
+                if need_jacobian:
+                    rr = row0 + np.arange(vid.size)
+                    for k, M in blocks:
+                        vals = sw * M[:, c, :]
+                        cols = 6 * k[:, None] + np.arange(6)[None, :]
+                        trip.append((np.repeat(rr, 6), cols.ravel(), vals.ravel()))
+                row0 += vid.size
+
         # ARAP rows
         g = self.xyz.astype(np.float64)[:, self.graph["node_vertex"]]
         st = state.astype(np.float64)
@@ -198,7 +231,7 @@ class Problem:
             row0 += 3 * ne
         F = np.concatenate(rows_F)
         b = np.concatenate(rows_b)
-        e["total"] = e["photo"] + e["sil"] + e["arap"]
+        e["total"] = e["photo"] + e["sil"] + e["arap"] + e["vel"]
         J = None
         if need_jacobian:
             r = np.concatenate([x[0] for x in trip])

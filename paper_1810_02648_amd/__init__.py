@@ -123,8 +123,10 @@ class FrameInputs:
                           _ptr(self.image), _ptr(self.node_state))
 
 
-def params(w_sil=1.0, w_photo=0.1, w_arap=10.0, gn_iters=5, pcg_iters=10, tau_color=math.inf):
-    return capi.NonrigidParams(w_sil, w_photo, w_arap, tau_color, gn_iters, pcg_iters, 0)
+def params(w_sil=1.0, w_photo=0.1, w_arap=10.0, gn_iters=5, pcg_iters=10, tau_color=math.inf, w_vel=0.0,
+           exclude_case2=False):
+    return capi.NonrigidParams(w_sil, w_photo, w_arap, tau_color, w_vel, gn_iters, pcg_iters,
+                               capi.FLAG_EXCLUDE_CASE2 if exclude_case2 else 0)
 
 
 def _frames(frames):
@@ -142,9 +144,10 @@ def workspace_bytes(ctx, frames):
 
 
 def _report_dict(r, gn):
-    return dict(energy=[r.energy[k] for k in range(gn + 1)], e_photo=r.e_photo, e_sil=r.e_sil,
-                e_sil_abs=r.e_sil_abs, e_arap=r.e_arap, n_visible=r.n_visible,
-                n_boundary=r.n_boundary, gn_done=r.gn_done, status=r.status)
+    return dict(energy=[r.energy[k] for k in range(r.gn_done + 1)], e_photo=r.e_photo, e_sil=r.e_sil,
+                e_sil_abs=r.e_sil_abs, e_arap=r.e_arap, e_vel=r.e_vel, n_visible=r.n_visible,
+                n_boundary=r.n_boundary, gn_done=r.gn_done, status=r.status, warm_start=r.warm_start,
+                energy_prev=r.energy_prev, energy_pred=r.energy_pred)
 
 
 def batch_solve(ctx, frames, prm):
@@ -184,7 +187,7 @@ def frame_decisions(ctx, frame):
 
 
 def linearize(ctx, frame, prm, p=None):
-    """rhs, diag (and A p) at the frame's node_state, plus the 4 energy terms."""
+    """rhs, diag (and A p) at the frame's node_state, plus the 5 energy terms."""
     arr = _frames([frame])
     ws = ctx.workspace(workspace_bytes(ctx, [frame]))
     nn = frame.template.nn
@@ -194,7 +197,7 @@ def linearize(ctx, frame, prm, p=None):
     Ap = torch.empty((6, nn), dtype=torch.float32, device=dev) if p is not None else None
     if p is not None:
         _need(p, torch.float32, (6, nn), "p")
-    e = (C.c_double * 4)()
+    e = (C.c_double * 5)()
     capi.check(ctx.lib.capture_linearize(ctx.h, arr, C.byref(prm), _ptr(rhs), _ptr(diag), _ptr(p), _ptr(Ap), e,
                                          _ptr(ws), ws.numel(), _stream()))
     return dict(rhs=rhs, diag=diag, Ap=Ap, energy=list(e))
@@ -214,3 +217,93 @@ def profile_read(ctx):
         capi.check(ctx.lib.capture_profile_read(ctx.h, name.encode(), C.byref(ms), C.byref(n)))
         out[name] = (ms.value, n.value)
     return out
+
+
+class WarmStart:
+    """The learned warm-start network (library-owned weights and Adam state)."""
+
+    def __init__(self, ctx, max_nodes, params):
+        import numpy as np
+        self.ctx = ctx
+        w = np.ascontiguousarray(np.asarray(params, dtype=np.float32))
+        if w.size != capi.WS_PARAMS:
+            raise ValueError("need %d parameters" % capi.WS_PARAMS)
+        h = C.c_void_p()
+        capi.check(ctx.lib.capture_warmstart_create(ctx.h, max_nodes, w.ctypes.data_as(C.c_void_p), C.byref(h)))
+        self.h = h
+
+    def __del__(self):
+        try:
+            if self.h:
+                self.ctx.lib.capture_warmstart_destroy(self.h)
+                self.h = None
+        except Exception:
+            pass
+
+    def set_scaling(self, mean, std):
+        import numpy as np
+        m = np.ascontiguousarray(np.asarray(mean, np.float32)[:27])
+        s = np.ascontiguousarray(np.asarray(std, np.float32)[:27])
+        capi.check(self.ctx.lib.capture_warmstart_set_scaling(self.h, m.ctypes.data_as(C.c_void_p),
+                                                              s.ctypes.data_as(C.c_void_p)))
+
+    def fit_scaling(self, features):
+        _need(features, torch.float32, (features.shape[0], 32), "features")
+        capi.check(self.ctx.lib.capture_warmstart_fit_scaling(self.ctx.h, self.h, _ptr(features),
+                                                              features.shape[0], _stream()))
+
+    def params(self):
+        import numpy as np
+        out = np.zeros(capi.WS_PARAMS, np.float32)
+        steps = C.c_int64()
+        capi.check(self.ctx.lib.capture_warmstart_get_params(self.h, out.ctypes.data_as(C.c_void_p),
+                                                             C.byref(steps)))
+        return out, steps.value
+
+    def forward(self, template, features):
+        _need(features, torch.float32, (template.nn, 32), "features")
+        y = torch.empty((template.nn, 6), dtype=torch.float32, device=features.device)
+        capi.check(self.ctx.lib.capture_warmstart_forward(self.ctx.h, self.h, template.h, _ptr(features), _ptr(y),
+                                                          _stream()))
+        return y
+
+    def train_step(self, template, features, target, lr=1e-3, update=True, grads=None):
+        _need(features, torch.float32, (template.nn, 32), "features")
+        _need(target, torch.float32, (template.nn, 6), "target")
+        if grads is not None:
+            _need(grads, torch.float32, (capi.WS_PARAMS,), "grads")
+        loss = C.c_double()
+        capi.check(self.ctx.lib.capture_warmstart_train_step(self.ctx.h, self.h, template.h, _ptr(features),
+                                                             _ptr(target), lr, 1 if update else 0, _ptr(grads),
+                                                             C.byref(loss), _stream()))
+        return loss.value
+
+
+def warmstart_features(ctx, frame, prm, state_prev2=None):
+    """Raw features [n_nodes][32] at the frame's node_state."""
+    arr = _frames([frame])
+    ws = ctx.workspace(workspace_bytes(ctx, [frame]))
+    X = torch.empty((frame.template.nn, 32), dtype=torch.float32, device=frame.xyz.device)
+    capi.check(ctx.lib.capture_warmstart_features(ctx.h, arr, _ptr(state_prev2), C.byref(prm), _ptr(X), _ptr(ws),
+                                                  ws.numel(), _stream()))
+    return X
+
+
+def warmstart_target(ctx, state_prev, state_next):
+    nn = state_prev.shape[1]
+    _need(state_prev, torch.float32, (12, nn), "state_prev")
+    _need(state_next, torch.float32, (12, nn), "state_next")
+    t = torch.empty((nn, 6), dtype=torch.float32, device=state_prev.device)
+    capi.check(ctx.lib.capture_warmstart_target(ctx.h, nn, _ptr(state_prev), _ptr(state_next), _ptr(t), _stream()))
+    return t
+
+
+def nonrigid_solve_warm(ctx, frame, prm, net, state_prev2=None, target_energy=-math.inf):
+    """Solve from the network's predicted start (or the frame's state when that is better)."""
+    arr = _frames([frame])
+    ws = ctx.workspace(workspace_bytes(ctx, [frame]))
+    rep = capi.Report()
+    capi.check(ctx.lib.capture_nonrigid_solve_warm(ctx.h, arr, C.byref(prm), net.h, _ptr(state_prev2),
+                                                   float(target_energy), C.byref(rep), _ptr(ws), ws.numel(),
+                                                   _stream()))
+    return _report_dict(rep, prm.gn_iters)

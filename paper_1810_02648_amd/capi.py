@@ -27,14 +27,19 @@ class Frame(C.Structure):
 
 class NonrigidParams(C.Structure):
     _fields_ = [("w_sil", C.c_float), ("w_photo", C.c_float), ("w_arap", C.c_float),
-                ("tau_color", C.c_float), ("gn_iters", C.c_int32), ("pcg_iters", C.c_int32),
-                ("flags", C.c_uint32)]
+                ("tau_color", C.c_float), ("w_vel", C.c_float), ("gn_iters", C.c_int32),
+                ("pcg_iters", C.c_int32), ("flags", C.c_uint32)]
+
+
+FLAG_EXCLUDE_CASE2 = 1
 
 
 class Report(C.Structure):
     _fields_ = [("energy", C.c_double * (MAX_GN + 1)), ("e_photo", C.c_double), ("e_sil", C.c_double),
-                ("e_sil_abs", C.c_double), ("e_arap", C.c_double), ("n_visible", C.c_int32),
-                ("n_boundary", C.c_int32), ("gn_done", C.c_int32), ("status", C.c_int32)]
+                ("e_sil_abs", C.c_double), ("e_arap", C.c_double), ("e_vel", C.c_double),
+                ("energy_prev", C.c_double),
+                ("energy_pred", C.c_double), ("n_visible", C.c_int32), ("n_boundary", C.c_int32),
+                ("gn_done", C.c_int32), ("warm_start", C.c_int32), ("status", C.c_int32)]
 
 
 _P = C.c_void_p
@@ -53,12 +58,26 @@ SIGNATURES = {
     "capture_frame_decisions": (C.c_int, [_P, C.POINTER(Frame), _P, _P, _P, _P, _P, C.c_size_t, _P]),
     "capture_linearize": (C.c_int, [_P, C.POINTER(Frame), C.POINTER(NonrigidParams), _P, _P, _P, _P,
                                     C.POINTER(C.c_double), _P, C.c_size_t, _P]),
+    "capture_warmstart_create": (C.c_int, [_P, C.c_int32, _P, C.POINTER(C.c_void_p)]),
+    "capture_warmstart_destroy": (None, [_P]),
+    "capture_warmstart_set_scaling": (C.c_int, [_P, _P, _P]),
+    "capture_warmstart_get_params": (C.c_int, [_P, _P, C.POINTER(C.c_int64)]),
+    "capture_warmstart_fit_scaling": (C.c_int, [_P, _P, _P, C.c_int64, _P]),
+    "capture_warmstart_target": (C.c_int, [_P, C.c_int32, _P, _P, _P, _P]),
+    "capture_warmstart_features": (C.c_int, [_P, C.POINTER(Frame), _P, C.POINTER(NonrigidParams), _P, _P,
+                                             C.c_size_t, _P]),
+    "capture_warmstart_forward": (C.c_int, [_P, _P, _P, _P, _P, _P]),
+    "capture_warmstart_train_step": (C.c_int, [_P, _P, _P, _P, _P, C.c_float, C.c_int, _P,
+                                               C.POINTER(C.c_double), _P]),
+    "capture_nonrigid_solve_warm": (C.c_int, [_P, C.POINTER(Frame), C.POINTER(NonrigidParams), _P, _P,
+                                              C.c_double, C.POINTER(Report), _P, C.c_size_t, _P]),
     "capture_profile_enable": (C.c_int, [_P, C.c_int]),
     "capture_profile_read": (C.c_int, [_P, C.c_char_p, C.POINTER(C.c_double), C.POINTER(C.c_int64)]),
 }
 
 KERNELS = ("blur", "contour", "dt_cols", "dt_rows", "deform_start", "raster", "contour_edges", "decide",
-           "linearize", "node_init", "apply", "node_pcg")
+           "linearize", "node_init", "apply", "node_pcg", "ws_features", "ws_mlp")
+WS_PARAMS = 38662
 
 _lib = None
 

@@ -13,6 +13,7 @@ namespace cap {
 __global__ void k_fill_u32(uint32_t *p, size_t n, uint32_t v);
 __global__ void k_blur(const ProbDev *P, int pass, float w0, float w1);
 __global__ void k_contour(const ProbDev *P);
+__global__ void k_dt_seg(const ProbDev *P);
 __global__ void k_dt_cols(const ProbDev *P);
 __global__ void k_dt_rows(const ProbDev *P);
 __global__ void k_deform_start(const ProbDev *P);
@@ -21,10 +22,28 @@ __global__ void k_contour_edges(const ProbDev *P);
 __global__ void k_decide(const ProbDev *P);
 __global__ void k_linearize(const ProbDev *P, int mode);
 __global__ void k_apply(const ProbDev *P);
-__global__ void k_node_init(const ProbDev *P, int gn, int energy_only);
+__global__ void k_node_init(const ProbDev *P, int gn, int energy_only, int check_target);
 __global__ void k_node_gather(const ProbDev *P);
+__global__ void k_scatter_p(const ProbDev *P);
 __global__ void k_node_pcg(const ProbDev *P, int last, int update_only);
+__global__ void k_scal_init(const ProbDev *P, int gn_iters);
 int build_template(const capture_template_desc *d, capture_template **out, int device);
+
+// warm-start kernels (warmstart.hip)
+__global__ void k_gemm(Gemm g);
+__global__ void k_mean_fwd(const float *z, int nn, const int *edge_dst, uint16_t *cat, int width);
+__global__ void k_mean_bwd(const float *dcat, const float *z, int nn, const int *in_beg, const int *in_src,
+                           const int *out_cnt, uint16_t *dzb, float *dz, int width);
+__global__ void k_colsum(const float *in, int rows, int cols, float *out);
+__global__ void k_mse_grad(const float *y, const float *t, int n, float *dy, uint16_t *dyb, float *se);
+__global__ void k_adam(float *w, const float *g, float *m, float *v, uint16_t *wb, int n, float lr, float c1, float c2);
+__global__ void k_to_bf16(const float *in, uint16_t *out, int n);
+__global__ void k_standardise(const float *X, int nn, const float *mu, const float *sd, uint16_t *Xb);
+__global__ void k_ws_features(const ProbDev *P, const float *prev2, float *X);
+__global__ void k_ws_delta(const ProbDev *P, const float *y);
+__global__ void k_ws_select(const ProbDev *P, int slot_prev, int slot_pred);
+__global__ void k_ws_target(const float *prev, const float *next, int nn, float *target);
+__global__ void k_ws_scaling(const float *X, long long rows, float *mu, float *sd);
 
 namespace {
 thread_local std::string g_err;
@@ -177,6 +196,9 @@ void carve(Layout &L, uint8_t *base, const capture_frame &f, ProbDev &pr) {
     pr.blurred = L.take<float>(base, 3 * hw);
     pr.dt = L.take<float>(base, hw);
     pr.colg = L.take<int>(base, hw);
+    const size_t nseg = (size_t(f.camera.height) + 15) / 16 * size_t(f.camera.width);
+    pr.seg_first = L.take<int>(base, nseg);
+    pr.seg_last = L.take<int>(base, nseg);
     pr.zbuf = L.take<uint32_t>(base, hw);
     pr.contour = L.take<uint8_t>(base, hw);
     pr.dx = L.take<float>(base, 3 * nv);
@@ -191,7 +213,10 @@ void carve(Layout &L, uint8_t *base, const capture_frame &f, ProbDev &pr) {
     pr.vcode = L.take<uint8_t>(base, nv);
     pr.Hm = L.take<float>(base, 6 * nv);
     pr.partial = L.take<float>(base, size_t(T.nslots) * 12);
-    pr.tile_e = L.take<double>(base, size_t(T.ntiles) * 4);
+    pr.spack = L.take<float>(base, size_t(T.nslots) * 12);
+    pr.pslot = L.take<float>(base, size_t(T.nslots) * 6);
+    pr.tile_e = L.take<double>(base, size_t(T.ntiles) * kTerms);
+    pr.pva = L.take<float>(base, 3 * nv);
     float **vecs[8] = {&pr.b, &pr.diag, &pr.dinv, &pr.x, &pr.r, &pr.z, &pr.p, &pr.Ap};
     for (float **v : vecs) *v = L.take<float>(base, 6 * nn);
     pr.scal = L.take<double>(base, kScalars);
@@ -238,8 +263,10 @@ int check_params(const capture_nonrigid_params *p) {
     if (!p) return fail(CAPTURE_EINVAL, "null params");
     if (p->gn_iters < 1 || p->gn_iters > CAPTURE_MAX_GN) return fail(CAPTURE_EINVAL, "gn_iters must be in [1, 32]");
     if (p->pcg_iters < 0 || p->pcg_iters > 10000) return fail(CAPTURE_EINVAL, "pcg_iters must be in [0, 10000]");
-    if (!finite(p->w_sil) || !finite(p->w_photo) || !finite(p->w_arap) || p->w_sil < 0 || p->w_photo < 0 || p->w_arap < 0)
+    if (!finite(p->w_sil) || !finite(p->w_photo) || !finite(p->w_arap) || !finite(p->w_vel) || p->w_sil < 0 ||
+        p->w_photo < 0 || p->w_arap < 0 || p->w_vel < 0)
         return fail(CAPTURE_EINVAL, "weights must be finite and non-negative");
+    if (p->flags & ~uint32_t(CAPTURE_FLAG_EXCLUDE_CASE2)) return fail(CAPTURE_EINVAL, "unknown flag bits");
     if (std::isnan(p->tau_color) || p->tau_color < 0) return fail(CAPTURE_EINVAL, "tau_color must be >= 0 or +inf");
     return CAPTURE_OK;
 }
@@ -258,7 +285,8 @@ struct Run {
 };
 
 const char *kKernelNames[K_COUNT] = {"blur", "contour", "dt_cols", "dt_rows", "deform_start", "raster",
-                                     "contour_edges", "decide", "linearize", "node_init", "apply", "node_pcg"};
+                                     "contour_edges", "decide", "linearize", "node_init", "apply", "node_pcg",
+                                     "ws_features", "ws_mlp"};
 
 // Launch `go` bracketed by events when timing is on.
 template <typename F>
@@ -310,6 +338,8 @@ int setup(Run &R, capture_ctx *ctx, int n, const capture_frame *frames, const ca
     const float wsil = params ? params->w_sil : 1.0f, wph = params ? params->w_photo : 0.1f,
                 war = params ? params->w_arap : 10.0f;
     const float tau = params ? (params->tau_color > 0 ? params->tau_color : INFINITY) : INFINITY;
+    const float wvel = params ? params->w_vel : 0.0f;
+    const int excl = params ? int(params->flags & CAPTURE_FLAG_EXCLUDE_CASE2) : 0;
     for (int i = 0; i < n; ++i) {
         const capture_frame &f = frames[i];
         ProbDev &pr = R.probs[i];
@@ -319,6 +349,8 @@ int setup(Run &R, capture_ctx *ctx, int n, const capture_frame *frames, const ca
         pr.fx = f.camera.fx; pr.fy = f.camera.fy; pr.cx = f.camera.cx; pr.cy = f.camera.cy;
         pr.sw_sil = std::sqrt(wsil); pr.sw_photo = std::sqrt(wph); pr.sw_arap = std::sqrt(war);
         pr.w_arap = war; pr.tau = tau;
+        pr.w_vel = wvel; pr.sw_vel = std::sqrt(wvel); pr.exclude_case2 = excl;
+        pr.target = -INFINITY;
         const TemplateDev &T = pr.T;
         R.max_nv = std::max(R.max_nv, T.nv);
         R.max_nf = std::max(R.max_nf, T.nf);
@@ -336,9 +368,10 @@ int setup(Run &R, capture_ctx *ctx, int n, const capture_frame *frames, const ca
 
 unsigned blocks(size_t n, unsigned t) { return unsigned((n + t - 1) / t); }
 
-int launch_frame(Run &R) {
+int launch_frame(Run &R, int gn_iters = 0) {
     const int n = R.n;
     hipStream_t s = R.s;
+    hipLaunchKernelGGL(k_scal_init, dim3(n), dim3(64), 0, s, R.dprobs, gn_iters);
     for (int i = 0; i < n; ++i) {
         const ProbDev &pr = R.probs[i];
         hipLaunchKernelGGL(k_fill_u32, dim3(blocks(size_t(pr.W) * pr.H, 256)), dim3(256), 0, s, pr.zbuf,
@@ -358,11 +391,13 @@ int launch_frame(Run &R) {
     timed(R, K_CONTOUR, [&] {
     hipLaunchKernelGGL(k_contour, gpx, dim3(256), 0, s, R.dprobs);
     });
+    const size_t nsegw = size_t(R.max_w) * ((R.max_h + 15) / 16);
     timed(R, K_DT_COLS, [&] {
-    hipLaunchKernelGGL(k_dt_cols, dim3(blocks(R.max_w, 64), n), dim3(64), 0, s, R.dprobs);
+        hipLaunchKernelGGL(k_dt_seg, dim3(blocks(nsegw, 256), n), dim3(256), 0, s, R.dprobs);
+        hipLaunchKernelGGL(k_dt_cols, dim3(blocks(nsegw, 256), n), dim3(256), 0, s, R.dprobs);
     });
     timed(R, K_DT_ROWS, [&] {
-    hipLaunchKernelGGL(k_dt_rows, dim3(R.max_h, n), dim3(256), sizeof(int) * R.max_w, s, R.dprobs);
+        hipLaunchKernelGGL(k_dt_rows, dim3(R.max_h, n), dim3(256), sizeof(int) * 3 * R.max_w, s, R.dprobs);
     });
     timed(R, K_DEFORM, [&] {
     hipLaunchKernelGGL(k_deform_start, gv, dim3(256), 0, s, R.dprobs);
@@ -380,19 +415,20 @@ int launch_frame(Run &R) {
     return CAPTURE_OK;
 }
 
-void launch_linearize(Run &R, int gn, int energy_only) {
+void launch_linearize(Run &R, int gn, int energy_only, int check_target = 0) {
     timed(R, K_LIN, [&] {
-    hipLaunchKernelGGL(k_linearize, dim3(R.max_tiles, R.n), dim3(kTileThreads), R.lds_lin, R.s, R.dprobs,
+        hipLaunchKernelGGL(k_linearize, dim3(R.max_tiles, R.n), dim3(kTileThreads), R.lds_lin, R.s, R.dprobs,
                            energy_only);
     });
     timed(R, K_NODE_INIT, [&] {
-    hipLaunchKernelGGL(k_node_init, dim3(R.n), dim3(kNodeThreads), 0, R.s, R.dprobs, gn, energy_only);
+        hipLaunchKernelGGL(k_node_init, dim3(R.n), dim3(kNodeThreads), 0, R.s, R.dprobs, gn, energy_only,
+                           check_target);
     });
 }
 
-int launch_solve(Run &R, const capture_nonrigid_params *prm) {
+int launch_solve(Run &R, const capture_nonrigid_params *prm, int check_target = 0) {
     for (int gn = 0; gn < prm->gn_iters; ++gn) {
-        launch_linearize(R, gn, 0);
+        launch_linearize(R, gn, 0, check_target);
         for (int j = 0; j < prm->pcg_iters; ++j) {
             timed(R, K_APPLY, [&] {
     hipLaunchKernelGGL(k_apply, dim3(R.max_tiles, R.n), dim3(kTileThreads), R.lds_apply, R.s, R.dprobs);
@@ -427,16 +463,67 @@ int collect(Run &R, int gn_iters, capture_report *reports) {
         capture_report &rep = reports[i];
         std::memset(&rep, 0, sizeof(rep));
         const double *sc = scal.data() + size_t(kScalars) * i;
-        for (int k = 0; k <= gn_iters; ++k) rep.energy[k] = sc[8 + 4 * k] + sc[8 + 4 * k + 1] + sc[8 + 4 * k + 3];
-        const double *e = sc + 8 + 4 * gn_iters;
-        rep.e_photo = e[0]; rep.e_sil = e[1]; rep.e_sil_abs = e[2]; rep.e_arap = e[3];
+        const int done = std::min(gn_iters, std::max(0, int(sc[3])));
+        for (int k = 0; k <= done; ++k) {
+            const double *ek = sc + 8 + kTerms * k;
+            rep.energy[k] = ek[0] + ek[1] + ek[3] + ek[4];
+        }
+        const double *e = sc + 8 + kTerms * done;
+        rep.e_photo = e[0]; rep.e_sil = e[1]; rep.e_sil_abs = e[2]; rep.e_arap = e[3]; rep.e_vel = e[4];
         rep.n_visible = counts[2 * i];
         rep.n_boundary = counts[2 * i + 1];
-        rep.gn_done = gn_iters;
-        rep.status = std::isfinite(rep.energy[gn_iters]) ? CAPTURE_OK : CAPTURE_ENONFINITE;
+        rep.gn_done = done;
+        rep.status = std::isfinite(rep.energy[done]) ? CAPTURE_OK : CAPTURE_ENONFINITE;
         if (rep.status) status = rep.status;
     }
     return status;
+}
+
+
+// ---------------------------------------------------------------- warm-start network
+constexpr int kOffW1 = 0, kOffB1 = 4096, kOffW2 = 4224, kOffB2 = 36992, kOffW3 = 37120, kOffB3 = 38656;
+constexpr int kParams = CAPTURE_WS_PARAMS;
+static_assert(kOffB3 + 6 == kParams, "parameter layout");
+
+void gemm(hipStream_t s, const uint16_t *A, long long sai, long long sak, const uint16_t *B, long long sbj,
+          long long sbk, float *C, long long sci, long long scj, int M, int N, int K, const float *bias,
+          uint16_t *Cb = nullptr, long long scbi = 0) {
+    Gemm g{A, sai, sak, B, sbj, sbk, C, sci, scj, M, N, K, bias, Cb, scbi, Cb ? 1 : 0};
+    const int tiles = ((M + 15) / 16) * ((N + 15) / 16);
+    hipLaunchKernelGGL(k_gemm, dim3((tiles + 3) / 4), dim3(256), 0, s, g);
+}
+
+// Forward pass on raw features X (device, [nn][32]) -> net->y [nn][6].
+void ws_forward(capture_warmstart *net, const TemplateDev &T, const float *X, hipStream_t s) {
+    const int nn = T.nn;
+    hipLaunchKernelGGL(k_standardise, dim3(blocks(size_t(nn) * 32, 256)), dim3(256), 0, s, X, nn, net->mu, net->sd,
+                       net->Xb);
+    gemm(s, net->Xb, 32, 1, net->wb + kOffW1, 32, 1, net->z1, 128, 1, nn, 128, 32, net->w + kOffB1, net->c1, 256);
+    hipLaunchKernelGGL(k_mean_fwd, dim3(blocks(size_t(nn) * 128, 256)), dim3(256), 0, s, net->z1, nn, T.edge_dst,
+                       net->c1, 128);
+    gemm(s, net->c1, 256, 1, net->wb + kOffW2, 256, 1, net->z2, 128, 1, nn, 128, 256, net->w + kOffB2, net->c2, 256);
+    hipLaunchKernelGGL(k_mean_fwd, dim3(blocks(size_t(nn) * 128, 256)), dim3(256), 0, s, net->z2, nn, T.edge_dst,
+                       net->c2, 128);
+    gemm(s, net->c2, 256, 1, net->wb + kOffW3, 256, 1, net->y, 6, 1, nn, 6, 256, net->w + kOffB3);
+}
+
+// Backward pass after ws_forward, with targets in net->tgt; gradients into net->g.
+void ws_backward(capture_warmstart *net, const TemplateDev &T, hipStream_t s) {
+    const int nn = T.nn;
+    hipLaunchKernelGGL(k_mse_grad, dim3(blocks(size_t(nn) * 6, 256)), dim3(256), 0, s, net->y, net->tgt, nn * 6,
+                       net->dy, net->dyb, net->se);
+    gemm(s, net->dyb, 1, 6, net->c2, 1, 256, net->g + kOffW3, 256, 1, 6, 256, nn, nullptr);
+    hipLaunchKernelGGL(k_colsum, dim3(1), dim3(64), 0, s, net->dy, nn, 6, net->g + kOffB3);
+    gemm(s, net->dyb, 6, 1, net->wb + kOffW3, 1, 256, net->dc, 256, 1, nn, 256, 6, nullptr);
+    hipLaunchKernelGGL(k_mean_bwd, dim3(blocks(size_t(nn) * 128, 256)), dim3(256), 0, s, net->dc, net->z2, nn,
+                       T.in_beg, T.in_src, T.out_cnt, net->dzb, net->dz, 128);
+    gemm(s, net->dzb, 1, 128, net->c1, 1, 256, net->g + kOffW2, 256, 1, 128, 256, nn, nullptr);
+    hipLaunchKernelGGL(k_colsum, dim3(1), dim3(128), 0, s, net->dz, nn, 128, net->g + kOffB2);
+    gemm(s, net->dzb, 128, 1, net->wb + kOffW2, 1, 256, net->dc, 256, 1, nn, 256, 128, nullptr);
+    hipLaunchKernelGGL(k_mean_bwd, dim3(blocks(size_t(nn) * 128, 256)), dim3(256), 0, s, net->dc, net->z1, nn,
+                       T.in_beg, T.in_src, T.out_cnt, net->dzb, net->dz, 128);
+    gemm(s, net->dzb, 1, 128, net->Xb, 1, 32, net->g + kOffW1, 32, 1, 128, 32, nn, nullptr);
+    hipLaunchKernelGGL(k_colsum, dim3(1), dim3(128), 0, s, net->dz, nn, 128, net->g + kOffB1);
 }
 
 }  // namespace cap
@@ -516,7 +603,7 @@ int capture_batch_solve(capture_ctx *ctx, int32_t n, const capture_frame *frames
     for (int i = 0; i < n; ++i)
         CAP_HIP(hipMemcpyAsync(R.probs[i].state0, frames[i].node_state, sizeof(float) * 12 * R.probs[i].T.nn,
                                hipMemcpyDeviceToDevice, R.s));
-    if ((rc = launch_frame(R))) return rc;
+    if ((rc = launch_frame(R, params->gn_iters))) return rc;
     if ((rc = launch_solve(R, params))) return rc;
     rc = collect(R, params->gn_iters, reports);
     if (rc) {
@@ -571,6 +658,7 @@ int capture_linearize(capture_ctx *ctx, const capture_frame *frame, const captur
         const double zero = 0.0;
         CAP_HIP(hipMemcpyAsync(pr.p, p, sizeof(float) * n6, hipMemcpyDeviceToDevice, R.s));
         CAP_HIP(hipMemcpyAsync(pr.scal + 1, &zero, sizeof(double), hipMemcpyHostToDevice, R.s));
+        hipLaunchKernelGGL(k_scatter_p, dim3(1), dim3(kNodeThreads), 0, R.s, R.dprobs);
         timed(R, K_APPLY, [&] {
     hipLaunchKernelGGL(k_apply, dim3(R.max_tiles, 1), dim3(kTileThreads), R.lds_apply, R.s, R.dprobs);
         });
@@ -584,7 +672,217 @@ int capture_linearize(capture_ctx *ctx, const capture_frame *frame, const captur
     CAP_HIP(hipMemcpyAsync(sc, pr.scal, sizeof(sc), hipMemcpyDeviceToHost, R.s));
     CAP_HIP(hipStreamSynchronize(R.s));
     settle(R);
-    if (energy) for (int q = 0; q < 4; ++q) energy[q] = sc[8 + q];
+    if (energy) for (int q = 0; q < kTerms; ++q) energy[q] = sc[8 + q];
+    return CAPTURE_OK;
+}
+
+
+int capture_warmstart_create(capture_ctx *ctx, int32_t max_nodes, const float *params, capture_warmstart **out) {
+    if (!ctx || !params || !out) return fail(CAPTURE_EINVAL, "null argument");
+    if (max_nodes < 1 || max_nodes > 65536) return fail(CAPTURE_EINVAL, "max_nodes must be in [1, 65536]");
+    for (int i = 0; i < kParams; ++i)
+        if (!std::isfinite(params[i])) return fail(CAPTURE_ENONFINITE, "non-finite initial parameter");
+    CAP_HIP(hipSetDevice(ctx->device));
+    const size_t nn = size_t(max_nodes);
+    Layout L;
+    auto plan = [&](uint8_t *base, capture_warmstart *n) {
+        L.off = 0;
+        n->w = L.take<float>(base, kParams); n->g = L.take<float>(base, kParams);
+        n->m = L.take<float>(base, kParams); n->v = L.take<float>(base, kParams);
+        n->wb = L.take<uint16_t>(base, kParams);
+        n->mu = L.take<float>(base, 32); n->sd = L.take<float>(base, 32);
+        n->X = L.take<float>(base, nn * 32); n->Xb = L.take<uint16_t>(base, nn * 32);
+        n->z1 = L.take<float>(base, nn * 128); n->c1 = L.take<uint16_t>(base, nn * 256);
+        n->z2 = L.take<float>(base, nn * 128); n->c2 = L.take<uint16_t>(base, nn * 256);
+        n->y = L.take<float>(base, nn * 6); n->tgt = L.take<float>(base, nn * 6);
+        n->dy = L.take<float>(base, nn * 6); n->dyb = L.take<uint16_t>(base, nn * 6);
+        n->se = L.take<float>(base, nn * 6); n->dc = L.take<float>(base, nn * 256);
+        n->dz = L.take<float>(base, nn * 128); n->dzb = L.take<uint16_t>(base, nn * 128);
+    };
+    capture_warmstart tmp{};
+    plan(nullptr, &tmp);
+    void *mem = nullptr;
+    if (hipMalloc(&mem, L.off) != hipSuccess) return fail(CAPTURE_ENOMEM, "warm start: device allocation failed");
+    capture_warmstart *n = new capture_warmstart{};
+    n->device = ctx->device;
+    n->max_nodes = max_nodes;
+    n->mem = mem;
+    plan(static_cast<uint8_t *>(mem), n);
+    std::vector<float> zeros(kParams, 0.0f), one(32, 1.0f), zero32(32, 0.0f);
+    hipError_t e = hipMemcpy(n->w, params, sizeof(float) * kParams, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(n->m, zeros.data(), sizeof(float) * kParams, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(n->v, zeros.data(), sizeof(float) * kParams, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(n->mu, zero32.data(), sizeof(float) * 32, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(n->sd, one.data(), sizeof(float) * 32, hipMemcpyHostToDevice);
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL(k_to_bf16, dim3(blocks(kParams, 256)), dim3(256), 0, nullptr, n->w, n->wb, kParams);
+        e = hipDeviceSynchronize();
+    }
+    if (e != hipSuccess) {
+        (void)hipFree(mem);
+        delete n;
+        return fail(CAPTURE_EHIP, std::string("warm start: ") + hipGetErrorString(e));
+    }
+    *out = n;
+    return CAPTURE_OK;
+}
+
+void capture_warmstart_destroy(capture_warmstart *net) {
+    if (!net) return;
+    (void)hipFree(net->mem);
+    delete net;
+}
+
+int capture_warmstart_set_scaling(capture_warmstart *net, const float *mean, const float *stddev) {
+    if (!net || !mean || !stddev) return fail(CAPTURE_EINVAL, "null argument");
+    for (int i = 0; i < 27; ++i)
+        if (!std::isfinite(mean[i]) || !std::isfinite(stddev[i]) || !(stddev[i] > 0.0f))
+            return fail(CAPTURE_EINVAL, "scaling: means must be finite and deviations positive");
+    CAP_HIP(hipSetDevice(net->device));
+    CAP_HIP(hipMemcpy(net->mu, mean, sizeof(float) * 27, hipMemcpyHostToDevice));
+    CAP_HIP(hipMemcpy(net->sd, stddev, sizeof(float) * 27, hipMemcpyHostToDevice));
+    return CAPTURE_OK;
+}
+
+int capture_warmstart_get_params(capture_warmstart *net, float *params, int64_t *adam_steps) {
+    if (!net) return fail(CAPTURE_EINVAL, "null argument");
+    CAP_HIP(hipSetDevice(net->device));
+    if (params) CAP_HIP(hipMemcpy(params, net->w, sizeof(float) * kParams, hipMemcpyDeviceToHost));
+    if (adam_steps) *adam_steps = net->steps;
+    return CAPTURE_OK;
+}
+
+int capture_warmstart_target(capture_ctx *ctx, int32_t n_nodes, const float *state_prev, const float *state_next,
+                             float *target, void *stream) {
+    if (!ctx || !state_prev || !state_next || !target) return fail(CAPTURE_EINVAL, "null argument");
+    if (n_nodes < 1) return fail(CAPTURE_EINVAL, "n_nodes must be >= 1");
+    CAP_HIP(hipSetDevice(ctx->device));
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    hipLaunchKernelGGL(k_ws_target, dim3(blocks(n_nodes, 256)), dim3(256), 0, s, state_prev, state_next, n_nodes,
+                       target);
+    CAP_HIP(hipGetLastError());
+    CAP_HIP(hipStreamSynchronize(s));
+    return CAPTURE_OK;
+}
+
+int capture_warmstart_fit_scaling(capture_ctx *ctx, capture_warmstart *net, const float *features, int64_t rows,
+                                  void *stream) {
+    if (!ctx || !net || !features) return fail(CAPTURE_EINVAL, "null argument");
+    if (rows < 1) return fail(CAPTURE_EINVAL, "rows must be >= 1");
+    CAP_HIP(hipSetDevice(ctx->device));
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    hipLaunchKernelGGL(k_ws_scaling, dim3(27), dim3(256), 0, s, features, (long long)rows, net->mu, net->sd);
+    CAP_HIP(hipGetLastError());
+    CAP_HIP(hipStreamSynchronize(s));
+    return CAPTURE_OK;
+}
+
+int capture_warmstart_features(capture_ctx *ctx, const capture_frame *frame, const float *state_prev2,
+                               const capture_nonrigid_params *params, float *features, void *workspace,
+                               size_t workspace_bytes, void *stream) {
+    if (!ctx || !params || !features) return fail(CAPTURE_EINVAL, "null argument");
+    CAP_HIP(hipSetDevice(ctx->device));
+    Run R;
+    int rc = setup(R, ctx, 1, frame, params, workspace, workspace_bytes, stream);
+    if (rc) return rc;
+    if ((rc = launch_frame(R))) return rc;
+    launch_linearize(R, 0, 0);
+    timed(R, K_WS_FEAT, [&] {
+        hipLaunchKernelGGL(k_ws_features, dim3(blocks(R.probs[0].T.nn, 256), 1), dim3(256), 0, R.s, R.dprobs,
+                           state_prev2, features);
+    });
+    CAP_HIP(hipGetLastError());
+    CAP_HIP(hipStreamSynchronize(R.s));
+    settle(R);
+    return CAPTURE_OK;
+}
+
+int capture_warmstart_forward(capture_ctx *ctx, capture_warmstart *net, const capture_template *tmpl,
+                              const float *features, float *y, void *stream) {
+    if (!ctx || !net || !tmpl || !features || !y) return fail(CAPTURE_EINVAL, "null argument");
+    if (tmpl->dev.nn > net->max_nodes) return fail(CAPTURE_EINVAL, "template has more nodes than the network's max_nodes");
+    CAP_HIP(hipSetDevice(ctx->device));
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    ws_forward(net, tmpl->dev, features, s);
+    CAP_HIP(hipGetLastError());
+    CAP_HIP(hipMemcpyAsync(y, net->y, sizeof(float) * 6 * tmpl->dev.nn, hipMemcpyDeviceToDevice, s));
+    CAP_HIP(hipStreamSynchronize(s));
+    return CAPTURE_OK;
+}
+
+int capture_warmstart_train_step(capture_ctx *ctx, capture_warmstart *net, const capture_template *tmpl,
+                                 const float *features, const float *target, float lr, int update, float *grads,
+                                 double *loss, void *stream) {
+    if (!ctx || !net || !tmpl || !features || !target) return fail(CAPTURE_EINVAL, "null argument");
+    if (tmpl->dev.nn > net->max_nodes) return fail(CAPTURE_EINVAL, "template has more nodes than the network's max_nodes");
+    if (!(lr >= 0.0f) || !std::isfinite(lr)) return fail(CAPTURE_EINVAL, "lr must be finite and >= 0");
+    CAP_HIP(hipSetDevice(ctx->device));
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const int nn = tmpl->dev.nn;
+    CAP_HIP(hipMemcpyAsync(net->tgt, target, sizeof(float) * 6 * nn, hipMemcpyDeviceToDevice, s));
+    ws_forward(net, tmpl->dev, features, s);
+    ws_backward(net, tmpl->dev, s);
+    if (grads) CAP_HIP(hipMemcpyAsync(grads, net->g, sizeof(float) * kParams, hipMemcpyDeviceToDevice, s));
+    if (update) {
+        net->steps += 1;
+        const float c1 = float(1.0 - std::pow(0.9, double(net->steps)));
+        const float c2 = float(1.0 - std::pow(0.999, double(net->steps)));
+        hipLaunchKernelGGL(k_adam, dim3(blocks(kParams, 256)), dim3(256), 0, s, net->w, net->g, net->m, net->v,
+                           net->wb, kParams, lr, c1, c2);
+    }
+    CAP_HIP(hipGetLastError());
+    std::vector<float> se(size_t(6) * nn);
+    CAP_HIP(hipMemcpyAsync(se.data(), net->se, sizeof(float) * se.size(), hipMemcpyDeviceToHost, s));
+    CAP_HIP(hipStreamSynchronize(s));
+    if (loss) {
+        double acc = 0.0;
+        for (float v : se) acc += v;
+        *loss = acc / double(se.size());
+    }
+    return CAPTURE_OK;
+}
+
+int capture_nonrigid_solve_warm(capture_ctx *ctx, const capture_frame *frame, const capture_nonrigid_params *params,
+                                capture_warmstart *net, const float *state_prev2, double target_energy,
+                                capture_report *report, void *workspace, size_t workspace_bytes, void *stream) {
+    if (!ctx || !params || !net || !report) return fail(CAPTURE_EINVAL, "null argument");
+    if (std::isnan(target_energy)) return fail(CAPTURE_EINVAL, "target_energy is NaN");
+    CAP_HIP(hipSetDevice(ctx->device));
+    Run R;
+    int rc = setup(R, ctx, 1, frame, params, workspace, workspace_bytes, stream);
+    if (rc) return rc;
+    if (R.probs[0].T.nn > net->max_nodes) return fail(CAPTURE_EINVAL, "template has more nodes than the network's max_nodes");
+    R.probs[0].target = target_energy;
+    CAP_HIP(hipMemcpyAsync(R.dprobs, R.probs.data(), sizeof(ProbDev), hipMemcpyHostToDevice, R.s));
+    const ProbDev &pr = R.probs[0];
+    const int pred_slot = CAPTURE_MAX_GN + 1;
+    CAP_HIP(hipMemcpyAsync(pr.state0, frame->node_state, sizeof(float) * 12 * pr.T.nn, hipMemcpyDeviceToDevice, R.s));
+    if ((rc = launch_frame(R, params->gn_iters))) return rc;
+    // linearisation at the previous frame's state: features and E(x_{t-1})
+    launch_linearize(R, 0, 0);
+    timed(R, K_WS_FEAT, [&] {
+        hipLaunchKernelGGL(k_ws_features, dim3(blocks(pr.T.nn, 256), 1), dim3(256), 0, R.s, R.dprobs, state_prev2,
+                           net->X);
+    });
+    timed(R, K_WS_MLP, [&] {
+        ws_forward(net, pr.T, net->X, R.s);
+        hipLaunchKernelGGL(k_ws_delta, dim3(blocks(size_t(6) * pr.T.nn, 256), 1), dim3(256), 0, R.s, R.dprobs, net->y);
+    });
+    hipLaunchKernelGGL(k_node_pcg, dim3(1), dim3(kNodeThreads), 0, R.s, R.dprobs, 0, 1);   // x' = x (+) delta
+    launch_linearize(R, pred_slot, 1);
+    hipLaunchKernelGGL(k_ws_select, dim3(1), dim3(256), 0, R.s, R.dprobs, 0, pred_slot);
+    if ((rc = launch_solve(R, params, 1))) return rc;
+    std::vector<double> sc(kScalars);
+    CAP_HIP(hipMemcpyAsync(sc.data(), pr.scal, sizeof(double) * kScalars, hipMemcpyDeviceToHost, R.s));
+    rc = collect(R, params->gn_iters, report);
+    report->energy_pred = sc[4];
+    report->energy_prev = sc[6];
+    report->warm_start = sc[5] != 0.0 ? 2 : 1;
+    if (rc) {
+        (void)hipMemcpyAsync(frame->node_state, pr.state0, sizeof(float) * 12 * pr.T.nn, hipMemcpyDeviceToDevice, R.s);
+        (void)hipStreamSynchronize(R.s);
+        return fail(rc, "non-finite energy; node state restored");
+    }
     return CAPTURE_OK;
 }
 

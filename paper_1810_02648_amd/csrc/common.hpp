@@ -30,7 +30,8 @@ constexpr int kMaxTileContrib = 1024; // contributions held in LDS per tile
 constexpr int kMaxTileSlots = 200;    // distinct nodes touched by a tile
 constexpr int kNodeThreads = 1024;    // threads of a per-problem node workgroup
 constexpr int kMaxImageSide = 4096;
-constexpr int kScalars = 8 + 4 * (CAPTURE_MAX_GN + 1);
+constexpr int kTerms = 5;   // energy terms per slot: photo, sil (with b), sil (with |b|), arap, velocity
+constexpr int kScalars = 8 + kTerms * (CAPTURE_MAX_GN + 2);   // slot MAX_GN + 1: predicted start
 
 // Static per-template data in library-owned device memory (plan order =
 // vertices grouped by their nearest node, nodes in breadth-first order of the
@@ -56,10 +57,14 @@ struct TemplateDev {
     const int *list_beg;       // [nslots+1] into list_idx
     const uint16_t *list_idx;  // tile-local contribution indices, grouped by slot
     const int *node_pbeg;      // [nn+1] into node_pidx
-    const int *node_pidx;      // global slot indices (partials) of each node, tile order
+    const int *node_pidx;      // global slot indices of each node, tile order (node-major positions)
+    const int *slot_dest;      // [nslots] node-major position of each slot's partial
     const int *vf_beg;         // [nv+1] vertex -> incident faces
     const int *vf_face;        // [3nf] ascending per vertex
     const int *medge;          // [4][nmedges]: a, b, f0, f1 (-1 = border)
+    const int *in_beg;         // [nn+1] node graph in-edges (source nodes), ascending
+    const int *in_src;         // [..]
+    const int *out_cnt;        // [nn] number of valid out-edges
 };
 
 // One problem (frame) of a batch: template, frame inputs and its workspace.
@@ -72,10 +77,12 @@ struct ProbDev {
     float *state;
     int W, H;
     float fx, fy, cx, cy;
-    float sw_sil, sw_photo, sw_arap, w_arap, tau;
+    float sw_sil, sw_photo, sw_arap, w_arap, tau, w_vel, sw_vel;
+    int exclude_case2;
     // images
     float *blur_tmp, *blurred, *dt;
     int *colg;
+    int *seg_first, *seg_last;   // [ceil(H/16)][W]
     uint32_t *zbuf;
     uint8_t *contour;
     // vertices (vertex order)
@@ -90,22 +97,42 @@ struct ProbDev {
     // vertices (plan order)
     float *px;        // [3][nv]
     float *pc;        // [3][nv]
-    uint8_t *vcode;   // [nv]
+    uint8_t *vcode;   // [nv] bit0 visible, bit1 silhouette residual, bit2 b_i = -1, bit3 velocity term
+    float *pva;       // [3][nv] velocity anchor: start positions (float32 recipe)
     float *Hm;        // [6][nv]
     // tiles / slots
-    float *partial;   // [nslots][12]
-    double *tile_e;   // [ntiles][4]
+    float *partial;   // [nslots][12], node-major positions (node_pbeg ranges)
+    float *spack;     // [nslots][12] per slot: R (9) and node position (3) of the current GN step
+    float *pslot;     // [nslots][6] per slot: the PCG direction p of its node
+    double *tile_e;   // [ntiles][kTerms]
     // nodes
     float *b, *diag, *dinv, *x, *r, *z, *p, *Ap;   // [6][nn]
-    double *scal;     // [kScalars]: rz, done, ..., energies [4] per GN step
+    double *scal;     // [kScalars]: rz, done, stopped, stop step, ..., kTerms energies per GN step
     int *counts;      // [2]
     float *state0;    // [12][nn] copy of the start state (restored on a device-detected error)
+    double target;    // stop once the energy at the start of a GN step is <= target (-inf: never)
+};
+
+// Arguments of the warm-start network's MFMA GEMM: C(i, j) = sum_k A(i, k) B(j, k)
+// [+ bias(j)], bf16 operands with arbitrary strides; optional bf16 ReLU copy.
+struct Gemm {
+    const uint16_t *A;
+    long long sai, sak;
+    const uint16_t *B;
+    long long sbj, sbk;
+    float *C;
+    long long sci, scj;
+    int M, N, K;
+    const float *bias;
+    uint16_t *Cb;
+    long long scbi;
+    int relu_copy;
 };
 
 // Optional per-kernel timing with HIP events (capture_profile_*).
 enum KernelId {
     K_BLUR, K_CONTOUR, K_DT_COLS, K_DT_ROWS, K_DEFORM, K_RASTER, K_CEDGES, K_DECIDE,
-    K_LIN, K_NODE_INIT, K_APPLY, K_NODE_PCG, K_COUNT
+    K_LIN, K_NODE_INIT, K_APPLY, K_NODE_PCG, K_WS_FEAT, K_WS_MLP, K_COUNT
 };
 
 struct Profiler {
@@ -122,6 +149,16 @@ struct Profiler {
 struct capture_ctx {
     int device;
     cap::Profiler prof;
+};
+
+struct capture_warmstart {
+    int device, max_nodes;
+    long long steps;
+    void *mem;
+    float *w, *g, *m, *v, *mu, *sd;
+    uint16_t *wb;
+    float *X, *z1, *z2, *y, *tgt, *dy, *se, *dc, *dz;
+    uint16_t *Xb, *c1, *c2, *dyb, *dzb;
 };
 
 struct capture_template {

@@ -108,17 +108,18 @@ __device__ inline void cell_of(double u, int &i, float &f) {
     if (f >= 1.0f) f = 0.99999994f;
 }
 
-// Deterministic block-wide sum of a double (fixed tree over threads).
+// Deterministic block-wide sum of a double: fixed butterfly inside each wave,
+// then the wave sums in wave order.  `sh` holds NT/64 doubles.
 template <int NT>
 __device__ inline double block_sum(double v, double *sh) {
-    sh[threadIdx.x] = v;
-    __syncthreads();
 #pragma unroll
-    for (int s = NT / 2; s > 0; s >>= 1) {
-        if (int(threadIdx.x) < s) sh[threadIdx.x] += sh[threadIdx.x + s];
-        __syncthreads();
-    }
-    double r = sh[0];
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    if (lane == 0) sh[wid] = v;
+    __syncthreads();
+    double r = 0.0;
+#pragma unroll
+    for (int w = 0; w < NT / 64; ++w) r += sh[w];
     __syncthreads();
     return r;
 }

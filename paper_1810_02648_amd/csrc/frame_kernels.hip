@@ -57,51 +57,130 @@ __global__ void k_contour(const ProbDev *__restrict__ P) {
 }
 
 constexpr int kFar = 1 << 20;
+constexpr int kSeg = 16;   // rows per column segment
 
-// Phase 1: per column, distance (rows) to the nearest contour pixel in the column.
+// Phase 1a: per (column, 16-row segment), the first and last contour row.
+__global__ void k_dt_seg(const ProbDev *__restrict__ P) {
+    const ProbDev &pr = P[blockIdx.y];
+    const int W = pr.W, H = pr.H, nseg = (H + kSeg - 1) / kSeg;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= W * nseg) return;
+    const int s = i / W, x = i - s * W;
+    int first = kFar, last = -kFar;
+    const int y0 = s * kSeg, y1 = min(H, y0 + kSeg);
+    for (int y = y0; y < y1; ++y)
+        if (pr.contour[size_t(y) * W + x]) { first = min(first, y); last = y; }
+    pr.seg_first[i] = first;
+    pr.seg_last[i] = last;
+}
+
+// Phase 1b: per (column, segment), distance in rows to the nearest contour
+// pixel of the column (carry from the other segments, then the segment's rows).
 __global__ void k_dt_cols(const ProbDev *__restrict__ P) {
     const ProbDev &pr = P[blockIdx.y];
-    const int W = pr.W, H = pr.H;
-    int x = blockIdx.x * blockDim.x + threadIdx.x;
-    if (x >= W) return;
-    const uint8_t *c = pr.contour + x;
-    int *g = pr.colg + x;
-    int last = -kFar;
-    for (int y = 0; y < H; ++y) {
-        if (c[size_t(y) * W]) last = y;
-        g[size_t(y) * W] = y - last;
+    const int W = pr.W, H = pr.H, nseg = (H + kSeg - 1) / kSeg;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= W * nseg) return;
+    const int s = i / W, x = i - s * W;
+    int above = -kFar, below = 2 * kFar;
+    for (int t = s - 1; t >= 0; --t) {
+        const int l = pr.seg_last[t * W + x];
+        if (l >= 0) { above = l; break; }
     }
-    int next = 2 * kFar;
-    for (int y = H - 1; y >= 0; --y) {
-        if (c[size_t(y) * W]) next = y;
-        int d = next - y;
-        int cur = g[size_t(y) * W];
-        g[size_t(y) * W] = d < cur ? d : cur;
+    for (int t = s + 1; t < nseg; ++t) {
+        const int f = pr.seg_first[t * W + x];
+        if (f < kFar) { below = f; break; }
+    }
+    const int y0 = s * kSeg, y1 = min(H, y0 + kSeg);
+    int d[kSeg];
+    uint8_t c[kSeg];
+#pragma unroll
+    for (int k = 0; k < kSeg; ++k) c[k] = (y0 + k < y1) ? pr.contour[size_t(y0 + k) * W + x] : 0;
+    int last = above;
+#pragma unroll
+    for (int k = 0; k < kSeg; ++k) {
+        if (c[k]) last = y0 + k;
+        d[k] = y0 + k - last;
+    }
+    int next = below;
+#pragma unroll
+    for (int k = kSeg - 1; k >= 0; --k) {
+        if (c[k]) next = y0 + k;
+        const int dd = next - (y0 + k);
+        if (y0 + k < y1) pr.colg[size_t(y0 + k) * W + x] = dd < d[k] ? dd : d[k];
     }
 }
 
-// Phase 2: per row, d^2(x) = min over x' of (x - x')^2 + g(x')^2, searched
-// outwards from x until (x - x')^2 reaches the best value (exact).
-__global__ void k_dt_rows(const ProbDev *__restrict__ P) {
-    extern __shared__ int G[];
+// Phase 2: per row, D(x) = min over x' of (x - x')^2 + g(x')^2, exact.  The
+// leftmost minimiser is non-decreasing in x ((x - x')^2 is a Monge cost), so
+// x is solved in dyadic order, each inside the bracket of minimisers of its
+// two already-solved neighbours.  One workgroup per row, all in LDS.
+__device__ inline void argmin_merge(int &v, int &a, int ov, int oa) {
+    if (ov < v || (ov == v && oa < a)) { v = ov; a = oa; }
+}
+
+__global__ __launch_bounds__(256) void k_dt_rows(const ProbDev *__restrict__ P) {
+    extern __shared__ int sh[];
     const ProbDev &pr = P[blockIdx.y];
     const int W = pr.W, H = pr.H;
     const int y = blockIdx.x;
     if (y >= H) return;
+    int *G = sh, *val = sh + W, *arg = sh + 2 * W;
+    __shared__ int wv[4], wa[4];
     const int far2 = 1 << 30;
     for (int x = threadIdx.x; x < W; x += blockDim.x) {
-        int g = pr.colg[size_t(y) * W + x];
+        const int g = pr.colg[size_t(y) * W + x];
         G[x] = g >= kFar ? far2 : g * g;
     }
     __syncthreads();
-    for (int x = threadIdx.x; x < W; x += blockDim.x) {
-        int best = G[x];
-        for (int r = 1; r < W && r * r < best; ++r) {
-            int rr = r * r;
-            if (x - r >= 0) { int c = rr + G[x - r]; best = c < best ? c : best; }
-            if (x + r < W) { int c = rr + G[x + r]; best = c < best ? c : best; }
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    // x = 0 over the whole row
+    {
+        int v = 0x7fffffff, a = 0x7fffffff;
+        for (int xp = threadIdx.x; xp < W; xp += blockDim.x) argmin_merge(v, a, xp * xp + G[xp], xp);
+        for (int o = 32; o > 0; o >>= 1) argmin_merge(v, a, __shfl_xor(v, o), __shfl_xor(a, o));
+        if (lane == 0) { wv[wid] = v; wa[wid] = a; }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            int bv = wv[0], ba = wa[0];
+            for (int w = 1; w < 4; ++w) argmin_merge(bv, ba, wv[w], wa[w]);
+            val[0] = bv;
+            arg[0] = ba;
         }
-        pr.dt[size_t(y) * W + x] = best >= far2 ? 0.0f : sqrtf(float(best));
+        __syncthreads();
+    }
+    int P2 = 1;
+    while (P2 < W) P2 <<= 1;
+    for (int s = P2 >> 1; s >= 1; s >>= 1) {
+        const int count = (W - 1 - s) >= 0 ? (W - 1 - s) / (2 * s) + 1 : 0;   // x = s, 3s, 5s, ... < W
+        if (count <= 4) {
+            // one wave per point
+            for (int m = wid; m < count; m += 4) {
+                const int x = s + 2 * s * m;
+                const int lo = arg[x - s], hi = (x + s < W) ? arg[x + s] : W - 1;
+                int v = 0x7fffffff, a = 0x7fffffff;
+                for (int xp = lo + lane; xp <= hi; xp += 64) argmin_merge(v, a, (x - xp) * (x - xp) + G[xp], xp);
+                for (int o = 32; o > 0; o >>= 1) argmin_merge(v, a, __shfl_xor(v, o), __shfl_xor(a, o));
+                if (lane == 0) { val[x] = v; arg[x] = a; }
+            }
+        } else {
+            for (int m = threadIdx.x; m < count; m += blockDim.x) {
+                const int x = s + 2 * s * m;
+                const int lo = arg[x - s], hi = (x + s < W) ? arg[x + s] : W - 1;
+                int v = 0x7fffffff, a = lo;
+                for (int xp = lo; xp <= hi; ++xp) {
+                    const int c = (x - xp) * (x - xp) + G[xp];
+                    if (c < v) { v = c; a = xp; }
+                }
+                val[x] = v;
+                arg[x] = a;
+            }
+        }
+        __syncthreads();
+    }
+    for (int x = threadIdx.x; x < W; x += blockDim.x) {
+        const int b = val[x];
+        pr.dt[size_t(y) * W + x] = b >= far2 ? 0.0f : sqrtf(float(b));
     }
 }
 
@@ -226,12 +305,16 @@ __global__ void k_contour_edges(const ProbDev *__restrict__ P) {
 // Per vertex: visibility, contour set and direction sign; writes the flags in
 // vertex order and the solver's code byte in plan order.
 __global__ void k_decide(const ProbDev *__restrict__ P) {
+    __shared__ int cnt[2];
     const ProbDev &pr = P[blockIdx.y];
     const TemplateDev &T = pr.T;
     const int nv = T.nv, nf = T.nf, W = pr.W, H = pr.H;
+    if (threadIdx.x < 2) cnt[threadIdx.x] = 0;
+    __syncthreads();
     int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= nv) return;
+    if (blockIdx.x * blockDim.x >= unsigned(nv)) return;
     uint8_t code = 0;
+    if (i < nv) {
     if (pr.dvalid[i]) {
         float u = pr.duv[i], v = pr.duv[nv + i];
         int px = int(rintf(u)), py = int(rintf(v));
@@ -262,15 +345,19 @@ __global__ void k_decide(const ProbDev *__restrict__ P) {
                     float s = a * (-gx) + b * (-gy);
                     size_t pix = size_t(py) * W + px;
                     bool inside = pr.mask[pix] != 0 && pr.dt[pix] >= 1.5f;
-                    if (inside && s < 0.0f) code |= 4;
-                    atomicAdd(pr.counts + 1, 1);
+                    if (inside && s < 0.0f) code = pr.exclude_case2 ? uint8_t(code & ~2) : uint8_t(code | 4);
+                    if (code & 2) atomicAdd(cnt + 1, 1);
                 }
-                atomicAdd(pr.counts, 1);
+                atomicAdd(cnt, 1);
             }
         }
     }
+    if (pr.w_vel > 0.0f) code |= 8;
     pr.vflags[i] = code;
     int p = T.plan_pos[i];
+    pr.pva[p] = pr.dx[i];
+    pr.pva[nv + p] = pr.dx[nv + i];
+    pr.pva[2 * nv + p] = pr.dx[2 * nv + i];
     pr.vcode[p] = code;
     pr.px[p] = pr.xyz[i];
     pr.px[nv + p] = pr.xyz[nv + i];
@@ -278,6 +365,9 @@ __global__ void k_decide(const ProbDev *__restrict__ P) {
     pr.pc[p] = pr.rgb[i];
     pr.pc[nv + p] = pr.rgb[nv + i];
     pr.pc[2 * nv + p] = pr.rgb[2 * nv + i];
+    }
+    __syncthreads();
+    if (threadIdx.x < 2 && cnt[threadIdx.x]) atomicAdd(pr.counts + threadIdx.x, cnt[threadIdx.x]);
 }
 
 }  // namespace cap

@@ -226,10 +226,28 @@ int build_template(const capture_template_desc *d, capture_template **out, int d
     std::vector<uint8_t> owned_eslot(size_t(8) * nn);
     for (int o = 0; o < nn; ++o)
         for (int e = 0; e < 8; ++e) owned_eslot[size_t(e) * nn + o] = owned_eslot_t[size_t(o) * 8 + e];
-    std::vector<int> node_pidx;
+    std::vector<int> node_pidx, slot_dest(slot_node.size());
     for (int k = 0; k < nn; ++k) {
-        for (int p : node_parts[k]) node_pidx.push_back(p);
+        for (int p : node_parts[k]) {
+            slot_dest[p] = int(node_pidx.size());
+            node_pidx.push_back(p);
+        }
         node_pbeg[k + 1] = int(node_pidx.size());
+    }
+    // node graph in-edges (for the warm-start network's backward message passing)
+    std::vector<int> in_beg(nn + 1, 0), in_src, out_cnt(nn, 0);
+    {
+        std::vector<std::vector<int>> ins(nn);
+        for (int k = 0; k < nn; ++k)
+            for (int e = 0; e < 8; ++e) {
+                int l = edst[size_t(e) * nn + k];
+                if (l >= 0) { ins[l].push_back(k); out_cnt[k]++; }
+            }
+        for (int l = 0; l < nn; ++l) {
+            std::sort(ins[l].begin(), ins[l].end());
+            in_src.insert(in_src.end(), ins[l].begin(), ins[l].end());
+            in_beg[l + 1] = int(in_src.size());
+        }
     }
     std::vector<float> plan_w(size_t(4) * nv);
     for (int p = 0; p < nv; ++p)
@@ -243,7 +261,8 @@ int build_template(const capture_template_desc *d, capture_template **out, int d
            o_onode = blob.add(owned_node), o_oslot = blob.add(owned_slot), o_oes = blob.add(owned_eslot),
            o_lb = blob.add(list_beg), o_li = blob.add(list_idx), o_npb = blob.add(node_pbeg),
            o_npi = blob.add(node_pidx), o_vfb = blob.add(vf_beg), o_vff = blob.add(vf_face),
-           o_me = blob.add(medge);
+           o_me = blob.add(medge), o_ib = blob.add(in_beg), o_is = blob.add(in_src), o_oc = blob.add(out_cnt),
+           o_sd = blob.add(slot_dest);
     void *mem = nullptr;
     hipError_t e = hipMalloc(&mem, blob.bytes.size());
     if (e != hipSuccess) return fail(CAPTURE_ENOMEM, "template: device allocation failed");
@@ -265,6 +284,8 @@ int build_template(const capture_template_desc *d, capture_template **out, int d
     D.list_beg = (const int *)at(o_lb); D.list_idx = (const uint16_t *)at(o_li);
     D.node_pbeg = (const int *)at(o_npb); D.node_pidx = (const int *)at(o_npi);
     D.vf_beg = (const int *)at(o_vfb); D.vf_face = (const int *)at(o_vff); D.medge = (const int *)at(o_me);
+    D.slot_dest = (const int *)at(o_sd);
+    D.in_beg = (const int *)at(o_ib); D.in_src = (const int *)at(o_is); D.out_cnt = (const int *)at(o_oc);
     t->mem = mem;
     t->bytes = blob.bytes.size();
     t->device = device;

@@ -29,15 +29,26 @@ __device__ inline TileLds tile_lds(float *base, int ns, int ncomp) {
 __device__ inline void load_slots(const ProbDev &pr, int sb, int ns, TileLds &L, bool with_p) {
     const TemplateDev &T = pr.T;
     const int nn = T.nn, nv = T.nv;
-    for (int s = threadIdx.x; s < ns; s += blockDim.x) {
-        int k = T.slot_node[sb + s];
-        for (int q = 0; q < 9; ++q) L.R[9 * s + q] = pr.state[size_t(q) * nn + k];
-        for (int q = 0; q < 3; ++q) L.t[3 * s + q] = pr.state[size_t(9 + q) * nn + k];
-        int gv = T.node_vertex[k];
-        for (int q = 0; q < 3; ++q) L.g[3 * s + q] = pr.xyz[size_t(q) * nv + gv];
-        if (with_p)
-            for (int q = 0; q < 6; ++q) L.p[6 * s + q] = pr.p[size_t(q) * nn + k];
+    const int nq = with_p ? 21 : 15;
+    for (int it = threadIdx.x; it < ns * nq; it += blockDim.x) {
+        const int s = it / nq, q = it - s * nq;
+        const int k = T.slot_node[sb + s];
+        if (q < 12) {
+            const float v = pr.state[size_t(q) * nn + k];
+            if (q < 9) L.R[9 * s + q] = v; else L.t[3 * s + q - 9] = v;
+        } else if (q < 15) {
+            L.g[3 * s + q - 12] = pr.xyz[size_t(q - 12) * nv + T.node_vertex[k]];
+        } else {
+            L.p[6 * s + q - 15] = pr.p[size_t(q - 15) * nn + k];
+        }
     }
+}
+
+// The tile's contribution lists (contiguous in list_idx) and slot offsets, into LDS.
+__device__ inline void load_lists(const TemplateDev &T, int sb, int ns, uint16_t *lidx, int *lbeg) {
+    const int l0 = T.list_beg[sb], l1 = T.list_beg[sb + ns];
+    for (int q = threadIdx.x; q < l1 - l0; q += blockDim.x) lidx[q] = T.list_idx[l0 + q];
+    for (int s = threadIdx.x; s <= ns; s += blockDim.x) lbeg[s] = T.list_beg[sb + s] - l0;
 }
 
 __device__ inline void rot_apply(const float *R, const float d[3], float q[3]) {
@@ -54,20 +65,23 @@ __device__ inline void rot_apply(const float *R, const float d[3], float q[3]) {
 // ----------------------------------------------------------------------------
 __global__ __launch_bounds__(kTileThreads) void k_linearize(const ProbDev *__restrict__ P, int mode) {
     extern __shared__ float lds[];
-    __shared__ double red[kTileThreads];
+    __shared__ double red[kTileThreads / 64];
+    __shared__ uint16_t lidx[kMaxTileContrib];
+    __shared__ int lbeg[kMaxTileSlots + 1];
     const ProbDev &pr = P[blockIdx.y];
     const TemplateDev &T = pr.T;
     const int tile = blockIdx.x;
-    if (tile >= T.ntiles) return;
+    if (tile >= T.ntiles || pr.scal[2] != 0.0) return;
     const int nv = T.nv, nn = T.nn;
     const int vb = T.tile_vbeg[tile], nvt = T.tile_vbeg[tile + 1] - vb;
     const int sb = T.tile_sbeg[tile], ns = T.tile_sbeg[tile + 1] - sb;
     const int ob = T.tile_obeg[tile], nown = T.tile_obeg[tile + 1] - ob;
     TileLds L = tile_lds(lds, ns, 12);
     load_slots(pr, sb, ns, L, false);
+    if (mode == 0) load_lists(T, sb, ns, lidx, lbeg);
     __syncthreads();
 
-    double e_ph = 0.0, e_s = 0.0, e_sa = 0.0, e_a = 0.0;
+    double e_ph = 0.0, e_s = 0.0, e_sa = 0.0, e_a = 0.0, e_v = 0.0;
     const int lv = threadIdx.x;
     if (lv < nvt) {
         const int p = vb + lv;
@@ -140,8 +154,16 @@ __global__ __launch_bounds__(kTileThreads) void k_linearize(const ProbDev *__res
                 e_sa += double(r) * double(r);
             }
         }
+        if (code & 8) {   // velocity prior: r = sqrt(w_vel) (V - V_anchor), dr/dV = sqrt(w_vel) I
+            for (int a = 0; a < 3; ++a) {
+                const double dv = V[a] - double(pr.pva[size_t(a) * nv + p]);
+                gi[a] += float(double(pr.w_vel) * dv);
+                e_v += double(pr.w_vel) * dv * dv;
+            }
+            Hm[0] += pr.w_vel; Hm[3] += pr.w_vel; Hm[5] += pr.w_vel;
+        }
         if (mode == 0) {
-            if (code & 3)
+            if (code & 11)
                 for (int q6 = 0; q6 < 6; ++q6) pr.Hm[size_t(q6) * nv + p] = Hm[q6];
             // contributions to the 4 bound nodes: rhs -w[q x g; g], diag w^2[diag(Q^T H Q); diag(H)]
 #pragma unroll
@@ -207,19 +229,20 @@ __global__ __launch_bounds__(kTileThreads) void k_linearize(const ProbDev *__res
     if (mode == 0) {
         for (int pair = threadIdx.x; pair < ns * 12; pair += blockDim.x) {
             const int s = pair / 12, comp = pair - s * 12;
-            const int lb = T.list_beg[sb + s], le = T.list_beg[sb + s + 1];
+            const int lb = lbeg[s], le = lbeg[s + 1];
             float acc = 0.0f;
-            for (int q = lb; q < le; ++q) acc += L.c[12 * T.list_idx[q] + comp];
-            pr.partial[size_t(sb + s) * 12 + comp] = acc;
+            for (int q = lb; q < le; ++q) acc += L.c[12 * lidx[q] + comp];
+            pr.partial[size_t(T.slot_dest[sb + s]) * 12 + comp] = acc;
         }
     }
     double s0 = block_sum<kTileThreads>(e_ph, red);
     double s1 = block_sum<kTileThreads>(e_s, red);
     double s2 = block_sum<kTileThreads>(e_sa, red);
     double s3 = block_sum<kTileThreads>(e_a, red);
+    double s4 = block_sum<kTileThreads>(e_v, red);
     if (threadIdx.x == 0) {
-        double *te = pr.tile_e + size_t(tile) * 4;
-        te[0] = s0; te[1] = s1; te[2] = s2; te[3] = s3;
+        double *te = pr.tile_e + size_t(tile) * kTerms;
+        te[0] = s0; te[1] = s1; te[2] = s2; te[3] = s3; te[4] = s4;
     }
 }
 
@@ -230,6 +253,8 @@ __global__ __launch_bounds__(kTileThreads) void k_linearize(const ProbDev *__res
 // ----------------------------------------------------------------------------
 __global__ __launch_bounds__(kTileThreads) void k_apply(const ProbDev *__restrict__ P) {
     extern __shared__ float lds[];
+    __shared__ uint16_t lidx[kMaxTileContrib];
+    __shared__ int lbeg[kMaxTileSlots + 1];
     const ProbDev &pr = P[blockIdx.y];
     if (pr.scal[1] != 0.0) return;
     const TemplateDev &T = pr.T;
@@ -240,13 +265,19 @@ __global__ __launch_bounds__(kTileThreads) void k_apply(const ProbDev *__restric
     const int sb = T.tile_sbeg[tile], ns = T.tile_sbeg[tile + 1] - sb;
     const int ob = T.tile_obeg[tile], nown = T.tile_obeg[tile + 1] - ob;
     TileLds L = tile_lds(lds, ns, 6);
-    load_slots(pr, sb, ns, L, true);
+    for (int it = threadIdx.x; it < ns * 18; it += blockDim.x) {   // packed per-slot R, g and p
+        const int s = it / 18, q = it - s * 18;
+        if (q < 9) L.R[9 * s + q] = pr.spack[size_t(sb + s) * 12 + q];
+        else if (q < 12) L.g[3 * s + q - 9] = pr.spack[size_t(sb + s) * 12 + q];
+        else L.p[6 * s + q - 12] = pr.pslot[size_t(sb + s) * 6 + q - 12];
+    }
+    load_lists(T, sb, ns, lidx, lbeg);
     __syncthreads();
     const int lv = threadIdx.x;
     if (lv < nvt) {
         const int p = vb + lv;
         float *c = L.c + 24 * lv;
-        if (pr.vcode[p] & 3) {
+        if (pr.vcode[p] & 11) {
             const uint32_t packed = T.plan_slot[p];
             const float v[3] = {pr.px[p], pr.px[nv + p], pr.px[2 * nv + p]};
             float q[4][3], w[4];
@@ -312,10 +343,10 @@ __global__ __launch_bounds__(kTileThreads) void k_apply(const ProbDev *__restric
     __syncthreads();
     for (int pair = threadIdx.x; pair < ns * 6; pair += blockDim.x) {
         const int s = pair / 6, comp = pair - s * 6;
-        const int lb = T.list_beg[sb + s], le = T.list_beg[sb + s + 1];
+        const int lb = lbeg[s], le = lbeg[s + 1];
         float acc = 0.0f;
-        for (int q = lb; q < le; ++q) acc += L.c[6 * T.list_idx[q] + comp];
-        pr.partial[size_t(sb + s) * 6 + comp] = acc;
+        for (int q = lb; q < le; ++q) acc += L.c[6 * lidx[q] + comp];
+        pr.partial[size_t(T.slot_dest[sb + s]) * 6 + comp] = acc;
     }
 }
 
@@ -323,43 +354,78 @@ __global__ __launch_bounds__(kTileThreads) void k_apply(const ProbDev *__restric
 // Node kernels: one workgroup per problem.
 // ----------------------------------------------------------------------------
 
+// Sum of a node's tile partials (stride floats per partial), in tile order.
+__device__ inline float gather_node(const TemplateDev &T, const float *__restrict__ partial, int stride, int k,
+                                    int c) {
+    const int pb = T.node_pbeg[k], pe = T.node_pbeg[k + 1];
+    float a = 0.0f;
+    for (int q = pb; q < pe; ++q) a += partial[size_t(q) * stride + c];
+    return a;
+}
+
 // After a linearisation: b, diag, Jacobi preconditioner, PCG start vectors
 // (x = 0, r = b, z = M^-1 r, p = z), r.z, and the energy of GN step `gn`.
-__global__ __launch_bounds__(kNodeThreads) void k_node_init(const ProbDev *__restrict__ P, int gn, int energy_only) {
-    __shared__ double red[kNodeThreads];
+// One thread per (component, node) item.
+__global__ __launch_bounds__(kNodeThreads) void k_node_init(const ProbDev *__restrict__ P, int gn, int energy_only, int check_target) {
+    __shared__ double red[kNodeThreads / 64];
     const ProbDev &pr = P[blockIdx.x];
+    if (pr.scal[2] != 0.0) return;   // stopped at the target energy
     const TemplateDev &T = pr.T;
     const int nn = T.nn;
     double rz = 0.0;
     if (!energy_only) {
-        for (int k = threadIdx.x; k < nn; k += blockDim.x) {
-            const int pb = T.node_pbeg[k], pe = T.node_pbeg[k + 1];
-            for (int c = 0; c < 6; ++c) {
-                float b = 0.0f, d = 0.0f;
-                for (int q = pb; q < pe; ++q) {
-                    b += pr.partial[size_t(T.node_pidx[q]) * 12 + c];
-                    d += pr.partial[size_t(T.node_pidx[q]) * 12 + 6 + c];
-                }
-                const float mi = d > 0.0f ? 1.0f / d : 1.0f;
-                const float z = mi * b;
-                const size_t o = size_t(c) * nn + k;
-                pr.b[o] = b; pr.diag[o] = d; pr.dinv[o] = mi;
-                pr.x[o] = 0.0f; pr.r[o] = b; pr.z[o] = z; pr.p[o] = z;
-                rz += double(b) * double(z);
-            }
+        for (int i = threadIdx.x; i < 6 * nn; i += blockDim.x) {
+            const int c = i / nn, k = i - c * nn;
+            const float b = gather_node(T, pr.partial, 12, k, c);
+            const float d = gather_node(T, pr.partial, 12, k, 6 + c);
+            const float mi = d > 0.0f ? 1.0f / d : 1.0f;
+            const float z = mi * b;
+            pr.b[i] = b; pr.diag[i] = d; pr.dinv[i] = mi;
+            pr.x[i] = 0.0f; pr.r[i] = b; pr.z[i] = z; pr.p[i] = z;
+            rz += double(b) * double(z);
+            for (int q = T.node_pbeg[k]; q < T.node_pbeg[k + 1]; ++q) pr.pslot[size_t(T.node_pidx[q]) * 6 + c] = z;
+        }
+        // per-slot copies of R_k and the node position for the PCG tile kernel
+        for (int i = threadIdx.x; i < 12 * nn; i += blockDim.x) {
+            const int q12 = i / nn, k = i - q12 * nn;
+            const float v = q12 < 9 ? pr.state[size_t(q12) * nn + k]
+                                    : pr.xyz[size_t(q12 - 9) * T.nv + T.node_vertex[k]];
+            for (int q = T.node_pbeg[k]; q < T.node_pbeg[k + 1]; ++q) pr.spack[size_t(T.node_pidx[q]) * 12 + q12] = v;
         }
     }
     rz = block_sum<kNodeThreads>(rz, red);
-    double e[4] = {0, 0, 0, 0};
+    double e[kTerms] = {0, 0, 0, 0, 0};
     for (int t = threadIdx.x; t < T.ntiles; t += blockDim.x)
-        for (int q = 0; q < 4; ++q) e[q] += pr.tile_e[size_t(t) * 4 + q];
-    for (int q = 0; q < 4; ++q) e[q] = block_sum<kNodeThreads>(e[q], red);
+        for (int q = 0; q < kTerms; ++q) e[q] += pr.tile_e[size_t(t) * kTerms + q];
+    for (int q = 0; q < kTerms; ++q) e[q] = block_sum<kNodeThreads>(e[q], red);
     if (threadIdx.x == 0) {
         if (!energy_only) {
             pr.scal[0] = rz;
             pr.scal[1] = rz == 0.0 ? 1.0 : 0.0;
+            if (check_target && e[0] + e[1] + e[3] + e[4] <= pr.target) {   // x = 0 above, so the step's update is void
+                pr.scal[1] = 1.0;
+                pr.scal[2] = 1.0;
+                pr.scal[3] = double(gn);
+            }
         }
-        for (int q = 0; q < 4; ++q) pr.scal[8 + 4 * gn + q] = e[q];
+        for (int q = 0; q < kTerms; ++q) pr.scal[8 + kTerms * gn + q] = e[q];
+    }
+}
+
+// Per-problem scalars at the start of a solve: nothing stopped, GN count = K.
+__global__ void k_scal_init(const ProbDev *__restrict__ P, int gn_iters) {
+    const ProbDev &pr = P[blockIdx.x];
+    for (int i = threadIdx.x; i < kScalars; i += blockDim.x) pr.scal[i] = i == 3 ? double(gn_iters) : 0.0;
+}
+
+// Copy p to the per-slot array (for a caller-supplied direction).
+__global__ __launch_bounds__(kNodeThreads) void k_scatter_p(const ProbDev *__restrict__ P) {
+    const ProbDev &pr = P[blockIdx.x];
+    const TemplateDev &T = pr.T;
+    const int nn = T.nn;
+    for (int i = threadIdx.x; i < 6 * nn; i += blockDim.x) {
+        const int c = i / nn, k = i - c * nn;
+        for (int q = T.node_pbeg[k]; q < T.node_pbeg[k + 1]; ++q) pr.pslot[size_t(T.node_pidx[q]) * 6 + c] = pr.p[i];
     }
 }
 
@@ -368,13 +434,9 @@ __global__ __launch_bounds__(kNodeThreads) void k_node_gather(const ProbDev *__r
     const ProbDev &pr = P[blockIdx.x];
     const TemplateDev &T = pr.T;
     const int nn = T.nn;
-    for (int k = threadIdx.x; k < nn; k += blockDim.x) {
-        const int pb = T.node_pbeg[k], pe = T.node_pbeg[k + 1];
-        for (int c = 0; c < 6; ++c) {
-            float a = 0.0f;
-            for (int q = pb; q < pe; ++q) a += pr.partial[size_t(T.node_pidx[q]) * 6 + c];
-            pr.Ap[size_t(c) * nn + k] = a;
-        }
+    for (int i = threadIdx.x; i < 6 * nn; i += blockDim.x) {
+        const int c = i / nn, k = i - c * nn;
+        pr.Ap[i] = gather_node(T, pr.partial, 6, k, c);
     }
 }
 
@@ -410,50 +472,95 @@ __device__ inline void node_update(const ProbDev &pr, int k) {
 
 // One PCG iteration after k_apply: A p, alpha, x/r/z updates, beta, p.
 // Stops (for this GN step) when p.Ap <= 0 or r.z == 0.  `last`: apply the
-// node update afterwards; `update_only`: only that.
+// node update afterwards; `update_only`: only that.  Items are (component,
+// node) pairs; each thread keeps its items' values in registers between phases.
+constexpr int kItems = 8;   // up to kItems * kNodeThreads = 8192 items (1365 nodes) in registers
+
 __global__ __launch_bounds__(kNodeThreads) void k_node_pcg(const ProbDev *__restrict__ P, int last, int update_only) {
-    __shared__ double red[kNodeThreads];
+    __shared__ double red[kNodeThreads / 64];
     const ProbDev &pr = P[blockIdx.x];
     const TemplateDev &T = pr.T;
-    const int nn = T.nn;
+    const int nn = T.nn, n6 = 6 * nn;
     const bool done = pr.scal[1] != 0.0;
     if (!done && !update_only) {
+        const bool regs = n6 <= kItems * kNodeThreads;
+        float ap[kItems], pp[kItems];
         double pap = 0.0;
-        for (int k = threadIdx.x; k < nn; k += blockDim.x) {
-            const int pb = T.node_pbeg[k], pe = T.node_pbeg[k + 1];
-            for (int c = 0; c < 6; ++c) {
-                float a = 0.0f;
-                for (int q = pb; q < pe; ++q) a += pr.partial[size_t(T.node_pidx[q]) * 6 + c];
-                const size_t o = size_t(c) * nn + k;
-                pr.Ap[o] = a;
-                pap += double(pr.p[o]) * double(a);
+        if (regs) {
+#pragma unroll
+            for (int j = 0; j < kItems; ++j) {
+                const int i = threadIdx.x + j * kNodeThreads;
+                ap[j] = 0.0f; pp[j] = 0.0f;
+                if (i < n6) {
+                    const int c = i / nn, k = i - c * nn;
+                    ap[j] = gather_node(T, pr.partial, 6, k, c);
+                    pp[j] = pr.p[i];
+                    pap += double(pp[j]) * double(ap[j]);
+                }
+            }
+        } else {
+            for (int i = threadIdx.x; i < n6; i += kNodeThreads) {
+                const int c = i / nn, k = i - c * nn;
+                const float a = gather_node(T, pr.partial, 6, k, c);
+                pr.Ap[i] = a;
+                pap += double(pr.p[i]) * double(a);
             }
         }
         pap = block_sum<kNodeThreads>(pap, red);
         const double rz = pr.scal[0];
         if (pap <= 0.0) {
-            __syncthreads();
             if (threadIdx.x == 0) pr.scal[1] = 1.0;
         } else {
             const double alpha = rz / pap;
             double rz2 = 0.0;
-            for (int k = threadIdx.x; k < nn; k += blockDim.x)
-                for (int c = 0; c < 6; ++c) {
-                    const size_t o = size_t(c) * nn + k;
-                    pr.x[o] = float(fma(alpha, double(pr.p[o]), double(pr.x[o])));
-                    const float r = float(fma(-alpha, double(pr.Ap[o]), double(pr.r[o])));
-                    const float z = pr.dinv[o] * r;
-                    pr.r[o] = r;
-                    pr.z[o] = z;
+            float zz[kItems];
+            if (regs) {
+#pragma unroll
+                for (int j = 0; j < kItems; ++j) {
+                    const int i = threadIdx.x + j * kNodeThreads;
+                    zz[j] = 0.0f;
+                    if (i < n6) {
+                        pr.x[i] = float(fma(alpha, double(pp[j]), double(pr.x[i])));
+                        const float r = float(fma(-alpha, double(ap[j]), double(pr.r[i])));
+                        const float z = pr.dinv[i] * r;
+                        pr.r[i] = r;
+                        zz[j] = z;
+                        rz2 += double(r) * double(z);
+                    }
+                }
+            } else {
+                for (int i = threadIdx.x; i < n6; i += kNodeThreads) {
+                    pr.x[i] = float(fma(alpha, double(pr.p[i]), double(pr.x[i])));
+                    const float r = float(fma(-alpha, double(pr.Ap[i]), double(pr.r[i])));
+                    const float z = pr.dinv[i] * r;
+                    pr.r[i] = r;
+                    pr.z[i] = z;
                     rz2 += double(r) * double(z);
                 }
+            }
             rz2 = block_sum<kNodeThreads>(rz2, red);
             const double beta = rz2 / rz;
-            for (int k = threadIdx.x; k < nn; k += blockDim.x)
-                for (int c = 0; c < 6; ++c) {
-                    const size_t o = size_t(c) * nn + k;
-                    pr.p[o] = float(fma(beta, double(pr.p[o]), double(pr.z[o])));
+            if (regs) {
+#pragma unroll
+                for (int j = 0; j < kItems; ++j) {
+                    const int i = threadIdx.x + j * kNodeThreads;
+                    if (i < n6) {
+                        const float pn = float(fma(beta, double(pp[j]), double(zz[j])));
+                        pr.p[i] = pn;
+                        const int c = i / nn, k = i - c * nn;
+                        for (int q = T.node_pbeg[k]; q < T.node_pbeg[k + 1]; ++q)
+                            pr.pslot[size_t(T.node_pidx[q]) * 6 + c] = pn;
+                    }
                 }
+            } else {
+                for (int i = threadIdx.x; i < n6; i += kNodeThreads) {
+                    const float pn = float(fma(beta, double(pr.p[i]), double(pr.z[i])));
+                    pr.p[i] = pn;
+                    const int c = i / nn, k = i - c * nn;
+                    for (int q = T.node_pbeg[k]; q < T.node_pbeg[k + 1]; ++q)
+                        pr.pslot[size_t(T.node_pidx[q]) * 6 + c] = pn;
+                }
+            }
             if (threadIdx.x == 0) {
                 pr.scal[0] = rz2;
                 if (rz2 == 0.0) pr.scal[1] = 1.0;

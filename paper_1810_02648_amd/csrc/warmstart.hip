@@ -1,0 +1,278 @@
+// Learned warm start: per-node features, a 3-layer per-node network with two
+// rounds of mean message passing over the node graph, trained and run with
+// BF16 MFMA (v_mfma_f32_16x16x16_bf16) and float32 accumulation and master
+// weights.  The paper's own warm start is the previous frame's result
+// (Sec. 3.4, displacement warping); learned motion priors are its stated
+// future work (Sec. 6).  The plain previous-frame start stays the fallback.
+#include <cmath>
+
+#include "device.hpp"
+
+namespace cap {
+
+typedef short s4v __attribute__((ext_vector_type(4)));
+typedef float f4v __attribute__((ext_vector_type(4)));
+
+// float -> bfloat16 bits, round to nearest even (NaN kept quiet)
+__device__ inline uint16_t f2bf(float f) {
+    uint32_t u = __float_as_uint(f);
+    if ((u & 0x7fffffffu) > 0x7f800000u) return uint16_t((u >> 16) | 0x40);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return uint16_t(u >> 16);
+}
+__device__ inline float bf2f(uint16_t b) { return __uint_as_float(uint32_t(b) << 16); }
+
+// ---------------------------------------------------------------- GEMM
+// C(i, j) = sum_k A(i, k) B(j, k) [+ bias(j)], A and B bfloat16 with arbitrary
+// strides, float32 accumulation, one wave per 16x16 output tile.  Optional
+// epilogue: a bfloat16 copy of ReLU(C) into Cb.
+__global__ __launch_bounds__(256) void k_gemm(Gemm g) {
+    const int wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int lane = threadIdx.x & 63;
+    const int tn = (g.N + 15) >> 4, tm = (g.M + 15) >> 4;
+    if (wave >= tm * tn) return;
+    const int ti = wave / tn, tj = wave - ti * tn;
+    const int r = lane & 15, kq = (lane >> 4) * 4;
+    const int ia = ti * 16 + r, jb = tj * 16 + r;
+    f4v acc = {0.0f, 0.0f, 0.0f, 0.0f};
+    for (int k0 = 0; k0 < g.K; k0 += 16) {
+        s4v a, b;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int k = k0 + kq + q;
+            a[q] = (ia < g.M && k < g.K) ? short(g.A[ia * g.sai + k * g.sak]) : short(0);
+            b[q] = (jb < g.N && k < g.K) ? short(g.B[jb * g.sbj + k * g.sbk]) : short(0);
+        }
+        acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc, 0, 0, 0);
+    }
+    const int j = tj * 16 + r;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int i = ti * 16 + (lane >> 4) * 4 + q;
+        if (i < g.M && j < g.N) {
+            float v = acc[q];
+            if (g.bias) v += g.bias[j];
+            g.C[i * g.sci + j * g.scj] = v;
+            if (g.relu_copy) g.Cb[i * g.scbi + j] = f2bf(v > 0.0f ? v : 0.0f);
+        }
+    }
+}
+
+// ---------------------------------------------------------------- message passing
+// out[k][off + f] = bf16(mean over valid out-edges l of relu(z[l][f]))
+__global__ void k_mean_fwd(const float *__restrict__ z, int nn, const int *__restrict__ edge_dst,
+                           uint16_t *__restrict__ cat, int width) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nn * width) return;
+    const int k = i / width, f = i - k * width;
+    float s = 0.0f;
+    int cnt = 0;
+    for (int e = 0; e < 8; ++e) {
+        const int l = edge_dst[e * nn + k];
+        if (l >= 0) {
+            const float v = z[size_t(l) * width + f];
+            s += v > 0.0f ? v : 0.0f;
+            ++cnt;
+        }
+    }
+    cat[size_t(k) * 2 * width + width + f] = f2bf(cnt ? s / float(cnt) : 0.0f);
+}
+
+// Backward through [h; mean(h)] and the ReLU:
+// dz[l][f] = (dcat[l][f] + sum over in-edges (k -> l) of dcat[k][width + f] / |N(k)|) * (z[l][f] > 0)
+__global__ void k_mean_bwd(const float *__restrict__ dcat, const float *__restrict__ z, int nn,
+                           const int *__restrict__ in_beg, const int *__restrict__ in_src,
+                           const int *__restrict__ out_cnt, uint16_t *__restrict__ dzb, float *__restrict__ dz,
+                           int width) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nn * width) return;
+    const int l = i / width, f = i - l * width;
+    float s = dcat[size_t(l) * 2 * width + f];
+    for (int q = in_beg[l]; q < in_beg[l + 1]; ++q) {
+        const int k = in_src[q];
+        s += dcat[size_t(k) * 2 * width + width + f] / float(out_cnt[k]);
+    }
+    const float v = z[size_t(l) * width + f] > 0.0f ? s : 0.0f;
+    dz[i] = v;
+    dzb[i] = f2bf(v);
+}
+
+// Column sums (bias gradients): out[j] = sum_i in[i][j], fixed order per column.
+__global__ void k_colsum(const float *__restrict__ in, int rows, int cols, float *__restrict__ out) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= cols) return;
+    float s = 0.0f;
+    for (int i = 0; i < rows; ++i) s += in[size_t(i) * cols + j];
+    out[j] = s;
+}
+
+// dy = 2 (y - t) / (6 nn), fp32 and bf16; per-item squared error for the loss.
+__global__ void k_mse_grad(const float *__restrict__ y, const float *__restrict__ t, int n, float *__restrict__ dy,
+                           uint16_t *__restrict__ dyb, float *__restrict__ se) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float d = y[i] - t[i];
+    const float g = 2.0f * d / float(n);
+    dy[i] = g;
+    dyb[i] = f2bf(g);
+    se[i] = d * d;
+}
+
+// Adam on the float32 master vector, then refresh the bf16 weight copy.
+__global__ void k_adam(float *__restrict__ w, const float *__restrict__ g, float *__restrict__ m,
+                       float *__restrict__ v, uint16_t *__restrict__ wb, int n, float lr, float c1, float c2) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float gi = g[i];
+    const float mi = 0.9f * m[i] + 0.1f * gi;
+    const float vi = 0.999f * v[i] + 0.001f * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    const float mh = mi / c1, vh = vi / c2;
+    const float wi = w[i] - lr * mh / (sqrtf(vh) + 1e-8f);
+    w[i] = wi;
+    wb[i] = f2bf(wi);
+}
+
+__global__ void k_to_bf16(const float *__restrict__ in, uint16_t *__restrict__ out, int n) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) out[i] = f2bf(in[i]);
+}
+
+// Standardise raw [nn][32] features into bf16 inputs (padding stays zero).
+__global__ void k_standardise(const float *__restrict__ X, int nn, const float *__restrict__ mu,
+                              const float *__restrict__ sd, uint16_t *__restrict__ Xb) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nn * 32) return;
+    const int f = i & 31;
+    Xb[i] = f2bf(f < 27 ? (X[i] - mu[f]) / sd[f] : 0.0f);
+}
+
+// ---------------------------------------------------------------- features
+__device__ inline void log_so3(const float R[9], float w[3]) {
+    const float c = fminf(fmaxf(((R[0] + R[4]) + R[8] - 1.0f) * 0.5f, -1.0f), 1.0f);
+    const float th = acosf(c);
+    const float v[3] = {R[7] - R[5], R[2] - R[6], R[3] - R[1]};
+    const float s = th < 1e-4f ? 0.5f + th * th / 12.0f : th / (2.0f * sinf(th));
+    for (int a = 0; a < 3; ++a) w[a] = s * v[a];
+}
+
+// Raw features of every node of problem blockIdx.y ([nn][32]): axis-angle of
+// R_k and t_k (0..5), their change since frame t-2 (6..11, zero without it),
+// sign(b) log(1 + |b|) of the right-hand side (12..17), log(1 + diag)
+// (18..23), node position minus the mean node position (24..26), zeros.
+__global__ void k_ws_features(const ProbDev *__restrict__ P, const float *__restrict__ prev2, float *__restrict__ X) {
+    __shared__ float mean[3];
+    const ProbDev &pr = P[blockIdx.y];
+    const TemplateDev &T = pr.T;
+    const int nn = T.nn, nv = T.nv;
+    if (threadIdx.x < 3) {
+        float s = 0.0f;
+        for (int k = 0; k < nn; ++k) s += pr.xyz[size_t(threadIdx.x) * nv + T.node_vertex[k]];
+        mean[threadIdx.x] = s / float(nn);
+    }
+    __syncthreads();
+    for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < nn; k += gridDim.x * blockDim.x) {
+        float *x = X + size_t(k) * 32;
+        float R[9], w[3];
+        for (int q = 0; q < 9; ++q) R[q] = pr.state[size_t(q) * nn + k];
+        log_so3(R, w);
+        for (int a = 0; a < 3; ++a) {
+            x[a] = w[a];
+            x[3 + a] = pr.state[size_t(9 + a) * nn + k];
+        }
+        if (prev2) {
+            float R2[9], D[9], dw[3];
+            for (int q = 0; q < 9; ++q) R2[q] = prev2[size_t(q) * nn + k];
+            for (int i = 0; i < 3; ++i)
+                for (int j = 0; j < 3; ++j)
+                    D[3 * i + j] = (R[3 * i] * R2[3 * j] + R[3 * i + 1] * R2[3 * j + 1]) + R[3 * i + 2] * R2[3 * j + 2];
+            log_so3(D, dw);
+            for (int a = 0; a < 3; ++a) {
+                x[6 + a] = dw[a];
+                x[9 + a] = pr.state[size_t(9 + a) * nn + k] - prev2[size_t(9 + a) * nn + k];
+            }
+        } else {
+            for (int a = 0; a < 6; ++a) x[6 + a] = 0.0f;
+        }
+        for (int c = 0; c < 6; ++c) {
+            const float b = pr.b[size_t(c) * nn + k], d = pr.diag[size_t(c) * nn + k];
+            x[12 + c] = copysignf(log1pf(fabsf(b)), b);
+            x[18 + c] = log1pf(fmaxf(d, 0.0f));
+        }
+        const int gv = T.node_vertex[k];
+        for (int a = 0; a < 3; ++a) x[24 + a] = pr.xyz[size_t(a) * nv + gv] - mean[a];
+        for (int a = 27; a < 32; ++a) x[a] = 0.0f;
+    }
+}
+
+// Scaled network output y [nn][6] -> node update x [6][nn] (rad, m).
+__global__ void k_ws_delta(const ProbDev *__restrict__ P, const float *__restrict__ y) {
+    const ProbDev &pr = P[blockIdx.y];
+    const int nn = pr.T.nn;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= 6 * nn) return;
+    const int c = i / nn, k = i - c * nn;
+    pr.x[i] = y[size_t(k) * 6 + c] * (c < 3 ? 0.05f : 0.01f);
+}
+
+// Keep the predicted start only if it lowers the energy; otherwise restore
+// the previous frame's state.  scal[4] = predicted-start energy, scal[5] = 1
+// when the prediction was rejected.
+__global__ void k_ws_select(const ProbDev *__restrict__ P, int slot_prev, int slot_pred) {
+    __shared__ int reject;
+    const ProbDev &pr = P[blockIdx.x];
+    const int nn = pr.T.nn;
+    if (threadIdx.x == 0) {
+        const double *e0 = pr.scal + 8 + kTerms * slot_prev, *e1 = pr.scal + 8 + kTerms * slot_pred;
+        const double E0 = e0[0] + e0[1] + e0[3] + e0[4], E1 = e1[0] + e1[1] + e1[3] + e1[4];
+        reject = !(E1 < E0);
+        pr.scal[4] = E1;
+        pr.scal[5] = reject ? 1.0 : 0.0;
+        pr.scal[6] = E0;
+    }
+    __syncthreads();
+    if (reject)
+        for (int i = threadIdx.x; i < 12 * nn; i += blockDim.x) pr.state[i] = pr.state0[i];
+}
+
+// Training target: per node (dw, dt) with R_next = Exp(dw) R_prev and
+// t_next = t_prev + dt, divided by (0.05 rad, 0.01 m); layout [nn][6].
+__global__ void k_ws_target(const float *__restrict__ prev, const float *__restrict__ next, int nn,
+                            float *__restrict__ target) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= nn) return;
+    float R0[9], R1[9], D[9], dw[3];
+    for (int q = 0; q < 9; ++q) { R0[q] = prev[size_t(q) * nn + k]; R1[q] = next[size_t(q) * nn + k]; }
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j)
+            D[3 * i + j] = (R1[3 * i] * R0[3 * j] + R1[3 * i + 1] * R0[3 * j + 1]) + R1[3 * i + 2] * R0[3 * j + 2];
+    log_so3(D, dw);
+    for (int a = 0; a < 3; ++a) {
+        target[size_t(k) * 6 + a] = dw[a] / 0.05f;
+        target[size_t(k) * 6 + 3 + a] = (next[size_t(9 + a) * nn + k] - prev[size_t(9 + a) * nn + k]) / 0.01f;
+    }
+}
+
+// Feature standardisation from `rows` feature rows ([rows][32]): one workgroup
+// per feature, float64 sums in a fixed order; deviation floored at 1e-6.
+__global__ __launch_bounds__(256) void k_ws_scaling(const float *__restrict__ X, long long rows, float *mu, float *sd) {
+    __shared__ double red[4];
+    const int f = blockIdx.x;
+    double s = 0.0, s2 = 0.0;
+    for (long long i = threadIdx.x; i < rows; i += blockDim.x) {
+        const double v = X[i * 32 + f];
+        s += v;
+        s2 += v * v;
+    }
+    s = block_sum<256>(s, red);
+    s2 = block_sum<256>(s2, red);
+    if (threadIdx.x == 0) {
+        const double m = s / double(rows);
+        const double var = fmax(s2 / double(rows) - m * m, 0.0);
+        mu[f] = float(m);
+        sd[f] = float(fmax(sqrt(var), 1e-6));
+    }
+}
+
+}  // namespace cap

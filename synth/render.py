@@ -20,7 +20,7 @@ def _project(xyz, cam):
     return u, v, Z
 
 
-def render_targets(xyz, tri, rgb, cam, chunk=60000, max_box=8):
+def render_targets(xyz, tri, rgb, cam, chunk=60000, boxes=(4, 8, 16, 32)):
     """Render mask (uint8 [H][W]) and colour (float32 [3][H][W]) images."""
     W, H = cam.width, cam.height
     u, v, Z = _project(xyz, cam)
@@ -41,8 +41,8 @@ def render_targets(xyz, tri, rgb, cam, chunk=60000, max_box=8):
     nonempty = ok & (i1 >= i0) & (j1 >= j0)
     bw = i1 - i0 + 1
     bh = j1 - j0 + 1
-    small = nonempty & (bw <= max_box) & (bh <= max_box)
-    big = np.nonzero(nonempty & ~small)[0]
+    ext = np.maximum(bw, bh)
+    big = np.nonzero(nonempty & (ext > boxes[-1]))[0]
 
     def merge(pix, iz, f, lam):
         if pix.size == 0:
@@ -73,18 +73,22 @@ def render_targets(xyz, tri, rgb, cam, chunk=60000, max_box=8):
         iz = lam[..., 0] / Z[a] + lam[..., 1] / Z[b] + lam[..., 2] / Z[c]
         return inside, lam, iz
 
-    small_idx = np.nonzero(small)[0]
-    oi, oj = np.meshgrid(np.arange(max_box), np.arange(max_box), indexing="xy")
-    oi, oj = oi.ravel(), oj.ravel()
-    for s in range(0, small_idx.size, chunk):
-        faces = small_idx[s:s + chunk][:, None]
-        ii = (i0[faces] + oi[None, :]).astype(np.float64)
-        jj = (j0[faces] + oj[None, :]).astype(np.float64)
-        inside, lam, iz = candidates(faces, ii, jj)
-        inside &= (oi[None, :] < bw[faces]) & (oj[None, :] < bh[faces])
-        fsel = np.broadcast_to(faces, ii.shape)[inside]
-        pix = (jj[inside].astype(np.int64) * W + ii[inside].astype(np.int64))
-        merge(pix, iz[inside], fsel, lam[inside])
+    lo = 0
+    for box in boxes:                       # vectorise triangles by bounding-box size class
+        cls = np.nonzero(nonempty & (ext > lo) & (ext <= box))[0]
+        lo = box
+        oi, oj = np.meshgrid(np.arange(box), np.arange(box), indexing="xy")
+        oi, oj = oi.ravel(), oj.ravel()
+        step = max(1, chunk * 64 // (box * box))
+        for s in range(0, cls.size, step):
+            faces = cls[s:s + step][:, None]
+            ii = (i0[faces] + oi[None, :]).astype(np.float64)
+            jj = (j0[faces] + oj[None, :]).astype(np.float64)
+            inside, lam, iz = candidates(faces, ii, jj)
+            inside &= (oi[None, :] < bw[faces]) & (oj[None, :] < bh[faces])
+            fsel = np.broadcast_to(faces, ii.shape)[inside]
+            pix = (jj[inside].astype(np.int64) * W + ii[inside].astype(np.int64))
+            merge(pix, iz[inside], fsel, lam[inside])
     for f in big:
         jj, ii = np.meshgrid(np.arange(j0[f], j1[f] + 1, dtype=np.float64),
                              np.arange(i0[f], i1[f] + 1, dtype=np.float64), indexing="ij")

@@ -144,6 +144,32 @@ def test_solve_matches_schedule_matched_oracle(ctx, frames, name, gn, pcg):
         assert abs(rep["energy"][k] - e["total"]) <= 1e-5 * e0, k
 
 
+def test_velocity_prior_and_case2_exclusion_match_oracle(ctx, frames):
+    """Temporal prior anchored at the start geometry, case-2 vertices excluded."""
+    import paper_1810_02648_amd as cap
+    from gpu_util import make_frame
+    f = frames["small1"]
+    g = og.build_graph(f["xyz"], 64)
+    rng = np.random.default_rng(12)
+    st = onr.apply_update(onr.identity_state(64), rng.normal(0, 0.03, 384)).astype(np.float32)
+    P = onr.Problem(f["xyz"], f["tri"], f["rgb"], g, f["cam"], f["mask"], f["image"], f["weights"], state0=st,
+                    w_vel=100.0, case2="exclude")
+    ref = onr.solve(P, 3, "pcg", 8)
+    fr = make_frame(ctx, f, g, state=st)
+    rep = cap.nonrigid_solve(ctx, fr, cap.params(*f["weights"], gn_iters=3, pcg_iters=8, w_vel=100.0,
+                                                 exclude_case2=True))
+    assert rep["n_boundary"] == ref["n_boundary"]
+    r_gpu, t_gpu = params_of(fr.node_state.cpu().numpy())
+    r_ref, t_ref = params_of(ref["state"])
+    r0, t0 = params_of(st)
+    assert np.linalg.norm(r_gpu - r_ref) <= 1e-4 * max(np.linalg.norm(r_ref - r0), 1e-6)
+    assert np.linalg.norm(t_gpu - t_ref) <= 1e-4 * max(np.linalg.norm(t_ref - t0), 1e-6)
+    e0 = ref["energies"][0]["total"]
+    for k, e in enumerate(ref["energies"]):
+        assert abs(rep["energy"][k] - e["total"]) <= 1e-5 * e0, k
+    assert abs(rep["e_vel"] - ref["energies"][-1]["vel"]) <= 1e-5 * e0
+
+
 def test_batch_equals_single_solves(ctx, frames):
     """An uneven batch in one launch sequence gives each frame's single-solve result."""
     import paper_1810_02648_amd as cap

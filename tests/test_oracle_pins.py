@@ -329,3 +329,56 @@ def test_energy_decreases_and_recovers(seed):
     err0 = np.sqrt(((proj(f["xyz"].astype(np.float64)) - gt) ** 2).sum(0)).mean()
     err1 = np.sqrt(((proj(V) - gt) ** 2).sum(0)).mean()
     assert err1 < err0
+
+
+# ---------------------------------------------------------------- warm-start network
+def test_warmstart_gradients_match_finite_differences():
+    from oracle import warmstart as ow
+    rng = np.random.default_rng(3)
+    nn = 40
+    X = rng.normal(size=(nn, ow.NF))
+    X[:, 27:] = 0.0
+    Y = rng.normal(size=(nn, 6))
+    edges = np.full((8, nn), -1, np.int64)
+    for k in range(nn):
+        nb = rng.choice(np.setdiff1d(np.arange(nn), [k]), size=rng.integers(0, 9), replace=False)
+        edges[:nb.size, k] = nb
+    P = ow.init_params(1)
+    P["W3"] = rng.normal(0, 0.1, P["W3"].shape)
+    P["b1"] = rng.normal(0, 0.1, ow.HID)
+    y, cache = ow.forward(P, X, edges)
+    g = ow.backward(P, cache, y, Y, edges)
+    h = 1e-6
+    for name in ("W1", "b1", "W2", "b2", "W3", "b3"):
+        flat = P[name].reshape(-1)
+        for idx in rng.choice(flat.size, 6, replace=False):
+            old = flat[idx]
+            flat[idx] = old + h
+            lp = ow.loss(ow.forward(P, X, edges)[0], Y)
+            flat[idx] = old - h
+            lm = ow.loss(ow.forward(P, X, edges)[0], Y)
+            flat[idx] = old
+            fd = (lp - lm) / (2 * h)
+            assert abs(fd - g[name].reshape(-1)[idx]) <= 1e-6 * max(1.0, abs(fd)), (name, idx)
+
+
+def test_neighbour_mean_adjoint():
+    """<mean(H), G> == <H, mean^T(G)> for random H, G (the backward pass's message passing)."""
+    from oracle import warmstart as ow
+    rng = np.random.default_rng(4)
+    nn = 30
+    edges = rng.integers(-1, nn, size=(8, nn))
+    H = rng.normal(size=(nn, 5))
+    G = rng.normal(size=(nn, 5))
+    M, cnt = ow.neighbour_mean(H, edges)
+    assert abs((M * G).sum() - (H * ow.neighbour_mean_transpose(G, edges, cnt)).sum()) < 1e-12
+
+
+def test_adam_matches_closed_form_first_step():
+    """First Adam step moves every parameter by lr * sign(g) (bias-corrected m/sqrt(v))."""
+    from oracle import warmstart as ow
+    P = {"w": np.array([1.0, -2.0, 3.0])}
+    g = {"w": np.array([0.5, -4.0, 1e-3])}
+    st = {}
+    ow.adam(P, g, st, lr=0.1)
+    assert np.allclose(P["w"], [1.0 - 0.1, -2.0 + 0.1, 3.0 - 0.1 * 1e-3 / (1e-3 + 1e-8)], atol=1e-12)
