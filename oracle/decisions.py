@@ -159,9 +159,20 @@ def mesh_edges(tri):
 
 
 def frame_decisions(xyz, tri, graph, state, cam, mask, dt):
-    """All per-frame decisions: dict with u, v, Z, zbuf, visible, boundary, bsign."""
-    W, H = cam.width, cam.height
+    """All per-frame decisions of the non-rigid stage (start positions by the ED recipe)."""
     X, Y, Z = ed_deform_f32(xyz, graph["node_vertex"], graph["bind_idx"], graph["bind_w"], state)
+    return frame_decisions_from_positions(X, Y, Z, tri, cam, mask, dt)
+
+
+def frame_decisions_from_positions(X, Y, Z, tri, cam, mask, dt, outline=False):
+    """Decisions from float32 start positions: u, v, Z, zbuf, visible, boundary, bsign.
+
+    outline: keep in B only contour vertices on the outline of the rendered
+    model, i.e. with an uncovered pixel (zbuf 0) in the 3x3 window around the
+    vertex pixel (window clipped to the image).  A mesh made of overlapping
+    closed parts has contour edges inside its own silhouette; they have no
+    counterpart in the image silhouette's distance transform."""
+    W, H = cam.width, cam.height
     u, v, valid = project_f32(X, Y, Z, cam)
     zb = raster_zbuffer(u, v, Z, valid, tri, W, H)
 
@@ -171,12 +182,13 @@ def frame_decisions(xyz, tri, graph, state, cam, mask, dt):
         py = np.where(valid, np.rint(v), -1).astype(np.int64)
     inside = valid & (px >= 0) & (px < W) & (py >= 0) & (py < H)
     vis = np.zeros(nv, dtype=bool)
-    zbf = zb.view(np.float32)
+    open_ = np.zeros(nv, dtype=bool)
     for i in np.nonzero(inside)[0]:
         y0, y1 = max(0, py[i] - 1), min(H - 1, py[i] + 1)
         x0, x1 = max(0, px[i] - 1), min(W - 1, px[i] + 1)
         blk = zb[y0:y1 + 1, x0:x1 + 1]
         cov = blk[blk > 0]
+        open_[i] = cov.size < blk.size
         if cov.size == 0:
             vis[i] = True
         else:
@@ -199,6 +211,8 @@ def frame_decisions(xyz, tri, graph, state, cam, mask, dt):
             cont[a] = True
             cont[b] = True
     bnd = vis & cont
+    if outline:
+        bnd &= open_
 
     # vertex normals: incident faces in ascending order
     n = [np.zeros(nv, dtype=F32) for _ in range(3)]
