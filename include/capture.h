@@ -269,11 +269,101 @@ CAPTURE_API int capture_nonrigid_solve_warm(capture_ctx *ctx, const capture_fram
                                             void *workspace, size_t workspace_bytes, void *stream);
 
 /* --------------------------------------------------------------------------
+ * Pose stage (Sec. 3.3 energy, Sec. 4 pose solver).  A skeleton of
+ * n_joints joints; each rotating joint carries three axis-angle unknowns
+ * (joint order; the root's rotation is the global rotation), followed by the
+ * root translation t (3) and the translation t' (3) that maps the
+ * root-relative 3D detections into the camera frame: n_unknowns =
+ * 3 * (rotating joints) + 6.  Joint rotations compose down the tree,
+ * R_j = R_parent Exp(theta_j), p_j = p_parent + R_parent (J_j - J_parent),
+ * p_root = J_root + t, and the mesh follows by linear blend skinning (the
+ * paper skins with dual quaternions; this library uses LBS) with 4
+ * influences per vertex: V_i = sum_s w_s (R_j (v_i - J_j) + p_j).
+ * Energy: E = l2d sum_j lambda_j ||pi(p_j) - P2D_j||^2
+ *           + l3d sum_j ||p_j - (P3D_j + t')||^2 + lsil sum_{i in B} b_i I_DT(pi(V_i))^2,
+ * decisions (visible set, contour set B, signs b_i) taken once per solve at
+ * the start pose with the same raster and decision rules as the non-rigid
+ * stage.  Each Gauss-Newton step solves (J^T J + mu I) delta = -J^T B F with
+ * mu = 1e-6 * max diag(J^T J) by a dense FP64 Cholesky factorisation, then
+ * theta <- theta + delta (additive axis-angle update).
+ * ------------------------------------------------------------------------ */
+#define CAPTURE_MAX_JOINTS 32
+#define CAPTURE_MAX_POSE_UNKNOWNS 81
+
+typedef struct capture_body capture_body;
+
+typedef struct {
+    int32_t n_vertices, n_triangles, n_joints;
+    const int32_t *tri;           /* [3][n_triangles] (closed parts may overlap) */
+    const float *xyz;             /* [3][n_vertices] rest mesh, skinned to the rest joints */
+    const int32_t *bind_joint;    /* [4][n_vertices] joint of each skinning influence */
+    const float *bind_w;          /* [4][n_vertices] influence weights (sum 1 per vertex) */
+    const int32_t *parents;       /* host [n_joints]: -1 for joint 0 only, otherwise parents[j] < j */
+    const double *rest_joints;    /* host [3][n_joints] rest joint positions (metres) */
+    const int32_t *has_rotation;  /* host [n_joints]: 1 = the joint carries 3 axis-angle unknowns */
+} capture_body_desc;
+
+/* Validates the description (sizes, tree order, indices, edge-manifold mesh,
+ * finite weights, n_unknowns <= CAPTURE_MAX_POSE_UNKNOWNS) and keeps a device
+ * copy of the mesh tables, skinning and skeleton.  Synchronous. */
+CAPTURE_API int capture_body_create(capture_ctx *ctx, const capture_body_desc *desc, capture_body **out);
+CAPTURE_API void capture_body_destroy(capture_body *body);
+CAPTURE_API int capture_body_unknowns(const capture_body *body, int32_t *n_unknowns);
+
+typedef struct {
+    const capture_body *body;
+    capture_camera camera;
+    const uint8_t *mask;          /* [H][W] foreground silhouette, 0 = background */
+    const double *p2d;            /* [2][n_joints] 2D joint detections (pixels) */
+    const double *p3d;            /* [3][n_joints] root-relative 3D joint detections (metres) */
+    const double *lambda;         /* [n_joints] per-joint 2D confidences, >= 0 */
+    double *pose;                 /* [n_unknowns] in: start pose, out: solution */
+} capture_pose_frame;
+
+/* CAPTURE_FLAG_OUTLINE_ONLY: B keeps only contour vertices on the outline of
+ * the rendered model (an uncovered pixel in the 3x3 window around the vertex
+ * pixel); contours of parts seen in front of other parts are dropped.  Also
+ * CAPTURE_FLAG_EXCLUDE_CASE2 as for the non-rigid stage. */
+#define CAPTURE_FLAG_OUTLINE_ONLY 2u
+typedef struct {
+    double l2d, l3d, lsil;        /* term weights, finite and >= 0 */
+    int32_t gn_iters;             /* 1..CAPTURE_MAX_GN */
+    uint32_t flags;               /* CAPTURE_FLAG_EXCLUDE_CASE2 | CAPTURE_FLAG_OUTLINE_ONLY */
+} capture_pose_params;
+
+typedef struct {
+    double energy[CAPTURE_MAX_GN + 1];    /* E at the start of each step, then the final E */
+    double e2d, e3d, e_sil, e_sil_abs;    /* final per-term energies (e_sil_abs: with |b_i|) */
+    int32_t n_visible, n_boundary, gn_done;
+    int32_t status;                       /* CAPTURE_OK or a device-detected error */
+} capture_pose_report;
+
+/* Workspace bytes of one pose frame (a host struct; its arrays are not read). */
+CAPTURE_API int capture_pose_workspace_size(capture_ctx *ctx, const capture_pose_frame *frame, size_t *bytes);
+
+/* Gauss-Newton pose solve of one frame.  On a device-detected error (a
+ * non-positive Cholesky pivot, a non-finite energy) frame->pose is restored
+ * to the start pose and the status is returned. */
+CAPTURE_API int capture_pose_solve(capture_ctx *ctx, const capture_pose_frame *frame,
+                                   const capture_pose_params *params, capture_pose_report *report,
+                                   void *workspace, size_t workspace_bytes, void *stream);
+
+/* Decisions and one linearisation at frame->pose (not modified):
+ *   system  [n_unknowns][n_unknowns + 1] (device, may be NULL): J^T J (undamped)
+ *           with -J^T B F as the last column
+ *   energy  host [4]: 2D, 3D, silhouette (with b_i), silhouette with |b_i|
+ *   vflags  [n_vertices] (device, may be NULL): bit0 visible, bit1 in B, bit2 b_i = -1 */
+CAPTURE_API int capture_pose_linearize(capture_ctx *ctx, const capture_pose_frame *frame,
+                                       const capture_pose_params *params, double *system, double *energy,
+                                       uint8_t *vflags, void *workspace, size_t workspace_bytes, void *stream);
+
+/* --------------------------------------------------------------------------
  * Kernel timing.  While enabled, every launch of the solver kernels is
  * bracketed by HIP events on the call's stream; elapsed times accumulate per
  * kernel until read.  Kernel names: "blur", "contour", "dt_cols", "dt_rows",
  * "deform_start", "raster", "contour_edges", "decide", "linearize",
- * "node_init", "apply", "node_pcg", "ws_features", "ws_mlp".
+ * "node_init", "apply", "node_pcg", "ws_features", "ws_mlp", "pose_lbs",
+ * "pose_rows", "pose_jtj", "pose_step".
  * ------------------------------------------------------------------------ */
 CAPTURE_API int capture_profile_enable(capture_ctx *ctx, int on);
 /* Accumulated time (ms) and launch count of `kernel` since the last read;

@@ -1,4 +1,4 @@
-"""MI355X-native per-frame Gauss-Newton solvers (LiveCap non-rigid stage).
+"""MI355X-native per-frame Gauss-Newton solvers (LiveCap pose and non-rigid stages).
 
 Thin Python binding over the C ABI in ``libcapture.so`` (include/capture.h).
 PyTorch only provides device memory and the stream: every step of the solve
@@ -13,7 +13,8 @@ import torch
 from . import capi
 from .capi import CaptureError  # noqa: F401
 
-__all__ = ["Context", "Template", "FrameInputs", "graph_build", "CaptureError"]
+__all__ = ["Context", "Template", "FrameInputs", "graph_build", "CaptureError", "Body", "PoseInputs",
+           "pose_params", "pose_solve", "pose_linearize"]
 
 
 def _ptr(t):
@@ -124,9 +125,9 @@ class FrameInputs:
 
 
 def params(w_sil=1.0, w_photo=0.1, w_arap=10.0, gn_iters=5, pcg_iters=10, tau_color=math.inf, w_vel=0.0,
-           exclude_case2=False):
-    return capi.NonrigidParams(w_sil, w_photo, w_arap, tau_color, w_vel, gn_iters, pcg_iters,
-                               capi.FLAG_EXCLUDE_CASE2 if exclude_case2 else 0)
+           exclude_case2=False, outline_only=False):
+    flags = (capi.FLAG_EXCLUDE_CASE2 if exclude_case2 else 0) | (capi.FLAG_OUTLINE_ONLY if outline_only else 0)
+    return capi.NonrigidParams(w_sil, w_photo, w_arap, tau_color, w_vel, gn_iters, pcg_iters, flags)
 
 
 def _frames(frames):
@@ -307,3 +308,93 @@ def nonrigid_solve_warm(ctx, frame, prm, net, state_prev2=None, target_energy=-m
                                                    float(target_energy), C.byref(rep), _ptr(ws), ws.numel(),
                                                    _stream()))
     return _report_dict(rep, prm.gn_iters)
+
+
+# ---------------------------------------------------------------- pose stage
+class Body:
+    """Skeleton, skinned mesh and mesh tables of the pose stage (capture_body)."""
+
+    def __init__(self, ctx, tri, xyz, bind_joint, bind_w, parents, rest_joints, has_rotation):
+        nf = tri.shape[1]
+        nv = xyz.shape[1]
+        nj = len(parents)
+        _need(tri, torch.int32, (3, nf), "tri")
+        _need(xyz, torch.float32, (3, nv), "xyz")
+        _need(bind_joint, torch.int32, (4, nv), "bind_joint")
+        _need(bind_w, torch.float32, (4, nv), "bind_w")
+        par = (C.c_int32 * nj)(*[int(p) for p in parents])
+        rest = (C.c_double * (3 * nj))(*[float(x) for x in rest_joints.reshape(-1)])
+        rot = (C.c_int32 * nj)(*[int(bool(r)) for r in has_rotation])
+        d = capi.BodyDesc(nv, nf, nj, _ptr(tri), _ptr(xyz), _ptr(bind_joint), _ptr(bind_w),
+                          C.cast(par, C.c_void_p), C.cast(rest, C.c_void_p), C.cast(rot, C.c_void_p))
+        h = C.c_void_p()
+        capi.check(ctx.lib.capture_body_create(ctx.h, C.byref(d), C.byref(h)))
+        self.ctx, self.h, self.nv, self.nf, self.nj = ctx, h, nv, nf, nj
+        n = C.c_int32()
+        capi.check(ctx.lib.capture_body_unknowns(h, C.byref(n)))
+        self.nu = n.value
+
+    def __del__(self):
+        try:
+            if self.h:
+                self.ctx.lib.capture_body_destroy(self.h)
+                self.h = None
+        except Exception:
+            pass
+
+
+class PoseInputs:
+    """Device tensors of one pose frame (see capture_pose_frame)."""
+
+    def __init__(self, body, camera, mask, p2d, p3d, lam, pose):
+        W, H = int(camera.width), int(camera.height)
+        nj = body.nj
+        _need(mask, torch.uint8, (H, W), "mask")
+        _need(p2d, torch.float64, (2, nj), "p2d")
+        _need(p3d, torch.float64, (3, nj), "p3d")
+        _need(lam, torch.float64, (nj,), "lambda")
+        _need(pose, torch.float64, (body.nu,), "pose")
+        self.body, self.mask, self.p2d, self.p3d, self.lam, self.pose = body, mask, p2d, p3d, lam, pose
+        self.camera = capi.Camera(W, H, float(camera.fx), float(camera.fy), float(camera.cx), float(camera.cy))
+
+    def struct(self):
+        return capi.PoseFrame(self.body.h, self.camera, _ptr(self.mask), _ptr(self.p2d), _ptr(self.p3d),
+                              _ptr(self.lam), _ptr(self.pose))
+
+
+def pose_params(l2d=1.0 / 9.0, l3d=2500.0, lsil=0.05, gn_iters=3, exclude_case2=True, outline_only=True):
+    flags = (capi.FLAG_EXCLUDE_CASE2 if exclude_case2 else 0) | (capi.FLAG_OUTLINE_ONLY if outline_only else 0)
+    return capi.PoseParams(l2d, l3d, lsil, gn_iters, flags)
+
+
+def _pose_ws(ctx, fr):
+    n = C.c_size_t()
+    capi.check(ctx.lib.capture_pose_workspace_size(ctx.h, C.byref(fr), C.byref(n)))
+    return ctx.workspace(n.value)
+
+
+def pose_solve(ctx, frame, prm):
+    """Gauss-Newton pose solve in place (frame.pose); returns the report as a dict."""
+    fr = frame.struct()
+    ws = _pose_ws(ctx, fr)
+    rep = capi.PoseReport()
+    capi.check(ctx.lib.capture_pose_solve(ctx.h, C.byref(fr), C.byref(prm), C.byref(rep), _ptr(ws), ws.numel(),
+                                          _stream()))
+    return dict(energy=[rep.energy[k] for k in range(rep.gn_done + 1)], e2d=rep.e2d, e3d=rep.e3d,
+                e_sil=rep.e_sil, e_sil_abs=rep.e_sil_abs, n_visible=rep.n_visible, n_boundary=rep.n_boundary,
+                gn_done=rep.gn_done, status=rep.status)
+
+
+def pose_linearize(ctx, frame, prm):
+    """Decisions and normal equations at frame.pose: system [nu][nu+1] (J^T J | -J^T B F),
+    the 4 energy terms and the vertex flags."""
+    fr = frame.struct()
+    ws = _pose_ws(ctx, fr)
+    nu = frame.body.nu
+    dev = frame.pose.device
+    system = torch.empty((nu, nu + 1), dtype=torch.float64, device=dev)
+    vflags = torch.empty(frame.body.nv, dtype=torch.uint8, device=dev)
+    e = (C.c_double * 4)()
+    capi.check(ctx.lib.capture_pose_linearize(ctx.h, C.byref(fr), C.byref(prm), _ptr(system), e, _ptr(vflags),
+                                              _ptr(ws), ws.numel(), _stream()))
+    return dict(system=system, energy=list(e), vflags=vflags)

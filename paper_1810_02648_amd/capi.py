@@ -32,6 +32,9 @@ class NonrigidParams(C.Structure):
 
 
 FLAG_EXCLUDE_CASE2 = 1
+FLAG_OUTLINE_ONLY = 2
+MAX_JOINTS = 32
+MAX_POSE_UNKNOWNS = 81
 
 
 class Report(C.Structure):
@@ -40,6 +43,28 @@ class Report(C.Structure):
                 ("energy_prev", C.c_double),
                 ("energy_pred", C.c_double), ("n_visible", C.c_int32), ("n_boundary", C.c_int32),
                 ("gn_done", C.c_int32), ("warm_start", C.c_int32), ("status", C.c_int32)]
+
+
+class BodyDesc(C.Structure):
+    _fields_ = [("n_vertices", C.c_int32), ("n_triangles", C.c_int32), ("n_joints", C.c_int32),
+                ("tri", C.c_void_p), ("xyz", C.c_void_p), ("bind_joint", C.c_void_p), ("bind_w", C.c_void_p),
+                ("parents", C.c_void_p), ("rest_joints", C.c_void_p), ("has_rotation", C.c_void_p)]
+
+
+class PoseFrame(C.Structure):
+    _fields_ = [("body", C.c_void_p), ("camera", Camera), ("mask", C.c_void_p), ("p2d", C.c_void_p),
+                ("p3d", C.c_void_p), ("lambda_", C.c_void_p), ("pose", C.c_void_p)]
+
+
+class PoseParams(C.Structure):
+    _fields_ = [("l2d", C.c_double), ("l3d", C.c_double), ("lsil", C.c_double), ("gn_iters", C.c_int32),
+                ("flags", C.c_uint32)]
+
+
+class PoseReport(C.Structure):
+    _fields_ = [("energy", C.c_double * (MAX_GN + 1)), ("e2d", C.c_double), ("e3d", C.c_double),
+                ("e_sil", C.c_double), ("e_sil_abs", C.c_double), ("n_visible", C.c_int32),
+                ("n_boundary", C.c_int32), ("gn_done", C.c_int32), ("status", C.c_int32)]
 
 
 _P = C.c_void_p
@@ -71,12 +96,21 @@ SIGNATURES = {
                                                C.POINTER(C.c_double), _P]),
     "capture_nonrigid_solve_warm": (C.c_int, [_P, C.POINTER(Frame), C.POINTER(NonrigidParams), _P, _P,
                                               C.c_double, C.POINTER(Report), _P, C.c_size_t, _P]),
+    "capture_body_create": (C.c_int, [_P, C.POINTER(BodyDesc), C.POINTER(C.c_void_p)]),
+    "capture_body_destroy": (None, [_P]),
+    "capture_body_unknowns": (C.c_int, [_P, C.POINTER(C.c_int32)]),
+    "capture_pose_workspace_size": (C.c_int, [_P, C.POINTER(PoseFrame), C.POINTER(C.c_size_t)]),
+    "capture_pose_solve": (C.c_int, [_P, C.POINTER(PoseFrame), C.POINTER(PoseParams), C.POINTER(PoseReport),
+                                     _P, C.c_size_t, _P]),
+    "capture_pose_linearize": (C.c_int, [_P, C.POINTER(PoseFrame), C.POINTER(PoseParams), _P,
+                                         C.POINTER(C.c_double), _P, _P, C.c_size_t, _P]),
     "capture_profile_enable": (C.c_int, [_P, C.c_int]),
     "capture_profile_read": (C.c_int, [_P, C.c_char_p, C.POINTER(C.c_double), C.POINTER(C.c_int64)]),
 }
 
 KERNELS = ("blur", "contour", "dt_cols", "dt_rows", "deform_start", "raster", "contour_edges", "decide",
-           "linearize", "node_init", "apply", "node_pcg", "ws_features", "ws_mlp")
+           "linearize", "node_init", "apply", "node_pcg", "ws_features", "ws_mlp", "pose_lbs", "pose_rows",
+           "pose_jtj", "pose_step")
 WS_PARAMS = 38662
 
 _lib = None

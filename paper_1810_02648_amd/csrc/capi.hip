@@ -6,6 +6,7 @@
 #include <vector>
 
 #include "device.hpp"
+#include "runtime.hpp"
 
 namespace cap {
 
@@ -178,16 +179,6 @@ __global__ __launch_bounds__(256) void k_node_edges(const float *__restrict__ xy
 }
 
 // ---------------------------------------------------------------- workspace layout
-struct Layout {
-    size_t off = 0;
-    template <typename T>
-    T *take(uint8_t *base, size_t n) {
-        off = (off + 255) & ~size_t(255);
-        T *p = base ? reinterpret_cast<T *>(base + off) : nullptr;
-        off += std::max<size_t>(n, 1) * sizeof(T);
-        return p;
-    }
-};
 
 void carve(Layout &L, uint8_t *base, const capture_frame &f, ProbDev &pr) {
     const TemplateDev &T = f.tmpl->dev;
@@ -266,7 +257,8 @@ int check_params(const capture_nonrigid_params *p) {
     if (!finite(p->w_sil) || !finite(p->w_photo) || !finite(p->w_arap) || !finite(p->w_vel) || p->w_sil < 0 ||
         p->w_photo < 0 || p->w_arap < 0 || p->w_vel < 0)
         return fail(CAPTURE_EINVAL, "weights must be finite and non-negative");
-    if (p->flags & ~uint32_t(CAPTURE_FLAG_EXCLUDE_CASE2)) return fail(CAPTURE_EINVAL, "unknown flag bits");
+    if (p->flags & ~uint32_t(CAPTURE_FLAG_EXCLUDE_CASE2 | CAPTURE_FLAG_OUTLINE_ONLY))
+        return fail(CAPTURE_EINVAL, "unknown flag bits");
     if (std::isnan(p->tau_color) || p->tau_color < 0) return fail(CAPTURE_EINVAL, "tau_color must be >= 0 or +inf");
     return CAPTURE_OK;
 }
@@ -274,52 +266,10 @@ int check_params(const capture_nonrigid_params *p) {
 // What a run should do beyond the per-frame preprocessing.
 enum class Stage { Decisions, Linearize, Solve };
 
-struct Run {
-    Profiler *prof = nullptr;
-    int n = 0;
-    std::vector<ProbDev> probs;
-    ProbDev *dprobs = nullptr;
-    int max_nv = 0, max_nf = 0, max_hw = 0, max_w = 0, max_h = 0, max_tiles = 0, max_me = 0;
-    size_t lds_lin = 0, lds_apply = 0;
-    hipStream_t s = nullptr;
-};
-
 const char *kKernelNames[K_COUNT] = {"blur", "contour", "dt_cols", "dt_rows", "deform_start", "raster",
                                      "contour_edges", "decide", "linearize", "node_init", "apply", "node_pcg",
-                                     "ws_features", "ws_mlp"};
-
-// Launch `go` bracketed by events when timing is on.
-template <typename F>
-void timed(Run &R, int kid, F go) {
-    Profiler *P = R.prof;
-    if (!P || !P->on) { go(); return; }
-    while (P->ev.size() < P->used + 2) {
-        hipEvent_t e;
-        if (hipEventCreate(&e) != hipSuccess) { go(); return; }
-        P->ev.push_back(e);
-    }
-    const size_t i = P->used;
-    P->used += 2;
-    (void)hipEventRecord(P->ev[i], R.s);
-    go();
-    (void)hipEventRecord(P->ev[i + 1], R.s);
-    P->pending.push_back({kid, i});
-}
-
-// After the stream has been synchronised: fold the event pairs into the totals.
-void settle(Run &R) {
-    Profiler *P = R.prof;
-    if (!P) return;
-    for (auto &pe : P->pending) {
-        float ms = 0.0f;
-        if (hipEventElapsedTime(&ms, P->ev[pe.second], P->ev[pe.second + 1]) == hipSuccess) {
-            P->total_ms[pe.first] += ms;
-            P->launches[pe.first] += 1;
-        }
-    }
-    P->pending.clear();
-    P->used = 0;
-}
+                                     "ws_features", "ws_mlp", "pose_lbs", "pose_rows", "pose_jtj",
+                                     "pose_step"};
 
 int setup(Run &R, capture_ctx *ctx, int n, const capture_frame *frames, const capture_nonrigid_params *params,
           void *ws, size_t ws_bytes, void *stream) {
@@ -340,6 +290,7 @@ int setup(Run &R, capture_ctx *ctx, int n, const capture_frame *frames, const ca
     const float tau = params ? (params->tau_color > 0 ? params->tau_color : INFINITY) : INFINITY;
     const float wvel = params ? params->w_vel : 0.0f;
     const int excl = params ? int(params->flags & CAPTURE_FLAG_EXCLUDE_CASE2) : 0;
+    const int outline = params ? int((params->flags & CAPTURE_FLAG_OUTLINE_ONLY) != 0) : 0;
     for (int i = 0; i < n; ++i) {
         const capture_frame &f = frames[i];
         ProbDev &pr = R.probs[i];
@@ -349,7 +300,7 @@ int setup(Run &R, capture_ctx *ctx, int n, const capture_frame *frames, const ca
         pr.fx = f.camera.fx; pr.fy = f.camera.fy; pr.cx = f.camera.cx; pr.cy = f.camera.cy;
         pr.sw_sil = std::sqrt(wsil); pr.sw_photo = std::sqrt(wph); pr.sw_arap = std::sqrt(war);
         pr.w_arap = war; pr.tau = tau;
-        pr.w_vel = wvel; pr.sw_vel = std::sqrt(wvel); pr.exclude_case2 = excl;
+        pr.w_vel = wvel; pr.sw_vel = std::sqrt(wvel); pr.exclude_case2 = excl; pr.outline_only = outline;
         pr.target = -INFINITY;
         const TemplateDev &T = pr.T;
         R.max_nv = std::max(R.max_nv, T.nv);
@@ -366,7 +317,6 @@ int setup(Run &R, capture_ctx *ctx, int n, const capture_frame *frames, const ca
     return CAPTURE_OK;
 }
 
-unsigned blocks(size_t n, unsigned t) { return unsigned((n + t - 1) / t); }
 
 int launch_frame(Run &R, int gn_iters = 0) {
     const int n = R.n;
@@ -397,7 +347,8 @@ int launch_frame(Run &R, int gn_iters = 0) {
         hipLaunchKernelGGL(k_dt_cols, dim3(blocks(nsegw, 256), n), dim3(256), 0, s, R.dprobs);
     });
     timed(R, K_DT_ROWS, [&] {
-        hipLaunchKernelGGL(k_dt_rows, dim3(R.max_h, n), dim3(256), sizeof(int) * 3 * R.max_w, s, R.dprobs);
+        hipLaunchKernelGGL(k_dt_rows, dim3(R.max_h, n), dim3(256), (sizeof(int) * 3 + sizeof(short)) * R.max_w + 16,
+                           s, R.dprobs);
     });
     timed(R, K_DEFORM, [&] {
     hipLaunchKernelGGL(k_deform_start, gv, dim3(256), 0, s, R.dprobs);

@@ -79,6 +79,7 @@ struct ProbDev {
     float fx, fy, cx, cy;
     float sw_sil, sw_photo, sw_arap, w_arap, tau, w_vel, sw_vel;
     int exclude_case2;
+    int outline_only;            // contour set B restricted to the rendered model's outline
     // images
     float *blur_tmp, *blurred, *dt;
     int *colg;
@@ -129,10 +130,54 @@ struct Gemm {
     int relu_copy;
 };
 
+// ---------------------------------------------------------------- pose stage
+constexpr int kMaxJoints = 32;
+constexpr int kMaxPoseUnknowns = 81;     // 3 per rotating joint + root t (3) + t' (3)
+constexpr int kPoseTile = 16;            // MFMA f64 16x16x4 tiles of J^T J
+constexpr int kPoseMaxCols = 96;         // unknowns + the b*F column, padded to 16
+constexpr int kPoseChunks = 8;           // row chunks of the J^T J reduction
+constexpr int kPoseRowThreads = 256;
+constexpr int kPoseStepThreads = 256;
+
+// Skeleton and skinning of a body (device copy of the static part).
+struct BodyDev {
+    int nj, nu, np, it, itp, maxdepth, nv;
+    int parent[kMaxJoints], col[kMaxJoints], depth[kMaxJoints];
+    uint32_t anc[kMaxJoints];        // bit k set: joint k is j itself or one of its ancestors
+    double rest[3][kMaxJoints];      // rest joint positions
+    const float *xyz;                // [3][nv] rest mesh
+    const int *bind_joint;           // [4][nv]
+    const float *bind_w;             // [4][nv]
+};
+
+// One pose problem: body, detections, weights and its workspace.
+struct PoseDev {
+    BodyDev B;
+    int W, H;
+    double fx, fy, cx, cy;
+    double s3d, ssil;                // square roots of the 3D and silhouette weights
+    double l2d;
+    const double *p2d, *p3d, *lam;   // [2][nj], [3][nj], [nj]
+    double *pose;                    // caller's [nu]
+    const float *dt;                 // [H][W]
+    const uint8_t *vflags;           // [nv] decision flags
+    double *jR, *jp, *jA;            // [nj][9], [nj][3], [nj][9]: global rotations, positions, derivative axes
+    double *pose0;                   // [nu] start pose (restored on a device-detected error)
+    int *blist;                      // [nv] contour set: (vertex << 1) | (b_i == -1), ascending
+    int *nb;                         // [1] |B|
+    double *rows;                    // [max_rows][np] Jacobian rows, column nu holds b*F
+    double *epart;                   // [row blocks][4] energy partials: 2D, 3D, sil, sil with |b|
+    double *tpart;                   // [kPoseChunks][ntp][256] J^T J tile partials
+    double *energy;                  // [MAX_GN + 1][4]
+    double *sys;                     // [nu][nu + 1] last assembled system (J^T J | -J^T B F), undamped
+    int *status;                     // [1]
+};
+
 // Optional per-kernel timing with HIP events (capture_profile_*).
 enum KernelId {
     K_BLUR, K_CONTOUR, K_DT_COLS, K_DT_ROWS, K_DEFORM, K_RASTER, K_CEDGES, K_DECIDE,
-    K_LIN, K_NODE_INIT, K_APPLY, K_NODE_PCG, K_WS_FEAT, K_WS_MLP, K_COUNT
+    K_LIN, K_NODE_INIT, K_APPLY, K_NODE_PCG, K_WS_FEAT, K_WS_MLP,
+    K_POSE_LBS, K_POSE_ROWS, K_POSE_JTJ, K_POSE_STEP, K_COUNT
 };
 
 struct Profiler {
@@ -159,6 +204,13 @@ struct capture_warmstart {
     uint16_t *wb;
     float *X, *z1, *z2, *y, *tgt, *dy, *se, *dc, *dz;
     uint16_t *Xb, *c1, *c2, *dyb, *dzb;
+};
+
+struct capture_body {
+    cap::BodyDev dev;
+    capture_template *topo;     // mesh tables for the raster and decision kernels
+    void *mem;                  // device copy of xyz and skinning
+    int device;
 };
 
 struct capture_template {

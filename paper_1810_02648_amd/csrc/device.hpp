@@ -108,6 +108,24 @@ __device__ inline void cell_of(double u, int &i, float &f) {
     if (f >= 1.0f) f = 0.99999994f;
 }
 
+// Start-state geometry of vertex i from its float32 position: projection,
+// 1/256-pixel snapping and validity (decision recipe), contour mark cleared.
+__device__ inline void store_start_vertex(const ProbDev &pr, int i, float X, float Y, float Z) {
+    const int nv = pr.T.nv;
+    float u = (pr.fx * X) / Z + pr.cx;
+    float vv = (pr.fy * Y) / Z + pr.cy;
+    bool valid = Z > 0.0f && fabsf(u) <= 65536.0f && fabsf(vv) <= 65536.0f;
+    pr.dx[i] = X;
+    pr.dx[nv + i] = Y;
+    pr.dx[2 * nv + i] = Z;
+    pr.duv[i] = u;
+    pr.duv[nv + i] = vv;
+    pr.dfix[i] = valid ? int(rintf(u * 256.0f)) : 0;
+    pr.dfix[nv + i] = valid ? int(rintf(vv * 256.0f)) : 0;
+    pr.dvalid[i] = valid ? 1 : 0;
+    pr.vcont[i] = 0;
+}
+
 // Deterministic block-wide sum of a double: fixed butterfly inside each wave,
 // then the wave sums in wave order.  `sh` holds NT/64 doubles.
 template <int NT>

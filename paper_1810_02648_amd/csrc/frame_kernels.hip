@@ -111,76 +111,92 @@ __global__ void k_dt_cols(const ProbDev *__restrict__ P) {
     }
 }
 
-// Phase 2: per row, D(x) = min over x' of (x - x')^2 + g(x')^2, exact.  The
-// leftmost minimiser is non-decreasing in x ((x - x')^2 is a Monge cost), so
-// x is solved in dyadic order, each inside the bracket of minimisers of its
-// two already-solved neighbours.  One workgroup per row, all in LDS.
-__device__ inline void argmin_merge(int &v, int &a, int ov, int oa) {
-    if (ov < v || (ov == v && oa < a)) { v = ov; a = oa; }
-}
+// Phase 2: per row, D(x) = min over x' of (x - x')^2 + G(x'), G = g^2, exact.
+// The row is cut into kChunks column chunks; one thread per chunk builds the
+// lower envelope of the chunk's parabolas (x - x')^2 + G(x') (sequential
+// envelope construction with exact rational breakpoints compared in int64),
+// then every pixel evaluates its own chunk's envelope by binary search and
+// visits neighbouring chunks outwards while their column distance can still
+// beat the best value.  One workgroup per row, all in LDS.
+constexpr int kChunks = 32;
 
 __global__ __launch_bounds__(256) void k_dt_rows(const ProbDev *__restrict__ P) {
     extern __shared__ int sh[];
+    __shared__ int cnt[kChunks];
     const ProbDev &pr = P[blockIdx.y];
     const int W = pr.W, H = pr.H;
     const int y = blockIdx.x;
     if (y >= H) return;
-    int *G = sh, *val = sh + W, *arg = sh + 2 * W;
-    __shared__ int wv[4], wa[4];
     const int far2 = 1 << 30;
+    int *G = sh, *zn = sh + W, *zd = sh + 2 * W;
+    short *ev = reinterpret_cast<short *>(sh + 3 * W);
     for (int x = threadIdx.x; x < W; x += blockDim.x) {
         const int g = pr.colg[size_t(y) * W + x];
         G[x] = g >= kFar ? far2 : g * g;
     }
     __syncthreads();
-    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    // x = 0 over the whole row
-    {
-        int v = 0x7fffffff, a = 0x7fffffff;
-        for (int xp = threadIdx.x; xp < W; xp += blockDim.x) argmin_merge(v, a, xp * xp + G[xp], xp);
-        for (int o = 32; o > 0; o >>= 1) argmin_merge(v, a, __shfl_xor(v, o), __shfl_xor(a, o));
-        if (lane == 0) { wv[wid] = v; wa[wid] = a; }
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            int bv = wv[0], ba = wa[0];
-            for (int w = 1; w < 4; ++w) argmin_merge(bv, ba, wv[w], wa[w]);
-            val[0] = bv;
-            arg[0] = ba;
-        }
-        __syncthreads();
-    }
-    int P2 = 1;
-    while (P2 < W) P2 <<= 1;
-    for (int s = P2 >> 1; s >= 1; s >>= 1) {
-        const int count = (W - 1 - s) >= 0 ? (W - 1 - s) / (2 * s) + 1 : 0;   // x = s, 3s, 5s, ... < W
-        if (count <= 4) {
-            // one wave per point
-            for (int m = wid; m < count; m += 4) {
-                const int x = s + 2 * s * m;
-                const int lo = arg[x - s], hi = (x + s < W) ? arg[x + s] : W - 1;
-                int v = 0x7fffffff, a = 0x7fffffff;
-                for (int xp = lo + lane; xp <= hi; xp += 64) argmin_merge(v, a, (x - xp) * (x - xp) + G[xp], xp);
-                for (int o = 32; o > 0; o >>= 1) argmin_merge(v, a, __shfl_xor(v, o), __shfl_xor(a, o));
-                if (lane == 0) { val[x] = v; arg[x] = a; }
+    const int cs = (W + kChunks - 1) / kChunks;
+    if (threadIdx.x < kChunks) {
+        const int c = threadIdx.x, a = c * cs, b = min(W, a + cs);
+        int k = -1;
+        for (int q = a; q < b; ++q) {
+            const int gq = G[q];
+            if (gq >= far2) continue;
+            if (k < 0) {
+                k = 0;
+                ev[a] = short(q);
+                zn[a] = -1;
+                zd[a] = 0;
+                continue;
             }
-        } else {
-            for (int m = threadIdx.x; m < count; m += blockDim.x) {
-                const int x = s + 2 * s * m;
-                const int lo = arg[x - s], hi = (x + s < W) ? arg[x + s] : W - 1;
-                int v = 0x7fffffff, a = lo;
-                for (int xp = lo; xp <= hi; ++xp) {
-                    const int c = (x - xp) * (x - xp) + G[xp];
-                    if (c < v) { v = c; a = xp; }
-                }
-                val[x] = v;
-                arg[x] = a;
+            int num, den;
+            for (;;) {
+                const int v = ev[a + k];
+                num = (gq + q * q) - (G[v] + v * v);
+                den = 2 * (q - v);
+                if (k > 0 && (long long)num * zd[a + k] <= (long long)zn[a + k] * den) { --k; continue; }
+                break;
             }
+            ++k;
+            ev[a + k] = short(q);
+            zn[a + k] = num;
+            zd[a + k] = den;
         }
-        __syncthreads();
+        cnt[c] = k + 1;
     }
+    __syncthreads();
+    auto eval = [&](int c, int x) {
+        const int n = cnt[c];
+        if (n == 0) return far2;
+        const int a = c * cs;
+        int lo = 0, hi = n - 1;   // last envelope piece whose left breakpoint is <= x
+        while (lo < hi) {
+            const int m = (lo + hi + 1) >> 1;
+            if ((long long)zn[a + m] <= (long long)x * zd[a + m]) lo = m; else hi = m - 1;
+        }
+        const int v = ev[a + lo];
+        return (x - v) * (x - v) + G[v];
+    };
     for (int x = threadIdx.x; x < W; x += blockDim.x) {
-        const int b = val[x];
-        pr.dt[size_t(y) * W + x] = b >= far2 ? 0.0f : sqrtf(float(b));
+        const int c0 = x / cs;
+        int best = eval(c0, x);
+        int l = c0 - 1, r = c0 + 1;
+        while (l >= 0 || r < kChunks) {
+            if (l >= 0) {
+                const int d = x - (min(W, l * cs + cs) - 1);
+                if (d * d < best) { const int e = eval(l, x); best = e < best ? e : best; --l; } else l = -1;
+            }
+            if (r < kChunks) {
+                if (r * cs < W && (r * cs - x) * (r * cs - x) < best) {
+                    const int e = eval(r, x);
+                    best = e < best ? e : best;
+                    ++r;
+                } else {
+                    r = kChunks;
+                }
+            }
+        }
+        pr.dt[size_t(y) * W + x] = best >= far2 ? 0.0f : sqrtf(float(best));
     }
 }
 
@@ -208,19 +224,7 @@ __global__ void k_deform_start(const ProbDev *__restrict__ P) {
             acc[a] = acc[a] + w * yv;
         }
     }
-    float X = acc[0], Y = acc[1], Z = acc[2];
-    float u = (pr.fx * X) / Z + pr.cx;
-    float vv = (pr.fy * Y) / Z + pr.cy;
-    bool valid = Z > 0.0f && fabsf(u) <= 65536.0f && fabsf(vv) <= 65536.0f;
-    pr.dx[i] = X;
-    pr.dx[nv + i] = Y;
-    pr.dx[2 * nv + i] = Z;
-    pr.duv[i] = u;
-    pr.duv[nv + i] = vv;
-    pr.dfix[i] = valid ? int(rintf(u * 256.0f)) : 0;
-    pr.dfix[nv + i] = valid ? int(rintf(vv * 256.0f)) : 0;
-    pr.dvalid[i] = valid ? 1 : 0;
-    pr.vcont[i] = 0;
+    store_start_vertex(pr, i, acc[0], acc[1], acc[2]);
 }
 
 // Per face: cross product (for normals), then rasterise the inverse depth with
@@ -320,16 +324,18 @@ __global__ void k_decide(const ProbDev *__restrict__ P) {
         int px = int(rintf(u)), py = int(rintf(v));
         if (px >= 0 && px < W && py >= 0 && py < H) {
             uint32_t m = 0xffffffffu;
+            bool open = false;      // an uncovered pixel in the window: the vertex is on the outline
             for (int y = max(py - 1, 0); y <= min(py + 1, H - 1); ++y)
                 for (int x = max(px - 1, 0); x <= min(px + 1, W - 1); ++x) {
                     uint32_t z = pr.zbuf[size_t(y) * W + x];
                     if (z != 0u && z < m) m = z;
+                    open = open || z == 0u;
                 }
             float X = pr.dx[i], Y = pr.dx[nv + i], Z = pr.dx[2 * nv + i];
             bool vis = m == 0xffffffffu ? true : (Z <= (1.0f / __uint_as_float(m)) + 0.05f);
             if (vis) {
                 code |= 1;
-                if (pr.vcont[i]) {
+                if (pr.vcont[i] && (open || !pr.outline_only)) {
                     code |= 2;
                     float n[3] = {0.0f, 0.0f, 0.0f};
                     for (int q = T.vf_beg[i]; q < T.vf_beg[i + 1]; ++q) {
@@ -362,9 +368,11 @@ __global__ void k_decide(const ProbDev *__restrict__ P) {
     pr.px[p] = pr.xyz[i];
     pr.px[nv + p] = pr.xyz[nv + i];
     pr.px[2 * nv + p] = pr.xyz[2 * nv + i];
-    pr.pc[p] = pr.rgb[i];
-    pr.pc[nv + p] = pr.rgb[nv + i];
-    pr.pc[2 * nv + p] = pr.rgb[2 * nv + i];
+    if (pr.rgb) {
+        pr.pc[p] = pr.rgb[i];
+        pr.pc[nv + p] = pr.rgb[nv + i];
+        pr.pc[2 * nv + p] = pr.rgb[2 * nv + i];
+    }
     }
     __syncthreads();
     if (threadIdx.x < 2 && cnt[threadIdx.x]) atomicAdd(pr.counts + threadIdx.x, cnt[threadIdx.x]);

@@ -38,6 +38,51 @@ struct Blob {
     }
 };
 
+// Mesh edges with their adjacent faces (edge-manifold check) and the
+// vertex -> incident faces lists, ascending.
+int topology(const std::vector<int> &tri, int nv, int nf, std::vector<int> &medge, int &nme,
+             std::vector<int> &vf_beg, std::vector<int> &vf_face) {
+    // ---- mesh edges with their adjacent faces (edge-manifold check)
+    std::vector<std::pair<uint64_t, int>> ek;
+    ek.reserve(size_t(3) * nf);
+    for (int f = 0; f < nf; ++f)
+        for (int c = 0; c < 3; ++c) {
+            uint64_t a = tri[size_t(c) * nf + f], b = tri[size_t((c + 1) % 3) * nf + f];
+            if (a == b) return fail(CAPTURE_EINVAL, "template: degenerate triangle");
+            uint64_t lo = std::min(a, b), hi = std::max(a, b);
+            ek.push_back({(lo << 32) | hi, f});
+        }
+    std::sort(ek.begin(), ek.end());
+    std::vector<int> me[4];
+    for (size_t i = 0; i < ek.size();) {
+        size_t j = i;
+        while (j < ek.size() && ek[j].first == ek[i].first) ++j;
+        if (j - i > 2) return fail(CAPTURE_EINVAL, "template: mesh is not edge-manifold");
+        me[0].push_back(int(ek[i].first >> 32));
+        me[1].push_back(int(ek[i].first & 0xffffffffu));
+        me[2].push_back(ek[i].second);
+        me[3].push_back(j - i == 2 ? ek[i + 1].second : -1);
+        i = j;
+    }
+    nme = int(me[0].size());
+    medge.clear();
+    for (int k = 0; k < 4; ++k) medge.insert(medge.end(), me[k].begin(), me[k].end());
+
+    // ---- vertex -> incident faces, ascending
+    vf_beg.assign(nv + 1, 0);
+    vf_face.assign(size_t(3) * nf, 0);
+    for (int f = 0; f < nf; ++f)
+        for (int c = 0; c < 3; ++c) vf_beg[tri[size_t(c) * nf + f] + 1]++;
+    for (int v = 0; v < nv; ++v) vf_beg[v + 1] += vf_beg[v];
+    {
+        std::vector<int> fill(vf_beg.begin(), vf_beg.end() - 1);
+        for (int f = 0; f < nf; ++f)
+            for (int c = 0; c < 3; ++c) vf_face[fill[tri[size_t(c) * nf + f]]++] = f;
+    }
+
+    return CAPTURE_OK;
+}
+
 }  // namespace
 
 int build_template(const capture_template_desc *d, capture_template **out, int device) {
@@ -62,42 +107,9 @@ int build_template(const capture_template_desc *d, capture_template **out, int d
     for (float w : bw) if (!(w == w) || w > 3.0e38f || w < -3.0e38f) return fail(CAPTURE_ENONFINITE, "template: non-finite binding weight");
     for (int v : edst) if (v < -1 || v >= nn) return fail(CAPTURE_EINVAL, "template: edge_dst out of range");
 
-    // ---- mesh edges with their adjacent faces (edge-manifold check)
-    std::vector<std::pair<uint64_t, int>> ek;
-    ek.reserve(size_t(3) * nf);
-    for (int f = 0; f < nf; ++f)
-        for (int c = 0; c < 3; ++c) {
-            uint64_t a = tri[size_t(c) * nf + f], b = tri[size_t((c + 1) % 3) * nf + f];
-            if (a == b) return fail(CAPTURE_EINVAL, "template: degenerate triangle");
-            uint64_t lo = std::min(a, b), hi = std::max(a, b);
-            ek.push_back({(lo << 32) | hi, f});
-        }
-    std::sort(ek.begin(), ek.end());
-    std::vector<int> me[4];
-    for (size_t i = 0; i < ek.size();) {
-        size_t j = i;
-        while (j < ek.size() && ek[j].first == ek[i].first) ++j;
-        if (j - i > 2) return fail(CAPTURE_EINVAL, "template: mesh is not edge-manifold");
-        me[0].push_back(int(ek[i].first >> 32));
-        me[1].push_back(int(ek[i].first & 0xffffffffu));
-        me[2].push_back(ek[i].second);
-        me[3].push_back(j - i == 2 ? ek[i + 1].second : -1);
-        i = j;
-    }
-    const int nme = int(me[0].size());
-    std::vector<int> medge;
-    for (int k = 0; k < 4; ++k) medge.insert(medge.end(), me[k].begin(), me[k].end());
-
-    // ---- vertex -> incident faces, ascending
-    std::vector<int> vf_beg(nv + 1, 0), vf_face(size_t(3) * nf);
-    for (int f = 0; f < nf; ++f)
-        for (int c = 0; c < 3; ++c) vf_beg[tri[size_t(c) * nf + f] + 1]++;
-    for (int v = 0; v < nv; ++v) vf_beg[v + 1] += vf_beg[v];
-    {
-        std::vector<int> fill(vf_beg.begin(), vf_beg.end() - 1);
-        for (int f = 0; f < nf; ++f)
-            for (int c = 0; c < 3; ++c) vf_face[fill[tri[size_t(c) * nf + f]]++] = f;
-    }
+    std::vector<int> medge, vf_beg, vf_face;
+    int nme = 0;
+    if ((rc = topology(tri, nv, nf, medge, nme, vf_beg, vf_face))) return rc;
 
     // ---- node order: breadth-first over the undirected node graph
     std::vector<std::vector<int>> adj(nn);
@@ -286,6 +298,42 @@ int build_template(const capture_template_desc *d, capture_template **out, int d
     D.vf_beg = (const int *)at(o_vfb); D.vf_face = (const int *)at(o_vff); D.medge = (const int *)at(o_me);
     D.slot_dest = (const int *)at(o_sd);
     D.in_beg = (const int *)at(o_ib); D.in_src = (const int *)at(o_is); D.out_cnt = (const int *)at(o_oc);
+    t->mem = mem;
+    t->bytes = blob.bytes.size();
+    t->device = device;
+    *out = t;
+    return CAPTURE_OK;
+}
+
+// Topology-only template (no deformation graph): the mesh tables that the
+// per-frame raster and decision kernels read, with the identity vertex order.
+int build_topology_template(const int *tri_dev, int nv, int nf, capture_template **out, int device) {
+    if (nv < 1 || nf < 1) return fail(CAPTURE_EINVAL, "mesh: need n_vertices >= 1 and n_triangles >= 1");
+    if (!tri_dev) return fail(CAPTURE_EINVAL, "mesh: null triangle array");
+    std::vector<int> tri;
+    int rc;
+    if ((rc = copy_down(tri, tri_dev, size_t(3) * nf))) return rc;
+    for (int v : tri) if (v < 0 || v >= nv) return fail(CAPTURE_EINVAL, "mesh: triangle index out of range");
+    std::vector<int> medge, vf_beg, vf_face, ident(nv);
+    int nme = 0;
+    if ((rc = topology(tri, nv, nf, medge, nme, vf_beg, vf_face))) return rc;
+    for (int v = 0; v < nv; ++v) ident[v] = v;
+    Blob blob;
+    size_t o_tri = blob.add(tri), o_id = blob.add(ident), o_vfb = blob.add(vf_beg), o_vff = blob.add(vf_face),
+           o_me = blob.add(medge);
+    void *mem = nullptr;
+    if (hipMalloc(&mem, blob.bytes.size()) != hipSuccess) return fail(CAPTURE_ENOMEM, "mesh: device allocation failed");
+    if (hipMemcpy(mem, blob.bytes.data(), blob.bytes.size(), hipMemcpyHostToDevice) != hipSuccess) {
+        (void)hipFree(mem);
+        return fail(CAPTURE_EHIP, "mesh: upload failed");
+    }
+    auto at = [&](size_t off) { return static_cast<uint8_t *>(mem) + off; };
+    capture_template *t = new capture_template{};
+    TemplateDev &D = t->dev;
+    D.nv = nv; D.nf = nf; D.nn = 0; D.nmedges = nme;
+    D.tri = (const int *)at(o_tri);
+    D.plan_vid = (const int *)at(o_id); D.plan_pos = (const int *)at(o_id);
+    D.vf_beg = (const int *)at(o_vfb); D.vf_face = (const int *)at(o_vff); D.medge = (const int *)at(o_me);
     t->mem = mem;
     t->bytes = blob.bytes.size();
     t->device = device;

@@ -1,0 +1,481 @@
+// Pose stage kernels (Sec. 3.3 energy, Sec. 4 pose solver): forward
+// kinematics, linear-blend skinning of the start pose, Jacobian rows of the
+// 2D, 3D and silhouette terms, J^T J on FP64 MFMA tiles and the dense
+// Cholesky Gauss-Newton step in one workgroup.
+//
+// Unknowns: 3 axis-angle values per rotating joint (joint order), the root
+// translation t, and the translation t' that maps the root-relative 3D
+// detections into the camera frame.  R_j = R_parent(j) Exp(theta_j),
+// p_j = p_parent + R_parent (J_j - J_parent), p_root = J_root + t.
+// The derivative of a point y carried by joint k's rotation is
+// -[y - p_k]x R_parent(k) J_l(theta_k) (left Jacobian of Exp).
+//
+// Exp and J_l use the series sin(x)/x, (1 - cos x)/x^2, (x - sin x)/x^3 in
+// x = |w|^2, each evaluated by nested steps S <- 1 - (x / (k (k + 1))) S with a
+// fixed number of terms, so the FP64 rotations do not depend on a libm.
+#include "device.hpp"
+
+namespace cap {
+
+constexpr int kExpTerms = 24;
+
+__device__ inline double exp_series(double x, int first) {
+    double s = 1.0;
+    for (int n = kExpTerms; n >= 1; --n) {
+        const int k = first + 2 * (n - 1);
+        s = 1.0 - (x / double(k * (k + 1))) * s;
+    }
+    return s;
+}
+
+// Local rotation Exp(w) (or J_l(w) with `jac`), row-major.
+__device__ inline void exp_or_jl(const double w[3], bool jac, double out[9]) {
+    const double x = (w[0] * w[0] + w[1] * w[1]) + w[2] * w[2];
+    double c1, c2;
+    if (!jac) {
+        c1 = exp_series(x, 2);
+        c2 = 0.5 * exp_series(x, 3);
+    } else {
+        c1 = 0.5 * exp_series(x, 3);
+        c2 = exp_series(x, 4) / 6.0;
+    }
+    const double K[9] = {0.0, -w[2], w[1], w[2], 0.0, -w[0], -w[1], w[0], 0.0};
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) {
+            const double kk = w[a] * w[b] - (a == b ? x : 0.0);
+            out[3 * a + b] = ((a == b ? 1.0 : 0.0) + c1 * K[3 * a + b]) + c2 * kk;
+        }
+}
+
+__device__ inline void mat3(const double *A, const double *B, double *C) {
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j)
+            C[3 * i + j] = (A[3 * i] * B[j] + A[3 * i + 1] * B[3 + j]) + A[3 * i + 2] * B[6 + j];
+}
+
+// Forward kinematics by the whole block: local Exp / J_l per joint in
+// parallel, then composition level by level down the tree.  Results go to
+// LDS (sR, sp, sA: [nj][9], [nj][3], [nj][9]).
+__device__ void fk_block(const BodyDev &B, const double *pose, double *sR, double *sp, double *sA, double *sL,
+                         double *sJ) {
+    const int nj = B.nj, t = threadIdx.x;
+    if (t < nj) {
+        const int c = B.col[t];
+        if (c >= 0) {
+            const double w[3] = {pose[c], pose[c + 1], pose[c + 2]};
+            exp_or_jl(w, false, sL + 9 * t);
+            exp_or_jl(w, true, sJ + 9 * t);
+        } else {
+            for (int e = 0; e < 9; ++e) {
+                sL[9 * t + e] = (e % 4 == 0) ? 1.0 : 0.0;
+                sJ[9 * t + e] = 0.0;
+            }
+        }
+    }
+    __syncthreads();
+    for (int d = 0; d <= B.maxdepth; ++d) {
+        if (t < nj && B.depth[t] == d) {
+            const int par = B.parent[t];
+            if (par < 0) {
+                for (int e = 0; e < 9; ++e) {
+                    sR[9 * t + e] = sL[9 * t + e];
+                    sA[9 * t + e] = sJ[9 * t + e];
+                }
+                for (int a = 0; a < 3; ++a) sp[3 * t + a] = B.rest[a][t] + pose[B.it + a];
+            } else {
+                mat3(sR + 9 * par, sL + 9 * t, sR + 9 * t);
+                mat3(sR + 9 * par, sJ + 9 * t, sA + 9 * t);
+                double off[3];
+                for (int a = 0; a < 3; ++a) off[a] = B.rest[a][t] - B.rest[a][par];
+                const double *Rp = sR + 9 * par;
+                for (int a = 0; a < 3; ++a)
+                    sp[3 * t + a] = sp[3 * par + a] + ((Rp[3 * a] * off[0] + Rp[3 * a + 1] * off[1]) + Rp[3 * a + 2] * off[2]);
+            }
+        }
+        __syncthreads();
+    }
+}
+
+__device__ inline void fk_store(const PoseDev &P, const double *sR, const double *sp, const double *sA) {
+    const int nj = P.B.nj;
+    for (int e = threadIdx.x; e < 9 * nj; e += blockDim.x) {
+        P.jR[e] = sR[e];
+        P.jA[e] = sA[e];
+    }
+    for (int e = threadIdx.x; e < 3 * nj; e += blockDim.x) P.jp[e] = sp[e];
+}
+
+// Start of a solve: keep the start pose, clear the status, kinematics at it.
+__global__ __launch_bounds__(kPoseStepThreads) void k_pose_fk(const PoseDev *__restrict__ PP) {
+    const PoseDev &P = *PP;
+    __shared__ double sR[9 * kMaxJoints], sp[3 * kMaxJoints], sA[9 * kMaxJoints], sL[9 * kMaxJoints],
+        sJ[9 * kMaxJoints];
+    for (int e = threadIdx.x; e < P.B.nu; e += blockDim.x) P.pose0[e] = P.pose[e];
+    if (threadIdx.x == 0) P.status[0] = 0;
+    fk_block(P.B, P.pose, sR, sp, sA, sL, sJ);
+    fk_store(P, sR, sp, sA);
+}
+
+// Linear blend skinning of the start pose, float32 recipe:
+// d = v - J_j; q_a = (R_a0 d0 + R_a1 d1) + R_a2 d2; acc_a = acc_a + w (q_a + p_j,a).
+__global__ __launch_bounds__(256) void k_pose_lbs(const PoseDev *__restrict__ PP, const ProbDev *__restrict__ PR) {
+    const PoseDev &P = *PP;
+    const BodyDev &B = P.B;
+    __shared__ float sR[9 * kMaxJoints], sp[3 * kMaxJoints], sJ[3 * kMaxJoints];
+    for (int e = threadIdx.x; e < 9 * B.nj; e += blockDim.x) sR[e] = float(P.jR[e]);
+    for (int e = threadIdx.x; e < 3 * B.nj; e += blockDim.x) {
+        sp[e] = float(P.jp[e]);
+        sJ[e] = float(B.rest[e % 3][e / 3]);
+    }
+    __syncthreads();
+    const int nv = B.nv;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nv) return;
+    const float v[3] = {B.xyz[i], B.xyz[nv + i], B.xyz[2 * nv + i]};
+    float acc[3] = {0.0f, 0.0f, 0.0f};
+    for (int s = 0; s < 4; ++s) {
+        const int j = B.bind_joint[size_t(s) * nv + i];
+        const float w = B.bind_w[size_t(s) * nv + i];
+        const float d[3] = {v[0] - sJ[3 * j], v[1] - sJ[3 * j + 1], v[2] - sJ[3 * j + 2]};
+        for (int a = 0; a < 3; ++a) {
+            const float *R = sR + 9 * j + 3 * a;
+            const float q = (R[0] * d[0] + R[1] * d[1]) + R[2] * d[2];
+            acc[a] = acc[a] + w * (q + sp[3 * j + a]);
+        }
+    }
+    store_start_vertex(*PR, i, acc[0], acc[1], acc[2]);
+}
+
+// Contour set B as an ascending list, by one block (wave ballots, then wave
+// offsets): entry (vertex << 1) | (b_i == -1).
+__global__ __launch_bounds__(1024) void k_pose_list(const PoseDev *__restrict__ PP) {
+    const PoseDev &P = *PP;
+    const int nv = P.B.nv;
+    __shared__ int wsum[16];
+    __shared__ int base;
+    if (threadIdx.x == 0) base = 0;
+    __syncthreads();
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    for (int c0 = 0; c0 < nv; c0 += blockDim.x) {
+        const int i = c0 + threadIdx.x;
+        const uint8_t f = i < nv ? P.vflags[i] : 0;
+        const bool in = (f & 2) != 0;
+        const unsigned long long m = __ballot(in);
+        const int before = __popcll(m & ((1ull << lane) - 1ull));
+        if (lane == 0) wsum[wid] = __popcll(m);
+        __syncthreads();
+        int off = base;
+        for (int w = 0; w < wid; ++w) off += wsum[w];
+        if (in) P.blist[off + before] = (i << 1) | ((f & 4) ? 1 : 0);
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            int tot = 0;
+            for (int w = 0; w < nw; ++w) tot += wsum[w];
+            base += tot;
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) P.nb[0] = base;
+}
+
+// Cubic convolution (a = -0.5) value and gradient at (u, v), FP64, clamp-to-edge.
+__device__ inline double sample_cubic_f64(const float *__restrict__ img, int W, int H, double u, double v, double &gu,
+                                          double &gv) {
+    u = fmin(fmax(u, -1.0e6), 1.0e6);
+    v = fmin(fmax(v, -1.0e6), 1.0e6);
+    const double fu = floor(u), fv = floor(v);
+    const int ix = int(fu), iy = int(fv);
+    double wx[4], dx[4], wy[4], dy[4];
+    const double f[2] = {u - fu, v - fv};
+    for (int ax = 0; ax < 2; ++ax) {
+        const double t = f[ax], t2 = t * t, t3 = t2 * t;
+        double *w = ax ? wy : wx, *d = ax ? dy : dx;
+        w[0] = ((2.0 * t2 - t3) - t) * 0.5;
+        w[1] = ((3.0 * t3 - 5.0 * t2) + 2.0) * 0.5;
+        w[2] = ((4.0 * t2 - 3.0 * t3) + t) * 0.5;
+        w[3] = (t3 - t2) * 0.5;
+        d[0] = ((4.0 * t - 3.0 * t2) - 1.0) * 0.5;
+        d[1] = (9.0 * t2 - 10.0 * t) * 0.5;
+        d[2] = ((8.0 * t - 9.0 * t2) + 1.0) * 0.5;
+        d[3] = (3.0 * t2 - 2.0 * t) * 0.5;
+    }
+    double val = 0.0, gx = 0.0, gy = 0.0;
+    for (int m = 0; m < 4; ++m) {
+        const float *row = img + size_t(min(max(iy + m - 1, 0), H - 1)) * W;
+        double rx = 0.0, rv = 0.0;
+        for (int n = 0; n < 4; ++n) {
+            const double t = row[min(max(ix + n - 1, 0), W - 1)];
+            rx += dx[n] * t;
+            rv += wx[n] * t;
+        }
+        gx += wy[m] * rx;
+        gy += dy[m] * rv;
+        val += wy[m] * rv;
+    }
+    gu = gx;
+    gv = gy;
+    return val;
+}
+
+// Row entries of g . dY/dtheta for the rotating joints in `mask`, with
+// dsum(k) = sum over carried points of weight * (y - p_k).  Written for every
+// unknown column of the row (zeros elsewhere) except t, t' and the F column.
+__device__ inline void rotation_entries(const BodyDev &B, double *row, const double g[3], const double *sp,
+                                        const double *sA, const double (*ys)[3], const double *ws,
+                                        const uint32_t *masks, int npts) {
+    for (int k = 0; k < B.nj; ++k) {
+        const int c = B.col[k];
+        if (c < 0) continue;
+        double d[3] = {0.0, 0.0, 0.0};
+        bool any = false;
+        for (int s = 0; s < npts; ++s)
+            if (masks[s] >> k & 1u) {
+                any = true;
+                for (int a = 0; a < 3; ++a) d[a] += ws[s] * (ys[s][a] - sp[3 * k + a]);
+            }
+        if (!any) {
+            row[c] = row[c + 1] = row[c + 2] = 0.0;
+            continue;
+        }
+        const double e[3] = {d[1] * g[2] - d[2] * g[1], d[2] * g[0] - d[0] * g[2], d[0] * g[1] - d[1] * g[0]};
+        const double *A = sA + 9 * k;
+        for (int cc = 0; cc < 3; ++cc) row[c + cc] = (e[0] * A[cc] + e[1] * A[3 + cc]) + e[2] * A[6 + cc];
+    }
+}
+
+// One Jacobian row per thread: 2 per joint (2D), 3 per joint (3D), one per
+// contour vertex (silhouette).  Column nu holds b * F.  With energy_only the
+// rows are not written.  Per-block energy partials go to epart.
+__global__ __launch_bounds__(kPoseRowThreads) void k_pose_rows(const PoseDev *__restrict__ PP, int energy_only) {
+    const PoseDev &P = *PP;
+    const BodyDev &B = P.B;
+    __shared__ double sR[9 * kMaxJoints], sp[3 * kMaxJoints], sA[9 * kMaxJoints];
+    __shared__ double red[kPoseRowThreads / 64];
+    for (int e = threadIdx.x; e < 9 * B.nj; e += blockDim.x) {
+        sR[e] = P.jR[e];
+        sA[e] = P.jA[e];
+    }
+    for (int e = threadIdx.x; e < 3 * B.nj; e += blockDim.x) sp[e] = P.jp[e];
+    __syncthreads();
+    const int nj = B.nj, nu = B.nu, np_ = B.np;
+    const int M = 5 * nj + P.nb[0];
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    double en[4] = {0.0, 0.0, 0.0, 0.0};
+    if (r < M) {
+        double *row = P.rows + size_t(r) * np_;
+        double g[3], F;
+        double ys[4][3], ws[4];
+        uint32_t masks[4];
+        int npts = 1;
+        double tw;                    // weight of the root translation columns
+        bool has_tp = false;
+        int tpc = 0;
+        if (r < 5 * nj) {
+            const bool is2d = r < 2 * nj;
+            const int j = is2d ? r >> 1 : (r - 2 * nj) / 3;
+            const int c = is2d ? r & 1 : (r - 2 * nj) % 3;
+            const double X = sp[3 * j], Y = sp[3 * j + 1], Z = sp[3 * j + 2];
+            if (is2d) {
+                const double s = sqrt(P.l2d * P.lam[j]);
+                if (c == 0) {
+                    const double u = (P.fx * X) / Z + P.cx;
+                    F = s * (u - P.p2d[j]);
+                    g[0] = s * (P.fx / Z); g[1] = 0.0; g[2] = s * (-(P.fx * X) / (Z * Z));
+                } else {
+                    const double v = (P.fy * Y) / Z + P.cy;
+                    F = s * (v - P.p2d[nj + j]);
+                    g[0] = 0.0; g[1] = s * (P.fy / Z); g[2] = s * (-(P.fy * Y) / (Z * Z));
+                }
+                en[0] = F * F;
+            } else {
+                F = P.s3d * ((sp[3 * j + c] - P.p3d[c * nj + j]) - P.pose[B.itp + c]);
+                g[0] = g[1] = g[2] = 0.0;
+                g[c] = P.s3d;
+                has_tp = true;
+                tpc = c;
+                en[1] = F * F;
+            }
+            ys[0][0] = X; ys[0][1] = Y; ys[0][2] = Z;
+            ws[0] = 1.0;
+            masks[0] = B.anc[j] & ~(1u << j);     // a joint does not move with its own rotation
+            tw = 1.0;
+        } else {
+            const int e = P.blist[r - 5 * nj];
+            const int i = e >> 1;
+            const double bs = (e & 1) ? -1.0 : 1.0;
+            const int nv = B.nv;
+            const double v[3] = {B.xyz[i], B.xyz[nv + i], B.xyz[2 * nv + i]};
+            double V[3] = {0.0, 0.0, 0.0};
+            tw = 0.0;
+            for (int s = 0; s < 4; ++s) {
+                const int j = B.bind_joint[size_t(s) * nv + i];
+                ws[s] = B.bind_w[size_t(s) * nv + i];
+                masks[s] = B.anc[j];
+                const double d[3] = {v[0] - B.rest[0][j], v[1] - B.rest[1][j], v[2] - B.rest[2][j]};
+                for (int a = 0; a < 3; ++a) {
+                    const double *R = sR + 9 * j + 3 * a;
+                    ys[s][a] = ((R[0] * d[0] + R[1] * d[1]) + R[2] * d[2]) + sp[3 * j + a];
+                    V[a] += ws[s] * ys[s][a];
+                }
+                tw += ws[s];
+            }
+            npts = 4;
+            const double X = V[0], Y = V[1], Z = V[2];
+            const double u = (P.fx * X) / Z + P.cx, vv = (P.fy * Y) / Z + P.cy;
+            double du, dv;
+            const double dist = sample_cubic_f64(P.dt, P.W, P.H, u, vv, du, dv);
+            const double rr = P.ssil * dist;
+            F = bs * rr;
+            g[0] = P.ssil * (du * (P.fx / Z));
+            g[1] = P.ssil * (dv * (P.fy / Z));
+            g[2] = P.ssil * (du * (-(P.fx * X) / (Z * Z)) + dv * (-(P.fy * Y) / (Z * Z)));
+            en[2] = bs * rr * rr;
+            en[3] = rr * rr;
+        }
+        if (!energy_only) {
+            rotation_entries(B, row, g, sp, sA, ys, ws, masks, npts);
+            for (int a = 0; a < 3; ++a) {
+                row[B.it + a] = tw * g[a];
+                row[B.itp + a] = 0.0;
+            }
+            if (has_tp) row[B.itp + tpc] = -P.s3d;
+            row[nu] = F;
+            for (int c = nu + 1; c < np_; ++c) row[c] = 0.0;
+        }
+    }
+    for (int q = 0; q < 4; ++q) {
+        const double s = block_sum<kPoseRowThreads>(en[q], red);
+        if (threadIdx.x == 0) P.epart[size_t(blockIdx.x) * 4 + q] = s;
+    }
+}
+
+// Upper-triangle 16x16 tiles of [J | bF]^T [J | bF], one wave per (tile,
+// row chunk), on V_MFMA_F64_16X16X4F64: A(i, k) = rows[r0 + k][I0 + i],
+// B(k, j) = rows[r0 + k][J0 + j].  Lane l supplies element (l % 16, l / 16)
+// of A and (l / 16, l % 16) of B, and holds D(4 (l / 16) + q, l % 16).
+typedef double dbl4 __attribute__((ext_vector_type(4)));
+
+__global__ __launch_bounds__(64) void k_pose_jtj(const PoseDev *__restrict__ PP) {
+    const PoseDev &P = *PP;
+    const int np_ = P.B.np, nt = np_ / kPoseTile, ntp = nt * (nt + 1) / 2;
+    const int tp = blockIdx.x, chunk = blockIdx.y;
+    int I = 0, rem = tp;
+    while (rem >= nt - I) { rem -= nt - I; ++I; }
+    const int Jt = I + rem;
+    const int M = 5 * P.B.nj + P.nb[0];
+    const int per = ((M + kPoseChunks - 1) / kPoseChunks + 3) & ~3;
+    const int beg = min(M, chunk * per), end = min(M, beg + per);
+    const int l = threadIdx.x, li = l & 15, lk = l >> 4;
+    dbl4 acc = {0.0, 0.0, 0.0, 0.0};
+    const double *col_a = P.rows + I * kPoseTile + li;
+    const double *col_b = P.rows + Jt * kPoseTile + li;
+    for (int r0 = beg; r0 < end; r0 += 4) {
+        const int r = r0 + lk;
+        const double a = r < end ? col_a[size_t(r) * np_] : 0.0;
+        const double b = r < end ? col_b[size_t(r) * np_] : 0.0;
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+    }
+    double *out = P.tpart + (size_t(chunk) * ntp + tp) * 256;
+    for (int q = 0; q < 4; ++q) out[(4 * lk + q) * kPoseTile + li] = acc[q];
+}
+
+// mode 0: energy of the step, assemble, damp, Cholesky, update, kinematics.
+// mode 1: energy only (final).  mode 2: energy and the undamped system only.
+__global__ __launch_bounds__(kPoseStepThreads) void k_pose_step(const PoseDev *__restrict__ PP, int gn, int nblk,
+                                                                int mode) {
+    const PoseDev &P = *PP;
+    const BodyDev &B = P.B;
+    const int nu = B.nu, np_ = B.np, nt = np_ / kPoseTile, ntp = nt * (nt + 1) / 2;
+    const int t = threadIdx.x, nth = blockDim.x;
+    __shared__ double A[kMaxPoseUnknowns * (kMaxPoseUnknowns + 1)];
+    __shared__ double y[kMaxPoseUnknowns], pn[kMaxPoseUnknowns];
+    __shared__ double sR[9 * kMaxJoints], sp[3 * kMaxJoints], sA[9 * kMaxJoints], sL[9 * kMaxJoints],
+        sJ[9 * kMaxJoints];
+    __shared__ double smax;
+    __shared__ int bad;
+    const int lda = nu + 1;
+    if (t == 0) bad = 0;
+    if (t < 4) {
+        double s = 0.0;
+        for (int b = 0; b < nblk; ++b) s += P.epart[size_t(b) * 4 + t];
+        P.energy[gn * 4 + t] = s;
+        if (!isfinite(s)) atomicOr(&bad, 1);
+    }
+    __syncthreads();
+    if (bad) {
+        if (t == 0 && P.status[0] == 0) P.status[0] = CAPTURE_ENONFINITE;
+        return;
+    }
+    if (mode == 1 || P.status[0] != 0) return;
+    // assemble J^T J (upper triangle mirrored) and -J^T B F
+    for (int e = t; e < nu * (nu + 1); e += nth) {
+        const int gi = e / (nu + 1), gj = e % (nu + 1);
+        const int lo = min(gi, gj), hi = max(gi, gj);
+        const int It = lo / kPoseTile, Jt = hi / kPoseTile;
+        const int tp = It * nt - It * (It - 1) / 2 + (Jt - It);
+        const int off = (lo % kPoseTile) * kPoseTile + hi % kPoseTile;
+        double s = 0.0;
+        for (int c = 0; c < kPoseChunks; ++c) s += P.tpart[(size_t(c) * ntp + tp) * 256 + off];
+        A[gi * lda + gj] = gj == nu ? -s : s;
+    }
+    __syncthreads();
+    for (int e = t; e < nu * lda; e += nth) P.sys[e] = A[e];
+    if (mode == 2) return;
+    if (t == 0) {
+        double m = A[0];
+        for (int i = 1; i < nu; ++i) m = fmax(m, A[i * lda + i]);
+        smax = m;
+    }
+    __syncthreads();
+    const double mu = 1e-6 * smax;
+    for (int i = t; i < nu; i += nth) A[i * lda + i] += mu;
+    __syncthreads();
+    // Cholesky, right-looking, lower triangle in place
+    for (int k = 0; k < nu; ++k) {
+        if (t == 0) {
+            const double d = A[k * lda + k];
+            if (!(d > 0.0) || !isfinite(d)) bad = 1;
+            A[k * lda + k] = sqrt(d);
+        }
+        __syncthreads();
+        if (bad) break;
+        const double dk = A[k * lda + k];
+        for (int i = k + 1 + t; i < nu; i += nth) A[i * lda + k] /= dk;
+        __syncthreads();
+        const int m = nu - k - 1;
+        for (int e = t; e < m * m; e += nth) {
+            const int i = k + 1 + e / m, j = k + 1 + e % m;
+            if (j <= i) A[i * lda + j] -= A[i * lda + k] * A[j * lda + k];
+        }
+        __syncthreads();
+    }
+    if (bad) {
+        for (int e = t; e < nu; e += nth) P.pose[e] = P.pose0[e];
+        if (t == 0) P.status[0] = CAPTURE_ENOTSPD;
+        return;
+    }
+    // L y = rhs, then L^T delta = y
+    for (int e = t; e < nu; e += nth) y[e] = A[e * lda + nu];
+    __syncthreads();
+    for (int k = 0; k < nu; ++k) {
+        if (t == 0) y[k] /= A[k * lda + k];
+        __syncthreads();
+        for (int i = k + 1 + t; i < nu; i += nth) y[i] -= A[i * lda + k] * y[k];
+        __syncthreads();
+    }
+    for (int k = nu - 1; k >= 0; --k) {
+        if (t == 0) y[k] /= A[k * lda + k];
+        __syncthreads();
+        for (int i = t; i < k; i += nth) y[i] -= A[k * lda + i] * y[k];
+        __syncthreads();
+    }
+    for (int e = t; e < nu; e += nth) {
+        pn[e] = P.pose[e] + y[e];
+        P.pose[e] = pn[e];
+    }
+    __syncthreads();
+    fk_block(B, pn, sR, sp, sA, sL, sJ);
+    fk_store(P, sR, sp, sA);
+}
+
+}  // namespace cap

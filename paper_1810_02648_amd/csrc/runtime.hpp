@@ -1,0 +1,66 @@
+// Host-side launch helpers shared by the entry points (internal).
+#pragma once
+#include <vector>
+
+#include "common.hpp"
+
+namespace cap {
+
+// Bump allocator over a caller workspace (base == nullptr: sizing pass).
+struct Layout {
+    size_t off = 0;
+    template <typename T>
+    T *take(uint8_t *base, size_t n) {
+        off = (off + 255) & ~size_t(255);
+        T *p = base ? reinterpret_cast<T *>(base + off) : nullptr;
+        off += std::max<size_t>(n, 1) * sizeof(T);
+        return p;
+    }
+};
+
+struct Run {
+    Profiler *prof = nullptr;
+    int n = 0;
+    std::vector<ProbDev> probs;
+    ProbDev *dprobs = nullptr;
+    int max_nv = 0, max_nf = 0, max_hw = 0, max_w = 0, max_h = 0, max_tiles = 0, max_me = 0;
+    size_t lds_lin = 0, lds_apply = 0;
+    hipStream_t s = nullptr;
+};
+
+// Launch `go` bracketed by events when timing is on.
+template <typename F>
+inline void timed(Run &R, int kid, F go) {
+    Profiler *P = R.prof;
+    if (!P || !P->on) { go(); return; }
+    while (P->ev.size() < P->used + 2) {
+        hipEvent_t e;
+        if (hipEventCreate(&e) != hipSuccess) { go(); return; }
+        P->ev.push_back(e);
+    }
+    const size_t i = P->used;
+    P->used += 2;
+    (void)hipEventRecord(P->ev[i], R.s);
+    go();
+    (void)hipEventRecord(P->ev[i + 1], R.s);
+    P->pending.push_back({kid, i});
+}
+
+// After the stream has been synchronised: fold the event pairs into the totals.
+inline void settle(Run &R) {
+    Profiler *P = R.prof;
+    if (!P) return;
+    for (auto &pe : P->pending) {
+        float ms = 0.0f;
+        if (hipEventElapsedTime(&ms, P->ev[pe.second], P->ev[pe.second + 1]) == hipSuccess) {
+            P->total_ms[pe.first] += ms;
+            P->launches[pe.first] += 1;
+        }
+    }
+    P->pending.clear();
+    P->used = 0;
+}
+
+inline unsigned blocks(size_t n, unsigned t) { return unsigned((n + t - 1) / t); }
+
+}  // namespace cap

@@ -20,7 +20,8 @@ def declared_functions():
 def test_header_declares_the_boundary():
     names = declared_functions()
     for required in ("capture_nonrigid_solve", "capture_batch_solve", "capture_graph_build",
-                     "capture_workspace_size", "capture_template_create", "capture_last_error"):
+                     "capture_workspace_size", "capture_template_create", "capture_last_error",
+                     "capture_pose_solve", "capture_body_create"):
         assert required in names
 
 
@@ -44,8 +45,10 @@ def test_struct_layouts_match_header():
 #include <stdio.h>
 #include "capture.h"
 int main(void) {
-  printf("%zu %zu %zu %zu %zu\n", sizeof(capture_camera), sizeof(capture_template_desc),
-         sizeof(capture_frame), sizeof(capture_nonrigid_params), sizeof(capture_report));
+  printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu\n", sizeof(capture_camera), sizeof(capture_template_desc),
+         sizeof(capture_frame), sizeof(capture_nonrigid_params), sizeof(capture_report),
+         sizeof(capture_body_desc), sizeof(capture_pose_frame), sizeof(capture_pose_params),
+         sizeof(capture_pose_report));
   return 0;
 }
 """
@@ -56,4 +59,5 @@ int main(void) {
         subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), c, "-o", exe], check=True)
         sizes = [int(x) for x in subprocess.run([exe], capture_output=True, text=True, check=True).stdout.split()]
     assert sizes == [ctypes.sizeof(capi.Camera), ctypes.sizeof(capi.TemplateDesc), ctypes.sizeof(capi.Frame),
-                     ctypes.sizeof(capi.NonrigidParams), ctypes.sizeof(capi.Report)]
+                     ctypes.sizeof(capi.NonrigidParams), ctypes.sizeof(capi.Report), ctypes.sizeof(capi.BodyDesc),
+                     ctypes.sizeof(capi.PoseFrame), ctypes.sizeof(capi.PoseParams), ctypes.sizeof(capi.PoseReport)]
