@@ -162,6 +162,7 @@ def bench_sequence(args, cap, torch):
 
 def bench_frame(args, cap, torch):
     """Single frames (or a batch of independent frames) from the rest state."""
+    import numpy as np
     import synth
     log("building workload", args.workload)
     f = synth.make_nonrigid_frame(args.workload, 0)
@@ -169,7 +170,7 @@ def bench_frame(args, cap, torch):
     ctx = cap.Context(0)
     xyz = torch.from_numpy(f["xyz"]).cuda()
     graph = cap.graph_build(ctx, xyz, nn)                     # on the GPU, per template (not timed)
-    tmpl = cap.Template(ctx, torch.from_numpy(f["tri"]).cuda(), graph)
+    tmpl = cap.Template(ctx, torch.from_numpy(f["tri"]).cuda(), graph, args.tile)
     start = torch.zeros((12, nn), dtype=torch.float32, device="cuda")
     start[0] = start[4] = start[8] = 1.0
     rgb = torch.from_numpy(f["rgb"]).cuda()
@@ -177,8 +178,31 @@ def bench_frame(args, cap, torch):
     image = torch.from_numpy(f["image"]).cuda()
     frames = [cap.FrameInputs(tmpl, xyz, rgb, f["cam"], mask, image, start.clone()) for _ in range(args.batch)]
     prm = cap.params(*f["weights"], gn_iters=gn, pcg_iters=pcg)
+    pose = None
+    if args.workload == "frame20k" and not args.no_pose:
+        # the paper-shaped frame runs both stages: the pose stage on a 5,000-vertex skinned body
+        from synth import body as sb
+        pf = sb.make_pose_frame(n_vertices=5000, side=f["cam"].width, seed=0)
+        b = pf["body"]
+        body = cap.Body(ctx, torch.from_numpy(b["tri"]).cuda(), torch.from_numpy(b["xyz"]).cuda(),
+                        torch.from_numpy(b["bind_idx"]).cuda(), torch.from_numpy(b["bind_w"]).cuda(), b["parents"],
+                        b["joints"], [j not in sb.NO_DOF for j in range(len(sb.JOINTS))])
+        rng = np.random.default_rng(11)
+        nr = 3 * len(sb.dof_joints())
+        pose0 = pf["gt_pose"].copy()
+        pose0[:nr] += rng.normal(0.0, 0.05, nr)
+        pose0[nr:nr + 3] += rng.normal(0.0, 0.02, 3)
+        pose0 = torch.from_numpy(pose0).cuda()
+        d64 = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).cuda()
+        pin = cap.PoseInputs(body, pf["cam"], torch.from_numpy(pf["mask"]).cuda(), d64(pf["p2d"]), d64(pf["p3d"]),
+                             d64(pf["lam"]), pose0.clone())
+        pprm = cap.pose_params(1.0 / 9.0, 2500.0, 0.05, gn_iters=3)
+        pose = dict(body=body, inputs=pin, prm=pprm, start=pose0, reports=[])
 
     def step():
+        if pose is not None:
+            pose["inputs"].pose.copy_(pose["start"])
+            pose["reports"].append(cap.pose_solve(ctx, pose["inputs"], pose["prm"]))
         for fr in frames:
             fr.node_state.copy_(start)
         return cap.batch_solve(ctx, frames, prm)
@@ -218,30 +242,131 @@ def bench_frame(args, cap, torch):
         "dtype": "f32",
         "data": "synthetic",
         "config": {
-            "workload": "%s: %d-vertex ellipsoid template, %d-node deformation graph, %dx%d silhouette/colour "
+            "workload": "%s: %s%d-vertex ellipsoid template, %d-node deformation graph, %dx%d silhouette/colour "
                         "targets, %d GN x %d PCG, plain start (rest state)"
-                        % (args.workload, f["xyz"].shape[1], nn, W, H, gn, pcg),
+                        % (args.workload, "pose stage + " if pose is not None else "", f["xyz"].shape[1], nn, W, H,
+                           gn, pcg),
             "batch": args.batch,
+            "vertices_per_tile": args.tile or 256,
             "visible_vertices": r0["n_visible"],
             "final_energy": r0["energy"][-1],
             "start_energy": r0["energy"][0],
+            "pose_stage": None if pose is None else {
+                "workload": "23-joint skinned body, 5000 vertices, 69 unknowns, %dx%d, 3 GN with dense FP64 "
+                            "Cholesky, start = ground truth + N(0, 0.05 rad)" % (W, H),
+                "contour_vertices": pose["reports"][-1]["n_boundary"],
+                "energy": [round(e, 3) for e in pose["reports"][-1]["energy"]],
+            },
         },
         "roofline": roof,
         "kernel_avg_us": {k: round(1000.0 * ms / n, 3) for k, (ms, n) in prof.items() if n},
     }, f
 
 
+def bench_batch(args, cap, torch):
+    """Many independent frames of uneven size (log-uniform vertices, nodes and image
+    sides) solved together by one batched call per step."""
+    import synth
+    n = args.batch if args.batch > 1 else 64
+    log("generating %d frames" % n)
+    frames_h = synth.make_batch(n, 0, workers=min(8, len(os.sched_getaffinity(0))))
+    gn, pcg, weights = 3, 8, (1.0, 0.1, 10.0)
+    ctx = cap.Context(0)
+    frames, starts, graphs = [], [], []
+    for f in frames_h:
+        xyz = torch.from_numpy(f["xyz"]).cuda()
+        g = cap.graph_build(ctx, xyz, f["n_nodes"])
+        tmpl = cap.Template(ctx, torch.from_numpy(f["tri"]).cuda(), g)
+        st = torch.zeros((12, f["n_nodes"]), dtype=torch.float32, device="cuda")
+        st[0] = st[4] = st[8] = 1.0
+        frames.append(cap.FrameInputs(tmpl, xyz, torch.from_numpy(f["rgb"]).cuda(), f["cam"],
+                                      torch.from_numpy(f["mask"]).cuda(), torch.from_numpy(f["image"]).cuda(),
+                                      st.clone()))
+        starts.append(st)
+        graphs.append(g)
+    prm = cap.params(*weights, gn_iters=gn, pcg_iters=pcg)
+
+    def step():
+        for fr, st in zip(frames, starts):
+            fr.node_state.copy_(st)
+        return cap.batch_solve(ctx, frames, prm)
+
+    for _ in range(args.warmup):
+        reps = step()
+    torch.cuda.synchronize()
+    log("timing", args.steps, "steps")
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        reps = step()
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    cap.profile_enable(ctx, True)
+    cap.profile_read(ctx)
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    prof = cap.profile_read(ctx)
+    cap.profile_enable(ctx, False)
+    per_step_us = {k: 1000.0 * ms / args.steps for k, (ms, c) in prof.items() if c}
+    dom = max(per_step_us, key=per_step_us.get)
+
+    def total_bytes(kernel):
+        s = 0
+        for f, g, r in zip(frames_h, graphs, reps):
+            ne = int((g["edge_dst"] >= 0).sum().item())
+            s += algorithmic_bytes(kernel, r["n_visible"], f["n_nodes"], ne, f["cam"].width * f["cam"].height,
+                                   f["tri"].shape[1], f["xyz"].shape[1])
+        return s
+
+    avg_s = prof[dom][0] / 1000.0 / prof[dom][1]
+    achieved = total_bytes(dom) / avg_s / 1e9
+    apply_s = prof["apply"][0] / 1000.0 / max(prof["apply"][1], 1)
+    roof = {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS, "traffic": None, "avg_us": avg_s * 1e6,
+            "algorithmic_bytes_per_launch": total_bytes(dom),
+            "apply_achieved_GBs": total_bytes("apply") / apply_s / 1e9, "apply_avg_us": apply_s * 1e6}
+    nv = [f["xyz"].shape[1] for f in frames_h]
+    return {
+        "metric": METRIC,
+        "value": args.steps * n / elapsed,
+        "unit": "frames/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1000.0 * elapsed / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": "batch of %d independent frames, log-uniform 4k-40k vertices, 128-1000 nodes, 512-1080 px "
+                        "square images (%d vertices, %.1f Mpx in total), %d GN x %d PCG, plain start, one batched "
+                        "call per step" % (n, sum(nv), sum(f["cam"].width ** 2 for f in frames_h) / 1e6, gn, pcg),
+            "batch": n,
+            "final_energy_sum": float(sum(r["energy"][-1] for r in reps)),
+            "start_energy_sum": float(sum(r["energy"][0] for r in reps)),
+        },
+        "roofline": roof,
+        "kernel_avg_us": {k: round(1000.0 * ms / c, 3) for k, (ms, c) in prof.items() if c},
+    }, frames_h
+
+
 def main():
+    import numpy as np
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--mode", default="sequence", choices=["sequence", "frame"])
+    ap.add_argument("--mode", default="sequence", choices=["sequence", "frame", "batch"])
     ap.add_argument("--workload", default=None,
                     help="sequence: seq20k (default) or seq_small; frame: frame20k (default), small, stress200k")
-    ap.add_argument("--batch", type=int, default=1, help="frame mode: independent frames solved together per step")
+    ap.add_argument("--batch", type=int, default=1,
+                    help="frame mode: copies of the frame solved together per step; batch mode: frames (default 64)")
     ap.add_argument("--epochs", type=int, default=40, help="sequence mode: training epochs")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-pose", action="store_true", help="frame mode: leave out the pose stage")
+    ap.add_argument("--tile", type=int, default=0, help="frame mode: vertices per tile (0 = library default)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the solver has no multi-GPU path "
@@ -256,11 +381,24 @@ def main():
 
     if args.mode == "sequence":
         result, data = bench_sequence(args, cap, torch)
+    elif args.mode == "batch":
+        result, data = bench_batch(args, cap, torch)
     else:
         result, data = bench_frame(args, cap, torch)
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")
-        if args.mode == "sequence":
+        if args.mode == "batch":
+            # frames at the 25th, 50th and 75th percentile of vertex count; rate = 1 / mean time
+            order = sorted(range(len(data)), key=lambda i: data[i]["xyz"].shape[1])
+            pick = [order[len(order) * q // 4] for q in (1, 2, 3)]
+            rates = [cpu_baseline(data[i], data[i]["n_nodes"], 3, 8, (1.0, 0.1, 10.0)) for i in pick]
+            cb = dict(rates[0])
+            cb["value"] = 1.0 / float(np.mean([1.0 / r["value"] for r in rates]))
+            cb["sample"] = ("3 frames of the batch (%s vertices: its 25th/50th/75th percentile), each per-frame "
+                            "preprocessing + 3 GN steps with exact sparse-Cholesky solves in float64; rate = 1 / mean "
+                            "time" % "/".join(str(data[i]["xyz"].shape[1]) for i in pick))
+            result["cpu_baseline"] = cb
+        elif args.mode == "sequence":
             t = data["n_train"]
             fr = dict(xyz=data["posed"][t], tri=data["tri"], rgb=data["rgb"], cam=data["cam"],
                       mask=data["masks"][t], image=data["images"][t])

@@ -28,6 +28,7 @@ __global__ void k_node_gather(const ProbDev *P);
 __global__ void k_scatter_p(const ProbDev *P);
 __global__ void k_node_pcg(const ProbDev *P, int last, int update_only);
 __global__ void k_scal_init(const ProbDev *P, int gn_iters);
+__global__ void k_clear_zbuf(const ProbDev *P);
 int build_template(const capture_template_desc *d, capture_template **out, int device);
 
 // warm-start kernels (warmstart.hip)
@@ -210,8 +211,6 @@ void carve(Layout &L, uint8_t *base, const capture_frame &f, ProbDev &pr) {
     pr.pva = L.take<float>(base, 3 * nv);
     float **vecs[8] = {&pr.b, &pr.diag, &pr.dinv, &pr.x, &pr.r, &pr.z, &pr.p, &pr.Ap};
     for (float **v : vecs) *v = L.take<float>(base, 6 * nn);
-    pr.scal = L.take<double>(base, kScalars);
-    pr.counts = L.take<int>(base, 2);
     pr.state0 = L.take<float>(base, 12 * nn);
 }
 
@@ -219,13 +218,19 @@ struct Plan {
     size_t bytes = 0;
 };
 
+// Layout: the descriptors, one block with every problem's scalars and counters
+// (read back by a single copy), then each problem's buffers.
 Plan plan_workspace(int n, const capture_frame *frames, uint8_t *base, std::vector<ProbDev> *probs) {
     Layout L;
     Plan pl;
     L.take<ProbDev>(base, n);
+    double *scal = L.take<double>(base, size_t(kScalars) * n);
+    int *counts = L.take<int>(base, size_t(2) * n);
     for (int i = 0; i < n; ++i) {
         ProbDev pr{};
         carve(L, base, frames[i], pr);
+        pr.scal = scal ? scal + size_t(kScalars) * i : nullptr;
+        pr.counts = counts ? counts + 2 * i : nullptr;
         if (probs) (*probs)[i] = pr;
     }
     pl.bytes = L.off;
@@ -274,6 +279,7 @@ const char *kKernelNames[K_COUNT] = {"blur", "contour", "dt_cols", "dt_rows", "d
 int setup(Run &R, capture_ctx *ctx, int n, const capture_frame *frames, const capture_nonrigid_params *params,
           void *ws, size_t ws_bytes, void *stream) {
     R.prof = &ctx->prof;
+    R.ctx = ctx;
     int rc = check_frames(n, frames);
     if (rc) return rc;
     if (params && (rc = check_params(params))) return rc;
@@ -313,7 +319,11 @@ int setup(Run &R, capture_ctx *ctx, int n, const capture_frame *frames, const ca
         R.lds_lin = std::max(R.lds_lin, sizeof(float) * (size_t(T.max_slots) * 15 + size_t(T.max_contrib) * 12));
         R.lds_apply = std::max(R.lds_apply, sizeof(float) * (size_t(T.max_slots) * 21 + size_t(T.max_contrib) * 6));
     }
-    CAP_HIP(hipMemcpyAsync(R.dprobs, R.probs.data(), sizeof(ProbDev) * n, hipMemcpyHostToDevice, R.s));
+    // sized once for both the descriptors and the report read-back of `collect`
+    void *stage = staging(ctx, sizeof(ProbDev) * n + sizeof(double) * kScalars * n + sizeof(int) * 2 * n + 512);
+    if (!stage) return fail(CAPTURE_ENOMEM, "pinned staging allocation failed");
+    std::memcpy(stage, R.probs.data(), sizeof(ProbDev) * n);
+    CAP_HIP(hipMemcpyAsync(R.dprobs, stage, sizeof(ProbDev) * n, hipMemcpyHostToDevice, R.s));
     return CAPTURE_OK;
 }
 
@@ -322,12 +332,7 @@ int launch_frame(Run &R, int gn_iters = 0) {
     const int n = R.n;
     hipStream_t s = R.s;
     hipLaunchKernelGGL(k_scal_init, dim3(n), dim3(64), 0, s, R.dprobs, gn_iters);
-    for (int i = 0; i < n; ++i) {
-        const ProbDev &pr = R.probs[i];
-        hipLaunchKernelGGL(k_fill_u32, dim3(blocks(size_t(pr.W) * pr.H, 256)), dim3(256), 0, s, pr.zbuf,
-                           size_t(pr.W) * pr.H, 0u);
-        hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, s, reinterpret_cast<uint32_t *>(pr.counts), size_t(2), 0u);
-    }
+    hipLaunchKernelGGL(k_clear_zbuf, dim3(blocks(R.max_hw, 1024), n), dim3(256), 0, s, R.dprobs);
     // Gaussian kernel 3, sigma = 0.3 * ((3 - 1) / 2 - 1) + 0.8 = 0.8, normalised
     const double e1 = std::exp(-1.0 / (2.0 * 0.8 * 0.8));
     const float w0 = float(e1 / (1.0 + 2.0 * e1)), w1 = float(1.0 / (1.0 + 2.0 * e1));
@@ -400,20 +405,21 @@ int launch_solve(Run &R, const capture_nonrigid_params *prm, int check_target = 
 }
 
 int collect(Run &R, int gn_iters, capture_report *reports) {
-    std::vector<double> scal(size_t(kScalars) * R.n);
-    std::vector<int> counts(size_t(2) * R.n);
-    for (int i = 0; i < R.n; ++i) {
-        CAP_HIP(hipMemcpyAsync(scal.data() + size_t(kScalars) * i, R.probs[i].scal, sizeof(double) * kScalars,
-                               hipMemcpyDeviceToHost, R.s));
-        CAP_HIP(hipMemcpyAsync(counts.data() + 2 * i, R.probs[i].counts, sizeof(int) * 2, hipMemcpyDeviceToHost, R.s));
-    }
+    const uint8_t *blk = reinterpret_cast<const uint8_t *>(R.probs[0].scal);
+    const size_t off_counts = reinterpret_cast<const uint8_t *>(R.probs[0].counts) - blk;
+    const size_t bytes = off_counts + sizeof(int) * 2 * R.n;
+    uint8_t *host = static_cast<uint8_t *>(staging(R.ctx, bytes));
+    if (!host) return fail(CAPTURE_ENOMEM, "pinned staging allocation failed");
+    CAP_HIP(hipMemcpyAsync(host, blk, bytes, hipMemcpyDeviceToHost, R.s));
     CAP_HIP(hipStreamSynchronize(R.s));
     settle(R);
+    const double *scal = reinterpret_cast<const double *>(host);
+    const int *counts = reinterpret_cast<const int *>(host + off_counts);
     int status = CAPTURE_OK;
     for (int i = 0; i < R.n; ++i) {
         capture_report &rep = reports[i];
         std::memset(&rep, 0, sizeof(rep));
-        const double *sc = scal.data() + size_t(kScalars) * i;
+        const double *sc = scal + size_t(kScalars) * i;
         const int done = std::min(gn_iters, std::max(0, int(sc[3])));
         for (int k = 0; k <= done; ++k) {
             const double *ek = sc + 8 + kTerms * k;
@@ -499,6 +505,7 @@ int capture_create(capture_ctx **ctx, int device) {
 void capture_destroy(capture_ctx *ctx) {
     if (!ctx) return;
     for (hipEvent_t e : ctx->prof.ev) (void)hipEventDestroy(e);
+    if (ctx->pinned) (void)hipHostFree(ctx->pinned);
     delete ctx;
 }
 

@@ -194,6 +194,8 @@ struct Profiler {
 struct capture_ctx {
     int device;
     cap::Profiler prof;
+    void *pinned = nullptr;      // pinned host staging (descriptors, report read-back)
+    size_t pinned_bytes = 0;
 };
 
 struct capture_warmstart {

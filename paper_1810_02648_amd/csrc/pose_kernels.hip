@@ -352,7 +352,9 @@ __global__ __launch_bounds__(kPoseRowThreads) void k_pose_rows(const PoseDev *__
 // Upper-triangle 16x16 tiles of [J | bF]^T [J | bF], one wave per (tile,
 // row chunk), on V_MFMA_F64_16X16X4F64: A(i, k) = rows[r0 + k][I0 + i],
 // B(k, j) = rows[r0 + k][J0 + j].  Lane l supplies element (l % 16, l / 16)
-// of A and (l / 16, l % 16) of B, and holds D(4 (l / 16) + q, l % 16).
+// of A and (l / 16, l % 16) of B; its accumulator register q holds
+// D(4 q + l / 16, l % 16) (one row group per register, unlike the 16x16
+// float32/bf16 shapes whose registers hold consecutive rows).
 typedef double dbl4 __attribute__((ext_vector_type(4)));
 
 __global__ __launch_bounds__(64) void k_pose_jtj(const PoseDev *__restrict__ PP) {
@@ -376,7 +378,7 @@ __global__ __launch_bounds__(64) void k_pose_jtj(const PoseDev *__restrict__ PP)
         acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
     }
     double *out = P.tpart + (size_t(chunk) * ntp + tp) * 256;
-    for (int q = 0; q < 4; ++q) out[(4 * lk + q) * kPoseTile + li] = acc[q];
+    for (int q = 0; q < 4; ++q) out[(4 * q + lk) * kPoseTile + li] = acc[q];
 }
 
 // mode 0: energy of the step, assemble, damp, Cholesky, update, kinematics.

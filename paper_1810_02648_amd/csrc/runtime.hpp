@@ -18,7 +18,22 @@ struct Layout {
     }
 };
 
+// Pinned host staging of a context, grown on demand (descriptor uploads and
+// report read-backs).  Calls on one context are serialised by the caller.
+inline void *staging(capture_ctx *ctx, size_t bytes) {
+    if (ctx->pinned_bytes < bytes) {
+        if (ctx->pinned) (void)hipHostFree(ctx->pinned);
+        ctx->pinned = nullptr;
+        ctx->pinned_bytes = 0;
+        const size_t want = std::max<size_t>(bytes, 64 * 1024);
+        if (hipHostMalloc(&ctx->pinned, want, hipHostMallocDefault) != hipSuccess) return nullptr;
+        ctx->pinned_bytes = want;
+    }
+    return ctx->pinned;
+}
+
 struct Run {
+    capture_ctx *ctx = nullptr;
     Profiler *prof = nullptr;
     int n = 0;
     std::vector<ProbDev> probs;

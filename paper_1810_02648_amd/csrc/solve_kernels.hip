@@ -412,10 +412,21 @@ __global__ __launch_bounds__(kNodeThreads) void k_node_init(const ProbDev *__res
     }
 }
 
-// Per-problem scalars at the start of a solve: nothing stopped, GN count = K.
+// Per-problem scalars at the start of a solve: nothing stopped, GN count = K;
+// visible / contour counters cleared.
 __global__ void k_scal_init(const ProbDev *__restrict__ P, int gn_iters) {
     const ProbDev &pr = P[blockIdx.x];
     for (int i = threadIdx.x; i < kScalars; i += blockDim.x) pr.scal[i] = i == 3 ? double(gn_iters) : 0.0;
+    if (threadIdx.x < 2) pr.counts[threadIdx.x] = 0;
+}
+
+// Empty depth buffers of every problem (4 pixels per thread).
+__global__ void k_clear_zbuf(const ProbDev *__restrict__ P) {
+    const ProbDev &pr = P[blockIdx.y];
+    const size_t hw = size_t(pr.W) * pr.H;
+    const size_t i = (size_t(blockIdx.x) * blockDim.x + threadIdx.x) * 4;
+    for (int q = 0; q < 4; ++q)
+        if (i + q < hw) pr.zbuf[i + q] = 0u;
 }
 
 // Copy p to the per-slot array (for a caller-supplied direction).

@@ -12,4 +12,4 @@ in for it with the same shapes.
 """
 from .meshes import icosphere, fibonacci_ellipsoid, ellipsoid_icosphere  # noqa: F401
 from .render import render_targets  # noqa: F401
-from .workloads import Camera, make_nonrigid_frame, CONFIGS  # noqa: F401
+from .workloads import Camera, make_nonrigid_frame, CONFIGS, batch_specs, make_batch  # noqa: F401

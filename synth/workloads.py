@@ -113,3 +113,35 @@ def make_nonrigid_frame(name="small", seed=0, n_vertices=None, n_nodes=None, sid
     return dict(name=name, seed=seed, xyz=xyz, tri=tri, rgb=rgb, cam=cam, gt_xyz=gt,
                 mask=mask, image=image, n_nodes=cfg["n_nodes"], gn=cfg["gn"], pcg=cfg["pcg"],
                 weights=cfg["weights"])
+
+
+def batch_specs(n=64, seed=0):
+    """Sizes of a batch of independent frames: vertex count, node count and
+    image side each drawn log-uniform (4,000-40,000 vertices, 128-1,000 nodes,
+    512-1,080 px square images), plus a seed per frame."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+
+    def lu(lo, hi):
+        return int(round(float(np.exp(rng.uniform(np.log(lo), np.log(hi))))))
+
+    specs = []
+    for i in range(n):
+        nv, nn, side = lu(4000, 40000), lu(128, 1000), lu(512, 1080)
+        specs.append(dict(n_vertices=nv, n_nodes=min(nn, nv), side=side, seed=1000 * seed + i))
+    return specs
+
+
+def _batch_frame(spec):
+    return make_nonrigid_frame("frame20k", spec["seed"], n_vertices=spec["n_vertices"], n_nodes=spec["n_nodes"],
+                               side=spec["side"])
+
+
+def make_batch(n=64, seed=0, workers=8):
+    """The frames of ``batch_specs`` (generated in worker processes)."""
+    specs = batch_specs(n, seed)
+    if workers <= 1:
+        return [_batch_frame(s) for s in specs]
+    import multiprocessing as mp
+    from concurrent.futures import ProcessPoolExecutor
+    with ProcessPoolExecutor(max_workers=workers, mp_context=mp.get_context("spawn")) as ex:
+        return list(ex.map(_batch_frame, specs))
