@@ -276,7 +276,7 @@ def bench_batch(args, cap, torch):
     for f in frames_h:
         xyz = torch.from_numpy(f["xyz"]).cuda()
         g = cap.graph_build(ctx, xyz, f["n_nodes"])
-        tmpl = cap.Template(ctx, torch.from_numpy(f["tri"]).cuda(), g)
+        tmpl = cap.Template(ctx, torch.from_numpy(f["tri"]).cuda(), g, args.tile)
         st = torch.zeros((12, f["n_nodes"]), dtype=torch.float32, device="cuda")
         st[0] = st[4] = st[8] = 1.0
         frames.append(cap.FrameInputs(tmpl, xyz, torch.from_numpy(f["rgb"]).cuda(), f["cam"],
@@ -344,6 +344,7 @@ def bench_batch(args, cap, torch):
                         "square images (%d vertices, %.1f Mpx in total), %d GN x %d PCG, plain start, one batched "
                         "call per step" % (n, sum(nv), sum(f["cam"].width ** 2 for f in frames_h) / 1e6, gn, pcg),
             "batch": n,
+            "vertices_per_tile": args.tile or 256,
             "final_energy_sum": float(sum(r["energy"][-1] for r in reps)),
             "start_energy_sum": float(sum(r["energy"][0] for r in reps)),
         },
@@ -366,7 +367,7 @@ def main():
     ap.add_argument("--epochs", type=int, default=40, help="sequence mode: training epochs")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-pose", action="store_true", help="frame mode: leave out the pose stage")
-    ap.add_argument("--tile", type=int, default=0, help="frame mode: vertices per tile (0 = library default)")
+    ap.add_argument("--tile", type=int, default=0, help="frame/batch mode: vertices per tile (0 = library default)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the solver has no multi-GPU path "

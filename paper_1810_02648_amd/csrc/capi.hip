@@ -19,6 +19,7 @@ __global__ void k_dt_cols(const ProbDev *P);
 __global__ void k_dt_rows(const ProbDev *P);
 __global__ void k_deform_start(const ProbDev *P);
 __global__ void k_raster(const ProbDev *P);
+__global__ void k_raster_big(const ProbDev *P);
 __global__ void k_contour_edges(const ProbDev *P);
 __global__ void k_decide(const ProbDev *P);
 __global__ void k_linearize(const ProbDev *P, int mode);
@@ -200,6 +201,7 @@ void carve(Layout &L, uint8_t *base, const capture_frame &f, ProbDev &pr) {
     pr.vcont = L.take<uint8_t>(base, nv);
     pr.vflags = L.take<uint8_t>(base, nv);
     pr.fcross = L.take<float>(base, 3 * nf);
+    pr.bigq = L.take<int>(base, nf);
     pr.px = L.take<float>(base, 3 * nv);
     pr.pc = L.take<float>(base, 3 * nv);
     pr.vcode = L.take<uint8_t>(base, nv);
@@ -225,12 +227,12 @@ Plan plan_workspace(int n, const capture_frame *frames, uint8_t *base, std::vect
     Plan pl;
     L.take<ProbDev>(base, n);
     double *scal = L.take<double>(base, size_t(kScalars) * n);
-    int *counts = L.take<int>(base, size_t(2) * n);
+    int *counts = L.take<int>(base, size_t(3) * n);
     for (int i = 0; i < n; ++i) {
         ProbDev pr{};
         carve(L, base, frames[i], pr);
         pr.scal = scal ? scal + size_t(kScalars) * i : nullptr;
-        pr.counts = counts ? counts + 2 * i : nullptr;
+        pr.counts = counts ? counts + 3 * i : nullptr;
         if (probs) (*probs)[i] = pr;
     }
     pl.bytes = L.off;
@@ -320,7 +322,7 @@ int setup(Run &R, capture_ctx *ctx, int n, const capture_frame *frames, const ca
         R.lds_apply = std::max(R.lds_apply, sizeof(float) * (size_t(T.max_slots) * 21 + size_t(T.max_contrib) * 6));
     }
     // sized once for both the descriptors and the report read-back of `collect`
-    void *stage = staging(ctx, sizeof(ProbDev) * n + sizeof(double) * kScalars * n + sizeof(int) * 2 * n + 512);
+    void *stage = staging(ctx, sizeof(ProbDev) * n + sizeof(double) * kScalars * n + sizeof(int) * 3 * n + 512);
     if (!stage) return fail(CAPTURE_ENOMEM, "pinned staging allocation failed");
     std::memcpy(stage, R.probs.data(), sizeof(ProbDev) * n);
     CAP_HIP(hipMemcpyAsync(R.dprobs, stage, sizeof(ProbDev) * n, hipMemcpyHostToDevice, R.s));
@@ -360,6 +362,7 @@ int launch_frame(Run &R, int gn_iters = 0) {
     });
     timed(R, K_RASTER, [&] {
     hipLaunchKernelGGL(k_raster, dim3(blocks(R.max_nf, 256), n), dim3(256), 0, s, R.dprobs);
+    hipLaunchKernelGGL(k_raster_big, dim3(kRasterBigBlocks, n), dim3(256), 0, s, R.dprobs);
     });
     timed(R, K_CEDGES, [&] {
     hipLaunchKernelGGL(k_contour_edges, dim3(blocks(R.max_me, 256), n), dim3(256), 0, s, R.dprobs);
@@ -407,7 +410,7 @@ int launch_solve(Run &R, const capture_nonrigid_params *prm, int check_target = 
 int collect(Run &R, int gn_iters, capture_report *reports) {
     const uint8_t *blk = reinterpret_cast<const uint8_t *>(R.probs[0].scal);
     const size_t off_counts = reinterpret_cast<const uint8_t *>(R.probs[0].counts) - blk;
-    const size_t bytes = off_counts + sizeof(int) * 2 * R.n;
+    const size_t bytes = off_counts + sizeof(int) * 3 * R.n;
     uint8_t *host = static_cast<uint8_t *>(staging(R.ctx, bytes));
     if (!host) return fail(CAPTURE_ENOMEM, "pinned staging allocation failed");
     CAP_HIP(hipMemcpyAsync(host, blk, bytes, hipMemcpyDeviceToHost, R.s));
@@ -427,8 +430,8 @@ int collect(Run &R, int gn_iters, capture_report *reports) {
         }
         const double *e = sc + 8 + kTerms * done;
         rep.e_photo = e[0]; rep.e_sil = e[1]; rep.e_sil_abs = e[2]; rep.e_arap = e[3]; rep.e_vel = e[4];
-        rep.n_visible = counts[2 * i];
-        rep.n_boundary = counts[2 * i + 1];
+        rep.n_visible = counts[3 * i];
+        rep.n_boundary = counts[3 * i + 1];
         rep.gn_done = done;
         rep.status = std::isfinite(rep.energy[done]) ? CAPTURE_OK : CAPTURE_ENONFINITE;
         if (rep.status) status = rep.status;

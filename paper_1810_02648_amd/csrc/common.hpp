@@ -30,6 +30,8 @@ constexpr int kMaxTileContrib = 1024; // contributions held in LDS per tile
 constexpr int kMaxTileSlots = 200;    // distinct nodes touched by a tile
 constexpr int kNodeThreads = 1024;    // threads of a per-problem node workgroup
 constexpr int kMaxImageSide = 4096;
+constexpr int kRasterSmall = 256;         // pixel-box size above which a face is rasterised by a workgroup
+constexpr int kRasterBigBlocks = 512;
 constexpr int kTerms = 5;   // energy terms per slot: photo, sil (with b), sil (with |b|), arap, velocity
 constexpr int kScalars = 8 + kTerms * (CAPTURE_MAX_GN + 2);   // slot MAX_GN + 1: predicted start
 
@@ -109,7 +111,8 @@ struct ProbDev {
     // nodes
     float *b, *diag, *dinv, *x, *r, *z, *p, *Ap;   // [6][nn]
     double *scal;     // [kScalars]: rz, done, stopped, stop step, ..., kTerms energies per GN step
-    int *counts;      // [2]
+    int *counts;      // [3] visible, contour set, queued large faces
+    int *bigq;        // [nf] faces rasterised by k_raster_big
     float *state0;    // [12][nn] copy of the start state (restored on a device-detected error)
     double target;    // stop once the energy at the start of a GN step is <= target (-inf: never)
 };
@@ -135,9 +138,7 @@ constexpr int kMaxJoints = 32;
 constexpr int kMaxPoseUnknowns = 81;     // 3 per rotating joint + root t (3) + t' (3)
 constexpr int kPoseTile = 16;            // MFMA f64 16x16x4 tiles of J^T J
 constexpr int kPoseMaxCols = 96;         // unknowns + the b*F column, padded to 16
-constexpr int kPoseChunks = 8;           // row chunks of the J^T J reduction
 constexpr int kPoseRowThreads = 256;
-constexpr int kPoseStepThreads = 256;
 
 // Skeleton and skinning of a body (device copy of the static part).
 struct BodyDev {
@@ -167,9 +168,8 @@ struct PoseDev {
     int *nb;                         // [1] |B|
     double *rows;                    // [max_rows][np] Jacobian rows, column nu holds b*F
     double *epart;                   // [row blocks][4] energy partials: 2D, 3D, sil, sil with |b|
-    double *tpart;                   // [kPoseChunks][ntp][256] J^T J tile partials
     double *energy;                  // [MAX_GN + 1][4]
-    double *sys;                     // [nu][nu + 1] last assembled system (J^T J | -J^T B F), undamped
+    double *sys;                     // [nu][nu + 1] system of the current step (J^T J | -J^T B F), undamped
     int *status;                     // [1]
 };
 

@@ -227,12 +227,72 @@ __global__ void k_deform_start(const ProbDev *__restrict__ P) {
     store_start_vertex(pr, i, acc[0], acc[1], acc[2]);
 }
 
-// Per face: cross product (for normals), then rasterise the inverse depth with
-// the fixed-point coverage rule; the buffer keeps the largest bit pattern.
+// Fixed-point triangle set-up of the coverage rule: 1/256-pixel vertices,
+// counter-clockwise order, pixel box clipped to the image, edge ownership.
+struct TriRaster {
+    long long U0, V0, U1, V1, U2, V2, dU0, dV0, dU1, dV1, dU2, dV2;
+    long long i0, i1, j0, j1;
+    bool o0, o1, o2;
+    float iz0, iz1, iz2, Af;
+};
+
+__device__ inline bool tri_setup(const ProbDev &pr, int f, TriRaster &s) {
+    const TemplateDev &T = pr.T;
+    const int nv = T.nv, nf = T.nf;
+    const int a = T.tri[f], b = T.tri[nf + f], c = T.tri[2 * size_t(nf) + f];
+    if (!(pr.dvalid[a] && pr.dvalid[b] && pr.dvalid[c])) return false;
+    s.U0 = pr.dfix[a]; s.V0 = pr.dfix[nv + a];
+    s.U1 = pr.dfix[b]; s.V1 = pr.dfix[nv + b];
+    s.U2 = pr.dfix[c]; s.V2 = pr.dfix[nv + c];
+    long long A = (s.U1 - s.U0) * (s.V2 - s.V0) - (s.V1 - s.V0) * (s.U2 - s.U0);
+    if (A == 0) return false;
+    int ib = b, ic = c;
+    if (A < 0) {
+        long long t;
+        t = s.U1; s.U1 = s.U2; s.U2 = t;
+        t = s.V1; s.V1 = s.V2; s.V2 = t;
+        ib = c; ic = b;
+        A = -A;
+    }
+    s.iz0 = 1.0f / pr.dx[2 * nv + a];
+    s.iz1 = 1.0f / pr.dx[2 * nv + ib];
+    s.iz2 = 1.0f / pr.dx[2 * nv + ic];
+    const long long umin = min(s.U0, min(s.U1, s.U2)), umax = max(s.U0, max(s.U1, s.U2));
+    const long long vmin = min(s.V0, min(s.V1, s.V2)), vmax = max(s.V0, max(s.V1, s.V2));
+    s.i0 = max(0LL, -((-umin) >> 8));
+    s.i1 = min((long long)pr.W - 1, umax >> 8);
+    s.j0 = max(0LL, -((-vmin) >> 8));
+    s.j1 = min((long long)pr.H - 1, vmax >> 8);
+    // edges 0: 1->2, 1: 2->0, 2: 0->1 and their boundary ownership
+    s.dU0 = s.U2 - s.U1; s.dV0 = s.V2 - s.V1;
+    s.dU1 = s.U0 - s.U2; s.dV1 = s.V0 - s.V2;
+    s.dU2 = s.U1 - s.U0; s.dV2 = s.V1 - s.V0;
+    s.o0 = s.dV0 < 0 || (s.dV0 == 0 && s.dU0 > 0);
+    s.o1 = s.dV1 < 0 || (s.dV1 == 0 && s.dU1 > 0);
+    s.o2 = s.dV2 < 0 || (s.dV2 == 0 && s.dU2 > 0);
+    s.Af = float(A);
+    return s.i0 <= s.i1 && s.j0 <= s.j1;
+}
+
+// Coverage and inverse depth of pixel (i, j); the buffer keeps the largest bits.
+__device__ inline void tri_pixel(const ProbDev &pr, const TriRaster &s, long long i, long long j) {
+    const long long Pu = i * 256, Pv = j * 256;
+    const long long E0 = s.dU0 * (Pv - s.V1) - s.dV0 * (Pu - s.U1);
+    const long long E1 = s.dU1 * (Pv - s.V2) - s.dV1 * (Pu - s.U2);
+    const long long E2 = s.dU2 * (Pv - s.V0) - s.dV2 * (Pu - s.U0);
+    const bool in = (E0 > 0 || (E0 == 0 && s.o0)) && (E1 > 0 || (E1 == 0 && s.o1)) && (E2 > 0 || (E2 == 0 && s.o2));
+    if (!in) return;
+    const float inv = ((float(E0) * s.iz0 + float(E1) * s.iz1) + float(E2) * s.iz2) / s.Af;
+    atomicMax(pr.zbuf + size_t(j) * pr.W + i, __float_as_uint(inv));
+}
+
+// Per face: cross product (for normals), then rasterise the inverse depth.
+// A face whose pixel box holds more than kRasterSmall pixels is queued for
+// k_raster_big instead, so one thread never walks a large box.
 __global__ void k_raster(const ProbDev *__restrict__ P) {
     const ProbDev &pr = P[blockIdx.y];
     const TemplateDev &T = pr.T;
-    const int nv = T.nv, nf = T.nf, W = pr.W, H = pr.H;
+    const int nv = T.nv, nf = T.nf;
     int f = blockIdx.x * blockDim.x + threadIdx.x;
     if (f >= nf) return;
     int a = T.tri[f], b = T.tri[nf + f], c = T.tri[2 * size_t(nf) + f];
@@ -244,43 +304,25 @@ __global__ void k_raster(const ProbDev *__restrict__ P) {
     pr.fcross[f] = cr[0];
     pr.fcross[nf + f] = cr[1];
     pr.fcross[2 * size_t(nf) + f] = cr[2];
-    if (!(pr.dvalid[a] && pr.dvalid[b] && pr.dvalid[c])) return;
-    long long U0 = pr.dfix[a], V0 = pr.dfix[nv + a];
-    long long U1 = pr.dfix[b], V1 = pr.dfix[nv + b];
-    long long U2 = pr.dfix[c], V2 = pr.dfix[nv + c];
-    long long A = (U1 - U0) * (V2 - V0) - (V1 - V0) * (U2 - U0);
-    if (A == 0) return;
-    int ib = b, ic = c;
-    if (A < 0) {
-        long long t;
-        t = U1; U1 = U2; U2 = t;
-        t = V1; V1 = V2; V2 = t;
-        ib = c; ic = b;
-        A = -A;
+    TriRaster s;
+    if (!tri_setup(pr, f, s)) return;
+    if ((s.i1 - s.i0 + 1) * (s.j1 - s.j0 + 1) > kRasterSmall) {
+        pr.bigq[atomicAdd(pr.counts + 2, 1)] = f;
+        return;
     }
-    float iz0 = 1.0f / pr.dx[2 * nv + a], iz1 = 1.0f / pr.dx[2 * nv + ib], iz2 = 1.0f / pr.dx[2 * nv + ic];
-    long long umin = min(U0, min(U1, U2)), umax = max(U0, max(U1, U2));
-    long long vmin = min(V0, min(V1, V2)), vmax = max(V0, max(V1, V2));
-    long long i0 = max(0LL, -((-umin) >> 8)), i1 = min((long long)W - 1, umax >> 8);
-    long long j0 = max(0LL, -((-vmin) >> 8)), j1 = min((long long)H - 1, vmax >> 8);
-    // edges 0: 1->2, 1: 2->0, 2: 0->1 and their boundary ownership
-    long long dU0 = U2 - U1, dV0 = V2 - V1, dU1 = U0 - U2, dV1 = V0 - V2, dU2 = U1 - U0, dV2 = V1 - V0;
-    bool o0 = dV0 < 0 || (dV0 == 0 && dU0 > 0);
-    bool o1 = dV1 < 0 || (dV1 == 0 && dU1 > 0);
-    bool o2 = dV2 < 0 || (dV2 == 0 && dU2 > 0);
-    float Af = float(A);
-    for (long long j = j0; j <= j1; ++j) {
-        long long Pv = j * 256;
-        for (long long i = i0; i <= i1; ++i) {
-            long long Pu = i * 256;
-            long long E0 = dU0 * (Pv - V1) - dV0 * (Pu - U1);
-            long long E1 = dU1 * (Pv - V2) - dV1 * (Pu - U2);
-            long long E2 = dU2 * (Pv - V0) - dV2 * (Pu - U0);
-            bool in = (E0 > 0 || (E0 == 0 && o0)) && (E1 > 0 || (E1 == 0 && o1)) && (E2 > 0 || (E2 == 0 && o2));
-            if (!in) continue;
-            float inv = ((float(E0) * iz0 + float(E1) * iz1) + float(E2) * iz2) / Af;
-            atomicMax(pr.zbuf + size_t(j) * W + i, __float_as_uint(inv));
-        }
+    for (long long j = s.j0; j <= s.j1; ++j)
+        for (long long i = s.i0; i <= s.i1; ++i) tri_pixel(pr, s, i, j);
+}
+
+// Queued large faces: one workgroup per face at a time, threads over its pixel box.
+__global__ __launch_bounds__(256) void k_raster_big(const ProbDev *__restrict__ P) {
+    const ProbDev &pr = P[blockIdx.y];
+    const int nq = pr.counts[2];
+    for (int q = blockIdx.x; q < nq; q += gridDim.x) {
+        TriRaster s;
+        if (!tri_setup(pr, pr.bigq[q], s)) continue;
+        const long long w = s.i1 - s.i0 + 1, area = w * (s.j1 - s.j0 + 1);
+        for (long long k = threadIdx.x; k < area; k += blockDim.x) tri_pixel(pr, s, s.i0 + k % w, s.j0 + k / w);
     }
 }
 

@@ -18,6 +18,7 @@ __global__ void k_dt_seg(const ProbDev *P);
 __global__ void k_dt_cols(const ProbDev *P);
 __global__ void k_dt_rows(const ProbDev *P);
 __global__ void k_raster(const ProbDev *P);
+__global__ void k_raster_big(const ProbDev *P);
 __global__ void k_contour_edges(const ProbDev *P);
 __global__ void k_decide(const ProbDev *P);
 __global__ void k_pose_fk(const PoseDev *P);
@@ -58,12 +59,12 @@ size_t carve_pose(uint8_t *base, const capture_pose_frame &f, ProbDev &pr, PoseD
     pr.vcont = L.take<uint8_t>(base, nv);
     pr.vflags = L.take<uint8_t>(base, nv);
     pr.fcross = L.take<float>(base, 3 * nf);
+    pr.bigq = L.take<int>(base, nf);
     pr.px = L.take<float>(base, 3 * nv);
     pr.vcode = L.take<uint8_t>(base, nv);
     pr.pva = L.take<float>(base, 3 * nv);
-    pr.counts = L.take<int>(base, 2);
+    pr.counts = L.take<int>(base, 3);
     max_rows = 5 * B.nj + int(nv);
-    const int nt = B.np / kPoseTile;
     pd.jR = L.take<double>(base, size_t(9) * B.nj);
     pd.jp = L.take<double>(base, size_t(3) * B.nj);
     pd.jA = L.take<double>(base, size_t(9) * B.nj);
@@ -72,7 +73,6 @@ size_t carve_pose(uint8_t *base, const capture_pose_frame &f, ProbDev &pr, PoseD
     pd.nb = L.take<int>(base, 1);
     pd.rows = L.take<double>(base, size_t(max_rows) * B.np);
     pd.epart = L.take<double>(base, size_t(blocks(max_rows, kPoseRowThreads)) * 4);
-    pd.tpart = L.take<double>(base, size_t(kPoseChunks) * (nt * (nt + 1) / 2) * 256);
     pd.energy = L.take<double>(base, size_t(CAPTURE_MAX_GN + 1) * 4);
     pd.sys = L.take<double>(base, size_t(B.nu) * (B.nu + 1));
     pd.status = L.take<int>(base, 1);
@@ -164,9 +164,9 @@ int launch_pose_decisions(PoseRun &P) {
     const ProbDev &pr = R.probs[0];
     const size_t hw = size_t(pr.W) * pr.H;
     hipLaunchKernelGGL(k_fill_u32, dim3(blocks(hw, 256)), dim3(256), 0, s, pr.zbuf, hw, 0u);
-    hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, s, reinterpret_cast<uint32_t *>(pr.counts), size_t(2), 0u);
+    hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, s, reinterpret_cast<uint32_t *>(pr.counts), size_t(3), 0u);
     timed(R, K_POSE_LBS, [&] {
-        hipLaunchKernelGGL(k_pose_fk, dim3(1), dim3(kPoseStepThreads), 0, s, P.dpose);
+        hipLaunchKernelGGL(k_pose_fk, dim3(1), dim3(64), 0, s, P.dpose);
         hipLaunchKernelGGL(k_pose_lbs, dim3(blocks(pr.T.nv, 256)), dim3(256), 0, s, P.dpose, R.dprobs);
     });
     const dim3 gpx(blocks(hw, 256));
@@ -182,6 +182,7 @@ int launch_pose_decisions(PoseRun &P) {
     });
     timed(R, K_RASTER, [&] {
         hipLaunchKernelGGL(k_raster, dim3(blocks(pr.T.nf, 256)), dim3(256), 0, s, R.dprobs);
+        hipLaunchKernelGGL(k_raster_big, dim3(kRasterBigBlocks), dim3(256), 0, s, R.dprobs);
     });
     timed(R, K_CEDGES, [&] {
         hipLaunchKernelGGL(k_contour_edges, dim3(blocks(pr.T.nmedges, 256)), dim3(256), 0, s, R.dprobs);
@@ -204,10 +205,10 @@ int launch_pose_step(PoseRun &P, int gn, int mode) {
     });
     if (!energy_only)
         timed(R, K_POSE_JTJ, [&] {
-            hipLaunchKernelGGL(k_pose_jtj, dim3(P.ntp, kPoseChunks), dim3(64), 0, s, P.dpose);
+            hipLaunchKernelGGL(k_pose_jtj, dim3(P.ntp), dim3(256), 0, s, P.dpose);
         });
     timed(R, K_POSE_STEP, [&] {
-        hipLaunchKernelGGL(k_pose_step, dim3(1), dim3(kPoseStepThreads), 0, s, P.dpose, gn, P.row_blocks, mode);
+        hipLaunchKernelGGL(k_pose_step, dim3(1), dim3(64), 0, s, P.dpose, gn, P.row_blocks, mode);
     });
     CAP_HIP(hipGetLastError());
     return CAPTURE_OK;

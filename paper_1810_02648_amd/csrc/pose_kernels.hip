@@ -106,7 +106,7 @@ __device__ inline void fk_store(const PoseDev &P, const double *sR, const double
 }
 
 // Start of a solve: keep the start pose, clear the status, kinematics at it.
-__global__ __launch_bounds__(kPoseStepThreads) void k_pose_fk(const PoseDev *__restrict__ PP) {
+__global__ __launch_bounds__(64) void k_pose_fk(const PoseDev *__restrict__ PP) {
     const PoseDev &P = *PP;
     __shared__ double sR[9 * kMaxJoints], sp[3 * kMaxJoints], sA[9 * kMaxJoints], sL[9 * kMaxJoints],
         sJ[9 * kMaxJoints];
@@ -349,129 +349,149 @@ __global__ __launch_bounds__(kPoseRowThreads) void k_pose_rows(const PoseDev *__
     }
 }
 
-// Upper-triangle 16x16 tiles of [J | bF]^T [J | bF], one wave per (tile,
-// row chunk), on V_MFMA_F64_16X16X4F64: A(i, k) = rows[r0 + k][I0 + i],
-// B(k, j) = rows[r0 + k][J0 + j].  Lane l supplies element (l % 16, l / 16)
-// of A and (l / 16, l % 16) of B; its accumulator register q holds
-// D(4 q + l / 16, l % 16) (one row group per register, unlike the 16x16
-// float32/bf16 shapes whose registers hold consecutive rows).
+// Upper-triangle 16x16 tiles of [J | bF]^T [J | bF] on V_MFMA_F64_16X16X4F64,
+// one workgroup of 4 waves per tile: wave w takes every 4th group of 32 rows,
+// A(i, k) = rows[r + k][I0 + i], B(k, j) = rows[r + k][J0 + j].  Lane l
+// supplies element (l % 16, l / 16) of A and (l / 16, l % 16) of B; its
+// accumulator register q holds D(4 q + l / 16, l % 16) (one row group per
+// register, unlike the 16x16 float32/bf16 shapes whose registers hold
+// consecutive rows).  The 4 wave sums are added in wave order, and the tile
+// is written into the system [nu][nu + 1] (both triangles; the column of
+// b F becomes the right-hand side -J^T B F).
 typedef double dbl4 __attribute__((ext_vector_type(4)));
+constexpr int kJtjWaves = 4, kJtjBatch = 8;
 
-__global__ __launch_bounds__(64) void k_pose_jtj(const PoseDev *__restrict__ PP) {
+__global__ __launch_bounds__(64 * kJtjWaves) void k_pose_jtj(const PoseDev *__restrict__ PP) {
     const PoseDev &P = *PP;
-    const int np_ = P.B.np, nt = np_ / kPoseTile, ntp = nt * (nt + 1) / 2;
-    const int tp = blockIdx.x, chunk = blockIdx.y;
-    int I = 0, rem = tp;
+    __shared__ double part[kJtjWaves][256];
+    const int np_ = P.B.np, nu = P.B.nu, nt = np_ / kPoseTile;
+    int I = 0, rem = blockIdx.x;
     while (rem >= nt - I) { rem -= nt - I; ++I; }
     const int Jt = I + rem;
     const int M = 5 * P.B.nj + P.nb[0];
-    const int per = ((M + kPoseChunks - 1) / kPoseChunks + 3) & ~3;
-    const int beg = min(M, chunk * per), end = min(M, beg + per);
-    const int l = threadIdx.x, li = l & 15, lk = l >> 4;
+    const int wv = threadIdx.x >> 6, l = threadIdx.x & 63, li = l & 15, lk = l >> 4;
     dbl4 acc = {0.0, 0.0, 0.0, 0.0};
     const double *col_a = P.rows + I * kPoseTile + li;
     const double *col_b = P.rows + Jt * kPoseTile + li;
-    for (int r0 = beg; r0 < end; r0 += 4) {
-        const int r = r0 + lk;
-        const double a = r < end ? col_a[size_t(r) * np_] : 0.0;
-        const double b = r < end ? col_b[size_t(r) * np_] : 0.0;
-        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+    constexpr int span = 4 * kJtjBatch;
+    for (int r0 = wv * span; r0 < M; r0 += kJtjWaves * span) {
+        double a[kJtjBatch], bb[kJtjBatch];
+#pragma unroll
+        for (int u = 0; u < kJtjBatch; ++u) {
+            const int r = r0 + 4 * u + lk;
+            a[u] = r < M ? col_a[size_t(r) * np_] : 0.0;
+            bb[u] = r < M ? col_b[size_t(r) * np_] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < kJtjBatch; ++u) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u], bb[u], acc, 0, 0, 0);
     }
-    double *out = P.tpart + (size_t(chunk) * ntp + tp) * 256;
-    for (int q = 0; q < 4; ++q) out[(4 * q + lk) * kPoseTile + li] = acc[q];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) part[wv][(4 * q + lk) * kPoseTile + li] = acc[q];
+    __syncthreads();
+    if (wv == 0) {
+        for (int q = 0; q < 4; ++q) {
+            const int e = (4 * q + lk) * kPoseTile + li;
+            double s = part[0][e];
+            for (int w = 1; w < kJtjWaves; ++w) s += part[w][e];
+            const int gi = I * kPoseTile + 4 * q + lk, gj = Jt * kPoseTile + li;
+            if (gi > gj) continue;      // a diagonal tile's lower half is the mirror of its upper half
+            if (gi < nu && gj < nu) {
+                P.sys[gi * (nu + 1) + gj] = s;
+                P.sys[gj * (nu + 1) + gi] = s;
+            } else if (gi < nu && gj == nu) {
+                P.sys[gi * (nu + 1) + nu] = -s;
+            }
+        }
+    }
 }
 
-// mode 0: energy of the step, assemble, damp, Cholesky, update, kinematics.
-// mode 1: energy only (final).  mode 2: energy and the undamped system only.
-__global__ __launch_bounds__(kPoseStepThreads) void k_pose_step(const PoseDev *__restrict__ PP, int gn, int nblk,
-                                                                int mode) {
+// One wave.  mode 0: energy of the step, damping, Cholesky A = U^T U (upper
+// factor, row-major in LDS so every inner loop runs along a row), solves,
+// update, kinematics at the new pose.  mode 1: energy only (final).
+// mode 2: energy only (the system is already in place for the caller).
+__global__ __launch_bounds__(64) void k_pose_step(const PoseDev *__restrict__ PP, int gn, int nblk, int mode) {
     const PoseDev &P = *PP;
     const BodyDev &B = P.B;
-    const int nu = B.nu, np_ = B.np, nt = np_ / kPoseTile, ntp = nt * (nt + 1) / 2;
-    const int t = threadIdx.x, nth = blockDim.x;
+    const int nu = B.nu, lda = nu + 1;
+    const int t = threadIdx.x;
     __shared__ double A[kMaxPoseUnknowns * (kMaxPoseUnknowns + 1)];
     __shared__ double y[kMaxPoseUnknowns], pn[kMaxPoseUnknowns];
+    __shared__ double ep[4 * 64];
     __shared__ double sR[9 * kMaxJoints], sp[3 * kMaxJoints], sA[9 * kMaxJoints], sL[9 * kMaxJoints],
         sJ[9 * kMaxJoints];
-    __shared__ double smax;
     __shared__ int bad;
-    const int lda = nu + 1;
+    // energies of the rows kernel's blocks, summed in block order
     if (t == 0) bad = 0;
-    if (t < 4) {
+    for (int q = 0; q < 4; ++q) {
         double s = 0.0;
-        for (int b = 0; b < nblk; ++b) s += P.epart[size_t(b) * 4 + t];
-        P.energy[gn * 4 + t] = s;
-        if (!isfinite(s)) atomicOr(&bad, 1);
+        for (int b0 = 0; b0 < nblk; b0 += 64) {
+            __syncthreads();
+            ep[t] = b0 + t < nblk ? P.epart[size_t(b0 + t) * 4 + q] : 0.0;
+            __syncthreads();
+            if (t == 0)
+                for (int b = 0; b < 64 && b0 + b < nblk; ++b) s += ep[b];
+        }
+        if (t == 0) {
+            P.energy[gn * 4 + q] = s;
+            if (!isfinite(s)) bad = 1;
+        }
     }
     __syncthreads();
     if (bad) {
         if (t == 0 && P.status[0] == 0) P.status[0] = CAPTURE_ENONFINITE;
         return;
     }
-    if (mode == 1 || P.status[0] != 0) return;
-    // assemble J^T J (upper triangle mirrored) and -J^T B F
-    for (int e = t; e < nu * (nu + 1); e += nth) {
-        const int gi = e / (nu + 1), gj = e % (nu + 1);
-        const int lo = min(gi, gj), hi = max(gi, gj);
-        const int It = lo / kPoseTile, Jt = hi / kPoseTile;
-        const int tp = It * nt - It * (It - 1) / 2 + (Jt - It);
-        const int off = (lo % kPoseTile) * kPoseTile + hi % kPoseTile;
-        double s = 0.0;
-        for (int c = 0; c < kPoseChunks; ++c) s += P.tpart[(size_t(c) * ntp + tp) * 256 + off];
-        A[gi * lda + gj] = gj == nu ? -s : s;
-    }
+    if (mode != 0 || P.status[0] != 0) return;
+    for (int e = t; e < nu * lda; e += 64) A[e] = P.sys[e];
     __syncthreads();
-    for (int e = t; e < nu * lda; e += nth) P.sys[e] = A[e];
-    if (mode == 2) return;
-    if (t == 0) {
-        double m = A[0];
-        for (int i = 1; i < nu; ++i) m = fmax(m, A[i * lda + i]);
-        smax = m;
-    }
+    double m = 0.0;
+    for (int i = t; i < nu; i += 64) m = fmax(m, A[i * lda + i]);
+    for (int o = 32; o > 0; o >>= 1) m = fmax(m, __shfl_xor(m, o));
+    const double mu = 1e-6 * m;
+    for (int i = t; i < nu; i += 64) A[i * lda + i] += mu;
     __syncthreads();
-    const double mu = 1e-6 * smax;
-    for (int i = t; i < nu; i += nth) A[i * lda + i] += mu;
-    __syncthreads();
-    // Cholesky, right-looking, lower triangle in place
+    // A = U^T U, U in the upper triangle
     for (int k = 0; k < nu; ++k) {
-        if (t == 0) {
-            const double d = A[k * lda + k];
-            if (!(d > 0.0) || !isfinite(d)) bad = 1;
-            A[k * lda + k] = sqrt(d);
+        const double d = A[k * lda + k];
+        if (!(d > 0.0) || !isfinite(d)) {
+            if (t == 0) bad = 1;
+            break;
         }
+        const double ukk = sqrt(d);
         __syncthreads();
-        if (bad) break;
-        const double dk = A[k * lda + k];
-        for (int i = k + 1 + t; i < nu; i += nth) A[i * lda + k] /= dk;
+        if (t == 0) A[k * lda + k] = ukk;
+        for (int j = k + 1 + t; j < nu; j += 64) A[k * lda + j] /= ukk;
         __syncthreads();
-        const int m = nu - k - 1;
-        for (int e = t; e < m * m; e += nth) {
-            const int i = k + 1 + e / m, j = k + 1 + e % m;
-            if (j <= i) A[i * lda + j] -= A[i * lda + k] * A[j * lda + k];
+        for (int i = k + 1; i < nu; ++i) {
+            const double uki = A[k * lda + i];
+            for (int j = i + t; j < nu; j += 64) A[i * lda + j] -= uki * A[k * lda + j];
         }
         __syncthreads();
     }
+    __syncthreads();
     if (bad) {
-        for (int e = t; e < nu; e += nth) P.pose[e] = P.pose0[e];
+        for (int e = t; e < nu; e += 64) P.pose[e] = P.pose0[e];
         if (t == 0) P.status[0] = CAPTURE_ENOTSPD;
         return;
     }
-    // L y = rhs, then L^T delta = y
-    for (int e = t; e < nu; e += nth) y[e] = A[e * lda + nu];
+    // U^T y = rhs, then U delta = y
+    for (int e = t; e < nu; e += 64) y[e] = A[e * lda + nu];
     __syncthreads();
     for (int k = 0; k < nu; ++k) {
-        if (t == 0) y[k] /= A[k * lda + k];
+        const double yk = y[k] / A[k * lda + k];
         __syncthreads();
-        for (int i = k + 1 + t; i < nu; i += nth) y[i] -= A[i * lda + k] * y[k];
+        if (t == 0) y[k] = yk;
+        for (int j = k + 1 + t; j < nu; j += 64) y[j] -= A[k * lda + j] * yk;
         __syncthreads();
     }
     for (int k = nu - 1; k >= 0; --k) {
-        if (t == 0) y[k] /= A[k * lda + k];
+        const double dk = y[k] / A[k * lda + k];
         __syncthreads();
-        for (int i = t; i < k; i += nth) y[i] -= A[k * lda + i] * y[k];
+        if (t == 0) y[k] = dk;
+        for (int i = t; i < k; i += 64) y[i] -= A[i * lda + k] * dk;
         __syncthreads();
     }
-    for (int e = t; e < nu; e += nth) {
+    for (int e = t; e < nu; e += 64) {
         pn[e] = P.pose[e] + y[e];
         P.pose[e] = pn[e];
     }

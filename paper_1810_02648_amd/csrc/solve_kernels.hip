@@ -413,11 +413,11 @@ __global__ __launch_bounds__(kNodeThreads) void k_node_init(const ProbDev *__res
 }
 
 // Per-problem scalars at the start of a solve: nothing stopped, GN count = K;
-// visible / contour counters cleared.
+// visible / contour / large-face counters cleared.
 __global__ void k_scal_init(const ProbDev *__restrict__ P, int gn_iters) {
     const ProbDev &pr = P[blockIdx.x];
     for (int i = threadIdx.x; i < kScalars; i += blockDim.x) pr.scal[i] = i == 3 ? double(gn_iters) : 0.0;
-    if (threadIdx.x < 2) pr.counts[threadIdx.x] = 0;
+    if (threadIdx.x < 3) pr.counts[threadIdx.x] = 0;
 }
 
 // Empty depth buffers of every problem (4 pixels per thread).

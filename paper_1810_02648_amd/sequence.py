@@ -98,15 +98,19 @@ def train(S, net, X, Y, epochs=40, lr=1e-3, seed=0, log=None):
     return losses
 
 
-def evaluate(S, net, states, frames):
+def evaluate(S, net, states, frames, step_cap=2):
     """Equal-energy comparison on held-out frames.
 
     For each frame t both methods start from x*_{t-1}: the plain start runs
     the full schedule and its final energy is the target; the learned start
     runs Gauss-Newton until the energy at the start of a step is at or below
-    that target (at most the same number of steps).  Returns per-frame steps
-    and the wall time of each method over all frames (synchronous calls,
-    identical host overhead)."""
+    that target, for at most step_cap times the plain schedule's steps (so a
+    worse start costs extra steps instead of ending above the target).
+    Returns per-frame steps and the wall time of each method over all frames
+    (synchronous calls, identical host overhead)."""
+    import copy
+    prm_l = copy.copy(S.prm)
+    prm_l.gn_iters = min(32, step_cap * S.prm.gn_iters)
     targets, plain_steps = [], []
     for t in frames:
         st = states[t - 1].clone()
@@ -125,7 +129,7 @@ def evaluate(S, net, states, frames):
         for b, t, e in zip(bufs, frames, targets):
             b.copy_(states[t - 1])
             prev2 = states[t - 2] if t >= 2 else None
-            reps.append(nonrigid_solve_warm(S.ctx, S.frame(t, b), S.prm, net, prev2, e))
+            reps.append(nonrigid_solve_warm(S.ctx, S.frame(t, b), prm_l, net, prev2, e))
         return reps
 
     run_plain()
