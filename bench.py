@@ -170,14 +170,21 @@ def bench_frame(args, cap, torch):
     ctx = cap.Context(0)
     xyz = torch.from_numpy(f["xyz"]).cuda()
     graph = cap.graph_build(ctx, xyz, nn)                     # on the GPU, per template (not timed)
-    tmpl = cap.Template(ctx, torch.from_numpy(f["tri"]).cuda(), graph, args.tile)
+    tri = torch.from_numpy(f["tri"]).cuda()
     start = torch.zeros((12, nn), dtype=torch.float32, device="cuda")
     start[0] = start[4] = start[8] = 1.0
     rgb = torch.from_numpy(f["rgb"]).cuda()
     mask = torch.from_numpy(f["mask"]).cuda()
     image = torch.from_numpy(f["image"]).cuda()
-    frames = [cap.FrameInputs(tmpl, xyz, rgb, f["cam"], mask, image, start.clone()) for _ in range(args.batch)]
     prm = cap.params(*f["weights"], gn_iters=gn, pcg_iters=pcg)
+    tile, tune = args.tile, None
+    if tile == 0:       # autotuned tile size (setup, not timed)
+        probe = cap.Template(ctx, tri, graph)
+        fr0 = [cap.FrameInputs(probe, xyz, rgb, f["cam"], mask, image, start.clone()) for _ in range(args.batch)]
+        tile, tune = cap.autotune_tiles(ctx, [tri] * args.batch, [graph] * args.batch, fr0, prm)
+        log("autotuned vertices_per_tile", tile, tune)
+    tmpl = cap.Template(ctx, tri, graph, tile)
+    frames = [cap.FrameInputs(tmpl, xyz, rgb, f["cam"], mask, image, start.clone()) for _ in range(args.batch)]
     pose = None
     if args.workload == "frame20k" and not args.no_pose:
         # the paper-shaped frame runs both stages: the pose stage on a 5,000-vertex skinned body
@@ -247,7 +254,8 @@ def bench_frame(args, cap, torch):
                         % (args.workload, "pose stage + " if pose is not None else "", f["xyz"].shape[1], nn, W, H,
                            gn, pcg),
             "batch": args.batch,
-            "vertices_per_tile": args.tile or 256,
+            "vertices_per_tile": tile,
+            "autotune_ms": None if tune is None else {str(k): round(v, 3) for k, v in tune.items()},
             "visible_vertices": r0["n_visible"],
             "final_energy": r0["energy"][-1],
             "start_energy": r0["energy"][0],
@@ -272,19 +280,27 @@ def bench_batch(args, cap, torch):
     frames_h = synth.make_batch(n, 0, workers=min(8, len(os.sched_getaffinity(0))))
     gn, pcg, weights = 3, 8, (1.0, 0.1, 10.0)
     ctx = cap.Context(0)
-    frames, starts, graphs = [], [], []
+    prm = cap.params(*weights, gn_iters=gn, pcg_iters=pcg)
+    dev_in = []
     for f in frames_h:
         xyz = torch.from_numpy(f["xyz"]).cuda()
         g = cap.graph_build(ctx, xyz, f["n_nodes"])
-        tmpl = cap.Template(ctx, torch.from_numpy(f["tri"]).cuda(), g, args.tile)
         st = torch.zeros((12, f["n_nodes"]), dtype=torch.float32, device="cuda")
         st[0] = st[4] = st[8] = 1.0
-        frames.append(cap.FrameInputs(tmpl, xyz, torch.from_numpy(f["rgb"]).cuda(), f["cam"],
-                                      torch.from_numpy(f["mask"]).cuda(), torch.from_numpy(f["image"]).cuda(),
-                                      st.clone()))
-        starts.append(st)
-        graphs.append(g)
-    prm = cap.params(*weights, gn_iters=gn, pcg_iters=pcg)
+        dev_in.append((xyz, torch.from_numpy(f["tri"]).cuda(), g, torch.from_numpy(f["rgb"]).cuda(),
+                       torch.from_numpy(f["mask"]).cuda(), torch.from_numpy(f["image"]).cuda(), st))
+
+    def make_frames(tile):
+        return [cap.FrameInputs(cap.Template(ctx, tri, g, tile), xyz, rgb, f["cam"], mask, image, st.clone())
+                for f, (xyz, tri, g, rgb, mask, image, st) in zip(frames_h, dev_in)]
+
+    tile, tune = args.tile, None
+    if tile == 0:       # autotuned tile size for the whole batch (setup, not timed)
+        tile, tune = cap.autotune_tiles(ctx, [d[1] for d in dev_in], [d[2] for d in dev_in], make_frames(0), prm)
+        log("autotuned vertices_per_tile", tile, tune)
+    frames = make_frames(tile)
+    starts = [d[6] for d in dev_in]
+    graphs = [d[2] for d in dev_in]
 
     def step():
         for fr, st in zip(frames, starts):
@@ -344,7 +360,8 @@ def bench_batch(args, cap, torch):
                         "square images (%d vertices, %.1f Mpx in total), %d GN x %d PCG, plain start, one batched "
                         "call per step" % (n, sum(nv), sum(f["cam"].width ** 2 for f in frames_h) / 1e6, gn, pcg),
             "batch": n,
-            "vertices_per_tile": args.tile or 256,
+            "vertices_per_tile": tile,
+            "autotune_ms": None if tune is None else {str(k): round(v, 3) for k, v in tune.items()},
             "final_energy_sum": float(sum(r["energy"][-1] for r in reps)),
             "start_energy_sum": float(sum(r["energy"][0] for r in reps)),
         },

@@ -174,6 +174,18 @@ CAPTURE_API int capture_batch_solve(capture_ctx *ctx, int32_t n, const capture_f
                         const capture_nonrigid_params *params, capture_report *reports,
                         void *workspace, size_t workspace_bytes, void *stream);
 
+/* Tile-size autotuner (setup time, not per frame).  For each candidate
+ * vertices_per_tile it builds the n templates of `descs` with that tile size,
+ * times one batched solve of `frames` (whose tmpl is replaced by the
+ * candidate's) three times after a warm-up, and keeps the fastest; *best
+ * receives that candidate and times_ms (host, n_candidates, may be NULL) the
+ * best time of each.  Every trial starts from the frames' node_state, which is
+ * left unchanged.  Allocates and frees its own device memory; synchronous. */
+CAPTURE_API int capture_autotune_tiles(capture_ctx *ctx, int32_t n, const capture_template_desc *descs,
+                                       const capture_frame *frames, const capture_nonrigid_params *params,
+                                       const int32_t *candidates, int32_t n_candidates, int32_t *best,
+                                       double *times_ms, void *stream);
+
 /* --------------------------------------------------------------------------
  * Stage entry points: the per-frame preprocessing and one linearisation, with
  * their intermediate results, for callers that need them (and for checking).

@@ -14,7 +14,7 @@ from . import capi
 from .capi import CaptureError  # noqa: F401
 
 __all__ = ["Context", "Template", "FrameInputs", "graph_build", "CaptureError", "Body", "PoseInputs",
-           "pose_params", "pose_solve", "pose_linearize"]
+           "pose_params", "pose_solve", "pose_linearize", "autotune_tiles"]
 
 
 def _ptr(t):
@@ -169,6 +169,26 @@ def nonrigid_solve(ctx, frame, prm):
     capi.check(ctx.lib.capture_nonrigid_solve(ctx.h, arr, C.byref(prm), C.byref(rep), _ptr(ws), ws.numel(),
                                               _stream()))
     return _report_dict(rep, prm.gn_iters)
+
+
+def autotune_tiles(ctx, tris, graphs, frames, prm, candidates=(64, 128, 192, 256)):
+    """Pick vertices_per_tile by timing batched solves of `frames` with templates
+    rebuilt from (tri, graph) at each candidate; frames' node states are kept.
+    Returns (best, {candidate: best ms})."""
+    n = len(frames)
+    keep = []
+    descs = (capi.TemplateDesc * n)()
+    for i, (tri, g) in enumerate(zip(tris, graphs)):
+        nv = g["bind_idx"].shape[1]
+        descs[i] = capi.TemplateDesc(nv, tri.shape[1], g["node_vertex"].shape[0], _ptr(tri), _ptr(g["node_vertex"]),
+                                     _ptr(g["bind_idx"]), _ptr(g["bind_w"]), _ptr(g["edge_dst"]), 0)
+        keep.append((tri, g))
+    cand = (C.c_int32 * len(candidates))(*candidates)
+    times = (C.c_double * len(candidates))()
+    best = C.c_int32()
+    capi.check(ctx.lib.capture_autotune_tiles(ctx.h, n, descs, _frames(frames), C.byref(prm), cand, len(candidates),
+                                              C.byref(best), times, _stream()))
+    return best.value, {c: times[k] for k, c in enumerate(candidates)}
 
 
 def frame_decisions(ctx, frame):

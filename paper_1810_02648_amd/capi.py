@@ -104,6 +104,9 @@ SIGNATURES = {
                                      _P, C.c_size_t, _P]),
     "capture_pose_linearize": (C.c_int, [_P, C.POINTER(PoseFrame), C.POINTER(PoseParams), _P,
                                          C.POINTER(C.c_double), _P, _P, C.c_size_t, _P]),
+    "capture_autotune_tiles": (C.c_int, [_P, C.c_int32, C.POINTER(TemplateDesc), C.POINTER(Frame),
+                                         C.POINTER(NonrigidParams), C.POINTER(C.c_int32), C.c_int32,
+                                         C.POINTER(C.c_int32), C.POINTER(C.c_double), _P]),
     "capture_profile_enable": (C.c_int, [_P, C.c_int]),
     "capture_profile_read": (C.c_int, [_P, C.c_char_p, C.POINTER(C.c_double), C.POINTER(C.c_int64)]),
 }

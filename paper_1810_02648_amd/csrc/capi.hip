@@ -1,6 +1,7 @@
 // C ABI entry points: argument checks, workspace layout and the launch
 // sequence of the per-frame solve.
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstring>
 #include <vector>
@@ -333,7 +334,7 @@ int setup(Run &R, capture_ctx *ctx, int n, const capture_frame *frames, const ca
 int launch_frame(Run &R, int gn_iters = 0) {
     const int n = R.n;
     hipStream_t s = R.s;
-    hipLaunchKernelGGL(k_scal_init, dim3(n), dim3(64), 0, s, R.dprobs, gn_iters);
+    hipLaunchKernelGGL(k_scal_init, dim3(n), dim3(256), 0, s, R.dprobs, gn_iters);
     hipLaunchKernelGGL(k_clear_zbuf, dim3(blocks(R.max_hw, 1024), n), dim3(256), 0, s, R.dprobs);
     // Gaussian kernel 3, sigma = 0.3 * ((3 - 1) / 2 - 1) + 0.8 = 0.8, normalised
     const double e1 = std::exp(-1.0 / (2.0 * 0.8 * 0.8));
@@ -561,10 +562,7 @@ int capture_batch_solve(capture_ctx *ctx, int32_t n, const capture_frame *frames
     Run R;
     int rc = setup(R, ctx, n, frames, params, workspace, workspace_bytes, stream);
     if (rc) return rc;
-    for (int i = 0; i < n; ++i)
-        CAP_HIP(hipMemcpyAsync(R.probs[i].state0, frames[i].node_state, sizeof(float) * 12 * R.probs[i].T.nn,
-                               hipMemcpyDeviceToDevice, R.s));
-    if ((rc = launch_frame(R, params->gn_iters))) return rc;
+    if ((rc = launch_frame(R, params->gn_iters))) return rc;      // keeps the start states (k_scal_init)
     if ((rc = launch_solve(R, params))) return rc;
     rc = collect(R, params->gn_iters, reports);
     if (rc) {
@@ -581,6 +579,75 @@ int capture_batch_solve(capture_ctx *ctx, int32_t n, const capture_frame *frames
 int capture_nonrigid_solve(capture_ctx *ctx, const capture_frame *frame, const capture_nonrigid_params *params,
                            capture_report *report, void *workspace, size_t workspace_bytes, void *stream) {
     return capture_batch_solve(ctx, 1, frame, params, report, workspace, workspace_bytes, stream);
+}
+
+int capture_autotune_tiles(capture_ctx *ctx, int32_t n, const capture_template_desc *descs, const capture_frame *frames,
+                           const capture_nonrigid_params *params, const int32_t *candidates, int32_t n_candidates,
+                           int32_t *best, double *times_ms, void *stream) {
+    if (!ctx || !descs || !frames || !params || !candidates || !best) return fail(CAPTURE_EINVAL, "null argument");
+    if (n < 1 || n_candidates < 1) return fail(CAPTURE_EINVAL, "need at least one frame and one candidate");
+    for (int c = 0; c < n_candidates; ++c)
+        if (candidates[c] < 1 || candidates[c] > kMaxTileVerts)
+            return fail(CAPTURE_EUNSUPPORTED, "candidate vertices_per_tile must be in [1, 256]");
+    int rc = check_frames(n, frames);
+    if (rc) return rc;
+    if ((rc = check_params(params))) return rc;
+    CAP_HIP(hipSetDevice(ctx->device));
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    // keep the callers' start states; every trial starts from them
+    size_t state_floats = 0;
+    for (int i = 0; i < n; ++i) state_floats += size_t(12) * frames[i].tmpl->dev.nn;
+    float *saved = nullptr;
+    if (hipMalloc(&saved, sizeof(float) * state_floats) != hipSuccess)
+        return fail(CAPTURE_ENOMEM, "autotune: device allocation failed");
+    auto copy_states = [&](bool save) {
+        size_t off = 0;
+        for (int i = 0; i < n; ++i) {
+            const size_t cnt = size_t(12) * frames[i].tmpl->dev.nn;
+            (void)hipMemcpyAsync(save ? saved + off : frames[i].node_state, save ? frames[i].node_state : saved + off,
+                                 sizeof(float) * cnt, hipMemcpyDeviceToDevice, s);
+            off += cnt;
+        }
+    };
+    copy_states(true);
+    std::vector<capture_report> reps(n);
+    double best_ms = INFINITY;
+    int best_c = -1;
+    for (int c = 0; c < n_candidates && rc == CAPTURE_OK; ++c) {
+        std::vector<capture_template *> tm(n, nullptr);
+        std::vector<capture_frame> fr(frames, frames + n);
+        for (int i = 0; i < n && rc == CAPTURE_OK; ++i) {
+            capture_template_desc d = descs[i];
+            d.vertices_per_tile = candidates[c];
+            rc = build_template(&d, &tm[i], ctx->device);
+            fr[i].tmpl = tm[i];
+        }
+        void *ws = nullptr;
+        size_t bytes = 0;
+        if (rc == CAPTURE_OK) {
+            bytes = plan_workspace(n, fr.data(), nullptr, nullptr).bytes;
+            if (hipMalloc(&ws, bytes) != hipSuccess) rc = fail(CAPTURE_ENOMEM, "autotune: device allocation failed");
+        }
+        double t_min = INFINITY;
+        for (int rep = 0; rep < 4 && rc == CAPTURE_OK; ++rep) {       // one warm-up, three timed
+            copy_states(false);
+            if (hipStreamSynchronize(s) != hipSuccess) { rc = fail(CAPTURE_EHIP, "autotune: stream error"); break; }
+            const auto t0 = std::chrono::steady_clock::now();
+            rc = capture_batch_solve(ctx, n, fr.data(), params, reps.data(), ws, bytes, stream);
+            const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+            if (rep > 0) t_min = std::min(t_min, ms);
+        }
+        if (times_ms) times_ms[c] = t_min;
+        if (rc == CAPTURE_OK && t_min < best_ms) { best_ms = t_min; best_c = candidates[c]; }
+        if (ws) (void)hipFree(ws);
+        for (capture_template *t : tm) capture_template_destroy(t);
+    }
+    copy_states(false);
+    (void)hipStreamSynchronize(s);
+    (void)hipFree(saved);
+    if (rc) return rc;
+    *best = best_c;
+    return CAPTURE_OK;
 }
 
 int capture_frame_decisions(capture_ctx *ctx, const capture_frame *frame, float *dt, float *blurred, uint32_t *zbuf,
@@ -817,8 +884,7 @@ int capture_nonrigid_solve_warm(capture_ctx *ctx, const capture_frame *frame, co
     CAP_HIP(hipMemcpyAsync(R.dprobs, R.probs.data(), sizeof(ProbDev), hipMemcpyHostToDevice, R.s));
     const ProbDev &pr = R.probs[0];
     const int pred_slot = CAPTURE_MAX_GN + 1;
-    CAP_HIP(hipMemcpyAsync(pr.state0, frame->node_state, sizeof(float) * 12 * pr.T.nn, hipMemcpyDeviceToDevice, R.s));
-    if ((rc = launch_frame(R, params->gn_iters))) return rc;
+    if ((rc = launch_frame(R, params->gn_iters))) return rc;     // keeps the given state in state0
     // linearisation at the previous frame's state: features and E(x_{t-1})
     launch_linearize(R, 0, 0);
     timed(R, K_WS_FEAT, [&] {

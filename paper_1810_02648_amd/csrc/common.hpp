@@ -61,6 +61,8 @@ struct TemplateDev {
     const int *node_pbeg;      // [nn+1] into node_pidx
     const int *node_pidx;      // global slot indices of each node, tile order (node-major positions)
     const int *slot_dest;      // [nslots] node-major position of each slot's partial
+    const uint16_t *plan_cpos; // [4][nv] tile-local position of each vertex contribution in slot order
+    const uint32_t *owned_cpos;// [8][nn] positions of an owned edge's two contributions (lo: source, hi: target)
     const int *vf_beg;         // [nv+1] vertex -> incident faces
     const int *vf_face;        // [3nf] ascending per vertex
     const int *medge;          // [4][nmedges]: a, b, f0, f1 (-1 = border)
@@ -166,7 +168,9 @@ struct PoseDev {
     double *pose0;                   // [nu] start pose (restored on a device-detected error)
     int *blist;                      // [nv] contour set: (vertex << 1) | (b_i == -1), ascending
     int *nb;                         // [1] |B|
-    double *rows;                    // [max_rows][np] Jacobian rows, column nu holds b*F
+    double *rows;                    // [np][ldr] Jacobian, column-major (row r, column c at c * ldr + r);
+                                     // column nu holds b*F
+    int ldr;                         // max_rows rounded up to 64
     double *epart;                   // [row blocks][4] energy partials: 2D, 3D, sil, sil with |b|
     double *energy;                  // [MAX_GN + 1][4]
     double *sys;                     // [nu][nu + 1] system of the current step (J^T J | -J^T B F), undamped

@@ -180,7 +180,8 @@ int build_template(const capture_template_desc *d, capture_template **out, int d
 
     std::vector<int> plan_vid, plan_pos(nv), tile_vbeg(1, 0), tile_sbeg(1, 0), slot_node, tile_obeg(1, 0),
         owned_node, list_beg(1, 0), node_pbeg(nn + 1, 0);
-    std::vector<uint32_t> plan_slot;
+    std::vector<uint32_t> plan_slot, owned_cpos_t;
+    std::vector<uint16_t> plan_cpos_t;       // [nv][4] in plan order
     std::vector<uint8_t> owned_slot, owned_eslot_t;
     std::vector<uint16_t> list_idx;
     std::vector<std::vector<int>> node_parts(nn);
@@ -220,13 +221,26 @@ int build_template(const capture_template_desc *d, capture_template **out, int d
                 }
             }
         }
+        // position of every contribution in the slot-sorted order (lists concatenated)
+        std::vector<int> cpos(size_t(4) * nvt + size_t(16) * t.owned.size(), 0xffff);
+        const int l0 = int(list_idx.size());
         for (int s = 0; s < ns; ++s) {
             std::sort(lists[s].begin(), lists[s].end());
-            for (int c : lists[s]) list_idx.push_back(uint16_t(c));
+            for (int c : lists[s]) {
+                cpos[c] = int(list_idx.size()) - l0;
+                list_idx.push_back(uint16_t(c));
+            }
             list_beg.push_back(int(list_idx.size()));
             node_parts[t.slots[s]].push_back(int(slot_node.size()));
             slot_node.push_back(t.slots[s]);
         }
+        for (int lv = 0; lv < nvt; ++lv)
+            for (int j = 0; j < 4; ++j) plan_cpos_t.push_back(uint16_t(cpos[lv * 4 + j]));
+        for (size_t o = 0; o < t.owned.size(); ++o)
+            for (int e = 0; e < 8; ++e) {
+                const int c = 4 * nvt + int(o * 8 + e) * 2;
+                owned_cpos_t.push_back(uint32_t(cpos[c]) | (uint32_t(cpos[c + 1]) << 16));
+            }
         tile_vbeg.push_back(int(plan_vid.size()));
         tile_sbeg.push_back(int(slot_node.size()));
         tile_obeg.push_back(int(owned_node.size()));
@@ -238,6 +252,13 @@ int build_template(const capture_template_desc *d, capture_template **out, int d
     std::vector<uint8_t> owned_eslot(size_t(8) * nn);
     for (int o = 0; o < nn; ++o)
         for (int e = 0; e < 8; ++e) owned_eslot[size_t(e) * nn + o] = owned_eslot_t[size_t(o) * 8 + e];
+    // the same transposed to [4][nv] and [8][nn] for coalesced loads
+    std::vector<uint16_t> plan_cpos(size_t(4) * nv);
+    std::vector<uint32_t> owned_cpos(size_t(8) * nn);
+    for (int q = 0; q < nv; ++q)
+        for (int j = 0; j < 4; ++j) plan_cpos[size_t(j) * nv + q] = plan_cpos_t[size_t(q) * 4 + j];
+    for (int o = 0; o < nn; ++o)
+        for (int e = 0; e < 8; ++e) owned_cpos[size_t(e) * nn + o] = owned_cpos_t[size_t(o) * 8 + e];
     std::vector<int> node_pidx, slot_dest(slot_node.size());
     for (int k = 0; k < nn; ++k) {
         for (int p : node_parts[k]) {
@@ -274,7 +295,7 @@ int build_template(const capture_template_desc *d, capture_template **out, int d
            o_lb = blob.add(list_beg), o_li = blob.add(list_idx), o_npb = blob.add(node_pbeg),
            o_npi = blob.add(node_pidx), o_vfb = blob.add(vf_beg), o_vff = blob.add(vf_face),
            o_me = blob.add(medge), o_ib = blob.add(in_beg), o_is = blob.add(in_src), o_oc = blob.add(out_cnt),
-           o_sd = blob.add(slot_dest);
+           o_sd = blob.add(slot_dest), o_pcp = blob.add(plan_cpos), o_ocp = blob.add(owned_cpos);
     void *mem = nullptr;
     hipError_t e = hipMalloc(&mem, blob.bytes.size());
     if (e != hipSuccess) return fail(CAPTURE_ENOMEM, "template: device allocation failed");
@@ -297,6 +318,8 @@ int build_template(const capture_template_desc *d, capture_template **out, int d
     D.node_pbeg = (const int *)at(o_npb); D.node_pidx = (const int *)at(o_npi);
     D.vf_beg = (const int *)at(o_vfb); D.vf_face = (const int *)at(o_vff); D.medge = (const int *)at(o_me);
     D.slot_dest = (const int *)at(o_sd);
+    D.plan_cpos = (const uint16_t *)at(o_pcp);
+    D.owned_cpos = (const uint32_t *)at(o_ocp);
     D.in_beg = (const int *)at(o_ib); D.in_src = (const int *)at(o_is); D.out_cnt = (const int *)at(o_oc);
     t->mem = mem;
     t->bytes = blob.bytes.size();

@@ -71,7 +71,8 @@ size_t carve_pose(uint8_t *base, const capture_pose_frame &f, ProbDev &pr, PoseD
     pd.pose0 = L.take<double>(base, B.nu);
     pd.blist = L.take<int>(base, nv);
     pd.nb = L.take<int>(base, 1);
-    pd.rows = L.take<double>(base, size_t(max_rows) * B.np);
+    pd.ldr = (max_rows + 63) & ~63;
+    pd.rows = L.take<double>(base, size_t(pd.ldr) * B.np);
     pd.epart = L.take<double>(base, size_t(blocks(max_rows, kPoseRowThreads)) * 4);
     pd.energy = L.take<double>(base, size_t(CAPTURE_MAX_GN + 1) * 4);
     pd.sys = L.take<double>(base, size_t(B.nu) * (B.nu + 1));

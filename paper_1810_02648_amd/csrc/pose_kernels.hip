@@ -220,7 +220,7 @@ __device__ inline double sample_cubic_f64(const float *__restrict__ img, int W, 
 // Row entries of g . dY/dtheta for the rotating joints in `mask`, with
 // dsum(k) = sum over carried points of weight * (y - p_k).  Written for every
 // unknown column of the row (zeros elsewhere) except t, t' and the F column.
-__device__ inline void rotation_entries(const BodyDev &B, double *row, const double g[3], const double *sp,
+__device__ inline void rotation_entries(const BodyDev &B, double *row, size_t ld, const double g[3], const double *sp,
                                         const double *sA, const double (*ys)[3], const double *ws,
                                         const uint32_t *masks, int npts) {
     for (int k = 0; k < B.nj; ++k) {
@@ -234,12 +234,12 @@ __device__ inline void rotation_entries(const BodyDev &B, double *row, const dou
                 for (int a = 0; a < 3; ++a) d[a] += ws[s] * (ys[s][a] - sp[3 * k + a]);
             }
         if (!any) {
-            row[c] = row[c + 1] = row[c + 2] = 0.0;
+            row[c * ld] = row[(c + 1) * ld] = row[(c + 2) * ld] = 0.0;
             continue;
         }
         const double e[3] = {d[1] * g[2] - d[2] * g[1], d[2] * g[0] - d[0] * g[2], d[0] * g[1] - d[1] * g[0]};
         const double *A = sA + 9 * k;
-        for (int cc = 0; cc < 3; ++cc) row[c + cc] = (e[0] * A[cc] + e[1] * A[3 + cc]) + e[2] * A[6 + cc];
+        for (int cc = 0; cc < 3; ++cc) row[(c + cc) * ld] = (e[0] * A[cc] + e[1] * A[3 + cc]) + e[2] * A[6 + cc];
     }
 }
 
@@ -258,11 +258,12 @@ __global__ __launch_bounds__(kPoseRowThreads) void k_pose_rows(const PoseDev *__
     for (int e = threadIdx.x; e < 3 * B.nj; e += blockDim.x) sp[e] = P.jp[e];
     __syncthreads();
     const int nj = B.nj, nu = B.nu, np_ = B.np;
+    const size_t ldr = P.ldr;
     const int M = 5 * nj + P.nb[0];
     const int r = blockIdx.x * blockDim.x + threadIdx.x;
     double en[4] = {0.0, 0.0, 0.0, 0.0};
     if (r < M) {
-        double *row = P.rows + size_t(r) * np_;
+        double *row = P.rows + r;      // column-major: entry c at row[c * ldr]
         double g[3], F;
         double ys[4][3], ws[4];
         uint32_t masks[4];
@@ -333,14 +334,14 @@ __global__ __launch_bounds__(kPoseRowThreads) void k_pose_rows(const PoseDev *__
             en[3] = rr * rr;
         }
         if (!energy_only) {
-            rotation_entries(B, row, g, sp, sA, ys, ws, masks, npts);
+            rotation_entries(B, row, ldr, g, sp, sA, ys, ws, masks, npts);
             for (int a = 0; a < 3; ++a) {
-                row[B.it + a] = tw * g[a];
-                row[B.itp + a] = 0.0;
+                row[(B.it + a) * ldr] = tw * g[a];
+                row[(B.itp + a) * ldr] = 0.0;
             }
-            if (has_tp) row[B.itp + tpc] = -P.s3d;
-            row[nu] = F;
-            for (int c = nu + 1; c < np_; ++c) row[c] = 0.0;
+            if (has_tp) row[(B.itp + tpc) * ldr] = -P.s3d;
+            row[nu * ldr] = F;
+            for (int c = nu + 1; c < np_; ++c) row[c * ldr] = 0.0;
         }
     }
     for (int q = 0; q < 4; ++q) {
@@ -371,16 +372,16 @@ __global__ __launch_bounds__(64 * kJtjWaves) void k_pose_jtj(const PoseDev *__re
     const int M = 5 * P.B.nj + P.nb[0];
     const int wv = threadIdx.x >> 6, l = threadIdx.x & 63, li = l & 15, lk = l >> 4;
     dbl4 acc = {0.0, 0.0, 0.0, 0.0};
-    const double *col_a = P.rows + I * kPoseTile + li;
-    const double *col_b = P.rows + Jt * kPoseTile + li;
+    const double *col_a = P.rows + size_t(I * kPoseTile + li) * P.ldr;     // column-major rows
+    const double *col_b = P.rows + size_t(Jt * kPoseTile + li) * P.ldr;
     constexpr int span = 4 * kJtjBatch;
     for (int r0 = wv * span; r0 < M; r0 += kJtjWaves * span) {
         double a[kJtjBatch], bb[kJtjBatch];
 #pragma unroll
         for (int u = 0; u < kJtjBatch; ++u) {
             const int r = r0 + 4 * u + lk;
-            a[u] = r < M ? col_a[size_t(r) * np_] : 0.0;
-            bb[u] = r < M ? col_b[size_t(r) * np_] : 0.0;
+            a[u] = r < M ? col_a[r] : 0.0;
+            bb[u] = r < M ? col_b[r] : 0.0;
         }
 #pragma unroll
         for (int u = 0; u < kJtjBatch; ++u) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u], bb[u], acc, 0, 0, 0);
@@ -462,9 +463,12 @@ __global__ __launch_bounds__(64) void k_pose_step(const PoseDev *__restrict__ PP
         if (t == 0) A[k * lda + k] = ukk;
         for (int j = k + 1 + t; j < nu; j += 64) A[k * lda + j] /= ukk;
         __syncthreads();
-        for (int i = k + 1; i < nu; ++i) {
-            const double uki = A[k * lda + i];
-            for (int j = i + t; j < nu; j += 64) A[i * lda + j] -= uki * A[k * lda + j];
+        // trailing update by columns: lane j runs down its own column, so the
+        // rows' updates are independent loads and stores, not a serial chain
+        for (int j = k + 1 + t; j < nu; j += 64) {
+            const double ukj = A[k * lda + j];
+#pragma unroll 4
+            for (int i = k + 1; i <= j; ++i) A[i * lda + j] -= A[k * lda + i] * ukj;
         }
         __syncthreads();
     }

@@ -44,11 +44,20 @@ __device__ inline void load_slots(const ProbDev &pr, int sb, int ns, TileLds &L,
     }
 }
 
-// The tile's contribution lists (contiguous in list_idx) and slot offsets, into LDS.
-__device__ inline void load_lists(const TemplateDev &T, int sb, int ns, uint16_t *lidx, int *lbeg) {
-    const int l0 = T.list_beg[sb], l1 = T.list_beg[sb + ns];
-    for (int q = threadIdx.x; q < l1 - l0; q += blockDim.x) lidx[q] = T.list_idx[l0 + q];
+// Slot offsets of the tile's contributions in slot order, into LDS.  The
+// contributions are stored component-major, C[comp][position], where each
+// vertex binding and regulariser edge end has a fixed position (plan_cpos,
+// owned_cpos) inside its slot's contiguous range, in ascending contribution
+// order; every slot sum therefore reads one contiguous run, in a fixed order.
+__device__ inline void load_offsets(const TemplateDev &T, int sb, int ns, int *lbeg) {
+    const int l0 = T.list_beg[sb];
     for (int s = threadIdx.x; s <= ns; s += blockDim.x) lbeg[s] = T.list_beg[sb + s] - l0;
+}
+
+__device__ inline float run_sum(const float *__restrict__ c, int b, int e) {
+    float acc = 0.0f;
+    for (int q = b; q < e; ++q) acc += c[q];
+    return acc;
 }
 
 __device__ inline void rot_apply(const float *R, const float d[3], float q[3]) {
@@ -66,7 +75,6 @@ __device__ inline void rot_apply(const float *R, const float d[3], float q[3]) {
 __global__ __launch_bounds__(kTileThreads) void k_linearize(const ProbDev *__restrict__ P, int mode) {
     extern __shared__ float lds[];
     __shared__ double red[kTileThreads / 64];
-    __shared__ uint16_t lidx[kMaxTileContrib];
     __shared__ int lbeg[kMaxTileSlots + 1];
     const ProbDev &pr = P[blockIdx.y];
     const TemplateDev &T = pr.T;
@@ -78,8 +86,9 @@ __global__ __launch_bounds__(kTileThreads) void k_linearize(const ProbDev *__res
     const int ob = T.tile_obeg[tile], nown = T.tile_obeg[tile + 1] - ob;
     TileLds L = tile_lds(lds, ns, 12);
     load_slots(pr, sb, ns, L, false);
-    if (mode == 0) load_lists(T, sb, ns, lidx, lbeg);
+    if (mode == 0) load_offsets(T, sb, ns, lbeg);
     __syncthreads();
+    const int NC = mode == 0 ? lbeg[ns] : 0;
 
     double e_ph = 0.0, e_s = 0.0, e_sa = 0.0, e_a = 0.0, e_v = 0.0;
     const int lv = threadIdx.x;
@@ -168,18 +177,18 @@ __global__ __launch_bounds__(kTileThreads) void k_linearize(const ProbDev *__res
             // contributions to the 4 bound nodes: rhs -w[q x g; g], diag w^2[diag(Q^T H Q); diag(H)]
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
-                float *c = L.c + 12 * (4 * lv + j);
+                float *c = L.c + T.plan_cpos[size_t(j) * nv + p];
                 const float *qq = q[j];
                 const float ww = w[j], w2 = w[j] * w[j];
                 float qxg[3];
                 cross3(qq, gi, qxg);
-                c[0] = -ww * qxg[0]; c[1] = -ww * qxg[1]; c[2] = -ww * qxg[2];
-                c[3] = -ww * gi[0]; c[4] = -ww * gi[1]; c[5] = -ww * gi[2];
+                c[0] = -ww * qxg[0]; c[NC] = -ww * qxg[1]; c[2 * NC] = -ww * qxg[2];
+                c[3 * NC] = -ww * gi[0]; c[4 * NC] = -ww * gi[1]; c[5 * NC] = -ww * gi[2];
                 const float xx = Hm[0], xy = Hm[1], xz = Hm[2], yy = Hm[3], yz = Hm[4], zz = Hm[5];
-                c[6] = w2 * ((qq[2] * qq[2] * yy - 2.0f * qq[2] * qq[1] * yz) + qq[1] * qq[1] * zz);
-                c[7] = w2 * ((qq[2] * qq[2] * xx - 2.0f * qq[2] * qq[0] * xz) + qq[0] * qq[0] * zz);
-                c[8] = w2 * ((qq[1] * qq[1] * xx - 2.0f * qq[1] * qq[0] * xy) + qq[0] * qq[0] * yy);
-                c[9] = w2 * xx; c[10] = w2 * yy; c[11] = w2 * zz;
+                c[6 * NC] = w2 * ((qq[2] * qq[2] * yy - 2.0f * qq[2] * qq[1] * yz) + qq[1] * qq[1] * zz);
+                c[7 * NC] = w2 * ((qq[2] * qq[2] * xx - 2.0f * qq[2] * qq[0] * xz) + qq[0] * qq[0] * zz);
+                c[8 * NC] = w2 * ((qq[1] * qq[1] * xx - 2.0f * qq[1] * qq[0] * xy) + qq[0] * qq[0] * yy);
+                c[9 * NC] = w2 * xx; c[10 * NC] = w2 * yy; c[11 * NC] = w2 * zz;
             }
         }
     }
@@ -188,13 +197,9 @@ __global__ __launch_bounds__(kTileThreads) void k_linearize(const ProbDev *__res
         const int o = idx >> 3, e = idx & 7;
         const int so = T.owned_slot[ob + o];
         const int se = T.owned_eslot[size_t(e) * nn + ob + o];
-        float *c0 = L.c + 12 * (4 * nvt + 2 * idx);
-        float *c1 = c0 + 12;
-        if (se == 255) {
-            if (mode == 0)
-                for (int q12 = 0; q12 < 12; ++q12) { c0[q12] = 0.0f; c1[q12] = 0.0f; }
-            continue;
-        }
+        if (se == 255) continue;
+        const uint32_t cp = T.owned_cpos[size_t(e) * nn + ob + o];
+        float *c0 = L.c + (cp & 0xffffu), *c1 = L.c + (cp >> 16);
         const float *gk = L.g + 3 * so, *gl = L.g + 3 * se;
         float d[3] = {gl[0] - gk[0], gl[1] - gk[1], gl[2] - gk[2]};
         float ekl[3];
@@ -213,26 +218,23 @@ __global__ __launch_bounds__(kTileThreads) void k_linearize(const ProbDev *__res
             float exr[3];
             cross3(ekl, r, exr);
             const float s = pr.sw_arap, wa = pr.w_arap;
-            c0[0] = -s * exr[0]; c0[1] = -s * exr[1]; c0[2] = -s * exr[2];
-            c0[3] = -s * r[0]; c0[4] = -s * r[1]; c0[5] = -s * r[2];
-            c0[6] = wa * (ekl[1] * ekl[1] + ekl[2] * ekl[2]);
-            c0[7] = wa * (ekl[0] * ekl[0] + ekl[2] * ekl[2]);
-            c0[8] = wa * (ekl[0] * ekl[0] + ekl[1] * ekl[1]);
-            c0[9] = wa; c0[10] = wa; c0[11] = wa;
-            c1[0] = 0.0f; c1[1] = 0.0f; c1[2] = 0.0f;
-            c1[3] = s * r[0]; c1[4] = s * r[1]; c1[5] = s * r[2];
-            c1[6] = 0.0f; c1[7] = 0.0f; c1[8] = 0.0f;
-            c1[9] = wa; c1[10] = wa; c1[11] = wa;
+            c0[0] = -s * exr[0]; c0[NC] = -s * exr[1]; c0[2 * NC] = -s * exr[2];
+            c0[3 * NC] = -s * r[0]; c0[4 * NC] = -s * r[1]; c0[5 * NC] = -s * r[2];
+            c0[6 * NC] = wa * (ekl[1] * ekl[1] + ekl[2] * ekl[2]);
+            c0[7 * NC] = wa * (ekl[0] * ekl[0] + ekl[2] * ekl[2]);
+            c0[8 * NC] = wa * (ekl[0] * ekl[0] + ekl[1] * ekl[1]);
+            c0[9 * NC] = wa; c0[10 * NC] = wa; c0[11 * NC] = wa;
+            c1[0] = 0.0f; c1[NC] = 0.0f; c1[2 * NC] = 0.0f;
+            c1[3 * NC] = s * r[0]; c1[4 * NC] = s * r[1]; c1[5 * NC] = s * r[2];
+            c1[6 * NC] = 0.0f; c1[7 * NC] = 0.0f; c1[8 * NC] = 0.0f;
+            c1[9 * NC] = wa; c1[10 * NC] = wa; c1[11 * NC] = wa;
         }
     }
     __syncthreads();
     if (mode == 0) {
         for (int pair = threadIdx.x; pair < ns * 12; pair += blockDim.x) {
             const int s = pair / 12, comp = pair - s * 12;
-            const int lb = lbeg[s], le = lbeg[s + 1];
-            float acc = 0.0f;
-            for (int q = lb; q < le; ++q) acc += L.c[12 * lidx[q] + comp];
-            pr.partial[size_t(T.slot_dest[sb + s]) * 12 + comp] = acc;
+            pr.partial[size_t(T.slot_dest[sb + s]) * 12 + comp] = run_sum(L.c + comp * NC, lbeg[s], lbeg[s + 1]);
         }
     }
     double s0 = block_sum<kTileThreads>(e_ph, red);
@@ -253,17 +255,35 @@ __global__ __launch_bounds__(kTileThreads) void k_linearize(const ProbDev *__res
 // ----------------------------------------------------------------------------
 __global__ __launch_bounds__(kTileThreads) void k_apply(const ProbDev *__restrict__ P) {
     extern __shared__ float lds[];
-    __shared__ uint16_t lidx[kMaxTileContrib];
     __shared__ int lbeg[kMaxTileSlots + 1];
     const ProbDev &pr = P[blockIdx.y];
-    if (pr.scal[1] != 0.0) return;
     const TemplateDev &T = pr.T;
     const int tile = blockIdx.x;
-    if (tile >= T.ntiles) return;
+    if (tile >= T.ntiles || pr.scal[1] != 0.0) return;
     const int nv = T.nv, nn = T.nn;
     const int vb = T.tile_vbeg[tile], nvt = T.tile_vbeg[tile + 1] - vb;
     const int sb = T.tile_sbeg[tile], ns = T.tile_sbeg[tile + 1] - sb;
     const int ob = T.tile_obeg[tile], nown = T.tile_obeg[tile + 1] - ob;
+    // the vertex's own inputs first, so their loads overlap the slot loads
+    const int lv = threadIdx.x, p = vb + lv;
+    const bool has_v = lv < nvt;
+    bool act = false;
+    uint32_t packed = 0;
+    int cp[4] = {0, 0, 0, 0};
+    float v[3] = {0, 0, 0}, w[4] = {0, 0, 0, 0}, Hm[6] = {0, 0, 0, 0, 0, 0};
+    if (has_v) {
+        act = (pr.vcode[p] & 11) != 0;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) cp[j] = T.plan_cpos[size_t(j) * nv + p];
+        if (act) {
+            packed = T.plan_slot[p];
+            v[0] = pr.px[p]; v[1] = pr.px[nv + p]; v[2] = pr.px[2 * nv + p];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) w[j] = T.plan_w[size_t(j) * nv + p];
+#pragma unroll
+            for (int q6 = 0; q6 < 6; ++q6) Hm[q6] = pr.Hm[size_t(q6) * nv + p];
+        }
+    }
     TileLds L = tile_lds(lds, ns, 6);
     for (int it = threadIdx.x; it < ns * 18; it += blockDim.x) {   // packed per-slot R, g and p
         const int s = it / 18, q = it - s * 18;
@@ -271,34 +291,26 @@ __global__ __launch_bounds__(kTileThreads) void k_apply(const ProbDev *__restric
         else if (q < 12) L.g[3 * s + q - 9] = pr.spack[size_t(sb + s) * 12 + q];
         else L.p[6 * s + q - 12] = pr.pslot[size_t(sb + s) * 6 + q - 12];
     }
-    load_lists(T, sb, ns, lidx, lbeg);
+    load_offsets(T, sb, ns, lbeg);
     __syncthreads();
-    const int lv = threadIdx.x;
-    if (lv < nvt) {
-        const int p = vb + lv;
-        float *c = L.c + 24 * lv;
-        if (pr.vcode[p] & 11) {
-            const uint32_t packed = T.plan_slot[p];
-            const float v[3] = {pr.px[p], pr.px[nv + p], pr.px[2 * nv + p]};
-            float q[4][3], w[4];
-            int sl[4];
+    const int NC = lbeg[ns];
+    float *C = L.c;     // [6][NC]
+    if (has_v) {
+        if (act) {
+            float q[4][3];
             float dV[3] = {0, 0, 0};
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
-                sl[j] = (packed >> (8 * j)) & 0xff;
-                w[j] = T.plan_w[size_t(j) * nv + p];
-                const float *g = L.g + 3 * sl[j];
+                const int sl = (packed >> (8 * j)) & 0xff;
+                const float *g = L.g + 3 * sl;
                 float d[3] = {v[0] - g[0], v[1] - g[1], v[2] - g[2]};
-                rot_apply(L.R + 9 * sl[j], d, q[j]);
-                const float *pp = L.p + 6 * sl[j];
+                rot_apply(L.R + 9 * sl, d, q[j]);
+                const float *pp = L.p + 6 * sl;
                 float oxq[3];
                 cross3(pp, q[j], oxq);
 #pragma unroll
                 for (int a = 0; a < 3; ++a) dV[a] += w[j] * (oxq[a] + pp[3 + a]);
             }
-            float Hm[6];
-#pragma unroll
-            for (int q6 = 0; q6 < 6; ++q6) Hm[q6] = pr.Hm[size_t(q6) * nv + p];
             const float f[3] = {(Hm[0] * dV[0] + Hm[1] * dV[1]) + Hm[2] * dV[2],
                                 (Hm[1] * dV[0] + Hm[3] * dV[1]) + Hm[4] * dV[2],
                                 (Hm[2] * dV[0] + Hm[4] * dV[1]) + Hm[5] * dV[2]};
@@ -306,24 +318,23 @@ __global__ __launch_bounds__(kTileThreads) void k_apply(const ProbDev *__restric
             for (int j = 0; j < 4; ++j) {
                 float qxf[3];
                 cross3(q[j], f, qxf);
-                float *cj = c + 6 * j;
-                cj[0] = w[j] * qxf[0]; cj[1] = w[j] * qxf[1]; cj[2] = w[j] * qxf[2];
-                cj[3] = w[j] * f[0]; cj[4] = w[j] * f[1]; cj[5] = w[j] * f[2];
+                float *cj = C + cp[j];
+                cj[0] = w[j] * qxf[0]; cj[NC] = w[j] * qxf[1]; cj[2 * NC] = w[j] * qxf[2];
+                cj[3 * NC] = w[j] * f[0]; cj[4 * NC] = w[j] * f[1]; cj[5 * NC] = w[j] * f[2];
             }
         } else {
-            for (int q = 0; q < 24; ++q) c[q] = 0.0f;
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                for (int q6 = 0; q6 < 6; ++q6) C[q6 * NC + cp[j]] = 0.0f;
         }
     }
     for (int idx = threadIdx.x; idx < nown * 8; idx += blockDim.x) {
         const int o = idx >> 3, e = idx & 7;
         const int so = T.owned_slot[ob + o];
         const int se = T.owned_eslot[size_t(e) * nn + ob + o];
-        float *c0 = L.c + 6 * (4 * nvt + 2 * idx);
-        float *c1 = c0 + 6;
-        if (se == 255) {
-            for (int q = 0; q < 6; ++q) { c0[q] = 0.0f; c1[q] = 0.0f; }
-            continue;
-        }
+        if (se == 255) continue;
+        const uint32_t cpe = T.owned_cpos[size_t(e) * nn + ob + o];
+        float *c0 = C + (cpe & 0xffffu), *c1 = C + (cpe >> 16);
         const float *gk = L.g + 3 * so, *gl = L.g + 3 * se;
         float d[3] = {gl[0] - gk[0], gl[1] - gk[1], gl[2] - gk[2]};
         float ekl[3];
@@ -335,18 +346,15 @@ __global__ __launch_bounds__(kTileThreads) void k_apply(const ProbDev *__restric
         float exu[3];
         cross3(ekl, u, exu);
         const float wa = pr.w_arap;
-        c0[0] = wa * exu[0]; c0[1] = wa * exu[1]; c0[2] = wa * exu[2];
-        c0[3] = wa * u[0]; c0[4] = wa * u[1]; c0[5] = wa * u[2];
-        c1[0] = 0.0f; c1[1] = 0.0f; c1[2] = 0.0f;
-        c1[3] = -wa * u[0]; c1[4] = -wa * u[1]; c1[5] = -wa * u[2];
+        c0[0] = wa * exu[0]; c0[NC] = wa * exu[1]; c0[2 * NC] = wa * exu[2];
+        c0[3 * NC] = wa * u[0]; c0[4 * NC] = wa * u[1]; c0[5 * NC] = wa * u[2];
+        c1[0] = 0.0f; c1[NC] = 0.0f; c1[2 * NC] = 0.0f;
+        c1[3 * NC] = -wa * u[0]; c1[4 * NC] = -wa * u[1]; c1[5 * NC] = -wa * u[2];
     }
     __syncthreads();
     for (int pair = threadIdx.x; pair < ns * 6; pair += blockDim.x) {
         const int s = pair / 6, comp = pair - s * 6;
-        const int lb = lbeg[s], le = lbeg[s + 1];
-        float acc = 0.0f;
-        for (int q = lb; q < le; ++q) acc += L.c[6 * lidx[q] + comp];
-        pr.partial[size_t(T.slot_dest[sb + s]) * 6 + comp] = acc;
+        pr.partial[size_t(T.slot_dest[sb + s]) * 6 + comp] = run_sum(C + comp * NC, lbeg[s], lbeg[s + 1]);
     }
 }
 
@@ -413,11 +421,14 @@ __global__ __launch_bounds__(kNodeThreads) void k_node_init(const ProbDev *__res
 }
 
 // Per-problem scalars at the start of a solve: nothing stopped, GN count = K;
-// visible / contour / large-face counters cleared.
+// visible / contour / large-face counters cleared; the start state kept
+// (restored on a device-detected error).
 __global__ void k_scal_init(const ProbDev *__restrict__ P, int gn_iters) {
     const ProbDev &pr = P[blockIdx.x];
     for (int i = threadIdx.x; i < kScalars; i += blockDim.x) pr.scal[i] = i == 3 ? double(gn_iters) : 0.0;
     if (threadIdx.x < 3) pr.counts[threadIdx.x] = 0;
+    const int n12 = 12 * pr.T.nn;
+    for (int i = threadIdx.x; i < n12; i += blockDim.x) pr.state0[i] = pr.state[i];
 }
 
 // Empty depth buffers of every problem (4 pixels per thread).

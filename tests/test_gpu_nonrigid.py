@@ -266,3 +266,29 @@ def test_invalid_arguments_are_rejected(ctx, frames):
     assert torch.equal(before, fr.node_state)
     with pytest.raises(cap.CaptureError):
         cap.graph_build(ctx, fr.xyz, 3)
+
+
+def test_tile_size_autotuner_and_tile_independence(ctx, frames):
+    """The autotuner returns one of its candidates and leaves the start states
+    alone; every tile size reproduces the oracle within the parity bar."""
+    import paper_1810_02648_amd as cap
+    from gpu_util import dev, device_graph, make_frame
+    f = frames["mid"]
+    g = og.build_graph(f["xyz"], 203)
+    P = onr.Problem(f["xyz"], f["tri"], f["rgb"], g, f["cam"], f["mask"], f["image"], f["weights"])
+    ref = onr.solve(P, 3, "pcg", 8)
+    prm = cap.params(*f["weights"], gn_iters=3, pcg_iters=8)
+    fr = make_frame(ctx, f, g)
+    start = fr.node_state.clone()
+    best, times = cap.autotune_tiles(ctx, [dev(f["tri"])], [device_graph(g)], [fr], prm, candidates=(64, 160, 256))
+    print("autotune", best, times, flush=True)
+    assert best in (64, 160, 256) and all(t > 0 for t in times.values())
+    assert torch.equal(fr.node_state, start)
+    r_ref, t_ref = params_of(ref["state"])
+    for tile in (64, 160, 256):
+        fr = make_frame(ctx, f, g, vertices_per_tile=tile)
+        rep = cap.nonrigid_solve(ctx, fr, prm)
+        r_gpu, t_gpu = params_of(fr.node_state.cpu().numpy())
+        assert np.linalg.norm(r_gpu - r_ref) <= 1e-4 * max(np.linalg.norm(r_ref), 1e-6), tile
+        assert np.linalg.norm(t_gpu - t_ref) <= 1e-4 * max(np.linalg.norm(t_ref), 1e-6), tile
+        assert abs(rep["energy"][-1] - ref["energies"][-1]["total"]) <= 1e-5 * ref["energies"][0]["total"]
