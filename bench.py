@@ -214,9 +214,13 @@ def bench_frame(args, cap, torch):
             fr.node_state.copy_(start)
         return cap.batch_solve(ctx, frames, prm)
 
-    for _ in range(args.warmup):
+    # warm-up: the given steps, and at least half a second so the clocks settle
+    tw = time.perf_counter()
+    k = 0
+    while k < args.warmup or time.perf_counter() - tw < 0.5:
         reps = step()
-    torch.cuda.synchronize()
+        torch.cuda.synchronize()
+        k += 1
     log("timing", args.steps, "steps")
     t0 = time.perf_counter()
     for _ in range(args.steps):
@@ -307,9 +311,13 @@ def bench_batch(args, cap, torch):
             fr.node_state.copy_(st)
         return cap.batch_solve(ctx, frames, prm)
 
-    for _ in range(args.warmup):
+    # warm-up: the given steps, and at least half a second so the clocks settle
+    tw = time.perf_counter()
+    k = 0
+    while k < args.warmup or time.perf_counter() - tw < 0.5:
         reps = step()
-    torch.cuda.synchronize()
+        torch.cuda.synchronize()
+        k += 1
     log("timing", args.steps, "steps")
     t0 = time.perf_counter()
     for _ in range(args.steps):

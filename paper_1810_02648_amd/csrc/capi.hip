@@ -27,7 +27,6 @@ __global__ void k_linearize(const ProbDev *P, int mode);
 __global__ void k_apply(const ProbDev *P);
 __global__ void k_node_init(const ProbDev *P, int gn, int energy_only, int check_target);
 __global__ void k_node_gather(const ProbDev *P);
-__global__ void k_scatter_p(const ProbDev *P);
 __global__ void k_node_pcg(const ProbDev *P, int last, int update_only);
 __global__ void k_scal_init(const ProbDev *P, int gn_iters);
 __global__ void k_clear_zbuf(const ProbDev *P);
@@ -209,7 +208,6 @@ void carve(Layout &L, uint8_t *base, const capture_frame &f, ProbDev &pr) {
     pr.Hm = L.take<float>(base, 6 * nv);
     pr.partial = L.take<float>(base, size_t(T.nslots) * 12);
     pr.spack = L.take<float>(base, size_t(T.nslots) * 12);
-    pr.pslot = L.take<float>(base, size_t(T.nslots) * 6);
     pr.tile_e = L.take<double>(base, size_t(T.ntiles) * kTerms);
     pr.pva = L.take<float>(base, 3 * nv);
     float **vecs[8] = {&pr.b, &pr.diag, &pr.dinv, &pr.x, &pr.r, &pr.z, &pr.p, &pr.Ap};
@@ -686,7 +684,6 @@ int capture_linearize(capture_ctx *ctx, const capture_frame *frame, const captur
         const double zero = 0.0;
         CAP_HIP(hipMemcpyAsync(pr.p, p, sizeof(float) * n6, hipMemcpyDeviceToDevice, R.s));
         CAP_HIP(hipMemcpyAsync(pr.scal + 1, &zero, sizeof(double), hipMemcpyHostToDevice, R.s));
-        hipLaunchKernelGGL(k_scatter_p, dim3(1), dim3(kNodeThreads), 0, R.s, R.dprobs);
         timed(R, K_APPLY, [&] {
     hipLaunchKernelGGL(k_apply, dim3(R.max_tiles, 1), dim3(kTileThreads), R.lds_apply, R.s, R.dprobs);
         });

@@ -108,7 +108,6 @@ struct ProbDev {
     // tiles / slots
     float *partial;   // [nslots][12], node-major positions (node_pbeg ranges)
     float *spack;     // [nslots][12] per slot: R (9) and node position (3) of the current GN step
-    float *pslot;     // [nslots][6] per slot: the PCG direction p of its node
     double *tile_e;   // [ntiles][kTerms]
     // nodes
     float *b, *diag, *dinv, *x, *r, *z, *p, *Ap;   // [6][nn]

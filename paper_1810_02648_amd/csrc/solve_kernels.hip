@@ -285,11 +285,11 @@ __global__ __launch_bounds__(kTileThreads) void k_apply(const ProbDev *__restric
         }
     }
     TileLds L = tile_lds(lds, ns, 6);
-    for (int it = threadIdx.x; it < ns * 18; it += blockDim.x) {   // packed per-slot R, g and p
+    for (int it = threadIdx.x; it < ns * 18; it += blockDim.x) {   // packed per-slot R and g, p of the slot's node
         const int s = it / 18, q = it - s * 18;
         if (q < 9) L.R[9 * s + q] = pr.spack[size_t(sb + s) * 12 + q];
         else if (q < 12) L.g[3 * s + q - 9] = pr.spack[size_t(sb + s) * 12 + q];
-        else L.p[6 * s + q - 12] = pr.pslot[size_t(sb + s) * 6 + q - 12];
+        else L.p[6 * s + q - 12] = pr.p[size_t(q - 12) * nn + T.slot_node[sb + s]];
     }
     load_offsets(T, sb, ns, lbeg);
     __syncthreads();
@@ -391,7 +391,6 @@ __global__ __launch_bounds__(kNodeThreads) void k_node_init(const ProbDev *__res
             pr.b[i] = b; pr.diag[i] = d; pr.dinv[i] = mi;
             pr.x[i] = 0.0f; pr.r[i] = b; pr.z[i] = z; pr.p[i] = z;
             rz += double(b) * double(z);
-            for (int q = T.node_pbeg[k]; q < T.node_pbeg[k + 1]; ++q) pr.pslot[size_t(T.node_pidx[q]) * 6 + c] = z;
         }
         // per-slot copies of R_k and the node position for the PCG tile kernel
         for (int i = threadIdx.x; i < 12 * nn; i += blockDim.x) {
@@ -438,17 +437,6 @@ __global__ void k_clear_zbuf(const ProbDev *__restrict__ P) {
     const size_t i = (size_t(blockIdx.x) * blockDim.x + threadIdx.x) * 4;
     for (int q = 0; q < 4; ++q)
         if (i + q < hw) pr.zbuf[i + q] = 0u;
-}
-
-// Copy p to the per-slot array (for a caller-supplied direction).
-__global__ __launch_bounds__(kNodeThreads) void k_scatter_p(const ProbDev *__restrict__ P) {
-    const ProbDev &pr = P[blockIdx.x];
-    const TemplateDev &T = pr.T;
-    const int nn = T.nn;
-    for (int i = threadIdx.x; i < 6 * nn; i += blockDim.x) {
-        const int c = i / nn, k = i - c * nn;
-        for (int q = T.node_pbeg[k]; q < T.node_pbeg[k + 1]; ++q) pr.pslot[size_t(T.node_pidx[q]) * 6 + c] = pr.p[i];
-    }
 }
 
 // Gather A p from the tile partials (no PCG update).
@@ -567,20 +555,12 @@ __global__ __launch_bounds__(kNodeThreads) void k_node_pcg(const ProbDev *__rest
                 for (int j = 0; j < kItems; ++j) {
                     const int i = threadIdx.x + j * kNodeThreads;
                     if (i < n6) {
-                        const float pn = float(fma(beta, double(pp[j]), double(zz[j])));
-                        pr.p[i] = pn;
-                        const int c = i / nn, k = i - c * nn;
-                        for (int q = T.node_pbeg[k]; q < T.node_pbeg[k + 1]; ++q)
-                            pr.pslot[size_t(T.node_pidx[q]) * 6 + c] = pn;
+                        pr.p[i] = float(fma(beta, double(pp[j]), double(zz[j])));
                     }
                 }
             } else {
                 for (int i = threadIdx.x; i < n6; i += kNodeThreads) {
-                    const float pn = float(fma(beta, double(pr.p[i]), double(pr.z[i])));
-                    pr.p[i] = pn;
-                    const int c = i / nn, k = i - c * nn;
-                    for (int q = T.node_pbeg[k]; q < T.node_pbeg[k + 1]; ++q)
-                        pr.pslot[size_t(T.node_pidx[q]) * 6 + c] = pn;
+                    pr.p[i] = float(fma(beta, double(pr.p[i]), double(pr.z[i])));
                 }
             }
             if (threadIdx.x == 0) {
