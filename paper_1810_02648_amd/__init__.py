@@ -224,6 +224,11 @@ def linearize(ctx, frame, prm, p=None):
     return dict(rhs=rhs, diag=diag, Ap=Ap, energy=list(e))
 
 
+def set_graphs(ctx, on=True):
+    """Replay solves from captured HIP graphs (see capture_set_graphs)."""
+    capi.check(ctx.lib.capture_set_graphs(ctx.h, 1 if on else 0))
+
+
 def profile_enable(ctx, on=True):
     """Bracket every solver-kernel launch with HIP events (see capture_profile_enable)."""
     capi.check(ctx.lib.capture_profile_enable(ctx.h, 1 if on else 0))

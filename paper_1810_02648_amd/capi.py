@@ -107,6 +107,7 @@ SIGNATURES = {
     "capture_autotune_tiles": (C.c_int, [_P, C.c_int32, C.POINTER(TemplateDesc), C.POINTER(Frame),
                                          C.POINTER(NonrigidParams), C.POINTER(C.c_int32), C.c_int32,
                                          C.POINTER(C.c_int32), C.POINTER(C.c_double), _P]),
+    "capture_set_graphs": (C.c_int, [_P, C.c_int]),
     "capture_profile_enable": (C.c_int, [_P, C.c_int]),
     "capture_profile_read": (C.c_int, [_P, C.c_char_p, C.POINTER(C.c_double), C.POINTER(C.c_int64)]),
 }

@@ -2,6 +2,7 @@
 // sequence of the per-frame solve.
 #include <algorithm>
 #include <chrono>
+#include <cstdio>
 #include <cmath>
 #include <cstring>
 #include <vector>
@@ -34,16 +35,18 @@ int build_template(const capture_template_desc *d, capture_template **out, int d
 
 // warm-start kernels (warmstart.hip)
 __global__ void k_gemm(Gemm g);
-__global__ void k_mean_fwd(const float *z, int nn, const int *edge_dst, uint16_t *cat, int width);
 __global__ void k_mean_bwd(const float *dcat, const float *z, int nn, const int *in_beg, const int *in_src,
                            const int *out_cnt, uint16_t *dzb, float *dz, int width);
 __global__ void k_colsum(const float *in, int rows, int cols, float *out);
 __global__ void k_mse_grad(const float *y, const float *t, int n, float *dy, uint16_t *dyb, float *se);
 __global__ void k_adam(float *w, const float *g, float *m, float *v, uint16_t *wb, int n, float lr, float c1, float c2);
 __global__ void k_to_bf16(const float *in, uint16_t *out, int n);
-__global__ void k_standardise(const float *X, int nn, const float *mu, const float *sd, uint16_t *Xb);
 __global__ void k_ws_features(const ProbDev *P, const float *prev2, float *X);
-__global__ void k_ws_delta(const ProbDev *P, const float *y);
+__global__ void k_ws_layer1(const float *X, int nn, const float *mu, const float *sd, const uint16_t *W,
+                            const float *bias, uint16_t *Xb, float *z, uint16_t *cat);
+template <int NT>
+__global__ void k_ws_layer_mp(uint16_t *cat, const float *zp, const int *edge_dst, int nn, const uint16_t *W,
+                              const float *bias, int N, float *z, uint16_t *cat_next, float *xdelta);
 __global__ void k_ws_select(const ProbDev *P, int slot_prev, int slot_pred);
 __global__ void k_ws_target(const float *prev, const float *next, int nn, float *target);
 __global__ void k_ws_scaling(const float *X, long long rows, float *mu, float *sd);
@@ -406,6 +409,54 @@ int launch_solve(Run &R, const capture_nonrigid_params *prm, int check_target = 
     return CAPTURE_OK;
 }
 
+// The solve's launch sequence (preprocessing, decisions, Gauss-Newton/PCG)
+// captured once per launch shape into a HIP graph on the context's capture
+// stream, then replayed on the caller's stream.  Kernels read everything
+// else from the descriptors, which setup uploads before the replay, so one
+// graph serves any inputs with the same sizes, workspace and schedule.  The
+// sequence holds kernels only (buffers are cleared by kernels, not memsets).
+int launch_graph(Run &R, const capture_nonrigid_params *prm) {
+    capture_ctx *ctx = R.ctx;
+    char key[512];
+    std::snprintf(key, sizeof key, "%d|%p|%d %d %d %d %d %d %d|%zu %zu|%d %d", R.n, (void *)R.dprobs, R.max_nv,
+                  R.max_nf, R.max_hw, R.max_w, R.max_h, R.max_tiles, R.max_me, R.lds_lin, R.lds_apply, prm->gn_iters,
+                  prm->pcg_iters);
+    auto &cache = ctx->graph_cache;
+    hipGraphExec_t exec = nullptr;
+    for (size_t i = 0; i < cache.size(); ++i)
+        if (cache[i].key == key) {
+            exec = cache[i].exec;
+            std::rotate(cache.begin() + i, cache.begin() + i + 1, cache.end());     // most recent last
+            break;
+        }
+    if (!exec) {
+        if (!ctx->capture_stream) CAP_HIP(hipStreamCreateWithFlags(&ctx->capture_stream, hipStreamNonBlocking));
+        Run C = R;
+        C.s = ctx->capture_stream;
+        C.prof = nullptr;
+        CAP_HIP(hipStreamBeginCapture(C.s, hipStreamCaptureModeThreadLocal));
+        int rc = launch_frame(C, prm->gn_iters);
+        if (!rc) rc = launch_solve(C, prm);
+        hipGraph_t graph = nullptr;
+        const hipError_t e = hipStreamEndCapture(C.s, &graph);
+        if (rc) {
+            if (graph) (void)hipGraphDestroy(graph);
+            return rc;
+        }
+        if (e != hipSuccess || !graph) return fail(CAPTURE_EHIP, "graph capture failed");
+        const hipError_t ei = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        if (ei != hipSuccess) return fail(CAPTURE_EHIP, "graph instantiation failed");
+        if (cache.size() >= size_t(kGraphCache)) {
+            (void)hipGraphExecDestroy(cache.front().exec);
+            cache.erase(cache.begin());
+        }
+        cache.push_back({key, exec});
+    }
+    CAP_HIP(hipGraphLaunch(exec, R.s));
+    return CAPTURE_OK;
+}
+
 int collect(Run &R, int gn_iters, capture_report *reports) {
     const uint8_t *blk = reinterpret_cast<const uint8_t *>(R.probs[0].scal);
     const size_t off_counts = reinterpret_cast<const uint8_t *>(R.probs[0].counts) - blk;
@@ -453,17 +504,17 @@ void gemm(hipStream_t s, const uint16_t *A, long long sai, long long sak, const 
 }
 
 // Forward pass on raw features X (device, [nn][32]) -> net->y [nn][6].
-void ws_forward(capture_warmstart *net, const TemplateDev &T, const float *X, hipStream_t s) {
+// Network forward: three fused layer kernels (one wave per 16 nodes); with
+// xdelta the last one also writes the scaled update in node-major layout.
+void ws_forward(capture_warmstart *net, const TemplateDev &T, const float *X, hipStream_t s, float *xdelta = nullptr) {
     const int nn = T.nn;
-    hipLaunchKernelGGL(k_standardise, dim3(blocks(size_t(nn) * 32, 256)), dim3(256), 0, s, X, nn, net->mu, net->sd,
-                       net->Xb);
-    gemm(s, net->Xb, 32, 1, net->wb + kOffW1, 32, 1, net->z1, 128, 1, nn, 128, 32, net->w + kOffB1, net->c1, 256);
-    hipLaunchKernelGGL(k_mean_fwd, dim3(blocks(size_t(nn) * 128, 256)), dim3(256), 0, s, net->z1, nn, T.edge_dst,
-                       net->c1, 128);
-    gemm(s, net->c1, 256, 1, net->wb + kOffW2, 256, 1, net->z2, 128, 1, nn, 128, 256, net->w + kOffB2, net->c2, 256);
-    hipLaunchKernelGGL(k_mean_fwd, dim3(blocks(size_t(nn) * 128, 256)), dim3(256), 0, s, net->z2, nn, T.edge_dst,
-                       net->c2, 128);
-    gemm(s, net->c2, 256, 1, net->wb + kOffW3, 256, 1, net->y, 6, 1, nn, 6, 256, net->w + kOffB3);
+    const dim3 g(unsigned((nn + 15) / 16));
+    hipLaunchKernelGGL(k_ws_layer1, g, dim3(64), 0, s, X, nn, net->mu, net->sd, net->wb + kOffW1, net->w + kOffB1,
+                       net->Xb, net->z1, net->c1);
+    hipLaunchKernelGGL(k_ws_layer_mp<8>, g, dim3(64), 0, s, net->c1, net->z1, T.edge_dst, nn, net->wb + kOffW2,
+                       net->w + kOffB2, 128, net->z2, net->c2, (float *)nullptr);
+    hipLaunchKernelGGL(k_ws_layer_mp<1>, g, dim3(64), 0, s, net->c2, net->z2, T.edge_dst, nn, net->wb + kOffW3,
+                       net->w + kOffB3, 6, net->y, (uint16_t *)nullptr, xdelta);
 }
 
 // Backward pass after ws_forward, with targets in net->tgt; gradients into net->g.
@@ -508,6 +559,8 @@ void capture_destroy(capture_ctx *ctx) {
     if (!ctx) return;
     for (hipEvent_t e : ctx->prof.ev) (void)hipEventDestroy(e);
     if (ctx->pinned) (void)hipHostFree(ctx->pinned);
+    for (auto &g : ctx->graph_cache) (void)hipGraphExecDestroy(g.exec);
+    if (ctx->capture_stream) (void)hipStreamDestroy(ctx->capture_stream);
     delete ctx;
 }
 
@@ -560,8 +613,12 @@ int capture_batch_solve(capture_ctx *ctx, int32_t n, const capture_frame *frames
     Run R;
     int rc = setup(R, ctx, n, frames, params, workspace, workspace_bytes, stream);
     if (rc) return rc;
-    if ((rc = launch_frame(R, params->gn_iters))) return rc;      // keeps the start states (k_scal_init)
-    if ((rc = launch_solve(R, params))) return rc;
+    if (ctx->graphs && !ctx->prof.on) {
+        if ((rc = launch_graph(R, params))) return rc;
+    } else {
+        if ((rc = launch_frame(R, params->gn_iters))) return rc;      // keeps the start states (k_scal_init)
+        if ((rc = launch_solve(R, params))) return rc;
+    }
     rc = collect(R, params->gn_iters, reports);
     if (rc) {
         for (int i = 0; i < n; ++i)
@@ -889,8 +946,7 @@ int capture_nonrigid_solve_warm(capture_ctx *ctx, const capture_frame *frame, co
                            net->X);
     });
     timed(R, K_WS_MLP, [&] {
-        ws_forward(net, pr.T, net->X, R.s);
-        hipLaunchKernelGGL(k_ws_delta, dim3(blocks(size_t(6) * pr.T.nn, 256), 1), dim3(256), 0, R.s, R.dprobs, net->y);
+        ws_forward(net, pr.T, net->X, R.s, pr.x);
     });
     hipLaunchKernelGGL(k_node_pcg, dim3(1), dim3(kNodeThreads), 0, R.s, R.dprobs, 0, 1);   // x' = x (+) delta
     launch_linearize(R, pred_slot, 1);
@@ -907,6 +963,12 @@ int capture_nonrigid_solve_warm(capture_ctx *ctx, const capture_frame *frame, co
         (void)hipStreamSynchronize(R.s);
         return fail(rc, "non-finite energy; node state restored");
     }
+    return CAPTURE_OK;
+}
+
+int capture_set_graphs(capture_ctx *ctx, int on) {
+    if (!ctx) return fail(CAPTURE_EINVAL, "null ctx");
+    ctx->graphs = on != 0;
     return CAPTURE_OK;
 }
 

@@ -32,6 +32,7 @@ constexpr int kNodeThreads = 1024;    // threads of a per-problem node workgroup
 constexpr int kMaxImageSide = 4096;
 constexpr int kRasterSmall = 256;         // pixel-box size above which a face is rasterised by a workgroup
 constexpr int kRasterBigBlocks = 512;
+constexpr int kGraphCache = 16;          // captured solve graphs kept per context
 constexpr int kTerms = 5;   // energy terms per slot: photo, sil (with b), sil (with |b|), arap, velocity
 constexpr int kScalars = 8 + kTerms * (CAPTURE_MAX_GN + 2);   // slot MAX_GN + 1: predicted start
 
@@ -199,6 +200,13 @@ struct capture_ctx {
     cap::Profiler prof;
     void *pinned = nullptr;      // pinned host staging (descriptors, report read-back)
     size_t pinned_bytes = 0;
+    bool graphs = false;         // replay solves from captured HIP graphs
+    hipStream_t capture_stream = nullptr;
+    struct Graph {
+        std::string key;
+        hipGraphExec_t exec;
+    };
+    std::vector<Graph> graph_cache;   // most recent last, at most kGraphCache entries
 };
 
 struct capture_warmstart {

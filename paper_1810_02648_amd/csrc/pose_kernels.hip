@@ -407,8 +407,8 @@ __global__ __launch_bounds__(64 * kJtjWaves) void k_pose_jtj(const PoseDev *__re
 }
 
 // One wave.  mode 0: energy of the step, damping, Cholesky A = U^T U (upper
-// factor, row-major in LDS so every inner loop runs along a row), solves,
-// update, kinematics at the new pose.  mode 1: energy only (final).
+// factor, row-major in LDS), the two triangular solves with the unknowns in
+// registers, update, kinematics at the new pose.  mode 1: energy only (final).
 // mode 2: energy only (the system is already in place for the caller).
 __global__ __launch_bounds__(64) void k_pose_step(const PoseDev *__restrict__ PP, int gn, int nblk, int mode) {
     const PoseDev &P = *PP;
@@ -416,8 +416,8 @@ __global__ __launch_bounds__(64) void k_pose_step(const PoseDev *__restrict__ PP
     const int nu = B.nu, lda = nu + 1;
     const int t = threadIdx.x;
     __shared__ double A[kMaxPoseUnknowns * (kMaxPoseUnknowns + 1)];
-    __shared__ double y[kMaxPoseUnknowns], pn[kMaxPoseUnknowns];
-    __shared__ double ep[4 * 64];
+    __shared__ double pn[kMaxPoseUnknowns];
+    __shared__ double ep[64];
     __shared__ double sR[9 * kMaxJoints], sp[3 * kMaxJoints], sA[9 * kMaxJoints], sL[9 * kMaxJoints],
         sJ[9 * kMaxJoints];
     __shared__ int bad;
@@ -443,7 +443,17 @@ __global__ __launch_bounds__(64) void k_pose_step(const PoseDev *__restrict__ PP
         return;
     }
     if (mode != 0 || P.status[0] != 0) return;
-    for (int e = t; e < nu * lda; e += 64) A[e] = P.sys[e];
+    {   // the system into LDS, eight independent loads in flight per lane
+        const int tot = nu * lda;
+        for (int e0 = t; e0 < tot; e0 += 64 * 8) {
+            double v[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) v[u] = e0 + 64 * u < tot ? P.sys[e0 + 64 * u] : 0.0;
+#pragma unroll
+            for (int u = 0; u < 8; ++u)
+                if (e0 + 64 * u < tot) A[e0 + 64 * u] = v[u];
+        }
+    }
     __syncthreads();
     double m = 0.0;
     for (int i = t; i < nu; i += 64) m = fmax(m, A[i * lda + i]);
@@ -451,24 +461,38 @@ __global__ __launch_bounds__(64) void k_pose_step(const PoseDev *__restrict__ PP
     const double mu = 1e-6 * m;
     for (int i = t; i < nu; i += 64) A[i * lda + i] += mu;
     __syncthreads();
-    // A = U^T U, U in the upper triangle
-    for (int k = 0; k < nu; ++k) {
-        const double d = A[k * lda + k];
+    // A = U^T U row by row: U[i][j] = (A[i][j] - sum_{k<i} U[k][i] U[k][j]) / U[i][i]
+    // for lanes j = i + t, i + t + 64.  The sums only read LDS (U[k][i] is a
+    // broadcast, U[k][j] contiguous over the lanes), so they pipeline.
+    for (int i = 0; i < nu; ++i) {
+        double s[2];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int j = i + t + 64 * h;
+            double a0 = 0.0, a1 = 0.0;
+            if (j < nu) {
+                int k = 0;
+                for (; k + 1 < i; k += 2) {
+                    a0 += A[k * lda + i] * A[k * lda + j];
+                    a1 += A[(k + 1) * lda + i] * A[(k + 1) * lda + j];
+                }
+                if (k < i) a0 += A[k * lda + i] * A[k * lda + j];
+                s[h] = A[i * lda + j] - (a0 + a1);
+            } else {
+                s[h] = 0.0;
+            }
+        }
+        const double d = __shfl(s[0], 0);          // the diagonal, held by lane 0
         if (!(d > 0.0) || !isfinite(d)) {
             if (t == 0) bad = 1;
             break;
         }
-        const double ukk = sqrt(d);
+        const double uii = sqrt(d);
         __syncthreads();
-        if (t == 0) A[k * lda + k] = ukk;
-        for (int j = k + 1 + t; j < nu; j += 64) A[k * lda + j] /= ukk;
-        __syncthreads();
-        // trailing update by columns: lane j runs down its own column, so the
-        // rows' updates are independent loads and stores, not a serial chain
-        for (int j = k + 1 + t; j < nu; j += 64) {
-            const double ukj = A[k * lda + j];
-#pragma unroll 4
-            for (int i = k + 1; i <= j; ++i) A[i * lda + j] -= A[k * lda + i] * ukj;
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int j = i + t + 64 * h;
+            if (j < nu) A[i * lda + j] = j == i ? uii : s[h] / uii;
         }
         __syncthreads();
     }
@@ -478,26 +502,38 @@ __global__ __launch_bounds__(64) void k_pose_step(const PoseDev *__restrict__ PP
         if (t == 0) P.status[0] = CAPTURE_ENOTSPD;
         return;
     }
-    // U^T y = rhs, then U delta = y
-    for (int e = t; e < nu; e += 64) y[e] = A[e * lda + nu];
-    __syncthreads();
-    for (int k = 0; k < nu; ++k) {
-        const double yk = y[k] / A[k * lda + k];
-        __syncthreads();
-        if (t == 0) y[k] = yk;
-        for (int j = k + 1 + t; j < nu; j += 64) y[j] -= A[k * lda + j] * yk;
-        __syncthreads();
+    // U^T y = rhs, then U delta = y; component e lives in lane e % 64 (slot e / 64)
+    // and each step's dot product is a fixed butterfly over the wave
+    double y0 = 0.0, y1 = 0.0;
+    for (int i = 0; i < nu; ++i) {
+        double part = 0.0;
+        if (t < i) part += A[t * lda + i] * y0;
+        if (t + 64 < i) part += A[(t + 64) * lda + i] * y1;
+        for (int o = 32; o > 0; o >>= 1) part += __shfl_xor(part, o);
+        const double yi = (A[i * lda + nu] - part) / A[i * lda + i];
+        if ((i & 63) == t) {
+            if (i < 64) y0 = yi; else y1 = yi;
+        }
     }
-    for (int k = nu - 1; k >= 0; --k) {
-        const double dk = y[k] / A[k * lda + k];
-        __syncthreads();
-        if (t == 0) y[k] = dk;
-        for (int i = t; i < k; i += 64) y[i] -= A[i * lda + k] * dk;
-        __syncthreads();
+    double d0 = 0.0, d1 = 0.0;
+    for (int i = nu - 1; i >= 0; --i) {
+        double part = 0.0;
+        if (t > i && t < nu) part += A[i * lda + t] * d0;
+        if (t + 64 > i && t + 64 < nu) part += A[i * lda + t + 64] * d1;
+        for (int o = 32; o > 0; o >>= 1) part += __shfl_xor(part, o);
+        const double yi = __shfl(i < 64 ? y0 : y1, i & 63);
+        const double di = (yi - part) / A[i * lda + i];
+        if ((i & 63) == t) {
+            if (i < 64) d0 = di; else d1 = di;
+        }
     }
-    for (int e = t; e < nu; e += 64) {
-        pn[e] = P.pose[e] + y[e];
-        P.pose[e] = pn[e];
+    if (t < nu) {
+        pn[t] = P.pose[t] + d0;
+        P.pose[t] = pn[t];
+    }
+    if (t + 64 < nu) {
+        pn[t + 64] = P.pose[t + 64] + d1;
+        P.pose[t + 64] = pn[t + 64];
     }
     __syncthreads();
     fk_block(B, pn, sR, sp, sA, sL, sJ);

@@ -58,25 +58,134 @@ __global__ __launch_bounds__(256) void k_gemm(Gemm g) {
     }
 }
 
-// ---------------------------------------------------------------- message passing
-// out[k][off + f] = bf16(mean over valid out-edges l of relu(z[l][f]))
-__global__ void k_mean_fwd(const float *__restrict__ z, int nn, const int *__restrict__ edge_dst,
-                           uint16_t *__restrict__ cat, int width) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= nn * width) return;
-    const int k = i / width, f = i - k * width;
-    float s = 0.0f;
-    int cnt = 0;
-    for (int e = 0; e < 8; ++e) {
-        const int l = edge_dst[e * nn + k];
-        if (l >= 0) {
-            const float v = z[size_t(l) * width + f];
-            s += v > 0.0f ? v : 0.0f;
-            ++cnt;
+// ---------------------------------------------------------------- fused forward
+// One wave per 16 nodes computes all outputs of a layer, so every input
+// element is formed once: layer 1 standardises the features to bf16 on the
+// fly; layers 2 and 3 build their second 128 inputs (the mean over valid
+// out-edges of ReLU(z) of the previous layer, bf16) while feeding the MFMA.
+// The rounding points are those of the layer definition (bf16 inputs and
+// weights, float32 accumulation over k in steps of 16, bias after the sum, the
+// mean of the float32 ReLU outputs rounded once); all intermediates (Xb, z1,
+// cat1, z2, cat2, y) stay for the backward pass.
+__global__ __launch_bounds__(64) void k_ws_layer1(const float *__restrict__ X, int nn, const float *__restrict__ mu,
+                                                  const float *__restrict__ sd, const uint16_t *__restrict__ W,
+                                                  const float *__restrict__ bias, uint16_t *__restrict__ Xb,
+                                                  float *__restrict__ z, uint16_t *__restrict__ cat) {
+    const int lane = threadIdx.x, r = lane & 15, kq = (lane >> 4) * 4;
+    const int i0 = blockIdx.x * 16, ia = i0 + r;
+    f4v acc[8];
+#pragma unroll
+    for (int t = 0; t < 8; ++t) acc[t] = f4v{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+    for (int k0 = 0; k0 < 32; k0 += 16) {
+        s4v a;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int k = k0 + kq + q;
+            uint16_t b = 0;
+            if (ia < nn) {
+                b = f2bf(k < 27 ? (X[size_t(ia) * 32 + k] - mu[k]) / sd[k] : 0.0f);
+                Xb[size_t(ia) * 32 + k] = b;
+            }
+            a[q] = short(b);
+        }
+#pragma unroll
+        for (int t = 0; t < 8; ++t) {
+            s4v bw;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) bw[q] = short(W[(t * 16 + r) * 32 + k0 + kq + q]);
+            acc[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, bw, acc[t], 0, 0, 0);
         }
     }
-    cat[size_t(k) * 2 * width + width + f] = f2bf(cnt ? s / float(cnt) : 0.0f);
+#pragma unroll
+    for (int t = 0; t < 8; ++t)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int i = i0 + (lane >> 4) * 4 + q, j = t * 16 + r;
+            if (i < nn) {
+                const float v = acc[t][q] + bias[j];
+                z[size_t(i) * 128 + j] = v;
+                cat[size_t(i) * 256 + j] = f2bf(v > 0.0f ? v : 0.0f);
+            }
+        }
 }
+
+// Layers 2 (NT = 8 output tiles, 128 outputs) and 3 (NT = 1, N = 6 outputs).
+// cat: [nn][256] bf16 inputs whose first half is ReLU(z_prev) (written by the
+// previous layer); this kernel writes its second half (the neighbour means).
+// cat_next (optional): bf16 ReLU copy of this layer's output into the next
+// layer's first half.  xdelta (optional): the warm-start update
+// x[c][k] = y[k][c] * (0.05 rad, 0.01 m scale) in node-major layout.
+template <int NT>
+__global__ __launch_bounds__(64) void k_ws_layer_mp(uint16_t *__restrict__ cat, const float *__restrict__ zp,
+                                                    const int *__restrict__ edge_dst, int nn,
+                                                    const uint16_t *__restrict__ W, const float *__restrict__ bias,
+                                                    int N, float *__restrict__ z, uint16_t *__restrict__ cat_next,
+                                                    float *__restrict__ xdelta) {
+    const int lane = threadIdx.x, r = lane & 15, kq = (lane >> 4) * 4;
+    const int i0 = blockIdx.x * 16, ia = i0 + r;
+    int nb[8];
+    int cnt = 0;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+        nb[e] = ia < nn ? edge_dst[e * nn + ia] : -1;
+        cnt += nb[e] >= 0 ? 1 : 0;
+    }
+    f4v acc[NT];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) acc[t] = f4v{0.0f, 0.0f, 0.0f, 0.0f};
+    for (int k0 = 0; k0 < 256; k0 += 16) {
+        s4v a;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int k = k0 + kq + q;
+            uint16_t b = 0;
+            if (ia < nn) {
+                if (k < 128) {
+                    b = cat[size_t(ia) * 256 + k];
+                } else {
+                    const int f = k - 128;
+                    float s = 0.0f;
+#pragma unroll
+                    for (int e = 0; e < 8; ++e)
+                        if (nb[e] >= 0) {
+                            const float v = zp[size_t(nb[e]) * 128 + f];
+                            s += v > 0.0f ? v : 0.0f;
+                        }
+                    b = f2bf(cnt ? s / float(cnt) : 0.0f);
+                    cat[size_t(ia) * 256 + k] = b;
+                }
+            }
+            a[q] = short(b);
+        }
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+            s4v bw;
+            const int jb = t * 16 + r;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) bw[q] = jb < N ? short(W[size_t(jb) * 256 + k0 + kq + q]) : short(0);
+            acc[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, bw, acc[t], 0, 0, 0);
+        }
+    }
+#pragma unroll
+    for (int t = 0; t < NT; ++t)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int i = i0 + (lane >> 4) * 4 + q, j = t * 16 + r;
+            if (i < nn && j < N) {
+                const float v = acc[t][q] + bias[j];
+                z[size_t(i) * N + j] = v;
+                if (cat_next) cat_next[size_t(i) * 256 + j] = f2bf(v > 0.0f ? v : 0.0f);
+                if (xdelta) xdelta[size_t(j) * nn + i] = v * (j < 3 ? 0.05f : 0.01f);
+            }
+        }
+}
+
+template __global__ void k_ws_layer_mp<8>(uint16_t *, const float *, const int *, int, const uint16_t *, const float *,
+                                          int, float *, uint16_t *, float *);
+template __global__ void k_ws_layer_mp<1>(uint16_t *, const float *, const int *, int, const uint16_t *, const float *,
+                                          int, float *, uint16_t *, float *);
+
 
 // Backward through [h; mean(h)] and the ReLU:
 // dz[l][f] = (dcat[l][f] + sum over in-edges (k -> l) of dcat[k][width + f] / |N(k)|) * (z[l][f] > 0)
@@ -139,14 +248,6 @@ __global__ void k_to_bf16(const float *__restrict__ in, uint16_t *__restrict__ o
     if (i < n) out[i] = f2bf(in[i]);
 }
 
-// Standardise raw [nn][32] features into bf16 inputs (padding stays zero).
-__global__ void k_standardise(const float *__restrict__ X, int nn, const float *__restrict__ mu,
-                              const float *__restrict__ sd, uint16_t *__restrict__ Xb) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= nn * 32) return;
-    const int f = i & 31;
-    Xb[i] = f2bf(f < 27 ? (X[i] - mu[f]) / sd[f] : 0.0f);
-}
 
 // ---------------------------------------------------------------- features
 __device__ inline void log_so3(const float R[9], float w[3]) {
@@ -161,17 +262,30 @@ __device__ inline void log_so3(const float R[9], float w[3]) {
 // R_k and t_k (0..5), their change since frame t-2 (6..11, zero without it),
 // sign(b) log(1 + |b|) of the right-hand side (12..17), log(1 + diag)
 // (18..23), node position minus the mean node position (24..26), zeros.
-__global__ void k_ws_features(const ProbDev *__restrict__ P, const float *__restrict__ prev2, float *__restrict__ X) {
+__global__ __launch_bounds__(256) void k_ws_features(const ProbDev *__restrict__ P, const float *__restrict__ prev2,
+                                                     float *__restrict__ X) {
+    __shared__ float part[3][256];
     __shared__ float mean[3];
     const ProbDev &pr = P[blockIdx.y];
     const TemplateDev &T = pr.T;
     const int nn = T.nn, nv = T.nv;
-    if (threadIdx.x < 3) {
-        float s = 0.0f;
-        for (int k = 0; k < nn; ++k) s += pr.xyz[size_t(threadIdx.x) * nv + T.node_vertex[k]];
-        mean[threadIdx.x] = s / float(nn);
+    // mean node position: strided partial sums, then a fixed-order tree over the block
+    {
+        float s[3] = {0.0f, 0.0f, 0.0f};
+        for (int k = threadIdx.x; k < nn; k += blockDim.x) {
+            const int gv = T.node_vertex[k];
+            for (int a = 0; a < 3; ++a) s[a] += pr.xyz[size_t(a) * nv + gv];
+        }
+        for (int a = 0; a < 3; ++a) part[a][threadIdx.x] = s[a];
+        __syncthreads();
+        for (int h = blockDim.x / 2; h > 0; h >>= 1) {
+            if (threadIdx.x < h)
+                for (int a = 0; a < 3; ++a) part[a][threadIdx.x] += part[a][threadIdx.x + h];
+            __syncthreads();
+        }
+        if (threadIdx.x < 3) mean[threadIdx.x] = part[threadIdx.x][0] / float(nn);
+        __syncthreads();
     }
-    __syncthreads();
     for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < nn; k += gridDim.x * blockDim.x) {
         float *x = X + size_t(k) * 32;
         float R[9], w[3];
@@ -206,15 +320,6 @@ __global__ void k_ws_features(const ProbDev *__restrict__ P, const float *__rest
     }
 }
 
-// Scaled network output y [nn][6] -> node update x [6][nn] (rad, m).
-__global__ void k_ws_delta(const ProbDev *__restrict__ P, const float *__restrict__ y) {
-    const ProbDev &pr = P[blockIdx.y];
-    const int nn = pr.T.nn;
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= 6 * nn) return;
-    const int c = i / nn, k = i - c * nn;
-    pr.x[i] = y[size_t(k) * 6 + c] * (c < 3 ? 0.05f : 0.01f);
-}
 
 // Keep the predicted start only if it lowers the energy; otherwise restore
 // the previous frame's state.  scal[4] = predicted-start energy, scal[5] = 1

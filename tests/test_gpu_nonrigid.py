@@ -205,6 +205,42 @@ def test_batch_equals_single_solves(ctx, frames):
         assert ra["energy"] == rb["energy"]
 
 
+def test_graph_replay_matches_eager(ctx, frames):
+    """Solves replayed from captured HIP graphs equal the eager launches bit for
+    bit, on every replay, with unrelated eager GPU work and synchronisations in
+    between, for two launch shapes (a batch of three and a single frame)."""
+    import paper_1810_02648_amd as cap
+    from gpu_util import make_frame
+    prm = cap.params(1.0, 0.1, 10.0, gn_iters=3, pcg_iters=6)
+    fs = []
+    for name, nn in (("small0", 64), ("mid", 203), ("small1", 64)):
+        f = frames[name]
+        fs.append(make_frame(ctx, f, og.build_graph(f["xyz"], nn)))
+    starts = [fr.node_state.clone() for fr in fs]
+
+    def run(batch):
+        for fr, st in zip(fs, starts):
+            fr.node_state.copy_(st)
+        reps = cap.batch_solve(ctx, fs, prm) if batch else [cap.nonrigid_solve(ctx, fs[1], prm)]
+        idx = range(3) if batch else [1]
+        return [fs[i].node_state.cpu().numpy().copy() for i in idx], [r["energy"] for r in reps]
+
+    eager = {b: run(b) for b in (True, False)}
+    cap.set_graphs(ctx, True)
+    try:
+        for rep in range(3):
+            for b in (True, False):
+                got = run(b)
+                for x, y in zip(got[0], eager[b][0]):
+                    assert np.array_equal(x, y), (rep, b)
+                assert got[1] == eager[b][1], (rep, b)
+                junk = torch.randn(1 << 16, device="cuda")
+                float(junk.square().sum())
+                torch.cuda.synchronize()
+    finally:
+        cap.set_graphs(ctx, False)
+
+
 def test_run_to_run_deterministic(ctx, frames):
     import paper_1810_02648_amd as cap
     from gpu_util import make_frame
