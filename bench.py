@@ -384,7 +384,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--mode", default="sequence", choices=["sequence", "frame", "batch"])
+    ap.add_argument("--mode", default="sequence", choices=["sequence", "frame", "batch", "copy"],
+                    help="copy: a plain device copy of known size (calibrates the profiler's byte counters)")
     ap.add_argument("--workload", default=None,
                     help="sequence: seq20k (default) or seq_small; frame: frame20k (default), small, stress200k")
     ap.add_argument("--batch", type=int, default=1,
@@ -405,6 +406,16 @@ def main():
 
     import paper_1810_02648_amd as cap
 
+    if args.mode == "copy":
+        n = 1 << 27                                   # 512 MiB of float32 each way
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(args.warmup + args.steps):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"mode": "copy", "bytes_read_per_launch": 4 * n, "bytes_written_per_launch": 4 * n,
+                          "launches": args.warmup + args.steps}), flush=True)
+        return
     if args.mode == "sequence":
         result, data = bench_sequence(args, cap, torch)
     elif args.mode == "batch":

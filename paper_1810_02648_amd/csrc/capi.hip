@@ -210,7 +210,7 @@ void carve(Layout &L, uint8_t *base, const capture_frame &f, ProbDev &pr) {
     pr.vcode = L.take<uint8_t>(base, nv);
     pr.Hm = L.take<float>(base, 6 * nv);
     pr.partial = L.take<float>(base, size_t(T.nslots) * 12);
-    pr.spack = L.take<float>(base, size_t(T.nslots) * 12);
+    pr.gpos = L.take<float>(base, size_t(3) * nn);
     pr.tile_e = L.take<double>(base, size_t(T.ntiles) * kTerms);
     pr.pva = L.take<float>(base, 3 * nv);
     float **vecs[8] = {&pr.b, &pr.diag, &pr.dinv, &pr.x, &pr.r, &pr.z, &pr.p, &pr.Ap};
@@ -504,16 +504,16 @@ void gemm(hipStream_t s, const uint16_t *A, long long sai, long long sak, const 
 }
 
 // Forward pass on raw features X (device, [nn][32]) -> net->y [nn][6].
-// Network forward: three fused layer kernels (one wave per 16 nodes); with
+// Network forward: three fused layer kernels (one 4-wave workgroup per 16 nodes); with
 // xdelta the last one also writes the scaled update in node-major layout.
 void ws_forward(capture_warmstart *net, const TemplateDev &T, const float *X, hipStream_t s, float *xdelta = nullptr) {
     const int nn = T.nn;
     const dim3 g(unsigned((nn + 15) / 16));
-    hipLaunchKernelGGL(k_ws_layer1, g, dim3(64), 0, s, X, nn, net->mu, net->sd, net->wb + kOffW1, net->w + kOffB1,
+    hipLaunchKernelGGL(k_ws_layer1, g, dim3(256), 0, s, X, nn, net->mu, net->sd, net->wb + kOffW1, net->w + kOffB1,
                        net->Xb, net->z1, net->c1);
-    hipLaunchKernelGGL(k_ws_layer_mp<8>, g, dim3(64), 0, s, net->c1, net->z1, T.edge_dst, nn, net->wb + kOffW2,
+    hipLaunchKernelGGL(k_ws_layer_mp<8>, g, dim3(256), 0, s, net->c1, net->z1, T.edge_dst, nn, net->wb + kOffW2,
                        net->w + kOffB2, 128, net->z2, net->c2, (float *)nullptr);
-    hipLaunchKernelGGL(k_ws_layer_mp<1>, g, dim3(64), 0, s, net->c2, net->z2, T.edge_dst, nn, net->wb + kOffW3,
+    hipLaunchKernelGGL(k_ws_layer_mp<1>, g, dim3(256), 0, s, net->c2, net->z2, T.edge_dst, nn, net->wb + kOffW3,
                        net->w + kOffB3, 6, net->y, (uint16_t *)nullptr, xdelta);
 }
 
@@ -523,17 +523,17 @@ void ws_backward(capture_warmstart *net, const TemplateDev &T, hipStream_t s) {
     hipLaunchKernelGGL(k_mse_grad, dim3(blocks(size_t(nn) * 6, 256)), dim3(256), 0, s, net->y, net->tgt, nn * 6,
                        net->dy, net->dyb, net->se);
     gemm(s, net->dyb, 1, 6, net->c2, 1, 256, net->g + kOffW3, 256, 1, 6, 256, nn, nullptr);
-    hipLaunchKernelGGL(k_colsum, dim3(1), dim3(64), 0, s, net->dy, nn, 6, net->g + kOffB3);
+    hipLaunchKernelGGL(k_colsum, dim3(6), dim3(256), 0, s, net->dy, nn, 6, net->g + kOffB3);
     gemm(s, net->dyb, 6, 1, net->wb + kOffW3, 1, 256, net->dc, 256, 1, nn, 256, 6, nullptr);
     hipLaunchKernelGGL(k_mean_bwd, dim3(blocks(size_t(nn) * 128, 256)), dim3(256), 0, s, net->dc, net->z2, nn,
                        T.in_beg, T.in_src, T.out_cnt, net->dzb, net->dz, 128);
     gemm(s, net->dzb, 1, 128, net->c1, 1, 256, net->g + kOffW2, 256, 1, 128, 256, nn, nullptr);
-    hipLaunchKernelGGL(k_colsum, dim3(1), dim3(128), 0, s, net->dz, nn, 128, net->g + kOffB2);
+    hipLaunchKernelGGL(k_colsum, dim3(128), dim3(256), 0, s, net->dz, nn, 128, net->g + kOffB2);
     gemm(s, net->dzb, 128, 1, net->wb + kOffW2, 1, 256, net->dc, 256, 1, nn, 256, 128, nullptr);
     hipLaunchKernelGGL(k_mean_bwd, dim3(blocks(size_t(nn) * 128, 256)), dim3(256), 0, s, net->dc, net->z1, nn,
                        T.in_beg, T.in_src, T.out_cnt, net->dzb, net->dz, 128);
     gemm(s, net->dzb, 1, 128, net->Xb, 1, 32, net->g + kOffW1, 32, 1, 128, 32, nn, nullptr);
-    hipLaunchKernelGGL(k_colsum, dim3(1), dim3(128), 0, s, net->dz, nn, 128, net->g + kOffB1);
+    hipLaunchKernelGGL(k_colsum, dim3(128), dim3(256), 0, s, net->dz, nn, 128, net->g + kOffB1);
 }
 
 }  // namespace cap

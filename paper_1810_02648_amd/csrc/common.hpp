@@ -108,7 +108,7 @@ struct ProbDev {
     float *Hm;        // [6][nv]
     // tiles / slots
     float *partial;   // [nslots][12], node-major positions (node_pbeg ranges)
-    float *spack;     // [nslots][12] per slot: R (9) and node position (3) of the current GN step
+    float *gpos;      // [3][nn] node positions (the frame's input mesh at the node vertices)
     double *tile_e;   // [ntiles][kTerms]
     // nodes
     float *b, *diag, *dinv, *x, *r, *z, *p, *Ap;   // [6][nn]

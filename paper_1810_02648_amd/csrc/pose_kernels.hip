@@ -469,15 +469,21 @@ __global__ __launch_bounds__(64) void k_pose_step(const PoseDev *__restrict__ PP
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
             const int j = i + t + 64 * h;
-            double a0 = 0.0, a1 = 0.0;
             if (j < nu) {
+                double acc[4] = {0.0, 0.0, 0.0, 0.0};
                 int k = 0;
-                for (; k + 1 < i; k += 2) {
-                    a0 += A[k * lda + i] * A[k * lda + j];
-                    a1 += A[(k + 1) * lda + i] * A[(k + 1) * lda + j];
+                for (; k + 8 <= i; k += 8) {       // eight pairs of loads in flight, then the products
+                    double ui[8], uj[8];
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) {
+                        ui[u] = A[(k + u) * lda + i];
+                        uj[u] = A[(k + u) * lda + j];
+                    }
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) acc[u & 3] += ui[u] * uj[u];
                 }
-                if (k < i) a0 += A[k * lda + i] * A[k * lda + j];
-                s[h] = A[i * lda + j] - (a0 + a1);
+                for (; k < i; ++k) acc[0] += A[k * lda + i] * A[k * lda + j];
+                s[h] = A[i * lda + j] - ((acc[0] + acc[1]) + (acc[2] + acc[3]));
             } else {
                 s[h] = 0.0;
             }

@@ -285,11 +285,12 @@ __global__ __launch_bounds__(kTileThreads) void k_apply(const ProbDev *__restric
         }
     }
     TileLds L = tile_lds(lds, ns, 6);
-    for (int it = threadIdx.x; it < ns * 18; it += blockDim.x) {   // packed per-slot R and g, p of the slot's node
+    for (int it = threadIdx.x; it < ns * 18; it += blockDim.x) {   // R, position and p of each slot's node
         const int s = it / 18, q = it - s * 18;
-        if (q < 9) L.R[9 * s + q] = pr.spack[size_t(sb + s) * 12 + q];
-        else if (q < 12) L.g[3 * s + q - 9] = pr.spack[size_t(sb + s) * 12 + q];
-        else L.p[6 * s + q - 12] = pr.p[size_t(q - 12) * nn + T.slot_node[sb + s]];
+        const int k = T.slot_node[sb + s];
+        if (q < 9) L.R[9 * s + q] = pr.state[size_t(q) * nn + k];
+        else if (q < 12) L.g[3 * s + q - 9] = pr.gpos[size_t(q - 9) * nn + k];
+        else L.p[6 * s + q - 12] = pr.p[size_t(q - 12) * nn + k];
     }
     load_offsets(T, sb, ns, lbeg);
     __syncthreads();
@@ -392,12 +393,10 @@ __global__ __launch_bounds__(kNodeThreads) void k_node_init(const ProbDev *__res
             pr.x[i] = 0.0f; pr.r[i] = b; pr.z[i] = z; pr.p[i] = z;
             rz += double(b) * double(z);
         }
-        // per-slot copies of R_k and the node position for the PCG tile kernel
-        for (int i = threadIdx.x; i < 12 * nn; i += blockDim.x) {
-            const int q12 = i / nn, k = i - q12 * nn;
-            const float v = q12 < 9 ? pr.state[size_t(q12) * nn + k]
-                                    : pr.xyz[size_t(q12 - 9) * T.nv + T.node_vertex[k]];
-            for (int q = T.node_pbeg[k]; q < T.node_pbeg[k + 1]; ++q) pr.spack[size_t(T.node_pidx[q]) * 12 + q12] = v;
+        // node positions, node-major, for the PCG tile kernel's slot loads
+        for (int i = threadIdx.x; i < 3 * nn; i += blockDim.x) {
+            const int a = i / nn, k = i - a * nn;
+            pr.gpos[i] = pr.xyz[size_t(a) * T.nv + T.node_vertex[k]];
         }
     }
     rz = block_sum<kNodeThreads>(rz, red);

@@ -59,55 +59,65 @@ __global__ __launch_bounds__(256) void k_gemm(Gemm g) {
 }
 
 // ---------------------------------------------------------------- fused forward
-// One wave per 16 nodes computes all outputs of a layer, so every input
-// element is formed once: layer 1 standardises the features to bf16 on the
-// fly; layers 2 and 3 build their second 128 inputs (the mean over valid
-// out-edges of ReLU(z) of the previous layer, bf16) while feeding the MFMA.
-// The rounding points are those of the layer definition (bf16 inputs and
-// weights, float32 accumulation over k in steps of 16, bias after the sum, the
-// mean of the float32 ReLU outputs rounded once); all intermediates (Xb, z1,
-// cat1, z2, cat2, y) stay for the backward pass.
-__global__ __launch_bounds__(64) void k_ws_layer1(const float *__restrict__ X, int nn, const float *__restrict__ mu,
-                                                  const float *__restrict__ sd, const uint16_t *__restrict__ W,
-                                                  const float *__restrict__ bias, uint16_t *__restrict__ Xb,
-                                                  float *__restrict__ z, uint16_t *__restrict__ cat) {
-    const int lane = threadIdx.x, r = lane & 15, kq = (lane >> 4) * 4;
-    const int i0 = blockIdx.x * 16, ia = i0 + r;
-    f4v acc[8];
-#pragma unroll
-    for (int t = 0; t < 8; ++t) acc[t] = f4v{0.0f, 0.0f, 0.0f, 0.0f};
-#pragma unroll
-    for (int k0 = 0; k0 < 32; k0 += 16) {
-        s4v a;
+// One workgroup (4 waves) per 16 nodes and layer.  The workgroup first forms
+// the layer's 16 x K bf16 input tile in LDS, each element once and with
+// coalesced loads: layer 1 standardises the raw features; layers 2 and 3 copy
+// ReLU(z_prev) and compute the mean over valid out-edges of ReLU(z_prev) of
+// the neighbours (also stored into cat for the backward pass).  Each wave
+// then owns output tiles t = wave, wave + 4 and accumulates over k in steps of
+// 16 on MFMA with B = W from global memory.  The rounding points are those
+// of the layer definition (bf16 inputs and weights, float32 accumulation in
+// ascending k, bias after the sum, the mean of float32 ReLU outputs rounded
+// once); all intermediates (Xb, z1, cat1, z2, cat2, y) stay for the backward.
+constexpr int kLayerThreads = 256;
+
+template <int K>
+__device__ inline f4v tile_mfma(const uint16_t (*As)[K + 8], const uint16_t *__restrict__ W, int jb, int N) {
+    const int lane = threadIdx.x & 63, r = lane & 15, kq = (lane >> 4) * 4;
+    f4v acc = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll 4
+    for (int k0 = 0; k0 < K; k0 += 16) {
+        s4v a, bw;
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-            const int k = k0 + kq + q;
-            uint16_t b = 0;
-            if (ia < nn) {
-                b = f2bf(k < 27 ? (X[size_t(ia) * 32 + k] - mu[k]) / sd[k] : 0.0f);
-                Xb[size_t(ia) * 32 + k] = b;
-            }
-            a[q] = short(b);
+            a[q] = short(As[r][k0 + kq + q]);
+            bw[q] = jb < N ? short(W[size_t(jb) * K + k0 + kq + q]) : short(0);
         }
-#pragma unroll
-        for (int t = 0; t < 8; ++t) {
-            s4v bw;
-#pragma unroll
-            for (int q = 0; q < 4; ++q) bw[q] = short(W[(t * 16 + r) * 32 + k0 + kq + q]);
-            acc[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, bw, acc[t], 0, 0, 0);
-        }
+        acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, bw, acc, 0, 0, 0);
     }
-#pragma unroll
-    for (int t = 0; t < 8; ++t)
+    return acc;
+}
+
+__global__ __launch_bounds__(kLayerThreads) void k_ws_layer1(const float *__restrict__ X, int nn,
+                                                             const float *__restrict__ mu, const float *__restrict__ sd,
+                                                             const uint16_t *__restrict__ W,
+                                                             const float *__restrict__ bias, uint16_t *__restrict__ Xb,
+                                                             float *__restrict__ z, uint16_t *__restrict__ cat) {
+    __shared__ uint16_t As[16][32 + 8];
+    const int i0 = blockIdx.x * 16;
+    for (int idx = threadIdx.x; idx < 16 * 32; idx += blockDim.x) {
+        const int r = idx >> 5, k = idx & 31, i = i0 + r;
+        uint16_t b = 0;
+        if (i < nn) {
+            b = f2bf(k < 27 ? (X[size_t(i) * 32 + k] - mu[k]) / sd[k] : 0.0f);
+            Xb[size_t(i) * 32 + k] = b;
+        }
+        As[r][k] = b;
+    }
+    __syncthreads();
+    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63, r = lane & 15;
+    for (int t = wv; t < 8; t += kLayerThreads / 64) {
+        const f4v acc = tile_mfma<32>(As, W, t * 16 + r, 128);
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             const int i = i0 + (lane >> 4) * 4 + q, j = t * 16 + r;
             if (i < nn) {
-                const float v = acc[t][q] + bias[j];
+                const float v = acc[q] + bias[j];
                 z[size_t(i) * 128 + j] = v;
                 cat[size_t(i) * 256 + j] = f2bf(v > 0.0f ? v : 0.0f);
             }
         }
+    }
 }
 
 // Layers 2 (NT = 8 output tiles, 128 outputs) and 3 (NT = 1, N = 6 outputs).
@@ -117,68 +127,61 @@ __global__ __launch_bounds__(64) void k_ws_layer1(const float *__restrict__ X, i
 // layer's first half.  xdelta (optional): the warm-start update
 // x[c][k] = y[k][c] * (0.05 rad, 0.01 m scale) in node-major layout.
 template <int NT>
-__global__ __launch_bounds__(64) void k_ws_layer_mp(uint16_t *__restrict__ cat, const float *__restrict__ zp,
-                                                    const int *__restrict__ edge_dst, int nn,
-                                                    const uint16_t *__restrict__ W, const float *__restrict__ bias,
-                                                    int N, float *__restrict__ z, uint16_t *__restrict__ cat_next,
-                                                    float *__restrict__ xdelta) {
-    const int lane = threadIdx.x, r = lane & 15, kq = (lane >> 4) * 4;
-    const int i0 = blockIdx.x * 16, ia = i0 + r;
-    int nb[8];
-    int cnt = 0;
-#pragma unroll
-    for (int e = 0; e < 8; ++e) {
-        nb[e] = ia < nn ? edge_dst[e * nn + ia] : -1;
-        cnt += nb[e] >= 0 ? 1 : 0;
+__global__ __launch_bounds__(kLayerThreads) void k_ws_layer_mp(uint16_t *__restrict__ cat,
+                                                               const float *__restrict__ zp,
+                                                               const int *__restrict__ edge_dst, int nn,
+                                                               const uint16_t *__restrict__ W,
+                                                               const float *__restrict__ bias, int N,
+                                                               float *__restrict__ z, uint16_t *__restrict__ cat_next,
+                                                               float *__restrict__ xdelta) {
+    __shared__ uint16_t As[16][256 + 8];
+    __shared__ int nbs[16][8];
+    const int i0 = blockIdx.x * 16;
+    if (threadIdx.x < 128) {
+        const int r = threadIdx.x >> 3, e = threadIdx.x & 7, i = i0 + r;
+        nbs[r][e] = i < nn ? edge_dst[e * nn + i] : -1;
     }
-    f4v acc[NT];
+    __syncthreads();
+    for (int idx = threadIdx.x; idx < 16 * 256; idx += blockDim.x) {
+        const int r = idx >> 8, k = idx & 255, i = i0 + r;
+        uint16_t b = 0;
+        if (i < nn) {
+            if (k < 128) {
+                b = cat[size_t(i) * 256 + k];
+            } else {
+                const int f = k - 128;
+                float s = 0.0f;
+                int cnt = 0;
 #pragma unroll
-    for (int t = 0; t < NT; ++t) acc[t] = f4v{0.0f, 0.0f, 0.0f, 0.0f};
-    for (int k0 = 0; k0 < 256; k0 += 16) {
-        s4v a;
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const int k = k0 + kq + q;
-            uint16_t b = 0;
-            if (ia < nn) {
-                if (k < 128) {
-                    b = cat[size_t(ia) * 256 + k];
-                } else {
-                    const int f = k - 128;
-                    float s = 0.0f;
-#pragma unroll
-                    for (int e = 0; e < 8; ++e)
-                        if (nb[e] >= 0) {
-                            const float v = zp[size_t(nb[e]) * 128 + f];
-                            s += v > 0.0f ? v : 0.0f;
-                        }
-                    b = f2bf(cnt ? s / float(cnt) : 0.0f);
-                    cat[size_t(ia) * 256 + k] = b;
+                for (int e = 0; e < 8; ++e) {
+                    const int l = nbs[r][e];
+                    if (l >= 0) {
+                        const float v = zp[size_t(l) * 128 + f];
+                        s += v > 0.0f ? v : 0.0f;
+                        ++cnt;
+                    }
                 }
+                b = f2bf(cnt ? s / float(cnt) : 0.0f);
+                cat[size_t(i) * 256 + k] = b;
             }
-            a[q] = short(b);
         }
-#pragma unroll
-        for (int t = 0; t < NT; ++t) {
-            s4v bw;
-            const int jb = t * 16 + r;
-#pragma unroll
-            for (int q = 0; q < 4; ++q) bw[q] = jb < N ? short(W[size_t(jb) * 256 + k0 + kq + q]) : short(0);
-            acc[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, bw, acc[t], 0, 0, 0);
-        }
+        As[r][k] = b;
     }
-#pragma unroll
-    for (int t = 0; t < NT; ++t)
+    __syncthreads();
+    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63, r = lane & 15;
+    for (int t = wv; t < NT; t += kLayerThreads / 64) {
+        const f4v acc = tile_mfma<256>(As, W, t * 16 + r, N);
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             const int i = i0 + (lane >> 4) * 4 + q, j = t * 16 + r;
             if (i < nn && j < N) {
-                const float v = acc[t][q] + bias[j];
+                const float v = acc[q] + bias[j];
                 z[size_t(i) * N + j] = v;
                 if (cat_next) cat_next[size_t(i) * 256 + j] = f2bf(v > 0.0f ? v : 0.0f);
                 if (xdelta) xdelta[size_t(j) * nn + i] = v * (j < 3 ? 0.05f : 0.01f);
             }
         }
+    }
 }
 
 template __global__ void k_ws_layer_mp<8>(uint16_t *, const float *, const int *, int, const uint16_t *, const float *,
@@ -186,7 +189,7 @@ template __global__ void k_ws_layer_mp<8>(uint16_t *, const float *, const int *
 template __global__ void k_ws_layer_mp<1>(uint16_t *, const float *, const int *, int, const uint16_t *, const float *,
                                           int, float *, uint16_t *, float *);
 
-
+// ---------------------------------------------------------------- message passing (backward)
 // Backward through [h; mean(h)] and the ReLU:
 // dz[l][f] = (dcat[l][f] + sum over in-edges (k -> l) of dcat[k][width + f] / |N(k)|) * (z[l][f] > 0)
 __global__ void k_mean_bwd(const float *__restrict__ dcat, const float *__restrict__ z, int nn,
@@ -206,13 +209,22 @@ __global__ void k_mean_bwd(const float *__restrict__ dcat, const float *__restri
     dzb[i] = f2bf(v);
 }
 
-// Column sums (bias gradients): out[j] = sum_i in[i][j], fixed order per column.
-__global__ void k_colsum(const float *__restrict__ in, int rows, int cols, float *__restrict__ out) {
-    const int j = blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= cols) return;
+// Column sums (bias gradients): out[j] = sum_i in[i][j].  One block per
+// column; strided partial sums, then a fixed-order tree, so the result does
+// not depend on timing.
+__global__ __launch_bounds__(256) void k_colsum(const float *__restrict__ in, int rows, int cols,
+                                                float *__restrict__ out) {
+    __shared__ float part[256];
+    const int j = blockIdx.x;
     float s = 0.0f;
-    for (int i = 0; i < rows; ++i) s += in[size_t(i) * cols + j];
-    out[j] = s;
+    for (int i = threadIdx.x; i < rows; i += blockDim.x) s += in[size_t(i) * cols + j];
+    part[threadIdx.x] = s;
+    __syncthreads();
+    for (int h = blockDim.x / 2; h > 0; h >>= 1) {
+        if (threadIdx.x < h) part[threadIdx.x] += part[threadIdx.x + h];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[j] = part[0];
 }
 
 // dy = 2 (y - t) / (6 nn), fp32 and bf16; per-item squared error for the loss.

@@ -84,12 +84,29 @@ def smooth_field(xyz, n_ctrl, rng, rot_sigma=0.05, trans_sigma=0.01):
     out = np.zeros_like(p)
     wsum = np.zeros(p.shape[0])
     mats = rot.as_matrix()
-    for m in range(n_ctrl):
-        d2 = ((p - c[m]) ** 2).sum(axis=1)
-        w = np.exp(-d2 / (2.0 * sigma * sigma))
-        moved = (p - c[m]) @ mats[m].T + c[m] + trans[m]
-        out += w[:, None] * moved
-        wsum += w
+    if n_ctrl * p.shape[0] <= 5e7:
+        for m in range(n_ctrl):
+            d2 = ((p - c[m]) ** 2).sum(axis=1)
+            w = np.exp(-d2 / (2.0 * sigma * sigma))
+            moved = (p - c[m]) @ mats[m].T + c[m] + trans[m]
+            out += w[:, None] * moved
+            wsum += w
+    else:
+        # large meshes: each control point only touches vertices within 6 sigma
+        # (the kernel is below exp(-18) beyond), found with a k-d tree
+        from scipy.spatial import cKDTree
+        tree = cKDTree(p)
+        for m in range(n_ctrl):
+            idx = np.asarray(tree.query_ball_point(c[m], 6.0 * sigma), dtype=np.int64)
+            if idx.size == 0:
+                continue
+            q = p[idx] - c[m]
+            w = np.exp(-(q * q).sum(axis=1) / (2.0 * sigma * sigma))
+            out[idx] += w[:, None] * (q @ mats[m].T + c[m] + trans[m])
+            wsum[idx] += w
+        far = wsum == 0.0          # beyond every control point's support: left in place
+        out[far] = p[far]
+        wsum[far] = 1.0
     out /= wsum[:, None]
     return np.ascontiguousarray(out.T.astype(np.float32))
 
