@@ -46,6 +46,14 @@ def algorithmic_bytes(kernel, n_act, n_nodes, n_edges, n_pix, n_faces, n_verts):
         return 12 * n_faces + 12 * n_verts + 8 * n_pix // 4
     if kernel in ("contour", "decide", "deform_start", "contour_edges"):
         return 5 * n_pix if kernel == "contour" else 64 * n_verts
+    if kernel == "pose_step":      # the 69 x 70 float64 system in, the pose out
+        return 8 * 69 * 70 + 8 * 69
+    if kernel == "pose_jtj":       # the Jacobian (about 115 + 400 rows x 80 float64) in, the system out
+        return 8 * 515 * 80 + 8 * 69 * 70
+    if kernel == "pose_rows":      # rows out, per contour vertex 44 B of vertex data in
+        return 8 * 515 * 80 + 44 * 400
+    if kernel == "pose_lbs":       # 5,000 vertices: xyz + binding in, positions out
+        return 5000 * (12 + 32 + 12)
     return 0
 
 
@@ -282,7 +290,7 @@ def bench_batch(args, cap, torch):
     n = args.batch if args.batch > 1 else 64
     log("generating %d frames" % n)
     frames_h = synth.make_batch(n, 0, workers=min(8, len(os.sched_getaffinity(0))))
-    gn, pcg, weights = 3, 8, (1.0, 0.1, 10.0)
+    gn, pcg, weights = 5, 10, (1.0, 0.1, 10.0)      # the small configuration's schedule and weights
     ctx = cap.Context(0)
     prm = cap.params(*weights, gn_iters=gn, pcg_iters=pcg)
     dev_in = []
@@ -428,11 +436,11 @@ def main():
             # frames at the 25th, 50th and 75th percentile of vertex count; rate = 1 / mean time
             order = sorted(range(len(data)), key=lambda i: data[i]["xyz"].shape[1])
             pick = [order[len(order) * q // 4] for q in (1, 2, 3)]
-            rates = [cpu_baseline(data[i], data[i]["n_nodes"], 3, 8, (1.0, 0.1, 10.0)) for i in pick]
+            rates = [cpu_baseline(data[i], data[i]["n_nodes"], 5, 10, (1.0, 0.1, 10.0)) for i in pick]
             cb = dict(rates[0])
             cb["value"] = 1.0 / float(np.mean([1.0 / r["value"] for r in rates]))
             cb["sample"] = ("3 frames of the batch (%s vertices: its 25th/50th/75th percentile), each per-frame "
-                            "preprocessing + 3 GN steps with exact sparse-Cholesky solves in float64; rate = 1 / mean "
+                            "preprocessing + 5 GN steps with exact sparse-Cholesky solves in float64; rate = 1 / mean "
                             "time" % "/".join(str(data[i]["xyz"].shape[1]) for i in pick))
             result["cpu_baseline"] = cb
         elif args.mode == "sequence":

@@ -24,13 +24,16 @@ __global__ void k_raster(const ProbDev *P);
 __global__ void k_raster_big(const ProbDev *P);
 __global__ void k_contour_edges(const ProbDev *P);
 __global__ void k_decide(const ProbDev *P);
-__global__ void k_linearize(const ProbDev *P, int mode);
-__global__ void k_apply(const ProbDev *P);
+__global__ void k_linearize(const ProbDev *P, const int *item_beg, int n, int mode);
+__global__ void k_apply(const ProbDev *P, const int *item_beg, int n);
 __global__ void k_node_init(const ProbDev *P, int gn, int energy_only, int check_target);
 __global__ void k_node_gather(const ProbDev *P);
 __global__ void k_node_pcg(const ProbDev *P, int last, int update_only);
 __global__ void k_scal_init(const ProbDev *P, int gn_iters);
 __global__ void k_clear_zbuf(const ProbDev *P);
+__global__ void k_pcg_split_a(const ProbDev *P);
+__global__ void k_pcg_split_b(const ProbDev *P, int it);
+__global__ void k_pcg_split_c(const ProbDev *P, int it, int last);
 int build_template(const capture_template_desc *d, capture_template **out, int device);
 
 // warm-start kernels (warmstart.hip)
@@ -47,7 +50,7 @@ __global__ void k_ws_layer1(const float *X, int nn, const float *mu, const float
 template <int NT>
 __global__ void k_ws_layer_mp(uint16_t *cat, const float *zp, const int *edge_dst, int nn, const uint16_t *W,
                               const float *bias, int N, float *z, uint16_t *cat_next, float *xdelta);
-__global__ void k_ws_select(const ProbDev *P, int slot_prev, int slot_pred);
+__global__ void k_ws_select(const ProbDev *P, int slot_prev, int slot_pred, int gn_iters);
 __global__ void k_ws_target(const float *prev, const float *next, int nn, float *target);
 __global__ void k_ws_scaling(const float *X, long long rows, float *mu, float *sd);
 
@@ -211,6 +214,7 @@ void carve(Layout &L, uint8_t *base, const capture_frame &f, ProbDev &pr) {
     pr.Hm = L.take<float>(base, 6 * nv);
     pr.partial = L.take<float>(base, size_t(T.nslots) * 12);
     pr.gpos = L.take<float>(base, size_t(3) * nn);
+    pr.dots = L.take<double>(base, 2 * ((6 * nn + kSplitItems - 1) / kSplitItems));
     pr.tile_e = L.take<double>(base, size_t(T.ntiles) * kTerms);
     pr.pva = L.take<float>(base, 3 * nv);
     float **vecs[8] = {&pr.b, &pr.diag, &pr.dinv, &pr.x, &pr.r, &pr.z, &pr.p, &pr.Ap};
@@ -227,7 +231,8 @@ struct Plan {
 Plan plan_workspace(int n, const capture_frame *frames, uint8_t *base, std::vector<ProbDev> *probs) {
     Layout L;
     Plan pl;
-    L.take<ProbDev>(base, n);
+    // descriptors, then the tile-kernel work list (prefix of tile counts), one upload
+    L.take<uint8_t>(base, sizeof(ProbDev) * n + sizeof(int) * (n + 1));
     double *scal = L.take<double>(base, size_t(kScalars) * n);
     int *counts = L.take<int>(base, size_t(3) * n);
     for (int i = 0; i < n; ++i) {
@@ -315,6 +320,7 @@ int setup(Run &R, capture_ctx *ctx, int n, const capture_frame *frames, const ca
         const TemplateDev &T = pr.T;
         R.max_nv = std::max(R.max_nv, T.nv);
         R.max_nf = std::max(R.max_nf, T.nf);
+        R.max_nn = std::max(R.max_nn, T.nn);
         R.max_me = std::max(R.max_me, T.nmedges);
         R.max_tiles = std::max(R.max_tiles, T.ntiles);
         R.max_hw = std::max(R.max_hw, pr.W * pr.H);
@@ -324,10 +330,16 @@ int setup(Run &R, capture_ctx *ctx, int n, const capture_frame *frames, const ca
         R.lds_apply = std::max(R.lds_apply, sizeof(float) * (size_t(T.max_slots) * 21 + size_t(T.max_contrib) * 6));
     }
     // sized once for both the descriptors and the report read-back of `collect`
-    void *stage = staging(ctx, sizeof(ProbDev) * n + sizeof(double) * kScalars * n + sizeof(int) * 3 * n + 512);
+    const size_t desc = sizeof(ProbDev) * n + sizeof(int) * (n + 1);
+    void *stage = staging(ctx, desc + sizeof(double) * kScalars * n + sizeof(int) * 3 * n + 512);
     if (!stage) return fail(CAPTURE_ENOMEM, "pinned staging allocation failed");
     std::memcpy(stage, R.probs.data(), sizeof(ProbDev) * n);
-    CAP_HIP(hipMemcpyAsync(R.dprobs, stage, sizeof(ProbDev) * n, hipMemcpyHostToDevice, R.s));
+    int *ib = reinterpret_cast<int *>(static_cast<uint8_t *>(stage) + sizeof(ProbDev) * n);
+    ib[0] = 0;
+    for (int i = 0; i < n; ++i) ib[i + 1] = ib[i] + R.probs[i].T.ntiles;
+    R.total_tiles = ib[n];
+    R.item_beg = reinterpret_cast<int *>(base + sizeof(ProbDev) * n);
+    CAP_HIP(hipMemcpyAsync(R.dprobs, stage, desc, hipMemcpyHostToDevice, R.s));
     return CAPTURE_OK;
 }
 
@@ -378,7 +390,7 @@ int launch_frame(Run &R, int gn_iters = 0) {
 
 void launch_linearize(Run &R, int gn, int energy_only, int check_target = 0) {
     timed(R, K_LIN, [&] {
-        hipLaunchKernelGGL(k_linearize, dim3(R.max_tiles, R.n), dim3(kTileThreads), R.lds_lin, R.s, R.dprobs,
+        hipLaunchKernelGGL(k_linearize, dim3(unsigned(R.total_tiles)), dim3(kTileThreads), R.lds_lin, R.s, R.dprobs, R.item_beg, R.n,
                            energy_only);
     });
     timed(R, K_NODE_INIT, [&] {
@@ -387,16 +399,25 @@ void launch_linearize(Run &R, int gn, int energy_only, int check_target = 0) {
     });
 }
 
-int launch_solve(Run &R, const capture_nonrigid_params *prm, int check_target = 0) {
+// first_done: step 0's linearisation has already been launched.
+int launch_solve(Run &R, const capture_nonrigid_params *prm, int check_target = 0, bool first_done = false) {
     for (int gn = 0; gn < prm->gn_iters; ++gn) {
-        launch_linearize(R, gn, 0, check_target);
+        if (gn > 0 || !first_done) launch_linearize(R, gn, 0, check_target);
         for (int j = 0; j < prm->pcg_iters; ++j) {
             timed(R, K_APPLY, [&] {
-    hipLaunchKernelGGL(k_apply, dim3(R.max_tiles, R.n), dim3(kTileThreads), R.lds_apply, R.s, R.dprobs);
+                hipLaunchKernelGGL(k_apply, dim3(unsigned(R.total_tiles)), dim3(kTileThreads), R.lds_apply, R.s,
+                                   R.dprobs, R.item_beg, R.n);
             });
             timed(R, K_NODE_PCG, [&] {
-    hipLaunchKernelGGL(k_node_pcg, dim3(R.n), dim3(kNodeThreads), 0, R.s, R.dprobs,
-                                   j == prm->pcg_iters - 1 ? 1 : 0, 0);
+                const int last = j == prm->pcg_iters - 1 ? 1 : 0;
+                if (6 * R.max_nn > kSplitMinItems) {
+                    const dim3 g(unsigned((6 * R.max_nn + kSplitItems - 1) / kSplitItems), unsigned(R.n));
+                    hipLaunchKernelGGL(k_pcg_split_a, g, dim3(kSplitThreads), 0, R.s, R.dprobs);
+                    hipLaunchKernelGGL(k_pcg_split_b, g, dim3(kSplitThreads), 0, R.s, R.dprobs, j);
+                    hipLaunchKernelGGL(k_pcg_split_c, g, dim3(kSplitThreads), 0, R.s, R.dprobs, j, last);
+                } else {
+                    hipLaunchKernelGGL(k_node_pcg, dim3(R.n), dim3(kNodeThreads), 0, R.s, R.dprobs, last, 0);
+                }
             });
         }
         if (prm->pcg_iters == 0)
@@ -418,9 +439,9 @@ int launch_solve(Run &R, const capture_nonrigid_params *prm, int check_target = 
 int launch_graph(Run &R, const capture_nonrigid_params *prm) {
     capture_ctx *ctx = R.ctx;
     char key[512];
-    std::snprintf(key, sizeof key, "%d|%p|%d %d %d %d %d %d %d|%zu %zu|%d %d", R.n, (void *)R.dprobs, R.max_nv,
-                  R.max_nf, R.max_hw, R.max_w, R.max_h, R.max_tiles, R.max_me, R.lds_lin, R.lds_apply, prm->gn_iters,
-                  prm->pcg_iters);
+    std::snprintf(key, sizeof key, "%d|%p|%d %d %d %d %d %d %d %d %d|%zu %zu|%d %d", R.n, (void *)R.dprobs, R.max_nv,
+                  R.max_nf, R.max_nn, R.max_hw, R.max_w, R.max_h, R.max_tiles, R.total_tiles, R.max_me, R.lds_lin,
+                  R.lds_apply, prm->gn_iters, prm->pcg_iters);
     auto &cache = ctx->graph_cache;
     hipGraphExec_t exec = nullptr;
     for (size_t i = 0; i < cache.size(); ++i)
@@ -504,16 +525,16 @@ void gemm(hipStream_t s, const uint16_t *A, long long sai, long long sak, const 
 }
 
 // Forward pass on raw features X (device, [nn][32]) -> net->y [nn][6].
-// Network forward: three fused layer kernels (one 4-wave workgroup per 16 nodes); with
+// Network forward: three fused layer kernels (one 8-wave workgroup per 16 nodes); with
 // xdelta the last one also writes the scaled update in node-major layout.
 void ws_forward(capture_warmstart *net, const TemplateDev &T, const float *X, hipStream_t s, float *xdelta = nullptr) {
     const int nn = T.nn;
     const dim3 g(unsigned((nn + 15) / 16));
-    hipLaunchKernelGGL(k_ws_layer1, g, dim3(256), 0, s, X, nn, net->mu, net->sd, net->wb + kOffW1, net->w + kOffB1,
+    hipLaunchKernelGGL(k_ws_layer1, g, dim3(512), 0, s, X, nn, net->mu, net->sd, net->wb + kOffW1, net->w + kOffB1,
                        net->Xb, net->z1, net->c1);
-    hipLaunchKernelGGL(k_ws_layer_mp<8>, g, dim3(256), 0, s, net->c1, net->z1, T.edge_dst, nn, net->wb + kOffW2,
+    hipLaunchKernelGGL(k_ws_layer_mp<8>, g, dim3(512), 0, s, net->c1, net->z1, T.edge_dst, nn, net->wb + kOffW2,
                        net->w + kOffB2, 128, net->z2, net->c2, (float *)nullptr);
-    hipLaunchKernelGGL(k_ws_layer_mp<1>, g, dim3(256), 0, s, net->c2, net->z2, T.edge_dst, nn, net->wb + kOffW3,
+    hipLaunchKernelGGL(k_ws_layer_mp<1>, g, dim3(512), 0, s, net->c2, net->z2, T.edge_dst, nn, net->wb + kOffW3,
                        net->w + kOffB3, 6, net->y, (uint16_t *)nullptr, xdelta);
 }
 
@@ -742,7 +763,7 @@ int capture_linearize(capture_ctx *ctx, const capture_frame *frame, const captur
         CAP_HIP(hipMemcpyAsync(pr.p, p, sizeof(float) * n6, hipMemcpyDeviceToDevice, R.s));
         CAP_HIP(hipMemcpyAsync(pr.scal + 1, &zero, sizeof(double), hipMemcpyHostToDevice, R.s));
         timed(R, K_APPLY, [&] {
-    hipLaunchKernelGGL(k_apply, dim3(R.max_tiles, 1), dim3(kTileThreads), R.lds_apply, R.s, R.dprobs);
+    hipLaunchKernelGGL(k_apply, dim3(unsigned(R.total_tiles)), dim3(kTileThreads), R.lds_apply, R.s, R.dprobs, R.item_beg, R.n);
         });
         hipLaunchKernelGGL(k_node_gather, dim3(1), dim3(kNodeThreads), 0, R.s, R.dprobs);
         CAP_HIP(hipGetLastError());
@@ -937,10 +958,10 @@ int capture_nonrigid_solve_warm(capture_ctx *ctx, const capture_frame *frame, co
     R.probs[0].target = target_energy;
     CAP_HIP(hipMemcpyAsync(R.dprobs, R.probs.data(), sizeof(ProbDev), hipMemcpyHostToDevice, R.s));
     const ProbDev &pr = R.probs[0];
-    const int pred_slot = CAPTURE_MAX_GN + 1;
+    const int prev_slot = CAPTURE_MAX_GN + 1;     // energy at the given start (x_{t-1})
     if ((rc = launch_frame(R, params->gn_iters))) return rc;     // keeps the given state in state0
     // linearisation at the previous frame's state: features and E(x_{t-1})
-    launch_linearize(R, 0, 0);
+    launch_linearize(R, prev_slot, 0);
     timed(R, K_WS_FEAT, [&] {
         hipLaunchKernelGGL(k_ws_features, dim3(blocks(pr.T.nn, 256), 1), dim3(256), 0, R.s, R.dprobs, state_prev2,
                            net->X);
@@ -949,9 +970,17 @@ int capture_nonrigid_solve_warm(capture_ctx *ctx, const capture_frame *frame, co
         ws_forward(net, pr.T, net->X, R.s, pr.x);
     });
     hipLaunchKernelGGL(k_node_pcg, dim3(1), dim3(kNodeThreads), 0, R.s, R.dprobs, 0, 1);   // x' = x (+) delta
-    launch_linearize(R, pred_slot, 1);
-    hipLaunchKernelGGL(k_ws_select, dim3(1), dim3(256), 0, R.s, R.dprobs, 0, pred_slot);
-    if ((rc = launch_solve(R, params, 1))) return rc;
+    // step 0's full linearisation at x' doubles as the energy test of the prediction;
+    // after a rejection the restored start is linearised again (conditional pass)
+    launch_linearize(R, 0, 0, 1);
+    hipLaunchKernelGGL(k_ws_select, dim3(1), dim3(256), 0, R.s, R.dprobs, prev_slot, 0, params->gn_iters);
+    timed(R, K_LIN, [&] {
+        hipLaunchKernelGGL(k_linearize, dim3(unsigned(R.total_tiles)), dim3(kTileThreads), R.lds_lin, R.s, R.dprobs, R.item_beg, R.n, 2);
+    });
+    timed(R, K_NODE_INIT, [&] {
+        hipLaunchKernelGGL(k_node_init, dim3(R.n), dim3(kNodeThreads), 0, R.s, R.dprobs, 0, 0, 3);
+    });
+    if ((rc = launch_solve(R, params, 1, true))) return rc;
     std::vector<double> sc(kScalars);
     CAP_HIP(hipMemcpyAsync(sc.data(), pr.scal, sizeof(double) * kScalars, hipMemcpyDeviceToHost, R.s));
     rc = collect(R, params->gn_iters, report);

@@ -33,6 +33,9 @@ constexpr int kMaxImageSide = 4096;
 constexpr int kRasterSmall = 256;         // pixel-box size above which a face is rasterised by a workgroup
 constexpr int kRasterBigBlocks = 512;
 constexpr int kGraphCache = 16;          // captured solve graphs kept per context
+constexpr int kSplitThreads = 256;       // PCG split over workgroups for large node counts:
+constexpr int kSplitItems = 1024;        //   (component, node) items per workgroup
+constexpr int kSplitMinItems = 8192;     //   used when 6 * n_nodes exceeds this (one workgroup's register capacity)
 constexpr int kTerms = 5;   // energy terms per slot: photo, sil (with b), sil (with |b|), arap, velocity
 constexpr int kScalars = 8 + kTerms * (CAPTURE_MAX_GN + 2);   // slot MAX_GN + 1: predicted start
 
@@ -113,6 +116,7 @@ struct ProbDev {
     // nodes
     float *b, *diag, *dinv, *x, *r, *z, *p, *Ap;   // [6][nn]
     double *scal;     // [kScalars]: rz, done, stopped, stop step, ..., kTerms energies per GN step
+    double *dots;     // [2][split blocks] per-workgroup dot-product sums of the split PCG
     int *counts;      // [3] visible, contour set, queued large faces
     int *bigq;        // [nf] faces rasterised by k_raster_big
     float *state0;    // [12][nn] copy of the start state (restored on a device-detected error)

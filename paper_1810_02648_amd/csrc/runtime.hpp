@@ -38,8 +38,10 @@ struct Run {
     int n = 0;
     std::vector<ProbDev> probs;
     ProbDev *dprobs = nullptr;
-    int max_nv = 0, max_nf = 0, max_hw = 0, max_w = 0, max_h = 0, max_tiles = 0, max_me = 0;
+    int max_nv = 0, max_nf = 0, max_nn = 0, max_hw = 0, max_w = 0, max_h = 0, max_tiles = 0, max_me = 0;
     size_t lds_lin = 0, lds_apply = 0;
+    int *item_beg = nullptr;     // device [n + 1]: prefix of the problems' tile counts
+    int total_tiles = 0;
     hipStream_t s = nullptr;
 };
 

@@ -1,5 +1,5 @@
 // Gauss-Newton / PCG kernels of the non-rigid stage (Sec. 3.4 energy, Sec. 4
-// solver).  Tile kernels (blockIdx.x = tile, blockIdx.y = problem) stream the
+// solver).  Tile kernels (one block per tile of every problem) stream the
 // plan-ordered vertices once and accumulate per-node 6-vectors in LDS; node
 // kernels (one workgroup per problem) finish the per-node sums in a fixed
 // order and run the PCG vector updates with float64 dot products.
@@ -44,6 +44,18 @@ __device__ inline void load_slots(const ProbDev &pr, int sb, int ns, TileLds &L,
     }
 }
 
+// Work item -> (problem, tile) of the flattened tile grid: item_beg is the
+// prefix of the problems' tile counts (one block per tile of every problem,
+// no idle blocks for the smaller problems of a batch).
+__device__ inline int item_problem(const int *__restrict__ item_beg, int n, int item) {
+    int lo = 0, hi = n;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (item_beg[mid] <= item) lo = mid; else hi = mid;
+    }
+    return lo;
+}
+
 // Slot offsets of the tile's contributions in slot order, into LDS.  The
 // contributions are stored component-major, C[comp][position], where each
 // vertex binding and regulariser edge end has a fixed position (plan_cpos,
@@ -70,25 +82,30 @@ __device__ inline void rot_apply(const float *R, const float d[3], float q[3]) {
 // Linearisation: residuals, per-vertex condensed normal-equation blocks
 // H_i = sum |b| G^T G (3x3) and g_i = sum b G^T r, the energy, and per-slot
 // partial sums of the right-hand side -J^T B F and of diag(J^T |B| J).
-// mode 0: full; mode 1: energy only.
+// mode bit 0: energy only; bit 1: run only if the warm start rejected its
+// prediction (scal[5] set), i.e. relinearise at the restored start.
 // ----------------------------------------------------------------------------
-__global__ __launch_bounds__(kTileThreads) void k_linearize(const ProbDev *__restrict__ P, int mode) {
+__global__ __launch_bounds__(kTileThreads) void k_linearize(const ProbDev *__restrict__ P,
+                                                            const int *__restrict__ item_beg, int n, int mode) {
     extern __shared__ float lds[];
     __shared__ double red[kTileThreads / 64];
     __shared__ int lbeg[kMaxTileSlots + 1];
-    const ProbDev &pr = P[blockIdx.y];
+    const int prob = item_problem(item_beg, n, blockIdx.x);
+    const ProbDev &pr = P[prob];
     const TemplateDev &T = pr.T;
-    const int tile = blockIdx.x;
-    if (tile >= T.ntiles || pr.scal[2] != 0.0) return;
+    const int tile = blockIdx.x - item_beg[prob];
+    if (pr.scal[2] != 0.0) return;
+    if ((mode & 2) && pr.scal[5] == 0.0) return;      // conditional pass: only after a rejected prediction
+    const bool full = (mode & 1) == 0;
     const int nv = T.nv, nn = T.nn;
     const int vb = T.tile_vbeg[tile], nvt = T.tile_vbeg[tile + 1] - vb;
     const int sb = T.tile_sbeg[tile], ns = T.tile_sbeg[tile + 1] - sb;
     const int ob = T.tile_obeg[tile], nown = T.tile_obeg[tile + 1] - ob;
     TileLds L = tile_lds(lds, ns, 12);
     load_slots(pr, sb, ns, L, false);
-    if (mode == 0) load_offsets(T, sb, ns, lbeg);
+    if (full) load_offsets(T, sb, ns, lbeg);
     __syncthreads();
-    const int NC = mode == 0 ? lbeg[ns] : 0;
+    const int NC = full ? lbeg[ns] : 0;
 
     double e_ph = 0.0, e_s = 0.0, e_sa = 0.0, e_a = 0.0, e_v = 0.0;
     const int lv = threadIdx.x;
@@ -171,7 +188,7 @@ __global__ __launch_bounds__(kTileThreads) void k_linearize(const ProbDev *__res
             }
             Hm[0] += pr.w_vel; Hm[3] += pr.w_vel; Hm[5] += pr.w_vel;
         }
-        if (mode == 0) {
+        if (full) {
             if (code & 11)
                 for (int q6 = 0; q6 < 6; ++q6) pr.Hm[size_t(q6) * nv + p] = Hm[q6];
             // contributions to the 4 bound nodes: rhs -w[q x g; g], diag w^2[diag(Q^T H Q); diag(H)]
@@ -214,7 +231,7 @@ __global__ __launch_bounds__(kTileThreads) void k_linearize(const ProbDev *__res
             }
         }
         e_a += double(r[0]) * r[0] + double(r[1]) * r[1] + double(r[2]) * r[2];
-        if (mode == 0) {
+        if (full) {
             float exr[3];
             cross3(ekl, r, exr);
             const float s = pr.sw_arap, wa = pr.w_arap;
@@ -231,7 +248,7 @@ __global__ __launch_bounds__(kTileThreads) void k_linearize(const ProbDev *__res
         }
     }
     __syncthreads();
-    if (mode == 0) {
+    if (full) {
         for (int pair = threadIdx.x; pair < ns * 12; pair += blockDim.x) {
             const int s = pair / 12, comp = pair - s * 12;
             pr.partial[size_t(T.slot_dest[sb + s]) * 12 + comp] = run_sum(L.c + comp * NC, lbeg[s], lbeg[s + 1]);
@@ -253,13 +270,15 @@ __global__ __launch_bounds__(kTileThreads) void k_linearize(const ProbDev *__res
 // f_i = H_i dV_i, node contributions w_j [q_j x f_i; f_i]; regulariser edges
 // u = w_k x e_kl + tau_k - tau_l add w_a [e x u; u] to k and w_a [0; -u] to l.
 // ----------------------------------------------------------------------------
-__global__ __launch_bounds__(kTileThreads) void k_apply(const ProbDev *__restrict__ P) {
+__global__ __launch_bounds__(kTileThreads) void k_apply(const ProbDev *__restrict__ P, const int *__restrict__ item_beg,
+                                                        int n) {
     extern __shared__ float lds[];
     __shared__ int lbeg[kMaxTileSlots + 1];
-    const ProbDev &pr = P[blockIdx.y];
+    const int prob = item_problem(item_beg, n, blockIdx.x);
+    const ProbDev &pr = P[prob];
     const TemplateDev &T = pr.T;
-    const int tile = blockIdx.x;
-    if (tile >= T.ntiles || pr.scal[1] != 0.0) return;
+    const int tile = blockIdx.x - item_beg[prob];
+    if (pr.scal[1] != 0.0) return;
     const int nv = T.nv, nn = T.nn;
     const int vb = T.tile_vbeg[tile], nvt = T.tile_vbeg[tile + 1] - vb;
     const int sb = T.tile_sbeg[tile], ns = T.tile_sbeg[tile + 1] - sb;
@@ -379,6 +398,7 @@ __global__ __launch_bounds__(kNodeThreads) void k_node_init(const ProbDev *__res
     __shared__ double red[kNodeThreads / 64];
     const ProbDev &pr = P[blockIdx.x];
     if (pr.scal[2] != 0.0) return;   // stopped at the target energy
+    if ((check_target & 2) && pr.scal[5] == 0.0) return;   // conditional pass (see k_linearize)
     const TemplateDev &T = pr.T;
     const int nn = T.nn;
     double rz = 0.0;
@@ -408,7 +428,7 @@ __global__ __launch_bounds__(kNodeThreads) void k_node_init(const ProbDev *__res
         if (!energy_only) {
             pr.scal[0] = rz;
             pr.scal[1] = rz == 0.0 ? 1.0 : 0.0;
-            if (check_target && e[0] + e[1] + e[3] + e[4] <= pr.target) {   // x = 0 above, so the step's update is void
+            if ((check_target & 1) && e[0] + e[1] + e[3] + e[4] <= pr.target) {   // x = 0 above, so the step's update is void
                 pr.scal[1] = 1.0;
                 pr.scal[2] = 1.0;
                 pr.scal[3] = double(gn);
@@ -571,6 +591,93 @@ __global__ __launch_bounds__(kNodeThreads) void k_node_pcg(const ProbDev *__rest
     if (last || update_only) {
         __syncthreads();
         for (int k = threadIdx.x; k < nn; k += blockDim.x) node_update(pr, k);
+    }
+}
+
+// ----------------------------------------------------------------------------
+// PCG iteration for large node counts, split over several workgroups per
+// problem (blockIdx.x = item block of kSplitItems (component, node) items).
+// Dot products are summed per workgroup, then every workgroup adds the
+// workgroup sums in block order, so all of them see the same value.  r.z
+// alternates between scal[0] (even iterations) and scal[7] (odd), so the
+// workgroup that stores the next value never races a reader of the current.
+// ----------------------------------------------------------------------------
+__device__ inline int split_blocks(int nn) { return (6 * nn + kSplitItems - 1) / kSplitItems; }
+
+// A p from the tile partials, and the workgroup's share of p.Ap.
+__global__ __launch_bounds__(kSplitThreads) void k_pcg_split_a(const ProbDev *__restrict__ P) {
+    __shared__ double red[kSplitThreads / 64];
+    const ProbDev &pr = P[blockIdx.y];
+    const TemplateDev &T = pr.T;
+    const int nn = T.nn, n6 = 6 * nn;
+    if (pr.scal[1] != 0.0 || int(blockIdx.x) >= split_blocks(nn)) return;
+    double pap = 0.0;
+    for (int u = 0; u < kSplitItems / kSplitThreads; ++u) {
+        const int i = blockIdx.x * kSplitItems + u * kSplitThreads + threadIdx.x;
+        if (i < n6) {
+            const int c = i / nn, k = i - c * nn;
+            const float a = gather_node(T, pr.partial, 6, k, c);
+            pr.Ap[i] = a;
+            pap += double(pr.p[i]) * double(a);
+        }
+    }
+    pap = block_sum<kSplitThreads>(pap, red);
+    if (threadIdx.x == 0) pr.dots[blockIdx.x] = pap;
+}
+
+// alpha = r.z / p.Ap; x, r, z updates; the workgroup's share of the new r.z.
+__global__ __launch_bounds__(kSplitThreads) void k_pcg_split_b(const ProbDev *__restrict__ P, int it) {
+    __shared__ double red[kSplitThreads / 64];
+    const ProbDev &pr = P[blockIdx.y];
+    const int nn = pr.T.nn, n6 = 6 * nn, G = split_blocks(nn);
+    if (pr.scal[1] != 0.0 || int(blockIdx.x) >= G) return;
+    double pap = 0.0;
+    for (int w = 0; w < G; ++w) pap += pr.dots[w];
+    if (pap <= 0.0) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) pr.scal[1] = 1.0;
+        return;
+    }
+    const double alpha = pr.scal[(it & 1) ? 7 : 0] / pap;
+    double rz2 = 0.0;
+    for (int u = 0; u < kSplitItems / kSplitThreads; ++u) {
+        const int i = blockIdx.x * kSplitItems + u * kSplitThreads + threadIdx.x;
+        if (i < n6) {
+            pr.x[i] = float(fma(alpha, double(pr.p[i]), double(pr.x[i])));
+            const float r = float(fma(-alpha, double(pr.Ap[i]), double(pr.r[i])));
+            const float z = pr.dinv[i] * r;
+            pr.r[i] = r;
+            pr.z[i] = z;
+            rz2 += double(r) * double(z);
+        }
+    }
+    rz2 = block_sum<kSplitThreads>(rz2, red);
+    if (threadIdx.x == 0) pr.dots[G + blockIdx.x] = rz2;
+}
+
+// beta = r.z' / r.z; p = z + beta p; the next r.z into the other slot.  With
+// `last`, the node update follows for this workgroup's share of the nodes.
+__global__ __launch_bounds__(kSplitThreads) void k_pcg_split_c(const ProbDev *__restrict__ P, int it, int last) {
+    const ProbDev &pr = P[blockIdx.y];
+    const int nn = pr.T.nn, n6 = 6 * nn, G = split_blocks(nn);
+    if (int(blockIdx.x) >= G) return;
+    if (pr.scal[1] == 0.0) {
+        double rz2 = 0.0;
+        for (int w = 0; w < G; ++w) rz2 += pr.dots[G + w];
+        const double beta = rz2 / pr.scal[(it & 1) ? 7 : 0];
+        for (int u = 0; u < kSplitItems / kSplitThreads; ++u) {
+            const int i = blockIdx.x * kSplitItems + u * kSplitThreads + threadIdx.x;
+            if (i < n6) pr.p[i] = float(fma(beta, double(pr.p[i]), double(pr.z[i])));
+        }
+        __syncthreads();
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            pr.scal[(it & 1) ? 0 : 7] = rz2;
+            if (rz2 == 0.0) pr.scal[1] = 1.0;
+        }
+    }
+    if (last) {
+        const int per = (nn + G - 1) / G;
+        for (int k = blockIdx.x * per + threadIdx.x; k < min(nn, int(blockIdx.x + 1) * per); k += blockDim.x)
+            node_update(pr, k);
     }
 }
 

@@ -59,31 +59,36 @@ __global__ __launch_bounds__(256) void k_gemm(Gemm g) {
 }
 
 // ---------------------------------------------------------------- fused forward
-// One workgroup (4 waves) per 16 nodes and layer.  The workgroup first forms
+// One workgroup (8 waves) per 16 nodes and layer.  The workgroup first forms
 // the layer's 16 x K bf16 input tile in LDS, each element once and with
 // coalesced loads: layer 1 standardises the raw features; layers 2 and 3 copy
 // ReLU(z_prev) and compute the mean over valid out-edges of ReLU(z_prev) of
 // the neighbours (also stored into cat for the backward pass).  Each wave
-// then owns output tiles t = wave, wave + 4 and accumulates over k in steps of
+// then owns output tile t = wave (layer 1 and 2: 8 tiles; layer 3: one) and accumulates over k in steps of
 // 16 on MFMA with B = W from global memory.  The rounding points are those
 // of the layer definition (bf16 inputs and weights, float32 accumulation in
 // ascending k, bias after the sum, the mean of float32 ReLU outputs rounded
 // once); all intermediates (Xb, z1, cat1, z2, cat2, y) stay for the backward.
-constexpr int kLayerThreads = 256;
+constexpr int kLayerThreads = 512;
 
+// One 16x16 output tile: all of the lane's weight fragments are loaded first
+// (one round of latency), then the MFMA chain runs over k from LDS.
 template <int K>
 __device__ inline f4v tile_mfma(const uint16_t (*As)[K + 8], const uint16_t *__restrict__ W, int jb, int N) {
     const int lane = threadIdx.x & 63, r = lane & 15, kq = (lane >> 4) * 4;
-    f4v acc = {0.0f, 0.0f, 0.0f, 0.0f};
-#pragma unroll 4
-    for (int k0 = 0; k0 < K; k0 += 16) {
-        s4v a, bw;
+    s4v bw[K / 16];
+    const uint16_t *wrow = W + size_t(jb < N ? jb : 0) * K + kq;
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            a[q] = short(As[r][k0 + kq + q]);
-            bw[q] = jb < N ? short(W[size_t(jb) * K + k0 + kq + q]) : short(0);
-        }
-        acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, bw, acc, 0, 0, 0);
+    for (int s = 0; s < K / 16; ++s)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) bw[s][q] = jb < N ? short(wrow[16 * s + q]) : short(0);
+    f4v acc = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+    for (int s = 0; s < K / 16; ++s) {
+        s4v a;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) a[q] = short(As[r][16 * s + kq + q]);
+        acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, bw[s], acc, 0, 0, 0);
     }
     return acc;
 }
@@ -142,7 +147,8 @@ __global__ __launch_bounds__(kLayerThreads) void k_ws_layer_mp(uint16_t *__restr
         nbs[r][e] = i < nn ? edge_dst[e * nn + i] : -1;
     }
     __syncthreads();
-    for (int idx = threadIdx.x; idx < 16 * 256; idx += blockDim.x) {
+#pragma unroll
+    for (int idx = threadIdx.x; idx < 16 * 256; idx += kLayerThreads) {
         const int r = idx >> 8, k = idx & 255, i = i0 + r;
         uint16_t b = 0;
         if (i < nn) {
@@ -150,17 +156,20 @@ __global__ __launch_bounds__(kLayerThreads) void k_ws_layer_mp(uint16_t *__restr
                 b = cat[size_t(i) * 256 + k];
             } else {
                 const int f = k - 128;
+                float v[8];
+#pragma unroll
+                for (int e = 0; e < 8; ++e) {         // all eight loads issued together (safe index when absent)
+                    const int l = nbs[r][e];
+                    v[e] = zp[size_t(l >= 0 ? l : 0) * 128 + f];
+                }
                 float s = 0.0f;
                 int cnt = 0;
 #pragma unroll
-                for (int e = 0; e < 8; ++e) {
-                    const int l = nbs[r][e];
-                    if (l >= 0) {
-                        const float v = zp[size_t(l) * 128 + f];
-                        s += v > 0.0f ? v : 0.0f;
+                for (int e = 0; e < 8; ++e)
+                    if (nbs[r][e] >= 0) {
+                        s += v[e] > 0.0f ? v[e] : 0.0f;
                         ++cnt;
                     }
-                }
                 b = f2bf(cnt ? s / float(cnt) : 0.0f);
                 cat[size_t(i) * 256 + k] = b;
             }
@@ -336,7 +345,7 @@ __global__ __launch_bounds__(256) void k_ws_features(const ProbDev *__restrict__
 // Keep the predicted start only if it lowers the energy; otherwise restore
 // the previous frame's state.  scal[4] = predicted-start energy, scal[5] = 1
 // when the prediction was rejected.
-__global__ void k_ws_select(const ProbDev *__restrict__ P, int slot_prev, int slot_pred) {
+__global__ void k_ws_select(const ProbDev *__restrict__ P, int slot_prev, int slot_pred, int gn_iters) {
     __shared__ int reject;
     const ProbDev &pr = P[blockIdx.x];
     const int nn = pr.T.nn;
@@ -347,6 +356,11 @@ __global__ void k_ws_select(const ProbDev *__restrict__ P, int slot_prev, int sl
         pr.scal[4] = E1;
         pr.scal[5] = reject ? 1.0 : 0.0;
         pr.scal[6] = E0;
+        if (reject) {      // the linearisation (and any stop) at the prediction no longer applies
+            pr.scal[1] = 0.0;
+            pr.scal[2] = 0.0;
+            pr.scal[3] = double(gn_iters);
+        }
     }
     __syncthreads();
     if (reject)

@@ -328,3 +328,24 @@ def test_tile_size_autotuner_and_tile_independence(ctx, frames):
         assert np.linalg.norm(r_gpu - r_ref) <= 1e-4 * max(np.linalg.norm(r_ref), 1e-6), tile
         assert np.linalg.norm(t_gpu - t_ref) <= 1e-4 * max(np.linalg.norm(t_ref), 1e-6), tile
         assert abs(rep["energy"][-1] - ref["energies"][-1]["total"]) <= 1e-5 * ref["energies"][0]["total"]
+
+
+def test_large_graph_split_pcg_matches_oracle(ctx):
+    """More than 1365 nodes: the PCG iteration runs split over workgroups."""
+    import paper_1810_02648_amd as cap
+    from gpu_util import make_frame
+    f = synth.make_nonrigid_frame("small", 5, n_vertices=12001, n_nodes=1500, side=400)
+    g = og.build_graph(f["xyz"], 1500)
+    P = onr.Problem(f["xyz"], f["tri"], f["rgb"], g, f["cam"], f["mask"], f["image"], f["weights"])
+    ref = onr.solve(P, 2, "pcg", 6)
+    fr = make_frame(ctx, f, g)
+    rep = cap.nonrigid_solve(ctx, fr, cap.params(*f["weights"], gn_iters=2, pcg_iters=6))
+    r_gpu, t_gpu = params_of(fr.node_state.cpu().numpy())
+    r_ref, t_ref = params_of(ref["state"])
+    er = np.linalg.norm(r_gpu - r_ref) / max(np.linalg.norm(r_ref), 1e-6)
+    et = np.linalg.norm(t_gpu - t_ref) / max(np.linalg.norm(t_ref), 1e-6)
+    print("split pcg: rel r err %.2e t err %.2e" % (er, et), flush=True)
+    assert er <= 1e-4 and et <= 1e-4
+    e0 = ref["energies"][0]["total"]
+    for k, e in enumerate(ref["energies"]):
+        assert abs(rep["energy"][k] - e["total"]) <= 1e-5 * e0, k
