@@ -102,6 +102,7 @@ def bench_sequence(args, cap, torch):
     log("generating sequence", args.workload)
     seq = synth.sequence.make_sequence(args.workload, 0)
     ctx = cap.Context(0)
+    cap.set_graphs(ctx, not args.no_graphs)
     S = sq.DeviceSequence(ctx, seq)
     log("plain tracking over %d frames" % S.n)
     states, _ = sq.track_plain(S)
@@ -148,6 +149,7 @@ def bench_sequence(args, cap, torch):
         "dtype": "f32",
         "data": "synthetic",
         "config": {
+            "launch": "eager" if args.no_graphs else "HIP graph replay",
             "workload": "%s: %d-frame sequence, %d-vertex template, %d-node graph, %dx%d targets, %d GN x %d PCG; "
                         "train frames 1-%d, held-out frames %d-%d; one step = all held-out frames solved from "
                         "the learned start until the plain schedule's final energy"
@@ -176,6 +178,7 @@ def bench_frame(args, cap, torch):
     f = synth.make_nonrigid_frame(args.workload, 0)
     nn, gn, pcg = f["n_nodes"], f["gn"], f["pcg"]
     ctx = cap.Context(0)
+    cap.set_graphs(ctx, not args.no_graphs)
     xyz = torch.from_numpy(f["xyz"]).cuda()
     graph = cap.graph_build(ctx, xyz, nn)                     # on the GPU, per template (not timed)
     tri = torch.from_numpy(f["tri"]).cuda()
@@ -261,6 +264,7 @@ def bench_frame(args, cap, torch):
         "dtype": "f32",
         "data": "synthetic",
         "config": {
+            "launch": "eager" if args.no_graphs else "HIP graph replay",
             "workload": "%s: %s%d-vertex ellipsoid template, %d-node deformation graph, %dx%d silhouette/colour "
                         "targets, %d GN x %d PCG, plain start (rest state)"
                         % (args.workload, "pose stage + " if pose is not None else "", f["xyz"].shape[1], nn, W, H,
@@ -292,6 +296,7 @@ def bench_batch(args, cap, torch):
     frames_h = synth.make_batch(n, 0, workers=min(8, len(os.sched_getaffinity(0))))
     gn, pcg, weights = 5, 10, (1.0, 0.1, 10.0)      # the small configuration's schedule and weights
     ctx = cap.Context(0)
+    cap.set_graphs(ctx, not args.no_graphs)
     prm = cap.params(*weights, gn_iters=gn, pcg_iters=pcg)
     dev_in = []
     for f in frames_h:
@@ -372,6 +377,7 @@ def bench_batch(args, cap, torch):
         "dtype": "f32",
         "data": "synthetic",
         "config": {
+            "launch": "eager" if args.no_graphs else "HIP graph replay",
             "workload": "batch of %d independent frames, log-uniform 4k-40k vertices, 128-1000 nodes, 512-1080 px "
                         "square images (%d vertices, %.1f Mpx in total), %d GN x %d PCG, plain start, one batched "
                         "call per step" % (n, sum(nv), sum(f["cam"].width ** 2 for f in frames_h) / 1e6, gn, pcg),
@@ -401,6 +407,8 @@ def main():
     ap.add_argument("--epochs", type=int, default=40, help="sequence mode: training epochs")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-pose", action="store_true", help="frame mode: leave out the pose stage")
+    ap.add_argument("--no-graphs", action="store_true",
+                    help="launch every kernel eagerly instead of replaying captured HIP graphs")
     ap.add_argument("--tile", type=int, default=0, help="frame/batch mode: vertices per tile (0 = library default)")
     args = ap.parse_args()
     if args.gpus != 1:

@@ -369,13 +369,15 @@ CAPTURE_API int capture_pose_linearize(capture_ctx *ctx, const capture_pose_fram
                                        const capture_pose_params *params, double *system, double *energy,
                                        uint8_t *vflags, void *workspace, size_t workspace_bytes, void *stream);
 
-/* Launch mode of capture_batch_solve / capture_nonrigid_solve.  With `on`,
- * the per-frame launch sequence (preprocessing, decisions and the full
- * Gauss-Newton/PCG schedule) is captured into a HIP graph the first time a
- * launch shape (frame count, sizes, workspace address, schedule) is seen and
- * replayed afterwards (at most 16 graphs per context, least recently used
- * dropped); results are identical to eager launches.  Off by default; while
- * kernel timing is enabled, solves launch eagerly. */
+/* Launch mode of capture_batch_solve / capture_nonrigid_solve /
+ * capture_nonrigid_solve_warm.  With `on`, the per-frame launch sequence
+ * (preprocessing, decisions, the warm-start prediction and selection, and the
+ * full Gauss-Newton/PCG schedule) is captured into a HIP graph the first time
+ * a launch shape (frame count, sizes, workspace address, schedule; for the
+ * learned start also the network and template) is seen and replayed
+ * afterwards (at most 16 graphs per context, least recently used dropped);
+ * results are identical to eager launches.  Off by default; while kernel
+ * timing is enabled, solves launch eagerly. */
 CAPTURE_API int capture_set_graphs(capture_ctx *ctx, int on);
 
 /* --------------------------------------------------------------------------

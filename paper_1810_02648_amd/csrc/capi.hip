@@ -24,8 +24,8 @@ __global__ void k_raster(const ProbDev *P);
 __global__ void k_raster_big(const ProbDev *P);
 __global__ void k_contour_edges(const ProbDev *P);
 __global__ void k_decide(const ProbDev *P);
-__global__ void k_linearize(const ProbDev *P, const int *item_beg, int n, int mode);
-__global__ void k_apply(const ProbDev *P, const int *item_beg, int n);
+__global__ void k_linearize(const ProbDev *P, const TileDesc *D, int mode);
+__global__ void k_apply(const ProbDev *P, const TileDesc *D);
 __global__ void k_node_init(const ProbDev *P, int gn, int energy_only, int check_target);
 __global__ void k_node_gather(const ProbDev *P);
 __global__ void k_node_pcg(const ProbDev *P, int last, int update_only);
@@ -44,7 +44,7 @@ __global__ void k_colsum(const float *in, int rows, int cols, float *out);
 __global__ void k_mse_grad(const float *y, const float *t, int n, float *dy, uint16_t *dyb, float *se);
 __global__ void k_adam(float *w, const float *g, float *m, float *v, uint16_t *wb, int n, float lr, float c1, float c2);
 __global__ void k_to_bf16(const float *in, uint16_t *out, int n);
-__global__ void k_ws_features(const ProbDev *P, const float *prev2, float *X);
+__global__ void k_ws_features(const ProbDev *P, float *X);
 __global__ void k_ws_layer1(const float *X, int nn, const float *mu, const float *sd, const uint16_t *W,
                             const float *bias, uint16_t *Xb, float *z, uint16_t *cat);
 template <int NT>
@@ -217,8 +217,8 @@ void carve(Layout &L, uint8_t *base, const capture_frame &f, ProbDev &pr) {
     pr.dots = L.take<double>(base, 2 * ((6 * nn + kSplitItems - 1) / kSplitItems));
     pr.tile_e = L.take<double>(base, size_t(T.ntiles) * kTerms);
     pr.pva = L.take<float>(base, 3 * nv);
-    float **vecs[8] = {&pr.b, &pr.diag, &pr.dinv, &pr.x, &pr.r, &pr.z, &pr.p, &pr.Ap};
-    for (float **v : vecs) *v = L.take<float>(base, 6 * nn);
+    gptr<float> *vecs[8] = {&pr.b, &pr.diag, &pr.dinv, &pr.x, &pr.r, &pr.z, &pr.p, &pr.Ap};
+    for (gptr<float> *v : vecs) *v = L.take<float>(base, 6 * nn);
     pr.state0 = L.take<float>(base, 12 * nn);
 }
 
@@ -228,11 +228,17 @@ struct Plan {
 
 // Layout: the descriptors, one block with every problem's scalars and counters
 // (read back by a single copy), then each problem's buffers.
+int grid_tiles(int n, const capture_frame *frames) {
+    long long t = 0;
+    for (int i = 0; i < n; ++i) t += frames[i].tmpl->dev.ntiles;
+    return int((t + 7) / 8 * 8);
+}
+
 Plan plan_workspace(int n, const capture_frame *frames, uint8_t *base, std::vector<ProbDev> *probs) {
     Layout L;
     Plan pl;
-    // descriptors, then the tile-kernel work list (prefix of tile counts), one upload
-    L.take<uint8_t>(base, sizeof(ProbDev) * n + sizeof(int) * (n + 1));
+    // descriptors, then the tile-kernel work list, one upload
+    L.take<uint8_t>(base, sizeof(ProbDev) * n + sizeof(TileDesc) * grid_tiles(n, frames));
     double *scal = L.take<double>(base, size_t(kScalars) * n);
     int *counts = L.take<int>(base, size_t(3) * n);
     for (int i = 0; i < n; ++i) {
@@ -316,7 +322,8 @@ int setup(Run &R, capture_ctx *ctx, int n, const capture_frame *frames, const ca
         pr.sw_sil = std::sqrt(wsil); pr.sw_photo = std::sqrt(wph); pr.sw_arap = std::sqrt(war);
         pr.w_arap = war; pr.tau = tau;
         pr.w_vel = wvel; pr.sw_vel = std::sqrt(wvel); pr.exclude_case2 = excl; pr.outline_only = outline;
-        pr.target = -INFINITY;
+        pr.target = i == 0 ? R.target : -INFINITY;
+        pr.prev2 = i == 0 ? R.prev2 : nullptr;
         const TemplateDev &T = pr.T;
         R.max_nv = std::max(R.max_nv, T.nv);
         R.max_nf = std::max(R.max_nf, T.nf);
@@ -330,15 +337,23 @@ int setup(Run &R, capture_ctx *ctx, int n, const capture_frame *frames, const ca
         R.lds_apply = std::max(R.lds_apply, sizeof(float) * (size_t(T.max_slots) * 21 + size_t(T.max_contrib) * 6));
     }
     // sized once for both the descriptors and the report read-back of `collect`
-    const size_t desc = sizeof(ProbDev) * n + sizeof(int) * (n + 1);
+    R.grid_tiles = grid_tiles(n, frames);
+    const size_t desc = sizeof(ProbDev) * n + sizeof(TileDesc) * R.grid_tiles;
     void *stage = staging(ctx, desc + sizeof(double) * kScalars * n + sizeof(int) * 3 * n + 512);
     if (!stage) return fail(CAPTURE_ENOMEM, "pinned staging allocation failed");
     std::memcpy(stage, R.probs.data(), sizeof(ProbDev) * n);
-    int *ib = reinterpret_cast<int *>(static_cast<uint8_t *>(stage) + sizeof(ProbDev) * n);
-    ib[0] = 0;
-    for (int i = 0; i < n; ++i) ib[i + 1] = ib[i] + R.probs[i].T.ntiles;
-    R.total_tiles = ib[n];
-    R.item_beg = reinterpret_cast<int *>(base + sizeof(ProbDev) * n);
+    TileDesc *td = reinterpret_cast<TileDesc *>(static_cast<uint8_t *>(stage) + sizeof(ProbDev) * n);
+    int k = 0;
+    for (int i = 0; i < n; ++i) {
+        const std::vector<int> &tr = frames[i].tmpl->tile_ranges;
+        for (int t = 0; t < R.probs[i].T.ntiles; ++t, ++k) {
+            const int *r = tr.data() + size_t(6) * t;
+            td[k] = TileDesc{i, t, r[0], r[1], r[2], r[3], r[4], r[5]};
+        }
+    }
+    R.total_tiles = k;
+    for (; k < R.grid_tiles; ++k) td[k] = TileDesc{-1, 0, 0, 0, 0, 0, 0, 0};
+    R.tiles = reinterpret_cast<TileDesc *>(base + sizeof(ProbDev) * n);
     CAP_HIP(hipMemcpyAsync(R.dprobs, stage, desc, hipMemcpyHostToDevice, R.s));
     return CAPTURE_OK;
 }
@@ -390,7 +405,7 @@ int launch_frame(Run &R, int gn_iters = 0) {
 
 void launch_linearize(Run &R, int gn, int energy_only, int check_target = 0) {
     timed(R, K_LIN, [&] {
-        hipLaunchKernelGGL(k_linearize, dim3(unsigned(R.total_tiles)), dim3(kTileThreads), R.lds_lin, R.s, R.dprobs, R.item_beg, R.n,
+        hipLaunchKernelGGL(k_linearize, dim3(unsigned(R.grid_tiles)), dim3(kTileThreads), R.lds_lin, R.s, R.dprobs, R.tiles,
                            energy_only);
     });
     timed(R, K_NODE_INIT, [&] {
@@ -399,14 +414,15 @@ void launch_linearize(Run &R, int gn, int energy_only, int check_target = 0) {
     });
 }
 
-// first_done: step 0's linearisation has already been launched.
-int launch_solve(Run &R, const capture_nonrigid_params *prm, int check_target = 0, bool first_done = false) {
-    for (int gn = 0; gn < prm->gn_iters; ++gn) {
-        if (gn > 0 || !first_done) launch_linearize(R, gn, 0, check_target);
+// Gauss-Newton steps [g0, g1): linearisation (skipped for the first step with
+// first_done, when it has already been launched) and the PCG iterations.
+void launch_steps(Run &R, const capture_nonrigid_params *prm, int check_target, bool first_done, int g0, int g1) {
+    for (int gn = g0; gn < g1; ++gn) {
+        if (gn > g0 || !first_done) launch_linearize(R, gn, 0, check_target);
         for (int j = 0; j < prm->pcg_iters; ++j) {
             timed(R, K_APPLY, [&] {
-                hipLaunchKernelGGL(k_apply, dim3(unsigned(R.total_tiles)), dim3(kTileThreads), R.lds_apply, R.s,
-                                   R.dprobs, R.item_beg, R.n);
+                hipLaunchKernelGGL(k_apply, dim3(unsigned(R.grid_tiles)), dim3(kTileThreads), R.lds_apply, R.s,
+                                   R.dprobs, R.tiles);
             });
             timed(R, K_NODE_PCG, [&] {
                 const int last = j == prm->pcg_iters - 1 ? 1 : 0;
@@ -425,23 +441,34 @@ int launch_solve(Run &R, const capture_nonrigid_params *prm, int check_target = 
     hipLaunchKernelGGL(k_node_pcg, dim3(R.n), dim3(kNodeThreads), 0, R.s, R.dprobs, 0, 1);
             });
     }
+}
+
+// The full schedule, then the energy at the final state.
+int launch_solve(Run &R, const capture_nonrigid_params *prm, int check_target = 0, bool first_done = false) {
+    launch_steps(R, prm, check_target, first_done, 0, prm->gn_iters);
     launch_linearize(R, prm->gn_iters, 1);
     CAP_HIP(hipGetLastError());
     return CAPTURE_OK;
 }
 
-// The solve's launch sequence (preprocessing, decisions, Gauss-Newton/PCG)
+// A solve's launch sequence (preprocessing, decisions, Gauss-Newton/PCG)
 // captured once per launch shape into a HIP graph on the context's capture
 // stream, then replayed on the caller's stream.  Kernels read everything
 // else from the descriptors, which setup uploads before the replay, so one
 // graph serves any inputs with the same sizes, workspace and schedule.  The
 // sequence holds kernels only (buffers are cleared by kernels, not memsets).
-int launch_graph(Run &R, const capture_nonrigid_params *prm) {
-    capture_ctx *ctx = R.ctx;
+// `key` names everything the sequence bakes into kernel arguments.
+std::string shape_key(const Run &R, const capture_nonrigid_params *prm) {
     char key[512];
     std::snprintf(key, sizeof key, "%d|%p|%d %d %d %d %d %d %d %d %d|%zu %zu|%d %d", R.n, (void *)R.dprobs, R.max_nv,
                   R.max_nf, R.max_nn, R.max_hw, R.max_w, R.max_h, R.max_tiles, R.total_tiles, R.max_me, R.lds_lin,
                   R.lds_apply, prm->gn_iters, prm->pcg_iters);
+    return key;
+}
+
+template <class F>
+int launch_graph(Run &R, const std::string &key, F &&sequence) {
+    capture_ctx *ctx = R.ctx;
     auto &cache = ctx->graph_cache;
     hipGraphExec_t exec = nullptr;
     for (size_t i = 0; i < cache.size(); ++i)
@@ -456,8 +483,7 @@ int launch_graph(Run &R, const capture_nonrigid_params *prm) {
         C.s = ctx->capture_stream;
         C.prof = nullptr;
         CAP_HIP(hipStreamBeginCapture(C.s, hipStreamCaptureModeThreadLocal));
-        int rc = launch_frame(C, prm->gn_iters);
-        if (!rc) rc = launch_solve(C, prm);
+        const int rc = sequence(C);
         hipGraph_t graph = nullptr;
         const hipError_t e = hipStreamEndCapture(C.s, &graph);
         if (rc) {
@@ -478,9 +504,9 @@ int launch_graph(Run &R, const capture_nonrigid_params *prm) {
     return CAPTURE_OK;
 }
 
-int collect(Run &R, int gn_iters, capture_report *reports) {
-    const uint8_t *blk = reinterpret_cast<const uint8_t *>(R.probs[0].scal);
-    const size_t off_counts = reinterpret_cast<const uint8_t *>(R.probs[0].counts) - blk;
+int collect(Run &R, int gn_iters, capture_report *reports, const double **scal_host = nullptr) {
+    const uint8_t *blk = reinterpret_cast<const uint8_t *>(R.probs[0].scal.ptr);
+    const size_t off_counts = reinterpret_cast<const uint8_t *>(R.probs[0].counts.ptr) - blk;
     const size_t bytes = off_counts + sizeof(int) * 3 * R.n;
     uint8_t *host = static_cast<uint8_t *>(staging(R.ctx, bytes));
     if (!host) return fail(CAPTURE_ENOMEM, "pinned staging allocation failed");
@@ -488,6 +514,7 @@ int collect(Run &R, int gn_iters, capture_report *reports) {
     CAP_HIP(hipStreamSynchronize(R.s));
     settle(R);
     const double *scal = reinterpret_cast<const double *>(host);
+    if (scal_host) *scal_host = scal;
     const int *counts = reinterpret_cast<const int *>(host + off_counts);
     int status = CAPTURE_OK;
     for (int i = 0; i < R.n; ++i) {
@@ -635,7 +662,11 @@ int capture_batch_solve(capture_ctx *ctx, int32_t n, const capture_frame *frames
     int rc = setup(R, ctx, n, frames, params, workspace, workspace_bytes, stream);
     if (rc) return rc;
     if (ctx->graphs && !ctx->prof.on) {
-        if ((rc = launch_graph(R, params))) return rc;
+        rc = launch_graph(R, shape_key(R, params), [&](Run &C) {
+            const int r = launch_frame(C, params->gn_iters);
+            return r ? r : launch_solve(C, params);
+        });
+        if (rc) return rc;
     } else {
         if ((rc = launch_frame(R, params->gn_iters))) return rc;      // keeps the start states (k_scal_init)
         if ((rc = launch_solve(R, params))) return rc;
@@ -763,7 +794,7 @@ int capture_linearize(capture_ctx *ctx, const capture_frame *frame, const captur
         CAP_HIP(hipMemcpyAsync(pr.p, p, sizeof(float) * n6, hipMemcpyDeviceToDevice, R.s));
         CAP_HIP(hipMemcpyAsync(pr.scal + 1, &zero, sizeof(double), hipMemcpyHostToDevice, R.s));
         timed(R, K_APPLY, [&] {
-    hipLaunchKernelGGL(k_apply, dim3(unsigned(R.total_tiles)), dim3(kTileThreads), R.lds_apply, R.s, R.dprobs, R.item_beg, R.n);
+    hipLaunchKernelGGL(k_apply, dim3(unsigned(R.grid_tiles)), dim3(kTileThreads), R.lds_apply, R.s, R.dprobs, R.tiles);
         });
         hipLaunchKernelGGL(k_node_gather, dim3(1), dim3(kNodeThreads), 0, R.s, R.dprobs);
         CAP_HIP(hipGetLastError());
@@ -886,13 +917,14 @@ int capture_warmstart_features(capture_ctx *ctx, const capture_frame *frame, con
     if (!ctx || !params || !features) return fail(CAPTURE_EINVAL, "null argument");
     CAP_HIP(hipSetDevice(ctx->device));
     Run R;
+    R.prev2 = state_prev2;
     int rc = setup(R, ctx, 1, frame, params, workspace, workspace_bytes, stream);
     if (rc) return rc;
     if ((rc = launch_frame(R))) return rc;
     launch_linearize(R, 0, 0);
     timed(R, K_WS_FEAT, [&] {
         hipLaunchKernelGGL(k_ws_features, dim3(blocks(R.probs[0].T.nn, 256), 1), dim3(256), 0, R.s, R.dprobs,
-                           state_prev2, features);
+                           features);
     });
     CAP_HIP(hipGetLastError());
     CAP_HIP(hipStreamSynchronize(R.s));
@@ -945,45 +977,92 @@ int capture_warmstart_train_step(capture_ctx *ctx, capture_warmstart *net, const
     return CAPTURE_OK;
 }
 
-int capture_nonrigid_solve_warm(capture_ctx *ctx, const capture_frame *frame, const capture_nonrigid_params *params,
-                                capture_warmstart *net, const float *state_prev2, double target_energy,
-                                capture_report *report, void *workspace, size_t workspace_bytes, void *stream) {
-    if (!ctx || !params || !net || !report) return fail(CAPTURE_EINVAL, "null argument");
-    if (std::isnan(target_energy)) return fail(CAPTURE_EINVAL, "target_energy is NaN");
-    CAP_HIP(hipSetDevice(ctx->device));
-    Run R;
-    int rc = setup(R, ctx, 1, frame, params, workspace, workspace_bytes, stream);
-    if (rc) return rc;
-    if (R.probs[0].T.nn > net->max_nodes) return fail(CAPTURE_EINVAL, "template has more nodes than the network's max_nodes");
-    R.probs[0].target = target_energy;
-    CAP_HIP(hipMemcpyAsync(R.dprobs, R.probs.data(), sizeof(ProbDev), hipMemcpyHostToDevice, R.s));
+// Launch sequence of the learned start: preprocessing, linearisation at the
+// previous frame's state (features and E(x_{t-1})), the network's prediction
+// x' = x (+) delta, Gauss-Newton step 0's full linearisation at x' as the
+// energy test, selection (restores x_{t-1} on a rejection; only then does the
+// conditional pass linearise the restored start again), then Gauss-Newton.
+// With `split`, the sequence ends after Gauss-Newton step 0 and the
+// linearisation of step 1 (whose energy test may stop the solve); the caller
+// launches the remaining steps only if it did not.
+int warm_sequence(Run &R, const capture_nonrigid_params *params, capture_warmstart *net, bool split) {
     const ProbDev &pr = R.probs[0];
     const int prev_slot = CAPTURE_MAX_GN + 1;     // energy at the given start (x_{t-1})
-    if ((rc = launch_frame(R, params->gn_iters))) return rc;     // keeps the given state in state0
-    // linearisation at the previous frame's state: features and E(x_{t-1})
+    int rc = launch_frame(R, params->gn_iters);   // keeps the given state in state0
+    if (rc) return rc;
     launch_linearize(R, prev_slot, 0);
     timed(R, K_WS_FEAT, [&] {
-        hipLaunchKernelGGL(k_ws_features, dim3(blocks(pr.T.nn, 256), 1), dim3(256), 0, R.s, R.dprobs, state_prev2,
-                           net->X);
+        hipLaunchKernelGGL(k_ws_features, dim3(blocks(pr.T.nn, 256), 1), dim3(256), 0, R.s, R.dprobs, net->X);
     });
     timed(R, K_WS_MLP, [&] {
         ws_forward(net, pr.T, net->X, R.s, pr.x);
     });
-    hipLaunchKernelGGL(k_node_pcg, dim3(1), dim3(kNodeThreads), 0, R.s, R.dprobs, 0, 1);   // x' = x (+) delta
-    // step 0's full linearisation at x' doubles as the energy test of the prediction;
-    // after a rejection the restored start is linearised again (conditional pass)
+    hipLaunchKernelGGL(k_node_pcg, dim3(1), dim3(kNodeThreads), 0, R.s, R.dprobs, 0, 1);
     launch_linearize(R, 0, 0, 1);
     hipLaunchKernelGGL(k_ws_select, dim3(1), dim3(256), 0, R.s, R.dprobs, prev_slot, 0, params->gn_iters);
     timed(R, K_LIN, [&] {
-        hipLaunchKernelGGL(k_linearize, dim3(unsigned(R.total_tiles)), dim3(kTileThreads), R.lds_lin, R.s, R.dprobs, R.item_beg, R.n, 2);
+        hipLaunchKernelGGL(k_linearize, dim3(unsigned(R.grid_tiles)), dim3(kTileThreads), R.lds_lin, R.s, R.dprobs,
+                           R.tiles, 2);
     });
     timed(R, K_NODE_INIT, [&] {
         hipLaunchKernelGGL(k_node_init, dim3(R.n), dim3(kNodeThreads), 0, R.s, R.dprobs, 0, 0, 3);
     });
-    if ((rc = launch_solve(R, params, 1, true))) return rc;
-    std::vector<double> sc(kScalars);
-    CAP_HIP(hipMemcpyAsync(sc.data(), pr.scal, sizeof(double) * kScalars, hipMemcpyDeviceToHost, R.s));
-    rc = collect(R, params->gn_iters, report);
+    if (!split) return launch_solve(R, params, 1, true);
+    launch_steps(R, params, 1, true, 0, 1);
+    launch_linearize(R, 1, 0, 1);
+    CAP_HIP(hipGetLastError());
+    return CAPTURE_OK;
+}
+
+// The rest of a split learned-start solve: steps 1.. and the final energy.
+int warm_rest(Run &R, const capture_nonrigid_params *params) {
+    launch_steps(R, params, 1, true, 1, params->gn_iters);
+    launch_linearize(R, params->gn_iters, 1);
+    CAP_HIP(hipGetLastError());
+    return CAPTURE_OK;
+}
+
+int capture_nonrigid_solve_warm(capture_ctx *ctx, const capture_frame *frame, const capture_nonrigid_params *params,
+                                capture_warmstart *net, const float *state_prev2, double target_energy,
+                                capture_report *report, void *workspace, size_t workspace_bytes, void *stream) {
+    if (!ctx || !params || !net || !report || !frame) return fail(CAPTURE_EINVAL, "null argument");
+    if (std::isnan(target_energy)) return fail(CAPTURE_EINVAL, "target_energy is NaN");
+    if (frame->tmpl && frame->tmpl->dev.nn > net->max_nodes)
+        return fail(CAPTURE_EINVAL, "template has more nodes than the network's max_nodes");
+    CAP_HIP(hipSetDevice(ctx->device));
+    Run R;
+    R.target = target_energy;
+    R.prev2 = state_prev2;
+    int rc = setup(R, ctx, 1, frame, params, workspace, workspace_bytes, stream);
+    if (rc) return rc;
+    const ProbDev &pr = R.probs[0];
+    // Most predictions reach the target within one step: the solve is launched
+    // in two parts, and the second only if the energy test at the start of
+    // step 1 has not stopped it (one read-back of the stop flag in between),
+    // so a stopped solve does not pay for the launches of its remaining steps.
+    const bool split = params->gn_iters > 1 && std::isfinite(target_energy);
+    const bool graph = ctx->graphs && !ctx->prof.on;
+    char net_key[128];    // the forward pass takes the network, edge table and x as arguments
+    std::snprintf(net_key, sizeof net_key, "warm%d|%p|%p|%p|", int(split), (void *)net,
+                  (const void *)pr.T.edge_dst, (void *)pr.x);
+    const std::string key = net_key + shape_key(R, params);
+    auto first = [&](Run &C) { return warm_sequence(C, params, net, split); };
+    rc = graph ? launch_graph(R, key, first) : first(R);
+    if (rc) return rc;
+    if (split) {
+        double *flag = static_cast<double *>(staging(ctx, sizeof(double)));
+        if (!flag) return fail(CAPTURE_ENOMEM, "pinned staging allocation failed");
+        CAP_HIP(hipMemcpyAsync(flag, pr.scal + 2, sizeof(double), hipMemcpyDeviceToHost, R.s));
+        CAP_HIP(hipStreamSynchronize(R.s));
+        if (*flag == 0.0) {
+            auto rest = [&](Run &C) { return warm_rest(C, params); };
+            rc = graph ? launch_graph(R, "rest|" + key, rest) : rest(R);
+            if (rc) return rc;
+        }
+    }
+    const double *sc = nullptr;
+    rc = collect(R, params->gn_iters, report, &sc);
+    if (!sc) return rc;
     report->energy_pred = sc[4];
     report->energy_prev = sc[6];
     report->warm_start = sc[5] != 0.0 ? 2 : 1;

@@ -5,6 +5,7 @@
 
 #include <cstdint>
 #include <string>
+#include <type_traits>
 #include <utility>
 #include <vector>
 
@@ -39,88 +40,114 @@ constexpr int kSplitMinItems = 8192;     //   used when 6 * n_nodes exceeds this
 constexpr int kTerms = 5;   // energy terms per slot: photo, sil (with b), sil (with |b|), arap, velocity
 constexpr int kScalars = 8 + kTerms * (CAPTURE_MAX_GN + 2);   // slot MAX_GN + 1: predicted start
 
+// A pointer to device global memory.  Indexing it reads and writes through
+// the global address space (global_load / global_store): a plain pointer held
+// in a struct in memory is generic to the compiler, and generic (flat)
+// accesses also count against the scalar-load counter, so every wait for a
+// scalar load would wait for them too.  Converts to and from T * for host code.
+#define CAP_GLOBAL __attribute__((address_space(1)))
+template <class T>
+struct gptr {
+    T *ptr = nullptr;
+    gptr() = default;
+    __host__ __device__ gptr(T *q) : ptr(q) {}
+    template <class U, class = typename std::enable_if<std::is_convertible<U *, T *>::value>::type>
+    __host__ __device__ gptr(const gptr<U> &q) : ptr(q.ptr) {}    // e.g. gptr<float> -> gptr<const float>
+    __host__ __device__ operator T *() const { return ptr; }
+    __device__ __forceinline__ CAP_GLOBAL T &operator[](size_t i) const { return ((CAP_GLOBAL T *)ptr)[i]; }
+    __device__ __forceinline__ CAP_GLOBAL T *g() const { return (CAP_GLOBAL T *)ptr; }
+};
+
 // Static per-template data in library-owned device memory (plan order =
 // vertices grouped by their nearest node, nodes in breadth-first order of the
 // node graph; tiles are contiguous ranges of the plan order).
 struct TemplateDev {
     int nv, nf, nn, ntiles, nslots, nmedges, max_slots, max_contrib;
-    const int *tri;            // [3][nf]
-    const int *node_vertex;    // [nn]
-    const int *bind_idx;       // [4][nv] (vertex order)
-    const float *bind_w;       // [4][nv] (vertex order)
-    const int *edge_dst;       // [8][nn]
-    const int *plan_vid;       // [nv] plan position -> vertex
-    const int *plan_pos;       // [nv] vertex -> plan position
-    const float *plan_w;       // [4][nv] binding weights in plan order
-    const uint32_t *plan_slot; // [nv] 4 tile-local slot indices (u8 each)
-    const int *tile_vbeg;      // [ntiles+1]
-    const int *tile_sbeg;      // [ntiles+1] into slot_node / partials
-    const int *slot_node;      // [nslots]
-    const int *tile_obeg;      // [ntiles+1] into owned_*
-    const int *owned_node;     // [nn]
-    const uint8_t *owned_slot; // [nn]
-    const uint8_t *owned_eslot;// [8][nn] slot of each out-edge target, 255 = none
-    const int *list_beg;       // [nslots+1] into list_idx
-    const uint16_t *list_idx;  // tile-local contribution indices, grouped by slot
-    const int *node_pbeg;      // [nn+1] into node_pidx
-    const int *node_pidx;      // global slot indices of each node, tile order (node-major positions)
-    const int *slot_dest;      // [nslots] node-major position of each slot's partial
-    const uint16_t *plan_cpos; // [4][nv] tile-local position of each vertex contribution in slot order
-    const uint32_t *owned_cpos;// [8][nn] positions of an owned edge's two contributions (lo: source, hi: target)
-    const int *vf_beg;         // [nv+1] vertex -> incident faces
-    const int *vf_face;        // [3nf] ascending per vertex
-    const int *medge;          // [4][nmedges]: a, b, f0, f1 (-1 = border)
-    const int *in_beg;         // [nn+1] node graph in-edges (source nodes), ascending
-    const int *in_src;         // [..]
-    const int *out_cnt;        // [nn] number of valid out-edges
+    gptr<const int> tri;            // [3][nf]
+    gptr<const int> node_vertex;    // [nn]
+    gptr<const int> bind_idx;       // [4][nv] (vertex order)
+    gptr<const float> bind_w;       // [4][nv] (vertex order)
+    gptr<const int> edge_dst;       // [8][nn]
+    gptr<const int> plan_vid;       // [nv] plan position -> vertex
+    gptr<const int> plan_pos;       // [nv] vertex -> plan position
+    gptr<const float> plan_w;       // [4][nv] binding weights in plan order
+    gptr<const uint32_t> plan_slot; // [nv] 4 tile-local slot indices (u8 each)
+    gptr<const int> tile_vbeg;      // [ntiles+1]
+    gptr<const int> tile_sbeg;      // [ntiles+1] into slot_node / partials
+    gptr<const int> slot_node;      // [nslots]
+    gptr<const int> tile_obeg;      // [ntiles+1] into owned_*
+    gptr<const int> owned_node;     // [nn]
+    gptr<const uint8_t> owned_slot; // [nn]
+    gptr<const uint8_t> owned_eslot;// [8][nn] slot of each out-edge target, 255 = none
+    gptr<const int> list_beg;       // [nslots+1] into list_idx
+    gptr<const uint16_t> list_idx;  // tile-local contribution indices, grouped by slot
+    gptr<const int> node_pbeg;      // [nn+1] into node_pidx
+    gptr<const int> node_pidx;      // global slot indices of each node, tile order (node-major positions)
+    gptr<const int> slot_dest;      // [nslots] node-major position of each slot's partial
+    gptr<const uint16_t> plan_cpos; // [4][nv] tile-local position of each vertex contribution in slot order
+    gptr<const uint32_t> owned_cpos;// [8][nn] positions of an owned edge's two contributions (lo: source, hi: target)
+    gptr<const int> vf_beg;         // [nv+1] vertex -> incident faces
+    gptr<const int> vf_face;        // [3nf] ascending per vertex
+    gptr<const int> medge;          // [4][nmedges]: a, b, f0, f1 (-1 = border)
+    gptr<const int> in_beg;         // [nn+1] node graph in-edges (source nodes), ascending
+    gptr<const int> in_src;         // [..]
+    gptr<const int> out_cnt;        // [nn] number of valid out-edges
+};
+
+// One work item of the tile kernels: a tile of one problem with its vertex
+// [vb, vb + nvt), slot [sb, sb + ns) and owned-node [ob, ob + nown) ranges.
+// Built on the host per solve; prob < 0 marks the padding of the grid.
+struct TileDesc {
+    int prob, tile, vb, nvt, sb, ns, ob, nown;
 };
 
 // One problem (frame) of a batch: template, frame inputs and its workspace.
 struct ProbDev {
     TemplateDev T;
-    const float *xyz;
-    const float *rgb;
-    const uint8_t *mask;
-    const float *image;
-    float *state;
+    gptr<const float> xyz;
+    gptr<const float> rgb;
+    gptr<const uint8_t> mask;
+    gptr<const float> image;
+    gptr<float> state;
     int W, H;
     float fx, fy, cx, cy;
     float sw_sil, sw_photo, sw_arap, w_arap, tau, w_vel, sw_vel;
     int exclude_case2;
     int outline_only;            // contour set B restricted to the rendered model's outline
     // images
-    float *blur_tmp, *blurred, *dt;
-    int *colg;
-    int *seg_first, *seg_last;   // [ceil(H/16)][W]
-    uint32_t *zbuf;
-    uint8_t *contour;
+    gptr<float> blur_tmp, blurred, dt;
+    gptr<int> colg;
+    gptr<int> seg_first, seg_last;   // [ceil(H/16)][W]
+    gptr<uint32_t> zbuf;
+    gptr<uint8_t> contour;
     // vertices (vertex order)
-    float *dx;        // [3][nv] deformed position at the start state (float32 recipe)
-    float *duv;       // [2][nv]
-    int *dfix;        // [2][nv] 1/256-pixel fixed point
-    uint8_t *dvalid;  // [nv]
-    uint8_t *vcont;   // [nv]
-    uint8_t *vflags;  // [nv] bit0 visible, bit1 contour set, bit2 b_i = -1
+    gptr<float> dx;        // [3][nv] deformed position at the start state (float32 recipe)
+    gptr<float> duv;       // [2][nv]
+    gptr<int> dfix;        // [2][nv] 1/256-pixel fixed point
+    gptr<uint8_t> dvalid;  // [nv]
+    gptr<uint8_t> vcont;   // [nv]
+    gptr<uint8_t> vflags;  // [nv] bit0 visible, bit1 contour set, bit2 b_i = -1
     // faces
-    float *fcross;    // [3][nf]
+    gptr<float> fcross;    // [3][nf]
     // vertices (plan order)
-    float *px;        // [3][nv]
-    float *pc;        // [3][nv]
-    uint8_t *vcode;   // [nv] bit0 visible, bit1 silhouette residual, bit2 b_i = -1, bit3 velocity term
-    float *pva;       // [3][nv] velocity anchor: start positions (float32 recipe)
-    float *Hm;        // [6][nv]
+    gptr<float> px;        // [3][nv]
+    gptr<float> pc;        // [3][nv]
+    gptr<uint8_t> vcode;   // [nv] bit0 visible, bit1 silhouette residual, bit2 b_i = -1, bit3 velocity term
+    gptr<float> pva;       // [3][nv] velocity anchor: start positions (float32 recipe)
+    gptr<float> Hm;        // [6][nv]
     // tiles / slots
-    float *partial;   // [nslots][12], node-major positions (node_pbeg ranges)
-    float *gpos;      // [3][nn] node positions (the frame's input mesh at the node vertices)
-    double *tile_e;   // [ntiles][kTerms]
+    gptr<float> partial;   // [nslots][12], node-major positions (node_pbeg ranges)
+    gptr<float> gpos;      // [3][nn] node positions (the frame's input mesh at the node vertices)
+    gptr<double> tile_e;   // [ntiles][kTerms]
     // nodes
-    float *b, *diag, *dinv, *x, *r, *z, *p, *Ap;   // [6][nn]
-    double *scal;     // [kScalars]: rz, done, stopped, stop step, ..., kTerms energies per GN step
-    double *dots;     // [2][split blocks] per-workgroup dot-product sums of the split PCG
-    int *counts;      // [3] visible, contour set, queued large faces
-    int *bigq;        // [nf] faces rasterised by k_raster_big
-    float *state0;    // [12][nn] copy of the start state (restored on a device-detected error)
+    gptr<float> b, diag, dinv, x, r, z, p, Ap;   // [6][nn]
+    gptr<double> scal;     // [kScalars]: rz, done, stopped, stop step, ..., kTerms energies per GN step
+    gptr<double> dots;     // [2][split blocks] per-workgroup dot-product sums of the split PCG
+    gptr<int> counts;      // [3] visible, contour set, queued large faces
+    gptr<int> bigq;        // [nf] faces rasterised by k_raster_big
+    gptr<float> state0;    // [12][nn] copy of the start state (restored on a device-detected error)
     double target;    // stop once the energy at the start of a GN step is <= target (-inf: never)
+    gptr<const float> prev2;   // [12][nn] state two frames back (warm-start features), or null
 };
 
 // Arguments of the warm-start network's MFMA GEMM: C(i, j) = sum_k A(i, k) B(j, k)
@@ -152,9 +179,9 @@ struct BodyDev {
     int parent[kMaxJoints], col[kMaxJoints], depth[kMaxJoints];
     uint32_t anc[kMaxJoints];        // bit k set: joint k is j itself or one of its ancestors
     double rest[3][kMaxJoints];      // rest joint positions
-    const float *xyz;                // [3][nv] rest mesh
-    const int *bind_joint;           // [4][nv]
-    const float *bind_w;             // [4][nv]
+    gptr<const float> xyz;                // [3][nv] rest mesh
+    gptr<const int> bind_joint;           // [4][nv]
+    gptr<const float> bind_w;             // [4][nv]
 };
 
 // One pose problem: body, detections, weights and its workspace.
@@ -164,21 +191,21 @@ struct PoseDev {
     double fx, fy, cx, cy;
     double s3d, ssil;                // square roots of the 3D and silhouette weights
     double l2d;
-    const double *p2d, *p3d, *lam;   // [2][nj], [3][nj], [nj]
-    double *pose;                    // caller's [nu]
-    const float *dt;                 // [H][W]
-    const uint8_t *vflags;           // [nv] decision flags
-    double *jR, *jp, *jA;            // [nj][9], [nj][3], [nj][9]: global rotations, positions, derivative axes
-    double *pose0;                   // [nu] start pose (restored on a device-detected error)
-    int *blist;                      // [nv] contour set: (vertex << 1) | (b_i == -1), ascending
-    int *nb;                         // [1] |B|
-    double *rows;                    // [np][ldr] Jacobian, column-major (row r, column c at c * ldr + r);
+    gptr<const double> p2d, p3d, lam;   // [2][nj], [3][nj], [nj]
+    gptr<double> pose;                    // caller's [nu]
+    gptr<const float> dt;                 // [H][W]
+    gptr<const uint8_t> vflags;           // [nv] decision flags
+    gptr<double> jR, jp, jA;            // [nj][9], [nj][3], [nj][9]: global rotations, positions, derivative axes
+    gptr<double> pose0;                   // [nu] start pose (restored on a device-detected error)
+    gptr<int> blist;                      // [nv] contour set: (vertex << 1) | (b_i == -1), ascending
+    gptr<int> nb;                         // [1] |B|
+    gptr<double> rows;                    // [np][ldr] Jacobian, column-major (row r, column c at c * ldr + r);
                                      // column nu holds b*F
     int ldr;                         // max_rows rounded up to 64
-    double *epart;                   // [row blocks][4] energy partials: 2D, 3D, sil, sil with |b|
-    double *energy;                  // [MAX_GN + 1][4]
-    double *sys;                     // [nu][nu + 1] system of the current step (J^T J | -J^T B F), undamped
-    int *status;                     // [1]
+    gptr<double> epart;                   // [row blocks][4] energy partials: 2D, 3D, sil, sil with |b|
+    gptr<double> energy;                  // [MAX_GN + 1][4]
+    gptr<double> sys;                     // [nu][nu + 1] system of the current step (J^T J | -J^T B F), undamped
+    gptr<int> status;                     // [1]
 };
 
 // Optional per-kernel timing with HIP events (capture_profile_*).
@@ -232,6 +259,7 @@ struct capture_body {
 
 struct capture_template {
     cap::TemplateDev dev;
+    std::vector<int> tile_ranges;   // host copy: [ntiles][6] vb, nvt, sb, ns, ob, nown
     void *mem;
     size_t bytes;
     int device;

@@ -26,7 +26,7 @@ __device__ inline void keys_weights(float f, float w[4], float d[4]) {
 // Value and gradient of the cubic interpolant of a [H][W] float image at the
 // point (ix + fx, iy + fy) (integer cell, fraction in [0, 1)), clamp-to-edge.
 // Rows are accumulated n = 0..3, then m = 0..3.
-__device__ inline float sample_cubic_cell(const float *__restrict__ img, int W, int H, int ix, float fx, int iy,
+__device__ inline float sample_cubic_cell(const CAP_GLOBAL float *__restrict__ img, int W, int H, int ix, float fx, int iy,
                                           float fy, float &gu, float &gv) {
     float wx[4], dx[4], wy[4], dy[4];
     keys_weights(fx, wx, dx);
@@ -37,7 +37,7 @@ __device__ inline float sample_cubic_cell(const float *__restrict__ img, int W, 
     float val = 0.0f, gx = 0.0f, gy = 0.0f;
 #pragma unroll
     for (int m = 0; m < 4; ++m) {
-        const float *row = img + size_t(min(max(iy + m - 1, 0), H - 1)) * W;
+        const CAP_GLOBAL float *row = img + size_t(min(max(iy + m - 1, 0), H - 1)) * W;
         float rx = 0.0f, rv = 0.0f;
 #pragma unroll
         for (int n = 0; n < 4; ++n) {
@@ -55,14 +55,14 @@ __device__ inline float sample_cubic_cell(const float *__restrict__ img, int W, 
 }
 
 // Float32 position: cell = floor(u), fraction = u - floor(u) (the decision recipe).
-__device__ inline float sample_cubic(const float *__restrict__ img, int W, int H, float u, float v, float &gu,
+__device__ inline float sample_cubic(const CAP_GLOBAL float *__restrict__ img, int W, int H, float u, float v, float &gu,
                                      float &gv) {
     const float fu = floorf(u), fv = floorf(v);
     return sample_cubic_cell(img, W, H, int(fu), u - fu, int(fv), v - fv, gu, gv);
 }
 
 // Three channels of a [3][H][W] image sharing the stencil.
-__device__ inline void sample_cubic3_cell(const float *__restrict__ img, int W, int H, int ix, float fx, int iy,
+__device__ inline void sample_cubic3_cell(const CAP_GLOBAL float *__restrict__ img, int W, int H, int ix, float fx, int iy,
                                           float fy, float val[3], float gu[3], float gv[3]) {
     float wx[4], dx[4], wy[4], dy[4];
     keys_weights(fx, wx, dx);
@@ -78,7 +78,7 @@ __device__ inline void sample_cubic3_cell(const float *__restrict__ img, int W, 
         size_t ro = size_t(min(max(iy + m - 1, 0), H - 1)) * W;
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-            const float *row = img + c * plane + ro;
+            const CAP_GLOBAL float *row = img + c * plane + ro;
             float rx = 0.0f, rv = 0.0f;
 #pragma unroll
             for (int n = 0; n < 4; ++n) {

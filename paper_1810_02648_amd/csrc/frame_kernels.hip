@@ -21,10 +21,10 @@ __global__ void k_blur(const ProbDev *__restrict__ P, int pass, float w0, float 
     if (i >= W * H) return;
     int y = i / W, x = i - y * W;
     const size_t plane = size_t(W) * H;
-    const float *src = pass == 0 ? pr.image : pr.blur_tmp;
-    float *dst = pass == 0 ? pr.blur_tmp : pr.blurred;
+    const CAP_GLOBAL float *src = pass == 0 ? pr.image.g() : pr.blur_tmp.g();
+    CAP_GLOBAL float *dst = pass == 0 ? pr.blur_tmp.g() : pr.blurred.g();
     for (int c = 0; c < 3; ++c) {
-        const float *s = src + c * plane;
+        const CAP_GLOBAL float *s = src + c * plane;
         float a, b, d;
         if (pass == 0) {
             a = s[size_t(y) * W + max(x - 1, 0)];
@@ -47,7 +47,7 @@ __global__ void k_contour(const ProbDev *__restrict__ P) {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= W * H) return;
     int y = i / W, x = i - y * W;
-    const uint8_t *m = pr.mask;
+    const CAP_GLOBAL uint8_t *m = pr.mask.g();
     uint8_t c = 0;
     if (m[i]) {
         bool bg = x == 0 || y == 0 || x == W - 1 || y == H - 1 || !m[i - 1] || !m[i + 1] || !m[i - W] || !m[i + W];
@@ -218,7 +218,7 @@ __global__ void k_deform_start(const ProbDev *__restrict__ P) {
         float g[3] = {pr.xyz[gv], pr.xyz[nv + gv], pr.xyz[2 * nv + gv]};
         float d[3] = {v[0] - g[0], v[1] - g[1], v[2] - g[2]};
         for (int a = 0; a < 3; ++a) {
-            const float *R = pr.state + size_t(3 * a) * nn + k;
+            const CAP_GLOBAL float *R = pr.state.g() + size_t(3 * a) * nn + k;
             float q = (R[0] * d[0] + R[nn] * d[1]) + R[2 * size_t(nn)] * d[2];
             float yv = (q + g[a]) + pr.state[size_t(9 + a) * nn + k];
             acc[a] = acc[a] + w * yv;
@@ -283,7 +283,8 @@ __device__ inline void tri_pixel(const ProbDev &pr, const TriRaster &s, long lon
     const bool in = (E0 > 0 || (E0 == 0 && s.o0)) && (E1 > 0 || (E1 == 0 && s.o1)) && (E2 > 0 || (E2 == 0 && s.o2));
     if (!in) return;
     const float inv = ((float(E0) * s.iz0 + float(E1) * s.iz1) + float(E2) * s.iz2) / s.Af;
-    atomicMax(pr.zbuf + size_t(j) * pr.W + i, __float_as_uint(inv));
+    __hip_atomic_fetch_max(pr.zbuf.g() + size_t(j) * pr.W + i, __float_as_uint(inv), __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // Per face: cross product (for normals), then rasterise the inverse depth.
@@ -307,7 +308,7 @@ __global__ void k_raster(const ProbDev *__restrict__ P) {
     TriRaster s;
     if (!tri_setup(pr, f, s)) return;
     if ((s.i1 - s.i0 + 1) * (s.j1 - s.j0 + 1) > kRasterSmall) {
-        pr.bigq[atomicAdd(pr.counts + 2, 1)] = f;
+        pr.bigq[__hip_atomic_fetch_add(pr.counts.g() + 2, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)] = f;
         return;
     }
     for (long long j = s.j0; j <= s.j1; ++j)
@@ -387,7 +388,7 @@ __global__ void k_decide(const ProbDev *__restrict__ P) {
                         n[2] = n[2] + pr.fcross[2 * size_t(nf) + f];
                     }
                     float gx, gy;
-                    (void)sample_cubic(pr.dt, W, H, u, v, gx, gy);
+                    (void)sample_cubic(pr.dt.g(), W, H, u, v, gx, gy);
                     float a = (n[0] * Z - n[2] * X) * pr.fx;
                     float b = (n[1] * Z - n[2] * Y) * pr.fy;
                     float s = a * (-gx) + b * (-gy);
@@ -417,7 +418,8 @@ __global__ void k_decide(const ProbDev *__restrict__ P) {
     }
     }
     __syncthreads();
-    if (threadIdx.x < 2 && cnt[threadIdx.x]) atomicAdd(pr.counts + threadIdx.x, cnt[threadIdx.x]);
+    if (threadIdx.x < 2 && cnt[threadIdx.x])
+        __hip_atomic_fetch_add(pr.counts.g() + threadIdx.x, cnt[threadIdx.x], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 }  // namespace cap

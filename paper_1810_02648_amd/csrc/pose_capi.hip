@@ -165,7 +165,7 @@ int launch_pose_decisions(PoseRun &P) {
     const ProbDev &pr = R.probs[0];
     const size_t hw = size_t(pr.W) * pr.H;
     hipLaunchKernelGGL(k_fill_u32, dim3(blocks(hw, 256)), dim3(256), 0, s, pr.zbuf, hw, 0u);
-    hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, s, reinterpret_cast<uint32_t *>(pr.counts), size_t(3), 0u);
+    hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, s, reinterpret_cast<uint32_t *>(pr.counts.ptr), size_t(3), 0u);
     timed(R, K_POSE_LBS, [&] {
         hipLaunchKernelGGL(k_pose_fk, dim3(1), dim3(64), 0, s, P.dpose);
         hipLaunchKernelGGL(k_pose_lbs, dim3(blocks(pr.T.nv, 256)), dim3(256), 0, s, P.dpose, R.dprobs);

@@ -56,7 +56,7 @@ __device__ inline void mat3(const double *A, const double *B, double *C) {
 // Forward kinematics by the whole block: local Exp / J_l per joint in
 // parallel, then composition level by level down the tree.  Results go to
 // LDS (sR, sp, sA: [nj][9], [nj][3], [nj][9]).
-__device__ void fk_block(const BodyDev &B, const double *pose, double *sR, double *sp, double *sA, double *sL,
+__device__ __forceinline__ void fk_block(const BodyDev &B, const double *pose, double *sR, double *sp, double *sA, double *sL,
                          double *sJ) {
     const int nj = B.nj, t = threadIdx.x;
     if (t < nj) {
@@ -179,7 +179,7 @@ __global__ __launch_bounds__(1024) void k_pose_list(const PoseDev *__restrict__ 
 }
 
 // Cubic convolution (a = -0.5) value and gradient at (u, v), FP64, clamp-to-edge.
-__device__ inline double sample_cubic_f64(const float *__restrict__ img, int W, int H, double u, double v, double &gu,
+__device__ inline double sample_cubic_f64(const CAP_GLOBAL float *__restrict__ img, int W, int H, double u, double v, double &gu,
                                           double &gv) {
     u = fmin(fmax(u, -1.0e6), 1.0e6);
     v = fmin(fmax(v, -1.0e6), 1.0e6);
@@ -201,7 +201,7 @@ __device__ inline double sample_cubic_f64(const float *__restrict__ img, int W, 
     }
     double val = 0.0, gx = 0.0, gy = 0.0;
     for (int m = 0; m < 4; ++m) {
-        const float *row = img + size_t(min(max(iy + m - 1, 0), H - 1)) * W;
+        const CAP_GLOBAL float *row = img + size_t(min(max(iy + m - 1, 0), H - 1)) * W;
         double rx = 0.0, rv = 0.0;
         for (int n = 0; n < 4; ++n) {
             const double t = row[min(max(ix + n - 1, 0), W - 1)];
@@ -220,7 +220,7 @@ __device__ inline double sample_cubic_f64(const float *__restrict__ img, int W, 
 // Row entries of g . dY/dtheta for the rotating joints in `mask`, with
 // dsum(k) = sum over carried points of weight * (y - p_k).  Written for every
 // unknown column of the row (zeros elsewhere) except t, t' and the F column.
-__device__ inline void rotation_entries(const BodyDev &B, double *row, size_t ld, const double g[3], const double *sp,
+__device__ inline void rotation_entries(const BodyDev &B, CAP_GLOBAL double *row, size_t ld, const double g[3], const double *sp,
                                         const double *sA, const double (*ys)[3], const double *ws,
                                         const uint32_t *masks, int npts) {
     for (int k = 0; k < B.nj; ++k) {
@@ -263,7 +263,7 @@ __global__ __launch_bounds__(kPoseRowThreads) void k_pose_rows(const PoseDev *__
     const int r = blockIdx.x * blockDim.x + threadIdx.x;
     double en[4] = {0.0, 0.0, 0.0, 0.0};
     if (r < M) {
-        double *row = P.rows + r;      // column-major: entry c at row[c * ldr]
+        CAP_GLOBAL double *row = P.rows.g() + r;      // column-major: entry c at row[c * ldr]
         double g[3], F;
         double ys[4][3], ws[4];
         uint32_t masks[4];
@@ -324,7 +324,7 @@ __global__ __launch_bounds__(kPoseRowThreads) void k_pose_rows(const PoseDev *__
             const double X = V[0], Y = V[1], Z = V[2];
             const double u = (P.fx * X) / Z + P.cx, vv = (P.fy * Y) / Z + P.cy;
             double du, dv;
-            const double dist = sample_cubic_f64(P.dt, P.W, P.H, u, vv, du, dv);
+            const double dist = sample_cubic_f64(P.dt.g(), P.W, P.H, u, vv, du, dv);
             const double rr = P.ssil * dist;
             F = bs * rr;
             g[0] = P.ssil * (du * (P.fx / Z));
@@ -372,8 +372,8 @@ __global__ __launch_bounds__(64 * kJtjWaves) void k_pose_jtj(const PoseDev *__re
     const int M = 5 * P.B.nj + P.nb[0];
     const int wv = threadIdx.x >> 6, l = threadIdx.x & 63, li = l & 15, lk = l >> 4;
     dbl4 acc = {0.0, 0.0, 0.0, 0.0};
-    const double *col_a = P.rows + size_t(I * kPoseTile + li) * P.ldr;     // column-major rows
-    const double *col_b = P.rows + size_t(Jt * kPoseTile + li) * P.ldr;
+    const CAP_GLOBAL double *col_a = P.rows.g() + size_t(I * kPoseTile + li) * P.ldr;     // column-major rows
+    const CAP_GLOBAL double *col_b = P.rows.g() + size_t(Jt * kPoseTile + li) * P.ldr;
     constexpr int span = 4 * kJtjBatch;
     for (int r0 = wv * span; r0 < M; r0 += kJtjWaves * span) {
         double a[kJtjBatch], bb[kJtjBatch];

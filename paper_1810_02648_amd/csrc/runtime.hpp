@@ -40,9 +40,13 @@ struct Run {
     ProbDev *dprobs = nullptr;
     int max_nv = 0, max_nf = 0, max_nn = 0, max_hw = 0, max_w = 0, max_h = 0, max_tiles = 0, max_me = 0;
     size_t lds_lin = 0, lds_apply = 0;
-    int *item_beg = nullptr;     // device [n + 1]: prefix of the problems' tile counts
-    int total_tiles = 0;
+    TileDesc *tiles = nullptr;   // device [grid_tiles]: tile-kernel work items (die-interleaved grid)
+    int total_tiles = 0;         // tiles of all problems
+    int grid_tiles = 0;          // total_tiles rounded up to a multiple of 8
     hipStream_t s = nullptr;
+    // set before setup; applied to problem 0 (single-frame entry points)
+    double target = -INFINITY;
+    const float *prev2 = nullptr;
 };
 
 // Launch `go` bracketed by events when timing is on.

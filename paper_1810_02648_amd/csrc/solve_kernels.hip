@@ -1,5 +1,6 @@
 // Gauss-Newton / PCG kernels of the non-rigid stage (Sec. 3.4 energy, Sec. 4
-// solver).  Tile kernels (one block per tile of every problem) stream the
+// solver).  Tile kernels (one block per tile of every problem, from a
+// host-built list of tile descriptors) stream the
 // plan-ordered vertices once and accumulate per-node 6-vectors in LDS; node
 // kernels (one workgroup per problem) finish the per-node sums in a fixed
 // order and run the PCG vector updates with float64 dot products.
@@ -44,17 +45,11 @@ __device__ inline void load_slots(const ProbDev &pr, int sb, int ns, TileLds &L,
     }
 }
 
-// Work item -> (problem, tile) of the flattened tile grid: item_beg is the
-// prefix of the problems' tile counts (one block per tile of every problem,
-// no idle blocks for the smaller problems of a batch).
-__device__ inline int item_problem(const int *__restrict__ item_beg, int n, int item) {
-    int lo = 0, hi = n;
-    while (hi - lo > 1) {
-        const int mid = (lo + hi) >> 1;
-        if (item_beg[mid] <= item) lo = mid; else hi = mid;
-    }
-    return lo;
-}
+// Work item of a block when consecutive blocks go to the accelerator dies
+// (XCDs) in turn: block b runs on die b % 8, so die x is given the x-th
+// contiguous eighth of the items and neighbouring tiles (which share slot
+// nodes) meet in the same L2.  The grid is a multiple of 8.
+__device__ inline int xcd_item(int b, int grid) { return (b & 7) * (grid >> 3) + (b >> 3); }
 
 // Slot offsets of the tile's contributions in slot order, into LDS.  The
 // contributions are stored component-major, C[comp][position], where each
@@ -86,21 +81,20 @@ __device__ inline void rot_apply(const float *R, const float d[3], float q[3]) {
 // prediction (scal[5] set), i.e. relinearise at the restored start.
 // ----------------------------------------------------------------------------
 __global__ __launch_bounds__(kTileThreads) void k_linearize(const ProbDev *__restrict__ P,
-                                                            const int *__restrict__ item_beg, int n, int mode) {
+                                                            const TileDesc *__restrict__ D, int mode) {
     extern __shared__ float lds[];
     __shared__ double red[kTileThreads / 64];
     __shared__ int lbeg[kMaxTileSlots + 1];
-    const int prob = item_problem(item_beg, n, blockIdx.x);
-    const ProbDev &pr = P[prob];
+    const TileDesc d = D[xcd_item(blockIdx.x, gridDim.x)];
+    if (d.prob < 0) return;
+    const ProbDev &pr = P[d.prob];
     const TemplateDev &T = pr.T;
-    const int tile = blockIdx.x - item_beg[prob];
+    const int tile = d.tile;
     if (pr.scal[2] != 0.0) return;
     if ((mode & 2) && pr.scal[5] == 0.0) return;      // conditional pass: only after a rejected prediction
     const bool full = (mode & 1) == 0;
     const int nv = T.nv, nn = T.nn;
-    const int vb = T.tile_vbeg[tile], nvt = T.tile_vbeg[tile + 1] - vb;
-    const int sb = T.tile_sbeg[tile], ns = T.tile_sbeg[tile + 1] - sb;
-    const int ob = T.tile_obeg[tile], nown = T.tile_obeg[tile + 1] - ob;
+    const int vb = d.vb, nvt = d.nvt, sb = d.sb, ns = d.ns, ob = d.ob, nown = d.nown;
     TileLds L = tile_lds(lds, ns, 12);
     load_slots(pr, sb, ns, L, false);
     if (full) load_offsets(T, sb, ns, lbeg);
@@ -148,7 +142,7 @@ __global__ __launch_bounds__(kTileThreads) void k_linearize(const ProbDev *__res
             const float P1[3] = {0.0f, pr.fy * iz, -pr.fy * Y * iz * iz};
             if (code & 1) {
                 float val[3], gu[3], gv[3];
-                sample_cubic3_cell(pr.blurred, pr.W, pr.H, cu, fu, cv, fv, val, gu, gv);
+                sample_cubic3_cell(pr.blurred.g(), pr.W, pr.H, cu, fu, cv, fv, val, gu, gv);
                 float res[3], n2 = 0.0f;
                 for (int c = 0; c < 3; ++c) {
                     res[c] = val[c] - pr.pc[size_t(c) * nv + p];
@@ -168,7 +162,7 @@ __global__ __launch_bounds__(kTileThreads) void k_linearize(const ProbDev *__res
             }
             if (code & 2) {
                 float gu, gv;
-                const float dval = sample_cubic_cell(pr.dt, pr.W, pr.H, cu, fu, cv, fv, gu, gv);
+                const float dval = sample_cubic_cell(pr.dt.g(), pr.W, pr.H, cu, fu, cv, fv, gu, gv);
                 const float r = pr.sw_sil * dval;
                 const float b = (code & 4) ? -1.0f : 1.0f;
                 float G[3];
@@ -260,7 +254,7 @@ __global__ __launch_bounds__(kTileThreads) void k_linearize(const ProbDev *__res
     double s3 = block_sum<kTileThreads>(e_a, red);
     double s4 = block_sum<kTileThreads>(e_v, red);
     if (threadIdx.x == 0) {
-        double *te = pr.tile_e + size_t(tile) * kTerms;
+        CAP_GLOBAL double *te = pr.tile_e.g() + size_t(tile) * kTerms;
         te[0] = s0; te[1] = s1; te[2] = s2; te[3] = s3; te[4] = s4;
     }
 }
@@ -270,48 +264,73 @@ __global__ __launch_bounds__(kTileThreads) void k_linearize(const ProbDev *__res
 // f_i = H_i dV_i, node contributions w_j [q_j x f_i; f_i]; regulariser edges
 // u = w_k x e_kl + tau_k - tau_l add w_a [e x u; u] to k and w_a [0; -u] to l.
 // ----------------------------------------------------------------------------
-__global__ __launch_bounds__(kTileThreads) void k_apply(const ProbDev *__restrict__ P, const int *__restrict__ item_beg,
-                                                        int n) {
+__global__ __launch_bounds__(kTileThreads) void k_apply(const ProbDev *__restrict__ P, const TileDesc *__restrict__ D) {
     extern __shared__ float lds[];
     __shared__ int lbeg[kMaxTileSlots + 1];
-    const int prob = item_problem(item_beg, n, blockIdx.x);
-    const ProbDev &pr = P[prob];
+    __shared__ int ldest[kMaxTileSlots];
+    const TileDesc d = D[xcd_item(blockIdx.x, gridDim.x)];
+    if (d.prob < 0) return;
+    const ProbDev &pr = P[d.prob];
     const TemplateDev &T = pr.T;
-    const int tile = blockIdx.x - item_beg[prob];
-    if (pr.scal[1] != 0.0) return;
-    const int nv = T.nv, nn = T.nn;
-    const int vb = T.tile_vbeg[tile], nvt = T.tile_vbeg[tile + 1] - vb;
-    const int sb = T.tile_sbeg[tile], ns = T.tile_sbeg[tile + 1] - sb;
-    const int ob = T.tile_obeg[tile], nown = T.tile_obeg[tile + 1] - ob;
-    // the vertex's own inputs first, so their loads overlap the slot loads
-    const int lv = threadIdx.x, p = vb + lv;
-    const bool has_v = lv < nvt;
-    bool act = false;
-    uint32_t packed = 0;
+    const int nv = T.nv, nn = T.nn, ns = d.ns, nown = d.nown;
+    // Global reads come in two dependent rounds: indices (vertex codes and
+    // contribution positions, slot nodes, run offsets, destinations, owned
+    // edges) and then the data they select; the stop flag is tested between.
+    const int lv = threadIdx.x, p = d.vb + lv;
+    const bool has_v = lv < d.nvt;
+    uint8_t code = 0;
     int cp[4] = {0, 0, 0, 0};
-    float v[3] = {0, 0, 0}, w[4] = {0, 0, 0, 0}, Hm[6] = {0, 0, 0, 0, 0, 0};
     if (has_v) {
-        act = (pr.vcode[p] & 11) != 0;
+        code = pr.vcode[p];
 #pragma unroll
         for (int j = 0; j < 4; ++j) cp[j] = T.plan_cpos[size_t(j) * nv + p];
-        if (act) {
-            packed = T.plan_slot[p];
-            v[0] = pr.px[p]; v[1] = pr.px[nv + p]; v[2] = pr.px[2 * nv + p];
+    }
+    static_assert(kMaxTileSlots < kTileThreads, "one thread per slot and run offset");
+    const bool has_s = lv < ns;
+    int snode = 0;
+    if (has_s) {
+        snode = T.slot_node[d.sb + lv];
+        ldest[lv] = T.slot_dest[d.sb + lv];
+    }
+    const int l0 = T.list_beg[d.sb];
+    if (lv <= ns) lbeg[lv] = T.list_beg[d.sb + lv] - l0;
+    const bool has_e = lv < nown * 8;
+    int e_so = 0, e_se = 255;
+    uint32_t e_cp = 0;
+    if (has_e) {
+        const int o = lv >> 3, e = lv & 7;
+        e_so = T.owned_slot[d.ob + o];
+        e_se = T.owned_eslot[size_t(e) * nn + d.ob + o];
+        e_cp = T.owned_cpos[size_t(e) * nn + d.ob + o];
+    }
+    if (pr.scal[1] != 0.0) return;    // this problem's PCG has stopped
+    const bool act = (code & 11) != 0;
+    uint32_t packed = 0;
+    float v[3] = {0, 0, 0}, w[4] = {0, 0, 0, 0}, Hm[6] = {0, 0, 0, 0, 0, 0};
+    if (act) {
+        packed = T.plan_slot[p];
+        v[0] = pr.px[p]; v[1] = pr.px[nv + p]; v[2] = pr.px[2 * nv + p];
 #pragma unroll
-            for (int j = 0; j < 4; ++j) w[j] = T.plan_w[size_t(j) * nv + p];
+        for (int j = 0; j < 4; ++j) w[j] = T.plan_w[size_t(j) * nv + p];
 #pragma unroll
-            for (int q6 = 0; q6 < 6; ++q6) Hm[q6] = pr.Hm[size_t(q6) * nv + p];
-        }
+        for (int q6 = 0; q6 < 6; ++q6) Hm[q6] = pr.Hm[size_t(q6) * nv + p];
     }
     TileLds L = tile_lds(lds, ns, 6);
-    for (int it = threadIdx.x; it < ns * 18; it += blockDim.x) {   // R, position and p of each slot's node
-        const int s = it / 18, q = it - s * 18;
-        const int k = T.slot_node[sb + s];
-        if (q < 9) L.R[9 * s + q] = pr.state[size_t(q) * nn + k];
-        else if (q < 12) L.g[3 * s + q - 9] = pr.gpos[size_t(q - 9) * nn + k];
-        else L.p[6 * s + q - 12] = pr.p[size_t(q - 12) * nn + k];
+    if (has_s) {      // R, position and p of the slot's node
+        float sv[18];
+#pragma unroll
+        for (int q = 0; q < 9; ++q) sv[q] = pr.state[size_t(q) * nn + snode];
+#pragma unroll
+        for (int q = 0; q < 3; ++q) sv[9 + q] = pr.gpos[size_t(q) * nn + snode];
+#pragma unroll
+        for (int q = 0; q < 6; ++q) sv[12 + q] = pr.p[size_t(q) * nn + snode];
+#pragma unroll
+        for (int q = 0; q < 9; ++q) L.R[9 * lv + q] = sv[q];
+#pragma unroll
+        for (int q = 0; q < 3; ++q) L.g[3 * lv + q] = sv[9 + q];
+#pragma unroll
+        for (int q = 0; q < 6; ++q) L.p[6 * lv + q] = sv[12 + q];
     }
-    load_offsets(T, sb, ns, lbeg);
     __syncthreads();
     const int NC = lbeg[ns];
     float *C = L.c;     // [6][NC]
@@ -323,8 +342,8 @@ __global__ __launch_bounds__(kTileThreads) void k_apply(const ProbDev *__restric
             for (int j = 0; j < 4; ++j) {
                 const int sl = (packed >> (8 * j)) & 0xff;
                 const float *g = L.g + 3 * sl;
-                float d[3] = {v[0] - g[0], v[1] - g[1], v[2] - g[2]};
-                rot_apply(L.R + 9 * sl, d, q[j]);
+                float dd[3] = {v[0] - g[0], v[1] - g[1], v[2] - g[2]};
+                rot_apply(L.R + 9 * sl, dd, q[j]);
                 const float *pp = L.p + 6 * sl;
                 float oxq[3];
                 cross3(pp, q[j], oxq);
@@ -348,33 +367,34 @@ __global__ __launch_bounds__(kTileThreads) void k_apply(const ProbDev *__restric
                 for (int q6 = 0; q6 < 6; ++q6) C[q6 * NC + cp[j]] = 0.0f;
         }
     }
-    for (int idx = threadIdx.x; idx < nown * 8; idx += blockDim.x) {
-        const int o = idx >> 3, e = idx & 7;
-        const int so = T.owned_slot[ob + o];
-        const int se = T.owned_eslot[size_t(e) * nn + ob + o];
-        if (se == 255) continue;
-        const uint32_t cpe = T.owned_cpos[size_t(e) * nn + ob + o];
+    const float wa = pr.w_arap;
+    auto edge = [&](int so, int se, uint32_t cpe) {
         float *c0 = C + (cpe & 0xffffu), *c1 = C + (cpe >> 16);
         const float *gk = L.g + 3 * so, *gl = L.g + 3 * se;
-        float d[3] = {gl[0] - gk[0], gl[1] - gk[1], gl[2] - gk[2]};
+        float dd[3] = {gl[0] - gk[0], gl[1] - gk[1], gl[2] - gk[2]};
         float ekl[3];
-        rot_apply(L.R + 9 * so, d, ekl);
+        rot_apply(L.R + 9 * so, dd, ekl);
         const float *pk = L.p + 6 * so, *pl = L.p + 6 * se;
         float oxe[3];
         cross3(pk, ekl, oxe);
         float u[3] = {(oxe[0] + pk[3]) - pl[3], (oxe[1] + pk[4]) - pl[4], (oxe[2] + pk[5]) - pl[5]};
         float exu[3];
         cross3(ekl, u, exu);
-        const float wa = pr.w_arap;
         c0[0] = wa * exu[0]; c0[NC] = wa * exu[1]; c0[2 * NC] = wa * exu[2];
         c0[3 * NC] = wa * u[0]; c0[4 * NC] = wa * u[1]; c0[5 * NC] = wa * u[2];
         c1[0] = 0.0f; c1[NC] = 0.0f; c1[2 * NC] = 0.0f;
         c1[3 * NC] = -wa * u[0]; c1[4 * NC] = -wa * u[1]; c1[5 * NC] = -wa * u[2];
+    };
+    if (has_e && e_se != 255) edge(e_so, e_se, e_cp);
+    for (int idx = lv + kTileThreads; idx < nown * 8; idx += kTileThreads) {    // more owned edges than threads
+        const int o = idx >> 3, e = idx & 7;
+        const int se = T.owned_eslot[size_t(e) * nn + d.ob + o];
+        if (se != 255) edge(T.owned_slot[d.ob + o], se, T.owned_cpos[size_t(e) * nn + d.ob + o]);
     }
     __syncthreads();
-    for (int pair = threadIdx.x; pair < ns * 6; pair += blockDim.x) {
+    for (int pair = lv; pair < ns * 6; pair += kTileThreads) {
         const int s = pair / 6, comp = pair - s * 6;
-        pr.partial[size_t(T.slot_dest[sb + s]) * 6 + comp] = run_sum(C + comp * NC, lbeg[s], lbeg[s + 1]);
+        pr.partial[size_t(ldest[s]) * 6 + comp] = run_sum(C + comp * NC, lbeg[s], lbeg[s + 1]);
     }
 }
 
@@ -383,7 +403,7 @@ __global__ __launch_bounds__(kTileThreads) void k_apply(const ProbDev *__restric
 // ----------------------------------------------------------------------------
 
 // Sum of a node's tile partials (stride floats per partial), in tile order.
-__device__ inline float gather_node(const TemplateDev &T, const float *__restrict__ partial, int stride, int k,
+__device__ inline float gather_node(const TemplateDev &T, gptr<const float> partial, int stride, int k,
                                     int c) {
     const int pb = T.node_pbeg[k], pe = T.node_pbeg[k + 1];
     float a = 0.0f;

@@ -283,12 +283,12 @@ __device__ inline void log_so3(const float R[9], float w[3]) {
 // R_k and t_k (0..5), their change since frame t-2 (6..11, zero without it),
 // sign(b) log(1 + |b|) of the right-hand side (12..17), log(1 + diag)
 // (18..23), node position minus the mean node position (24..26), zeros.
-__global__ __launch_bounds__(256) void k_ws_features(const ProbDev *__restrict__ P, const float *__restrict__ prev2,
-                                                     float *__restrict__ X) {
+__global__ __launch_bounds__(256) void k_ws_features(const ProbDev *__restrict__ P, float *__restrict__ X) {
     __shared__ float part[3][256];
     __shared__ float mean[3];
     const ProbDev &pr = P[blockIdx.y];
     const TemplateDev &T = pr.T;
+    const CAP_GLOBAL float *__restrict__ prev2 = pr.prev2.g();
     const int nn = T.nn, nv = T.nv;
     // mean node position: strided partial sums, then a fixed-order tree over the block
     {
@@ -350,7 +350,7 @@ __global__ void k_ws_select(const ProbDev *__restrict__ P, int slot_prev, int sl
     const ProbDev &pr = P[blockIdx.x];
     const int nn = pr.T.nn;
     if (threadIdx.x == 0) {
-        const double *e0 = pr.scal + 8 + kTerms * slot_prev, *e1 = pr.scal + 8 + kTerms * slot_pred;
+        const CAP_GLOBAL double *e0 = pr.scal.g() + 8 + kTerms * slot_prev, *e1 = pr.scal.g() + 8 + kTerms * slot_pred;
         const double E0 = e0[0] + e0[1] + e0[3] + e0[4], E1 = e1[0] + e1[1] + e1[3] + e1[4];
         reject = !(E1 < E0);
         pr.scal[4] = E1;

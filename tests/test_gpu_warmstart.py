@@ -143,6 +143,30 @@ def test_rejected_prediction_reproduces_plain_solve(ctx, small):
     assert rb["warm_start"] == 2 and rb["gn_done"] == 3
     assert np.array_equal(a.node_state.cpu().numpy(), b.node_state.cpu().numpy())
     assert ra["energy"] == rb["energy"]
+    # with the lowest plain energy as the target and twice the steps, the solve
+    # is launched in two parts (the second after the step-1 energy test) and
+    # stops at the first step whose start energy reaches the target, with the
+    # state of a plain solve of that many steps
+    import copy
+    target = min(ra["energy"])
+    stop = next(k for k, e in enumerate(ra["energy"]) if e <= target)
+    assert stop >= 2, ra["energy"]      # the second part must run
+    prm_s = copy.copy(prm)
+    prm_s.gn_iters = stop
+    d = make_frame(ctx, f, g, tmpl=a.template)
+    rd = cap.nonrigid_solve(ctx, d, prm_s)
+    prm2 = copy.copy(prm)
+    prm2.gn_iters = 6
+    for graphs in (False, True):
+        cap.set_graphs(ctx, graphs)
+        try:
+            c = make_frame(ctx, f, g, tmpl=a.template)
+            rc = cap.nonrigid_solve_warm(ctx, c, prm2, net, None, target)
+        finally:
+            cap.set_graphs(ctx, False)
+        assert rc["warm_start"] == 2 and rc["gn_done"] == stop, graphs
+        assert np.array_equal(d.node_state.cpu().numpy(), c.node_state.cpu().numpy()), graphs
+        assert rc["energy"] == ra["energy"][:stop + 1] == rd["energy"], graphs
 
 
 def test_trained_warm_start_reaches_plain_energy_in_fewer_steps(ctx):
@@ -160,3 +184,32 @@ def test_trained_warm_start_reaches_plain_energy_in_fewer_steps(ctx):
     print("plain steps", ev["plain_steps"], "learned steps", ev["learned_steps"], "used", ev["used_prediction"])
     assert np.mean(ev["reached"]) >= 0.9
     assert np.mean(ev["learned_steps"]) < np.mean(ev["plain_steps"])
+    # the learned start replayed from captured HIP graphs equals the eager
+    # launches bit for bit, across frames whose previous states (and so the
+    # feature inputs) differ, with unrelated GPU work between the replays
+    import copy
+    prm_l = copy.copy(S.prm)
+    prm_l.gn_iters = 2 * S.prm.gn_iters
+    test = list(range(ntr, min(S.n, ntr + 3)))
+
+    def run_learned():
+        out = []
+        for t in test:
+            b = states[t - 1].clone()
+            r = cap.nonrigid_solve_warm(ctx, S.frame(t, b), prm_l, net, states[t - 2], ev["targets"][t - ntr])
+            out.append((b.cpu().numpy(), r["energy"], r["warm_start"], r["energy_pred"], r["energy_prev"]))
+        return out
+
+    eager = run_learned()
+    cap.set_graphs(ctx, True)
+    try:
+        for rep in range(3):
+            got = run_learned()
+            for (xa, *ra), (xb, *rb) in zip(got, eager):
+                assert np.array_equal(xa, xb), rep
+                assert ra == rb, rep
+            junk = torch.randn(1 << 16, device="cuda")
+            float(junk.square().sum())
+            torch.cuda.synchronize()
+    finally:
+        cap.set_graphs(ctx, False)
