@@ -108,6 +108,21 @@ CAPTURE_API int capture_template_create(capture_ctx *ctx, const capture_template
                             capture_template **out);
 CAPTURE_API void capture_template_destroy(capture_template *tmpl);
 
+/* Shape of a template's execution plan (host memory, filled by
+ * capture_template_info; no device work).  Tiles are contiguous ranges of the
+ * plan's vertex order processed by one workgroup each; a slot is a graph node
+ * touched by a tile; contributions are the per-tile (vertex binding or
+ * regulariser edge end) terms summed per slot. */
+typedef struct {
+    int32_t n_vertices, n_triangles, n_nodes;
+    int32_t n_tiles, n_slots;       /* tiles, and slots over all tiles */
+    int32_t max_slots, max_contrib; /* largest per-tile counts */
+    int32_t vertices_per_tile;      /* the cap the plan was built with */
+} capture_template_info;
+
+/* Returns CAPTURE_EINVAL for a null argument. */
+CAPTURE_API int capture_template_info_get(const capture_template *tmpl, capture_template_info *out);
+
 /* One frame of the non-rigid stage (Sec. 3.4). */
 typedef struct {
     const capture_template *tmpl;

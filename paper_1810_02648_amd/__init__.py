@@ -94,6 +94,10 @@ class Template:
         h = C.c_void_p()
         capi.check(ctx.lib.capture_template_create(ctx.h, C.byref(d), C.byref(h)))
         self.h = h
+        info = capi.TemplateInfo()
+        capi.check(ctx.lib.capture_template_info_get(h, C.byref(info)))
+        self.info = {name: getattr(info, name) for name, _ in capi.TemplateInfo._fields_}
+        self.n_tiles = info.n_tiles
 
     def __del__(self):
         try:

@@ -20,6 +20,12 @@ class TemplateDesc(C.Structure):
                 ("bind_w", C.c_void_p), ("edge_dst", C.c_void_p), ("vertices_per_tile", C.c_int32)]
 
 
+class TemplateInfo(C.Structure):
+    _fields_ = [("n_vertices", C.c_int32), ("n_triangles", C.c_int32), ("n_nodes", C.c_int32),
+                ("n_tiles", C.c_int32), ("n_slots", C.c_int32), ("max_slots", C.c_int32),
+                ("max_contrib", C.c_int32), ("vertices_per_tile", C.c_int32)]
+
+
 class Frame(C.Structure):
     _fields_ = [("tmpl", C.c_void_p), ("xyz", C.c_void_p), ("rgb", C.c_void_p), ("camera", Camera),
                 ("mask", C.c_void_p), ("image", C.c_void_p), ("node_state", C.c_void_p)]
@@ -75,6 +81,7 @@ SIGNATURES = {
     "capture_graph_build": (C.c_int, [_P, _P, C.c_int32, C.c_int32, _P, _P, _P, _P, _P]),
     "capture_template_create": (C.c_int, [_P, C.POINTER(TemplateDesc), C.POINTER(C.c_void_p)]),
     "capture_template_destroy": (None, [_P]),
+    "capture_template_info_get": (C.c_int, [_P, C.POINTER(TemplateInfo)]),
     "capture_workspace_size": (C.c_int, [_P, C.c_int32, C.POINTER(Frame), C.POINTER(C.c_size_t)]),
     "capture_nonrigid_solve": (C.c_int, [_P, C.POINTER(Frame), C.POINTER(NonrigidParams), C.POINTER(Report),
                                          _P, C.c_size_t, _P]),

@@ -25,12 +25,12 @@ __global__ void k_raster_big(const ProbDev *P);
 __global__ void k_contour_edges(const ProbDev *P);
 __global__ void k_decide(const ProbDev *P);
 __global__ void k_linearize(const ProbDev *P, const TileDesc *D, int mode);
+template <int kSplit>
 __global__ void k_apply(const ProbDev *P, const TileDesc *D);
 __global__ void k_node_init(const ProbDev *P, int gn, int energy_only, int check_target);
 __global__ void k_node_gather(const ProbDev *P);
 __global__ void k_node_pcg(const ProbDev *P, int last, int update_only);
-__global__ void k_scal_init(const ProbDev *P, int gn_iters);
-__global__ void k_clear_zbuf(const ProbDev *P);
+__global__ void k_frame_init(const ProbDev *P, int gn_iters);
 __global__ void k_pcg_split_a(const ProbDev *P);
 __global__ void k_pcg_split_b(const ProbDev *P, int it);
 __global__ void k_pcg_split_c(const ProbDev *P, int it, int last);
@@ -330,11 +330,12 @@ int setup(Run &R, capture_ctx *ctx, int n, const capture_frame *frames, const ca
         R.max_nn = std::max(R.max_nn, T.nn);
         R.max_me = std::max(R.max_me, T.nmedges);
         R.max_tiles = std::max(R.max_tiles, T.ntiles);
+        R.max_contrib = std::max(R.max_contrib, T.max_contrib);
         R.max_hw = std::max(R.max_hw, pr.W * pr.H);
         R.max_w = std::max(R.max_w, pr.W);
         R.max_h = std::max(R.max_h, pr.H);
         R.lds_lin = std::max(R.lds_lin, sizeof(float) * (size_t(T.max_slots) * 15 + size_t(T.max_contrib) * 12));
-        R.lds_apply = std::max(R.lds_apply, sizeof(float) * (size_t(T.max_slots) * 21 + size_t(T.max_contrib) * 6));
+        R.lds_apply = std::max(R.lds_apply, sizeof(float) * (size_t(T.max_slots) * 18 + size_t(T.max_contrib) * 6));
     }
     // sized once for both the descriptors and the report read-back of `collect`
     R.grid_tiles = grid_tiles(n, frames);
@@ -362,8 +363,7 @@ int setup(Run &R, capture_ctx *ctx, int n, const capture_frame *frames, const ca
 int launch_frame(Run &R, int gn_iters = 0) {
     const int n = R.n;
     hipStream_t s = R.s;
-    hipLaunchKernelGGL(k_scal_init, dim3(n), dim3(256), 0, s, R.dprobs, gn_iters);
-    hipLaunchKernelGGL(k_clear_zbuf, dim3(blocks(R.max_hw, 1024), n), dim3(256), 0, s, R.dprobs);
+    hipLaunchKernelGGL(k_frame_init, dim3(blocks(R.max_hw, 1024), n), dim3(256), 0, s, R.dprobs, gn_iters);
     // Gaussian kernel 3, sigma = 0.3 * ((3 - 1) / 2 - 1) + 0.8 = 0.8, normalised
     const double e1 = std::exp(-1.0 / (2.0 * 0.8 * 0.8));
     const float w0 = float(e1 / (1.0 + 2.0 * e1)), w1 = float(1.0 / (1.0 + 2.0 * e1));
@@ -403,6 +403,18 @@ int launch_frame(Run &R, int gn_iters = 0) {
     return CAPTURE_OK;
 }
 
+// J^T J p over all tiles.  Grids that the chip holds at once take the
+// one-pass reduction; larger ones the two-pass variant with half the LDS.
+void launch_apply(Run &R) {
+    if (R.grid_tiles > kApplySplitTiles) {
+        const size_t lds = R.lds_apply - sizeof(float) * 3 * R.max_contrib;
+        hipLaunchKernelGGL(k_apply<1>, dim3(unsigned(R.grid_tiles)), dim3(kTileThreads), lds, R.s, R.dprobs, R.tiles);
+    } else {
+        hipLaunchKernelGGL(k_apply<0>, dim3(unsigned(R.grid_tiles)), dim3(kTileThreads), R.lds_apply, R.s, R.dprobs,
+                           R.tiles);
+    }
+}
+
 void launch_linearize(Run &R, int gn, int energy_only, int check_target = 0) {
     timed(R, K_LIN, [&] {
         hipLaunchKernelGGL(k_linearize, dim3(unsigned(R.grid_tiles)), dim3(kTileThreads), R.lds_lin, R.s, R.dprobs, R.tiles,
@@ -421,8 +433,7 @@ void launch_steps(Run &R, const capture_nonrigid_params *prm, int check_target, 
         if (gn > g0 || !first_done) launch_linearize(R, gn, 0, check_target);
         for (int j = 0; j < prm->pcg_iters; ++j) {
             timed(R, K_APPLY, [&] {
-                hipLaunchKernelGGL(k_apply, dim3(unsigned(R.grid_tiles)), dim3(kTileThreads), R.lds_apply, R.s,
-                                   R.dprobs, R.tiles);
+                launch_apply(R);
             });
             timed(R, K_NODE_PCG, [&] {
                 const int last = j == prm->pcg_iters - 1 ? 1 : 0;
@@ -646,6 +657,14 @@ void capture_template_destroy(capture_template *t) {
     delete t;
 }
 
+int capture_template_info_get(const capture_template *t, capture_template_info *out) {
+    if (!t || !out) return fail(CAPTURE_EINVAL, "null argument");
+    const TemplateDev &D = t->dev;
+    *out = capture_template_info{D.nv, D.nf, D.nn, D.ntiles, D.nslots, D.max_slots, D.max_contrib,
+                                 t->vertices_per_tile};
+    return CAPTURE_OK;
+}
+
 int capture_workspace_size(capture_ctx *ctx, int32_t n, const capture_frame *frames, size_t *bytes) {
     if (!ctx || !bytes) return fail(CAPTURE_EINVAL, "null argument");
     int rc = check_frames(n, frames);
@@ -668,7 +687,7 @@ int capture_batch_solve(capture_ctx *ctx, int32_t n, const capture_frame *frames
         });
         if (rc) return rc;
     } else {
-        if ((rc = launch_frame(R, params->gn_iters))) return rc;      // keeps the start states (k_scal_init)
+        if ((rc = launch_frame(R, params->gn_iters))) return rc;      // keeps the start states (k_frame_init)
         if ((rc = launch_solve(R, params))) return rc;
     }
     rc = collect(R, params->gn_iters, reports);
@@ -794,7 +813,7 @@ int capture_linearize(capture_ctx *ctx, const capture_frame *frame, const captur
         CAP_HIP(hipMemcpyAsync(pr.p, p, sizeof(float) * n6, hipMemcpyDeviceToDevice, R.s));
         CAP_HIP(hipMemcpyAsync(pr.scal + 1, &zero, sizeof(double), hipMemcpyHostToDevice, R.s));
         timed(R, K_APPLY, [&] {
-    hipLaunchKernelGGL(k_apply, dim3(unsigned(R.grid_tiles)), dim3(kTileThreads), R.lds_apply, R.s, R.dprobs, R.tiles);
+    launch_apply(R);
         });
         hipLaunchKernelGGL(k_node_gather, dim3(1), dim3(kNodeThreads), 0, R.s, R.dprobs);
         CAP_HIP(hipGetLastError());

@@ -33,6 +33,7 @@ constexpr int kNodeThreads = 1024;    // threads of a per-problem node workgroup
 constexpr int kMaxImageSide = 4096;
 constexpr int kRasterSmall = 256;         // pixel-box size above which a face is rasterised by a workgroup
 constexpr int kRasterBigBlocks = 512;
+constexpr int kApplySplitTiles = 1024;   // tile grids above this take the two-pass J^T J p reduction
 constexpr int kGraphCache = 16;          // captured solve graphs kept per context
 constexpr int kSplitThreads = 256;       // PCG split over workgroups for large node counts:
 constexpr int kSplitItems = 1024;        //   (component, node) items per workgroup
@@ -260,6 +261,7 @@ struct capture_body {
 struct capture_template {
     cap::TemplateDev dev;
     std::vector<int> tile_ranges;   // host copy: [ntiles][6] vb, nvt, sb, ns, ob, nown
+    int vertices_per_tile = 0;
     void *mem;
     size_t bytes;
     int device;

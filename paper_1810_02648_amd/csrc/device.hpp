@@ -142,4 +142,27 @@ __device__ inline double block_sum(double v, double *sh) {
     return r;
 }
 
+// The same for N doubles at once (one exchange through LDS); `sh` holds
+// NT/64 rows of N doubles.  v[] is replaced by the block sums.
+template <int NT, int N>
+__device__ inline void block_sum_n(double (&v)[N], double (*sh)[N]) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1)
+#pragma unroll
+        for (int q = 0; q < N; ++q) v[q] += __shfl_xor(v[q], o);
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    if (lane == 0)
+#pragma unroll
+        for (int q = 0; q < N; ++q) sh[wid][q] = v[q];
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < N; ++q) {
+        double r = 0.0;
+#pragma unroll
+        for (int w = 0; w < NT / 64; ++w) r += sh[w][q];
+        v[q] = r;
+    }
+    __syncthreads();
+}
+
 }  // namespace cap

@@ -321,6 +321,7 @@ int build_template(const capture_template_desc *d, capture_template **out, int d
     D.plan_cpos = (const uint16_t *)at(o_pcp);
     D.owned_cpos = (const uint32_t *)at(o_ocp);
     D.in_beg = (const int *)at(o_ib); D.in_src = (const int *)at(o_is); D.out_cnt = (const int *)at(o_oc);
+    t->vertices_per_tile = vcap;
     t->tile_ranges.resize(size_t(6) * nt);
     for (int i = 0; i < nt; ++i) {
         int *r = t->tile_ranges.data() + size_t(6) * i;

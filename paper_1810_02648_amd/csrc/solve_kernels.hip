@@ -27,40 +27,17 @@ __device__ inline TileLds tile_lds(float *base, int ns, int ncomp) {
     return L;
 }
 
-__device__ inline void load_slots(const ProbDev &pr, int sb, int ns, TileLds &L, bool with_p) {
-    const TemplateDev &T = pr.T;
-    const int nn = T.nn, nv = T.nv;
-    const int nq = with_p ? 21 : 15;
-    for (int it = threadIdx.x; it < ns * nq; it += blockDim.x) {
-        const int s = it / nq, q = it - s * nq;
-        const int k = T.slot_node[sb + s];
-        if (q < 12) {
-            const float v = pr.state[size_t(q) * nn + k];
-            if (q < 9) L.R[9 * s + q] = v; else L.t[3 * s + q - 9] = v;
-        } else if (q < 15) {
-            L.g[3 * s + q - 12] = pr.xyz[size_t(q - 12) * nv + T.node_vertex[k]];
-        } else {
-            L.p[6 * s + q - 15] = pr.p[size_t(q - 15) * nn + k];
-        }
-    }
-}
-
 // Work item of a block when consecutive blocks go to the accelerator dies
 // (XCDs) in turn: block b runs on die b % 8, so die x is given the x-th
 // contiguous eighth of the items and neighbouring tiles (which share slot
 // nodes) meet in the same L2.  The grid is a multiple of 8.
 __device__ inline int xcd_item(int b, int grid) { return (b & 7) * (grid >> 3) + (b >> 3); }
 
-// Slot offsets of the tile's contributions in slot order, into LDS.  The
-// contributions are stored component-major, C[comp][position], where each
-// vertex binding and regulariser edge end has a fixed position (plan_cpos,
-// owned_cpos) inside its slot's contiguous range, in ascending contribution
-// order; every slot sum therefore reads one contiguous run, in a fixed order.
-__device__ inline void load_offsets(const TemplateDev &T, int sb, int ns, int *lbeg) {
-    const int l0 = T.list_beg[sb];
-    for (int s = threadIdx.x; s <= ns; s += blockDim.x) lbeg[s] = T.list_beg[sb + s] - l0;
-}
-
+// The tile's contributions are stored component-major, C[comp][position],
+// where each vertex binding and regulariser edge end has a fixed position
+// (plan_cpos, owned_cpos) inside its slot's contiguous range, in ascending
+// contribution order; every slot sum therefore reads one contiguous run
+// [lbeg[s], lbeg[s + 1]), in a fixed order.
 __device__ inline float run_sum(const float *__restrict__ c, int b, int e) {
     float acc = 0.0f;
     for (int q = b; q < e; ++q) acc += c[q];
@@ -83,34 +60,82 @@ __device__ inline void rot_apply(const float *R, const float d[3], float q[3]) {
 __global__ __launch_bounds__(kTileThreads) void k_linearize(const ProbDev *__restrict__ P,
                                                             const TileDesc *__restrict__ D, int mode) {
     extern __shared__ float lds[];
-    __shared__ double red[kTileThreads / 64];
+    __shared__ double red[kTileThreads / 64][kTerms];
     __shared__ int lbeg[kMaxTileSlots + 1];
+    __shared__ int ldest[kMaxTileSlots];
     const TileDesc d = D[xcd_item(blockIdx.x, gridDim.x)];
     if (d.prob < 0) return;
     const ProbDev &pr = P[d.prob];
     const TemplateDev &T = pr.T;
     const int tile = d.tile;
-    if (pr.scal[2] != 0.0) return;
-    if ((mode & 2) && pr.scal[5] == 0.0) return;      // conditional pass: only after a rejected prediction
     const bool full = (mode & 1) == 0;
     const int nv = T.nv, nn = T.nn;
     const int vb = d.vb, nvt = d.nvt, sb = d.sb, ns = d.ns, ob = d.ob, nown = d.nown;
+    // Every global read that needs no other global value first (the vertex's
+    // own data, slot nodes, run offsets, destinations, owned edges), then the
+    // slot nodes' state; the stop tests sit between the two rounds.
+    const int lv = threadIdx.x, p = vb + lv;
+    const bool has_v = lv < nvt;
+    uint8_t code = 0;
+    uint32_t packed = 0;
+    float v[3] = {0, 0, 0}, w[4] = {0, 0, 0, 0}, pcol[3] = {0, 0, 0}, pva[3] = {0, 0, 0};
+    int cp[4] = {0, 0, 0, 0};
+    if (has_v) {
+        code = pr.vcode[p];
+        packed = T.plan_slot[p];
+        v[0] = pr.px[p]; v[1] = pr.px[nv + p]; v[2] = pr.px[2 * nv + p];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) w[j] = T.plan_w[size_t(j) * nv + p];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) pcol[c] = pr.pc[size_t(c) * nv + p];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) pva[a] = pr.pva[size_t(a) * nv + p];
+        if (full)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) cp[j] = T.plan_cpos[size_t(j) * nv + p];
+    }
+    static_assert(kMaxTileSlots < kTileThreads, "one thread per slot and run offset");
+    const bool has_s = lv < ns;
+    int snode = 0;
+    if (has_s) {
+        snode = T.slot_node[sb + lv];
+        if (full) ldest[lv] = T.slot_dest[sb + lv];
+    }
+    const int l0 = T.list_beg[sb];
+    if (full && lv <= ns) lbeg[lv] = T.list_beg[sb + lv] - l0;
+    const bool has_e = lv < nown * 8;
+    int e_so = 0, e_se = 255;
+    uint32_t e_cp = 0;
+    if (has_e) {
+        const int o = lv >> 3, e = lv & 7;
+        e_so = T.owned_slot[ob + o];
+        e_se = T.owned_eslot[size_t(e) * nn + ob + o];
+        e_cp = T.owned_cpos[size_t(e) * nn + ob + o];
+    }
+    if (pr.scal[2] != 0.0) return;
+    if ((mode & 2) && pr.scal[5] == 0.0) return;      // conditional pass: only after a rejected prediction
     TileLds L = tile_lds(lds, ns, 12);
-    load_slots(pr, sb, ns, L, false);
-    if (full) load_offsets(T, sb, ns, lbeg);
+    if (has_s) {      // R, t and position of the slot's node
+        float sv[15];
+#pragma unroll
+        for (int q = 0; q < 12; ++q) sv[q] = pr.state[size_t(q) * nn + snode];
+#pragma unroll
+        for (int q = 0; q < 3; ++q) sv[12 + q] = pr.gpos[size_t(q) * nn + snode];
+#pragma unroll
+        for (int q = 0; q < 9; ++q) L.R[9 * lv + q] = sv[q];
+#pragma unroll
+        for (int q = 0; q < 3; ++q) L.t[3 * lv + q] = sv[9 + q];
+#pragma unroll
+        for (int q = 0; q < 3; ++q) L.g[3 * lv + q] = sv[12 + q];
+    }
     __syncthreads();
     const int NC = full ? lbeg[ns] : 0;
 
     double e_ph = 0.0, e_s = 0.0, e_sa = 0.0, e_a = 0.0, e_v = 0.0;
-    const int lv = threadIdx.x;
-    if (lv < nvt) {
-        const int p = vb + lv;
-        const uint8_t code = pr.vcode[p];
+    if (has_v) {
         float Hm[6] = {0, 0, 0, 0, 0, 0}, gi[3] = {0, 0, 0};
-        float q[4][3], w[4];
+        float q[4][3];
         int sl[4];
-        const uint32_t packed = T.plan_slot[p];
-        const float v[3] = {pr.px[p], pr.px[nv + p], pr.px[2 * nv + p]};
         // the deformed position and its projection in float64: an image
         // coordinate of ~1e3 px in float32 is only good to ~1e-4 px, which the
         // photometric and silhouette residuals would feel
@@ -118,13 +143,12 @@ __global__ __launch_bounds__(kTileThreads) void k_linearize(const ProbDev *__res
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
             sl[j] = (packed >> (8 * j)) & 0xff;
-            w[j] = T.plan_w[size_t(j) * nv + p];
             const float *g = L.g + 3 * sl[j];
             const float *Rm = L.R + 9 * sl[j];
-            const double d[3] = {double(v[0]) - g[0], double(v[1]) - g[1], double(v[2]) - g[2]};
+            const double dd[3] = {double(v[0]) - g[0], double(v[1]) - g[1], double(v[2]) - g[2]};
 #pragma unroll
             for (int a = 0; a < 3; ++a) {
-                const double qa = (double(Rm[3 * a]) * d[0] + double(Rm[3 * a + 1]) * d[1]) + double(Rm[3 * a + 2]) * d[2];
+                const double qa = (double(Rm[3 * a]) * dd[0] + double(Rm[3 * a + 1]) * dd[1]) + double(Rm[3 * a + 2]) * dd[2];
                 q[j][a] = float(qa);
                 V[a] += double(w[j]) * ((qa + g[a]) + L.t[3 * sl[j] + a]);
             }
@@ -145,7 +169,7 @@ __global__ __launch_bounds__(kTileThreads) void k_linearize(const ProbDev *__res
                 sample_cubic3_cell(pr.blurred.g(), pr.W, pr.H, cu, fu, cv, fv, val, gu, gv);
                 float res[3], n2 = 0.0f;
                 for (int c = 0; c < 3; ++c) {
-                    res[c] = val[c] - pr.pc[size_t(c) * nv + p];
+                    res[c] = val[c] - pcol[c];
                     n2 += res[c] * res[c];
                 }
                 if (!(sqrtf(n2) > pr.tau)) {
@@ -176,7 +200,7 @@ __global__ __launch_bounds__(kTileThreads) void k_linearize(const ProbDev *__res
         }
         if (code & 8) {   // velocity prior: r = sqrt(w_vel) (V - V_anchor), dr/dV = sqrt(w_vel) I
             for (int a = 0; a < 3; ++a) {
-                const double dv = V[a] - double(pr.pva[size_t(a) * nv + p]);
+                const double dv = V[a] - double(pva[a]);
                 gi[a] += float(double(pr.w_vel) * dv);
                 e_v += double(pr.w_vel) * dv * dv;
             }
@@ -188,7 +212,7 @@ __global__ __launch_bounds__(kTileThreads) void k_linearize(const ProbDev *__res
             // contributions to the 4 bound nodes: rhs -w[q x g; g], diag w^2[diag(Q^T H Q); diag(H)]
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
-                float *c = L.c + T.plan_cpos[size_t(j) * nv + p];
+                float *c = L.c + cp[j];
                 const float *qq = q[j];
                 const float ww = w[j], w2 = w[j] * w[j];
                 float qxg[3];
@@ -204,13 +228,13 @@ __global__ __launch_bounds__(kTileThreads) void k_linearize(const ProbDev *__res
         }
     }
     // regulariser edges owned by this tile: r = sqrt(w)(R_k(g_l - g_k) + g_k + t_k - g_l - t_l)
-    for (int idx = threadIdx.x; idx < nown * 8; idx += blockDim.x) {
+    for (int idx = lv; idx < nown * 8; idx += kTileThreads) {
         const int o = idx >> 3, e = idx & 7;
-        const int so = T.owned_slot[ob + o];
-        const int se = T.owned_eslot[size_t(e) * nn + ob + o];
+        const int so = idx == lv ? e_so : T.owned_slot[ob + o];
+        const int se = idx == lv ? e_se : T.owned_eslot[size_t(e) * nn + ob + o];
         if (se == 255) continue;
-        const uint32_t cp = T.owned_cpos[size_t(e) * nn + ob + o];
-        float *c0 = L.c + (cp & 0xffffu), *c1 = L.c + (cp >> 16);
+        const uint32_t cpe = idx == lv ? e_cp : T.owned_cpos[size_t(e) * nn + ob + o];
+        float *c0 = L.c + (cpe & 0xffffu), *c1 = L.c + (cpe >> 16);
         const float *gk = L.g + 3 * so, *gl = L.g + 3 * se;
         float d[3] = {gl[0] - gk[0], gl[1] - gk[1], gl[2] - gk[2]};
         float ekl[3];
@@ -245,17 +269,14 @@ __global__ __launch_bounds__(kTileThreads) void k_linearize(const ProbDev *__res
     if (full) {
         for (int pair = threadIdx.x; pair < ns * 12; pair += blockDim.x) {
             const int s = pair / 12, comp = pair - s * 12;
-            pr.partial[size_t(T.slot_dest[sb + s]) * 12 + comp] = run_sum(L.c + comp * NC, lbeg[s], lbeg[s + 1]);
+            pr.partial[size_t(ldest[s]) * 12 + comp] = run_sum(L.c + comp * NC, lbeg[s], lbeg[s + 1]);
         }
     }
-    double s0 = block_sum<kTileThreads>(e_ph, red);
-    double s1 = block_sum<kTileThreads>(e_s, red);
-    double s2 = block_sum<kTileThreads>(e_sa, red);
-    double s3 = block_sum<kTileThreads>(e_a, red);
-    double s4 = block_sum<kTileThreads>(e_v, red);
+    double es[kTerms] = {e_ph, e_s, e_sa, e_a, e_v};
+    block_sum_n<kTileThreads, kTerms>(es, red);
     if (threadIdx.x == 0) {
         CAP_GLOBAL double *te = pr.tile_e.g() + size_t(tile) * kTerms;
-        te[0] = s0; te[1] = s1; te[2] = s2; te[3] = s3; te[4] = s4;
+        for (int q = 0; q < kTerms; ++q) te[q] = es[q];
     }
 }
 
@@ -264,6 +285,7 @@ __global__ __launch_bounds__(kTileThreads) void k_linearize(const ProbDev *__res
 // f_i = H_i dV_i, node contributions w_j [q_j x f_i; f_i]; regulariser edges
 // u = w_k x e_kl + tau_k - tau_l add w_a [e x u; u] to k and w_a [0; -u] to l.
 // ----------------------------------------------------------------------------
+template <int kSplit>
 __global__ __launch_bounds__(kTileThreads) void k_apply(const ProbDev *__restrict__ P, const TileDesc *__restrict__ D) {
     extern __shared__ float lds[];
     __shared__ int lbeg[kMaxTileSlots + 1];
@@ -315,7 +337,9 @@ __global__ __launch_bounds__(kTileThreads) void k_apply(const ProbDev *__restric
 #pragma unroll
         for (int q6 = 0; q6 < 6; ++q6) Hm[q6] = pr.Hm[size_t(q6) * nv + p];
     }
-    TileLds L = tile_lds(lds, ns, 6);
+    // LDS: R [ns][9], g [ns][3], p [ns][6], then contributions [3][NC]
+    // (kSplit) or [6][NC]
+    float *sR = lds, *sg = sR + 9 * ns, *sp = sg + 3 * ns, *C = sp + 6 * ns;
     if (has_s) {      // R, position and p of the slot's node
         float sv[18];
 #pragma unroll
@@ -325,15 +349,21 @@ __global__ __launch_bounds__(kTileThreads) void k_apply(const ProbDev *__restric
 #pragma unroll
         for (int q = 0; q < 6; ++q) sv[12 + q] = pr.p[size_t(q) * nn + snode];
 #pragma unroll
-        for (int q = 0; q < 9; ++q) L.R[9 * lv + q] = sv[q];
+        for (int q = 0; q < 9; ++q) sR[9 * lv + q] = sv[q];
 #pragma unroll
-        for (int q = 0; q < 3; ++q) L.g[3 * lv + q] = sv[9 + q];
+        for (int q = 0; q < 3; ++q) sg[3 * lv + q] = sv[9 + q];
 #pragma unroll
-        for (int q = 0; q < 6; ++q) L.p[6 * lv + q] = sv[12 + q];
+        for (int q = 0; q < 6; ++q) sp[6 * lv + q] = sv[12 + q];
     }
     __syncthreads();
     const int NC = lbeg[ns];
-    float *C = L.c;     // [6][NC]
+    // With kSplit the six components are reduced in two passes of three
+    // (rotational, then translational) through one [3][NC] buffer, which
+    // halves the LDS of a workgroup and so raises the workgroups a CU holds
+    // (for grids larger than the chip); otherwise in one pass through [6][NC]
+    // (shorter workgroup life, for small grids).
+    float *C2 = kSplit ? C : C + 3 * NC;    // translational components
+    float f[3] = {0, 0, 0};
     if (has_v) {
         if (act) {
             float q[4][3];
@@ -341,66 +371,106 @@ __global__ __launch_bounds__(kTileThreads) void k_apply(const ProbDev *__restric
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
                 const int sl = (packed >> (8 * j)) & 0xff;
-                const float *g = L.g + 3 * sl;
+                const float *g = sg + 3 * sl;
                 float dd[3] = {v[0] - g[0], v[1] - g[1], v[2] - g[2]};
-                rot_apply(L.R + 9 * sl, dd, q[j]);
-                const float *pp = L.p + 6 * sl;
+                rot_apply(sR + 9 * sl, dd, q[j]);
+                const float *pp = sp + 6 * sl;
                 float oxq[3];
                 cross3(pp, q[j], oxq);
 #pragma unroll
                 for (int a = 0; a < 3; ++a) dV[a] += w[j] * (oxq[a] + pp[3 + a]);
             }
-            const float f[3] = {(Hm[0] * dV[0] + Hm[1] * dV[1]) + Hm[2] * dV[2],
-                                (Hm[1] * dV[0] + Hm[3] * dV[1]) + Hm[4] * dV[2],
-                                (Hm[2] * dV[0] + Hm[4] * dV[1]) + Hm[5] * dV[2]};
+            f[0] = (Hm[0] * dV[0] + Hm[1] * dV[1]) + Hm[2] * dV[2];
+            f[1] = (Hm[1] * dV[0] + Hm[3] * dV[1]) + Hm[4] * dV[2];
+            f[2] = (Hm[2] * dV[0] + Hm[4] * dV[1]) + Hm[5] * dV[2];
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
                 float qxf[3];
                 cross3(q[j], f, qxf);
                 float *cj = C + cp[j];
                 cj[0] = w[j] * qxf[0]; cj[NC] = w[j] * qxf[1]; cj[2 * NC] = w[j] * qxf[2];
-                cj[3 * NC] = w[j] * f[0]; cj[4 * NC] = w[j] * f[1]; cj[5 * NC] = w[j] * f[2];
             }
         } else {
 #pragma unroll
-            for (int j = 0; j < 4; ++j)
-                for (int q6 = 0; q6 < 6; ++q6) C[q6 * NC + cp[j]] = 0.0f;
+            for (int j = 0; j < 4; ++j) {
+                w[j] = 0.0f;      // zero contributions in both passes
+                for (int q3 = 0; q3 < 3; ++q3) C[q3 * NC + cp[j]] = 0.0f;
+            }
         }
     }
     const float wa = pr.w_arap;
-    auto edge = [&](int so, int se, uint32_t cpe) {
-        float *c0 = C + (cpe & 0xffffu), *c1 = C + (cpe >> 16);
-        const float *gk = L.g + 3 * so, *gl = L.g + 3 * se;
+    // regulariser edge k -> l: u = w_k x e_kl + tau_k - tau_l; rotational part e x u
+    auto edge_u = [&](int so, int se, float ekl[3], float u[3]) {
+        const float *gk = sg + 3 * so, *gl = sg + 3 * se;
         float dd[3] = {gl[0] - gk[0], gl[1] - gk[1], gl[2] - gk[2]};
-        float ekl[3];
-        rot_apply(L.R + 9 * so, dd, ekl);
-        const float *pk = L.p + 6 * so, *pl = L.p + 6 * se;
+        rot_apply(sR + 9 * so, dd, ekl);
+        const float *pk = sp + 6 * so, *pl = sp + 6 * se;
         float oxe[3];
         cross3(pk, ekl, oxe);
-        float u[3] = {(oxe[0] + pk[3]) - pl[3], (oxe[1] + pk[4]) - pl[4], (oxe[2] + pk[5]) - pl[5]};
-        float exu[3];
-        cross3(ekl, u, exu);
-        c0[0] = wa * exu[0]; c0[NC] = wa * exu[1]; c0[2 * NC] = wa * exu[2];
-        c0[3 * NC] = wa * u[0]; c0[4 * NC] = wa * u[1]; c0[5 * NC] = wa * u[2];
-        c1[0] = 0.0f; c1[NC] = 0.0f; c1[2 * NC] = 0.0f;
-        c1[3 * NC] = -wa * u[0]; c1[4 * NC] = -wa * u[1]; c1[5 * NC] = -wa * u[2];
+        u[0] = (oxe[0] + pk[3]) - pl[3]; u[1] = (oxe[1] + pk[4]) - pl[4]; u[2] = (oxe[2] + pk[5]) - pl[5];
     };
-    if (has_e && e_se != 255) edge(e_so, e_se, e_cp);
-    for (int idx = lv + kTileThreads; idx < nown * 8; idx += kTileThreads) {    // more owned edges than threads
+    float eu[3] = {0, 0, 0};
+    for (int idx = lv; idx < nown * 8; idx += kTileThreads) {
         const int o = idx >> 3, e = idx & 7;
-        const int se = T.owned_eslot[size_t(e) * nn + d.ob + o];
-        if (se != 255) edge(T.owned_slot[d.ob + o], se, T.owned_cpos[size_t(e) * nn + d.ob + o]);
+        const int so = idx == lv ? e_so : T.owned_slot[d.ob + o];
+        const int se = idx == lv ? e_se : T.owned_eslot[size_t(e) * nn + d.ob + o];
+        if (se == 255) continue;
+        const uint32_t cpe = idx == lv ? e_cp : T.owned_cpos[size_t(e) * nn + d.ob + o];
+        float ekl[3], u[3], exu[3];
+        edge_u(so, se, ekl, u);
+        cross3(ekl, u, exu);
+        float *c0 = C + (cpe & 0xffffu), *c1 = C + (cpe >> 16);
+        c0[0] = wa * exu[0]; c0[NC] = wa * exu[1]; c0[2 * NC] = wa * exu[2];
+        c1[0] = 0.0f; c1[NC] = 0.0f; c1[2 * NC] = 0.0f;
+        if (idx == lv) { eu[0] = u[0]; eu[1] = u[1]; eu[2] = u[2]; }
+    }
+    if (kSplit) {
+        __syncthreads();
+        for (int pair = lv; pair < ns * 3; pair += kTileThreads) {
+            const int s = pair / 3, comp = pair - s * 3;
+            pr.partial[size_t(ldest[s]) * 6 + comp] = run_sum(C + comp * NC, lbeg[s], lbeg[s + 1]);
+        }
+        __syncthreads();
+    }
+    if (has_v) {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            float *cj = C2 + cp[j];
+            cj[0] = w[j] * f[0]; cj[NC] = w[j] * f[1]; cj[2 * NC] = w[j] * f[2];
+        }
+    }
+    for (int idx = lv; idx < nown * 8; idx += kTileThreads) {
+        const int o = idx >> 3, e = idx & 7;
+        const int se = idx == lv ? e_se : T.owned_eslot[size_t(e) * nn + d.ob + o];
+        if (se == 255) continue;
+        const uint32_t cpe = idx == lv ? e_cp : T.owned_cpos[size_t(e) * nn + d.ob + o];
+        float u[3];
+        if (idx == lv) {
+            u[0] = eu[0]; u[1] = eu[1]; u[2] = eu[2];
+        } else {
+            float ekl[3];
+            edge_u(T.owned_slot[d.ob + o], se, ekl, u);
+        }
+        float *c0 = C2 + (cpe & 0xffffu), *c1 = C2 + (cpe >> 16);
+        c0[0] = wa * u[0]; c0[NC] = wa * u[1]; c0[2 * NC] = wa * u[2];
+        c1[0] = -wa * u[0]; c1[NC] = -wa * u[1]; c1[2 * NC] = -wa * u[2];
     }
     __syncthreads();
-    for (int pair = lv; pair < ns * 6; pair += kTileThreads) {
-        const int s = pair / 6, comp = pair - s * 6;
-        pr.partial[size_t(ldest[s]) * 6 + comp] = run_sum(C + comp * NC, lbeg[s], lbeg[s + 1]);
+    constexpr int kComps = kSplit ? 3 : 6;
+    for (int pair = lv; pair < ns * kComps; pair += kTileThreads) {
+        const int s = pair / kComps, comp = pair - s * kComps;
+        pr.partial[size_t(ldest[s]) * 6 + (kSplit ? 3 : 0) + comp] = run_sum(C + comp * NC, lbeg[s], lbeg[s + 1]);
     }
 }
+
+template __global__ void k_apply<0>(const ProbDev *, const TileDesc *);
+template __global__ void k_apply<1>(const ProbDev *, const TileDesc *);
 
 // ----------------------------------------------------------------------------
 // Node kernels: one workgroup per problem.
 // ----------------------------------------------------------------------------
+
+constexpr int kItems = 8;   // node kernels: up to kItems * kNodeThreads = 8192 items (1365 nodes) in registers
 
 // Sum of a node's tile partials (stride floats per partial), in tile order.
 __device__ inline float gather_node(const TemplateDev &T, gptr<const float> partial, int stride, int k,
@@ -413,67 +483,96 @@ __device__ inline float gather_node(const TemplateDev &T, gptr<const float> part
 
 // After a linearisation: b, diag, Jacobi preconditioner, PCG start vectors
 // (x = 0, r = b, z = M^-1 r, p = z), r.z, and the energy of GN step `gn`.
-// One thread per (component, node) item.
+// One thread per (component, node) item; every load is issued before the
+// stop tests, and r.z and the energy terms share one block reduction.
 __global__ __launch_bounds__(kNodeThreads) void k_node_init(const ProbDev *__restrict__ P, int gn, int energy_only, int check_target) {
-    __shared__ double red[kNodeThreads / 64];
+    __shared__ double red[kNodeThreads / 64][1 + kTerms];
     const ProbDev &pr = P[blockIdx.x];
-    if (pr.scal[2] != 0.0) return;   // stopped at the target energy
-    if ((check_target & 2) && pr.scal[5] == 0.0) return;   // conditional pass (see k_linearize)
     const TemplateDev &T = pr.T;
-    const int nn = T.nn;
-    double rz = 0.0;
-    if (!energy_only) {
-        for (int i = threadIdx.x; i < 6 * nn; i += blockDim.x) {
-            const int c = i / nn, k = i - c * nn;
-            const float b = gather_node(T, pr.partial, 12, k, c);
-            const float d = gather_node(T, pr.partial, 12, k, 6 + c);
-            const float mi = d > 0.0f ? 1.0f / d : 1.0f;
-            const float z = mi * b;
-            pr.b[i] = b; pr.diag[i] = d; pr.dinv[i] = mi;
-            pr.x[i] = 0.0f; pr.r[i] = b; pr.z[i] = z; pr.p[i] = z;
-            rz += double(b) * double(z);
-        }
-        // node positions, node-major, for the PCG tile kernel's slot loads
-        for (int i = threadIdx.x; i < 3 * nn; i += blockDim.x) {
-            const int a = i / nn, k = i - a * nn;
-            pr.gpos[i] = pr.xyz[size_t(a) * T.nv + T.node_vertex[k]];
+    const int nn = T.nn, n6 = 6 * nn;
+    double v[1 + kTerms] = {0, 0, 0, 0, 0, 0};   // r.z, then the energy terms
+    for (int t = threadIdx.x; t < T.ntiles; t += blockDim.x)
+        for (int q = 0; q < kTerms; ++q) v[1 + q] += pr.tile_e[size_t(t) * kTerms + q];
+    const bool regs = n6 <= kItems * kNodeThreads;
+    int pb[kItems], pe[kItems];
+    if (!energy_only && regs) {
+#pragma unroll
+        for (int j = 0; j < kItems; ++j) {
+            const int i = threadIdx.x + j * kNodeThreads;
+            pb[j] = pe[j] = 0;
+            if (i < n6) {
+                const int k = i % nn;
+                pb[j] = T.node_pbeg[k]; pe[j] = T.node_pbeg[k + 1];
+            }
         }
     }
-    rz = block_sum<kNodeThreads>(rz, red);
-    double e[kTerms] = {0, 0, 0, 0, 0};
-    for (int t = threadIdx.x; t < T.ntiles; t += blockDim.x)
-        for (int q = 0; q < kTerms; ++q) e[q] += pr.tile_e[size_t(t) * kTerms + q];
-    for (int q = 0; q < kTerms; ++q) e[q] = block_sum<kNodeThreads>(e[q], red);
+    if (pr.scal[2] != 0.0) return;   // stopped at the target energy
+    if ((check_target & 2) && pr.scal[5] == 0.0) return;   // conditional pass (see k_linearize)
+    if (!energy_only) {
+        if (regs) {
+#pragma unroll
+            for (int j = 0; j < kItems; ++j) {
+                const int i = threadIdx.x + j * kNodeThreads;
+                if (i < n6) {
+                    const int c = i / nn;
+                    float b = 0.0f, d = 0.0f;
+                    for (int q = pb[j]; q < pe[j]; ++q) b += pr.partial[size_t(q) * 12 + c];
+                    for (int q = pb[j]; q < pe[j]; ++q) d += pr.partial[size_t(q) * 12 + 6 + c];
+                    const float mi = d > 0.0f ? 1.0f / d : 1.0f;
+                    const float z = mi * b;
+                    pr.b[i] = b; pr.diag[i] = d; pr.dinv[i] = mi;
+                    pr.x[i] = 0.0f; pr.r[i] = b; pr.z[i] = z; pr.p[i] = z;
+                    v[0] += double(b) * double(z);
+                }
+            }
+        } else {
+            for (int i = threadIdx.x; i < n6; i += blockDim.x) {
+                const int c = i / nn, k = i - c * nn;
+                const float b = gather_node(T, pr.partial, 12, k, c);
+                const float d = gather_node(T, pr.partial, 12, k, 6 + c);
+                const float mi = d > 0.0f ? 1.0f / d : 1.0f;
+                const float z = mi * b;
+                pr.b[i] = b; pr.diag[i] = d; pr.dinv[i] = mi;
+                pr.x[i] = 0.0f; pr.r[i] = b; pr.z[i] = z; pr.p[i] = z;
+                v[0] += double(b) * double(z);
+            }
+        }
+    }
+    block_sum_n<kNodeThreads, 1 + kTerms>(v, red);
     if (threadIdx.x == 0) {
+        const double rz = v[0];
         if (!energy_only) {
             pr.scal[0] = rz;
             pr.scal[1] = rz == 0.0 ? 1.0 : 0.0;
-            if ((check_target & 1) && e[0] + e[1] + e[3] + e[4] <= pr.target) {   // x = 0 above, so the step's update is void
+            if ((check_target & 1) && v[1] + v[2] + v[4] + v[5] <= pr.target) {   // x = 0 above, so the step's update is void
                 pr.scal[1] = 1.0;
                 pr.scal[2] = 1.0;
                 pr.scal[3] = double(gn);
             }
         }
-        for (int q = 0; q < kTerms; ++q) pr.scal[8 + kTerms * gn + q] = e[q];
+        for (int q = 0; q < kTerms; ++q) pr.scal[8 + kTerms * gn + q] = v[1 + q];
     }
 }
 
-// Per-problem scalars at the start of a solve: nothing stopped, GN count = K;
-// visible / contour / large-face counters cleared; the start state kept
-// (restored on a device-detected error).
-__global__ void k_scal_init(const ProbDev *__restrict__ P, int gn_iters) {
-    const ProbDev &pr = P[blockIdx.x];
-    for (int i = threadIdx.x; i < kScalars; i += blockDim.x) pr.scal[i] = i == 3 ? double(gn_iters) : 0.0;
-    if (threadIdx.x < 3) pr.counts[threadIdx.x] = 0;
-    const int n12 = 12 * pr.T.nn;
-    for (int i = threadIdx.x; i < n12; i += blockDim.x) pr.state0[i] = pr.state[i];
-}
-
-// Empty depth buffers of every problem (4 pixels per thread).
-__global__ void k_clear_zbuf(const ProbDev *__restrict__ P) {
+// Per-frame set-up of every problem: scalars and counters (block 0), the
+// start-state copy and the node positions (the frame's mesh at the node
+// vertices, node-major, read by the tile kernels), and empty depth buffers
+// (4 pixels per thread).  Grid: (blocks over the largest image, problems).
+__global__ void k_frame_init(const ProbDev *__restrict__ P, int gn_iters) {
     const ProbDev &pr = P[blockIdx.y];
+    const TemplateDev &T = pr.T;
+    const int nn = T.nn, tid = blockIdx.x * blockDim.x + threadIdx.x, nt = gridDim.x * blockDim.x;
+    if (blockIdx.x == 0) {
+        for (int i = threadIdx.x; i < kScalars; i += blockDim.x) pr.scal[i] = i == 3 ? double(gn_iters) : 0.0;
+        if (threadIdx.x < 3) pr.counts[threadIdx.x] = 0;
+    }
+    for (int i = tid; i < 12 * nn; i += nt) pr.state0[i] = pr.state[i];
+    for (int i = tid; i < 3 * nn; i += nt) {
+        const int a = i / nn, k = i - a * nn;
+        pr.gpos[i] = pr.xyz[size_t(a) * T.nv + T.node_vertex[k]];
+    }
     const size_t hw = size_t(pr.W) * pr.H;
-    const size_t i = (size_t(blockIdx.x) * blockDim.x + threadIdx.x) * 4;
+    const size_t i = size_t(tid) * 4;
     for (int q = 0; q < 4; ++q)
         if (i + q < hw) pr.zbuf[i + q] = 0u;
 }
@@ -523,37 +622,79 @@ __device__ inline void node_update(const ProbDev &pr, int k) {
 // Stops (for this GN step) when p.Ap <= 0 or r.z == 0.  `last`: apply the
 // node update afterwards; `update_only`: only that.  Items are (component,
 // node) pairs; each thread keeps its items' values in registers between phases.
-constexpr int kItems = 8;   // up to kItems * kNodeThreads = 8192 items (1365 nodes) in registers
-
 __global__ __launch_bounds__(kNodeThreads) void k_node_pcg(const ProbDev *__restrict__ P, int last, int update_only) {
     __shared__ double red[kNodeThreads / 64];
     const ProbDev &pr = P[blockIdx.x];
     const TemplateDev &T = pr.T;
     const int nn = T.nn, n6 = 6 * nn;
-    const bool done = pr.scal[1] != 0.0;
-    if (!done && !update_only) {
-        const bool regs = n6 <= kItems * kNodeThreads;
-        float ap[kItems], pp[kItems];
-        double pap = 0.0;
-        if (regs) {
+    if (!update_only && n6 <= kItems * kNodeThreads) {
+        // every load of the iteration up front (p, x, r, 1/diag, the node's
+        // partial range, r.z and the stop flag), then the partial sums
+        float pp[kItems], xx[kItems], rr[kItems], di[kItems];
+        int pb[kItems], pe[kItems];
+#pragma unroll
+        for (int j = 0; j < kItems; ++j) {
+            const int i = threadIdx.x + j * kNodeThreads;
+            pp[j] = xx[j] = rr[j] = di[j] = 0.0f;
+            pb[j] = pe[j] = 0;
+            if (i < n6) {
+                const int k = i % nn;
+                pp[j] = pr.p[i]; xx[j] = pr.x[i]; rr[j] = pr.r[i]; di[j] = pr.dinv[i];
+                pb[j] = T.node_pbeg[k]; pe[j] = T.node_pbeg[k + 1];
+            }
+        }
+        const double rz = pr.scal[0];
+        if (pr.scal[1] == 0.0) {
+            float ap[kItems];
+            double pap = 0.0;
 #pragma unroll
             for (int j = 0; j < kItems; ++j) {
-                const int i = threadIdx.x + j * kNodeThreads;
-                ap[j] = 0.0f; pp[j] = 0.0f;
-                if (i < n6) {
-                    const int c = i / nn, k = i - c * nn;
-                    ap[j] = gather_node(T, pr.partial, 6, k, c);
-                    pp[j] = pr.p[i];
-                    pap += double(pp[j]) * double(ap[j]);
+                const int c = (threadIdx.x + j * kNodeThreads) / nn;
+                float acc = 0.0f;
+                for (int q = pb[j]; q < pe[j]; ++q) acc += pr.partial[size_t(q) * 6 + c];
+                ap[j] = acc;
+                pap += double(pp[j]) * double(acc);
+            }
+            pap = block_sum<kNodeThreads>(pap, red);
+            if (pap <= 0.0) {
+                if (threadIdx.x == 0) pr.scal[1] = 1.0;
+            } else {
+                const double alpha = rz / pap;
+                double rz2 = 0.0;
+                float zz[kItems];
+#pragma unroll
+                for (int j = 0; j < kItems; ++j) {
+                    const int i = threadIdx.x + j * kNodeThreads;
+                    zz[j] = 0.0f;
+                    if (i < n6) {
+                        pr.x[i] = float(fma(alpha, double(pp[j]), double(xx[j])));
+                        const float r = float(fma(-alpha, double(ap[j]), double(rr[j])));
+                        const float z = di[j] * r;
+                        pr.r[i] = r;
+                        zz[j] = z;
+                        rz2 += double(r) * double(z);
+                    }
+                }
+                rz2 = block_sum<kNodeThreads>(rz2, red);
+                const double beta = rz2 / rz;
+#pragma unroll
+                for (int j = 0; j < kItems; ++j) {
+                    const int i = threadIdx.x + j * kNodeThreads;
+                    if (i < n6) pr.p[i] = float(fma(beta, double(pp[j]), double(zz[j])));
+                }
+                if (threadIdx.x == 0) {
+                    pr.scal[0] = rz2;
+                    if (rz2 == 0.0) pr.scal[1] = 1.0;
                 }
             }
-        } else {
-            for (int i = threadIdx.x; i < n6; i += kNodeThreads) {
-                const int c = i / nn, k = i - c * nn;
-                const float a = gather_node(T, pr.partial, 6, k, c);
-                pr.Ap[i] = a;
-                pap += double(pr.p[i]) * double(a);
-            }
+        }
+    } else if (!update_only && pr.scal[1] == 0.0) {      // more items than registers
+        double pap = 0.0;
+        for (int i = threadIdx.x; i < n6; i += kNodeThreads) {
+            const int c = i / nn, k = i - c * nn;
+            const float a = gather_node(T, pr.partial, 6, k, c);
+            pr.Ap[i] = a;
+            pap += double(pr.p[i]) * double(a);
         }
         pap = block_sum<kNodeThreads>(pap, red);
         const double rz = pr.scal[0];
@@ -562,46 +703,17 @@ __global__ __launch_bounds__(kNodeThreads) void k_node_pcg(const ProbDev *__rest
         } else {
             const double alpha = rz / pap;
             double rz2 = 0.0;
-            float zz[kItems];
-            if (regs) {
-#pragma unroll
-                for (int j = 0; j < kItems; ++j) {
-                    const int i = threadIdx.x + j * kNodeThreads;
-                    zz[j] = 0.0f;
-                    if (i < n6) {
-                        pr.x[i] = float(fma(alpha, double(pp[j]), double(pr.x[i])));
-                        const float r = float(fma(-alpha, double(ap[j]), double(pr.r[i])));
-                        const float z = pr.dinv[i] * r;
-                        pr.r[i] = r;
-                        zz[j] = z;
-                        rz2 += double(r) * double(z);
-                    }
-                }
-            } else {
-                for (int i = threadIdx.x; i < n6; i += kNodeThreads) {
-                    pr.x[i] = float(fma(alpha, double(pr.p[i]), double(pr.x[i])));
-                    const float r = float(fma(-alpha, double(pr.Ap[i]), double(pr.r[i])));
-                    const float z = pr.dinv[i] * r;
-                    pr.r[i] = r;
-                    pr.z[i] = z;
-                    rz2 += double(r) * double(z);
-                }
+            for (int i = threadIdx.x; i < n6; i += kNodeThreads) {
+                pr.x[i] = float(fma(alpha, double(pr.p[i]), double(pr.x[i])));
+                const float r = float(fma(-alpha, double(pr.Ap[i]), double(pr.r[i])));
+                const float z = pr.dinv[i] * r;
+                pr.r[i] = r;
+                pr.z[i] = z;
+                rz2 += double(r) * double(z);
             }
             rz2 = block_sum<kNodeThreads>(rz2, red);
             const double beta = rz2 / rz;
-            if (regs) {
-#pragma unroll
-                for (int j = 0; j < kItems; ++j) {
-                    const int i = threadIdx.x + j * kNodeThreads;
-                    if (i < n6) {
-                        pr.p[i] = float(fma(beta, double(pp[j]), double(zz[j])));
-                    }
-                }
-            } else {
-                for (int i = threadIdx.x; i < n6; i += kNodeThreads) {
-                    pr.p[i] = float(fma(beta, double(pr.p[i]), double(pr.z[i])));
-                }
-            }
+            for (int i = threadIdx.x; i < n6; i += kNodeThreads) pr.p[i] = float(fma(beta, double(pr.p[i]), double(pr.z[i])));
             if (threadIdx.x == 0) {
                 pr.scal[0] = rz2;
                 if (rz2 == 0.0) pr.scal[1] = 1.0;

@@ -205,6 +205,29 @@ def test_batch_equals_single_solves(ctx, frames):
         assert ra["energy"] == rb["energy"]
 
 
+def test_large_tile_grid_equals_single_solves(ctx, frames):
+    """A batch whose tile grid exceeds what the chip holds at once (16-vertex
+    tiles, over 1024 tiles in total) takes the two-pass J^T J p reduction; its
+    frames equal their single solves (one-pass reduction) bit for bit."""
+    import paper_1810_02648_amd as cap
+    from gpu_util import make_frame
+    prm = cap.params(1.0, 0.1, 10.0, gn_iters=2, pcg_iters=5)
+    singles, batch = [], []
+    for name, nn in (("mid", 203), ("small0", 64), ("mid", 203), ("small1", 64), ("mid", 203)):
+        f = frames[name]
+        g = og.build_graph(f["xyz"], nn)
+        a = make_frame(ctx, f, g, vertices_per_tile=16)
+        b = make_frame(ctx, f, g, tmpl=a.template)
+        singles.append((a, cap.nonrigid_solve(ctx, a, prm)))
+        batch.append(b)
+    assert sum(fr.template.n_tiles for fr in batch) > 1024
+    assert all(a.template.n_tiles <= 1024 for a, _ in singles)
+    reps = cap.batch_solve(ctx, batch, prm)
+    for (a, ra), b, rb in zip(singles, batch, reps):
+        assert np.array_equal(a.node_state.cpu().numpy(), b.node_state.cpu().numpy())
+        assert ra["energy"] == rb["energy"]
+
+
 def test_graph_replay_matches_eager(ctx, frames):
     """Solves replayed from captured HIP graphs equal the eager launches bit for
     bit, on every replay, with unrelated eager GPU work and synchronisations in

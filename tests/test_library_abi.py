@@ -45,10 +45,10 @@ def test_struct_layouts_match_header():
 #include <stdio.h>
 #include "capture.h"
 int main(void) {
-  printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu\n", sizeof(capture_camera), sizeof(capture_template_desc),
+  printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\n", sizeof(capture_camera), sizeof(capture_template_desc),
          sizeof(capture_frame), sizeof(capture_nonrigid_params), sizeof(capture_report),
          sizeof(capture_body_desc), sizeof(capture_pose_frame), sizeof(capture_pose_params),
-         sizeof(capture_pose_report));
+         sizeof(capture_pose_report), sizeof(capture_template_info));
   return 0;
 }
 """
@@ -60,4 +60,5 @@ int main(void) {
         sizes = [int(x) for x in subprocess.run([exe], capture_output=True, text=True, check=True).stdout.split()]
     assert sizes == [ctypes.sizeof(capi.Camera), ctypes.sizeof(capi.TemplateDesc), ctypes.sizeof(capi.Frame),
                      ctypes.sizeof(capi.NonrigidParams), ctypes.sizeof(capi.Report), ctypes.sizeof(capi.BodyDesc),
-                     ctypes.sizeof(capi.PoseFrame), ctypes.sizeof(capi.PoseParams), ctypes.sizeof(capi.PoseReport)]
+                     ctypes.sizeof(capi.PoseFrame), ctypes.sizeof(capi.PoseParams), ctypes.sizeof(capi.PoseReport),
+                     ctypes.sizeof(capi.TemplateInfo)]
