@@ -14,9 +14,10 @@ namespace cap {
 
 // kernels defined in the other translation units
 __global__ void k_fill_u32(uint32_t *p, size_t n, uint32_t v);
-__global__ void k_blur(const ProbDev *P, int pass, float w0, float w1);
+__global__ void k_blur(const ProbDev *P, float w0, float w1);
 __global__ void k_contour(const ProbDev *P);
 __global__ void k_dt_seg(const ProbDev *P);
+__global__ void k_dt_scan(const ProbDev *P);
 __global__ void k_dt_cols(const ProbDev *P);
 __global__ void k_dt_rows(const ProbDev *P);
 __global__ void k_deform_start(const ProbDev *P);
@@ -191,7 +192,6 @@ __global__ __launch_bounds__(256) void k_node_edges(const float *__restrict__ xy
 void carve(Layout &L, uint8_t *base, const capture_frame &f, ProbDev &pr) {
     const TemplateDev &T = f.tmpl->dev;
     const size_t nv = T.nv, nf = T.nf, nn = T.nn, hw = size_t(f.camera.width) * f.camera.height;
-    pr.blur_tmp = L.take<float>(base, 3 * hw);
     pr.blurred = L.take<float>(base, 3 * hw);
     pr.dt = L.take<float>(base, hw);
     pr.colg = L.take<int>(base, hw);
@@ -369,10 +369,7 @@ int launch_frame(Run &R, int gn_iters = 0) {
     const float w0 = float(e1 / (1.0 + 2.0 * e1)), w1 = float(1.0 / (1.0 + 2.0 * e1));
     const dim3 gpx(blocks(R.max_hw, 256), n), gv(blocks(R.max_nv, 256), n);
     timed(R, K_BLUR, [&] {
-    hipLaunchKernelGGL(k_blur, gpx, dim3(256), 0, s, R.dprobs, 0, w0, w1);
-    });
-    timed(R, K_BLUR, [&] {
-    hipLaunchKernelGGL(k_blur, gpx, dim3(256), 0, s, R.dprobs, 1, w0, w1);
+    hipLaunchKernelGGL(k_blur, gpx, dim3(256), 0, s, R.dprobs, w0, w1);
     });
     timed(R, K_CONTOUR, [&] {
     hipLaunchKernelGGL(k_contour, gpx, dim3(256), 0, s, R.dprobs);
@@ -380,11 +377,11 @@ int launch_frame(Run &R, int gn_iters = 0) {
     const size_t nsegw = size_t(R.max_w) * ((R.max_h + 15) / 16);
     timed(R, K_DT_COLS, [&] {
         hipLaunchKernelGGL(k_dt_seg, dim3(blocks(nsegw, 256), n), dim3(256), 0, s, R.dprobs);
+        hipLaunchKernelGGL(k_dt_scan, dim3(blocks(R.max_w, 64), n), dim3(64), 0, s, R.dprobs);
         hipLaunchKernelGGL(k_dt_cols, dim3(blocks(nsegw, 256), n), dim3(256), 0, s, R.dprobs);
     });
     timed(R, K_DT_ROWS, [&] {
-        hipLaunchKernelGGL(k_dt_rows, dim3(R.max_h, n), dim3(256), (sizeof(int) * 3 + sizeof(short)) * R.max_w + 16,
-                           s, R.dprobs);
+        hipLaunchKernelGGL(k_dt_rows, dim3(R.max_h, n), dim3(256), dt_rows_lds(R.max_w), s, R.dprobs);
     });
     timed(R, K_DEFORM, [&] {
     hipLaunchKernelGGL(k_deform_start, gv, dim3(256), 0, s, R.dprobs);

@@ -33,6 +33,9 @@ constexpr int kNodeThreads = 1024;    // threads of a per-problem node workgroup
 constexpr int kMaxImageSide = 4096;
 constexpr int kRasterSmall = 256;         // pixel-box size above which a face is rasterised by a workgroup
 constexpr int kRasterBigBlocks = 512;
+constexpr int kDtChunks = 32;            // column chunks of the exact distance transform's row pass
+// Dynamic LDS of the row pass for rows of W pixels: G and breakpoints (int), sites (short).
+inline size_t dt_rows_lds(int W) { return (sizeof(int) * 3 + sizeof(short)) * size_t(W) + 16; }
 constexpr int kApplySplitTiles = 1024;   // tile grids above this take the two-pass J^T J p reduction
 constexpr int kGraphCache = 16;          // captured solve graphs kept per context
 constexpr int kSplitThreads = 256;       // PCG split over workgroups for large node counts:
@@ -116,7 +119,7 @@ struct ProbDev {
     int exclude_case2;
     int outline_only;            // contour set B restricted to the rendered model's outline
     // images
-    gptr<float> blur_tmp, blurred, dt;
+    gptr<float> blurred, dt;
     gptr<int> colg;
     gptr<int> seg_first, seg_last;   // [ceil(H/16)][W]
     gptr<uint32_t> zbuf;

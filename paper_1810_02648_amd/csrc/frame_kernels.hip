@@ -13,29 +13,27 @@ __global__ void k_fill_u32(uint32_t *p, size_t n, uint32_t v) {
 }
 
 // ---------------------------------------------------------------- blur
-// Separable Gaussian (kernel 3), clamp-to-edge; pass 0 horizontal, 1 vertical.
-__global__ void k_blur(const ProbDev *__restrict__ P, int pass, float w0, float w1) {
+// Separable Gaussian (kernel 3), clamp-to-edge, in one pass: each pixel forms
+// the horizontal sums of its three rows (rounded as a horizontal pass would
+// store them) and then the vertical sum.
+__global__ void k_blur(const ProbDev *__restrict__ P, float w0, float w1) {
     const ProbDev &pr = P[blockIdx.y];
     const int W = pr.W, H = pr.H;
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= W * H) return;
     int y = i / W, x = i - y * W;
     const size_t plane = size_t(W) * H;
-    const CAP_GLOBAL float *src = pass == 0 ? pr.image.g() : pr.blur_tmp.g();
-    CAP_GLOBAL float *dst = pass == 0 ? pr.blur_tmp.g() : pr.blurred.g();
+    const int xl = max(x - 1, 0), xr = min(x + 1, W - 1);
+    const int rows[3] = {max(y - 1, 0), y, min(y + 1, H - 1)};
     for (int c = 0; c < 3; ++c) {
-        const CAP_GLOBAL float *s = src + c * plane;
-        float a, b, d;
-        if (pass == 0) {
-            a = s[size_t(y) * W + max(x - 1, 0)];
-            b = s[size_t(y) * W + x];
-            d = s[size_t(y) * W + min(x + 1, W - 1)];
-        } else {
-            a = s[size_t(max(y - 1, 0)) * W + x];
-            b = s[size_t(y) * W + x];
-            d = s[size_t(min(y + 1, H - 1)) * W + x];
+        const CAP_GLOBAL float *s = pr.image.g() + c * plane;
+        float h[3];
+#pragma unroll
+        for (int r = 0; r < 3; ++r) {     // horizontal pass of rows y-1, y, y+1 (clamped)
+            const CAP_GLOBAL float *row = s + size_t(rows[r]) * W;
+            h[r] = (w0 * row[xl] + w1 * row[x]) + w0 * row[xr];
         }
-        dst[c * plane + i] = (w0 * a + w1 * b) + w0 * d;
+        pr.blurred[c * plane + i] = (w0 * h[0] + w1 * h[1]) + w0 * h[2];
     }
 }
 
@@ -74,7 +72,42 @@ __global__ void k_dt_seg(const ProbDev *__restrict__ P) {
     pr.seg_last[i] = last;
 }
 
-// Phase 1b: per (column, segment), distance in rows to the nearest contour
+// Phase 1b: per column, in one pass down and one up, the nearest contour row
+// above and below each segment, written over seg_last (above) and seg_first
+// (below).  Segments are read kScanBatch at a time into registers, so the
+// loads of a batch are in flight together.
+constexpr int kScanBatch = 16;
+
+__global__ void k_dt_scan(const ProbDev *__restrict__ P) {
+    const ProbDev &pr = P[blockIdx.y];
+    const int W = pr.W, H = pr.H, nseg = (H + kSeg - 1) / kSeg;
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    if (x >= W) return;
+    int carry = -kFar;
+    for (int t0 = 0; t0 < nseg; t0 += kScanBatch) {
+        int v[kScanBatch];
+#pragma unroll
+        for (int u = 0; u < kScanBatch; ++u) v[u] = t0 + u < nseg ? pr.seg_last[(t0 + u) * W + x] : -kFar;
+#pragma unroll
+        for (int u = 0; u < kScanBatch; ++u) {
+            if (t0 + u < nseg) pr.seg_last[(t0 + u) * W + x] = carry;
+            if (v[u] >= 0) carry = v[u];
+        }
+    }
+    carry = 2 * kFar;
+    for (int t1 = nseg; t1 > 0; t1 -= kScanBatch) {
+        int v[kScanBatch];
+#pragma unroll
+        for (int u = 0; u < kScanBatch; ++u) v[u] = t1 - 1 - u >= 0 ? pr.seg_first[(t1 - 1 - u) * W + x] : kFar;
+#pragma unroll
+        for (int u = 0; u < kScanBatch; ++u) {
+            if (t1 - 1 - u >= 0) pr.seg_first[(t1 - 1 - u) * W + x] = carry;
+            if (v[u] < kFar) carry = v[u];
+        }
+    }
+}
+
+// Phase 1c: per (column, segment), distance in rows to the nearest contour
 // pixel of the column (carry from the other segments, then the segment's rows).
 __global__ void k_dt_cols(const ProbDev *__restrict__ P) {
     const ProbDev &pr = P[blockIdx.y];
@@ -82,15 +115,7 @@ __global__ void k_dt_cols(const ProbDev *__restrict__ P) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= W * nseg) return;
     const int s = i / W, x = i - s * W;
-    int above = -kFar, below = 2 * kFar;
-    for (int t = s - 1; t >= 0; --t) {
-        const int l = pr.seg_last[t * W + x];
-        if (l >= 0) { above = l; break; }
-    }
-    for (int t = s + 1; t < nseg; ++t) {
-        const int f = pr.seg_first[t * W + x];
-        if (f < kFar) { below = f; break; }
-    }
+    const int above = pr.seg_last[i], below = pr.seg_first[i];
     const int y0 = s * kSeg, y1 = min(H, y0 + kSeg);
     int d[kSeg];
     uint8_t c[kSeg];
@@ -112,17 +137,17 @@ __global__ void k_dt_cols(const ProbDev *__restrict__ P) {
 }
 
 // Phase 2: per row, D(x) = min over x' of (x - x')^2 + G(x'), G = g^2, exact.
-// The row is cut into kChunks column chunks; one thread per chunk builds the
+// The row is cut into kDtChunks column chunks; one thread per chunk builds the
 // lower envelope of the chunk's parabolas (x - x')^2 + G(x') (sequential
-// envelope construction with exact rational breakpoints compared in int64),
-// then every pixel evaluates its own chunk's envelope by binary search and
-// visits neighbouring chunks outwards while their column distance can still
-// beat the best value.  One workgroup per row, all in LDS.
-constexpr int kChunks = 32;
-
+// envelope construction with exact rational breakpoints compared in int64)
+// and the chunk's smallest G.  Every pixel then evaluates its own chunk's
+// envelope by binary search and visits the neighbouring chunks outwards while
+// their column distance can still beat the best value; a chunk whose bound
+// (column distance)^2 + min G cannot beat it is passed over without a search.
+// One workgroup per row, all in LDS.
 __global__ __launch_bounds__(256) void k_dt_rows(const ProbDev *__restrict__ P) {
     extern __shared__ int sh[];
-    __shared__ int cnt[kChunks];
+    __shared__ int cnt[kDtChunks], cmin[kDtChunks];
     const ProbDev &pr = P[blockIdx.y];
     const int W = pr.W, H = pr.H;
     const int y = blockIdx.x;
@@ -135,13 +160,14 @@ __global__ __launch_bounds__(256) void k_dt_rows(const ProbDev *__restrict__ P) 
         G[x] = g >= kFar ? far2 : g * g;
     }
     __syncthreads();
-    const int cs = (W + kChunks - 1) / kChunks;
-    if (threadIdx.x < kChunks) {
+    const int cs = (W + kDtChunks - 1) / kDtChunks;
+    if (threadIdx.x < kDtChunks) {
         const int c = threadIdx.x, a = c * cs, b = min(W, a + cs);
-        int k = -1;
+        int k = -1, gmin = far2;
         for (int q = a; q < b; ++q) {
             const int gq = G[q];
             if (gq >= far2) continue;
+            gmin = min(gmin, gq);
             if (k < 0) {
                 k = 0;
                 ev[a] = short(q);
@@ -163,6 +189,7 @@ __global__ __launch_bounds__(256) void k_dt_rows(const ProbDev *__restrict__ P) 
             zd[a + k] = den;
         }
         cnt[c] = k + 1;
+        cmin[c] = gmin;
     }
     __syncthreads();
     auto eval = [&](int c, int x) {
@@ -181,18 +208,23 @@ __global__ __launch_bounds__(256) void k_dt_rows(const ProbDev *__restrict__ P) 
         const int c0 = x / cs;
         int best = eval(c0, x);
         int l = c0 - 1, r = c0 + 1;
-        while (l >= 0 || r < kChunks) {
+        while (l >= 0 || r < kDtChunks) {
             if (l >= 0) {
                 const int d = x - (min(W, l * cs + cs) - 1);
-                if (d * d < best) { const int e = eval(l, x); best = e < best ? e : best; --l; } else l = -1;
+                if (d * d < best) {
+                    if (d * d + cmin[l] < best) { const int e = eval(l, x); best = e < best ? e : best; }
+                    --l;
+                } else {
+                    l = -1;
+                }
             }
-            if (r < kChunks) {
-                if (r * cs < W && (r * cs - x) * (r * cs - x) < best) {
-                    const int e = eval(r, x);
-                    best = e < best ? e : best;
+            if (r < kDtChunks) {
+                const int d = r * cs - x;
+                if (r * cs < W && d * d < best) {
+                    if (d * d + cmin[r] < best) { const int e = eval(r, x); best = e < best ? e : best; }
                     ++r;
                 } else {
-                    r = kChunks;
+                    r = kDtChunks;
                 }
             }
         }
