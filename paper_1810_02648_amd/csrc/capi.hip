@@ -330,12 +330,14 @@ int setup(Run &R, capture_ctx *ctx, int n, const capture_frame *frames, const ca
         R.max_nn = std::max(R.max_nn, T.nn);
         R.max_me = std::max(R.max_me, T.nmedges);
         R.max_tiles = std::max(R.max_tiles, T.ntiles);
-        R.max_contrib = std::max(R.max_contrib, T.max_contrib);
         R.max_hw = std::max(R.max_hw, pr.W * pr.H);
         R.max_w = std::max(R.max_w, pr.W);
         R.max_h = std::max(R.max_h, pr.H);
-        R.lds_lin = std::max(R.lds_lin, sizeof(float) * (size_t(T.max_slots) * 15 + size_t(T.max_contrib) * 12));
-        R.lds_apply = std::max(R.lds_apply, sizeof(float) * (size_t(T.max_slots) * 18 + size_t(T.max_contrib) * 6));
+        // contribution buffers: components at an odd stride (max_contrib | 1)
+        R.lds_lin = std::max(R.lds_lin, sizeof(float) * (size_t(T.max_slots) * 15 + size_t(T.max_contrib | 1) * 12));
+        R.lds_apply = std::max(R.lds_apply, sizeof(float) * (size_t(T.max_slots) * 18 + size_t(T.max_contrib | 1) * 6));
+        R.lds_apply_split =
+            std::max(R.lds_apply_split, sizeof(float) * (size_t(T.max_slots) * 18 + size_t(T.max_contrib | 1) * 3));
     }
     // sized once for both the descriptors and the report read-back of `collect`
     R.grid_tiles = grid_tiles(n, frames);
@@ -404,8 +406,8 @@ int launch_frame(Run &R, int gn_iters = 0) {
 // one-pass reduction; larger ones the two-pass variant with half the LDS.
 void launch_apply(Run &R) {
     if (R.grid_tiles > kApplySplitTiles) {
-        const size_t lds = R.lds_apply - sizeof(float) * 3 * R.max_contrib;
-        hipLaunchKernelGGL(k_apply<1>, dim3(unsigned(R.grid_tiles)), dim3(kTileThreads), lds, R.s, R.dprobs, R.tiles);
+        hipLaunchKernelGGL(k_apply<1>, dim3(unsigned(R.grid_tiles)), dim3(kTileThreads), R.lds_apply_split, R.s,
+                           R.dprobs, R.tiles);
     } else {
         hipLaunchKernelGGL(k_apply<0>, dim3(unsigned(R.grid_tiles)), dim3(kTileThreads), R.lds_apply, R.s, R.dprobs,
                            R.tiles);

@@ -39,8 +39,7 @@ struct Run {
     std::vector<ProbDev> probs;
     ProbDev *dprobs = nullptr;
     int max_nv = 0, max_nf = 0, max_nn = 0, max_hw = 0, max_w = 0, max_h = 0, max_tiles = 0, max_me = 0;
-    size_t lds_lin = 0, lds_apply = 0;
-    int max_contrib = 0;
+    size_t lds_lin = 0, lds_apply = 0, lds_apply_split = 0;
     TileDesc *tiles = nullptr;   // device [grid_tiles]: tile-kernel work items (die-interleaved grid)
     int total_tiles = 0;         // tiles of all problems
     int grid_tiles = 0;          // total_tiles rounded up to a multiple of 8

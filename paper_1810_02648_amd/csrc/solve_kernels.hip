@@ -129,7 +129,9 @@ __global__ __launch_bounds__(kTileThreads) void k_linearize(const ProbDev *__res
         for (int q = 0; q < 3; ++q) L.g[3 * lv + q] = sv[12 + q];
     }
     __syncthreads();
-    const int NC = full ? lbeg[ns] : 0;
+    // component stride of the contribution buffer: odd, so that the twelve
+    // components of one position sit in different LDS banks
+    const int NC = full ? (lbeg[ns] | 1) : 0;
 
     double e_ph = 0.0, e_s = 0.0, e_sa = 0.0, e_a = 0.0, e_v = 0.0;
     if (has_v) {
@@ -356,7 +358,7 @@ __global__ __launch_bounds__(kTileThreads) void k_apply(const ProbDev *__restric
         for (int q = 0; q < 6; ++q) sp[6 * lv + q] = sv[12 + q];
     }
     __syncthreads();
-    const int NC = lbeg[ns];
+    const int NC = lbeg[ns] | 1;     // odd component stride: components in different LDS banks
     // With kSplit the six components are reduced in two passes of three
     // (rotational, then translational) through one [3][NC] buffer, which
     // halves the LDS of a workgroup and so raises the workgroups a CU holds
