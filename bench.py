@@ -57,6 +57,39 @@ def algorithmic_bytes(kernel, n_act, n_nodes, n_edges, n_pix, n_faces, n_verts):
     return 0
 
 
+# HBM bytes per launch of the J^T J p kernel, measured with rocprofv3 counter
+# runs (FETCH_SIZE, WRITE_SIZE, scaled by a plain copy of known size) and kept
+# in profiles/ with the fingerprint of the kernel sources they were taken on;
+# a changed kernel reports null until it is measured again.
+TRAFFIC_TABLE = os.path.join(ROOT, "profiles", "k_apply_hbm_traffic.md")
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_1810_02648_amd", "csrc", f)
+                  for f in ("solve_kernels.hip", "common.hpp", "device.hpp")]
+
+
+def kernel_fingerprint():
+    import hashlib
+    h = hashlib.sha256()
+    for fn in KERNEL_SOURCES:
+        with open(fn, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel, key):
+    """HBM bytes per launch for `kernel` on workload `key`, or None."""
+    if kernel != "apply" or not os.path.exists(TRAFFIC_TABLE):
+        return None
+    fp = kernel_fingerprint()
+    for line in open(TRAFFIC_TABLE):
+        cells = [c.strip() for c in line.strip().strip("|").split("|")]
+        if len(cells) == 5 and cells[0] == key and cells[1] == fp:
+            try:
+                return float(cells[4].replace(",", ""))
+            except ValueError:
+                return None
+    return None
+
+
 def cpu_baseline(frame_dict, n_nodes, gn, pcg, weights):
     """The FP64 oracle (exact Cholesky solves) on one frame of the same workload."""
     import numpy as np  # noqa: F401
@@ -78,7 +111,7 @@ def cpu_baseline(frame_dict, n_nodes, gn, pcg, weights):
                        % (gn, dt, out["energies"][-1]["total"]))
 
 
-def roofline_for(prof, steps, batch, n_act, nn, n_edges, W, H, nf, nv):
+def roofline_for(prof, steps, batch, n_act, nn, n_edges, W, H, nf, nv, key):
     per_step_us = {k: 1000.0 * ms / steps for k, (ms, n) in prof.items() if n}
     dom = max(per_step_us, key=per_step_us.get)
     bytes_launch = batch * algorithmic_bytes(dom, n_act, nn, n_edges, W * H, nf, nv)
@@ -87,9 +120,9 @@ def roofline_for(prof, steps, batch, n_act, nn, n_edges, W, H, nf, nv):
     apply_s = prof["apply"][0] / 1000.0 / max(prof["apply"][1], 1)
     apply_bytes = batch * algorithmic_bytes("apply", n_act, nn, n_edges, W * H, 0, 0)
     return {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS, "traffic": None, "avg_us": avg_s * 1e6,
-            "algorithmic_bytes_per_launch": bytes_launch, "apply_achieved_GBs": apply_bytes / apply_s / 1e9,
-            "apply_avg_us": apply_s * 1e6}
+            "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(dom, key), "traffic_key": key,
+            "avg_us": avg_s * 1e6, "algorithmic_bytes_per_launch": bytes_launch,
+            "apply_achieved_GBs": apply_bytes / apply_s / 1e9, "apply_avg_us": apply_s * 1e6}
 
 
 def bench_sequence(args, cap, torch):
@@ -134,7 +167,8 @@ def bench_sequence(args, cap, torch):
     n_act = cap.nonrigid_solve(ctx, S.frame(test[0], states[test[0] - 1].clone()), S.prm)["n_visible"]
     n_edges = int((S.graph["edge_dst"] >= 0).sum().item())
     calls = 2 * len(test)    # one evaluate pass = one plain and one learned solve per frame
-    roof = roofline_for(prof, calls, 1, n_act, S.nn, n_edges, W, H, seq["tri"].shape[1], seq["xyz"].shape[1])
+    roof = roofline_for(prof, calls, 1, n_act, S.nn, n_edges, W, H, seq["tri"].shape[1], seq["xyz"].shape[1],
+                        "%s/tile0" % args.workload)
     return {
         "metric": METRIC,
         "value": n / tl,
@@ -249,7 +283,7 @@ def bench_frame(args, cap, torch):
     W, H = f["cam"].width, f["cam"].height
     n_edges = int((graph["edge_dst"] >= 0).sum().item())
     roof = roofline_for(prof, args.steps, args.batch, r0["n_visible"], nn, n_edges, W, H, f["tri"].shape[1],
-                        f["xyz"].shape[1])
+                        f["xyz"].shape[1], "%sx%d/tile%d" % (args.workload, args.batch, tile))
     return {
         "metric": METRIC,
         "value": args.steps * args.batch / elapsed,
@@ -358,8 +392,10 @@ def bench_batch(args, cap, torch):
     avg_s = prof[dom][0] / 1000.0 / prof[dom][1]
     achieved = total_bytes(dom) / avg_s / 1e9
     apply_s = prof["apply"][0] / 1000.0 / max(prof["apply"][1], 1)
+    key = "batch%d/tile%d" % (n, tile)
     roof = {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS, "traffic": None, "avg_us": avg_s * 1e6,
+            "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(dom, key), "traffic_key": key,
+            "avg_us": avg_s * 1e6,
             "algorithmic_bytes_per_launch": total_bytes(dom),
             "apply_achieved_GBs": total_bytes("apply") / apply_s / 1e9, "apply_avg_us": apply_s * 1e6}
     nv = [f["xyz"].shape[1] for f in frames_h]
