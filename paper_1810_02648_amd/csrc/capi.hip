@@ -18,6 +18,7 @@ __global__ void k_blur(const ProbDev *P, float w0, float w1);
 __global__ void k_contour(const ProbDev *P);
 __global__ void k_dt_seg(const ProbDev *P);
 __global__ void k_dt_scan(const ProbDev *P);
+__global__ void k_dt_scan_cols(const ProbDev *P);
 __global__ void k_dt_cols(const ProbDev *P);
 __global__ void k_dt_rows(const ProbDev *P);
 __global__ void k_deform_start(const ProbDev *P);
@@ -379,7 +380,10 @@ int launch_frame(Run &R, int gn_iters = 0) {
     const size_t nsegw = size_t(R.max_w) * ((R.max_h + 15) / 16);
     timed(R, K_DT_COLS, [&] {
         hipLaunchKernelGGL(k_dt_seg, dim3(blocks(nsegw, 256), n), dim3(256), 0, s, R.dprobs);
-        hipLaunchKernelGGL(k_dt_scan, dim3(blocks(R.max_w, 64), n), dim3(64), 0, s, R.dprobs);
+        if (size_t(n) * R.max_w >= kScanColsMin)      // enough columns: a thread per column
+            hipLaunchKernelGGL(k_dt_scan_cols, dim3(blocks(R.max_w, 64), n), dim3(64), 0, s, R.dprobs);
+        else                                            // few columns: a wave per column
+            hipLaunchKernelGGL(k_dt_scan, dim3(blocks(R.max_w, 4), n), dim3(256), 0, s, R.dprobs);
         hipLaunchKernelGGL(k_dt_cols, dim3(blocks(nsegw, 256), n), dim3(256), 0, s, R.dprobs);
     });
     timed(R, K_DT_ROWS, [&] {
@@ -420,7 +424,7 @@ void launch_linearize(Run &R, int gn, int energy_only, int check_target = 0) {
                            energy_only);
     });
     timed(R, K_NODE_INIT, [&] {
-        hipLaunchKernelGGL(k_node_init, dim3(R.n), dim3(kNodeThreads), 0, R.s, R.dprobs, gn, energy_only,
+        hipLaunchKernelGGL(k_node_init, dim3(R.n), dim3(kInitThreads), 0, R.s, R.dprobs, gn, energy_only,
                            check_target);
     });
 }
@@ -1023,7 +1027,7 @@ int warm_sequence(Run &R, const capture_nonrigid_params *params, capture_warmsta
                            R.tiles, 2);
     });
     timed(R, K_NODE_INIT, [&] {
-        hipLaunchKernelGGL(k_node_init, dim3(R.n), dim3(kNodeThreads), 0, R.s, R.dprobs, 0, 0, 3);
+        hipLaunchKernelGGL(k_node_init, dim3(R.n), dim3(kInitThreads), 0, R.s, R.dprobs, 0, 0, 3);
     });
     if (!split) return launch_solve(R, params, 1, true);
     launch_steps(R, params, 1, true, 0, 1);

@@ -30,9 +30,11 @@ constexpr int kMaxTileVerts = 256;    // vertices per tile
 constexpr int kMaxTileContrib = 1024; // contributions held in LDS per tile
 constexpr int kMaxTileSlots = 200;    // distinct nodes touched by a tile
 constexpr int kNodeThreads = 1024;    // threads of a per-problem node workgroup
+constexpr int kInitThreads = 512;     // threads of the post-linearisation node workgroup (k_node_init)
 constexpr int kMaxImageSide = 4096;
 constexpr int kRasterSmall = 256;         // pixel-box size above which a face is rasterised by a workgroup
 constexpr int kRasterBigBlocks = 512;
+constexpr int kScanColsMin = 16384;      // image columns (all frames) from which the segment scan runs a thread per column
 constexpr int kDtChunks = 32;            // column chunks of the exact distance transform's row pass
 // Dynamic LDS of the row pass for rows of W pixels: G and breakpoints (int), sites (short).
 inline size_t dt_rows_lds(int W) { return (sizeof(int) * 3 + sizeof(short)) * size_t(W) + 16; }

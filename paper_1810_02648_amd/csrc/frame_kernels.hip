@@ -72,13 +72,71 @@ __global__ void k_dt_seg(const ProbDev *__restrict__ P) {
     pr.seg_last[i] = last;
 }
 
-// Phase 1b: per column, in one pass down and one up, the nearest contour row
-// above and below each segment, written over seg_last (above) and seg_first
-// (below).  Segments are read kScanBatch at a time into registers, so the
-// loads of a batch are in flight together.
+// Phase 1b: per column, the nearest contour row above and below each segment,
+// written over seg_last (above) and seg_first (below).  One wave per column,
+// a lane per segment (kScanChunks chunks of 64 segments): the rows above are
+// an exclusive prefix maximum of the segments' last contour rows (rows grow
+// with the segment), the rows below an exclusive suffix minimum of their
+// first ones, both formed with lane shuffles.
+constexpr int kScanChunks = (kMaxImageSide / kSeg + 63) / 64;
+
+__global__ __launch_bounds__(256) void k_dt_scan(const ProbDev *__restrict__ P) {
+    const ProbDev &pr = P[blockIdx.y];
+    const int W = pr.W, H = pr.H, nseg = (H + kSeg - 1) / kSeg;
+    const int x = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+    if (x >= W) return;
+    int last[kScanChunks], first[kScanChunks];
+#pragma unroll
+    for (int q = 0; q < kScanChunks; ++q) {
+        const int t = q * 64 + lane;
+        last[q] = t < nseg ? pr.seg_last[t * W + x] : -kFar;
+        first[q] = t < nseg ? pr.seg_first[t * W + x] : kFar;
+    }
+    int up = -kFar;        // rows above: carried forward over the chunks
+#pragma unroll
+    for (int q = 0; q < kScanChunks; ++q) {
+        int v = last[q];
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const int u = __shfl_up(v, o);
+            if (lane >= o) v = max(v, u);
+        }
+        const int before = __shfl_up(v, 1);
+        const int excl = lane == 0 ? up : max(up, before);
+        up = max(up, __shfl(v, 63));
+        last[q] = excl;
+    }
+    int down = kFar;       // rows below: carried backward over the chunks
+#pragma unroll
+    for (int q = kScanChunks - 1; q >= 0; --q) {
+        int v = first[q];
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const int u = __shfl_down(v, o);
+            if (lane + o < 64) v = min(v, u);
+        }
+        const int after = __shfl_down(v, 1);
+        const int excl = lane == 63 ? down : min(down, after);
+        down = min(down, __shfl(v, 0));
+        first[q] = excl;
+    }
+#pragma unroll
+    for (int q = 0; q < kScanChunks; ++q) {
+        const int t = q * 64 + lane;
+        if (t < nseg) {
+            pr.seg_last[t * W + x] = last[q] < 0 ? -kFar : last[q];
+            pr.seg_first[t * W + x] = first[q] >= kFar ? 2 * kFar : first[q];
+        }
+    }
+}
+
+// The same with one thread per column (coalesced across columns), in one pass
+// down and one up; segments are read kScanBatch at a time into registers, so
+// the loads of a batch are in flight together.  Used when the frames have
+// enough columns in total to fill the chip.
 constexpr int kScanBatch = 16;
 
-__global__ void k_dt_scan(const ProbDev *__restrict__ P) {
+__global__ void k_dt_scan_cols(const ProbDev *__restrict__ P) {
     const ProbDev &pr = P[blockIdx.y];
     const int W = pr.W, H = pr.H, nseg = (H + kSeg - 1) / kSeg;
     const int x = blockIdx.x * blockDim.x + threadIdx.x;

@@ -16,6 +16,7 @@ __global__ void k_fill_u32(uint32_t *p, size_t n, uint32_t v);
 __global__ void k_contour(const ProbDev *P);
 __global__ void k_dt_seg(const ProbDev *P);
 __global__ void k_dt_scan(const ProbDev *P);
+__global__ void k_dt_scan_cols(const ProbDev *P);
 __global__ void k_dt_cols(const ProbDev *P);
 __global__ void k_dt_rows(const ProbDev *P);
 __global__ void k_raster(const ProbDev *P);
@@ -176,7 +177,7 @@ int launch_pose_decisions(PoseRun &P) {
     const size_t nsegw = size_t(pr.W) * ((pr.H + 15) / 16);
     timed(R, K_DT_COLS, [&] {
         hipLaunchKernelGGL(k_dt_seg, dim3(blocks(nsegw, 256)), dim3(256), 0, s, R.dprobs);
-        hipLaunchKernelGGL(k_dt_scan, dim3(blocks(pr.W, 64)), dim3(64), 0, s, R.dprobs);
+        hipLaunchKernelGGL(k_dt_scan, dim3(blocks(pr.W, 4)), dim3(256), 0, s, R.dprobs);
         hipLaunchKernelGGL(k_dt_cols, dim3(blocks(nsegw, 256)), dim3(256), 0, s, R.dprobs);
     });
     timed(R, K_DT_ROWS, [&] {

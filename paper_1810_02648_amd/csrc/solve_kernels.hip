@@ -473,34 +473,49 @@ template __global__ void k_apply<1>(const ProbDev *, const TileDesc *);
 // ----------------------------------------------------------------------------
 
 constexpr int kItems = 8;   // node kernels: up to kItems * kNodeThreads = 8192 items (1365 nodes) in registers
+constexpr int kInitItems = 16;   // k_node_init (kInitThreads): the same 8192 items, 256 VGPRs per lane
 
 // Sum of a node's tile partials (stride floats per partial), in tile order.
+// Sum of partials [pb, pe) (component c, stride floats apart) in order; the
+// first kParts loads are issued together (a node is touched by a handful of
+// tiles), the rest, if any, one after another.
+constexpr int kParts = 8;
+
+__device__ inline float sum_parts(gptr<const float> partial, int stride, int c, int pb, int pe) {
+    float v[kParts];
+#pragma unroll
+    for (int u = 0; u < kParts; ++u) v[u] = pb + u < pe ? partial[size_t(pb + u) * stride + c] : 0.0f;
+    float a = 0.0f;
+#pragma unroll
+    for (int u = 0; u < kParts; ++u)
+        if (pb + u < pe) a += v[u];
+    for (int q = pb + kParts; q < pe; ++q) a += partial[size_t(q) * stride + c];
+    return a;
+}
+
 __device__ inline float gather_node(const TemplateDev &T, gptr<const float> partial, int stride, int k,
                                     int c) {
-    const int pb = T.node_pbeg[k], pe = T.node_pbeg[k + 1];
-    float a = 0.0f;
-    for (int q = pb; q < pe; ++q) a += partial[size_t(q) * stride + c];
-    return a;
+    return sum_parts(partial, stride, c, T.node_pbeg[k], T.node_pbeg[k + 1]);
 }
 
 // After a linearisation: b, diag, Jacobi preconditioner, PCG start vectors
 // (x = 0, r = b, z = M^-1 r, p = z), r.z, and the energy of GN step `gn`.
 // One thread per (component, node) item; every load is issued before the
 // stop tests, and r.z and the energy terms share one block reduction.
-__global__ __launch_bounds__(kNodeThreads) void k_node_init(const ProbDev *__restrict__ P, int gn, int energy_only, int check_target) {
-    __shared__ double red[kNodeThreads / 64][1 + kTerms];
+__global__ __launch_bounds__(kInitThreads) void k_node_init(const ProbDev *__restrict__ P, int gn, int energy_only, int check_target) {
+    __shared__ double red[kInitThreads / 64][1 + kTerms];
     const ProbDev &pr = P[blockIdx.x];
     const TemplateDev &T = pr.T;
     const int nn = T.nn, n6 = 6 * nn;
     double v[1 + kTerms] = {0, 0, 0, 0, 0, 0};   // r.z, then the energy terms
     for (int t = threadIdx.x; t < T.ntiles; t += blockDim.x)
         for (int q = 0; q < kTerms; ++q) v[1 + q] += pr.tile_e[size_t(t) * kTerms + q];
-    const bool regs = n6 <= kItems * kNodeThreads;
-    int pb[kItems], pe[kItems];
+    const bool regs = n6 <= kInitItems * kInitThreads;
+    int pb[kInitItems], pe[kInitItems];
     if (!energy_only && regs) {
 #pragma unroll
-        for (int j = 0; j < kItems; ++j) {
-            const int i = threadIdx.x + j * kNodeThreads;
+        for (int j = 0; j < kInitItems; ++j) {
+            const int i = threadIdx.x + j * kInitThreads;
             pb[j] = pe[j] = 0;
             if (i < n6) {
                 const int k = i % nn;
@@ -513,19 +528,33 @@ __global__ __launch_bounds__(kNodeThreads) void k_node_init(const ProbDev *__res
     if (!energy_only) {
         if (regs) {
 #pragma unroll
-            for (int j = 0; j < kItems; ++j) {
-                const int i = threadIdx.x + j * kNodeThreads;
+            for (int j = 0; j < kInitItems; ++j) {
+                const int i = threadIdx.x + j * kInitThreads;
                 if (i < n6) {
                     const int c = i / nn;
+                    // the two components' loads interleaved: b and the diagonal of one part share a line
+                    float vb[kParts], vd[kParts];
+#pragma unroll
+                    for (int u = 0; u < kParts; ++u) {
+                        const bool in = pb[j] + u < pe[j];
+                        vb[u] = in ? pr.partial[size_t(pb[j] + u) * 12 + c] : 0.0f;
+                        vd[u] = in ? pr.partial[size_t(pb[j] + u) * 12 + 6 + c] : 0.0f;
+                    }
                     float b = 0.0f, d = 0.0f;
-                    for (int q = pb[j]; q < pe[j]; ++q) b += pr.partial[size_t(q) * 12 + c];
-                    for (int q = pb[j]; q < pe[j]; ++q) d += pr.partial[size_t(q) * 12 + 6 + c];
+#pragma unroll
+                    for (int u = 0; u < kParts; ++u)
+                        if (pb[j] + u < pe[j]) { b += vb[u]; d += vd[u]; }
+                    for (int q = pb[j] + kParts; q < pe[j]; ++q) {
+                        b += pr.partial[size_t(q) * 12 + c];
+                        d += pr.partial[size_t(q) * 12 + 6 + c];
+                    }
                     const float mi = d > 0.0f ? 1.0f / d : 1.0f;
                     const float z = mi * b;
                     pr.b[i] = b; pr.diag[i] = d; pr.dinv[i] = mi;
                     pr.x[i] = 0.0f; pr.r[i] = b; pr.z[i] = z; pr.p[i] = z;
                     v[0] += double(b) * double(z);
                 }
+                __asm__ volatile("" ::: "memory");    // one item's loads in flight at a time (registers)
             }
         } else {
             for (int i = threadIdx.x; i < n6; i += blockDim.x) {
@@ -540,7 +569,7 @@ __global__ __launch_bounds__(kNodeThreads) void k_node_init(const ProbDev *__res
             }
         }
     }
-    block_sum_n<kNodeThreads, 1 + kTerms>(v, red);
+    block_sum_n<kInitThreads, 1 + kTerms>(v, red);
     if (threadIdx.x == 0) {
         const double rz = v[0];
         if (!energy_only) {
@@ -652,10 +681,8 @@ __global__ __launch_bounds__(kNodeThreads) void k_node_pcg(const ProbDev *__rest
 #pragma unroll
             for (int j = 0; j < kItems; ++j) {
                 const int c = (threadIdx.x + j * kNodeThreads) / nn;
-                float acc = 0.0f;
-                for (int q = pb[j]; q < pe[j]; ++q) acc += pr.partial[size_t(q) * 6 + c];
-                ap[j] = acc;
-                pap += double(pp[j]) * double(acc);
+                ap[j] = sum_parts(pr.partial, 6, c, pb[j], pe[j]);
+                pap += double(pp[j]) * double(ap[j]);
             }
             pap = block_sum<kNodeThreads>(pap, red);
             if (pap <= 0.0) {

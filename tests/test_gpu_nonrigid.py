@@ -228,6 +228,26 @@ def test_large_tile_grid_equals_single_solves(ctx, frames):
         assert ra["energy"] == rb["energy"]
 
 
+def test_wide_batch_equals_single_solves(ctx, frames):
+    """A batch with 16384 or more image columns in total takes the
+    thread-per-column segment scan of the distance transform (single frames
+    take the wave-per-column scan); its frames equal their single solves bit
+    for bit."""
+    import paper_1810_02648_amd as cap
+    from gpu_util import make_frame
+    prm = cap.params(1.0, 0.1, 10.0, gn_iters=1, pcg_iters=2)
+    f = frames["mid"]
+    g = og.build_graph(f["xyz"], 203)
+    a = make_frame(ctx, f, g)
+    ra = cap.nonrigid_solve(ctx, a, prm)
+    batch = [make_frame(ctx, f, g, tmpl=a.template) for _ in range(32)]
+    assert sum(fr.camera.width for fr in batch) >= 16384
+    reps = cap.batch_solve(ctx, batch, prm)
+    for b, rb in zip(batch, reps):
+        assert np.array_equal(a.node_state.cpu().numpy(), b.node_state.cpu().numpy())
+        assert ra["energy"] == rb["energy"]
+
+
 def test_graph_replay_matches_eager(ctx, frames):
     """Solves replayed from captured HIP graphs equal the eager launches bit for
     bit, on every replay, with unrelated eager GPU work and synchronisations in
