@@ -35,9 +35,12 @@ constexpr int kMaxImageSide = 4096;
 constexpr int kRasterSmall = 256;         // pixel-box size above which a face is rasterised by a workgroup
 constexpr int kRasterBigBlocks = 512;
 constexpr int kScanColsMin = 16384;      // image columns (all frames) from which the segment scan runs a thread per column
-constexpr int kDtChunks = 32;            // column chunks of the exact distance transform's row pass
-// Dynamic LDS of the row pass for rows of W pixels: G and breakpoints (int), sites (short).
-inline size_t dt_rows_lds(int W) { return (sizeof(int) * 3 + sizeof(short)) * size_t(W) + 16; }
+#ifndef CAP_DT_CHUNKS
+#define CAP_DT_CHUNKS 32
+#endif
+constexpr int kDtChunks = CAP_DT_CHUNKS; // column chunks of the exact distance transform's row pass
+// Dynamic LDS of the row pass for rows of W pixels: G (int).
+inline size_t dt_rows_lds(int W) { return sizeof(int) * size_t(W) + 16; }
 constexpr int kApplySplitTiles = 1024;   // tile grids above this take the two-pass J^T J p reduction
 constexpr int kGraphCache = 16;          // captured solve graphs kept per context
 constexpr int kSplitThreads = 256;       // PCG split over workgroups for large node counts:

@@ -195,24 +195,26 @@ __global__ void k_dt_cols(const ProbDev *__restrict__ P) {
 }
 
 // Phase 2: per row, D(x) = min over x' of (x - x')^2 + G(x'), G = g^2, exact.
-// The row is cut into kDtChunks column chunks; one thread per chunk builds the
-// lower envelope of the chunk's parabolas (x - x')^2 + G(x') (sequential
-// envelope construction with exact rational breakpoints compared in int64)
-// and the chunk's smallest G.  Every pixel then evaluates its own chunk's
-// envelope by binary search and visits the neighbouring chunks outwards while
-// their column distance can still beat the best value; a chunk whose bound
-// (column distance)^2 + min G cannot beat it is passed over without a search.
-// One workgroup per row, all in LDS.
+// The row's G is staged in LDS and cut into kDtChunks column chunks with their
+// smallest G.  Each pixel takes the minimum over its own chunk's columns
+// (every lane of a wave reads the same G values, so the LDS reads broadcast
+// and none depends on another), then visits the neighbouring chunks outwards
+// while their column distance can still beat the best value, and scans a
+// chunk only if its column distance^2 plus its smallest G can.  Integer
+// arithmetic throughout, so the result is exact.  One workgroup per row.
+#ifndef CAP_DT_UNROLL
+#define CAP_DT_UNROLL 8
+#endif
+constexpr int kDtUnroll = CAP_DT_UNROLL;
+
 __global__ __launch_bounds__(256) void k_dt_rows(const ProbDev *__restrict__ P) {
-    extern __shared__ int sh[];
-    __shared__ int cnt[kDtChunks], cmin[kDtChunks];
+    extern __shared__ int G[];
+    __shared__ int cmin[kDtChunks];
     const ProbDev &pr = P[blockIdx.y];
     const int W = pr.W, H = pr.H;
     const int y = blockIdx.x;
     if (y >= H) return;
     const int far2 = 1 << 30;
-    int *G = sh, *zn = sh + W, *zd = sh + 2 * W;
-    short *ev = reinterpret_cast<short *>(sh + 3 * W);
     for (int x = threadIdx.x; x < W; x += blockDim.x) {
         const int g = pr.colg[size_t(y) * W + x];
         G[x] = g >= kFar ? far2 : g * g;
@@ -220,57 +222,36 @@ __global__ __launch_bounds__(256) void k_dt_rows(const ProbDev *__restrict__ P) 
     __syncthreads();
     const int cs = (W + kDtChunks - 1) / kDtChunks;
     if (threadIdx.x < kDtChunks) {
-        const int c = threadIdx.x, a = c * cs, b = min(W, a + cs);
-        int k = -1, gmin = far2;
-        for (int q = a; q < b; ++q) {
-            const int gq = G[q];
-            if (gq >= far2) continue;
-            gmin = min(gmin, gq);
-            if (k < 0) {
-                k = 0;
-                ev[a] = short(q);
-                zn[a] = -1;
-                zd[a] = 0;
-                continue;
-            }
-            int num, den;
-            for (;;) {
-                const int v = ev[a + k];
-                num = (gq + q * q) - (G[v] + v * v);
-                den = 2 * (q - v);
-                if (k > 0 && (long long)num * zd[a + k] <= (long long)zn[a + k] * den) { --k; continue; }
-                break;
-            }
-            ++k;
-            ev[a + k] = short(q);
-            zn[a + k] = num;
-            zd[a + k] = den;
-        }
-        cnt[c] = k + 1;
-        cmin[c] = gmin;
+        const int a = threadIdx.x * cs, b = min(W, a + cs);
+        int m = far2;
+        for (int q = a; q < b; ++q) m = min(m, G[q]);
+        cmin[threadIdx.x] = m;
     }
     __syncthreads();
-    auto eval = [&](int c, int x) {
-        const int n = cnt[c];
-        if (n == 0) return far2;
-        const int a = c * cs;
-        int lo = 0, hi = n - 1;   // last envelope piece whose left breakpoint is <= x
-        while (lo < hi) {
-            const int m = (lo + hi + 1) >> 1;
-            if ((long long)zn[a + m] <= (long long)x * zd[a + m]) lo = m; else hi = m - 1;
+    // min over the chunk's columns of (x - q)^2 + G(q); columns without a site
+    // have G = 2^30, so they never beat a site (and the sum stays below 2^31)
+    auto scan = [&](int c, int x, int best) {
+        const int a = c * cs, b = min(W, a + cs);
+        int q = a;
+        for (; q + kDtUnroll <= b; q += kDtUnroll) {      // kDtUnroll independent reads in flight
+            int v[kDtUnroll];
+#pragma unroll
+            for (int u = 0; u < kDtUnroll; ++u) v[u] = (x - q - u) * (x - q - u) + G[q + u];
+#pragma unroll
+            for (int u = 0; u < kDtUnroll; ++u) best = min(best, v[u]);
         }
-        const int v = ev[a + lo];
-        return (x - v) * (x - v) + G[v];
+        for (; q < b; ++q) best = min(best, (x - q) * (x - q) + G[q]);
+        return best;
     };
     for (int x = threadIdx.x; x < W; x += blockDim.x) {
         const int c0 = x / cs;
-        int best = eval(c0, x);
+        int best = scan(c0, x, far2);
         int l = c0 - 1, r = c0 + 1;
         while (l >= 0 || r < kDtChunks) {
             if (l >= 0) {
                 const int d = x - (min(W, l * cs + cs) - 1);
                 if (d * d < best) {
-                    if (d * d + cmin[l] < best) { const int e = eval(l, x); best = e < best ? e : best; }
+                    if (d * d + cmin[l] < best) best = scan(l, x, best);
                     --l;
                 } else {
                     l = -1;
@@ -279,7 +260,7 @@ __global__ __launch_bounds__(256) void k_dt_rows(const ProbDev *__restrict__ P) 
             if (r < kDtChunks) {
                 const int d = r * cs - x;
                 if (r * cs < W && d * d < best) {
-                    if (d * d + cmin[r] < best) { const int e = eval(r, x); best = e < best ? e : best; }
+                    if (d * d + cmin[r] < best) best = scan(r, x, best);
                     ++r;
                 } else {
                     r = kDtChunks;
