@@ -71,17 +71,23 @@ __global__ __launch_bounds__(256) void k_gemm(Gemm g) {
 // once); all intermediates (Xb, z1, cat1, z2, cat2, y) stay for the backward.
 constexpr int kLayerThreads = 512;
 
-// One 16x16 output tile: all of the lane's weight fragments are loaded first
-// (one round of latency), then the MFMA chain runs over k from LDS.
+// One 16x16 output tile of a layer: the lane's weight fragments (output
+// column jb, all of k) are loaded into registers at the start of the kernel,
+// before the input tile is formed, so that round of latency overlaps the
+// gathers; the MFMA chain then runs over k from LDS.
 template <int K>
-__device__ inline f4v tile_mfma(const uint16_t (*As)[K + 8], const uint16_t *__restrict__ W, int jb, int N) {
-    const int lane = threadIdx.x & 63, r = lane & 15, kq = (lane >> 4) * 4;
-    s4v bw[K / 16];
+__device__ inline void load_wfrag(const uint16_t *__restrict__ W, int jb, int N, s4v (&bw)[K / 16]) {
+    const int kq = ((threadIdx.x & 63) >> 4) * 4;
     const uint16_t *wrow = W + size_t(jb < N ? jb : 0) * K + kq;
 #pragma unroll
     for (int s = 0; s < K / 16; ++s)
 #pragma unroll
         for (int q = 0; q < 4; ++q) bw[s][q] = jb < N ? short(wrow[16 * s + q]) : short(0);
+}
+
+template <int K>
+__device__ inline f4v tile_mfma(const uint16_t (*As)[K + 8], const s4v (&bw)[K / 16]) {
+    const int lane = threadIdx.x & 63, r = lane & 15, kq = (lane >> 4) * 4;
     f4v acc = {0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
     for (int s = 0; s < K / 16; ++s) {
@@ -98,8 +104,12 @@ __global__ __launch_bounds__(kLayerThreads) void k_ws_layer1(const float *__rest
                                                              const uint16_t *__restrict__ W,
                                                              const float *__restrict__ bias, uint16_t *__restrict__ Xb,
                                                              float *__restrict__ z, uint16_t *__restrict__ cat) {
+    static_assert(kLayerThreads / 64 == 8, "one output tile per wave");
     __shared__ uint16_t As[16][32 + 8];
     const int i0 = blockIdx.x * 16;
+    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63, r = lane & 15;
+    s4v bw[2];
+    load_wfrag<32>(W, wv * 16 + r, 128, bw);
     for (int idx = threadIdx.x; idx < 16 * 32; idx += blockDim.x) {
         const int r = idx >> 5, k = idx & 31, i = i0 + r;
         uint16_t b = 0;
@@ -110,9 +120,9 @@ __global__ __launch_bounds__(kLayerThreads) void k_ws_layer1(const float *__rest
         As[r][k] = b;
     }
     __syncthreads();
-    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63, r = lane & 15;
-    for (int t = wv; t < 8; t += kLayerThreads / 64) {
-        const f4v acc = tile_mfma<32>(As, W, t * 16 + r, 128);
+    {
+        const int t = wv;
+        const f4v acc = tile_mfma<32>(As, bw);
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             const int i = i0 + (lane >> 4) * 4 + q, j = t * 16 + r;
@@ -139,47 +149,54 @@ __global__ __launch_bounds__(kLayerThreads) void k_ws_layer_mp(uint16_t *__restr
                                                                const float *__restrict__ bias, int N,
                                                                float *__restrict__ z, uint16_t *__restrict__ cat_next,
                                                                float *__restrict__ xdelta) {
+    static_assert(NT <= kLayerThreads / 64, "at most one output tile per wave");
     __shared__ uint16_t As[16][256 + 8];
     __shared__ int nbs[16][8];
     const int i0 = blockIdx.x * 16;
+    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63, r = lane & 15;
+    s4v bw[16];
+    if (wv < NT) load_wfrag<256>(W, wv * 16 + r, N, bw);
     if (threadIdx.x < 128) {
         const int r = threadIdx.x >> 3, e = threadIdx.x & 7, i = i0 + r;
         nbs[r][e] = i < nn ? edge_dst[e * nn + i] : -1;
     }
     __syncthreads();
+    // the input tile: ReLU(z_prev) copied (2048 values) and the neighbour means
+    // (2048 values of 8 loads each), kFill of each per thread, every load of
+    // the thread issued before any sum
+    constexpr int kFill = 16 * 128 / kLayerThreads;
+    uint16_t own[kFill];
+    float v[kFill][8];
 #pragma unroll
-    for (int idx = threadIdx.x; idx < 16 * 256; idx += kLayerThreads) {
-        const int r = idx >> 8, k = idx & 255, i = i0 + r;
-        uint16_t b = 0;
-        if (i < nn) {
-            if (k < 128) {
-                b = cat[size_t(i) * 256 + k];
-            } else {
-                const int f = k - 128;
-                float v[8];
+    for (int m = 0; m < kFill; ++m) {
+        const int idx = threadIdx.x + kLayerThreads * m, rr = idx >> 7, f = idx & 127, i = i0 + rr;
+        own[m] = i < nn ? cat[size_t(i) * 256 + f] : uint16_t(0);
 #pragma unroll
-                for (int e = 0; e < 8; ++e) {         // all eight loads issued together (safe index when absent)
-                    const int l = nbs[r][e];
-                    v[e] = zp[size_t(l >= 0 ? l : 0) * 128 + f];
-                }
-                float s = 0.0f;
-                int cnt = 0;
-#pragma unroll
-                for (int e = 0; e < 8; ++e)
-                    if (nbs[r][e] >= 0) {
-                        s += v[e] > 0.0f ? v[e] : 0.0f;
-                        ++cnt;
-                    }
-                b = f2bf(cnt ? s / float(cnt) : 0.0f);
-                cat[size_t(i) * 256 + k] = b;
-            }
+        for (int e = 0; e < 8; ++e) {         // safe index when the edge is absent
+            const int l = nbs[rr][e];
+            v[m][e] = i < nn ? zp[size_t(l >= 0 ? l : 0) * 128 + f] : 0.0f;
         }
-        As[r][k] = b;
+    }
+#pragma unroll
+    for (int m = 0; m < kFill; ++m) {
+        const int idx = threadIdx.x + kLayerThreads * m, rr = idx >> 7, f = idx & 127, i = i0 + rr;
+        float sum = 0.0f;
+        int cnt = 0;
+#pragma unroll
+        for (int e = 0; e < 8; ++e)
+            if (nbs[rr][e] >= 0) {
+                sum += v[m][e] > 0.0f ? v[m][e] : 0.0f;
+                ++cnt;
+            }
+        const uint16_t b = i < nn ? f2bf(cnt ? sum / float(cnt) : 0.0f) : uint16_t(0);
+        if (i < nn) cat[size_t(i) * 256 + 128 + f] = b;
+        As[rr][f] = own[m];
+        As[rr][128 + f] = b;
     }
     __syncthreads();
-    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63, r = lane & 15;
-    for (int t = wv; t < NT; t += kLayerThreads / 64) {
-        const f4v acc = tile_mfma<256>(As, W, t * 16 + r, N);
+    if (wv < NT) {
+        const int t = wv;
+        const f4v acc = tile_mfma<256>(As, bw);
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             const int i = i0 + (lane >> 4) * 4 + q, j = t * 16 + r;
@@ -289,14 +306,12 @@ __global__ __launch_bounds__(256) void k_ws_features(const ProbDev *__restrict__
     const ProbDev &pr = P[blockIdx.y];
     const TemplateDev &T = pr.T;
     const CAP_GLOBAL float *__restrict__ prev2 = pr.prev2.g();
-    const int nn = T.nn, nv = T.nv;
+    const int nn = T.nn;
     // mean node position: strided partial sums, then a fixed-order tree over the block
     {
         float s[3] = {0.0f, 0.0f, 0.0f};
-        for (int k = threadIdx.x; k < nn; k += blockDim.x) {
-            const int gv = T.node_vertex[k];
-            for (int a = 0; a < 3; ++a) s[a] += pr.xyz[size_t(a) * nv + gv];
-        }
+        for (int k = threadIdx.x; k < nn; k += blockDim.x)      // node positions (set up per frame)
+            for (int a = 0; a < 3; ++a) s[a] += pr.gpos[size_t(a) * nn + k];
         for (int a = 0; a < 3; ++a) part[a][threadIdx.x] = s[a];
         __syncthreads();
         for (int h = blockDim.x / 2; h > 0; h >>= 1) {
@@ -335,8 +350,7 @@ __global__ __launch_bounds__(256) void k_ws_features(const ProbDev *__restrict__
             x[12 + c] = copysignf(log1pf(fabsf(b)), b);
             x[18 + c] = log1pf(fmaxf(d, 0.0f));
         }
-        const int gv = T.node_vertex[k];
-        for (int a = 0; a < 3; ++a) x[24 + a] = pr.xyz[size_t(a) * nv + gv] - mean[a];
+        for (int a = 0; a < 3; ++a) x[24 + a] = pr.gpos[size_t(a) * nn + k] - mean[a];
         for (int a = 27; a < 32; ++a) x[a] = 0.0f;
     }
 }
