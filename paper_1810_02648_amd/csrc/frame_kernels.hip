@@ -282,11 +282,12 @@ __global__ void k_deform_start(const ProbDev *__restrict__ P) {
     if (i >= nv) return;
     float v[3] = {pr.xyz[i], pr.xyz[nv + i], pr.xyz[2 * nv + i]};
     float acc[3] = {0.0f, 0.0f, 0.0f};
+#pragma unroll
     for (int j = 0; j < 4; ++j) {
         int k = T.bind_idx[size_t(j) * nv + i];
         float w = T.bind_w[size_t(j) * nv + i];
-        int gv = T.node_vertex[k];
-        float g[3] = {pr.xyz[gv], pr.xyz[nv + gv], pr.xyz[2 * nv + gv]};
+        // the node's position: the frame's mesh at the node vertex (set up per frame)
+        float g[3] = {pr.gpos[k], pr.gpos[nn + k], pr.gpos[2 * size_t(nn) + k]};
         float d[3] = {v[0] - g[0], v[1] - g[1], v[2] - g[2]};
         for (int a = 0; a < 3; ++a) {
             const CAP_GLOBAL float *R = pr.state.g() + size_t(3 * a) * nn + k;

@@ -211,7 +211,7 @@ int launch_pose_step(PoseRun &P, int gn, int mode) {
             hipLaunchKernelGGL(k_pose_jtj, dim3(P.ntp), dim3(256), 0, s, P.dpose);
         });
     timed(R, K_POSE_STEP, [&] {
-        hipLaunchKernelGGL(k_pose_step, dim3(1), dim3(64), 0, s, P.dpose, gn, P.row_blocks, mode);
+        hipLaunchKernelGGL(k_pose_step, dim3(1), dim3(1024), 0, s, P.dpose, gn, P.row_blocks, mode);
     });
     CAP_HIP(hipGetLastError());
     return CAPTURE_OK;

@@ -21,9 +21,10 @@ constexpr int kExpTerms = 24;
 
 __device__ inline double exp_series(double x, int first) {
     double s = 1.0;
+#pragma unroll
     for (int n = kExpTerms; n >= 1; --n) {
         const int k = first + 2 * (n - 1);
-        s = 1.0 - (x / double(k * (k + 1))) * s;
+        s = 1.0 - (x * (1.0 / double(k * (k + 1)))) * s;    // a reciprocal per term (a constant once unrolled)
     }
     return s;
 }
@@ -58,7 +59,20 @@ __device__ inline void mat3(const double *A, const double *B, double *C) {
 // LDS (sR, sp, sA: [nj][9], [nj][3], [nj][9]).
 __device__ __forceinline__ void fk_block(const BodyDev &B, const double *pose, double *sR, double *sp, double *sA, double *sL,
                          double *sJ) {
-    const int nj = B.nj, t = threadIdx.x;
+    const int nj = B.nj, t = threadIdx.x, maxdepth = B.maxdepth;
+    // this joint's tables in registers up front (one round of loads), so the
+    // depth sweep below touches only LDS
+    int depth = -1, par = -1;
+    double off[3] = {0.0, 0.0, 0.0}, root[3] = {0.0, 0.0, 0.0};
+    if (t < nj) {
+        depth = B.depth[t];
+        par = B.parent[t];
+        for (int a = 0; a < 3; ++a) {
+            const double rt = B.rest[a][t];
+            off[a] = par >= 0 ? rt - B.rest[a][par] : 0.0;
+            root[a] = par < 0 ? rt + pose[B.it + a] : 0.0;
+        }
+    }
     if (t < nj) {
         const int c = B.col[t];
         if (c >= 0) {
@@ -73,20 +87,17 @@ __device__ __forceinline__ void fk_block(const BodyDev &B, const double *pose, d
         }
     }
     __syncthreads();
-    for (int d = 0; d <= B.maxdepth; ++d) {
-        if (t < nj && B.depth[t] == d) {
-            const int par = B.parent[t];
+    for (int d = 0; d <= maxdepth; ++d) {
+        if (depth == d) {
             if (par < 0) {
                 for (int e = 0; e < 9; ++e) {
                     sR[9 * t + e] = sL[9 * t + e];
                     sA[9 * t + e] = sJ[9 * t + e];
                 }
-                for (int a = 0; a < 3; ++a) sp[3 * t + a] = B.rest[a][t] + pose[B.it + a];
+                for (int a = 0; a < 3; ++a) sp[3 * t + a] = root[a];
             } else {
                 mat3(sR + 9 * par, sL + 9 * t, sR + 9 * t);
                 mat3(sR + 9 * par, sJ + 9 * t, sA + 9 * t);
-                double off[3];
-                for (int a = 0; a < 3; ++a) off[a] = B.rest[a][t] - B.rest[a][par];
                 const double *Rp = sR + 9 * par;
                 for (int a = 0; a < 3; ++a)
                     sp[3 * t + a] = sp[3 * par + a] + ((Rp[3 * a] * off[0] + Rp[3 * a + 1] * off[1]) + Rp[3 * a + 2] * off[2]);
@@ -406,36 +417,41 @@ __global__ __launch_bounds__(64 * kJtjWaves) void k_pose_jtj(const PoseDev *__re
     }
 }
 
-// One wave.  mode 0: energy of the step, damping, Cholesky A = U^T U (upper
-// factor, row-major in LDS), the two triangular solves with the unknowns in
-// registers, update, kinematics at the new pose.  mode 1: energy only (final).
-// mode 2: energy only (the system is already in place for the caller).
-__global__ __launch_bounds__(64) void k_pose_step(const PoseDev *__restrict__ PP, int gn, int nblk, int mode) {
+// One workgroup of kStepThreads.  mode 0: energy of the step, damping,
+// elimination of the augmented system [A + mu I | -J^T B F] without pivoting
+// (A = L D L^T with the right-hand side carried along: a right-looking update
+// of the trailing upper triangle, one barrier per pivot, every pivot tested
+// for positivity, which holds exactly for a positive definite system), back
+// substitution in one wave with the unknowns in registers (reciprocal pivots
+// from the elimination), update, kinematics
+// at the new pose.  mode 1: energy only (final).  mode 2: energy only (the
+// system is already in place for the caller).
+constexpr int kStepThreads = 1024;
+
+__global__ __launch_bounds__(kStepThreads) void k_pose_step(const PoseDev *__restrict__ PP, int gn, int nblk, int mode) {
     const PoseDev &P = *PP;
     const BodyDev &B = P.B;
     const int nu = B.nu, lda = nu + 1;
     const int t = threadIdx.x;
     __shared__ double A[kMaxPoseUnknowns * (kMaxPoseUnknowns + 1)];
     __shared__ double pn[kMaxPoseUnknowns];
-    __shared__ double ep[64];
-    __shared__ double sR[9 * kMaxJoints], sp[3 * kMaxJoints], sA[9 * kMaxJoints], sL[9 * kMaxJoints],
-        sJ[9 * kMaxJoints];
+    __shared__ double ep[64 * 4];
+    __shared__ double red[kStepThreads / 64];
     __shared__ int bad;
-    // energies of the rows kernel's blocks, summed in block order
+    // energies of the rows kernel's blocks (4 terms each), summed in block
+    // order by four threads, 64 blocks' partials per round of loads
     if (t == 0) bad = 0;
-    for (int q = 0; q < 4; ++q) {
-        double s = 0.0;
-        for (int b0 = 0; b0 < nblk; b0 += 64) {
-            __syncthreads();
-            ep[t] = b0 + t < nblk ? P.epart[size_t(b0 + t) * 4 + q] : 0.0;
-            __syncthreads();
-            if (t == 0)
-                for (int b = 0; b < 64 && b0 + b < nblk; ++b) s += ep[b];
-        }
-        if (t == 0) {
-            P.energy[gn * 4 + q] = s;
-            if (!isfinite(s)) bad = 1;
-        }
+    double es = 0.0;
+    for (int b0 = 0; b0 < nblk; b0 += 64) {
+        __syncthreads();
+        if (t < 256) ep[t] = b0 + (t >> 2) < nblk ? P.epart[size_t(b0) * 4 + t] : 0.0;
+        __syncthreads();
+        if (t < 4)
+            for (int b = 0; b < 64 && b0 + b < nblk; ++b) es += ep[b * 4 + t];
+    }
+    if (t < 4) {
+        P.energy[gn * 4 + t] = es;
+        if (!isfinite(es)) bad = 1;
     }
     __syncthreads();
     if (bad) {
@@ -445,103 +461,100 @@ __global__ __launch_bounds__(64) void k_pose_step(const PoseDev *__restrict__ PP
     if (mode != 0 || P.status[0] != 0) return;
     {   // the system into LDS, eight independent loads in flight per lane
         const int tot = nu * lda;
-        for (int e0 = t; e0 < tot; e0 += 64 * 8) {
+        for (int e0 = t; e0 < tot; e0 += kStepThreads * 8) {
             double v[8];
 #pragma unroll
-            for (int u = 0; u < 8; ++u) v[u] = e0 + 64 * u < tot ? P.sys[e0 + 64 * u] : 0.0;
+            for (int u = 0; u < 8; ++u) v[u] = e0 + kStepThreads * u < tot ? P.sys[e0 + kStepThreads * u] : 0.0;
 #pragma unroll
             for (int u = 0; u < 8; ++u)
-                if (e0 + 64 * u < tot) A[e0 + 64 * u] = v[u];
+                if (e0 + kStepThreads * u < tot) A[e0 + kStepThreads * u] = v[u];
         }
     }
     __syncthreads();
-    double m = 0.0;
-    for (int i = t; i < nu; i += 64) m = fmax(m, A[i * lda + i]);
-    for (int o = 32; o > 0; o >>= 1) m = fmax(m, __shfl_xor(m, o));
-    const double mu = 1e-6 * m;
-    for (int i = t; i < nu; i += 64) A[i * lda + i] += mu;
-    __syncthreads();
-    // A = U^T U row by row: U[i][j] = (A[i][j] - sum_{k<i} U[k][i] U[k][j]) / U[i][i]
-    // for lanes j = i + t, i + t + 64.  The sums only read LDS (U[k][i] is a
-    // broadcast, U[k][j] contiguous over the lanes), so they pipeline.
-    for (int i = 0; i < nu; ++i) {
-        double s[2];
-#pragma unroll
-        for (int h = 0; h < 2; ++h) {
-            const int j = i + t + 64 * h;
-            if (j < nu) {
-                double acc[4] = {0.0, 0.0, 0.0, 0.0};
-                int k = 0;
-                for (; k + 8 <= i; k += 8) {       // eight pairs of loads in flight, then the products
-                    double ui[8], uj[8];
-#pragma unroll
-                    for (int u = 0; u < 8; ++u) {
-                        ui[u] = A[(k + u) * lda + i];
-                        uj[u] = A[(k + u) * lda + j];
-                    }
-#pragma unroll
-                    for (int u = 0; u < 8; ++u) acc[u & 3] += ui[u] * uj[u];
-                }
-                for (; k < i; ++k) acc[0] += A[k * lda + i] * A[k * lda + j];
-                s[h] = A[i * lda + j] - ((acc[0] + acc[1]) + (acc[2] + acc[3]));
-            } else {
-                s[h] = 0.0;
-            }
-        }
-        const double d = __shfl(s[0], 0);          // the diagonal, held by lane 0
-        if (!(d > 0.0) || !isfinite(d)) {
+    {   // damping mu = 1e-6 max diag
+        double m = 0.0;
+        for (int i = t; i < nu; i += kStepThreads) m = fmax(m, A[i * lda + i]);
+        for (int o = 32; o > 0; o >>= 1) m = fmax(m, __shfl_xor(m, o));
+        if ((t & 63) == 0) red[t >> 6] = m;
+        __syncthreads();
+        double mx = red[0];
+        for (int w = 1; w < kStepThreads / 64; ++w) mx = fmax(mx, red[w]);
+        if (t < nu) A[t * lda + t] += 1e-6 * mx;
+        __syncthreads();
+    }
+    // elimination: for pivot k, rows i > k of the upper triangle and the
+    // right-hand side column: A[i][j] -= (A[k][i] / A[k][k]) A[k][j], j >= i
+    // (thread t owns column k + 1 + (t % 128) of every kRowGroups-th trailing row)
+    constexpr int kRowGroups = kStepThreads / 128, kRowsPer = (kMaxPoseUnknowns + kRowGroups - 1) / kRowGroups;
+    const int tc = t & 127, tr = t >> 7;
+    for (int k = 0; k < nu; ++k) {
+        const double akk = A[k * lda + k];
+        if (!(akk > 0.0) || !isfinite(akk)) {      // every thread reads the same pivot
             if (t == 0) bad = 1;
             break;
         }
-        const double uii = sqrt(d);
-        __syncthreads();
+        const double inv = 1.0 / akk;
+        if (t == 0) pn[k] = inv;                  // reciprocal pivots for the back substitution
+        const int j = k + 1 + tc;
+        if (j <= nu) {
+            const double akj = A[k * lda + j];
+            const int iend = min(j, nu - 1);
+            // all of the thread's rows at once: their loads in flight together, then the stores
+            double aki[kRowsPer], aij[kRowsPer];
 #pragma unroll
-        for (int h = 0; h < 2; ++h) {
-            const int j = i + t + 64 * h;
-            if (j < nu) A[i * lda + j] = j == i ? uii : s[h] / uii;
+            for (int u = 0; u < kRowsPer; ++u) {
+                const int i = k + 1 + tr + u * kRowGroups;
+                aki[u] = i <= iend ? A[k * lda + i] : 0.0;
+                aij[u] = i <= iend ? A[i * lda + j] : 0.0;
+            }
+#pragma unroll
+            for (int u = 0; u < kRowsPer; ++u) {
+                const int i = k + 1 + tr + u * kRowGroups;
+                if (i <= iend) A[i * lda + j] = aij[u] - (aki[u] * inv) * akj;
+            }
         }
         __syncthreads();
     }
     __syncthreads();
     if (bad) {
-        for (int e = t; e < nu; e += 64) P.pose[e] = P.pose0[e];
+        for (int e = t; e < nu; e += kStepThreads) P.pose[e] = P.pose0[e];
         if (t == 0) P.status[0] = CAPTURE_ENOTSPD;
         return;
     }
-    // U^T y = rhs, then U delta = y; component e lives in lane e % 64 (slot e / 64)
-    // and each step's dot product is a fixed butterfly over the wave
-    double y0 = 0.0, y1 = 0.0;
-    for (int i = 0; i < nu; ++i) {
-        double part = 0.0;
-        if (t < i) part += A[t * lda + i] * y0;
-        if (t + 64 < i) part += A[(t + 64) * lda + i] * y1;
-        for (int o = 32; o > 0; o >>= 1) part += __shfl_xor(part, o);
-        const double yi = (A[i * lda + nu] - part) / A[i * lda + i];
-        if ((i & 63) == t) {
-            if (i < 64) y0 = yi; else y1 = yi;
+    // back substitution D L^T delta = z in the first wave: component e lives in
+    // lane e % 64 (slot e / 64); after delta_i is known it is taken out of the
+    // right-hand sides of the rows above
+    double d0s[2] = {0.0, 0.0};
+    if (t < 64) {
+        double b0 = t < nu ? A[t * lda + nu] : 0.0, b1 = t + 64 < nu ? A[(t + 64) * lda + nu] : 0.0;
+        double d0 = 0.0, d1 = 0.0;
+        for (int i = nu - 1; i >= 0; --i) {
+            const double bi = __shfl(i < 64 ? b0 : b1, i & 63);
+            const double di = bi * pn[i];
+            if ((i & 63) == t) {
+                if (i < 64) d0 = di; else d1 = di;
+            }
+            if (t < i) b0 -= A[t * lda + i] * di;
+            if (t + 64 < i) b1 -= A[(t + 64) * lda + i] * di;
         }
+        d0s[0] = d0;
+        d0s[1] = d1;
     }
-    double d0 = 0.0, d1 = 0.0;
-    for (int i = nu - 1; i >= 0; --i) {
-        double part = 0.0;
-        if (t > i && t < nu) part += A[i * lda + t] * d0;
-        if (t + 64 > i && t + 64 < nu) part += A[i * lda + t + 64] * d1;
-        for (int o = 32; o > 0; o >>= 1) part += __shfl_xor(part, o);
-        const double yi = __shfl(i < 64 ? y0 : y1, i & 63);
-        const double di = (yi - part) / A[i * lda + i];
-        if ((i & 63) == t) {
-            if (i < 64) d0 = di; else d1 = di;
+    __syncthreads();      // the reciprocal pivots in pn are no longer needed
+    if (t < 64) {
+        if (t < nu) {
+            pn[t] = P.pose[t] + d0s[0];
+            P.pose[t] = pn[t];
         }
-    }
-    if (t < nu) {
-        pn[t] = P.pose[t] + d0;
-        P.pose[t] = pn[t];
-    }
-    if (t + 64 < nu) {
-        pn[t + 64] = P.pose[t + 64] + d1;
-        P.pose[t + 64] = pn[t + 64];
+        if (t + 64 < nu) {
+            pn[t + 64] = P.pose[t + 64] + d0s[1];
+            P.pose[t + 64] = pn[t + 64];
+        }
     }
     __syncthreads();
+    // kinematics at the new pose; its joint tables reuse the system's LDS
+    double *sR = A, *sp = sR + 9 * kMaxJoints, *sA = sp + 3 * kMaxJoints, *sL = sA + 9 * kMaxJoints,
+           *sJ = sL + 9 * kMaxJoints;
     fk_block(B, pn, sR, sp, sA, sL, sJ);
     fk_store(P, sR, sp, sA);
 }
