@@ -40,7 +40,15 @@ __device__ inline int xcd_item(int b, int grid) { return (b & 7) * (grid >> 3) +
 // [lbeg[s], lbeg[s + 1]), in a fixed order.
 __device__ inline float run_sum(const float *__restrict__ c, int b, int e) {
     float acc = 0.0f;
-    for (int q = b; q < e; ++q) acc += c[q];
+    int q = b;
+    for (; q + 8 <= e; q += 8) {       // eight LDS reads in flight, then the adds in order
+        float v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v[u] = c[q + u];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) acc += v[u];
+    }
+    for (; q < e; ++q) acc += c[q];
     return acc;
 }
 
