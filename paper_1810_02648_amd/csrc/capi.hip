@@ -336,9 +336,9 @@ int setup(Run &R, capture_ctx *ctx, int n, const capture_frame *frames, const ca
         R.max_h = std::max(R.max_h, pr.H);
         // contribution buffers: components at an odd stride (max_contrib | 1)
         R.lds_lin = std::max(R.lds_lin, sizeof(float) * (size_t(T.max_slots) * 15 + size_t(T.max_contrib | 1) * 12));
-        R.lds_apply = std::max(R.lds_apply, sizeof(float) * (size_t(T.max_slots) * 18 + size_t(T.max_contrib | 1) * 6));
+        R.lds_apply = std::max(R.lds_apply, sizeof(float) * (size_t(T.max_slots) * 20 + size_t(T.max_contrib | 1) * 6));
         R.lds_apply_split =
-            std::max(R.lds_apply_split, sizeof(float) * (size_t(T.max_slots) * 18 + size_t(T.max_contrib | 1) * 3));
+            std::max(R.lds_apply_split, sizeof(float) * (size_t(T.max_slots) * 20 + size_t(T.max_contrib | 1) * 3));
     }
     // sized once for both the descriptors and the report read-back of `collect`
     R.grid_tiles = grid_tiles(n, frames);

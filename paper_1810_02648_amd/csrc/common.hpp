@@ -41,7 +41,10 @@ constexpr int kScanColsMin = 16384;      // image columns (all frames) from whic
 constexpr int kDtChunks = CAP_DT_CHUNKS; // column chunks of the exact distance transform's row pass
 // Dynamic LDS of the row pass for rows of W pixels: G (int).
 inline size_t dt_rows_lds(int W) { return sizeof(int) * size_t(W) + 16; }
-constexpr int kApplySplitTiles = 1024;   // tile grids above this take the two-pass J^T J p reduction
+#ifndef CAP_APPLY_SPLIT_TILES
+#define CAP_APPLY_SPLIT_TILES 1024
+#endif
+constexpr int kApplySplitTiles = CAP_APPLY_SPLIT_TILES;   // tile grids above this take the two-pass J^T J p reduction
 constexpr int kGraphCache = 16;          // captured solve graphs kept per context
 constexpr int kSplitThreads = 256;       // PCG split over workgroups for large node counts:
 constexpr int kSplitItems = 1024;        //   (component, node) items per workgroup

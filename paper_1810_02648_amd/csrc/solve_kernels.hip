@@ -52,6 +52,17 @@ __device__ inline float run_sum(const float *__restrict__ c, int b, int e) {
     return acc;
 }
 
+// A slot's node in the product kernel's LDS: five float4 (R row-major, the
+// node position, p; two floats of padding), read with 16-byte loads.
+constexpr int kSlotRec = 20;
+
+__device__ inline void slot_rec(const float4 *S, int sl, float R[9], float g[3], float p[6]) {
+    const float4 a = S[5 * sl], b = S[5 * sl + 1], c = S[5 * sl + 2], d = S[5 * sl + 3], e = S[5 * sl + 4];
+    R[0] = a.x; R[1] = a.y; R[2] = a.z; R[3] = a.w; R[4] = b.x; R[5] = b.y; R[6] = b.z; R[7] = b.w; R[8] = c.x;
+    g[0] = c.y; g[1] = c.z; g[2] = c.w;
+    p[0] = d.x; p[1] = d.y; p[2] = d.z; p[3] = d.w; p[4] = e.x; p[5] = e.y;
+}
+
 __device__ inline void rot_apply(const float *R, const float d[3], float q[3]) {
     q[0] = (R[0] * d[0] + R[1] * d[1]) + R[2] * d[2];
     q[1] = (R[3] * d[0] + R[4] * d[1]) + R[5] * d[2];
@@ -347,23 +358,21 @@ __global__ __launch_bounds__(kTileThreads) void k_apply(const ProbDev *__restric
 #pragma unroll
         for (int q6 = 0; q6 < 6; ++q6) Hm[q6] = pr.Hm[size_t(q6) * nv + p];
     }
-    // LDS: R [ns][9], g [ns][3], p [ns][6], then contributions [3][NC]
-    // (kSplit) or [6][NC]
-    float *sR = lds, *sg = sR + 9 * ns, *sp = sg + 3 * ns, *C = sp + 6 * ns;
+    // LDS: one 80-byte record per slot (R, node position, p: five float4),
+    // then contributions [3][NC] (kSplit) or [6][NC]
+    float4 *S = reinterpret_cast<float4 *>(lds);
+    float *C = lds + kSlotRec * ns;
     if (has_s) {      // R, position and p of the slot's node
-        float sv[18];
+        float sv[20];
 #pragma unroll
         for (int q = 0; q < 9; ++q) sv[q] = pr.state[size_t(q) * nn + snode];
 #pragma unroll
         for (int q = 0; q < 3; ++q) sv[9 + q] = pr.gpos[size_t(q) * nn + snode];
 #pragma unroll
         for (int q = 0; q < 6; ++q) sv[12 + q] = pr.p[size_t(q) * nn + snode];
+        sv[18] = sv[19] = 0.0f;
 #pragma unroll
-        for (int q = 0; q < 9; ++q) sR[9 * lv + q] = sv[q];
-#pragma unroll
-        for (int q = 0; q < 3; ++q) sg[3 * lv + q] = sv[9 + q];
-#pragma unroll
-        for (int q = 0; q < 6; ++q) sp[6 * lv + q] = sv[12 + q];
+        for (int q = 0; q < 5; ++q) S[5 * lv + q] = make_float4(sv[4 * q], sv[4 * q + 1], sv[4 * q + 2], sv[4 * q + 3]);
     }
     __syncthreads();
     const int NC = lbeg[ns] | 1;     // odd component stride: components in different LDS banks
@@ -381,10 +390,10 @@ __global__ __launch_bounds__(kTileThreads) void k_apply(const ProbDev *__restric
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
                 const int sl = (packed >> (8 * j)) & 0xff;
-                const float *g = sg + 3 * sl;
+                float R[9], g[3], pp[6];
+                slot_rec(S, sl, R, g, pp);
                 float dd[3] = {v[0] - g[0], v[1] - g[1], v[2] - g[2]};
-                rot_apply(sR + 9 * sl, dd, q[j]);
-                const float *pp = sp + 6 * sl;
+                rot_apply(R, dd, q[j]);
                 float oxq[3];
                 cross3(pp, q[j], oxq);
 #pragma unroll
@@ -411,10 +420,11 @@ __global__ __launch_bounds__(kTileThreads) void k_apply(const ProbDev *__restric
     const float wa = pr.w_arap;
     // regulariser edge k -> l: u = w_k x e_kl + tau_k - tau_l; rotational part e x u
     auto edge_u = [&](int so, int se, float ekl[3], float u[3]) {
-        const float *gk = sg + 3 * so, *gl = sg + 3 * se;
+        float Rk[9], gk[3], pk[6], Rl[9], gl[3], pl[6];
+        slot_rec(S, so, Rk, gk, pk);
+        slot_rec(S, se, Rl, gl, pl);
         float dd[3] = {gl[0] - gk[0], gl[1] - gk[1], gl[2] - gk[2]};
-        rot_apply(sR + 9 * so, dd, ekl);
-        const float *pk = sp + 6 * so, *pl = sp + 6 * se;
+        rot_apply(Rk, dd, ekl);
         float oxe[3];
         cross3(pk, ekl, oxe);
         u[0] = (oxe[0] + pk[3]) - pl[3]; u[1] = (oxe[1] + pk[4]) - pl[4]; u[2] = (oxe[2] + pk[5]) - pl[5];
