@@ -148,7 +148,7 @@ struct ProbDev {
     gptr<float> pva;       // [3][nv] velocity anchor: start positions (float32 recipe)
     gptr<float> Hm;        // [6][nv]
     // tiles / slots
-    gptr<float> partial;   // [nslots][12], node-major positions (node_pbeg ranges)
+    gptr<float> partial;   // [12][nslots] component-major; positions node-major (node_pbeg ranges)
     gptr<float> gpos;      // [3][nn] node positions (the frame's input mesh at the node vertices)
     gptr<double> tile_e;   // [ntiles][kTerms]
     // nodes

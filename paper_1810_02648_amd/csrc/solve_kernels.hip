@@ -290,7 +290,7 @@ __global__ __launch_bounds__(kTileThreads) void k_linearize(const ProbDev *__res
     if (full) {
         for (int pair = threadIdx.x; pair < ns * 12; pair += blockDim.x) {
             const int s = pair / 12, comp = pair - s * 12;
-            pr.partial[size_t(ldest[s]) * 12 + comp] = run_sum(L.c + comp * NC, lbeg[s], lbeg[s + 1]);
+            pr.partial[size_t(comp) * T.nslots + ldest[s]] = run_sum(L.c + comp * NC, lbeg[s], lbeg[s + 1]);
         }
     }
     double es[kTerms] = {e_ph, e_s, e_sa, e_a, e_v};
@@ -448,7 +448,7 @@ __global__ __launch_bounds__(kTileThreads) void k_apply(const ProbDev *__restric
         __syncthreads();
         for (int pair = lv; pair < ns * 3; pair += kTileThreads) {
             const int s = pair / 3, comp = pair - s * 3;
-            pr.partial[size_t(ldest[s]) * 6 + comp] = run_sum(C + comp * NC, lbeg[s], lbeg[s + 1]);
+            pr.partial[size_t(comp) * T.nslots + ldest[s]] = run_sum(C + comp * NC, lbeg[s], lbeg[s + 1]);
         }
         __syncthreads();
     }
@@ -479,7 +479,7 @@ __global__ __launch_bounds__(kTileThreads) void k_apply(const ProbDev *__restric
     constexpr int kComps = kSplit ? 3 : 6;
     for (int pair = lv; pair < ns * kComps; pair += kTileThreads) {
         const int s = pair / kComps, comp = pair - s * kComps;
-        pr.partial[size_t(ldest[s]) * 6 + (kSplit ? 3 : 0) + comp] = run_sum(C + comp * NC, lbeg[s], lbeg[s + 1]);
+        pr.partial[size_t((kSplit ? 3 : 0) + comp) * T.nslots + ldest[s]] = run_sum(C + comp * NC, lbeg[s], lbeg[s + 1]);
     }
 }
 
@@ -493,8 +493,9 @@ template __global__ void k_apply<1>(const ProbDev *, const TileDesc *);
 constexpr int kItems = 8;   // node kernels: up to kItems * kNodeThreads = 8192 items (1365 nodes) in registers
 constexpr int kInitItems = 16;   // k_node_init (kInitThreads): the same 8192 items, 256 VGPRs per lane
 
-// Sum of a node's tile partials (stride floats per partial), in tile order.
-// Sum of partials [pb, pe) (component c, stride floats apart) in order; the
+// Sum of partials [pb, pe) of component c (components are rows of `stride`
+// floats: the partials are stored component-major, so the parts of
+// neighbouring nodes are neighbours in memory) in order; the
 // first kParts loads are issued together (a node is touched by a handful of
 // tiles), the rest, if any, one after another.
 constexpr int kParts = 8;
@@ -502,12 +503,12 @@ constexpr int kParts = 8;
 __device__ inline float sum_parts(gptr<const float> partial, int stride, int c, int pb, int pe) {
     float v[kParts];
 #pragma unroll
-    for (int u = 0; u < kParts; ++u) v[u] = pb + u < pe ? partial[size_t(pb + u) * stride + c] : 0.0f;
+    for (int u = 0; u < kParts; ++u) v[u] = pb + u < pe ? partial[size_t(c) * stride + pb + u] : 0.0f;
     float a = 0.0f;
 #pragma unroll
     for (int u = 0; u < kParts; ++u)
         if (pb + u < pe) a += v[u];
-    for (int q = pb + kParts; q < pe; ++q) a += partial[size_t(q) * stride + c];
+    for (int q = pb + kParts; q < pe; ++q) a += partial[size_t(c) * stride + q];
     return a;
 }
 
@@ -555,16 +556,16 @@ __global__ __launch_bounds__(kInitThreads) void k_node_init(const ProbDev *__res
 #pragma unroll
                     for (int u = 0; u < kParts; ++u) {
                         const bool in = pb[j] + u < pe[j];
-                        vb[u] = in ? pr.partial[size_t(pb[j] + u) * 12 + c] : 0.0f;
-                        vd[u] = in ? pr.partial[size_t(pb[j] + u) * 12 + 6 + c] : 0.0f;
+                        vb[u] = in ? pr.partial[size_t(c) * T.nslots + pb[j] + u] : 0.0f;
+                        vd[u] = in ? pr.partial[size_t(6 + c) * T.nslots + pb[j] + u] : 0.0f;
                     }
                     float b = 0.0f, d = 0.0f;
 #pragma unroll
                     for (int u = 0; u < kParts; ++u)
                         if (pb[j] + u < pe[j]) { b += vb[u]; d += vd[u]; }
                     for (int q = pb[j] + kParts; q < pe[j]; ++q) {
-                        b += pr.partial[size_t(q) * 12 + c];
-                        d += pr.partial[size_t(q) * 12 + 6 + c];
+                        b += pr.partial[size_t(c) * T.nslots + q];
+                        d += pr.partial[size_t(6 + c) * T.nslots + q];
                     }
                     const float mi = d > 0.0f ? 1.0f / d : 1.0f;
                     const float z = mi * b;
@@ -577,8 +578,8 @@ __global__ __launch_bounds__(kInitThreads) void k_node_init(const ProbDev *__res
         } else {
             for (int i = threadIdx.x; i < n6; i += blockDim.x) {
                 const int c = i / nn, k = i - c * nn;
-                const float b = gather_node(T, pr.partial, 12, k, c);
-                const float d = gather_node(T, pr.partial, 12, k, 6 + c);
+                const float b = gather_node(T, pr.partial, T.nslots, k, c);
+                const float d = gather_node(T, pr.partial, T.nslots, k, 6 + c);
                 const float mi = d > 0.0f ? 1.0f / d : 1.0f;
                 const float z = mi * b;
                 pr.b[i] = b; pr.diag[i] = d; pr.dinv[i] = mi;
@@ -633,7 +634,7 @@ __global__ __launch_bounds__(kNodeThreads) void k_node_gather(const ProbDev *__r
     const int nn = T.nn;
     for (int i = threadIdx.x; i < 6 * nn; i += blockDim.x) {
         const int c = i / nn, k = i - c * nn;
-        pr.Ap[i] = gather_node(T, pr.partial, 6, k, c);
+        pr.Ap[i] = gather_node(T, pr.partial, T.nslots, k, c);
     }
 }
 
@@ -699,7 +700,7 @@ __global__ __launch_bounds__(kNodeThreads) void k_node_pcg(const ProbDev *__rest
 #pragma unroll
             for (int j = 0; j < kItems; ++j) {
                 const int c = (threadIdx.x + j * kNodeThreads) / nn;
-                ap[j] = sum_parts(pr.partial, 6, c, pb[j], pe[j]);
+                ap[j] = sum_parts(pr.partial, T.nslots, c, pb[j], pe[j]);
                 pap += double(pp[j]) * double(ap[j]);
             }
             pap = block_sum<kNodeThreads>(pap, red);
@@ -739,7 +740,7 @@ __global__ __launch_bounds__(kNodeThreads) void k_node_pcg(const ProbDev *__rest
         double pap = 0.0;
         for (int i = threadIdx.x; i < n6; i += kNodeThreads) {
             const int c = i / nn, k = i - c * nn;
-            const float a = gather_node(T, pr.partial, 6, k, c);
+            const float a = gather_node(T, pr.partial, T.nslots, k, c);
             pr.Ap[i] = a;
             pap += double(pr.p[i]) * double(a);
         }
@@ -795,7 +796,7 @@ __global__ __launch_bounds__(kSplitThreads) void k_pcg_split_a(const ProbDev *__
         const int i = blockIdx.x * kSplitItems + u * kSplitThreads + threadIdx.x;
         if (i < n6) {
             const int c = i / nn, k = i - c * nn;
-            const float a = gather_node(T, pr.partial, 6, k, c);
+            const float a = gather_node(T, pr.partial, T.nslots, k, c);
             pr.Ap[i] = a;
             pap += double(pr.p[i]) * double(a);
         }
