@@ -29,7 +29,10 @@ constexpr int kTileThreads = 256;     // threads of a tile workgroup (one vertex
 constexpr int kMaxTileVerts = 256;    // vertices per tile
 constexpr int kMaxTileContrib = 1024; // contributions held in LDS per tile
 constexpr int kMaxTileSlots = 200;    // distinct nodes touched by a tile
-constexpr int kNodeThreads = 1024;    // threads of a per-problem node workgroup
+#ifndef CAP_NODE_THREADS
+#define CAP_NODE_THREADS 1024
+#endif
+constexpr int kNodeThreads = CAP_NODE_THREADS;    // threads of a per-problem node workgroup
 constexpr int kInitThreads = 512;     // threads of the post-linearisation node workgroup (k_node_init)
 constexpr int kMaxImageSide = 4096;
 constexpr int kRasterSmall = 256;         // pixel-box size above which a face is rasterised by a workgroup

@@ -490,7 +490,7 @@ template __global__ void k_apply<1>(const ProbDev *, const TileDesc *);
 // Node kernels: one workgroup per problem.
 // ----------------------------------------------------------------------------
 
-constexpr int kItems = 8;   // node kernels: up to kItems * kNodeThreads = 8192 items (1365 nodes) in registers
+constexpr int kItems = 8192 / kNodeThreads;   // node kernels: 8192 items (1365 nodes) in registers
 constexpr int kInitItems = 16;   // k_node_init (kInitThreads): the same 8192 items, 256 VGPRs per lane
 
 // Sum of partials [pb, pe) of component c (components are rows of `stride`
