@@ -335,7 +335,7 @@ int setup(Run &R, capture_ctx *ctx, int n, const capture_frame *frames, const ca
         R.max_w = std::max(R.max_w, pr.W);
         R.max_h = std::max(R.max_h, pr.H);
         // contribution buffers: components at an odd stride (max_contrib | 1)
-        R.lds_lin = std::max(R.lds_lin, sizeof(float) * (size_t(T.max_slots) * 15 + size_t(T.max_contrib | 1) * 12));
+        R.lds_lin = std::max(R.lds_lin, sizeof(float) * (size_t(T.max_slots) * 16 + size_t(T.max_contrib | 1) * 12));
         R.lds_apply = std::max(R.lds_apply, sizeof(float) * (size_t(T.max_slots) * 20 + size_t(T.max_contrib | 1) * 6));
         R.lds_apply_split =
             std::max(R.lds_apply_split, sizeof(float) * (size_t(T.max_slots) * 20 + size_t(T.max_contrib | 1) * 3));

@@ -8,25 +8,6 @@
 
 namespace cap {
 
-// LDS layout of a tile workgroup.
-struct TileLds {
-    float *R;   // [ns][9]
-    float *t;   // [ns][3]
-    float *g;   // [ns][3]
-    float *p;   // [ns][6]
-    float *c;   // [ncontrib][nc]
-};
-
-__device__ inline TileLds tile_lds(float *base, int ns, int ncomp) {
-    TileLds L;
-    L.R = base;
-    L.t = L.R + 9 * ns;
-    L.g = L.t + 3 * ns;
-    L.p = L.g + 3 * ns;
-    L.c = L.p + (ncomp == 6 ? 6 * ns : 0);
-    return L;
-}
-
 // Work item of a block when consecutive blocks go to the accelerator dies
 // (XCDs) in turn: block b runs on die b % 8, so die x is given the x-th
 // contiguous eighth of the items and neighbouring tiles (which share slot
@@ -61,6 +42,17 @@ __device__ inline void slot_rec(const float4 *S, int sl, float R[9], float g[3],
     R[0] = a.x; R[1] = a.y; R[2] = a.z; R[3] = a.w; R[4] = b.x; R[5] = b.y; R[6] = b.z; R[7] = b.w; R[8] = c.x;
     g[0] = c.y; g[1] = c.z; g[2] = c.w;
     p[0] = d.x; p[1] = d.y; p[2] = d.z; p[3] = d.w; p[4] = e.x; p[5] = e.y;
+}
+
+// A slot's node in the linearisation's LDS: four float4 (R row-major, t, the
+// node position; one float of padding).
+constexpr int kSlotRecLin = 16;
+
+__device__ inline void slot_rec_lin(const float4 *S, int sl, float R[9], float t[3], float g[3]) {
+    const float4 a = S[4 * sl], b = S[4 * sl + 1], c = S[4 * sl + 2], d = S[4 * sl + 3];
+    R[0] = a.x; R[1] = a.y; R[2] = a.z; R[3] = a.w; R[4] = b.x; R[5] = b.y; R[6] = b.z; R[7] = b.w; R[8] = c.x;
+    t[0] = c.y; t[1] = c.z; t[2] = c.w;
+    g[0] = d.x; g[1] = d.y; g[2] = d.z;
 }
 
 __device__ inline void rot_apply(const float *R, const float d[3], float q[3]) {
@@ -133,19 +125,19 @@ __global__ __launch_bounds__(kTileThreads) void k_linearize(const ProbDev *__res
     }
     if (pr.scal[2] != 0.0) return;
     if ((mode & 2) && pr.scal[5] == 0.0) return;      // conditional pass: only after a rejected prediction
-    TileLds L = tile_lds(lds, ns, 12);
+    // LDS: one 64-byte record per slot (R, t, node position: four float4),
+    // then contributions [12][NC]
+    float4 *S = reinterpret_cast<float4 *>(lds);
+    float *Cl = lds + kSlotRecLin * ns;
     if (has_s) {      // R, t and position of the slot's node
-        float sv[15];
+        float sv[16];
 #pragma unroll
         for (int q = 0; q < 12; ++q) sv[q] = pr.state[size_t(q) * nn + snode];
 #pragma unroll
         for (int q = 0; q < 3; ++q) sv[12 + q] = pr.gpos[size_t(q) * nn + snode];
+        sv[15] = 0.0f;
 #pragma unroll
-        for (int q = 0; q < 9; ++q) L.R[9 * lv + q] = sv[q];
-#pragma unroll
-        for (int q = 0; q < 3; ++q) L.t[3 * lv + q] = sv[9 + q];
-#pragma unroll
-        for (int q = 0; q < 3; ++q) L.g[3 * lv + q] = sv[12 + q];
+        for (int q = 0; q < 4; ++q) S[4 * lv + q] = make_float4(sv[4 * q], sv[4 * q + 1], sv[4 * q + 2], sv[4 * q + 3]);
     }
     __syncthreads();
     // component stride of the contribution buffer: odd, so that the twelve
@@ -164,14 +156,14 @@ __global__ __launch_bounds__(kTileThreads) void k_linearize(const ProbDev *__res
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
             sl[j] = (packed >> (8 * j)) & 0xff;
-            const float *g = L.g + 3 * sl[j];
-            const float *Rm = L.R + 9 * sl[j];
+            float Rm[9], tt[3], g[3];
+            slot_rec_lin(S, sl[j], Rm, tt, g);
             const double dd[3] = {double(v[0]) - g[0], double(v[1]) - g[1], double(v[2]) - g[2]};
 #pragma unroll
             for (int a = 0; a < 3; ++a) {
                 const double qa = (double(Rm[3 * a]) * dd[0] + double(Rm[3 * a + 1]) * dd[1]) + double(Rm[3 * a + 2]) * dd[2];
                 q[j][a] = float(qa);
-                V[a] += double(w[j]) * ((qa + g[a]) + L.t[3 * sl[j] + a]);
+                V[a] += double(w[j]) * ((qa + g[a]) + tt[a]);
             }
         }
         if ((code & 3) && V[2] > 0.0) {
@@ -233,7 +225,7 @@ __global__ __launch_bounds__(kTileThreads) void k_linearize(const ProbDev *__res
             // contributions to the 4 bound nodes: rhs -w[q x g; g], diag w^2[diag(Q^T H Q); diag(H)]
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
-                float *c = L.c + cp[j];
+                float *c = Cl + cp[j];
                 const float *qq = q[j];
                 const float ww = w[j], w2 = w[j] * w[j];
                 float qxg[3];
@@ -255,18 +247,19 @@ __global__ __launch_bounds__(kTileThreads) void k_linearize(const ProbDev *__res
         const int se = idx == lv ? e_se : T.owned_eslot[size_t(e) * nn + ob + o];
         if (se == 255) continue;
         const uint32_t cpe = idx == lv ? e_cp : T.owned_cpos[size_t(e) * nn + ob + o];
-        float *c0 = L.c + (cpe & 0xffffu), *c1 = L.c + (cpe >> 16);
-        const float *gk = L.g + 3 * so, *gl = L.g + 3 * se;
+        float *c0 = Cl + (cpe & 0xffffu), *c1 = Cl + (cpe >> 16);
+        float Rk[9], tk[3], gk[3], Rl[9], tl[3], gl[3];
+        slot_rec_lin(S, so, Rk, tk, gk);
+        slot_rec_lin(S, se, Rl, tl, gl);
         float d[3] = {gl[0] - gk[0], gl[1] - gk[1], gl[2] - gk[2]};
         float ekl[3];
-        rot_apply(L.R + 9 * so, d, ekl);
+        rot_apply(Rk, d, ekl);
         float r[3];
         {
-            const float *Rk = L.R + 9 * so;
             const double dd[3] = {double(gl[0]) - gk[0], double(gl[1]) - gk[1], double(gl[2]) - gk[2]};
             for (int a = 0; a < 3; ++a) {
                 const double ed = (double(Rk[3 * a]) * dd[0] + double(Rk[3 * a + 1]) * dd[1]) + double(Rk[3 * a + 2]) * dd[2];
-                r[a] = float(double(pr.sw_arap) * ((ed - dd[a]) + (double(L.t[3 * so + a]) - L.t[3 * se + a])));
+                r[a] = float(double(pr.sw_arap) * ((ed - dd[a]) + (double(tk[a]) - tl[a])));
             }
         }
         e_a += double(r[0]) * r[0] + double(r[1]) * r[1] + double(r[2]) * r[2];
@@ -290,7 +283,7 @@ __global__ __launch_bounds__(kTileThreads) void k_linearize(const ProbDev *__res
     if (full) {
         for (int pair = threadIdx.x; pair < ns * 12; pair += blockDim.x) {
             const int s = pair / 12, comp = pair - s * 12;
-            pr.partial[size_t(comp) * T.nslots + ldest[s]] = run_sum(L.c + comp * NC, lbeg[s], lbeg[s + 1]);
+            pr.partial[size_t(comp) * T.nslots + ldest[s]] = run_sum(Cl + comp * NC, lbeg[s], lbeg[s + 1]);
         }
     }
     double es[kTerms] = {e_ph, e_s, e_sa, e_a, e_v};
