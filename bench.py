@@ -38,12 +38,20 @@ def algorithmic_bytes(kernel, n_act, n_nodes, n_edges, n_pix, n_faces, n_verts):
         return 240 * n_nodes
     if kernel == "blur":           # one pass: 3 channels read + written
         return 24 * n_pix
-    if kernel == "dt_rows":        # column distances in, distances out
-        return 8 * n_pix
+    if kernel == "dt_rows":        # column distances in, distances out (+ contour edges per vertex)
+        return 8 * n_pix + 64 * n_verts
     if kernel == "dt_cols":        # contour byte in, column distance written and re-read
         return 13 * n_pix
     if kernel == "raster":
         return 12 * n_faces + 12 * n_verts + 8 * n_pix // 4
+    if kernel == "prep_image":     # blur 24 B, contour 5 B, depth-buffer clear 4 B per pixel
+        return 33 * n_pix
+    if kernel == "prep_geom":      # deformed start per vertex; contour bytes read by the segment pass
+        return 64 * n_verts + n_pix
+    if kernel == "prep_raster":    # faces, and the segment rows (8 B per 16-row segment, read and written)
+        return 12 * n_faces + 12 * n_verts + 8 * n_pix // 4 + n_pix
+    if kernel == "prep_cols":      # column distances (large faces: a few queued faces)
+        return 13 * n_pix
     if kernel in ("contour", "decide", "deform_start", "contour_edges"):
         return 5 * n_pix if kernel == "contour" else 64 * n_verts
     if kernel == "pose_step":      # the 69 x 70 float64 system in, the pose out

@@ -401,7 +401,15 @@ CAPTURE_API int capture_set_graphs(capture_ctx *ctx, int on);
  * kernel until read.  Kernel names: "blur", "contour", "dt_cols", "dt_rows",
  * "deform_start", "raster", "contour_edges", "decide", "linearize",
  * "node_init", "apply", "node_pcg", "ws_features", "ws_mlp", "pose_lbs",
- * "pose_rows", "pose_jtj", "pose_step".
+ * "pose_rows", "pose_jtj", "pose_step", "prep_image", "prep_geom",
+ * "prep_raster", "prep_cols".  The non-rigid stage's per-frame steps run in
+ * combined launches: "prep_image" (frame set-up, blur, contour pixels),
+ * "prep_geom" (deformed start, column segments), "prep_raster"
+ * (rasterisation and, for few image columns, the segment scan; with many
+ * columns the scan is its own launch, timed as "dt_cols"), "prep_cols"
+ * (large faces, column distances), "dt_rows" (row pass, then contour
+ * edges), "decide".  The pose stage launches the steps one by one under the
+ * other names.
  * ------------------------------------------------------------------------ */
 CAPTURE_API int capture_profile_enable(capture_ctx *ctx, int on);
 /* Accumulated time (ms) and launch count of `kernel` since the last read;

@@ -121,7 +121,7 @@ SIGNATURES = {
 
 KERNELS = ("blur", "contour", "dt_cols", "dt_rows", "deform_start", "raster", "contour_edges", "decide",
            "linearize", "node_init", "apply", "node_pcg", "ws_features", "ws_mlp", "pose_lbs", "pose_rows",
-           "pose_jtj", "pose_step")
+           "pose_jtj", "pose_step", "prep_image", "prep_geom", "prep_raster", "prep_cols")
 WS_PARAMS = 38662
 
 _lib = None

@@ -14,25 +14,27 @@ namespace cap {
 
 // kernels defined in the other translation units
 __global__ void k_fill_u32(uint32_t *p, size_t n, uint32_t v);
-__global__ void k_blur(const ProbDev *P, float w0, float w1);
 __global__ void k_contour(const ProbDev *P);
 __global__ void k_dt_seg(const ProbDev *P);
 __global__ void k_dt_scan(const ProbDev *P);
 __global__ void k_dt_scan_cols(const ProbDev *P);
 __global__ void k_dt_cols(const ProbDev *P);
 __global__ void k_dt_rows(const ProbDev *P);
-__global__ void k_deform_start(const ProbDev *P);
 __global__ void k_raster(const ProbDev *P);
 __global__ void k_raster_big(const ProbDev *P);
 __global__ void k_contour_edges(const ProbDev *P);
 __global__ void k_decide(const ProbDev *P);
+__global__ void k_prep_image(const ProbDev *P, int nb_init, int nb_px, int gn_iters, float w0, float w1);
+__global__ void k_prep_geom(const ProbDev *P, int nb_v);
+__global__ void k_prep_raster(const ProbDev *P, int nb_f, int scan);
+__global__ void k_prep_cols(const ProbDev *P);
+__global__ void k_prep_rows(const ProbDev *P, int nb_rows);
 __global__ void k_linearize(const ProbDev *P, const TileDesc *D, int mode);
 template <int kSplit>
 __global__ void k_apply(const ProbDev *P, const TileDesc *D);
 __global__ void k_node_init(const ProbDev *P, int gn, int energy_only, int check_target);
 __global__ void k_node_gather(const ProbDev *P);
 __global__ void k_node_pcg(const ProbDev *P, int last, int update_only);
-__global__ void k_frame_init(const ProbDev *P, int gn_iters);
 __global__ void k_pcg_split_a(const ProbDev *P);
 __global__ void k_pcg_split_b(const ProbDev *P, int it);
 __global__ void k_pcg_split_c(const ProbDev *P, int it, int last);
@@ -290,7 +292,8 @@ enum class Stage { Decisions, Linearize, Solve };
 const char *kKernelNames[K_COUNT] = {"blur", "contour", "dt_cols", "dt_rows", "deform_start", "raster",
                                      "contour_edges", "decide", "linearize", "node_init", "apply", "node_pcg",
                                      "ws_features", "ws_mlp", "pose_lbs", "pose_rows", "pose_jtj",
-                                     "pose_step"};
+                                     "pose_step", "prep_image", "prep_geom", "prep_raster",
+                                     "prep_cols"};
 
 int setup(Run &R, capture_ctx *ctx, int n, const capture_frame *frames, const capture_nonrigid_params *params,
           void *ws, size_t ws_bytes, void *stream) {
@@ -366,41 +369,38 @@ int setup(Run &R, capture_ctx *ctx, int n, const capture_frame *frames, const ca
 int launch_frame(Run &R, int gn_iters = 0) {
     const int n = R.n;
     hipStream_t s = R.s;
-    hipLaunchKernelGGL(k_frame_init, dim3(blocks(R.max_hw, 1024), n), dim3(256), 0, s, R.dprobs, gn_iters);
     // Gaussian kernel 3, sigma = 0.3 * ((3 - 1) / 2 - 1) + 0.8 = 0.8, normalised
     const double e1 = std::exp(-1.0 / (2.0 * 0.8 * 0.8));
     const float w0 = float(e1 / (1.0 + 2.0 * e1)), w1 = float(1.0 / (1.0 + 2.0 * e1));
-    const dim3 gpx(blocks(R.max_hw, 256), n), gv(blocks(R.max_nv, 256), n);
-    timed(R, K_BLUR, [&] {
-    hipLaunchKernelGGL(k_blur, gpx, dim3(256), 0, s, R.dprobs, w0, w1);
-    });
-    timed(R, K_CONTOUR, [&] {
-    hipLaunchKernelGGL(k_contour, gpx, dim3(256), 0, s, R.dprobs);
-    });
     const size_t nsegw = size_t(R.max_w) * ((R.max_h + 15) / 16);
-    timed(R, K_DT_COLS, [&] {
-        hipLaunchKernelGGL(k_dt_seg, dim3(blocks(nsegw, 256), n), dim3(256), 0, s, R.dprobs);
-        if (size_t(n) * R.max_w >= kScanColsMin)      // enough columns: a thread per column
+    const int nb_init = blocks(R.max_hw, 1024), nb_px = blocks(R.max_hw, 256), nb_v = blocks(R.max_nv, 256);
+    const int nb_seg = blocks(nsegw, 256), nb_f = blocks(R.max_nf, 256), nb_me = blocks(R.max_me, 256);
+    // enough columns in all: the segment scan runs a thread per column in its own launch
+    const bool scan_cols = size_t(n) * R.max_w >= kScanColsMin;
+    const int nb_scan = scan_cols ? 0 : blocks(R.max_w, 4);
+    timed(R, K_PREP_IMAGE, [&] {
+        hipLaunchKernelGGL(k_prep_image, dim3(nb_init + 2 * nb_px, n), dim3(256), 0, s, R.dprobs, nb_init, nb_px,
+                           gn_iters, w0, w1);
+    });
+    timed(R, K_PREP_GEOM, [&] {
+        hipLaunchKernelGGL(k_prep_geom, dim3(nb_v + nb_seg, n), dim3(256), 0, s, R.dprobs, nb_v);
+    });
+    timed(R, K_PREP_RASTER, [&] {
+        hipLaunchKernelGGL(k_prep_raster, dim3(nb_f + nb_scan, n), dim3(256), 0, s, R.dprobs, nb_f, scan_cols ? 0 : 1);
+    });
+    if (scan_cols)
+        timed(R, K_DT_COLS, [&] {
             hipLaunchKernelGGL(k_dt_scan_cols, dim3(blocks(R.max_w, 64), n), dim3(64), 0, s, R.dprobs);
-        else                                            // few columns: a wave per column
-            hipLaunchKernelGGL(k_dt_scan, dim3(blocks(R.max_w, 4), n), dim3(256), 0, s, R.dprobs);
-        hipLaunchKernelGGL(k_dt_cols, dim3(blocks(nsegw, 256), n), dim3(256), 0, s, R.dprobs);
+        });
+    timed(R, K_PREP_COLS, [&] {
+        hipLaunchKernelGGL(k_prep_cols, dim3(kRasterBigBlocks + nb_seg, n), dim3(256), 0, s, R.dprobs);
     });
     timed(R, K_DT_ROWS, [&] {
-        hipLaunchKernelGGL(k_dt_rows, dim3(R.max_h, n), dim3(256), dt_rows_lds(R.max_w), s, R.dprobs);
-    });
-    timed(R, K_DEFORM, [&] {
-    hipLaunchKernelGGL(k_deform_start, gv, dim3(256), 0, s, R.dprobs);
-    });
-    timed(R, K_RASTER, [&] {
-    hipLaunchKernelGGL(k_raster, dim3(blocks(R.max_nf, 256), n), dim3(256), 0, s, R.dprobs);
-    hipLaunchKernelGGL(k_raster_big, dim3(kRasterBigBlocks, n), dim3(256), 0, s, R.dprobs);
-    });
-    timed(R, K_CEDGES, [&] {
-    hipLaunchKernelGGL(k_contour_edges, dim3(blocks(R.max_me, 256), n), dim3(256), 0, s, R.dprobs);
+        hipLaunchKernelGGL(k_prep_rows, dim3(R.max_h + nb_me, n), dim3(256), dt_rows_lds(R.max_w), s, R.dprobs,
+                           R.max_h);
     });
     timed(R, K_DECIDE, [&] {
-    hipLaunchKernelGGL(k_decide, gv, dim3(256), 0, s, R.dprobs);
+        hipLaunchKernelGGL(k_decide, dim3(nb_v, n), dim3(256), 0, s, R.dprobs);
     });
     CAP_HIP(hipGetLastError());
     return CAPTURE_OK;

@@ -16,10 +16,9 @@ __global__ void k_fill_u32(uint32_t *p, size_t n, uint32_t v) {
 // Separable Gaussian (kernel 3), clamp-to-edge, in one pass: each pixel forms
 // the horizontal sums of its three rows (rounded as a horizontal pass would
 // store them) and then the vertical sum.
-__global__ void k_blur(const ProbDev *__restrict__ P, float w0, float w1) {
-    const ProbDev &pr = P[blockIdx.y];
+__device__ inline void blur_body(const ProbDev &pr, int bx, float w0, float w1) {
     const int W = pr.W, H = pr.H;
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    int i = bx * blockDim.x + threadIdx.x;
     if (i >= W * H) return;
     int y = i / W, x = i - y * W;
     const size_t plane = size_t(W) * H;
@@ -39,10 +38,9 @@ __global__ void k_blur(const ProbDev *__restrict__ P, float w0, float w1) {
 
 // ---------------------------------------------------------------- distance transform
 // Contour pixels: foreground with a background 4-neighbour (outside = background).
-__global__ void k_contour(const ProbDev *__restrict__ P) {
-    const ProbDev &pr = P[blockIdx.y];
+__device__ inline void contour_body(const ProbDev &pr, int bx) {
     const int W = pr.W, H = pr.H;
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    int i = bx * blockDim.x + threadIdx.x;
     if (i >= W * H) return;
     int y = i / W, x = i - y * W;
     const CAP_GLOBAL uint8_t *m = pr.mask.g();
@@ -54,14 +52,15 @@ __global__ void k_contour(const ProbDev *__restrict__ P) {
     pr.contour[i] = c;
 }
 
+__global__ void k_contour(const ProbDev *__restrict__ P) { contour_body(P[blockIdx.y], blockIdx.x); }
+
 constexpr int kFar = 1 << 20;
 constexpr int kSeg = 16;   // rows per column segment
 
 // Phase 1a: per (column, 16-row segment), the first and last contour row.
-__global__ void k_dt_seg(const ProbDev *__restrict__ P) {
-    const ProbDev &pr = P[blockIdx.y];
+__device__ inline void dt_seg_body(const ProbDev &pr, int bx) {
     const int W = pr.W, H = pr.H, nseg = (H + kSeg - 1) / kSeg;
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int i = bx * blockDim.x + threadIdx.x;
     if (i >= W * nseg) return;
     const int s = i / W, x = i - s * W;
     int first = kFar, last = -kFar;
@@ -72,6 +71,8 @@ __global__ void k_dt_seg(const ProbDev *__restrict__ P) {
     pr.seg_last[i] = last;
 }
 
+__global__ void k_dt_seg(const ProbDev *__restrict__ P) { dt_seg_body(P[blockIdx.y], blockIdx.x); }
+
 // Phase 1b: per column, the nearest contour row above and below each segment,
 // written over seg_last (above) and seg_first (below).  One wave per column,
 // a lane per segment (kScanChunks chunks of 64 segments): the rows above are
@@ -80,10 +81,9 @@ __global__ void k_dt_seg(const ProbDev *__restrict__ P) {
 // first ones, both formed with lane shuffles.
 constexpr int kScanChunks = (kMaxImageSide / kSeg + 63) / 64;
 
-__global__ __launch_bounds__(256) void k_dt_scan(const ProbDev *__restrict__ P) {
-    const ProbDev &pr = P[blockIdx.y];
+__device__ inline void dt_scan_body(const ProbDev &pr, int bx) {
     const int W = pr.W, H = pr.H, nseg = (H + kSeg - 1) / kSeg;
-    const int x = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+    const int x = bx * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
     if (x >= W) return;
     int last[kScanChunks], first[kScanChunks];
 #pragma unroll
@@ -130,6 +130,8 @@ __global__ __launch_bounds__(256) void k_dt_scan(const ProbDev *__restrict__ P) 
     }
 }
 
+__global__ __launch_bounds__(256) void k_dt_scan(const ProbDev *__restrict__ P) { dt_scan_body(P[blockIdx.y], blockIdx.x); }
+
 // The same with one thread per column (coalesced across columns), in one pass
 // down and one up; segments are read kScanBatch at a time into registers, so
 // the loads of a batch are in flight together.  Used when the frames have
@@ -167,10 +169,9 @@ __global__ void k_dt_scan_cols(const ProbDev *__restrict__ P) {
 
 // Phase 1c: per (column, segment), distance in rows to the nearest contour
 // pixel of the column (carry from the other segments, then the segment's rows).
-__global__ void k_dt_cols(const ProbDev *__restrict__ P) {
-    const ProbDev &pr = P[blockIdx.y];
+__device__ inline void dt_cols_body(const ProbDev &pr, int bx) {
     const int W = pr.W, H = pr.H, nseg = (H + kSeg - 1) / kSeg;
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int i = bx * blockDim.x + threadIdx.x;
     if (i >= W * nseg) return;
     const int s = i / W, x = i - s * W;
     const int above = pr.seg_last[i], below = pr.seg_first[i];
@@ -194,6 +195,8 @@ __global__ void k_dt_cols(const ProbDev *__restrict__ P) {
     }
 }
 
+__global__ void k_dt_cols(const ProbDev *__restrict__ P) { dt_cols_body(P[blockIdx.y], blockIdx.x); }
+
 // Phase 2: per row, D(x) = min over x' of (x - x')^2 + G(x'), G = g^2, exact.
 // The row's G is staged in LDS and cut into kDtChunks column chunks with their
 // smallest G.  Each pixel takes the minimum over its own chunk's columns
@@ -207,12 +210,10 @@ __global__ void k_dt_cols(const ProbDev *__restrict__ P) {
 #endif
 constexpr int kDtUnroll = CAP_DT_UNROLL;
 
-__global__ __launch_bounds__(256) void k_dt_rows(const ProbDev *__restrict__ P) {
+__device__ inline void dt_rows_body(const ProbDev &pr, int y) {
     extern __shared__ int G[];
     __shared__ int cmin[kDtChunks];
-    const ProbDev &pr = P[blockIdx.y];
     const int W = pr.W, H = pr.H;
-    const int y = blockIdx.x;
     if (y >= H) return;
     const int far2 = 1 << 30;
     for (int x = threadIdx.x; x < W; x += blockDim.x) {
@@ -271,14 +272,15 @@ __global__ __launch_bounds__(256) void k_dt_rows(const ProbDev *__restrict__ P) 
     }
 }
 
+__global__ __launch_bounds__(256) void k_dt_rows(const ProbDev *__restrict__ P) { dt_rows_body(P[blockIdx.y], blockIdx.x); }
+
 // ---------------------------------------------------------------- start-state geometry
 // Embedded deformation at the start state, float32 recipe, then projection
 // and 1/256-pixel snapping.  Vertex order.
-__global__ void k_deform_start(const ProbDev *__restrict__ P) {
-    const ProbDev &pr = P[blockIdx.y];
+__device__ inline void deform_start_body(const ProbDev &pr, int bx) {
     const TemplateDev &T = pr.T;
     const int nv = T.nv, nn = T.nn;
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    int i = bx * blockDim.x + threadIdx.x;
     if (i >= nv) return;
     float v[3] = {pr.xyz[i], pr.xyz[nv + i], pr.xyz[2 * nv + i]};
     float acc[3] = {0.0f, 0.0f, 0.0f};
@@ -362,11 +364,10 @@ __device__ inline void tri_pixel(const ProbDev &pr, const TriRaster &s, long lon
 // Per face: cross product (for normals), then rasterise the inverse depth.
 // A face whose pixel box holds more than kRasterSmall pixels is queued for
 // k_raster_big instead, so one thread never walks a large box.
-__global__ void k_raster(const ProbDev *__restrict__ P) {
-    const ProbDev &pr = P[blockIdx.y];
+__device__ inline void raster_body(const ProbDev &pr, int bx) {
     const TemplateDev &T = pr.T;
     const int nv = T.nv, nf = T.nf;
-    int f = blockIdx.x * blockDim.x + threadIdx.x;
+    int f = bx * blockDim.x + threadIdx.x;
     if (f >= nf) return;
     int a = T.tri[f], b = T.tri[nf + f], c = T.tri[2 * size_t(nf) + f];
     float p0[3] = {pr.dx[a], pr.dx[nv + a], pr.dx[2 * nv + a]};
@@ -387,11 +388,12 @@ __global__ void k_raster(const ProbDev *__restrict__ P) {
         for (long long i = s.i0; i <= s.i1; ++i) tri_pixel(pr, s, i, j);
 }
 
+__global__ void k_raster(const ProbDev *__restrict__ P) { raster_body(P[blockIdx.y], blockIdx.x); }
+
 // Queued large faces: one workgroup per face at a time, threads over its pixel box.
-__global__ __launch_bounds__(256) void k_raster_big(const ProbDev *__restrict__ P) {
-    const ProbDev &pr = P[blockIdx.y];
+__device__ inline void raster_big_body(const ProbDev &pr, int bx, int nbx) {
     const int nq = pr.counts[2];
-    for (int q = blockIdx.x; q < nq; q += gridDim.x) {
+    for (int q = bx; q < nq; q += nbx) {
         TriRaster s;
         if (!tri_setup(pr, pr.bigq[q], s)) continue;
         const long long w = s.i1 - s.i0 + 1, area = w * (s.j1 - s.j0 + 1);
@@ -399,13 +401,16 @@ __global__ __launch_bounds__(256) void k_raster_big(const ProbDev *__restrict__ 
     }
 }
 
+__global__ __launch_bounds__(256) void k_raster_big(const ProbDev *__restrict__ P) {
+    raster_big_body(P[blockIdx.y], blockIdx.x, gridDim.x);
+}
+
 // Per mesh edge: contour edge when its faces' facing differs (a border edge
 // when its one face is front-facing); marks both endpoints.
-__global__ void k_contour_edges(const ProbDev *__restrict__ P) {
-    const ProbDev &pr = P[blockIdx.y];
+__device__ inline void contour_edges_body(const ProbDev &pr, int bx) {
     const TemplateDev &T = pr.T;
     const int nv = T.nv, nf = T.nf, ne = T.nmedges;
-    int e = blockIdx.x * blockDim.x + threadIdx.x;
+    int e = bx * blockDim.x + threadIdx.x;
     if (e >= ne) return;
     int a = T.medge[e], b = T.medge[ne + e], f0 = T.medge[2 * ne + e], f1 = T.medge[3 * ne + e];
     auto back = [&](int f) {
@@ -419,6 +424,96 @@ __global__ void k_contour_edges(const ProbDev *__restrict__ P) {
         pr.vcont[a] = 1;
         pr.vcont[b] = 1;
     }
+}
+
+__global__ void k_contour_edges(const ProbDev *__restrict__ P) { contour_edges_body(P[blockIdx.y], blockIdx.x); }
+
+// ---------------------------------------------------------------- per-frame set-up
+// Scalars and counters (block 0), the start-state copy and the node positions
+// (the frame's mesh at the node vertices, node-major, read by the tile
+// kernels), and an empty depth buffer (4 pixels per thread), over nbx blocks.
+__device__ inline void frame_init_body(const ProbDev &pr, int bx, int nbx, int gn_iters) {
+    const TemplateDev &T = pr.T;
+    const int nn = T.nn, tid = bx * blockDim.x + threadIdx.x, nt = nbx * blockDim.x;
+    if (bx == 0) {
+        for (int i = threadIdx.x; i < kScalars; i += blockDim.x) pr.scal[i] = i == 3 ? double(gn_iters) : 0.0;
+        if (threadIdx.x < 3) pr.counts[threadIdx.x] = 0;
+    }
+    for (int i = tid; i < 12 * nn; i += nt) pr.state0[i] = pr.state[i];
+    for (int i = tid; i < 3 * nn; i += nt) {
+        const int a = i / nn, k = i - a * nn;
+        pr.gpos[i] = pr.xyz[size_t(a) * T.nv + T.node_vertex[k]];
+    }
+    const size_t hw = size_t(pr.W) * pr.H;
+    const size_t i = size_t(tid) * 4;
+    for (int q = 0; q < 4; ++q)
+        if (i + q < hw) pr.zbuf[i + q] = 0u;
+}
+
+// ---------------------------------------------------------------- combined launches
+// A frame's preprocessing is two independent chains, the image one (blur;
+// contour pixels, column segments, segment scan, column distances, row pass)
+// and the geometric one (deformed start, rasterisation, large faces, contour
+// edges), joined by the per-vertex decisions.  Steps of the two chains that
+// have the same predecessors share a launch: consecutive block ranges of one
+// grid run different steps (256 threads each; blockIdx.y = problem), which
+// takes a frame from eleven launches to six.  The contour edges run last in
+// the row pass's launch, so the vertex and face data they read is fresh in
+// cache for the decisions that follow.
+
+// Set-up (nb_init blocks), blur (nb_px), contour pixels (nb_px).
+__global__ __launch_bounds__(256) void k_prep_image(const ProbDev *__restrict__ P, int nb_init, int nb_px, int gn_iters,
+                                                    float w0, float w1) {
+    const ProbDev &pr = P[blockIdx.y];
+    const int bx = blockIdx.x;
+    if (bx < nb_init)
+        frame_init_body(pr, bx, nb_init, gn_iters);
+    else if (bx < nb_init + nb_px)
+        blur_body(pr, bx - nb_init, w0, w1);
+    else
+        contour_body(pr, bx - nb_init - nb_px);
+}
+
+// Deformed start (nb_v blocks), then the column segments' contour rows.
+__global__ __launch_bounds__(256) void k_prep_geom(const ProbDev *__restrict__ P, int nb_v) {
+    const ProbDev &pr = P[blockIdx.y];
+    const int bx = blockIdx.x;
+    if (bx < nb_v)
+        deform_start_body(pr, bx);
+    else
+        dt_seg_body(pr, bx - nb_v);
+}
+
+// Rasterisation (nb_f blocks), then (when `scan`) the segment scan, a wave
+// per column.
+__global__ __launch_bounds__(256) void k_prep_raster(const ProbDev *__restrict__ P, int nb_f, int scan) {
+    const ProbDev &pr = P[blockIdx.y];
+    const int bx = blockIdx.x;
+    if (bx < nb_f)
+        raster_body(pr, bx);
+    else if (scan)
+        dt_scan_body(pr, bx - nb_f);
+}
+
+// Large faces (kRasterBigBlocks blocks), then the column distances.
+__global__ __launch_bounds__(256) void k_prep_cols(const ProbDev *__restrict__ P) {
+    const ProbDev &pr = P[blockIdx.y];
+    const int bx = blockIdx.x;
+    if (bx < kRasterBigBlocks)
+        raster_big_body(pr, bx, kRasterBigBlocks);
+    else
+        dt_cols_body(pr, bx - kRasterBigBlocks);
+}
+
+// Row pass (one block per row of the largest image, nb_rows; dynamic LDS
+// dt_rows_lds(largest width)), then the contour edges.
+__global__ __launch_bounds__(256) void k_prep_rows(const ProbDev *__restrict__ P, int nb_rows) {
+    const ProbDev &pr = P[blockIdx.y];
+    const int bx = blockIdx.x;
+    if (bx < nb_rows)
+        dt_rows_body(pr, bx);
+    else
+        contour_edges_body(pr, bx - nb_rows);
 }
 
 // Per vertex: visibility, contour set and direction sign; writes the flags in

@@ -597,29 +597,6 @@ __global__ __launch_bounds__(kInitThreads) void k_node_init(const ProbDev *__res
     }
 }
 
-// Per-frame set-up of every problem: scalars and counters (block 0), the
-// start-state copy and the node positions (the frame's mesh at the node
-// vertices, node-major, read by the tile kernels), and empty depth buffers
-// (4 pixels per thread).  Grid: (blocks over the largest image, problems).
-__global__ void k_frame_init(const ProbDev *__restrict__ P, int gn_iters) {
-    const ProbDev &pr = P[blockIdx.y];
-    const TemplateDev &T = pr.T;
-    const int nn = T.nn, tid = blockIdx.x * blockDim.x + threadIdx.x, nt = gridDim.x * blockDim.x;
-    if (blockIdx.x == 0) {
-        for (int i = threadIdx.x; i < kScalars; i += blockDim.x) pr.scal[i] = i == 3 ? double(gn_iters) : 0.0;
-        if (threadIdx.x < 3) pr.counts[threadIdx.x] = 0;
-    }
-    for (int i = tid; i < 12 * nn; i += nt) pr.state0[i] = pr.state[i];
-    for (int i = tid; i < 3 * nn; i += nt) {
-        const int a = i / nn, k = i - a * nn;
-        pr.gpos[i] = pr.xyz[size_t(a) * T.nv + T.node_vertex[k]];
-    }
-    const size_t hw = size_t(pr.W) * pr.H;
-    const size_t i = size_t(tid) * 4;
-    for (int q = 0; q < 4; ++q)
-        if (i + q < hw) pr.zbuf[i + q] = 0u;
-}
-
 // Gather A p from the tile partials (no PCG update).
 __global__ __launch_bounds__(kNodeThreads) void k_node_gather(const ProbDev *__restrict__ P) {
     const ProbDev &pr = P[blockIdx.x];
