@@ -74,15 +74,29 @@ constexpr int kLayerThreads = 512;
 // One 16x16 output tile of a layer: the lane's weight fragments (output
 // column jb, all of k) are loaded into registers at the start of the kernel,
 // before the input tile is formed, so that round of latency overlaps the
-// gathers; the MFMA chain then runs over k from LDS.
+// gathers; the MFMA chain then runs over k from LDS.  A fragment is four
+// consecutive bf16 of a weight row, one 8-byte load (rows are K elements and
+// the weight blocks start on 8-byte boundaries).
 template <int K>
 __device__ inline void load_wfrag(const uint16_t *__restrict__ W, int jb, int N, s4v (&bw)[K / 16]) {
     const int kq = ((threadIdx.x & 63) >> 4) * 4;
-    const uint16_t *wrow = W + size_t(jb < N ? jb : 0) * K + kq;
+    const uint2 *wrow = reinterpret_cast<const uint2 *>(W + size_t(jb < N ? jb : 0) * K + kq);
 #pragma unroll
-    for (int s = 0; s < K / 16; ++s)
-#pragma unroll
-        for (int q = 0; q < 4; ++q) bw[s][q] = jb < N ? short(wrow[16 * s + q]) : short(0);
+    for (int s = 0; s < K / 16; ++s) {      // lanes past N load row 0: their output columns are never stored
+        const uint2 u = wrow[4 * s];
+        bw[s][0] = short(u.x & 0xffffu);
+        bw[s][1] = short(u.x >> 16);
+        bw[s][2] = short(u.y & 0xffffu);
+        bw[s][3] = short(u.y >> 16);
+    }
+}
+
+// Workgroup barrier that orders LDS accesses only (global loads in flight
+// stay in flight across it).
+__device__ inline void lds_barrier() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
 }
 
 template <int K>
@@ -119,7 +133,7 @@ __global__ __launch_bounds__(kLayerThreads) void k_ws_layer1(const float *__rest
         }
         As[r][k] = b;
     }
-    __syncthreads();
+    lds_barrier();
     {
         const int t = wv;
         const f4v acc = tile_mfma<32>(As, bw);
@@ -154,17 +168,25 @@ __global__ __launch_bounds__(kLayerThreads) void k_ws_layer_mp(uint16_t *__restr
     __shared__ int nbs[16][8];
     const int i0 = blockIdx.x * 16;
     const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63, r = lane & 15;
+    // the neighbour list (every thread loads an entry, the first 128 store
+    // them) and the weights, unconditionally (no branches between the loads);
+    // the barriers order LDS only
+    const int ri = threadIdx.x & 127, ni = i0 + (ri >> 3);
+    int nb = edge_dst[(ri & 7) * nn + min(ni, nn - 1)];
+    if (ni >= nn) nb = -1;
     s4v bw[16];
-    if (wv < NT) load_wfrag<256>(W, wv * 16 + r, N, bw);
-    if (threadIdx.x < 128) {
-        const int r = threadIdx.x >> 3, e = threadIdx.x & 7, i = i0 + r;
-        nbs[r][e] = i < nn ? edge_dst[e * nn + i] : -1;
-    }
-    __syncthreads();
+    load_wfrag<256>(W, (wv < NT ? wv : 0) * 16 + r, N, bw);
+    if (threadIdx.x < 128) nbs[ri >> 3][ri & 7] = nb;
+    lds_barrier();
     // the input tile: ReLU(z_prev) copied (2048 values) and the neighbour means
     // (2048 values of 8 loads each), kFill of each per thread, every load of
     // the thread issued before any sum
     constexpr int kFill = 16 * 128 / kLayerThreads;
+    int nbr[kFill][8];      // the rows' neighbour lists, all read from LDS before any load
+#pragma unroll
+    for (int m = 0; m < kFill; ++m)
+#pragma unroll
+        for (int e = 0; e < 8; ++e) nbr[m][e] = nbs[(threadIdx.x + kLayerThreads * m) >> 7][e];
     uint16_t own[kFill];
     float v[kFill][8];
 #pragma unroll
@@ -173,7 +195,7 @@ __global__ __launch_bounds__(kLayerThreads) void k_ws_layer_mp(uint16_t *__restr
         own[m] = i < nn ? cat[size_t(i) * 256 + f] : uint16_t(0);
 #pragma unroll
         for (int e = 0; e < 8; ++e) {         // safe index when the edge is absent
-            const int l = nbs[rr][e];
+            const int l = nbr[m][e];
             v[m][e] = i < nn ? zp[size_t(l >= 0 ? l : 0) * 128 + f] : 0.0f;
         }
     }
@@ -184,7 +206,7 @@ __global__ __launch_bounds__(kLayerThreads) void k_ws_layer_mp(uint16_t *__restr
         int cnt = 0;
 #pragma unroll
         for (int e = 0; e < 8; ++e)
-            if (nbs[rr][e] >= 0) {
+            if (nbr[m][e] >= 0) {
                 sum += v[m][e] > 0.0f ? v[m][e] : 0.0f;
                 ++cnt;
             }
@@ -193,7 +215,7 @@ __global__ __launch_bounds__(kLayerThreads) void k_ws_layer_mp(uint16_t *__restr
         As[rr][f] = own[m];
         As[rr][128 + f] = b;
     }
-    __syncthreads();
+    lds_barrier();
     if (wv < NT) {
         const int t = wv;
         const f4v acc = tile_mfma<256>(As, bw);
