@@ -84,47 +84,62 @@ __global__ __launch_bounds__(kTileThreads) void k_linearize(const ProbDev *__res
     const int vb = d.vb, nvt = d.nvt, sb = d.sb, ns = d.ns, ob = d.ob, nown = d.nown;
     // Every global read that needs no other global value first (the vertex's
     // own data, slot nodes, run offsets, destinations, owned edges), then the
-    // slot nodes' state; the stop tests sit between the two rounds.
-    const int lv = threadIdx.x, p = vb + lv;
-    const bool has_v = lv < nvt;
-    uint8_t code = 0;
-    uint32_t packed = 0;
-    float v[3] = {0, 0, 0}, w[4] = {0, 0, 0, 0}, pcol[3] = {0, 0, 0}, pva[3] = {0, 0, 0};
-    int cp[4] = {0, 0, 0, 0};
-    if (has_v) {
-        code = pr.vcode[p];
-        packed = T.plan_slot[p];
-        v[0] = pr.px[p]; v[1] = pr.px[nv + p]; v[2] = pr.px[2 * nv + p];
-#pragma unroll
-        for (int j = 0; j < 4; ++j) w[j] = T.plan_w[size_t(j) * nv + p];
-#pragma unroll
-        for (int c = 0; c < 3; ++c) pcol[c] = pr.pc[size_t(c) * nv + p];
-#pragma unroll
-        for (int a = 0; a < 3; ++a) pva[a] = pr.pva[size_t(a) * nv + p];
-        if (full)
-#pragma unroll
-            for (int j = 0; j < 4; ++j) cp[j] = T.plan_cpos[size_t(j) * nv + p];
-    }
+    // slot nodes' state; the stop tests sit between the two rounds.  The
+    // first round is branch-free: every thread loads at clamped (in-bounds)
+    // positions and replaces what lies outside its ranges afterwards, so all
+    // of its loads are in flight together.
     static_assert(kMaxTileSlots < kTileThreads, "one thread per slot and run offset");
-    const bool has_s = lv < ns;
-    int snode = 0;
-    if (has_s) {
-        snode = T.slot_node[sb + lv];
-        if (full) ldest[lv] = T.slot_dest[sb + lv];
-    }
+    const int lv = threadIdx.x, p = vb + lv;
+    const bool has_v = lv < nvt, has_s = lv < ns, has_e = lv < nown * 8;
+    const int pv = min(p, nv - 1), ps = min(sb + lv, T.nslots - 1), pl = min(sb + lv, T.nslots);
+    const int po = min(ob + (lv >> 3), nn - 1), pe8 = (lv & 7) * nn + po;
+    uint8_t code = pr.vcode[pv];
+    uint32_t packed = T.plan_slot[pv];
+    float v[3], w[4], pcol[3], pva[3];
+    int cp[4];
+    v[0] = pr.px[pv]; v[1] = pr.px[nv + pv]; v[2] = pr.px[2 * nv + pv];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) w[j] = T.plan_w[size_t(j) * nv + pv];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) pcol[c] = pr.pc[size_t(c) * nv + pv];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) pva[a] = pr.pva[size_t(a) * nv + pv];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) cp[j] = T.plan_cpos[size_t(j) * nv + pv];
+    int snode = T.slot_node[ps];
+    const int sdest = T.slot_dest[ps];
+    const int lb = T.list_beg[pl];
+    int e_so = T.owned_slot[po], e_se = T.owned_eslot[pe8];
+    uint32_t e_cp = T.owned_cpos[pe8];
     const int l0 = T.list_beg[sb];
-    if (full && lv <= ns) lbeg[lv] = T.list_beg[sb + lv] - l0;
-    const bool has_e = lv < nown * 8;
-    int e_so = 0, e_se = 255;
-    uint32_t e_cp = 0;
-    if (has_e) {
-        const int o = lv >> 3, e = lv & 7;
-        e_so = T.owned_slot[ob + o];
-        e_se = T.owned_eslot[size_t(e) * nn + ob + o];
-        e_cp = T.owned_cpos[size_t(e) * nn + ob + o];
+    const double stopped = pr.scal[2], rejected = pr.scal[5];     // read here, tested below
+    // the destinations and run offsets are consumed here, unconditionally, so
+    // that their loads are not moved into the branches below (behind the rest)
+    __asm__ volatile("" ::"v"(sdest), "v"(lb));
+    if (!has_v) {
+        code = 0;
+        packed = 0;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) v[a] = pcol[a] = pva[a] = 0.0f;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            w[j] = 0.0f;
+            cp[j] = 0;
+        }
     }
-    if (pr.scal[2] != 0.0) return;
-    if ((mode & 2) && pr.scal[5] == 0.0) return;      // conditional pass: only after a rejected prediction
+    if (!full)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) cp[j] = 0;
+    if (!has_s) snode = 0;
+    if (!has_e) {
+        e_so = 0;
+        e_se = 255;
+        e_cp = 0;
+    }
+    if (full && has_s) ldest[lv] = sdest;
+    if (full && lv <= ns) lbeg[lv] = lb - l0;
+    if (stopped != 0.0) return;
+    if ((mode & 2) && rejected == 0.0) return;      // conditional pass: only after a rejected prediction
     // LDS: one 64-byte record per slot (R, t, node position: four float4),
     // then contributions [12][NC]
     float4 *S = reinterpret_cast<float4 *>(lds);
@@ -312,34 +327,42 @@ __global__ __launch_bounds__(kTileThreads) void k_apply(const ProbDev *__restric
     // Global reads come in two dependent rounds: indices (vertex codes and
     // contribution positions, slot nodes, run offsets, destinations, owned
     // edges) and then the data they select; the stop flag is tested between.
-    const int lv = threadIdx.x, p = d.vb + lv;
-    const bool has_v = lv < d.nvt;
-    uint8_t code = 0;
-    int cp[4] = {0, 0, 0, 0};
-    if (has_v) {
-        code = pr.vcode[p];
-#pragma unroll
-        for (int j = 0; j < 4; ++j) cp[j] = T.plan_cpos[size_t(j) * nv + p];
-    }
+    // The first round is branch-free: every thread loads at clamped (in-bounds)
+    // positions and replaces what lies outside its ranges afterwards, so all
+    // of its loads are in flight together.
     static_assert(kMaxTileSlots < kTileThreads, "one thread per slot and run offset");
-    const bool has_s = lv < ns;
-    int snode = 0;
-    if (has_s) {
-        snode = T.slot_node[d.sb + lv];
-        ldest[lv] = T.slot_dest[d.sb + lv];
-    }
+    const int lv = threadIdx.x, p = d.vb + lv;
+    const bool has_v = lv < d.nvt, has_s = lv < ns, has_e = lv < nown * 8;
+    const int pv = min(p, nv - 1), ps = min(d.sb + lv, T.nslots - 1), pl = min(d.sb + lv, T.nslots);
+    const int po = min(d.ob + (lv >> 3), nn - 1), pe8 = (lv & 7) * nn + po;
+    uint8_t code = pr.vcode[pv];
+    int cp[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) cp[j] = T.plan_cpos[size_t(j) * nv + pv];
+    int snode = T.slot_node[ps];
+    const int sdest = T.slot_dest[ps];
+    const int lb = T.list_beg[pl];
+    int e_so = T.owned_slot[po], e_se = T.owned_eslot[pe8];
+    uint32_t e_cp = T.owned_cpos[pe8];
     const int l0 = T.list_beg[d.sb];
-    if (lv <= ns) lbeg[lv] = T.list_beg[d.sb + lv] - l0;
-    const bool has_e = lv < nown * 8;
-    int e_so = 0, e_se = 255;
-    uint32_t e_cp = 0;
-    if (has_e) {
-        const int o = lv >> 3, e = lv & 7;
-        e_so = T.owned_slot[d.ob + o];
-        e_se = T.owned_eslot[size_t(e) * nn + d.ob + o];
-        e_cp = T.owned_cpos[size_t(e) * nn + d.ob + o];
+    const double pcg_stopped = pr.scal[1];     // read here, tested below
+    // the destinations and run offsets are consumed here, unconditionally, so
+    // that their loads are not moved into the branches below (behind the rest)
+    __asm__ volatile("" ::"v"(sdest), "v"(lb));
+    if (!has_v) {
+        code = 0;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) cp[j] = 0;
     }
-    if (pr.scal[1] != 0.0) return;    // this problem's PCG has stopped
+    if (!has_s) snode = 0;
+    if (!has_e) {
+        e_so = 0;
+        e_se = 255;
+        e_cp = 0;
+    }
+    if (has_s) ldest[lv] = sdest;
+    if (lv <= ns) lbeg[lv] = lb - l0;
+    if (pcg_stopped != 0.0) return;    // this problem's PCG has stopped
     const bool act = (code & 11) != 0;
     uint32_t packed = 0;
     float v[3] = {0, 0, 0}, w[4] = {0, 0, 0, 0}, Hm[6] = {0, 0, 0, 0, 0, 0};
