@@ -528,6 +528,37 @@ __device__ inline float sum_parts(gptr<const float> partial, int stride, int c, 
     return a;
 }
 
+// The same for G items at once, without branches between the loads: every
+// item's first kParts loads are issued unconditionally (positions past pe
+// re-read the node's last part, part 0 for a node without parts) and in
+// flight together, then the items' sums, then (rarely) their parts past
+// kParts; each item's sum is formed in the same order as by sum_parts.  The
+// c[] must be components (0..11).  This pays where the branchy loads
+// serialise many items (k_node_init); with few parts per item the extra
+// loads cost more than the waits they save (k_node_pcg).
+template <int G>
+__device__ inline void sum_parts_n(gptr<const float> partial, int stride, const int (&c)[G], const int (&pb)[G],
+                                   const int (&pe)[G], float (&out)[G]) {
+    float v[G][kParts];
+#pragma unroll
+    for (int h = 0; h < G; ++h) {
+        const int qmax = max(pe[h] - 1, 0);
+#pragma unroll
+        for (int u = 0; u < kParts; ++u) v[h][u] = partial[size_t(c[h]) * stride + min(pb[h] + u, qmax)];
+    }
+#pragma unroll
+    for (int h = 0; h < G; ++h) {
+        float a = 0.0f;
+#pragma unroll
+        for (int u = 0; u < kParts; ++u)
+            if (pb[h] + u < pe[h]) a += v[h][u];
+        out[h] = a;
+    }
+#pragma unroll
+    for (int h = 0; h < G; ++h)
+        for (int q = pb[h] + kParts; q < pe[h]; ++q) out[h] += partial[size_t(c[h]) * stride + q];
+}
+
 __device__ inline float gather_node(const TemplateDev &T, gptr<const float> partial, int stride, int k,
                                     int c) {
     return sum_parts(partial, stride, c, T.node_pbeg[k], T.node_pbeg[k + 1]);
@@ -547,49 +578,50 @@ __global__ __launch_bounds__(kInitThreads) void k_node_init(const ProbDev *__res
         for (int q = 0; q < kTerms; ++q) v[1 + q] += pr.tile_e[size_t(t) * kTerms + q];
     const bool regs = n6 <= kInitItems * kInitThreads;
     int pb[kInitItems], pe[kInitItems];
-    if (!energy_only && regs) {
+    if (!energy_only && regs) {     // unconditional loads at clamped positions, zeroed past the items
 #pragma unroll
         for (int j = 0; j < kInitItems; ++j) {
-            const int i = threadIdx.x + j * kInitThreads;
-            pb[j] = pe[j] = 0;
-            if (i < n6) {
-                const int k = i % nn;
-                pb[j] = T.node_pbeg[k]; pe[j] = T.node_pbeg[k + 1];
-            }
+            const int k = min(int(threadIdx.x) + j * kInitThreads, n6 - 1) % nn;
+            pb[j] = T.node_pbeg[k]; pe[j] = T.node_pbeg[k + 1];
         }
+#pragma unroll
+        for (int j = 0; j < kInitItems; ++j)
+            if (int(threadIdx.x) + j * kInitThreads >= n6) pb[j] = pe[j] = 0;
     }
     if (pr.scal[2] != 0.0) return;   // stopped at the target energy
     if ((check_target & 2) && pr.scal[5] == 0.0) return;   // conditional pass (see k_linearize)
     if (!energy_only) {
         if (regs) {
+            // items in groups of four, each group's loads (b and the diagonal,
+            // kParts parts each) in flight together
+            constexpr int G = 4;
+            static_assert(kInitItems % G == 0, "whole groups");
 #pragma unroll
-            for (int j = 0; j < kInitItems; ++j) {
-                const int i = threadIdx.x + j * kInitThreads;
-                if (i < n6) {
-                    const int c = i / nn;
-                    // the two components' loads interleaved: b and the diagonal of one part share a line
-                    float vb[kParts], vd[kParts];
+            for (int g = 0; g < kInitItems; g += G) {
+                if (g * kInitThreads >= n6) break;           // (uniform) no thread has these items
+                int cb[G], cd[G], gb[G], ge[G];
+                float bb[G], dd[G];
 #pragma unroll
-                    for (int u = 0; u < kParts; ++u) {
-                        const bool in = pb[j] + u < pe[j];
-                        vb[u] = in ? pr.partial[size_t(c) * T.nslots + pb[j] + u] : 0.0f;
-                        vd[u] = in ? pr.partial[size_t(6 + c) * T.nslots + pb[j] + u] : 0.0f;
-                    }
-                    float b = 0.0f, d = 0.0f;
-#pragma unroll
-                    for (int u = 0; u < kParts; ++u)
-                        if (pb[j] + u < pe[j]) { b += vb[u]; d += vd[u]; }
-                    for (int q = pb[j] + kParts; q < pe[j]; ++q) {
-                        b += pr.partial[size_t(c) * T.nslots + q];
-                        d += pr.partial[size_t(6 + c) * T.nslots + q];
-                    }
-                    const float mi = d > 0.0f ? 1.0f / d : 1.0f;
-                    const float z = mi * b;
-                    pr.b[i] = b; pr.diag[i] = d; pr.dinv[i] = mi;
-                    pr.x[i] = 0.0f; pr.r[i] = b; pr.z[i] = z; pr.p[i] = z;
-                    v[0] += double(b) * double(z);
+                for (int h = 0; h < G; ++h) {
+                    cb[h] = min(int(threadIdx.x) + (g + h) * kInitThreads, n6 - 1) / nn;
+                    cd[h] = 6 + cb[h];
+                    gb[h] = pb[g + h];
+                    ge[h] = pe[g + h];
                 }
-                __asm__ volatile("" ::: "memory");    // one item's loads in flight at a time (registers)
+                sum_parts_n<G>(pr.partial, T.nslots, cb, gb, ge, bb);
+                sum_parts_n<G>(pr.partial, T.nslots, cd, gb, ge, dd);
+#pragma unroll
+                for (int h = 0; h < G; ++h) {
+                    const int i = threadIdx.x + (g + h) * kInitThreads;
+                    if (i < n6) {
+                        const float b = bb[h], d = dd[h];
+                        const float mi = d > 0.0f ? 1.0f / d : 1.0f;
+                        const float z = mi * b;
+                        pr.b[i] = b; pr.diag[i] = d; pr.dinv[i] = mi;
+                        pr.x[i] = 0.0f; pr.r[i] = b; pr.z[i] = z; pr.p[i] = z;
+                        v[0] += double(b) * double(z);
+                    }
+                }
             }
         } else {
             for (int i = threadIdx.x; i < n6; i += blockDim.x) {
