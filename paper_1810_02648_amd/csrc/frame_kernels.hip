@@ -310,27 +310,48 @@ struct TriRaster {
     float iz0, iz1, iz2, Af;
 };
 
-__device__ inline bool tri_setup(const ProbDev &pr, int f, TriRaster &s) {
-    const TemplateDev &T = pr.T;
-    const int nv = T.nv, nf = T.nf;
-    const int a = T.tri[f], b = T.tri[nf + f], c = T.tri[2 * size_t(nf) + f];
-    if (!(pr.dvalid[a] && pr.dvalid[b] && pr.dvalid[c])) return false;
-    s.U0 = pr.dfix[a]; s.V0 = pr.dfix[nv + a];
-    s.U1 = pr.dfix[b]; s.V1 = pr.dfix[nv + b];
-    s.U2 = pr.dfix[c]; s.V2 = pr.dfix[nv + c];
+// The face's vertex data (fixed-point coordinates, depths, validity) held in
+// registers, loaded in one round.
+struct TriVerts {
+    int u[3], v[3];
+    float z[3];
+    bool valid;
+};
+
+__device__ inline TriVerts tri_verts(const ProbDev &pr, int a, int b, int c) {
+    const int nv = pr.T.nv;
+    const int id[3] = {a, b, c};
+    TriVerts t;
+    uint8_t ok[3];
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+        ok[q] = pr.dvalid[id[q]];
+        t.u[q] = pr.dfix[id[q]];
+        t.v[q] = pr.dfix[nv + id[q]];
+        t.z[q] = pr.dx[2 * nv + id[q]];
+    }
+    t.valid = (ok[0] != 0) & (ok[1] != 0) & (ok[2] != 0);     // no short circuit: the loads go together
+    return t;
+}
+
+__device__ inline bool tri_setup_from(const ProbDev &pr, const TriVerts &t, TriRaster &s) {
+    if (!t.valid) return false;
+    s.U0 = t.u[0]; s.V0 = t.v[0];
+    s.U1 = t.u[1]; s.V1 = t.v[1];
+    s.U2 = t.u[2]; s.V2 = t.v[2];
     long long A = (s.U1 - s.U0) * (s.V2 - s.V0) - (s.V1 - s.V0) * (s.U2 - s.U0);
     if (A == 0) return false;
-    int ib = b, ic = c;
+    int ib = 1, ic = 2;
     if (A < 0) {
-        long long t;
-        t = s.U1; s.U1 = s.U2; s.U2 = t;
-        t = s.V1; s.V1 = s.V2; s.V2 = t;
-        ib = c; ic = b;
+        long long tt;
+        tt = s.U1; s.U1 = s.U2; s.U2 = tt;
+        tt = s.V1; s.V1 = s.V2; s.V2 = tt;
+        ib = 2; ic = 1;
         A = -A;
     }
-    s.iz0 = 1.0f / pr.dx[2 * nv + a];
-    s.iz1 = 1.0f / pr.dx[2 * nv + ib];
-    s.iz2 = 1.0f / pr.dx[2 * nv + ic];
+    s.iz0 = 1.0f / t.z[0];
+    s.iz1 = 1.0f / (ib == 1 ? t.z[1] : t.z[2]);
+    s.iz2 = 1.0f / (ic == 1 ? t.z[1] : t.z[2]);
     const long long umin = min(s.U0, min(s.U1, s.U2)), umax = max(s.U0, max(s.U1, s.U2));
     const long long vmin = min(s.V0, min(s.V1, s.V2)), vmax = max(s.V0, max(s.V1, s.V2));
     s.i0 = max(0LL, -((-umin) >> 8));
@@ -346,6 +367,12 @@ __device__ inline bool tri_setup(const ProbDev &pr, int f, TriRaster &s) {
     s.o2 = s.dV2 < 0 || (s.dV2 == 0 && s.dU2 > 0);
     s.Af = float(A);
     return s.i0 <= s.i1 && s.j0 <= s.j1;
+}
+
+__device__ inline bool tri_setup(const ProbDev &pr, int f, TriRaster &s) {
+    const TemplateDev &T = pr.T;
+    const int nf = T.nf;
+    return tri_setup_from(pr, tri_verts(pr, T.tri[f], T.tri[nf + f], T.tri[2 * size_t(nf) + f]), s);
 }
 
 // Coverage and inverse depth of pixel (i, j); the buffer keeps the largest bits.
@@ -370,16 +397,24 @@ __device__ inline void raster_body(const ProbDev &pr, int bx) {
     int f = bx * blockDim.x + threadIdx.x;
     if (f >= nf) return;
     int a = T.tri[f], b = T.tri[nf + f], c = T.tri[2 * size_t(nf) + f];
+    // every vertex datum of the face in one round (positions, then the
+    // rasterisation data), before the normal is stored
     float p0[3] = {pr.dx[a], pr.dx[nv + a], pr.dx[2 * nv + a]};
-    float e1[3] = {pr.dx[b] - p0[0], pr.dx[nv + b] - p0[1], pr.dx[2 * nv + b] - p0[2]};
-    float e2[3] = {pr.dx[c] - p0[0], pr.dx[nv + c] - p0[1], pr.dx[2 * nv + c] - p0[2]};
+    float p1[3] = {pr.dx[b], pr.dx[nv + b], pr.dx[2 * nv + b]};
+    float p2[3] = {pr.dx[c], pr.dx[nv + c], pr.dx[2 * nv + c]};
+    const TriVerts tv = tri_verts(pr, a, b, c);
+    // consumed here so that the coordinate loads are not moved behind the
+    // validity test (a round of their own)
+    __asm__ volatile("" ::"v"(tv.u[0]), "v"(tv.u[1]), "v"(tv.u[2]), "v"(tv.v[0]), "v"(tv.v[1]), "v"(tv.v[2]));
+    float e1[3] = {p1[0] - p0[0], p1[1] - p0[1], p1[2] - p0[2]};
+    float e2[3] = {p2[0] - p0[0], p2[1] - p0[1], p2[2] - p0[2]};
     float cr[3];
     cross3(e1, e2, cr);
     pr.fcross[f] = cr[0];
     pr.fcross[nf + f] = cr[1];
     pr.fcross[2 * size_t(nf) + f] = cr[2];
     TriRaster s;
-    if (!tri_setup(pr, f, s)) return;
+    if (!tri_setup_from(pr, tv, s)) return;
     if ((s.i1 - s.i0 + 1) * (s.j1 - s.j0 + 1) > kRasterSmall) {
         pr.bigq[__hip_atomic_fetch_add(pr.counts.g() + 2, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)] = f;
         return;
@@ -419,7 +454,11 @@ __device__ inline void contour_edges_body(const ProbDev &pr, int bx) {
                   pr.dx[2 * nv + v0] * pr.fcross[2 * size_t(nf) + f];
         return s >= 0.0f;
     };
-    bool c = f1 >= 0 ? (back(f0) != back(f1)) : !back(f0);
+    // both faces evaluated (a border edge's missing face as face f0 again), so
+    // that their loads go together
+    __asm__ volatile("" ::"v"(a), "v"(b));     // the endpoints' loads stay with the faces' (not behind the test)
+    const bool b0 = back(f0), b1 = back(f1 >= 0 ? f1 : f0);
+    bool c = f1 >= 0 ? (b0 != b1) : !b0;
     if (c) {
         pr.vcont[a] = 1;
         pr.vcont[b] = 1;
@@ -529,23 +568,38 @@ __global__ void k_decide(const ProbDev *__restrict__ P) {
     if (blockIdx.x * blockDim.x >= unsigned(nv)) return;
     uint8_t code = 0;
     if (i < nv) {
-    if (pr.dvalid[i]) {
-        float u = pr.duv[i], v = pr.duv[nv + i];
-        int px = int(rintf(u)), py = int(rintf(v));
-        if (px >= 0 && px < W && py >= 0 && py < H) {
+    // the vertex's own data, all at once; then its 3x3 depth window (clamped
+    // into the image: a repeated edge pixel changes neither the minimum nor
+    // the test for an uncovered pixel), read whether or not it is needed
+    const bool valid = pr.dvalid[i] != 0;
+    const float u = pr.duv[i], v = pr.duv[nv + i];
+    const float X = pr.dx[i], Y = pr.dx[nv + i], Z = pr.dx[2 * nv + i];
+    const bool cont = pr.vcont[i] != 0;
+    // (an invalid vertex's projection may be non-finite: not converted)
+    const int px = valid ? int(rintf(u)) : 0, py = valid ? int(rintf(v)) : 0;
+    const bool inside = valid && px >= 0 && px < W && py >= 0 && py < H;
+    uint32_t zw[9];
+#pragma unroll
+    for (int dy = 0; dy < 3; ++dy)
+#pragma unroll
+        for (int dx = 0; dx < 3; ++dx) {
+            const int y = min(max(py + dy - 1, 0), H - 1), x = min(max(px + dx - 1, 0), W - 1);
+            zw[3 * dy + dx] = pr.zbuf[size_t(y) * W + x];
+        }
+    if (inside) {
+        {
             uint32_t m = 0xffffffffu;
             bool open = false;      // an uncovered pixel in the window: the vertex is on the outline
-            for (int y = max(py - 1, 0); y <= min(py + 1, H - 1); ++y)
-                for (int x = max(px - 1, 0); x <= min(px + 1, W - 1); ++x) {
-                    uint32_t z = pr.zbuf[size_t(y) * W + x];
-                    if (z != 0u && z < m) m = z;
-                    open = open || z == 0u;
-                }
-            float X = pr.dx[i], Y = pr.dx[nv + i], Z = pr.dx[2 * nv + i];
+#pragma unroll
+            for (int q = 0; q < 9; ++q) {
+                const uint32_t z = zw[q];
+                if (z != 0u && z < m) m = z;
+                open = open || z == 0u;
+            }
             bool vis = m == 0xffffffffu ? true : (Z <= (1.0f / __uint_as_float(m)) + 0.05f);
             if (vis) {
                 code |= 1;
-                if (pr.vcont[i] && (open || !pr.outline_only)) {
+                if (cont && (open || !pr.outline_only)) {
                     code |= 2;
                     float n[3] = {0.0f, 0.0f, 0.0f};
                     for (int q = T.vf_beg[i]; q < T.vf_beg[i + 1]; ++q) {
@@ -560,8 +614,8 @@ __global__ void k_decide(const ProbDev *__restrict__ P) {
                     float b = (n[1] * Z - n[2] * Y) * pr.fy;
                     float s = a * (-gx) + b * (-gy);
                     size_t pix = size_t(py) * W + px;
-                    bool inside = pr.mask[pix] != 0 && pr.dt[pix] >= 1.5f;
-                    if (inside && s < 0.0f) code = pr.exclude_case2 ? uint8_t(code & ~2) : uint8_t(code | 4);
+                    const bool in_mask = pr.mask[pix] != 0 && pr.dt[pix] >= 1.5f;
+                    if (in_mask && s < 0.0f) code = pr.exclude_case2 ? uint8_t(code & ~2) : uint8_t(code | 4);
                     if (code & 2) atomicAdd(cnt + 1, 1);
                 }
                 atomicAdd(cnt, 1);
@@ -571,9 +625,9 @@ __global__ void k_decide(const ProbDev *__restrict__ P) {
     if (pr.w_vel > 0.0f) code |= 8;
     pr.vflags[i] = code;
     int p = T.plan_pos[i];
-    pr.pva[p] = pr.dx[i];
-    pr.pva[nv + p] = pr.dx[nv + i];
-    pr.pva[2 * nv + p] = pr.dx[2 * nv + i];
+    pr.pva[p] = X;
+    pr.pva[nv + p] = Y;
+    pr.pva[2 * nv + p] = Z;
     pr.vcode[p] = code;
     pr.px[p] = pr.xyz[i];
     pr.px[nv + p] = pr.xyz[nv + i];
