@@ -322,6 +322,63 @@ __device__ inline void log_so3(const float R[9], float w[3]) {
 // R_k and t_k (0..5), their change since frame t-2 (6..11, zero without it),
 // sign(b) log(1 + |b|) of the right-hand side (12..17), log(1 + diag)
 // (18..23), node position minus the mean node position (24..26), zeros.
+// A thread's first node has all of its loads issued before the block forms
+// the mean position (strided partial sums, then a fixed-order tree), so the
+// two overlap; further nodes (more nodes than threads) load afterwards.
+struct WsNodeIn {
+    float R[9], t[3], R2[9], t2[3], b[6], d[6], g[3];
+};
+
+__device__ inline void ws_node_load(const ProbDev &pr, const CAP_GLOBAL float *__restrict__ prev2, int nn, int k,
+                                    WsNodeIn &in) {
+#pragma unroll
+    for (int q = 0; q < 9; ++q) in.R[q] = pr.state[size_t(q) * nn + k];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) in.t[a] = pr.state[size_t(9 + a) * nn + k];
+    if (prev2) {
+#pragma unroll
+        for (int q = 0; q < 9; ++q) in.R2[q] = prev2[size_t(q) * nn + k];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) in.t2[a] = prev2[size_t(9 + a) * nn + k];
+    }
+#pragma unroll
+    for (int c = 0; c < 6; ++c) {
+        in.b[c] = pr.b[size_t(c) * nn + k];
+        in.d[c] = pr.diag[size_t(c) * nn + k];
+    }
+#pragma unroll
+    for (int a = 0; a < 3; ++a) in.g[a] = pr.gpos[size_t(a) * nn + k];
+}
+
+__device__ inline void ws_node_features(const WsNodeIn &in, bool has_prev2, const float mean[3], float *x) {
+    float w[3];
+    log_so3(in.R, w);
+    for (int a = 0; a < 3; ++a) {
+        x[a] = w[a];
+        x[3 + a] = in.t[a];
+    }
+    if (has_prev2) {
+        float D[9], dw[3];
+        for (int i = 0; i < 3; ++i)
+            for (int j = 0; j < 3; ++j)
+                D[3 * i + j] = (in.R[3 * i] * in.R2[3 * j] + in.R[3 * i + 1] * in.R2[3 * j + 1]) +
+                               in.R[3 * i + 2] * in.R2[3 * j + 2];
+        log_so3(D, dw);
+        for (int a = 0; a < 3; ++a) {
+            x[6 + a] = dw[a];
+            x[9 + a] = in.t[a] - in.t2[a];
+        }
+    } else {
+        for (int a = 0; a < 6; ++a) x[6 + a] = 0.0f;
+    }
+    for (int c = 0; c < 6; ++c) {
+        x[12 + c] = copysignf(log1pf(fabsf(in.b[c])), in.b[c]);
+        x[18 + c] = log1pf(fmaxf(in.d[c], 0.0f));
+    }
+    for (int a = 0; a < 3; ++a) x[24 + a] = in.g[a] - mean[a];
+    for (int a = 27; a < 32; ++a) x[a] = 0.0f;
+}
+
 __global__ __launch_bounds__(256) void k_ws_features(const ProbDev *__restrict__ P, float *__restrict__ X) {
     __shared__ float part[3][256];
     __shared__ float mean[3];
@@ -329,6 +386,9 @@ __global__ __launch_bounds__(256) void k_ws_features(const ProbDev *__restrict__
     const TemplateDev &T = pr.T;
     const CAP_GLOBAL float *__restrict__ prev2 = pr.prev2.g();
     const int nn = T.nn;
+    const int k0 = blockIdx.x * blockDim.x + threadIdx.x, stride = gridDim.x * blockDim.x;
+    WsNodeIn first;
+    if (k0 < nn) ws_node_load(pr, prev2, nn, k0, first);
     // mean node position: strided partial sums, then a fixed-order tree over the block
     {
         float s[3] = {0.0f, 0.0f, 0.0f};
@@ -344,36 +404,12 @@ __global__ __launch_bounds__(256) void k_ws_features(const ProbDev *__restrict__
         if (threadIdx.x < 3) mean[threadIdx.x] = part[threadIdx.x][0] / float(nn);
         __syncthreads();
     }
-    for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < nn; k += gridDim.x * blockDim.x) {
-        float *x = X + size_t(k) * 32;
-        float R[9], w[3];
-        for (int q = 0; q < 9; ++q) R[q] = pr.state[size_t(q) * nn + k];
-        log_so3(R, w);
-        for (int a = 0; a < 3; ++a) {
-            x[a] = w[a];
-            x[3 + a] = pr.state[size_t(9 + a) * nn + k];
-        }
-        if (prev2) {
-            float R2[9], D[9], dw[3];
-            for (int q = 0; q < 9; ++q) R2[q] = prev2[size_t(q) * nn + k];
-            for (int i = 0; i < 3; ++i)
-                for (int j = 0; j < 3; ++j)
-                    D[3 * i + j] = (R[3 * i] * R2[3 * j] + R[3 * i + 1] * R2[3 * j + 1]) + R[3 * i + 2] * R2[3 * j + 2];
-            log_so3(D, dw);
-            for (int a = 0; a < 3; ++a) {
-                x[6 + a] = dw[a];
-                x[9 + a] = pr.state[size_t(9 + a) * nn + k] - prev2[size_t(9 + a) * nn + k];
-            }
-        } else {
-            for (int a = 0; a < 6; ++a) x[6 + a] = 0.0f;
-        }
-        for (int c = 0; c < 6; ++c) {
-            const float b = pr.b[size_t(c) * nn + k], d = pr.diag[size_t(c) * nn + k];
-            x[12 + c] = copysignf(log1pf(fabsf(b)), b);
-            x[18 + c] = log1pf(fmaxf(d, 0.0f));
-        }
-        for (int a = 0; a < 3; ++a) x[24 + a] = pr.gpos[size_t(a) * nn + k] - mean[a];
-        for (int a = 27; a < 32; ++a) x[a] = 0.0f;
+    const float m[3] = {mean[0], mean[1], mean[2]};
+    if (k0 < nn) ws_node_features(first, prev2 != nullptr, m, X + size_t(k0) * 32);
+    for (int k = k0 + stride; k < nn; k += stride) {
+        WsNodeIn in;
+        ws_node_load(pr, prev2, nn, k, in);
+        ws_node_features(in, prev2 != nullptr, m, X + size_t(k) * 32);
     }
 }
 
