@@ -32,7 +32,7 @@ __global__ void k_prep_rows(const ProbDev *P, int nb_rows);
 __global__ void k_linearize(const ProbDev *P, const TileDesc *D, int mode);
 template <int kSplit>
 __global__ void k_apply(const ProbDev *P, const TileDesc *D);
-__global__ void k_node_init(const ProbDev *P, int gn, int energy_only, int check_target);
+__global__ void k_node_init(const ProbDev *P, int gn, int energy_only, int check_target, int slot_prev, int gn_iters);
 __global__ void k_node_gather(const ProbDev *P);
 __global__ void k_node_pcg(const ProbDev *P, int last, int update_only);
 __global__ void k_pcg_split_a(const ProbDev *P);
@@ -53,8 +53,8 @@ __global__ void k_ws_layer1(const float *X, int nn, const float *mu, const float
                             const float *bias, uint16_t *Xb, float *z, uint16_t *cat);
 template <int NT>
 __global__ void k_ws_layer_mp(uint16_t *cat, const float *zp, const int *edge_dst, int nn, const uint16_t *W,
-                              const float *bias, int N, float *z, uint16_t *cat_next, float *xdelta);
-__global__ void k_ws_select(const ProbDev *P, int slot_prev, int slot_pred, int gn_iters);
+                              const float *bias, int N, float *z, uint16_t *cat_next, float *xdelta,
+                              const ProbDev *upd);
 __global__ void k_ws_target(const float *prev, const float *next, int nn, float *target);
 __global__ void k_ws_scaling(const float *X, long long rows, float *mu, float *sd);
 
@@ -418,14 +418,15 @@ void launch_apply(Run &R) {
     }
 }
 
-void launch_linearize(Run &R, int gn, int energy_only, int check_target = 0) {
+// check_target: see k_node_init (with bit 2, slot_prev and gn_iters of the selection).
+void launch_linearize(Run &R, int gn, int energy_only, int check_target = 0, int slot_prev = 0, int gn_iters = 0) {
     timed(R, K_LIN, [&] {
         hipLaunchKernelGGL(k_linearize, dim3(unsigned(R.grid_tiles)), dim3(kTileThreads), R.lds_lin, R.s, R.dprobs, R.tiles,
                            energy_only);
     });
     timed(R, K_NODE_INIT, [&] {
         hipLaunchKernelGGL(k_node_init, dim3(R.n), dim3(kInitThreads), 0, R.s, R.dprobs, gn, energy_only,
-                           check_target);
+                           check_target, slot_prev, gn_iters);
     });
 }
 
@@ -568,15 +569,19 @@ void gemm(hipStream_t s, const uint16_t *A, long long sai, long long sak, const 
 // Forward pass on raw features X (device, [nn][32]) -> net->y [nn][6].
 // Network forward: three fused layer kernels (one 8-wave workgroup per 16 nodes); with
 // xdelta the last one also writes the scaled update in node-major layout.
-void ws_forward(capture_warmstart *net, const TemplateDev &T, const float *X, hipStream_t s, float *xdelta = nullptr) {
+// The network's forward pass; with xdelta, the prediction is also written as
+// a PCG solution ([6][nn]), and with upd (the problem on the device) applied
+// to that problem's node state by the last layer.
+void ws_forward(capture_warmstart *net, const TemplateDev &T, const float *X, hipStream_t s, float *xdelta = nullptr,
+                const ProbDev *upd = nullptr) {
     const int nn = T.nn;
     const dim3 g(unsigned((nn + 15) / 16));
     hipLaunchKernelGGL(k_ws_layer1, g, dim3(512), 0, s, X, nn, net->mu, net->sd, net->wb + kOffW1, net->w + kOffB1,
                        net->Xb, net->z1, net->c1);
     hipLaunchKernelGGL(k_ws_layer_mp<8>, g, dim3(512), 0, s, net->c1, net->z1, T.edge_dst, nn, net->wb + kOffW2,
-                       net->w + kOffB2, 128, net->z2, net->c2, (float *)nullptr);
+                       net->w + kOffB2, 128, net->z2, net->c2, (float *)nullptr, (const ProbDev *)nullptr);
     hipLaunchKernelGGL(k_ws_layer_mp<1>, g, dim3(512), 0, s, net->c2, net->z2, T.edge_dst, nn, net->wb + kOffW3,
-                       net->w + kOffB3, 6, net->y, (uint16_t *)nullptr, xdelta);
+                       net->w + kOffB3, 6, net->y, (uint16_t *)nullptr, xdelta, upd);
 }
 
 // Backward pass after ws_forward, with targets in net->tgt; gradients into net->g.
@@ -1016,18 +1021,16 @@ int warm_sequence(Run &R, const capture_nonrigid_params *params, capture_warmsta
     timed(R, K_WS_FEAT, [&] {
         hipLaunchKernelGGL(k_ws_features, dim3(blocks(pr.T.nn, 256), 1), dim3(256), 0, R.s, R.dprobs, net->X);
     });
-    timed(R, K_WS_MLP, [&] {
-        ws_forward(net, pr.T, net->X, R.s, pr.x);
+    timed(R, K_WS_MLP, [&] {      // the prediction, applied to the node state by the last layer
+        ws_forward(net, pr.T, net->X, R.s, pr.x, R.dprobs);
     });
-    hipLaunchKernelGGL(k_node_pcg, dim3(1), dim3(kNodeThreads), 0, R.s, R.dprobs, 0, 1);
-    launch_linearize(R, 0, 0, 1);
-    hipLaunchKernelGGL(k_ws_select, dim3(1), dim3(256), 0, R.s, R.dprobs, prev_slot, 0, params->gn_iters);
+    launch_linearize(R, 0, 0, 1 | 4, prev_slot, params->gn_iters);      // energy test and selection
     timed(R, K_LIN, [&] {
         hipLaunchKernelGGL(k_linearize, dim3(unsigned(R.grid_tiles)), dim3(kTileThreads), R.lds_lin, R.s, R.dprobs,
                            R.tiles, 2);
     });
     timed(R, K_NODE_INIT, [&] {
-        hipLaunchKernelGGL(k_node_init, dim3(R.n), dim3(kInitThreads), 0, R.s, R.dprobs, 0, 0, 3);
+        hipLaunchKernelGGL(k_node_init, dim3(R.n), dim3(kInitThreads), 0, R.s, R.dprobs, 0, 0, 3, 0, 0);
     });
     if (!split) return launch_solve(R, params, 1, true);
     launch_steps(R, params, 1, true, 0, 1);

@@ -126,6 +126,42 @@ __device__ inline void store_start_vertex(const ProbDev &pr, int i, float X, flo
     pr.vcont[i] = 0;
 }
 
+// Node k's update by (dw, dt): R <- Exp(dw) R (Rodrigues, float32), t <- t + dt.
+__device__ inline void node_update_from(const ProbDev &pr, int k, const float w[3], const float tau[3]) {
+    const int nn = pr.T.nn;
+    const float th2 = (w[0] * w[0] + w[1] * w[1]) + w[2] * w[2];
+    float A, B;
+    if (th2 < 1e-8f) {
+        A = 1.0f - th2 / 6.0f;
+        B = 0.5f - th2 / 24.0f;
+    } else {
+        const float th = sqrtf(th2);
+        A = sinf(th) / th;
+        B = (1.0f - cosf(th)) / th2;
+    }
+    float K[9] = {0.0f, -w[2], w[1], w[2], 0.0f, -w[0], -w[1], w[0], 0.0f};
+    float E[9];
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) {
+            float kk = (K[3 * i] * K[j] + K[3 * i + 1] * K[3 + j]) + K[3 * i + 2] * K[6 + j];
+            E[3 * i + j] = (i == j ? 1.0f : 0.0f) + A * K[3 * i + j] + B * kk;
+        }
+    float R[9];
+    for (int q = 0; q < 9; ++q) R[q] = pr.state[size_t(q) * nn + k];
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j)
+            pr.state[size_t(3 * i + j) * nn + k] = (E[3 * i] * R[j] + E[3 * i + 1] * R[3 + j]) + E[3 * i + 2] * R[6 + j];
+    for (int a = 0; a < 3; ++a) pr.state[size_t(9 + a) * nn + k] += tau[a];
+}
+
+// The same with (dw, dt) read from the PCG solution x ([6][nn]).
+__device__ inline void node_update(const ProbDev &pr, int k) {
+    const int nn = pr.T.nn;
+    float w[3], tau[3];
+    for (int a = 0; a < 3; ++a) { w[a] = pr.x[size_t(a) * nn + k]; tau[a] = pr.x[size_t(3 + a) * nn + k]; }
+    node_update_from(pr, k, w, tau);
+}
+
 // Deterministic block-wide sum of a double: fixed butterfly inside each wave,
 // then the wave sums in wave order.  `sh` holds NT/64 doubles.
 template <int NT>

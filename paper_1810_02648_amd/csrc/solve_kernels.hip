@@ -568,8 +568,17 @@ __device__ inline float gather_node(const TemplateDev &T, gptr<const float> part
 // (x = 0, r = b, z = M^-1 r, p = z), r.z, and the energy of GN step `gn`.
 // One thread per (component, node) item; every load is issued before the
 // stop tests, and r.z and the energy terms share one block reduction.
-__global__ __launch_bounds__(kInitThreads) void k_node_init(const ProbDev *__restrict__ P, int gn, int energy_only, int check_target) {
+// check_target bit 0: stop when the energy reaches the target; bit 1: the
+// conditional pass (see k_linearize); bit 2: the learned start's selection
+// after the linearisation at the prediction: keep the prediction only if
+// its energy is below the energy in scal slot `slot_prev` (that of the
+// previous frame's state), otherwise undo any stop (the schedule is again
+// gn_iters steps) and restore the start state from state0; scal[4] and
+// scal[6] receive the two energies, scal[5] the rejection.
+__global__ __launch_bounds__(kInitThreads) void k_node_init(const ProbDev *__restrict__ P, int gn, int energy_only,
+                                                          int check_target, int slot_prev, int gn_iters) {
     __shared__ double red[kInitThreads / 64][1 + kTerms];
+    __shared__ int reject;
     const ProbDev &pr = P[blockIdx.x];
     const TemplateDev &T = pr.T;
     const int nn = T.nn, n6 = 6 * nn;
@@ -588,7 +597,9 @@ __global__ __launch_bounds__(kInitThreads) void k_node_init(const ProbDev *__res
         for (int j = 0; j < kInitItems; ++j)
             if (int(threadIdx.x) + j * kInitThreads >= n6) pb[j] = pe[j] = 0;
     }
-    if (pr.scal[2] != 0.0) return;   // stopped at the target energy
+    // stopped at the target energy (never so at the selection, which follows
+    // the frame set-up's cleared flags)
+    if (pr.scal[2] != 0.0 && !(check_target & 4)) return;
     if ((check_target & 2) && pr.scal[5] == 0.0) return;   // conditional pass (see k_linearize)
     if (!energy_only) {
         if (regs) {
@@ -649,6 +660,24 @@ __global__ __launch_bounds__(kInitThreads) void k_node_init(const ProbDev *__res
             }
         }
         for (int q = 0; q < kTerms; ++q) pr.scal[8 + kTerms * gn + q] = v[1 + q];
+        if (check_target & 4) {
+            const CAP_GLOBAL double *e0 = pr.scal.g() + 8 + kTerms * slot_prev;
+            const double E0 = e0[0] + e0[1] + e0[3] + e0[4], E1 = v[1] + v[2] + v[4] + v[5];
+            reject = !(E1 < E0);
+            pr.scal[4] = E1;
+            pr.scal[5] = reject ? 1.0 : 0.0;
+            pr.scal[6] = E0;
+            if (reject) {      // the linearisation (and any stop) at the prediction no longer applies
+                pr.scal[1] = 0.0;
+                pr.scal[2] = 0.0;
+                pr.scal[3] = double(gn_iters);
+            }
+        }
+    }
+    if (check_target & 4) {
+        __syncthreads();
+        if (reject)
+            for (int i = threadIdx.x; i < 12 * T.nn; i += blockDim.x) pr.state[i] = pr.state0[i];
     }
 }
 
@@ -661,36 +690,6 @@ __global__ __launch_bounds__(kNodeThreads) void k_node_gather(const ProbDev *__r
         const int c = i / nn, k = i - c * nn;
         pr.Ap[i] = gather_node(T, pr.partial, T.nslots, k, c);
     }
-}
-
-// R <- Exp(dw) R (Rodrigues, float32), t <- t + dt.
-__device__ inline void node_update(const ProbDev &pr, int k) {
-    const int nn = pr.T.nn;
-    float w[3], tau[3];
-    for (int a = 0; a < 3; ++a) { w[a] = pr.x[size_t(a) * nn + k]; tau[a] = pr.x[size_t(3 + a) * nn + k]; }
-    const float th2 = (w[0] * w[0] + w[1] * w[1]) + w[2] * w[2];
-    float A, B;
-    if (th2 < 1e-8f) {
-        A = 1.0f - th2 / 6.0f;
-        B = 0.5f - th2 / 24.0f;
-    } else {
-        const float th = sqrtf(th2);
-        A = sinf(th) / th;
-        B = (1.0f - cosf(th)) / th2;
-    }
-    float K[9] = {0.0f, -w[2], w[1], w[2], 0.0f, -w[0], -w[1], w[0], 0.0f};
-    float E[9];
-    for (int i = 0; i < 3; ++i)
-        for (int j = 0; j < 3; ++j) {
-            float kk = (K[3 * i] * K[j] + K[3 * i + 1] * K[3 + j]) + K[3 * i + 2] * K[6 + j];
-            E[3 * i + j] = (i == j ? 1.0f : 0.0f) + A * K[3 * i + j] + B * kk;
-        }
-    float R[9];
-    for (int q = 0; q < 9; ++q) R[q] = pr.state[size_t(q) * nn + k];
-    for (int i = 0; i < 3; ++i)
-        for (int j = 0; j < 3; ++j)
-            pr.state[size_t(3 * i + j) * nn + k] = (E[3 * i] * R[j] + E[3 * i + 1] * R[3 + j]) + E[3 * i + 2] * R[6 + j];
-    for (int a = 0; a < 3; ++a) pr.state[size_t(9 + a) * nn + k] += tau[a];
 }
 
 // One PCG iteration after k_apply: A p, alpha, x/r/z updates, beta, p.

@@ -154,7 +154,9 @@ __global__ __launch_bounds__(kLayerThreads) void k_ws_layer1(const float *__rest
 // previous layer); this kernel writes its second half (the neighbour means).
 // cat_next (optional): bf16 ReLU copy of this layer's output into the next
 // layer's first half.  xdelta (optional): the warm-start update
-// x[c][k] = y[k][c] * (0.05 rad, 0.01 m scale) in node-major layout.
+// x[c][k] = y[k][c] * (0.05 rad, 0.01 m scale) in node-major layout; with
+// `upd` as well (N = 6), the block then applies that update to its nodes'
+// state (the node update of a PCG solution, from the values in registers).
 template <int NT>
 __global__ __launch_bounds__(kLayerThreads) void k_ws_layer_mp(uint16_t *__restrict__ cat,
                                                                const float *__restrict__ zp,
@@ -162,10 +164,11 @@ __global__ __launch_bounds__(kLayerThreads) void k_ws_layer_mp(uint16_t *__restr
                                                                const uint16_t *__restrict__ W,
                                                                const float *__restrict__ bias, int N,
                                                                float *__restrict__ z, uint16_t *__restrict__ cat_next,
-                                                               float *__restrict__ xdelta) {
+                                                               float *__restrict__ xdelta, const ProbDev *__restrict__ upd) {
     static_assert(NT <= kLayerThreads / 64, "at most one output tile per wave");
     __shared__ uint16_t As[16][256 + 8];
     __shared__ int nbs[16][8];
+    __shared__ float xs[16][6];     // the block's updates, for `upd`
     const int i0 = blockIdx.x * 16;
     const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63, r = lane & 15;
     // the neighbour list (every thread loads an entry, the first 128 store
@@ -226,16 +229,25 @@ __global__ __launch_bounds__(kLayerThreads) void k_ws_layer_mp(uint16_t *__restr
                 const float v = acc[q] + bias[j];
                 z[size_t(i) * N + j] = v;
                 if (cat_next) cat_next[size_t(i) * 256 + j] = f2bf(v > 0.0f ? v : 0.0f);
-                if (xdelta) xdelta[size_t(j) * nn + i] = v * (j < 3 ? 0.05f : 0.01f);
+                if (xdelta) {
+                    const float u = v * (j < 3 ? 0.05f : 0.01f);
+                    xdelta[size_t(j) * nn + i] = u;
+                    if (upd) xs[i - i0][j] = u;
+                }
             }
         }
+    }
+    if (xdelta && upd) {        // (uniform)
+        lds_barrier();
+        const int k = i0 + int(threadIdx.x);
+        if (threadIdx.x < 16 && k < nn) node_update_from(*upd, k, xs[threadIdx.x], xs[threadIdx.x] + 3);
     }
 }
 
 template __global__ void k_ws_layer_mp<8>(uint16_t *, const float *, const int *, int, const uint16_t *, const float *,
-                                          int, float *, uint16_t *, float *);
+                                          int, float *, uint16_t *, float *, const ProbDev *);
 template __global__ void k_ws_layer_mp<1>(uint16_t *, const float *, const int *, int, const uint16_t *, const float *,
-                                          int, float *, uint16_t *, float *);
+                                          int, float *, uint16_t *, float *, const ProbDev *);
 
 // ---------------------------------------------------------------- message passing (backward)
 // Backward through [h; mean(h)] and the ReLU:
@@ -413,31 +425,6 @@ __global__ __launch_bounds__(256) void k_ws_features(const ProbDev *__restrict__
     }
 }
 
-
-// Keep the predicted start only if it lowers the energy; otherwise restore
-// the previous frame's state.  scal[4] = predicted-start energy, scal[5] = 1
-// when the prediction was rejected.
-__global__ void k_ws_select(const ProbDev *__restrict__ P, int slot_prev, int slot_pred, int gn_iters) {
-    __shared__ int reject;
-    const ProbDev &pr = P[blockIdx.x];
-    const int nn = pr.T.nn;
-    if (threadIdx.x == 0) {
-        const CAP_GLOBAL double *e0 = pr.scal.g() + 8 + kTerms * slot_prev, *e1 = pr.scal.g() + 8 + kTerms * slot_pred;
-        const double E0 = e0[0] + e0[1] + e0[3] + e0[4], E1 = e1[0] + e1[1] + e1[3] + e1[4];
-        reject = !(E1 < E0);
-        pr.scal[4] = E1;
-        pr.scal[5] = reject ? 1.0 : 0.0;
-        pr.scal[6] = E0;
-        if (reject) {      // the linearisation (and any stop) at the prediction no longer applies
-            pr.scal[1] = 0.0;
-            pr.scal[2] = 0.0;
-            pr.scal[3] = double(gn_iters);
-        }
-    }
-    __syncthreads();
-    if (reject)
-        for (int i = threadIdx.x; i < 12 * nn; i += blockDim.x) pr.state[i] = pr.state0[i];
-}
 
 // Training target: per node (dw, dt) with R_next = Exp(dw) R_prev and
 // t_next = t_prev + dt, divided by (0.05 rad, 0.01 m); layout [nn][6].
