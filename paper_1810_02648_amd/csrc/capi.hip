@@ -14,15 +14,7 @@ namespace cap {
 
 // kernels defined in the other translation units
 __global__ void k_fill_u32(uint32_t *p, size_t n, uint32_t v);
-__global__ void k_contour(const ProbDev *P);
-__global__ void k_dt_seg(const ProbDev *P);
-__global__ void k_dt_scan(const ProbDev *P);
 __global__ void k_dt_scan_cols(const ProbDev *P);
-__global__ void k_dt_cols(const ProbDev *P);
-__global__ void k_dt_rows(const ProbDev *P);
-__global__ void k_raster(const ProbDev *P);
-__global__ void k_raster_big(const ProbDev *P);
-__global__ void k_contour_edges(const ProbDev *P);
 __global__ void k_decide(const ProbDev *P);
 __global__ void k_prep_image(const ProbDev *P, int nb_init, int nb_px, int gn_iters, float w0, float w1);
 __global__ void k_prep_geom(const ProbDev *P, int nb_v);
@@ -695,7 +687,7 @@ int capture_batch_solve(capture_ctx *ctx, int32_t n, const capture_frame *frames
         });
         if (rc) return rc;
     } else {
-        if ((rc = launch_frame(R, params->gn_iters))) return rc;      // keeps the start states (k_frame_init)
+        if ((rc = launch_frame(R, params->gn_iters))) return rc;      // keeps the start states (frame set-up)
         if ((rc = launch_solve(R, params))) return rc;
     }
     rc = collect(R, params->gn_iters, reports);
