@@ -483,38 +483,75 @@ __global__ __launch_bounds__(kStepThreads) void k_pose_step(const PoseDev *__res
         __syncthreads();
     }
     // elimination: for pivot k, rows i > k of the upper triangle and the
-    // right-hand side column: A[i][j] -= (A[k][i] / A[k][k]) A[k][j], j >= i
-    // (thread t owns column k + 1 + (t % 128) of every kRowGroups-th trailing row)
+    // right-hand side column: A[i][j] -= (A[k][i] / A[k][k]) A[k][j], j >= i.
+    // Pivots go in pairs (k, k + 1) with one barrier per pair: every thread
+    // forms the values of row k + 1 after pivot k that it needs itself (the
+    // same operations as that row's own update), applies pivot k and then
+    // pivot k + 1 to its entries of rows i > k + 1; the owners of row k + 1's
+    // columns store that row after the next barrier (the pair still reads its
+    // old values; no later pair reads it).  The operations and their order per
+    // entry are those of one pivot at a time.  Thread t owns column
+    // k + 1 + (t % 128) of every kRowGroups-th row from k + 2 on.
     constexpr int kRowGroups = kStepThreads / 128, kRowsPer = (kMaxPoseUnknowns + kRowGroups - 1) / kRowGroups;
     const int tc = t & 127, tr = t >> 7;
-    for (int k = 0; k < nu; ++k) {
+    int row1_at = -1;          // LDS index and value of the thread's pending row k + 1 entry
+    double row1 = 0.0;
+    for (int k = 0; k < nu; k += 2) {
+        if (row1_at >= 0) A[row1_at] = row1;
+        row1_at = -1;
         const double akk = A[k * lda + k];
         if (!(akk > 0.0) || !isfinite(akk)) {      // every thread reads the same pivot
             if (t == 0) bad = 1;
             break;
         }
         const double inv = 1.0 / akk;
-        if (t == 0) pn[k] = inv;                  // reciprocal pivots for the back substitution
+        const bool two = k + 1 < nu;
+        // row k + 1 after pivot k: A1[k+1][c] = A[k+1][c] - (A[k][k+1] / A[k][k]) A[k][c]
+        const double f1 = two ? A[k * lda + k + 1] * inv : 0.0;
+        double inv1 = 0.0;
+        if (two) {
+            const double a1 = A[(k + 1) * lda + k + 1] - f1 * A[k * lda + k + 1];
+            if (!(a1 > 0.0) || !isfinite(a1)) {
+                if (t == 0) bad = 1;
+                break;
+            }
+            inv1 = 1.0 / a1;
+        }
+        if (t == 0) {                             // reciprocal pivots for the back substitution
+            pn[k] = inv;
+            if (two) pn[k + 1] = inv1;
+        }
         const int j = k + 1 + tc;
         if (j <= nu) {
             const double akj = A[k * lda + j];
+            const double a1j = two ? A[(k + 1) * lda + j] - f1 * akj : 0.0;     // A1[k+1][j]
             const int iend = min(j, nu - 1);
             // all of the thread's rows at once: their loads in flight together, then the stores
-            double aki[kRowsPer], aij[kRowsPer];
+            double aki[kRowsPer], a1i[kRowsPer], aij[kRowsPer];
 #pragma unroll
             for (int u = 0; u < kRowsPer; ++u) {
-                const int i = k + 1 + tr + u * kRowGroups;
+                const int i = k + 2 + tr + u * kRowGroups;
                 aki[u] = i <= iend ? A[k * lda + i] : 0.0;
+                a1i[u] = i <= iend ? A[(k + 1) * lda + i] : 0.0;
                 aij[u] = i <= iend ? A[i * lda + j] : 0.0;
             }
 #pragma unroll
             for (int u = 0; u < kRowsPer; ++u) {
-                const int i = k + 1 + tr + u * kRowGroups;
-                if (i <= iend) A[i * lda + j] = aij[u] - (aki[u] * inv) * akj;
+                const int i = k + 2 + tr + u * kRowGroups;
+                if (i <= iend) {
+                    const double b = aij[u] - (aki[u] * inv) * akj;                 // pivot k
+                    const double a1ki = a1i[u] - f1 * aki[u];                       // A1[k+1][i]
+                    A[i * lda + j] = b - (a1ki * inv1) * a1j;                       // pivot k + 1
+                }
+            }
+            if (two && tr == 0) {       // row k + 1 after pivot k, stored after the barrier
+                row1_at = (k + 1) * lda + j;
+                row1 = a1j;
             }
         }
         __syncthreads();
     }
+    if (row1_at >= 0) A[row1_at] = row1;       // (none pending after a bad pivot)
     __syncthreads();
     if (bad) {
         for (int e = t; e < nu; e += kStepThreads) P.pose[e] = P.pose0[e];
