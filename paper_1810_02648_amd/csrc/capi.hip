@@ -511,15 +511,25 @@ int launch_graph(Run &R, const std::string &key, F &&sequence) {
     return CAPTURE_OK;
 }
 
-int collect(Run &R, int gn_iters, capture_report *reports, const double **scal_host = nullptr) {
+// Every problem's scalars and counters, copied to pinned host memory in one
+// read-back (waits for the stream) into *host.
+int read_back(Run &R, const uint8_t **host) {
     const uint8_t *blk = reinterpret_cast<const uint8_t *>(R.probs[0].scal.ptr);
     const size_t off_counts = reinterpret_cast<const uint8_t *>(R.probs[0].counts.ptr) - blk;
     const size_t bytes = off_counts + sizeof(int) * 3 * R.n;
-    uint8_t *host = static_cast<uint8_t *>(staging(R.ctx, bytes));
-    if (!host) return fail(CAPTURE_ENOMEM, "pinned staging allocation failed");
-    CAP_HIP(hipMemcpyAsync(host, blk, bytes, hipMemcpyDeviceToHost, R.s));
+    uint8_t *h = static_cast<uint8_t *>(staging(R.ctx, bytes));
+    if (!h) return fail(CAPTURE_ENOMEM, "pinned staging allocation failed");
+    CAP_HIP(hipMemcpyAsync(h, blk, bytes, hipMemcpyDeviceToHost, R.s));
     CAP_HIP(hipStreamSynchronize(R.s));
-    settle(R);
+    *host = h;
+    return CAPTURE_OK;
+}
+
+// The reports from a read-back block.
+int reports_from(Run &R, const uint8_t *host, int gn_iters, capture_report *reports,
+                 const double **scal_host = nullptr) {
+    const uint8_t *blk = reinterpret_cast<const uint8_t *>(R.probs[0].scal.ptr);
+    const size_t off_counts = reinterpret_cast<const uint8_t *>(R.probs[0].counts.ptr) - blk;
     const double *scal = reinterpret_cast<const double *>(host);
     if (scal_host) *scal_host = scal;
     const int *counts = reinterpret_cast<const int *>(host + off_counts);
@@ -542,6 +552,14 @@ int collect(Run &R, int gn_iters, capture_report *reports, const double **scal_h
         if (rep.status) status = rep.status;
     }
     return status;
+}
+
+int collect(Run &R, int gn_iters, capture_report *reports, const double **scal_host = nullptr) {
+    const uint8_t *host = nullptr;
+    const int rc = read_back(R, &host);
+    if (rc) return rc;
+    settle(R);
+    return reports_from(R, host, gn_iters, reports, scal_host);
 }
 
 
@@ -1066,19 +1084,22 @@ int capture_nonrigid_solve_warm(capture_ctx *ctx, const capture_frame *frame, co
     auto first = [&](Run &C) { return warm_sequence(C, params, net, split); };
     rc = graph ? launch_graph(R, key, first) : first(R);
     if (rc) return rc;
-    if (split) {
-        double *flag = static_cast<double *>(staging(ctx, sizeof(double)));
-        if (!flag) return fail(CAPTURE_ENOMEM, "pinned staging allocation failed");
-        CAP_HIP(hipMemcpyAsync(flag, pr.scal + 2, sizeof(double), hipMemcpyDeviceToHost, R.s));
-        CAP_HIP(hipStreamSynchronize(R.s));
-        if (*flag == 0.0) {
+    const double *sc = nullptr;
+    bool done = false;
+    if (split) {      // the read-back of the stop flag brings the whole report along
+        const uint8_t *host = nullptr;
+        if ((rc = read_back(R, &host))) return rc;
+        if (reinterpret_cast<const double *>(host)[2] != 0.0) {      // stopped: nothing more runs
+            settle(R);
+            rc = reports_from(R, host, params->gn_iters, report, &sc);
+            done = true;
+        } else {
             auto rest = [&](Run &C) { return warm_rest(C, params); };
             rc = graph ? launch_graph(R, "rest|" + key, rest) : rest(R);
             if (rc) return rc;
         }
     }
-    const double *sc = nullptr;
-    rc = collect(R, params->gn_iters, report, &sc);
+    if (!done) rc = collect(R, params->gn_iters, report, &sc);
     if (!sc) return rc;
     report->energy_pred = sc[4];
     report->energy_prev = sc[6];
