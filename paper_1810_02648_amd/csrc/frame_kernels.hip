@@ -65,8 +65,14 @@ __device__ inline void dt_seg_body(const ProbDev &pr, int bx) {
     const int s = i / W, x = i - s * W;
     int first = kFar, last = -kFar;
     const int y0 = s * kSeg, y1 = min(H, y0 + kSeg);
-    for (int y = y0; y < y1; ++y)
-        if (pr.contour[size_t(y) * W + x]) { first = min(first, y); last = y; }
+    // the segment's kSeg rows loaded together (rows past the image re-read
+    // its last row and are not counted), then scanned in order
+    uint8_t c[kSeg];
+#pragma unroll
+    for (int k = 0; k < kSeg; ++k) c[k] = pr.contour[size_t(min(y0 + k, H - 1)) * W + x];
+#pragma unroll
+    for (int k = 0; k < kSeg; ++k)
+        if (y0 + k < y1 && c[k]) { first = min(first, y0 + k); last = y0 + k; }
     pr.seg_first[i] = first;
     pr.seg_last[i] = last;
 }
@@ -179,7 +185,10 @@ __device__ inline void dt_cols_body(const ProbDev &pr, int bx) {
     int d[kSeg];
     uint8_t c[kSeg];
 #pragma unroll
-    for (int k = 0; k < kSeg; ++k) c[k] = (y0 + k < y1) ? pr.contour[size_t(y0 + k) * W + x] : 0;
+    for (int k = 0; k < kSeg; ++k) {      // loaded together: rows past the image re-read its last row
+        c[k] = pr.contour[size_t(min(y0 + k, H - 1)) * W + x];
+        if (y0 + k >= y1) c[k] = 0;
+    }
     int last = above;
 #pragma unroll
     for (int k = 0; k < kSeg; ++k) {
