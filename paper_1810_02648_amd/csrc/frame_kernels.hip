@@ -24,14 +24,25 @@ __device__ inline void blur_body(const ProbDev &pr, int bx, float w0, float w1) 
     const size_t plane = size_t(W) * H;
     const int xl = max(x - 1, 0), xr = min(x + 1, W - 1);
     const int rows[3] = {max(y - 1, 0), y, min(y + 1, H - 1)};
+    // all 27 taps loaded before any store (the output could alias the input
+    // as far as the compiler knows, which would order each channel's loads
+    // behind the previous channel's store)
+    float v[3][3][3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+#pragma unroll
+        for (int r = 0; r < 3; ++r) {
+            const CAP_GLOBAL float *row = pr.image.g() + c * plane + size_t(rows[r]) * W;
+            v[c][r][0] = row[xl];
+            v[c][r][1] = row[x];
+            v[c][r][2] = row[xr];
+        }
+#pragma unroll
     for (int c = 0; c < 3; ++c) {
-        const CAP_GLOBAL float *s = pr.image.g() + c * plane;
         float h[3];
 #pragma unroll
-        for (int r = 0; r < 3; ++r) {     // horizontal pass of rows y-1, y, y+1 (clamped)
-            const CAP_GLOBAL float *row = s + size_t(rows[r]) * W;
-            h[r] = (w0 * row[xl] + w1 * row[x]) + w0 * row[xr];
-        }
+        for (int r = 0; r < 3; ++r)      // horizontal pass of rows y-1, y, y+1 (clamped)
+            h[r] = (w0 * v[c][r][0] + w1 * v[c][r][1]) + w0 * v[c][r][2];
         pr.blurred[c * plane + i] = (w0 * h[0] + w1 * h[1]) + w0 * h[2];
     }
 }
@@ -44,12 +55,13 @@ __device__ inline void contour_body(const ProbDev &pr, int bx) {
     if (i >= W * H) return;
     int y = i / W, x = i - y * W;
     const CAP_GLOBAL uint8_t *m = pr.mask.g();
-    uint8_t c = 0;
-    if (m[i]) {
-        bool bg = x == 0 || y == 0 || x == W - 1 || y == H - 1 || !m[i - 1] || !m[i + 1] || !m[i - W] || !m[i + W];
-        c = bg ? 1 : 0;
-    }
-    pr.contour[i] = c;
+    // the pixel and its four neighbours loaded together (clamped at the border,
+    // where the pixel counts as contour anyway), then tested
+    const uint8_t mc = m[i], ml = m[x > 0 ? i - 1 : i], mr = m[x < W - 1 ? i + 1 : i];
+    const uint8_t mu = m[y > 0 ? i - W : i], md = m[y < H - 1 ? i + W : i];
+    const bool border = x == 0 || y == 0 || x == W - 1 || y == H - 1;
+    const bool bg = border | (ml == 0) | (mr == 0) | (mu == 0) | (md == 0);
+    pr.contour[i] = (mc != 0 && bg) ? 1 : 0;
 }
 
 __global__ void k_contour(const ProbDev *__restrict__ P) { contour_body(P[blockIdx.y], blockIdx.x); }
