@@ -237,9 +237,18 @@ __device__ inline void dt_rows_body(const ProbDev &pr, int y) {
     const int W = pr.W, H = pr.H;
     if (y >= H) return;
     const int far2 = 1 << 30;
-    for (int x = threadIdx.x; x < W; x += blockDim.x) {
-        const int g = pr.colg[size_t(y) * W + x];
-        G[x] = g >= kFar ? far2 : g * g;
+    // the row's column distances staged four per thread per round (loads at
+    // clamped columns in flight together, then the LDS stores)
+    for (int x0 = threadIdx.x; x0 < W; x0 += 4 * blockDim.x) {
+        int g[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) g[u] = pr.colg[size_t(y) * W + min(x0 + u * int(blockDim.x), W - 1)];
+        __asm__ volatile("" ::"v"(g[0]), "v"(g[1]), "v"(g[2]), "v"(g[3]));     // (none moved behind a store)
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int x = x0 + u * int(blockDim.x);
+            if (x < W) G[x] = g[u] >= kFar ? far2 : g[u] * g[u];
+        }
     }
     __syncthreads();
     const int cs = (W + kDtChunks - 1) / kDtChunks;
