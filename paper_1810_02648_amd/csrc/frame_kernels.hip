@@ -631,8 +631,28 @@ __global__ void k_decide(const ProbDev *__restrict__ P) {
                 code |= 1;
                 if (cont && (open || !pr.outline_only)) {
                     code |= 2;
+                    // the sum of the vertex's face normals, in face-list order: the
+                    // first kVertFaces face indices loaded together (clamped into the
+                    // list), then their normals, then the rare remaining faces
+                    constexpr int kVertFaces = 8;
+                    const int q0 = T.vf_beg[i], q1 = T.vf_beg[i + 1], qc = max(q1 - 1, 0);
+                    int fs[kVertFaces];
+#pragma unroll
+                    for (int u = 0; u < kVertFaces; ++u) fs[u] = T.vf_face[min(q0 + u, qc)];
+                    float fn[kVertFaces][3];
+#pragma unroll
+                    for (int u = 0; u < kVertFaces; ++u)
+#pragma unroll
+                        for (int a = 0; a < 3; ++a) fn[u][a] = pr.fcross[a * size_t(nf) + fs[u]];
                     float n[3] = {0.0f, 0.0f, 0.0f};
-                    for (int q = T.vf_beg[i]; q < T.vf_beg[i + 1]; ++q) {
+#pragma unroll
+                    for (int u = 0; u < kVertFaces; ++u)
+                        if (q0 + u < q1) {
+                            n[0] = n[0] + fn[u][0];
+                            n[1] = n[1] + fn[u][1];
+                            n[2] = n[2] + fn[u][2];
+                        }
+                    for (int q = q0 + kVertFaces; q < q1; ++q) {
                         int f = T.vf_face[q];
                         n[0] = n[0] + pr.fcross[f];
                         n[1] = n[1] + pr.fcross[nf + f];
