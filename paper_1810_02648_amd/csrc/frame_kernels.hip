@@ -313,19 +313,33 @@ __device__ inline void deform_start_body(const ProbDev &pr, int bx) {
     int i = bx * blockDim.x + threadIdx.x;
     if (i >= nv) return;
     float v[3] = {pr.xyz[i], pr.xyz[nv + i], pr.xyz[2 * nv + i]};
+    // the four bindings and then all of their nodes' data (position: the
+    // frame's mesh at the node vertex, set up per frame; R and t) in two
+    // rounds of loads, before the arithmetic
+    int k[4];
+    float w[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        k[j] = T.bind_idx[size_t(j) * nv + i];
+        w[j] = T.bind_w[size_t(j) * nv + i];
+    }
+    float g[4][3], S[4][12];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+#pragma unroll
+        for (int a = 0; a < 3; ++a) g[j][a] = pr.gpos[size_t(a) * nn + k[j]];
+#pragma unroll
+        for (int q = 0; q < 12; ++q) S[j][q] = pr.state[size_t(q) * nn + k[j]];
+    }
     float acc[3] = {0.0f, 0.0f, 0.0f};
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
-        int k = T.bind_idx[size_t(j) * nv + i];
-        float w = T.bind_w[size_t(j) * nv + i];
-        // the node's position: the frame's mesh at the node vertex (set up per frame)
-        float g[3] = {pr.gpos[k], pr.gpos[nn + k], pr.gpos[2 * size_t(nn) + k]};
-        float d[3] = {v[0] - g[0], v[1] - g[1], v[2] - g[2]};
+        float d[3] = {v[0] - g[j][0], v[1] - g[j][1], v[2] - g[j][2]};
         for (int a = 0; a < 3; ++a) {
-            const CAP_GLOBAL float *R = pr.state.g() + size_t(3 * a) * nn + k;
-            float q = (R[0] * d[0] + R[nn] * d[1]) + R[2 * size_t(nn)] * d[2];
-            float yv = (q + g[a]) + pr.state[size_t(9 + a) * nn + k];
-            acc[a] = acc[a] + w * yv;
+            const float *R = S[j] + 3 * a;
+            float q = (R[0] * d[0] + R[1] * d[1]) + R[2] * d[2];
+            float yv = (q + g[j][a]) + S[j][9 + a];
+            acc[a] = acc[a] + w[j] * yv;
         }
     }
     store_start_vertex(pr, i, acc[0], acc[1], acc[2]);
