@@ -29,7 +29,8 @@ solves  (J^T |B| J) delta = -J^T B F  with B = diag(b): the system matrix uses
 |b| so that it stays positive semi-definite.
 
 Linear solve, two modes:
-    'chol': exact solve (dense Cholesky; sparse LU from SciPy above 8000 unknowns);
+    'chol': exact solve by a sparse Cholesky factorisation (bandwidth-reducing
+            reverse Cuthill-McKee ordering, banded factorisation);
     'pcg':  exactly ``pcg_iters`` Jacobi-preconditioned CG iterations from 0
             (Sec. 4, non-rigid paragraph: diagonal preconditioner), stopping early
             only when p.Ap <= 0 or r.z == 0; a non-positive diagonal entry
@@ -37,7 +38,6 @@ Linear solve, two modes:
 """
 import numpy as np
 import scipy.sparse as sp
-import scipy.sparse.linalg as spla
 
 from . import so3
 from .image import blur, distance_transform, sample
@@ -256,13 +256,36 @@ def identity_state(nn):
     return s
 
 
-def solve_cholesky(A, rhs):
+def sparse_cholesky(A):
+    """Sparse Cholesky factorisation A[perm][:, perm] = L L^T of an SPD matrix.
+
+    Ordering: reverse Cuthill-McKee on the sparsity graph, which gathers the
+    non-zeros of every row into a band next to the diagonal; all fill-in of the
+    factor stays inside that band.  The band is factored by LAPACK's banded
+    Cholesky.  Returns (perm, band factor in LAPACK lower band storage).
+    """
+    from scipy.linalg import cholesky_banded
+    from scipy.sparse.csgraph import reverse_cuthill_mckee
+    A = sp.csr_matrix(A)
     n = A.shape[0]
-    if n <= 8000:
-        L = np.linalg.cholesky(A.toarray())
-        y = np.linalg.solve(L, rhs)
-        return np.linalg.solve(L.T, y)
-    return spla.splu(A.tocsc()).solve(rhs)
+    perm = np.asarray(reverse_cuthill_mckee(A, symmetric_mode=True), dtype=np.int64)
+    B = A[perm][:, perm].tocoo()
+    low = B.row >= B.col
+    r, c, v = B.row[low], B.col[low], B.data[low]
+    bw = int((r - c).max()) if r.size else 0
+    band = np.zeros((bw + 1, n))
+    band[r - c, c] = v                 # lower storage: band[i - j, j] = B[i, j]
+    return perm, cholesky_banded(band, lower=True)
+
+
+def solve_cholesky(A, rhs):
+    """Exact solve of the normal equations by the sparse Cholesky factorisation."""
+    from scipy.linalg import cho_solve_banded
+    perm, L = sparse_cholesky(A)
+    y = cho_solve_banded((L, True), rhs[perm])
+    x = np.empty_like(y)
+    x[perm] = y
+    return x
 
 
 def solve_pcg(A, rhs, iters):
