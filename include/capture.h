@@ -182,6 +182,26 @@ CAPTURE_API int capture_nonrigid_solve(capture_ctx *ctx, const capture_frame *fr
                            const capture_nonrigid_params *params, capture_report *report,
                            void *workspace, size_t workspace_bytes, void *stream);
 
+/* For callers that cannot allocate memory (code under HIP graph capture,
+ * serving loops, harnesses that forbid hipMalloc): the same solve of one frame
+ * as capture_nonrigid_solve, with no workspace argument.  Scratch is a 32 MiB
+ * device array that the library holds on every device it runs on until the
+ * process ends (its address is looked up once per device by capture_create);
+ * descriptor upload and report read-back go through a fixed 64 KiB host
+ * buffer.  On success the call performs no device, pinned or host allocation
+ * and launches eagerly (graphs and kernel timing do not apply).  Every call
+ * on a device shares that device's scratch and the one host buffer, and the
+ * scratch keeps the last call's contents (the solve initialises everything
+ * it reads): calls that overlap, on any stream or thread, race and must be
+ * serialised by the caller.  A frame whose workspace (capture_workspace_size)
+ * exceeds 32 MiB, e.g. a 1080x1080 image with a 20,000-vertex template fits
+ * and a 1200x1200 image does not, or whose descriptors exceed the host
+ * buffer, returns CAPTURE_EUNSUPPORTED before any launch.  Errors as for
+ * capture_nonrigid_solve. */
+CAPTURE_API int capture_nonrigid_solve_noalloc(capture_ctx *ctx, const capture_frame *frame,
+                                               const capture_nonrigid_params *params, capture_report *report,
+                                               void *stream);
+
 /* The same solve for `n` independent frames of possibly different sizes in one
  * sequence of batched launches.  `frames` and `reports` are host arrays of n;
  * all frames share `params`. */

@@ -175,6 +175,14 @@ def nonrigid_solve(ctx, frame, prm):
     return _report_dict(rep, prm.gn_iters)
 
 
+def nonrigid_solve_noalloc(ctx, frame, prm):
+    """capture_nonrigid_solve_noalloc: the solve with the library's fixed device scratch."""
+    arr = _frames([frame])
+    rep = capi.Report()
+    capi.check(ctx.lib.capture_nonrigid_solve_noalloc(ctx.h, arr, C.byref(prm), C.byref(rep), _stream()))
+    return _report_dict(rep, prm.gn_iters)
+
+
 def autotune_tiles(ctx, tris, graphs, frames, prm, candidates=(64, 128, 192, 256)):
     """Pick vertices_per_tile by timing batched solves of `frames` with templates
     rebuilt from (tri, graph) at each candidate; frames' node states are kept.

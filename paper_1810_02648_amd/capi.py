@@ -85,6 +85,8 @@ SIGNATURES = {
     "capture_workspace_size": (C.c_int, [_P, C.c_int32, C.POINTER(Frame), C.POINTER(C.c_size_t)]),
     "capture_nonrigid_solve": (C.c_int, [_P, C.POINTER(Frame), C.POINTER(NonrigidParams), C.POINTER(Report),
                                          _P, C.c_size_t, _P]),
+    "capture_nonrigid_solve_noalloc": (C.c_int, [_P, C.POINTER(Frame), C.POINTER(NonrigidParams),
+                                                 C.POINTER(Report), _P]),
     "capture_batch_solve": (C.c_int, [_P, C.c_int32, C.POINTER(Frame), C.POINTER(NonrigidParams),
                                       C.POINTER(Report), _P, C.c_size_t, _P]),
     "capture_frame_decisions": (C.c_int, [_P, C.POINTER(Frame), _P, _P, _P, _P, _P, C.c_size_t, _P]),

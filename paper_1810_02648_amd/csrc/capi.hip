@@ -5,6 +5,7 @@
 #include <cstdio>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <vector>
 
 #include "device.hpp"
@@ -51,14 +52,16 @@ __global__ void k_ws_target(const float *prev, const float *next, int nn, float 
 __global__ void k_ws_scaling(const float *X, long long rows, float *mu, float *sd);
 
 namespace {
-thread_local std::string g_err;
+// The last error message (fixed storage: setting it allocates nothing).
+thread_local char g_err[512];
 }
 
-void set_error(const std::string &msg) { g_err = msg; }
-int fail(int code, const std::string &msg) {
-    g_err = msg;
+void set_error(const std::string &msg) { (void)fail(0, msg.c_str()); }
+int fail(int code, const char *msg) {
+    std::snprintf(g_err, sizeof g_err, "%s", msg ? msg : "");
     return code;
 }
+int fail(int code, const std::string &msg) { return fail(code, msg.c_str()); }
 
 // ---------------------------------------------------------------- graph build kernels
 __device__ inline float d2f(float ax, float ay, float az, float bx, float by, float bz) {
@@ -229,7 +232,7 @@ int grid_tiles(int n, const capture_frame *frames) {
     return int((t + 7) / 8 * 8);
 }
 
-Plan plan_workspace(int n, const capture_frame *frames, uint8_t *base, std::vector<ProbDev> *probs) {
+Plan plan_workspace(int n, const capture_frame *frames, uint8_t *base, ProbDev *probs) {
     Layout L;
     Plan pl;
     // descriptors, then the tile-kernel work list, one upload
@@ -241,7 +244,7 @@ Plan plan_workspace(int n, const capture_frame *frames, uint8_t *base, std::vect
         carve(L, base, frames[i], pr);
         pr.scal = scal ? scal + size_t(kScalars) * i : nullptr;
         pr.counts = counts ? counts + 3 * i : nullptr;
-        if (probs) (*probs)[i] = pr;
+        if (probs) probs[i] = pr;
     }
     pl.bytes = L.off;
     return pl;
@@ -289,7 +292,7 @@ const char *kKernelNames[K_COUNT] = {"blur", "contour", "dt_cols", "dt_rows", "d
 
 int setup(Run &R, capture_ctx *ctx, int n, const capture_frame *frames, const capture_nonrigid_params *params,
           void *ws, size_t ws_bytes, void *stream) {
-    R.prof = &ctx->prof;
+    R.prof = R.fixed_stage ? nullptr : &ctx->prof;
     R.ctx = ctx;
     int rc = check_frames(n, frames);
     if (rc) return rc;
@@ -299,7 +302,7 @@ int setup(Run &R, capture_ctx *ctx, int n, const capture_frame *frames, const ca
     R.n = n;
     R.probs.resize(n);
     uint8_t *base = static_cast<uint8_t *>(ws);
-    plan_workspace(n, frames, base, &R.probs);
+    plan_workspace(n, frames, base, R.probs.data());
     R.dprobs = reinterpret_cast<ProbDev *>(base);
     R.s = static_cast<hipStream_t>(stream);
     const float wsil = params ? params->w_sil : 1.0f, wph = params ? params->w_photo : 0.1f,
@@ -338,8 +341,8 @@ int setup(Run &R, capture_ctx *ctx, int n, const capture_frame *frames, const ca
     // sized once for both the descriptors and the report read-back of `collect`
     R.grid_tiles = grid_tiles(n, frames);
     const size_t desc = sizeof(ProbDev) * n + sizeof(TileDesc) * R.grid_tiles;
-    void *stage = staging(ctx, desc + sizeof(double) * kScalars * n + sizeof(int) * 3 * n + 512);
-    if (!stage) return fail(CAPTURE_ENOMEM, "pinned staging allocation failed");
+    void *stage = run_staging(R, desc + sizeof(double) * kScalars * n + sizeof(int) * 3 * n + 512);
+    if (!stage) return fail(R.fixed_stage ? CAPTURE_EUNSUPPORTED : CAPTURE_ENOMEM, "host staging too small or its allocation failed");
     std::memcpy(stage, R.probs.data(), sizeof(ProbDev) * n);
     TileDesc *td = reinterpret_cast<TileDesc *>(static_cast<uint8_t *>(stage) + sizeof(ProbDev) * n);
     int k = 0;
@@ -517,8 +520,8 @@ int read_back(Run &R, const uint8_t **host) {
     const uint8_t *blk = reinterpret_cast<const uint8_t *>(R.probs[0].scal.ptr);
     const size_t off_counts = reinterpret_cast<const uint8_t *>(R.probs[0].counts.ptr) - blk;
     const size_t bytes = off_counts + sizeof(int) * 3 * R.n;
-    uint8_t *h = static_cast<uint8_t *>(staging(R.ctx, bytes));
-    if (!h) return fail(CAPTURE_ENOMEM, "pinned staging allocation failed");
+    uint8_t *h = static_cast<uint8_t *>(run_staging(R, bytes));
+    if (!h) return fail(CAPTURE_ENOMEM, "host staging too small or its allocation failed");
     CAP_HIP(hipMemcpyAsync(h, blk, bytes, hipMemcpyDeviceToHost, R.s));
     CAP_HIP(hipStreamSynchronize(R.s));
     *host = h;
@@ -613,13 +616,47 @@ void ws_backward(capture_warmstart *net, const TemplateDev &T, hipStream_t s) {
     hipLaunchKernelGGL(k_colsum, dim3(128), dim3(256), 0, s, net->dz, nn, 128, net->g + kOffB1);
 }
 
+// ---------------------------------------------------------------- allocation-free solve
+// Device scratch of capture_nonrigid_solve_noalloc: one copy of this array on
+// every device the library runs on, held until the process ends and shared by
+// every such call on that device.  Host code never uses the array's name as a
+// device address: its per-device address comes from hipGetSymbolAddress,
+// resolved once per device when a context is created on it.
+constexpr size_t kNoAllocScratch = size_t(32) << 20;
+constexpr size_t kNoAllocStage = size_t(64) << 10;
+constexpr int kNoAllocDevices = 64;
+static __device__ __align__(256) uint8_t scratch[kNoAllocScratch];
+
+namespace {
+std::mutex g_scratch_mu;
+void *g_scratch_dev[kNoAllocDevices] = {};
+// Host staging of the allocation-free calls (descriptor upload, report
+// read-back): fixed, shared like the device scratch.
+alignas(256) uint8_t g_noalloc_stage[kNoAllocStage];
+}  // namespace
+
+// The device address of `scratch` on `device` (the current device), looked up
+// on the first call for that device.
+int resolve_scratch(int device, void **out) {
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (device >= kNoAllocDevices) return fail(CAPTURE_EUNSUPPORTED, "device index beyond the scratch table");
+    if (!g_scratch_dev[device]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) return fail(CAPTURE_EHIP, "hipGetSymbolAddress(scratch) failed");
+        g_scratch_dev[device] = p;
+    }
+    *out = g_scratch_dev[device];
+    return CAPTURE_OK;
+}
+
 }  // namespace cap
 
 using namespace cap;
 
 extern "C" {
 
-const char *capture_last_error(void) { return g_err.c_str(); }
+const char *capture_last_error(void) { return g_err; }
 
 int capture_create(capture_ctx **ctx, int device) {
     if (!ctx) return fail(CAPTURE_EINVAL, "null ctx pointer");
@@ -627,8 +664,12 @@ int capture_create(capture_ctx **ctx, int device) {
     CAP_HIP(hipGetDeviceCount(&count));
     if (device < 0 || device >= count) return fail(CAPTURE_EINVAL, "no such device");
     CAP_HIP(hipSetDevice(device));
+    void *scr = nullptr;
+    const int rc = device < kNoAllocDevices ? resolve_scratch(device, &scr) : CAPTURE_OK;
+    if (rc) return rc;
     *ctx = new capture_ctx();
     (*ctx)->device = device;
+    (*ctx)->scratch = scr;
     return CAPTURE_OK;
 }
 
@@ -723,6 +764,36 @@ int capture_batch_solve(capture_ctx *ctx, int32_t n, const capture_frame *frames
 int capture_nonrigid_solve(capture_ctx *ctx, const capture_frame *frame, const capture_nonrigid_params *params,
                            capture_report *report, void *workspace, size_t workspace_bytes, void *stream) {
     return capture_batch_solve(ctx, 1, frame, params, report, workspace, workspace_bytes, stream);
+}
+
+// The same launch sequence as capture_nonrigid_solve, eagerly launched, with
+// the device scratch as workspace and fixed host staging: no device, pinned
+// or host allocation on any path that returns CAPTURE_OK.
+int capture_nonrigid_solve_noalloc(capture_ctx *ctx, const capture_frame *frame,
+                                   const capture_nonrigid_params *params, capture_report *report, void *stream) {
+    if (!ctx || !params || !report) return fail(CAPTURE_EINVAL, "null argument");
+    int rc = check_frames(1, frame);
+    if (rc) return rc;
+    if ((rc = check_params(params))) return rc;
+    if (!ctx->scratch) return fail(CAPTURE_EUNSUPPORTED, "no device scratch on this device");
+    if (plan_workspace(1, frame, nullptr, nullptr).bytes > kNoAllocScratch)
+        return fail(CAPTURE_EUNSUPPORTED, "frame needs more than the 32 MiB device scratch of the allocation-free solve");
+    CAP_HIP(hipSetDevice(ctx->device));
+    Run R;
+    R.fixed_stage = g_noalloc_stage;
+    R.fixed_stage_bytes = kNoAllocStage;
+    if ((rc = setup(R, ctx, 1, frame, params, ctx->scratch, kNoAllocScratch, stream))) return rc;
+    if ((rc = launch_frame(R, params->gn_iters))) return rc;
+    if ((rc = launch_solve(R, params))) return rc;
+    rc = collect(R, params->gn_iters, report);
+    if (rc) {
+        if (report->status)
+            (void)hipMemcpyAsync(frame->node_state, R.probs[0].state0, sizeof(float) * 12 * R.probs[0].T.nn,
+                                 hipMemcpyDeviceToDevice, R.s);
+        (void)hipStreamSynchronize(R.s);
+        return fail(rc, "non-finite energy; node state restored");
+    }
+    return CAPTURE_OK;
 }
 
 int capture_autotune_tiles(capture_ctx *ctx, int32_t n, const capture_template_desc *descs, const capture_frame *frames,

@@ -15,6 +15,7 @@ namespace cap {
 
 // ---------------------------------------------------------------- errors
 void set_error(const std::string &msg);
+int fail(int code, const char *msg);     // copies msg into a fixed thread-local buffer
 int fail(int code, const std::string &msg);
 
 #define CAP_HIP(expr)                                                                        \
@@ -248,6 +249,7 @@ struct capture_ctx {
     void *pinned = nullptr;      // pinned host staging (descriptors, report read-back)
     size_t pinned_bytes = 0;
     bool graphs = false;         // replay solves from captured HIP graphs
+    void *scratch = nullptr;     // this device's address of the allocation-free solve's scratch
     hipStream_t capture_stream = nullptr;
     struct Graph {
         std::string key;

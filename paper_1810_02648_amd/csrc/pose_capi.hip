@@ -143,7 +143,8 @@ int pose_setup(PoseRun &P, capture_ctx *ctx, const capture_pose_frame *f, const 
     Run &R = P.R;
     R.prof = &ctx->prof;
     R.n = 1;
-    R.probs.assign(1, pr);
+    R.probs.resize(1);
+    R.probs[0] = pr;
     R.dprobs = reinterpret_cast<ProbDev *>(base);
     R.s = static_cast<hipStream_t>(stream);
     R.max_nv = pr.T.nv; R.max_nf = pr.T.nf; R.max_me = pr.T.nmedges;

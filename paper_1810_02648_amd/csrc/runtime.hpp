@@ -32,11 +32,31 @@ inline void *staging(capture_ctx *ctx, size_t bytes) {
     return ctx->pinned;
 }
 
+// Per-problem descriptors on the host: inline storage for one problem (the
+// single-frame entry points allocate nothing for it), heap storage for batches.
+class ProbList {
+  public:
+    void resize(int n) {
+        n_ = n;
+        if (n > 1) heap_.resize(size_t(n));
+    }
+    ProbDev *data() { return n_ > 1 ? heap_.data() : &one_; }
+    const ProbDev *data() const { return n_ > 1 ? heap_.data() : &one_; }
+    ProbDev &operator[](size_t i) { return data()[i]; }
+    const ProbDev &operator[](size_t i) const { return data()[i]; }
+    size_t size() const { return size_t(n_); }
+
+  private:
+    int n_ = 0;
+    ProbDev one_{};
+    std::vector<ProbDev> heap_;
+};
+
 struct Run {
     capture_ctx *ctx = nullptr;
     Profiler *prof = nullptr;
     int n = 0;
-    std::vector<ProbDev> probs;
+    ProbList probs;
     ProbDev *dprobs = nullptr;
     int max_nv = 0, max_nf = 0, max_nn = 0, max_hw = 0, max_w = 0, max_h = 0, max_tiles = 0, max_me = 0;
     size_t lds_lin = 0, lds_apply = 0, lds_apply_split = 0;
@@ -47,7 +67,18 @@ struct Run {
     // set before setup; applied to problem 0 (single-frame entry points)
     double target = -INFINITY;
     const float *prev2 = nullptr;
+    // allocation-free calls: host staging of fixed size instead of the
+    // context's growable pinned buffer, and no kernel timing
+    uint8_t *fixed_stage = nullptr;
+    size_t fixed_stage_bytes = 0;
 };
+
+// Host staging of a run: the fixed buffer when the run has one (nullptr if it
+// is too small), else the context's pinned buffer.
+inline void *run_staging(Run &R, size_t bytes) {
+    if (R.fixed_stage) return bytes <= R.fixed_stage_bytes ? R.fixed_stage : nullptr;
+    return staging(R.ctx, bytes);
+}
 
 // Launch `go` bracketed by events when timing is on.
 template <typename F>
