@@ -139,8 +139,10 @@ typedef struct {
 /* Weights and schedule.  E = w_photo*sum||sigma_c(I_Gauss(pi(V_i)) - C_i)||^2
  *  + w_sil*sum b_i I_DT(pi(V_i))^2 + w_arap*sum||R_k(g_l - g_k) + g_k + t_k - g_l - t_l||^2
  *  + w_vel*sum_i ||V_i - V_i^a||^2.
- * tau_color: the photometric robust-kernel threshold (residual set to zero when
- * the colour difference norm exceeds it); +inf or 0 disables it.
+ * tau_color: the photometric robust-kernel threshold sigma_c (Sec. 3.4: a
+ * vertex's colour residual is set to zero when the norm of its colour
+ * difference exceeds tau_color, compared in float32); +inf disables it, 0
+ * prunes every residual whose colour difference is not exactly zero.
  * w_vel: the paper's temporal prior E_velocity (Sec. 3.4) over all vertices, with
  * the previous frame's result carried to the current pose: V^a is the input
  * mesh deformed by the start node state (the previous frame's solution);

@@ -327,9 +327,12 @@ def apply_update(state, delta):
     return st
 
 
-def solve(problem, gn_iters, mode="chol", pcg_iters=10):
-    """Run the Gauss-Newton schedule; returns state (float64) and energies."""
-    state = problem.state0.astype(np.float64)
+def solve(problem, gn_iters, mode="chol", pcg_iters=10, start=None):
+    """Run the Gauss-Newton schedule; returns state (float64) and energies.
+
+    The schedule starts at ``start`` if given (e.g. a predicted start), else at
+    the state the frame's decisions were taken at (problem.state0)."""
+    state = (problem.state0 if start is None else start).astype(np.float64)
     energies = []
     for _ in range(gn_iters):
         A, rhs, e = problem.normal_equations(state)

@@ -307,7 +307,7 @@ int setup(Run &R, capture_ctx *ctx, int n, const capture_frame *frames, const ca
     R.s = static_cast<hipStream_t>(stream);
     const float wsil = params ? params->w_sil : 1.0f, wph = params ? params->w_photo : 0.1f,
                 war = params ? params->w_arap : 10.0f;
-    const float tau = params ? (params->tau_color > 0 ? params->tau_color : INFINITY) : INFINITY;
+    const float tau = params ? params->tau_color : INFINITY;     // sigma_c threshold; +inf keeps every residual
     const float wvel = params ? params->w_vel : 0.0f;
     const int excl = params ? int(params->flags & CAPTURE_FLAG_EXCLUDE_CASE2) : 0;
     const int outline = params ? int((params->flags & CAPTURE_FLAG_OUTLINE_ONLY) != 0) : 0;

@@ -152,13 +152,14 @@ def test_velocity_prior_and_case2_exclusion_match_oracle(ctx, frames, sigma, w_v
     """Temporal prior anchored at the start geometry, case-2 vertices excluded,
     from the rest state and from perturbed starts (sigma: rad and m per component).
 
-    The parameter bar is 1e-4 of the parameter change for starts within 0.01
-    of the solution.  From a 0.03 start the first steps are large and the
-    float32 accumulation of J^T J p and of the right-hand side (terms that
-    cancel, |error| ~ eps32 * sum |terms|) moves the 8-iteration PCG iterate
-    by up to ~6e-4 of the change; an FP64 model of exactly that rounding (the
-    oracle with eps32 * |A| |p| noise on each product) shows 3.7e-4, so the
-    stated bound for these starts is 1e-3.  Energies stay within 1e-5."""
+    The first Gauss-Newton step is held to 1e-4 of the parameter change in
+    every case (measured: 1.3e-5 from the 0.03 starts, where splitting the
+    float32 error showed it to come from the float32 linearisation, which
+    enters the right-hand side and J^T J p consistently).  The three-step
+    result keeps 1e-4 for starts within 0.01 of the solution.  From the 0.03
+    starts the schedule itself amplifies a first-step error of that size to
+    1.6e-4 ... 1.3e-3 in FP64 alone (tests/test_oracle_sensitivity.py), so the
+    three-step bar there is 1e-3; energies stay within 1e-5 everywhere."""
     import paper_1810_02648_amd as cap
     from gpu_util import make_frame
     f = frames["small1"]
@@ -167,23 +168,24 @@ def test_velocity_prior_and_case2_exclusion_match_oracle(ctx, frames, sigma, w_v
     st = onr.apply_update(onr.identity_state(64), rng.normal(0, sigma, 384)).astype(np.float32)
     P = onr.Problem(f["xyz"], f["tri"], f["rgb"], g, f["cam"], f["mask"], f["image"], f["weights"], state0=st,
                     w_vel=w_vel, case2=case2)
-    ref = onr.solve(P, 3, "pcg", 8)
-    fr = make_frame(ctx, f, g, state=st)
-    rep = cap.nonrigid_solve(ctx, fr, cap.params(*f["weights"], gn_iters=3, pcg_iters=8, w_vel=w_vel,
-                                                 exclude_case2=case2 == "exclude"))
-    assert rep["n_boundary"] == ref["n_boundary"]
-    r_gpu, t_gpu = params_of(fr.node_state.cpu().numpy())
-    r_ref, t_ref = params_of(ref["state"])
     r0, t0 = params_of(st)
-    er = np.linalg.norm(r_gpu - r_ref) / max(np.linalg.norm(r_ref - r0), 1e-6)
-    et = np.linalg.norm(t_gpu - t_ref) / max(np.linalg.norm(t_ref - t0), 1e-6)
-    e0 = ref["energies"][0]["total"]
-    print("sigma %g w_vel %g: rel r err %.2e, t err %.2e; E gpu %s ref %s" % (
-        sigma, w_vel, er, et, rep["energy"], [e["total"] for e in ref["energies"]]), flush=True)
-    assert er <= bar and et <= bar
-    for k, e in enumerate(ref["energies"]):
-        assert abs(rep["energy"][k] - e["total"]) <= 1e-5 * e0, k
-    assert abs(rep["e_vel"] - ref["energies"][-1]["vel"]) <= 1e-5 * e0
+    for gn, step_bar in ((1, 1e-4), (3, bar)):
+        ref = onr.solve(P, gn, "pcg", 8)
+        fr = make_frame(ctx, f, g, state=st)
+        rep = cap.nonrigid_solve(ctx, fr, cap.params(*f["weights"], gn_iters=gn, pcg_iters=8, w_vel=w_vel,
+                                                     exclude_case2=case2 == "exclude"))
+        assert rep["n_boundary"] == ref["n_boundary"]
+        r_gpu, t_gpu = params_of(fr.node_state.cpu().numpy())
+        r_ref, t_ref = params_of(ref["state"])
+        er = np.linalg.norm(r_gpu - r_ref) / max(np.linalg.norm(r_ref - r0), 1e-6)
+        et = np.linalg.norm(t_gpu - t_ref) / max(np.linalg.norm(t_ref - t0), 1e-6)
+        e0 = ref["energies"][0]["total"]
+        print("sigma %g w_vel %g, %d GN: rel r err %.2e, t err %.2e; E gpu %s ref %s" % (
+            sigma, w_vel, gn, er, et, rep["energy"], [e["total"] for e in ref["energies"]]), flush=True)
+        assert er <= step_bar and et <= step_bar, gn
+        for k, e in enumerate(ref["energies"]):
+            assert abs(rep["energy"][k] - e["total"]) <= 1e-5 * e0, k
+        assert abs(rep["e_vel"] - ref["energies"][-1]["vel"]) <= 1e-5 * e0
 
 
 def test_batch_equals_single_solves(ctx, frames):
