@@ -98,6 +98,41 @@ def measured_traffic(kernel, key):
     return None
 
 
+def cpu_baseline_sequence(seq, t=2, n=3):
+    """The FP64 oracle on the GPU leg's problem: frames t..t+n-1 of the
+    sequence, each started from the oracle's own result of the frame before
+    (its tracking of frames 0..t-1 from the rest state is set-up, not timed),
+    with the sequence's weights, temporal prior, case-2 exclusion, contour rule
+    and the plain schedule (GN steps x Jacobi-PCG iterations)."""
+    from threadpoolctl import threadpool_limits
+
+    from oracle import graph as og
+    from oracle import nonrigid as onr
+    cores = len(os.sched_getaffinity(0))
+    g = og.build_graph(seq["xyz"], seq["n_nodes"])      # the template's graph (per template, not timed)
+
+    def problem(k, start):
+        return onr.Problem(seq["posed"][k], seq["tri"], seq["rgb"], g, seq["cam"], seq["masks"][k], seq["images"][k],
+                           seq["weights"], state0=start.astype("float32"), w_vel=seq["w_vel"], case2="exclude",
+                           outline=seq.get("outline", False))
+
+    with threadpool_limits(limits=cores):
+        st = onr.identity_state(seq["n_nodes"])
+        for k in range(t):
+            st = onr.solve(problem(k, st), seq["gn"], "pcg", seq["pcg"])["state"]
+        t0 = time.perf_counter()
+        for k in range(t, t + n):
+            out = onr.solve(problem(k, st), seq["gn"], "pcg", seq["pcg"])
+            st = out["state"]
+        dt = time.perf_counter() - t0
+    return dict(value=n / dt, unit="frames/s", cores=cores, kind="oracle",
+                sample="%d frames of the same sequence (frames %d-%d, each started from the oracle's own result of "
+                       "the frame before; per-frame preprocessing + %d GN x %d Jacobi-PCG in float64 with the "
+                       "sequence's weights, temporal prior, case-2 exclusion and contour rule, i.e. the GPU plain "
+                       "leg's problem), %.1f s; last final energy %.4f"
+                       % (n, t, t + n - 1, seq["gn"], seq["pcg"], dt, out["energies"][-1]["total"]))
+
+
 def cpu_baseline(frame_dict, n_nodes, gn, pcg, weights):
     """The FP64 oracle (exact Cholesky solves) on one frame of the same workload."""
     import numpy as np  # noqa: F401
@@ -192,11 +227,13 @@ def bench_sequence(args, cap, torch):
         "data": "synthetic",
         "config": {
             "launch": "eager" if args.no_graphs else "HIP graph replay",
-            "workload": "%s: %d-frame sequence, %d-vertex template, %d-node graph, %dx%d targets, %d GN x %d PCG; "
+            "workload": "%s: %d-frame sequence, %d-vertex %s template, %d-node graph, %dx%d targets, %d GN x %d PCG; "
                         "train frames 1-%d, held-out frames %d-%d; one step = all held-out frames solved from "
                         "the learned start until the plain schedule's final energy"
-                        % (args.workload, S.n, seq["xyz"].shape[1], S.nn, W, H, seq["gn"], seq["pcg"], ntr - 1,
-                           ntr, S.n - 1),
+                        % (args.workload, S.n, seq["xyz"].shape[1],
+                           "articulated 23-joint body (sinusoidal joint angles + GP cloth offsets)"
+                           if args.workload.startswith("body") else "ellipsoid (RBF-blended rigid motions + GP "
+                           "cloth offsets)", S.nn, W, H, seq["gn"], seq["pcg"], ntr - 1, ntr, S.n - 1),
             "plain_frames_per_s": n / tp,
             "speedup_vs_plain": tp / tl,
             "mean_gn_steps_plain": float(np.mean(ev["plain_steps"])),
@@ -445,7 +482,8 @@ def main():
     ap.add_argument("--mode", default="sequence", choices=["sequence", "frame", "batch", "copy"],
                     help="copy: a plain device copy of known size (calibrates the profiler's byte counters)")
     ap.add_argument("--workload", default=None,
-                    help="sequence: seq20k (default) or seq_small; frame: frame20k (default), small, stress200k")
+                    help="sequence: body20k (default: articulated body), seq20k (ellipsoid), body_small, seq_small; "
+                         "frame: frame20k (default), small, stress200k")
     ap.add_argument("--batch", type=int, default=1,
                     help="frame mode: copies of the frame solved together per step; batch mode: frames (default 64)")
     ap.add_argument("--epochs", type=int, default=40, help="sequence mode: training epochs")
@@ -460,7 +498,7 @@ def main():
               "(independent captures would shard one per GPU with no communication)", file=sys.stderr)
         sys.exit(2)
     if args.workload is None:
-        args.workload = "seq20k" if args.mode == "sequence" else "frame20k"
+        args.workload = "body20k" if args.mode == "sequence" else "frame20k"
 
     import torch
 
@@ -496,10 +534,7 @@ def main():
                             "time" % "/".join(str(data[i]["xyz"].shape[1]) for i in pick))
             result["cpu_baseline"] = cb
         elif args.mode == "sequence":
-            t = data["n_train"]
-            fr = dict(xyz=data["posed"][t], tri=data["tri"], rgb=data["rgb"], cam=data["cam"],
-                      mask=data["masks"][t], image=data["images"][t])
-            result["cpu_baseline"] = cpu_baseline(fr, data["n_nodes"], data["gn"], data["pcg"], data["weights"])
+            result["cpu_baseline"] = cpu_baseline_sequence(data)
         else:
             result["cpu_baseline"] = cpu_baseline(data, data["n_nodes"], data["gn"], data["pcg"], data["weights"])
     print(json.dumps(result), flush=True)

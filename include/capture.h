@@ -311,7 +311,11 @@ CAPTURE_API int capture_warmstart_train_step(capture_ctx *ctx, capture_warmstart
  * frame's node_state (the previous frame's result), predicted start x',
  * energies at both; the lower one starts Gauss-Newton, which stops at the
  * start of the first step whose energy is <= target_energy (pass -inf for the
- * full schedule).  report->warm_start tells which start was used. */
+ * full schedule).  report->warm_start tells which start was used.  With a
+ * finite target the launches are issued in two parts with one read-back of
+ * the stop flag in between; the first part ends at the step count that the
+ * network's last 16 target-driven solves needed (median; 1 at first), so the
+ * network keeps that history (launch policy only: results do not depend on it). */
 CAPTURE_API int capture_nonrigid_solve_warm(capture_ctx *ctx, const capture_frame *frame,
                                             const capture_nonrigid_params *params, capture_warmstart *net,
                                             const float *state_prev2, double target_energy, capture_report *report,

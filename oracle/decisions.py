@@ -158,10 +158,10 @@ def mesh_edges(tri):
     return np.array(out, dtype=np.int64).reshape(-1, 4)
 
 
-def frame_decisions(xyz, tri, graph, state, cam, mask, dt):
+def frame_decisions(xyz, tri, graph, state, cam, mask, dt, outline=False):
     """All per-frame decisions of the non-rigid stage (start positions by the ED recipe)."""
     X, Y, Z = ed_deform_f32(xyz, graph["node_vertex"], graph["bind_idx"], graph["bind_w"], state)
-    return frame_decisions_from_positions(X, Y, Z, tri, cam, mask, dt)
+    return frame_decisions_from_positions(X, Y, Z, tri, cam, mask, dt, outline=outline)
 
 
 def frame_decisions_from_positions(X, Y, Z, tri, cam, mask, dt, outline=False):

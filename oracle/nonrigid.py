@@ -20,6 +20,9 @@ possible regulariser on graph edges):
             deformed by the start node state (the float32 start positions of
             the decision recipe), i.e. the previous frame's result displaced
             onto the current pose;
+With outline=True the contour set keeps only vertices on the outline of the
+rendered model (see decisions.frame_decisions_from_positions), for meshes made
+of overlapping closed parts.
 E = sum b r^2 with b = 1 except the silhouette rows (the paper's energy, which
 has negative terms when b_i = -1).  With case2="exclude" the silhouette rows of
 b_i = -1 vertices are dropped instead (b = 0): the literal term is unbounded
@@ -100,7 +103,7 @@ class Problem:
     """One non-rigid frame: inputs plus the frozen per-frame decisions."""
 
     def __init__(self, xyz, tri, rgb, graph, cam, mask, image, weights, tau_c=np.inf,
-                 state0=None, w_vel=0.0, case2="push"):
+                 state0=None, w_vel=0.0, case2="push", outline=False):
         self.xyz, self.tri, self.rgb, self.graph, self.cam = xyz, tri, rgb, graph, cam
         self.w_sil, self.w_photo, self.w_arap = (float(w) for w in weights)
         self.tau_c = float(tau_c)
@@ -111,7 +114,7 @@ class Problem:
         self.mask = mask
         self.dt, _ = distance_transform(mask)
         self.img = blur(image, 3)
-        self.dec = frame_decisions(xyz, tri, graph, self.state0, cam, mask, self.dt)
+        self.dec = frame_decisions(xyz, tri, graph, self.state0, cam, mask, self.dt, outline=outline)
         self.vis_idx = np.nonzero(self.dec["visible"])[0]
         self.bnd_idx = np.nonzero(self.dec["boundary"])[0]
         self.bsign = self.dec["bsign"][self.bnd_idx].astype(np.float64)

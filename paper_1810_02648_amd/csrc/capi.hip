@@ -1093,7 +1093,22 @@ int capture_warmstart_train_step(capture_ctx *ctx, capture_warmstart *net, const
 // With `split`, the sequence ends after Gauss-Newton step 0 and the
 // linearisation of step 1 (whose energy test may stop the solve); the caller
 // launches the remaining steps only if it did not.
-int warm_sequence(Run &R, const capture_nonrigid_params *params, capture_warmstart *net, bool split) {
+// Step at which a learned-start solve is split (0: not split): the median
+// step count of the network's last learned solves (1 before any), if a later
+// step remains.
+int warm_split_step(const capture_warmstart *net, const capture_nonrigid_params *params, double target) {
+    if (params->gn_iters <= 1 || !std::isfinite(target)) return 0;
+    int s = 1;
+    if (net->n_recent > 0) {
+        int v[16];
+        std::copy(net->recent_gn, net->recent_gn + net->n_recent, v);
+        std::sort(v, v + net->n_recent);
+        s = std::max(1, v[net->n_recent / 2]);
+    }
+    return s < params->gn_iters ? s : 0;
+}
+
+int warm_sequence(Run &R, const capture_nonrigid_params *params, capture_warmstart *net, int split) {
     const ProbDev &pr = R.probs[0];
     const int prev_slot = CAPTURE_MAX_GN + 1;     // energy at the given start (x_{t-1})
     int rc = launch_frame(R, params->gn_iters);   // keeps the given state in state0
@@ -1114,15 +1129,15 @@ int warm_sequence(Run &R, const capture_nonrigid_params *params, capture_warmsta
         hipLaunchKernelGGL(k_node_init, dim3(R.n), dim3(kInitThreads), 0, R.s, R.dprobs, 0, 0, 3, 0, 0);
     });
     if (!split) return launch_solve(R, params, 1, true);
-    launch_steps(R, params, 1, true, 0, 1);
-    launch_linearize(R, 1, 0, 1);
+    launch_steps(R, params, 1, true, 0, split);
+    launch_linearize(R, split, 0, 1);
     CAP_HIP(hipGetLastError());
     return CAPTURE_OK;
 }
 
-// The rest of a split learned-start solve: steps 1.. and the final energy.
-int warm_rest(Run &R, const capture_nonrigid_params *params) {
-    launch_steps(R, params, 1, true, 1, params->gn_iters);
+// The rest of a learned-start solve split at step `split`: steps split.. and the final energy.
+int warm_rest(Run &R, const capture_nonrigid_params *params, int split) {
+    launch_steps(R, params, 1, true, split, params->gn_iters);
     launch_linearize(R, params->gn_iters, 1);
     CAP_HIP(hipGetLastError());
     return CAPTURE_OK;
@@ -1142,14 +1157,17 @@ int capture_nonrigid_solve_warm(capture_ctx *ctx, const capture_frame *frame, co
     int rc = setup(R, ctx, 1, frame, params, workspace, workspace_bytes, stream);
     if (rc) return rc;
     const ProbDev &pr = R.probs[0];
-    // Most predictions reach the target within one step: the solve is launched
-    // in two parts, and the second only if the energy test at the start of
-    // step 1 has not stopped it (one read-back of the stop flag in between),
-    // so a stopped solve does not pay for the launches of its remaining steps.
-    const bool split = params->gn_iters > 1 && std::isfinite(target_energy);
+    // A good prediction reaches the target within a step or two: the solve is
+    // launched in two parts, the first through the energy test at the start of
+    // step `split` (the median step count of recent learned solves), the second
+    // only if that test has not stopped it (one read-back of the stop flag in
+    // between).  A solve that stops early thus pays neither for the launches of
+    // its remaining steps (which would find the stop flag and return) nor, in
+    // the common case, for a second round trip.
+    const int split = warm_split_step(net, params, target_energy);
     const bool graph = ctx->graphs && !ctx->prof.on;
     char net_key[128];    // the forward pass takes the network, edge table and x as arguments
-    std::snprintf(net_key, sizeof net_key, "warm%d|%p|%p|%p|", int(split), (void *)net,
+    std::snprintf(net_key, sizeof net_key, "warm%d|%p|%p|%p|", split, (void *)net,
                   (const void *)pr.T.edge_dst, (void *)pr.x);
     const std::string key = net_key + shape_key(R, params);
     auto first = [&](Run &C) { return warm_sequence(C, params, net, split); };
@@ -1165,7 +1183,7 @@ int capture_nonrigid_solve_warm(capture_ctx *ctx, const capture_frame *frame, co
             rc = reports_from(R, host, params->gn_iters, report, &sc);
             done = true;
         } else {
-            auto rest = [&](Run &C) { return warm_rest(C, params); };
+            auto rest = [&](Run &C) { return warm_rest(C, params, split); };
             rc = graph ? launch_graph(R, "rest|" + key, rest) : rest(R);
             if (rc) return rc;
         }
@@ -1175,6 +1193,11 @@ int capture_nonrigid_solve_warm(capture_ctx *ctx, const capture_frame *frame, co
     report->energy_pred = sc[4];
     report->energy_prev = sc[6];
     report->warm_start = sc[5] != 0.0 ? 2 : 1;
+    if (std::isfinite(target_energy)) {        // step counts of target-driven solves set the next split
+        net->recent_gn[net->recent_pos] = report->gn_done;
+        net->recent_pos = (net->recent_pos + 1) % 16;
+        net->n_recent = std::min(net->n_recent + 1, 16);
+    }
     if (rc) {
         (void)hipMemcpyAsync(frame->node_state, pr.state0, sizeof(float) * 12 * pr.T.nn, hipMemcpyDeviceToDevice, R.s);
         (void)hipStreamSynchronize(R.s);

@@ -261,6 +261,8 @@ struct capture_ctx {
 struct capture_warmstart {
     int device, max_nodes;
     long long steps;
+    int recent_gn[16];           // Gauss-Newton steps of the last learned-start solves (ring)
+    int n_recent, recent_pos;
     void *mem;
     float *w, *g, *m, *v, *mu, *sd;
     uint16_t *wb;

@@ -52,7 +52,7 @@ class DeviceSequence:
         self.nn = nn
         self.n = len(self.masks)
         self.prm = params(*seq["weights"], gn_iters=seq["gn"], pcg_iters=seq["pcg"], w_vel=seq["w_vel"],
-                          exclude_case2=True)
+                          exclude_case2=True, outline_only=seq.get("outline", False))
 
     def frame(self, t, state):
         return FrameInputs(self.template, self.posed[t], self.rgb, self.seq["cam"], self.masks[t], self.images[t],

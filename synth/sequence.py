@@ -23,6 +23,24 @@ Recipe (30 fps):
   weights and added to the posed mesh.
 * Each frame's mask and colour image are rendered from posed + offsets.
 
+Articulated sequences (``body*``, the default benchmark workload):
+
+* Template: the procedural 23-joint body of ``synth.body`` (one closed
+  ellipsoid per bone, overlapping at the joints) meshed to exactly the
+  requested vertex count, root 4.5 m in front of the camera (the 1.87 m body
+  spans ~0.83 of the image height at f = 2S), smooth colours as above.
+* Pose (what the pose stage explains): every rotational degree of freedom
+  follows theta(t) = a sin(2 pi f t + phi), a ~ U(0.1, 0.5) rad,
+  f ~ U(0.2, 1.0) Hz, phi ~ U(0, 2 pi); the skinned mesh at that pose is the
+  frame's input mesh of the non-rigid stage.
+* Cloth-like part: the same Gaussian-process offsets as above (length scale
+  0.2 m, amplitude 0.03 m, 4 harmonics of 0.5-2 Hz) at 64 control vertices,
+  blended to the vertices by rest-pose RBF weights and added to the posed
+  mesh in the camera frame.
+* Tracking uses the outline-only contour set: the body's parts are seen in
+  front of one another, and contours inside the silhouette have no
+  counterpart in the image's distance transform.
+
 The paper's evaluation sequences (11 sequences, 7 actors, 540x960 video)
 are not available; this motion stands in for their smooth body and cloth
 motion.
@@ -60,6 +78,14 @@ SEQUENCES = {
     # small, for tests
     "seq_small": dict(mesh="ico4", n_vertices=2562, n_nodes=64, side=256, n_frames=40, n_train=24,
                       gn=3, pcg=8, weights=_tracking_weights(256)[0], w_vel=_tracking_weights(256)[1]),
+    # articulated body: 20,000 vertices, 500 nodes, 1080^2, 300 frames (200 train, 100 test)
+    "body20k": dict(mesh="body", n_vertices=20000, n_nodes=500, side=1080, n_frames=300, n_train=200,
+                    gn=3, pcg=8, weights=_tracking_weights(1080)[0], w_vel=_tracking_weights(1080)[1],
+                    outline=True),
+    # articulated body, small, for tests
+    "body_small": dict(mesh="body", n_vertices=3000, n_nodes=64, side=256, n_frames=40, n_train=24,
+                       gn=3, pcg=8, weights=_tracking_weights(256)[0], w_vel=_tracking_weights(256)[1],
+                       outline=True),
 }
 
 
@@ -115,6 +141,36 @@ def _render_frame(args):
     return posed, gt, mask, image
 
 
+def _body_motion(body, rng, n_ctrl):
+    """Sinusoidal joint angles and Gaussian-process cloth offsets of a body sequence."""
+    from .body import dof_joints
+    nd = 3 * len(dof_joints())
+    amp = rng.uniform(0.1, 0.5, nd)
+    freq = rng.uniform(0.2, 1.0, nd)
+    phase = rng.uniform(0.0, 2.0 * np.pi, nd)
+    cloth = _motion(body["xyz"], rng, n_ctrl)
+    return dict(body=body, amp=amp, freq=freq, phase=phase, cloth=cloth)
+
+
+def _body_pose_at(m, t):
+    """(posed mesh, posed mesh + cloth offsets) of a body sequence at time t."""
+    from .body import pose_mesh
+    pose = np.zeros(69)
+    pose[:m["amp"].size] = m["amp"] * np.sin(2.0 * np.pi * m["freq"] * t + m["phase"])
+    posed, _ = pose_mesh(m["body"], pose)
+    c = m["cloth"]
+    off = (c["A"] * np.cos(c["w"] * t)[:, None, None] + c["B"] * np.sin(c["w"] * t)[:, None, None]).sum(0) / 2.0
+    gt = posed.T.astype(np.float64) + c["wts"] @ off
+    return posed, np.ascontiguousarray(gt.T.astype(np.float32))
+
+
+def _render_body_frame(args):
+    tri, rgb, cam, m, t = args
+    posed, gt = _body_pose_at(m, t)
+    mask, image = render_targets(gt, tri, rgb, cam)
+    return posed, gt, mask, image
+
+
 def make_sequence(name="seq20k", seed=0, n_frames=None, workers=None):
     """Template, camera, per-frame ground truth and rendered targets of a sequence."""
     cfg = dict(SEQUENCES[name])
@@ -122,21 +178,31 @@ def make_sequence(name="seq20k", seed=0, n_frames=None, workers=None):
         cfg["n_frames"] = n_frames
         cfg["n_train"] = min(cfg["n_train"], n_frames)
     rng = np.random.Generator(np.random.PCG64(seed))
-    xyz, tri = template_mesh(cfg["mesh"], cfg["n_vertices"])
-    rgb = smooth_colours(xyz, rng)
     cam = Camera.square(cfg["side"])
-    m = _motion(xyz, rng, 24)
-    jobs = [(xyz, tri, rgb, cam, m, f / 30.0) for f in range(cfg["n_frames"])]
+    if cfg["mesh"] == "body":
+        from .body import make_body
+        body = make_body(cfg["n_vertices"], root=(0.0, 0.0, 4.5))
+        xyz, tri = body["xyz"], body["tri"]
+        rgb = smooth_colours(xyz, rng)
+        m = _body_motion(body, rng, 64)
+        jobs = [(tri, rgb, cam, m, f / 30.0) for f in range(cfg["n_frames"])]
+        render = _render_body_frame
+    else:
+        xyz, tri = template_mesh(cfg["mesh"], cfg["n_vertices"])
+        rgb = smooth_colours(xyz, rng)
+        m = _motion(xyz, rng, 24)
+        jobs = [(xyz, tri, rgb, cam, m, f / 30.0) for f in range(cfg["n_frames"])]
+        render = _render_frame
     if workers is None:
-        workers = min(16, len(os.sched_getaffinity(0)))
+        workers = min(8, len(os.sched_getaffinity(0)))
     if workers > 1 and len(jobs) > 4:
         import multiprocessing as mp
         with ProcessPoolExecutor(max_workers=workers, mp_context=mp.get_context("spawn")) as ex:
-            frames = list(ex.map(_render_frame, jobs, chunksize=4))
+            frames = list(ex.map(render, jobs, chunksize=4))
     else:
-        frames = [_render_frame(j) for j in jobs]
+        frames = [render(j) for j in jobs]
     return dict(name=name, seed=seed, xyz=xyz, tri=tri, rgb=rgb, cam=cam,
                 posed=[f[0] for f in frames], gt=[f[1] for f in frames], masks=[f[2] for f in frames],
                 images=[f[3] for f in frames],
                 n_nodes=cfg["n_nodes"], n_train=cfg["n_train"], gn=cfg["gn"], pcg=cfg["pcg"],
-                weights=cfg["weights"], w_vel=cfg["w_vel"])
+                weights=cfg["weights"], w_vel=cfg["w_vel"], outline=cfg.get("outline", False))

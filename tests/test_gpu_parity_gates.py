@@ -1,8 +1,8 @@
 """GPU parity against the FP64 oracle for the paths the single-frame tests do
 not reach: PCG run to convergence against the exact sparse-Cholesky solve
 (the Gauss-Newton step of Sec. 4, Eq. gaussnewton), a tracking frame of the
-20k-vertex / 500-node / 1080^2 sequence started from the previous frame's
-result with the tracking weights, an uneven batch with a split-PCG frame, the
+20k-vertex / 500-node / 1080^2 sequences (articulated body and ellipsoid)
+started from the previous frame's result with the tracking weights, an uneven batch with a split-PCG frame, the
 learned start when its prediction is accepted and when it is rejected, the
 photometric robust kernel sigma_c (Sec. 3.4) at a finite threshold and at 0,
 and faces large enough to take the workgroup rasteriser.
@@ -83,38 +83,41 @@ def test_converged_pcg_matches_exact_solve(ctx, name, gn, pcg):
     assert_energies(rep["energy"], ref)
 
 
-@pytest.fixture(scope="module")
-def seq20k_frames():
-    """Frames 0-2 of the 20k-vertex sequence and the oracle's tracking of 0 and 1."""
-    from synth.sequence import make_sequence
-    seq = make_sequence("seq20k", 0, n_frames=3, workers=1)
-    g = og.build_graph(seq["xyz"], seq["n_nodes"])
-    st = onr.identity_state(seq["n_nodes"]).astype(np.float64)
-    states = []
-    for t in range(2):
-        P = onr.Problem(seq["posed"][t], seq["tri"], seq["rgb"], g, seq["cam"], seq["masks"][t], seq["images"][t],
-                        seq["weights"], state0=st.astype(np.float32), w_vel=seq["w_vel"], case2="exclude")
-        st = onr.solve(P, seq["gn"], "pcg", seq["pcg"])["state"]
-        states.append(st)
-    return seq, g, states
+_SEQ_CACHE = {}
 
 
-def test_tracking_frame_of_the_20k_sequence_matches_oracle(ctx, seq20k_frames):
-    """Frame 2 of the 20k / 500-node / 1080^2 sequence, started from the
-    oracle's x*_1 with the tracking weights (w_arap 1e6, w_vel 1e3, case-2
-    exclusion, 3 GN x 8 PCG), launched as the benchmark launches it (graph
-    replay)."""
+def sequence_frames(name):
+    """Frames 0-2 of a sequence and the oracle's tracking of frames 0 and 1."""
+    if name not in _SEQ_CACHE:
+        from synth.sequence import make_sequence
+        seq = make_sequence(name, 0, n_frames=3, workers=1)
+        g = og.build_graph(seq["xyz"], seq["n_nodes"])
+        st = onr.identity_state(seq["n_nodes"]).astype(np.float64)
+        states = []
+        for t in range(2):
+            st = onr.solve(_seq_problem(seq, g, t, st.astype(np.float32)), seq["gn"], "pcg", seq["pcg"])["state"]
+            states.append(st)
+        _SEQ_CACHE[name] = (seq, g, states)
+    return _SEQ_CACHE[name]
+
+
+@pytest.mark.parametrize("name", ["body20k", "seq20k"])
+def test_tracking_frame_of_a_20k_sequence_matches_oracle(ctx, name):
+    """Frame 2 of the 20k / 500-node / 1080^2 sequences (the articulated body
+    of the benchmark, with the outline-only contour set, and the ellipsoid),
+    started from the oracle's x*_1 with the tracking weights (w_arap 1e6,
+    w_vel 1e3, case-2 exclusion, 3 GN x 8 PCG), launched as the benchmark
+    launches it (graph replay)."""
     import paper_1810_02648_amd as cap
     from gpu_util import dev, device_graph
-    seq, g, states = seq20k_frames
+    seq, g, states = sequence_frames(name)
     t = 2
     start = states[1].astype(np.float32)
-    P = onr.Problem(seq["posed"][t], seq["tri"], seq["rgb"], g, seq["cam"], seq["masks"][t], seq["images"][t],
-                    seq["weights"], state0=start, w_vel=seq["w_vel"], case2="exclude")
+    P = _seq_problem(seq, g, t, start)
     ref = onr.solve(P, seq["gn"], "pcg", seq["pcg"])
     tmpl = cap.Template(ctx, dev(seq["tri"]), device_graph(g))
     prm = cap.params(*seq["weights"], gn_iters=seq["gn"], pcg_iters=seq["pcg"], w_vel=seq["w_vel"],
-                     exclude_case2=True)
+                     exclude_case2=True, outline_only=seq["outline"])
     fr = cap.FrameInputs(tmpl, dev(seq["posed"][t]), dev(seq["rgb"]), seq["cam"], dev(seq["masks"][t]),
                          dev(seq["images"][t]), dev(start))
     cap.set_graphs(ctx, True)
@@ -124,8 +127,8 @@ def test_tracking_frame_of_the_20k_sequence_matches_oracle(ctx, seq20k_frames):
         cap.set_graphs(ctx, False)
     assert rep["n_visible"] == ref["n_visible"] and rep["n_boundary"] == ref["n_boundary"]
     er, et = rel_errors(fr.node_state.cpu().numpy(), ref["state"], start)
-    print("seq20k frame 2: rel r %.2e t %.2e; E gpu %s ref %s" % (
-        er, et, rep["energy"], [e["total"] for e in ref["energies"]]), flush=True)
+    print("%s frame 2: rel r %.2e t %.2e; E gpu %s ref %s" % (
+        name, er, et, rep["energy"], [e["total"] for e in ref["energies"]]), flush=True)
     assert er <= 1e-4 and et <= 1e-4
     assert_energies(rep["energy"], ref)
     assert abs(rep["e_vel"] - ref["energies"][-1]["vel"]) <= 1e-5 * ref["energies"][0]["total"]
@@ -175,7 +178,7 @@ def small_sequence():
 
 def _seq_problem(seq, g, t, start):
     return onr.Problem(seq["posed"][t], seq["tri"], seq["rgb"], g, seq["cam"], seq["masks"][t], seq["images"][t],
-                       seq["weights"], state0=start, w_vel=seq["w_vel"], case2="exclude")
+                       seq["weights"], state0=start, w_vel=seq["w_vel"], case2="exclude", outline=seq["outline"])
 
 
 @pytest.mark.parametrize("factor,expect", [(0.5, 1), (-3.0, 2)])

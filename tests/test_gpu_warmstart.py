@@ -172,7 +172,9 @@ def test_rejected_prediction_reproduces_plain_solve(ctx, small):
 def test_trained_warm_start_reaches_plain_energy_in_fewer_steps(ctx):
     import paper_1810_02648_amd as cap
     from paper_1810_02648_amd import sequence as sq
-    seq = synth.sequence.make_sequence("seq_small", 0, workers=1)
+    # 120 frames of the small sequence: trained on frames 1-95, held out 96-119
+    seq = synth.sequence.make_sequence("seq_small", 0, n_frames=120, workers=1)
+    seq["n_train"] = 96
     S = sq.DeviceSequence(ctx, seq)
     states, _ = sq.track_plain(S)
     ntr = seq["n_train"]
@@ -182,8 +184,11 @@ def test_trained_warm_start_reaches_plain_energy_in_fewer_steps(ctx):
     assert losses[-1] < 0.5 * losses[0]
     ev = sq.evaluate(S, net, states, range(ntr, S.n))
     print("plain steps", ev["plain_steps"], "learned steps", ev["learned_steps"], "used", ev["used_prediction"])
+    # the prediction is used on most held-out frames, every frame reaches the
+    # plain schedule's final energy, and clearly fewer steps are needed
     assert np.mean(ev["reached"]) >= 0.9
-    assert np.mean(ev["learned_steps"]) < np.mean(ev["plain_steps"])
+    assert np.mean(ev["used_prediction"]) >= 0.75
+    assert np.mean(ev["learned_steps"]) <= 0.8 * np.mean(ev["plain_steps"])
     # the learned start replayed from captured HIP graphs equals the eager
     # launches bit for bit, across frames whose previous states (and so the
     # feature inputs) differ, with unrelated GPU work between the replays
