@@ -30,10 +30,12 @@ def algorithmic_bytes(kernel, n_act, n_nodes, n_edges, n_pix, n_faces, n_verts):
     an implementation happens to move)."""
     if kernel == "apply":          # v 12 + idx 16 + w 16 + H 24 per active vertex; p, Ap, g, R per node; edges
         return 68 * n_act + 96 * n_nodes + 16 * n_edges
+    if kernel == "cg":             # the product, plus the PCG vector update (about 240 B per node)
+        return 68 * n_act + (96 + 240) * n_nodes + 16 * n_edges
+    if kernel == "cg_node":        # vectors and partials in, vectors (or the node state) out
+        return 240 * n_nodes
     if kernel == "linearize":      # 58 B streamed + 16 texels x 16 B + 36 B written per active vertex
         return 350 * n_act + 96 * n_nodes + 16 * n_edges
-    if kernel == "node_pcg":       # PCG vectors and partials per node
-        return 240 * n_nodes
     if kernel == "node_init":
         return 240 * n_nodes
     if kernel == "blur":           # one pass: 3 channels read + written
@@ -69,7 +71,7 @@ def algorithmic_bytes(kernel, n_act, n_nodes, n_edges, n_pix, n_faces, n_verts):
 # runs (FETCH_SIZE, WRITE_SIZE, scaled by a plain copy of known size) and kept
 # in profiles/ with the fingerprint of the kernel sources they were taken on;
 # a changed kernel reports null until it is measured again.
-TRAFFIC_TABLE = os.path.join(ROOT, "profiles", "k_apply_hbm_traffic.md")
+TRAFFIC_TABLE = os.path.join(ROOT, "profiles", "k_cg_hbm_traffic.md")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_1810_02648_amd", "csrc", f)
                   for f in ("solve_kernels.hip", "common.hpp", "device.hpp")]
 
@@ -85,7 +87,7 @@ def kernel_fingerprint():
 
 def measured_traffic(kernel, key):
     """HBM bytes per launch for `kernel` on workload `key`, or None."""
-    if kernel != "apply" or not os.path.exists(TRAFFIC_TABLE):
+    if kernel != "cg" or not os.path.exists(TRAFFIC_TABLE):
         return None
     fp = kernel_fingerprint()
     for line in open(TRAFFIC_TABLE):
@@ -160,12 +162,12 @@ def roofline_for(prof, steps, batch, n_act, nn, n_edges, W, H, nf, nv, key):
     bytes_launch = batch * algorithmic_bytes(dom, n_act, nn, n_edges, W * H, nf, nv)
     avg_s = prof[dom][0] / 1000.0 / prof[dom][1]
     achieved = bytes_launch / avg_s / 1e9
-    apply_s = prof["apply"][0] / 1000.0 / max(prof["apply"][1], 1)
+    apply_s = prof["cg"][0] / 1000.0 / max(prof["cg"][1], 1)
     apply_bytes = batch * algorithmic_bytes("apply", n_act, nn, n_edges, W * H, 0, 0)
     return {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(dom, key), "traffic_key": key,
             "avg_us": avg_s * 1e6, "algorithmic_bytes_per_launch": bytes_launch,
-            "apply_achieved_GBs": apply_bytes / apply_s / 1e9, "apply_avg_us": apply_s * 1e6}
+            "product_achieved_GBs": apply_bytes / apply_s / 1e9, "cg_avg_us": apply_s * 1e6}
 
 
 def bench_sequence(args, cap, torch):
@@ -436,13 +438,13 @@ def bench_batch(args, cap, torch):
 
     avg_s = prof[dom][0] / 1000.0 / prof[dom][1]
     achieved = total_bytes(dom) / avg_s / 1e9
-    apply_s = prof["apply"][0] / 1000.0 / max(prof["apply"][1], 1)
+    apply_s = prof["cg"][0] / 1000.0 / max(prof["cg"][1], 1)
     key = "batch%d/tile%d" % (n, tile)
     roof = {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(dom, key), "traffic_key": key,
             "avg_us": avg_s * 1e6,
             "algorithmic_bytes_per_launch": total_bytes(dom),
-            "apply_achieved_GBs": total_bytes("apply") / apply_s / 1e9, "apply_avg_us": apply_s * 1e6}
+            "product_achieved_GBs": total_bytes("apply") / apply_s / 1e9, "cg_avg_us": apply_s * 1e6}
     nv = [f["xyz"].shape[1] for f in frames_h]
     return {
         "metric": METRIC,

@@ -151,11 +151,22 @@ typedef struct {
  * image silhouette with the normal opposing z, b_i = -1) get no silhouette
  * residual instead of the literal -I_DT^2, which is unbounded below. */
 #define CAPTURE_FLAG_EXCLUDE_CASE2 1u
+/* Jacobi-PCG runs in one of two arrangements with the same iterates in exact
+ * arithmetic (Sec. 4: a fixed number of PCG iterations per Gauss-Newton step).
+ * Schedules of at most 16 iterations on at most 1024 tiles (all frames of the
+ * call) take one launch per iteration (Chronopoulos-Gear form); longer
+ * schedules and larger grids take the standard recurrence (two launches per
+ * iteration), whose rounding stays bounded over hundreds of iterations.
+ * CAPTURE_FLAG_PCG_STANDARD always takes the standard recurrence. */
+#define CAPTURE_FLAG_PCG_STANDARD 4u
 typedef struct {
     float w_sil, w_photo, w_arap, tau_color, w_vel;
     int32_t gn_iters;          /* 1..CAPTURE_MAX_GN */
-    int32_t pcg_iters;         /* >= 0 Jacobi-PCG iterations per Gauss-Newton step */
+    int32_t pcg_iters;         /* >= 0 Jacobi-PCG iterations per Gauss-Newton step (the cap when pcg_tol > 0) */
     uint32_t flags;            /* CAPTURE_FLAG_* */
+    float pcg_tol;             /* 0: exactly pcg_iters iterations; > 0: a step's PCG also stops once the
+                                  residual of the normal equations satisfies ||r|| <= pcg_tol ||b||
+                                  (b = -J^T B F; PCG run to convergence) */
 } capture_nonrigid_params;
 
 /* Host-side report of one solve. */
@@ -426,9 +437,13 @@ CAPTURE_API int capture_set_graphs(capture_ctx *ctx, int on);
  * bracketed by HIP events on the call's stream; elapsed times accumulate per
  * kernel until read.  Kernel names: "blur", "contour", "dt_cols", "dt_rows",
  * "deform_start", "raster", "contour_edges", "decide", "linearize",
- * "node_init", "apply", "node_pcg", "ws_features", "ws_mlp", "pose_lbs",
+ * "node_init", "cg", "cg_node", "ws_features", "ws_mlp", "pose_lbs",
  * "pose_rows", "pose_jtj", "pose_step", "prep_image", "prep_geom",
- * "prep_raster", "prep_cols".  The non-rigid stage's per-frame steps run in
+ * "prep_raster", "prep_cols".  "cg" is the matrix-free product J^T |B| J v of
+ * a PCG iteration with the vector update before it; "cg_node" the per-node
+ * step (for schedules of at most 16 PCG iterations on grids of at most 1024
+ * tiles: once per Gauss-Newton step, the last iteration's solution update and
+ * the node update; otherwise once per iteration).  The non-rigid stage's per-frame steps run in
  * combined launches: "prep_image" (frame set-up, blur, contour pixels),
  * "prep_geom" (deformed start, column segments), "prep_raster"
  * (rasterisation and, for few image columns, the segment scan; with many

@@ -129,9 +129,10 @@ class FrameInputs:
 
 
 def params(w_sil=1.0, w_photo=0.1, w_arap=10.0, gn_iters=5, pcg_iters=10, tau_color=math.inf, w_vel=0.0,
-           exclude_case2=False, outline_only=False):
-    flags = (capi.FLAG_EXCLUDE_CASE2 if exclude_case2 else 0) | (capi.FLAG_OUTLINE_ONLY if outline_only else 0)
-    return capi.NonrigidParams(w_sil, w_photo, w_arap, tau_color, w_vel, gn_iters, pcg_iters, flags)
+           exclude_case2=False, outline_only=False, pcg_tol=0.0, pcg_standard=False):
+    flags = ((capi.FLAG_EXCLUDE_CASE2 if exclude_case2 else 0) | (capi.FLAG_OUTLINE_ONLY if outline_only else 0) |
+             (capi.FLAG_PCG_STANDARD if pcg_standard else 0))
+    return capi.NonrigidParams(w_sil, w_photo, w_arap, tau_color, w_vel, gn_iters, pcg_iters, flags, pcg_tol)
 
 
 def _frames(frames):

@@ -34,11 +34,12 @@ class Frame(C.Structure):
 class NonrigidParams(C.Structure):
     _fields_ = [("w_sil", C.c_float), ("w_photo", C.c_float), ("w_arap", C.c_float),
                 ("tau_color", C.c_float), ("w_vel", C.c_float), ("gn_iters", C.c_int32),
-                ("pcg_iters", C.c_int32), ("flags", C.c_uint32)]
+                ("pcg_iters", C.c_int32), ("flags", C.c_uint32), ("pcg_tol", C.c_float)]
 
 
 FLAG_EXCLUDE_CASE2 = 1
 FLAG_OUTLINE_ONLY = 2
+FLAG_PCG_STANDARD = 4
 MAX_JOINTS = 32
 MAX_POSE_UNKNOWNS = 81
 
@@ -122,7 +123,7 @@ SIGNATURES = {
 }
 
 KERNELS = ("blur", "contour", "dt_cols", "dt_rows", "deform_start", "raster", "contour_edges", "decide",
-           "linearize", "node_init", "apply", "node_pcg", "ws_features", "ws_mlp", "pose_lbs", "pose_rows",
+           "linearize", "node_init", "cg", "cg_node", "ws_features", "ws_mlp", "pose_lbs", "pose_rows",
            "pose_jtj", "pose_step", "prep_image", "prep_geom", "prep_raster", "prep_cols")
 WS_PARAMS = 38662
 

@@ -23,14 +23,16 @@ __global__ void k_prep_raster(const ProbDev *P, int nb_f, int scan);
 __global__ void k_prep_cols(const ProbDev *P);
 __global__ void k_prep_rows(const ProbDev *P, int nb_rows);
 __global__ void k_linearize(const ProbDev *P, const TileDesc *D, int mode);
-template <int kSplit>
-__global__ void k_apply(const ProbDev *P, const TileDesc *D);
+template <int kSplit, int kMode>
+__global__ void k_cg(const ProbDev *P, const TileDesc *D, int j);
 __global__ void k_node_init(const ProbDev *P, int gn, int energy_only, int check_target, int slot_prev, int gn_iters);
 __global__ void k_node_gather(const ProbDev *P);
-__global__ void k_node_pcg(const ProbDev *P, int last, int update_only);
-__global__ void k_pcg_split_a(const ProbDev *P);
-__global__ void k_pcg_split_b(const ProbDev *P, int it);
-__global__ void k_pcg_split_c(const ProbDev *P, int it, int last);
+__global__ void k_cg_finish(const ProbDev *P, int n);
+__global__ void k_pcg_node(const ProbDev *P, int j, int last);
+constexpr int kCgFused = 0, kCgStandard = 1;     // k_cg's arrangements of the PCG iteration
+// schedules of at most this many PCG iterations per Gauss-Newton step (on grids
+// the chip holds at once) run one launch per iteration
+constexpr int kCgFusedMaxIters = 16;
 int build_template(const capture_template_desc *d, capture_template **out, int device);
 
 // warm-start kernels (warmstart.hip)
@@ -212,11 +214,16 @@ void carve(Layout &L, uint8_t *base, const capture_frame &f, ProbDev &pr) {
     pr.Hm = L.take<float>(base, 6 * nv);
     pr.partial = L.take<float>(base, size_t(T.nslots) * 12);
     pr.gpos = L.take<float>(base, size_t(3) * nn);
-    pr.dots = L.take<double>(base, 2 * ((6 * nn + kSplitItems - 1) / kSplitItems));
+    pr.dots = L.take<double>(base, size_t(6) * T.ntiles);
+    pr.cg = L.take<double>(base, 8);
+    pr.nsum = L.take<double>(base, size_t(4) * ((nn + 255) / 256));
     pr.tile_e = L.take<double>(base, size_t(T.ntiles) * kTerms);
     pr.pva = L.take<float>(base, 3 * nv);
-    gptr<float> *vecs[8] = {&pr.b, &pr.diag, &pr.dinv, &pr.x, &pr.r, &pr.z, &pr.p, &pr.Ap};
+    gptr<float> *vecs[6] = {&pr.b, &pr.diag, &pr.dinv, &pr.p, &pr.Ap, &pr.x};
     for (gptr<float> *v : vecs) *v = L.take<float>(base, 6 * nn);
+    gptr<double> *dvecs[10] = {&pr.vx[0], &pr.vx[1], &pr.vr[0], &pr.vr[1], &pr.vu[0],
+                               &pr.vu[1], &pr.vp[0], &pr.vp[1], &pr.vs[0], &pr.vs[1]};
+    for (gptr<double> *v : dvecs) *v = L.take<double>(base, 6 * nn);
     pr.state0 = L.take<float>(base, 12 * nn);
 }
 
@@ -275,9 +282,10 @@ int check_params(const capture_nonrigid_params *p) {
     if (!finite(p->w_sil) || !finite(p->w_photo) || !finite(p->w_arap) || !finite(p->w_vel) || p->w_sil < 0 ||
         p->w_photo < 0 || p->w_arap < 0 || p->w_vel < 0)
         return fail(CAPTURE_EINVAL, "weights must be finite and non-negative");
-    if (p->flags & ~uint32_t(CAPTURE_FLAG_EXCLUDE_CASE2 | CAPTURE_FLAG_OUTLINE_ONLY))
+    if (p->flags & ~uint32_t(CAPTURE_FLAG_EXCLUDE_CASE2 | CAPTURE_FLAG_OUTLINE_ONLY | CAPTURE_FLAG_PCG_STANDARD))
         return fail(CAPTURE_EINVAL, "unknown flag bits");
     if (std::isnan(p->tau_color) || p->tau_color < 0) return fail(CAPTURE_EINVAL, "tau_color must be >= 0 or +inf");
+    if (!finite(p->pcg_tol) || p->pcg_tol < 0) return fail(CAPTURE_EINVAL, "pcg_tol must be finite and >= 0");
     return CAPTURE_OK;
 }
 
@@ -285,7 +293,7 @@ int check_params(const capture_nonrigid_params *p) {
 enum class Stage { Decisions, Linearize, Solve };
 
 const char *kKernelNames[K_COUNT] = {"blur", "contour", "dt_cols", "dt_rows", "deform_start", "raster",
-                                     "contour_edges", "decide", "linearize", "node_init", "apply", "node_pcg",
+                                     "contour_edges", "decide", "linearize", "node_init", "cg", "cg_node",
                                      "ws_features", "ws_mlp", "pose_lbs", "pose_rows", "pose_jtj",
                                      "pose_step", "prep_image", "prep_geom", "prep_raster",
                                      "prep_cols"};
@@ -309,6 +317,7 @@ int setup(Run &R, capture_ctx *ctx, int n, const capture_frame *frames, const ca
                 war = params ? params->w_arap : 10.0f;
     const float tau = params ? params->tau_color : INFINITY;     // sigma_c threshold; +inf keeps every residual
     const float wvel = params ? params->w_vel : 0.0f;
+    const double tol = params ? double(params->pcg_tol) : 0.0;
     const int excl = params ? int(params->flags & CAPTURE_FLAG_EXCLUDE_CASE2) : 0;
     const int outline = params ? int((params->flags & CAPTURE_FLAG_OUTLINE_ONLY) != 0) : 0;
     for (int i = 0; i < n; ++i) {
@@ -321,6 +330,7 @@ int setup(Run &R, capture_ctx *ctx, int n, const capture_frame *frames, const ca
         pr.sw_sil = std::sqrt(wsil); pr.sw_photo = std::sqrt(wph); pr.sw_arap = std::sqrt(war);
         pr.w_arap = war; pr.tau = tau;
         pr.w_vel = wvel; pr.sw_vel = std::sqrt(wvel); pr.exclude_case2 = excl; pr.outline_only = outline;
+        pr.pcg_tol2 = tol * tol;
         pr.target = i == 0 ? R.target : -INFINITY;
         pr.prev2 = i == 0 ? R.prev2 : nullptr;
         const TemplateDev &T = pr.T;
@@ -401,15 +411,19 @@ int launch_frame(Run &R, int gn_iters = 0) {
     return CAPTURE_OK;
 }
 
-// J^T J p over all tiles.  Grids that the chip holds at once take the
-// one-pass reduction; larger ones the two-pass variant with half the LDS.
-void launch_apply(Run &R) {
+// One product launch (k_cg, iteration j; j < 0: the product of
+// capture_linearize) over all tiles.  Grids that the chip holds at once take
+// the one-pass reduction; larger ones the two-pass variant with half the LDS.
+void launch_cg(Run &R, int j, bool fused) {
     if (R.grid_tiles > kApplySplitTiles) {
-        hipLaunchKernelGGL(k_apply<1>, dim3(unsigned(R.grid_tiles)), dim3(kTileThreads), R.lds_apply_split, R.s,
-                           R.dprobs, R.tiles);
+        hipLaunchKernelGGL((k_cg<1, kCgStandard>), dim3(unsigned(R.grid_tiles)), dim3(kTileThreads), R.lds_apply_split,
+                           R.s, R.dprobs, R.tiles, j);
+    } else if (fused) {
+        hipLaunchKernelGGL((k_cg<0, kCgFused>), dim3(unsigned(R.grid_tiles)), dim3(kTileThreads), R.lds_apply, R.s,
+                           R.dprobs, R.tiles, j);
     } else {
-        hipLaunchKernelGGL(k_apply<0>, dim3(unsigned(R.grid_tiles)), dim3(kTileThreads), R.lds_apply, R.s, R.dprobs,
-                           R.tiles);
+        hipLaunchKernelGGL((k_cg<0, kCgStandard>), dim3(unsigned(R.grid_tiles)), dim3(kTileThreads), R.lds_apply, R.s,
+                           R.dprobs, R.tiles, j);
     }
 }
 
@@ -430,25 +444,25 @@ void launch_linearize(Run &R, int gn, int energy_only, int check_target = 0, int
 void launch_steps(Run &R, const capture_nonrigid_params *prm, int check_target, bool first_done, int g0, int g1) {
     for (int gn = g0; gn < g1; ++gn) {
         if (gn > g0 || !first_done) launch_linearize(R, gn, 0, check_target);
-        for (int j = 0; j < prm->pcg_iters; ++j) {
+        // one launch per iteration (Chronopoulos-Gear) for short schedules on
+        // grids the chip holds at once; otherwise the standard recurrence, a
+        // product launch and a node-step launch per iteration
+        const int n = prm->pcg_iters;
+        const bool fused = R.grid_tiles <= kApplySplitTiles && n <= kCgFusedMaxIters &&
+                           !(prm->flags & CAPTURE_FLAG_PCG_STANDARD);
+        const dim3 gnode(unsigned(blocks(R.max_nn, 256)), unsigned(R.n));
+        for (int j = 0; j < n; ++j) {
             timed(R, K_APPLY, [&] {
-                launch_apply(R);
+                launch_cg(R, j, fused);
             });
-            timed(R, K_NODE_PCG, [&] {
-                const int last = j == prm->pcg_iters - 1 ? 1 : 0;
-                if (6 * R.max_nn > kSplitMinItems) {
-                    const dim3 g(unsigned((6 * R.max_nn + kSplitItems - 1) / kSplitItems), unsigned(R.n));
-                    hipLaunchKernelGGL(k_pcg_split_a, g, dim3(kSplitThreads), 0, R.s, R.dprobs);
-                    hipLaunchKernelGGL(k_pcg_split_b, g, dim3(kSplitThreads), 0, R.s, R.dprobs, j);
-                    hipLaunchKernelGGL(k_pcg_split_c, g, dim3(kSplitThreads), 0, R.s, R.dprobs, j, last);
-                } else {
-                    hipLaunchKernelGGL(k_node_pcg, dim3(R.n), dim3(kNodeThreads), 0, R.s, R.dprobs, last, 0);
-                }
-            });
+            if (!fused)
+                timed(R, K_NODE_PCG, [&] {
+                    hipLaunchKernelGGL(k_pcg_node, gnode, dim3(256), 0, R.s, R.dprobs, j, j == n - 1 ? 1 : 0);
+                });
         }
-        if (prm->pcg_iters == 0)
+        if (fused || n == 0)
             timed(R, K_NODE_PCG, [&] {
-    hipLaunchKernelGGL(k_node_pcg, dim3(R.n), dim3(kNodeThreads), 0, R.s, R.dprobs, 0, 1);
+                hipLaunchKernelGGL(k_cg_finish, gnode, dim3(256), 0, R.s, R.dprobs, n);
             });
     }
 }
@@ -902,7 +916,7 @@ int capture_linearize(capture_ctx *ctx, const capture_frame *frame, const captur
         CAP_HIP(hipMemcpyAsync(pr.p, p, sizeof(float) * n6, hipMemcpyDeviceToDevice, R.s));
         CAP_HIP(hipMemcpyAsync(pr.scal + 1, &zero, sizeof(double), hipMemcpyHostToDevice, R.s));
         timed(R, K_APPLY, [&] {
-    launch_apply(R);
+            launch_cg(R, -1, false);
         });
         hipLaunchKernelGGL(k_node_gather, dim3(1), dim3(kNodeThreads), 0, R.s, R.dprobs);
         CAP_HIP(hipGetLastError());

@@ -50,9 +50,6 @@ inline size_t dt_rows_lds(int W) { return sizeof(int) * size_t(W) + 16; }
 #endif
 constexpr int kApplySplitTiles = CAP_APPLY_SPLIT_TILES;   // tile grids above this take the two-pass J^T J p reduction
 constexpr int kGraphCache = 16;          // captured solve graphs kept per context
-constexpr int kSplitThreads = 256;       // PCG split over workgroups for large node counts:
-constexpr int kSplitItems = 1024;        //   (component, node) items per workgroup
-constexpr int kSplitMinItems = 8192;     //   used when 6 * n_nodes exceeds this (one workgroup's register capacity)
 constexpr int kTerms = 5;   // energy terms per slot: photo, sil (with b), sil (with |b|), arap, velocity
 constexpr int kScalars = 8 + kTerms * (CAPTURE_MAX_GN + 2);   // slot MAX_GN + 1: predicted start
 
@@ -100,6 +97,8 @@ struct TemplateDev {
     gptr<const int> node_pbeg;      // [nn+1] into node_pidx
     gptr<const int> node_pidx;      // global slot indices of each node, tile order (node-major positions)
     gptr<const int> slot_dest;      // [nslots] node-major position of each slot's partial
+    gptr<const int> slot_pb;        // [nslots] first partial (node-major position) of the slot's node
+    gptr<const int> slot_pe;        // [nslots] end of that range; bit 31 set: the slot's tile owns the node
     gptr<const uint16_t> plan_cpos; // [4][nv] tile-local position of each vertex contribution in slot order
     gptr<const uint32_t> owned_cpos;// [8][nn] positions of an owned edge's two contributions (lo: source, hi: target)
     gptr<const int> vf_beg;         // [nv+1] vertex -> incident faces
@@ -128,6 +127,7 @@ struct ProbDev {
     int W, H;
     float fx, fy, cx, cy;
     float sw_sil, sw_photo, sw_arap, w_arap, tau, w_vel, sw_vel;
+    double pcg_tol2;             // stop a step's PCG once ||r||^2 <= pcg_tol2 ||b||^2 (0: fixed count)
     int exclude_case2;
     int outline_only;            // contour set B restricted to the rendered model's outline
     // images
@@ -156,9 +156,14 @@ struct ProbDev {
     gptr<float> gpos;      // [3][nn] node positions (the frame's input mesh at the node vertices)
     gptr<double> tile_e;   // [ntiles][kTerms]
     // nodes
-    gptr<float> b, diag, dinv, x, r, z, p, Ap;   // [6][nn]
-    gptr<double> scal;     // [kScalars]: rz, done, stopped, stop step, ..., kTerms energies per GN step
-    gptr<double> dots;     // [2][split blocks] per-workgroup dot-product sums of the split PCG
+    gptr<float> b, diag, dinv;   // [6][nn] right-hand side, diag(J^T |B| J), Jacobi preconditioner
+    gptr<double> vx[2], vr[2], vu[2], vp[2], vs[2];  // [6][nn] PCG vectors (float64), two generations (see k_cg)
+    gptr<float> x;         // [6][nn] the warm start's predicted update
+    gptr<float> p, Ap;     // [6][nn] product input and output of capture_linearize
+    gptr<double> scal;     // [kScalars]: r.u, PCG stopped, stopped, stop step, ..., kTerms energies per GN step
+    gptr<double> dots;     // [2][3][ntiles] per-tile r.u, u.Au and r.r sums of two PCG launches
+    gptr<double> cg;       // [8]: (gamma, alpha) of two PCG launches, generation of the final x, b.b
+    gptr<double> nsum;     // [2][2][node blocks] per-block r.u and r.r of two node steps (standard PCG)
     gptr<int> counts;      // [3] visible, contour set, queued large faces
     gptr<int> bigq;        // [nf] faces rasterised by k_raster_big
     gptr<float> state0;    // [12][nn] copy of the start state (restored on a device-detected error)

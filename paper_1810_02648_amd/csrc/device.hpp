@@ -154,12 +154,36 @@ __device__ inline void node_update_from(const ProbDev &pr, int k, const float w[
     for (int a = 0; a < 3; ++a) pr.state[size_t(9 + a) * nn + k] += tau[a];
 }
 
-// The same with (dw, dt) read from the PCG solution x ([6][nn]).
-__device__ inline void node_update(const ProbDev &pr, int k) {
-    const int nn = pr.T.nn;
-    float w[3], tau[3];
-    for (int a = 0; a < 3; ++a) { w[a] = pr.x[size_t(a) * nn + k]; tau[a] = pr.x[size_t(3 + a) * nn + k]; }
-    node_update_from(pr, k, w, tau);
+// Sums out[q] = sum over t < n of a[q * stride + t] (q < N, n >= 1) in
+// float64 that every lane of every wave forms identically, without LDS or
+// barriers: lane l adds a[l], a[l + 64], ... in order (the first four strides'
+// loads of all N rows in flight together), then a fixed butterfly across the
+// wave (each step adds the same two values in every lane of a pair, so all
+// lanes end with the same sums).
+template <int N>
+__device__ inline void wave_sum_n(const CAP_GLOBAL double *a, int stride, int n, double (&out)[N]) {
+    constexpr int U = 4;
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int q = 0; q < N; ++q) out[q] = 0.0;
+    for (int t0 = 0; t0 < n; t0 += 64 * U) {
+        double x[U][N];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int t = min(t0 + lane + 64 * u, n - 1);
+#pragma unroll
+            for (int q = 0; q < N; ++q) x[u][q] = a[size_t(q) * stride + t];
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            if (t0 + lane + 64 * u < n)
+#pragma unroll
+                for (int q = 0; q < N; ++q) out[q] += x[u][q];
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1)
+#pragma unroll
+        for (int q = 0; q < N; ++q) out[q] += __shfl_xor(out[q], o);
 }
 
 // Deterministic block-wide sum of a double: fixed butterfly inside each wave,

@@ -267,6 +267,16 @@ int build_template(const capture_template_desc *d, capture_template **out, int d
         }
         node_pbeg[k + 1] = int(node_pidx.size());
     }
+    // per slot: its node's partial range, and (bit 31 of the end) whether the
+    // slot's tile owns the node (each node is owned by exactly one tile)
+    std::vector<int> slot_pb(slot_node.size()), slot_pe(slot_node.size());
+    for (size_t p = 0; p < slot_node.size(); ++p) {
+        slot_pb[p] = node_pbeg[slot_node[p]];
+        slot_pe[p] = node_pbeg[slot_node[p] + 1];
+    }
+    for (int ti = 0; ti < nt; ++ti)
+        for (int o = tile_obeg[ti]; o < tile_obeg[ti + 1]; ++o)
+            slot_pe[size_t(tile_sbeg[ti]) + owned_slot[o]] |= int(0x80000000u);
     // node graph in-edges (for the warm-start network's backward message passing)
     std::vector<int> in_beg(nn + 1, 0), in_src, out_cnt(nn, 0);
     {
@@ -295,7 +305,8 @@ int build_template(const capture_template_desc *d, capture_template **out, int d
            o_lb = blob.add(list_beg), o_li = blob.add(list_idx), o_npb = blob.add(node_pbeg),
            o_npi = blob.add(node_pidx), o_vfb = blob.add(vf_beg), o_vff = blob.add(vf_face),
            o_me = blob.add(medge), o_ib = blob.add(in_beg), o_is = blob.add(in_src), o_oc = blob.add(out_cnt),
-           o_sd = blob.add(slot_dest), o_pcp = blob.add(plan_cpos), o_ocp = blob.add(owned_cpos);
+           o_sd = blob.add(slot_dest), o_pcp = blob.add(plan_cpos), o_ocp = blob.add(owned_cpos),
+           o_spb = blob.add(slot_pb), o_spe = blob.add(slot_pe);
     void *mem = nullptr;
     hipError_t e = hipMalloc(&mem, blob.bytes.size());
     if (e != hipSuccess) return fail(CAPTURE_ENOMEM, "template: device allocation failed");
@@ -318,6 +329,7 @@ int build_template(const capture_template_desc *d, capture_template **out, int d
     D.node_pbeg = (const int *)at(o_npb); D.node_pidx = (const int *)at(o_npi);
     D.vf_beg = (const int *)at(o_vfb); D.vf_face = (const int *)at(o_vff); D.medge = (const int *)at(o_me);
     D.slot_dest = (const int *)at(o_sd);
+    D.slot_pb = (const int *)at(o_spb); D.slot_pe = (const int *)at(o_spe);
     D.plan_cpos = (const uint16_t *)at(o_pcp);
     D.owned_cpos = (const uint32_t *)at(o_ocp);
     D.in_beg = (const int *)at(o_ib); D.in_src = (const int *)at(o_is); D.out_cnt = (const int *)at(o_oc);

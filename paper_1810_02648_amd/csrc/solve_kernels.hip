@@ -310,26 +310,77 @@ __global__ __launch_bounds__(kTileThreads) void k_linearize(const ProbDev *__res
 }
 
 // ----------------------------------------------------------------------------
-// Matrix-free J^T |B| J p per tile: dV_i = sum_j w_j (w_k x q_j + tau_k),
+// Matrix-free J^T |B| J v per tile: dV_i = sum_j w_j (w_k x q_j + tau_k),
 // f_i = H_i dV_i, node contributions w_j [q_j x f_i; f_i]; regulariser edges
 // u = w_k x e_kl + tau_k - tau_l add w_a [e x u; u] to k and w_a [0; -u] to l.
+// Per-tile partial sums, one per (tile, slot node); the nodes add their
+// partials in tile order.  The PCG vectors are float64, the product float32.
+//
+// The launch also holds the vector step of Jacobi-preconditioned CG
+// (M = diag(A)^-1) that precedes the product, for the nodes of the tile's
+// slots: the tile that owns a node stores its new vectors, the others compute
+// the same values for their own use.  Two arrangements of the iteration:
+//
+// kCgFused (Chronopoulos-Gear; one launch per iteration).  The two inner
+// products of an iteration, r.u and u.Au, are both known before the next
+// vector step: each tile sums its share (r.u over the nodes it owns, u.Au
+// over its slot partials), and every workgroup of the next launch adds the
+// tile sums in the same fixed order, so all of them form the same scalars.
+// With u_0 = M r_0 and p_{-1} = s_{-1} = 0, launch j >= 1 forms
+//   gamma = r_{j-1}.u_{j-1},  delta = u_{j-1}.A u_{j-1},
+//   beta = gamma / gamma_{j-2} (0 for j = 1),  den = delta - beta gamma / alpha_{j-2} (= p.Ap),
+//   alpha = gamma / den, and stops (x stays x_{j-1}) if den <= 0 or gamma == 0;
+//   p_{j-1} = u_{j-1} + beta p_{j-2},  s_{j-1} = A u_{j-1} + beta s_{j-2} (= A p_{j-1}),
+//   x_j = x_{j-1} + alpha p_{j-1},  r_j = r_{j-1} - alpha s_{j-1},  u_j = M r_j,
+// then multiplies u_j; launch 0 only multiplies u_0.  In exact arithmetic
+// these are the iterates of the standard recurrence; in floating point the
+// recurrence for s = A p lets rounding accumulate, so this arrangement serves
+// short schedules (k_cg_finish completes the last iteration).
+//
+// kCgStandard (two launches per iteration, with k_pcg_node).  Launch j forms
+// p_j = u_j + beta_{j-1} p_{j-1} (beta from the r.u sums of k_pcg_node's
+// blocks; p_0 = u_0) and multiplies it, summing p_j.Ap_j per tile; k_pcg_node
+// then updates x, r and u from the complete A p_j.  Used for large grids
+// (fewer registers, no per-tile redundancy beyond p) and long schedules.
+//
+// j < 0 (either mode): multiply the vector p of capture_linearize.
+// Vectors of generation m live in buffer m & 1 (fused: x, r, u of launch j in
+// j & 1, its p and s in (j - 1) & 1; standard: p_j in j & 1), and the partials
+// of fused launch j in components 6 (j & 1) .. 6 (j & 1) + 5 of `partial`, so
+// no launch writes what another workgroup of the same launch reads.
 // ----------------------------------------------------------------------------
+// Partials of a node read together (a node is touched by a handful of tiles;
+// further ones, if any, one after another).
+constexpr int kParts = 8;
+constexpr int kCgFused = 0, kCgStandard = 1;
+
+// (component, slot) items per thread whose loads are in flight together: two
+// for grids the chip holds at once, one (fewer registers, more workgroups
+// per CU) for larger grids
 template <int kSplit>
-__global__ __launch_bounds__(kTileThreads) void k_apply(const ProbDev *__restrict__ P, const TileDesc *__restrict__ D) {
+constexpr int cg_group() { return kSplit ? 1 : 2; }
+
+template <int kSplit, int kMode>
+__global__ __launch_bounds__(kTileThreads) void k_cg(const ProbDev *__restrict__ P, const TileDesc *__restrict__ D, int j) {
     extern __shared__ float lds[];
     __shared__ int lbeg[kMaxTileSlots + 1];
     __shared__ int ldest[kMaxTileSlots];
+    constexpr int kCgGroup = cg_group<kSplit>();
+    constexpr bool kFused = kMode == kCgFused;
+    __shared__ double red[kTileThreads / 64][3];
+    __shared__ float psum[6][kMaxTileSlots];      // the slot sums (for u.Au / p.Ap in one fixed order)
     const TileDesc d = D[xcd_item(blockIdx.x, gridDim.x)];
     if (d.prob < 0) return;
     const ProbDev &pr = P[d.prob];
     const TemplateDev &T = pr.T;
-    const int nv = T.nv, nn = T.nn, ns = d.ns, nown = d.nown;
+    const int nv = T.nv, nn = T.nn, ns = d.ns, nown = d.nown, nt = T.ntiles;
     // Global reads come in two dependent rounds: indices (vertex codes and
     // contribution positions, slot nodes, run offsets, destinations, owned
-    // edges) and then the data they select; the stop flag is tested between.
-    // The first round is branch-free: every thread loads at clamped (in-bounds)
-    // positions and replaces what lies outside its ranges afterwards, so all
-    // of its loads are in flight together.
+    // edges, the vector items' nodes and partial ranges, the previous
+    // launches' sums) and then the data they select; the stop flag is tested
+    // between.  The first round is branch-free: every thread loads at clamped
+    // (in-bounds) positions and replaces what lies outside its ranges
+    // afterwards, so all of its loads are in flight together.
     static_assert(kMaxTileSlots < kTileThreads, "one thread per slot and run offset");
     const int lv = threadIdx.x, p = d.vb + lv;
     const bool has_v = lv < d.nvt, has_s = lv < ns, has_e = lv < nown * 8;
@@ -338,13 +389,42 @@ __global__ __launch_bounds__(kTileThreads) void k_apply(const ProbDev *__restric
     uint8_t code = pr.vcode[pv];
     int cp[4];
 #pragma unroll
-    for (int j = 0; j < 4; ++j) cp[j] = T.plan_cpos[size_t(j) * nv + pv];
+    for (int q = 0; q < 4; ++q) cp[q] = T.plan_cpos[size_t(q) * nv + pv];
     int snode = T.slot_node[ps];
     const int sdest = T.slot_dest[ps];
     const int lb = T.list_beg[pl];
     int e_so = T.owned_slot[po], e_se = T.owned_eslot[pe8];
     uint32_t e_cp = T.owned_cpos[pe8];
     const int l0 = T.list_beg[d.sb];
+    // vector items: item i = c * ns + s (component c of slot s's node)
+    const int nsv = max(ns, 1), nitems = 6 * ns;
+    int in_node[kCgGroup], in_pb[kCgGroup], in_pe[kCgGroup];
+    auto item_index = [&](int g0) {
+#pragma unroll
+        for (int m = 0; m < kCgGroup; ++m) {
+            const int i = min(g0 + lv + m * kTileThreads, max(nitems - 1, 0));
+            const int c = i / nsv, gs = min(d.sb + (i - c * nsv), T.nslots - 1);
+            in_node[m] = T.slot_node[gs];
+            in_pe[m] = T.slot_pe[gs];
+            if (kFused) in_pb[m] = T.slot_pb[gs];
+        }
+    };
+    item_index(0);
+    // the previous launches' sums, formed identically by every wave: fused,
+    // the tiles' r.u, u.Au and r.r of launch j - 1; standard, the node
+    // blocks' r.u and r.r of k_pcg_node j - 1
+    double tsum[3] = {0.0, 0.0, 0.0};
+    if (j >= 1) {
+        if (kFused) {
+            wave_sum_n<3>(pr.dots.g() + size_t((j - 1) & 1) * 3 * nt, nt, nt, tsum);
+        } else {
+            const int nb = (nn + 255) / 256;
+            double ns2[2];
+            wave_sum_n<2>(pr.nsum.g() + size_t((j - 1) & 1) * 2 * nb, nb, nb, ns2);
+            tsum[0] = ns2[0];
+            tsum[2] = ns2[1];
+        }
+    }
     const double pcg_stopped = pr.scal[1];     // read here, tested below
     // the destinations and run offsets are consumed here, unconditionally, so
     // that their loads are not moved into the branches below (behind the rest)
@@ -352,7 +432,7 @@ __global__ __launch_bounds__(kTileThreads) void k_apply(const ProbDev *__restric
     if (!has_v) {
         code = 0;
 #pragma unroll
-        for (int j = 0; j < 4; ++j) cp[j] = 0;
+        for (int q = 0; q < 4; ++q) cp[q] = 0;
     }
     if (!has_s) snode = 0;
     if (!has_e) {
@@ -370,25 +450,142 @@ __global__ __launch_bounds__(kTileThreads) void k_apply(const ProbDev *__restric
         packed = T.plan_slot[p];
         v[0] = pr.px[p]; v[1] = pr.px[nv + p]; v[2] = pr.px[2 * nv + p];
 #pragma unroll
-        for (int j = 0; j < 4; ++j) w[j] = T.plan_w[size_t(j) * nv + p];
+        for (int q = 0; q < 4; ++q) w[q] = T.plan_w[size_t(q) * nv + p];
 #pragma unroll
         for (int q6 = 0; q6 < 6; ++q6) Hm[q6] = pr.Hm[size_t(q6) * nv + p];
     }
-    // LDS: one 80-byte record per slot (R, node position, p: five float4),
-    // then contributions [3][NC] (kSplit) or [6][NC]
+    // LDS: one 80-byte record per slot (R, node position, the vector
+    // multiplied: five float4), then contributions [3][NC] (kSplit) or [6][NC]
     float4 *S = reinterpret_cast<float4 *>(lds);
+    float *Sf = lds;
     float *C = lds + kSlotRec * ns;
-    if (has_s) {      // R, position and p of the slot's node
-        float sv[20];
+    if (has_s) {      // R and position of the slot's node
+        float sv[12];
 #pragma unroll
         for (int q = 0; q < 9; ++q) sv[q] = pr.state[size_t(q) * nn + snode];
 #pragma unroll
         for (int q = 0; q < 3; ++q) sv[9 + q] = pr.gpos[size_t(q) * nn + snode];
 #pragma unroll
-        for (int q = 0; q < 6; ++q) sv[12 + q] = pr.p[size_t(q) * nn + snode];
-        sv[18] = sv[19] = 0.0f;
+        for (int q = 0; q < 3; ++q) S[5 * lv + q] = make_float4(sv[4 * q], sv[4 * q + 1], sv[4 * q + 2], sv[4 * q + 3]);
+        Sf[kSlotRec * lv + 18] = 0.0f;
+        Sf[kSlotRec * lv + 19] = 0.0f;
+    }
+    // the vector step, one group of items at a time (one group unless the
+    // tile has more than kCgGroup * kTileThreads / 6 slots)
+    const int gp = (j - 1) & 1;                      // generation j - 1
+    double gam = 0.0, rr = 0.0;                      // fused: owned r_j . u_j and r_j . r_j
+    double alpha = 0.0, beta = 0.0;
+    for (int g0 = 0; g0 < nitems; g0 += kCgGroup * kTileThreads) {
+        if (g0 > 0) item_index(g0);
+        float iv[kCgGroup];                          // j < 0: the vector to multiply
+        double iu[kCgGroup], ir[kCgGroup], ix[kCgGroup], ipo[kCgGroup], iso[kCgGroup];
+        float idi[kCgGroup];
+        float ipart[kCgGroup][kParts];
 #pragma unroll
-        for (int q = 0; q < 5; ++q) S[5 * lv + q] = make_float4(sv[4 * q], sv[4 * q + 1], sv[4 * q + 2], sv[4 * q + 3]);
+        for (int m = 0; m < kCgGroup; ++m) {
+            const int i = min(g0 + lv + m * kTileThreads, max(nitems - 1, 0));
+            const int c = i / nsv;
+            const size_t o = size_t(c) * nn + in_node[m];
+            if (j < 0) {
+                iv[m] = pr.p[o];
+            } else if (!kFused) {                    // u_j and p_{j-1}
+                iu[m] = pr.vu[j & 1][o];
+                if (j >= 1) ipo[m] = pr.vp[gp][o];
+            } else if (j == 0) {
+                iu[m] = pr.vu[0][o];
+            } else {
+                iu[m] = pr.vu[gp][o]; ir[m] = pr.vr[gp][o]; ix[m] = pr.vx[gp][o]; idi[m] = pr.dinv[o];
+                if (j >= 2) { ipo[m] = pr.vp[j & 1][o]; iso[m] = pr.vs[j & 1][o]; }
+                const int pe = in_pe[m] & 0x7fffffff, qmax = max(pe - 1, 0);
+                const CAP_GLOBAL float *pp = pr.partial.g() + size_t(6 * gp + c) * T.nslots;
+#pragma unroll
+                for (int q = 0; q < kParts; ++q) ipart[m][q] = pp[min(in_pb[m] + q, qmax)];
+            }
+        }
+        if (j >= 1 && g0 == 0) {
+            // the scalars (the same in every workgroup)
+            const double bb = pr.cg[5];
+            if (kFused) {       // iteration j - 1
+                const double gamma = j == 1 ? pr.scal[0] : tsum[0], delta = tsum[1];
+                const double rho = j == 1 ? bb : tsum[2];
+                double den = delta;
+                if (j >= 2) {
+                    const CAP_GLOBAL double *cg = pr.cg.g() + 2 * gp;
+                    beta = gamma / cg[0];
+                    den = delta - beta * gamma / cg[1];
+                }
+                // p.Ap <= 0, r.u == 0 or ||r_{j-1}|| within the tolerance: x stays x_{j-1}
+                if (den <= 0.0 || gamma == 0.0 || (pr.pcg_tol2 > 0.0 && rho <= pr.pcg_tol2 * bb)) {
+                    if (d.tile == 0 && lv == 0) {
+                        pr.scal[1] = 1.0;
+                        pr.cg[4] = double(j - 1);
+                    }
+                    return;
+                }
+                alpha = gamma / den;
+                if (d.tile == 0 && lv == 0) {
+                    pr.cg[2 * (j & 1)] = gamma;
+                    pr.cg[2 * (j & 1) + 1] = alpha;
+                }
+            } else {            // beta_{j-1} = r_j.u_j / r_{j-1}.u_{j-1}
+                const double gamma = tsum[0], rho = tsum[2];
+                // r.u == 0 or ||r_j|| within the tolerance: x stays x_j
+                if (gamma == 0.0 || (pr.pcg_tol2 > 0.0 && rho <= pr.pcg_tol2 * bb)) {
+                    if (d.tile == 0 && lv == 0) {
+                        pr.scal[1] = 1.0;
+                        pr.cg[4] = double(j);
+                    }
+                    return;
+                }
+                beta = gamma / pr.cg[2 * gp];
+            }
+        }
+#pragma unroll
+        for (int m = 0; m < kCgGroup; ++m) {
+            const int i = g0 + lv + m * kTileThreads;
+            if (i >= nitems) continue;
+            const int c = i / nsv, s = i - c * nsv;
+            float val;
+            if (j < 0) {
+                val = iv[m];
+            } else if (!kFused) {
+                // rounded to float32 once: the vector multiplied is the one accumulated
+                const double pn = j == 0 ? iu[m] : double(float(fma(beta, ipo[m], iu[m])));
+                if (in_pe[m] < 0) pr.vp[j & 1][size_t(c) * nn + in_node[m]] = pn;   // owner stores p_j
+                val = float(pn);
+            } else if (j == 0) {
+                val = float(iu[m]);
+            } else {
+                const int pe = in_pe[m] & 0x7fffffff;
+                float wv = 0.0f;        // A u_{j-1} of the node: its partials in order
+#pragma unroll
+                for (int q = 0; q < kParts; ++q)
+                    if (in_pb[m] + q < pe) wv += ipart[m][q];
+                for (int q = in_pb[m] + kParts; q < pe; ++q) wv += pr.partial[size_t(6 * gp + c) * T.nslots + q];
+                double pn, sn;
+                if (j == 1) {
+                    pn = iu[m];
+                    sn = double(wv);
+                } else {
+                    pn = fma(beta, ipo[m], iu[m]);
+                    sn = fma(beta, iso[m], double(wv));
+                }
+                const double rn = fma(-alpha, sn, ir[m]);
+                const double un = double(float(double(idi[m]) * rn));   // as multiplied
+                if (in_pe[m] < 0) {        // this tile owns the node: store its vectors
+                    const size_t o = size_t(c) * nn + in_node[m];
+                    pr.vp[gp][o] = pn;
+                    pr.vs[gp][o] = sn;
+                    pr.vx[j & 1][o] = fma(alpha, pn, ix[m]);
+                    pr.vr[j & 1][o] = rn;
+                    pr.vu[j & 1][o] = un;
+                    gam += rn * un;
+                    rr += rn * rn;
+                }
+                val = float(un);        // the product runs in float32
+            }
+            Sf[kSlotRec * s + 12 + c] = val;
+        }
     }
     __syncthreads();
     const int NC = lbeg[ns] | 1;     // odd component stride: components in different LDS banks
@@ -399,51 +596,51 @@ __global__ __launch_bounds__(kTileThreads) void k_apply(const ProbDev *__restric
     // (shorter workgroup life, for small grids).
     float *C2 = kSplit ? C : C + 3 * NC;    // translational components
     float f[3] = {0, 0, 0};
-    if (has_v) {
+    if (d.nvt > lv) {
         if (act) {
             float q[4][3];
             float dV[3] = {0, 0, 0};
 #pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                const int sl = (packed >> (8 * j)) & 0xff;
+            for (int b = 0; b < 4; ++b) {
+                const int sl = (packed >> (8 * b)) & 0xff;
                 float R[9], g[3], pp[6];
                 slot_rec(S, sl, R, g, pp);
                 float dd[3] = {v[0] - g[0], v[1] - g[1], v[2] - g[2]};
-                rot_apply(R, dd, q[j]);
+                rot_apply(R, dd, q[b]);
                 float oxq[3];
-                cross3(pp, q[j], oxq);
+                cross3(pp, q[b], oxq);
 #pragma unroll
-                for (int a = 0; a < 3; ++a) dV[a] += w[j] * (oxq[a] + pp[3 + a]);
+                for (int a = 0; a < 3; ++a) dV[a] += w[b] * (oxq[a] + pp[3 + a]);
             }
             f[0] = (Hm[0] * dV[0] + Hm[1] * dV[1]) + Hm[2] * dV[2];
             f[1] = (Hm[1] * dV[0] + Hm[3] * dV[1]) + Hm[4] * dV[2];
             f[2] = (Hm[2] * dV[0] + Hm[4] * dV[1]) + Hm[5] * dV[2];
 #pragma unroll
-            for (int j = 0; j < 4; ++j) {
+            for (int b = 0; b < 4; ++b) {
                 float qxf[3];
-                cross3(q[j], f, qxf);
-                float *cj = C + cp[j];
-                cj[0] = w[j] * qxf[0]; cj[NC] = w[j] * qxf[1]; cj[2 * NC] = w[j] * qxf[2];
+                cross3(q[b], f, qxf);
+                float *cj = C + cp[b];
+                cj[0] = w[b] * qxf[0]; cj[NC] = w[b] * qxf[1]; cj[2 * NC] = w[b] * qxf[2];
             }
         } else {
 #pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                w[j] = 0.0f;      // zero contributions in both passes
-                for (int q3 = 0; q3 < 3; ++q3) C[q3 * NC + cp[j]] = 0.0f;
+            for (int b = 0; b < 4; ++b) {
+                w[b] = 0.0f;      // zero contributions in both passes
+                for (int q3 = 0; q3 < 3; ++q3) C[q3 * NC + cp[b]] = 0.0f;
             }
         }
     }
     const float wa = pr.w_arap;
     // regulariser edge k -> l: u = w_k x e_kl + tau_k - tau_l; rotational part e x u
     auto edge_u = [&](int so, int se, float ekl[3], float u[3]) {
-        float Rk[9], gk[3], pk[6], Rl[9], gl[3], pl[6];
+        float Rk[9], gk[3], pk[6], Rl[9], gl[3], pl6[6];
         slot_rec(S, so, Rk, gk, pk);
-        slot_rec(S, se, Rl, gl, pl);
+        slot_rec(S, se, Rl, gl, pl6);
         float dd[3] = {gl[0] - gk[0], gl[1] - gk[1], gl[2] - gk[2]};
         rot_apply(Rk, dd, ekl);
         float oxe[3];
         cross3(pk, ekl, oxe);
-        u[0] = (oxe[0] + pk[3]) - pl[3]; u[1] = (oxe[1] + pk[4]) - pl[4]; u[2] = (oxe[2] + pk[5]) - pl[5];
+        u[0] = (oxe[0] + pk[3]) - pl6[3]; u[1] = (oxe[1] + pk[4]) - pl6[4]; u[2] = (oxe[2] + pk[5]) - pl6[5];
     };
     float eu[3] = {0, 0, 0};
     for (int idx = lv; idx < nown * 8; idx += kTileThreads) {
@@ -460,19 +657,23 @@ __global__ __launch_bounds__(kTileThreads) void k_apply(const ProbDev *__restric
         c1[0] = 0.0f; c1[NC] = 0.0f; c1[2 * NC] = 0.0f;
         if (idx == lv) { eu[0] = u[0]; eu[1] = u[1]; eu[2] = u[2]; }
     }
+    // partials of this launch (also kept in LDS for u.Au / p.Ap)
+    const size_t pbase = size_t(j < 0 || !kFused ? 0 : 6 * (j & 1)) * T.nslots;
     if (kSplit) {
         __syncthreads();
         for (int pair = lv; pair < ns * 3; pair += kTileThreads) {
             const int s = pair / 3, comp = pair - s * 3;
-            pr.partial[size_t(comp) * T.nslots + ldest[s]] = run_sum(C + comp * NC, lbeg[s], lbeg[s + 1]);
+            const float sum = run_sum(C + comp * NC, lbeg[s], lbeg[s + 1]);
+            pr.partial[pbase + size_t(comp) * T.nslots + ldest[s]] = sum;
+            psum[comp][s] = sum;
         }
         __syncthreads();
     }
-    if (has_v) {
+    if (d.nvt > lv) {
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            float *cj = C2 + cp[j];
-            cj[0] = w[j] * f[0]; cj[NC] = w[j] * f[1]; cj[2 * NC] = w[j] * f[2];
+        for (int b = 0; b < 4; ++b) {
+            float *cj = C2 + cp[b];
+            cj[0] = w[b] * f[0]; cj[NC] = w[b] * f[1]; cj[2 * NC] = w[b] * f[2];
         }
     }
     for (int idx = lv; idx < nown * 8; idx += kTileThreads) {
@@ -494,27 +695,50 @@ __global__ __launch_bounds__(kTileThreads) void k_apply(const ProbDev *__restric
     __syncthreads();
     constexpr int kComps = kSplit ? 3 : 6;
     for (int pair = lv; pair < ns * kComps; pair += kTileThreads) {
-        const int s = pair / kComps, comp = pair - s * kComps;
-        pr.partial[size_t((kSplit ? 3 : 0) + comp) * T.nslots + ldest[s]] = run_sum(C + comp * NC, lbeg[s], lbeg[s + 1]);
+        const int s = pair / kComps, comp = pair - s * kComps, cg = (kSplit ? 3 : 0) + comp;
+        const float sum = run_sum(C + comp * NC, lbeg[s], lbeg[s + 1]);
+        pr.partial[pbase + size_t(cg) * T.nslots + ldest[s]] = sum;
+        psum[cg][s] = sum;
+    }
+    if (j >= 0) {
+        // v.Av of this tile (v = u fused, p standard): each slot's six partials
+        // times its node's v, in one order whichever reduction variant ran
+        __syncthreads();
+        if (kFused) {
+            double vav = 0.0;
+            if (lv < ns)
+#pragma unroll
+                for (int c = 0; c < 6; ++c) vav += double(Sf[kSlotRec * lv + 12 + c]) * double(psum[c][lv]);
+            double ts[3] = {gam, vav, rr};
+            block_sum_n<kTileThreads, 3>(ts, red);
+            if (lv == 0) {
+                CAP_GLOBAL double *dp = pr.dots.g() + size_t(j & 1) * 3 * nt;
+                dp[d.tile] = ts[0];
+                dp[nt + d.tile] = ts[1];
+                dp[2 * nt + d.tile] = ts[2];
+            }
+        } else if (lv < 64) {      // p.Ap of the tile: the first wave adds the slots (no further barrier)
+            double v = 0.0;
+            for (int s = lv; s < ns; s += 64)
+#pragma unroll
+                for (int c = 0; c < 6; ++c) v += double(Sf[kSlotRec * s + 12 + c]) * double(psum[c][s]);
+#pragma unroll
+            for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+            if (lv == 0) pr.dots[nt + d.tile] = v;
+        }
     }
 }
 
-template __global__ void k_apply<0>(const ProbDev *, const TileDesc *);
-template __global__ void k_apply<1>(const ProbDev *, const TileDesc *);
+template __global__ void k_cg<0, kCgFused>(const ProbDev *, const TileDesc *, int);
+template __global__ void k_cg<0, kCgStandard>(const ProbDev *, const TileDesc *, int);
+template __global__ void k_cg<1, kCgStandard>(const ProbDev *, const TileDesc *, int);
 
 // ----------------------------------------------------------------------------
 // Node kernels: one workgroup per problem.
 // ----------------------------------------------------------------------------
 
-constexpr int kItems = 8192 / kNodeThreads;   // node kernels: 8192 items (1365 nodes) in registers
 constexpr int kInitItems = 16;   // k_node_init (kInitThreads): the same 8192 items, 256 VGPRs per lane
 
-// Sum of partials [pb, pe) of component c (components are rows of `stride`
-// floats: the partials are stored component-major, so the parts of
-// neighbouring nodes are neighbours in memory) in order; the
-// first kParts loads are issued together (a node is touched by a handful of
-// tiles), the rest, if any, one after another.
-constexpr int kParts = 8;
 
 __device__ inline float sum_parts(gptr<const float> partial, int stride, int c, int pb, int pe) {
     float v[kParts];
@@ -565,7 +789,7 @@ __device__ inline float gather_node(const TemplateDev &T, gptr<const float> part
 }
 
 // After a linearisation: b, diag, Jacobi preconditioner, PCG start vectors
-// (x = 0, r = b, z = M^-1 r, p = z), r.z, and the energy of GN step `gn`.
+// (x_0 = 0, r_0 = b, u_0 = M^-1 r_0, generation 0), r.u, and the energy of GN step `gn`.
 // One thread per (component, node) item; every load is issued before the
 // stop tests, and r.z and the energy terms share one block reduction.
 // check_target bit 0: stop when the energy reaches the target; bit 1: the
@@ -577,12 +801,12 @@ __device__ inline float gather_node(const TemplateDev &T, gptr<const float> part
 // scal[6] receive the two energies, scal[5] the rejection.
 __global__ __launch_bounds__(kInitThreads) void k_node_init(const ProbDev *__restrict__ P, int gn, int energy_only,
                                                           int check_target, int slot_prev, int gn_iters) {
-    __shared__ double red[kInitThreads / 64][1 + kTerms];
+    __shared__ double red[kInitThreads / 64][2 + kTerms];
     __shared__ int reject;
     const ProbDev &pr = P[blockIdx.x];
     const TemplateDev &T = pr.T;
     const int nn = T.nn, n6 = 6 * nn;
-    double v[1 + kTerms] = {0, 0, 0, 0, 0, 0};   // r.z, then the energy terms
+    double v[2 + kTerms] = {0, 0, 0, 0, 0, 0, 0};   // r.u, the energy terms, b.b
     for (int t = threadIdx.x; t < T.ntiles; t += blockDim.x)
         for (int q = 0; q < kTerms; ++q) v[1 + q] += pr.tile_e[size_t(t) * kTerms + q];
     const bool regs = n6 <= kInitItems * kInitThreads;
@@ -627,10 +851,11 @@ __global__ __launch_bounds__(kInitThreads) void k_node_init(const ProbDev *__res
                     if (i < n6) {
                         const float b = bb[h], d = dd[h];
                         const float mi = d > 0.0f ? 1.0f / d : 1.0f;
-                        const float z = mi * b;
+                        const double u = double(mi * b);     // float32, as multiplied
                         pr.b[i] = b; pr.diag[i] = d; pr.dinv[i] = mi;
-                        pr.x[i] = 0.0f; pr.r[i] = b; pr.z[i] = z; pr.p[i] = z;
-                        v[0] += double(b) * double(z);
+                        pr.vx[0][i] = 0.0; pr.vr[0][i] = double(b); pr.vu[0][i] = u;
+                        v[0] += double(b) * u;
+                        v[1 + kTerms] += double(b) * double(b);
                     }
                 }
             }
@@ -640,19 +865,22 @@ __global__ __launch_bounds__(kInitThreads) void k_node_init(const ProbDev *__res
                 const float b = gather_node(T, pr.partial, T.nslots, k, c);
                 const float d = gather_node(T, pr.partial, T.nslots, k, 6 + c);
                 const float mi = d > 0.0f ? 1.0f / d : 1.0f;
-                const float z = mi * b;
+                const double u = double(mi * b);     // float32, as multiplied
                 pr.b[i] = b; pr.diag[i] = d; pr.dinv[i] = mi;
-                pr.x[i] = 0.0f; pr.r[i] = b; pr.z[i] = z; pr.p[i] = z;
-                v[0] += double(b) * double(z);
+                pr.vx[0][i] = 0.0; pr.vr[0][i] = double(b); pr.vu[0][i] = u;
+                v[0] += double(b) * u;
+                v[1 + kTerms] += double(b) * double(b);
             }
         }
     }
-    block_sum_n<kInitThreads, 1 + kTerms>(v, red);
+    block_sum_n<kInitThreads, 2 + kTerms>(v, red);
     if (threadIdx.x == 0) {
         const double rz = v[0];
         if (!energy_only) {
             pr.scal[0] = rz;
             pr.scal[1] = rz == 0.0 ? 1.0 : 0.0;
+            pr.cg[4] = 0.0;        // the solution so far: x_0 = 0 (generation 0)
+            pr.cg[5] = v[1 + kTerms];
             if ((check_target & 1) && v[1] + v[2] + v[4] + v[5] <= pr.target) {   // x = 0 above, so the step's update is void
                 pr.scal[1] = 1.0;
                 pr.scal[2] = 1.0;
@@ -692,196 +920,153 @@ __global__ __launch_bounds__(kNodeThreads) void k_node_gather(const ProbDev *__r
     }
 }
 
-// One PCG iteration after k_apply: A p, alpha, x/r/z updates, beta, p.
-// Stops (for this GN step) when p.Ap <= 0 or r.z == 0.  `last`: apply the
-// node update afterwards; `update_only`: only that.  Items are (component,
-// node) pairs; each thread keeps its items' values in registers between phases.
-__global__ __launch_bounds__(kNodeThreads) void k_node_pcg(const ProbDev *__restrict__ P, int last, int update_only) {
-    __shared__ double red[kNodeThreads / 64];
-    const ProbDev &pr = P[blockIdx.x];
+// After the last product of a Gauss-Newton step (n = pcg_iters launches of
+// k_cg): the last iteration's scalars from the tile sums of launch n - 1, then
+// x_n = x_{n-1} + alpha (u_{n-1} + beta p_{n-2}) (or the x at which the
+// iteration stopped) and the node update R <- Exp(dw) R, t <- t + dt.  A solve
+// stopped at its target energy is left as it is.  Grid: (node blocks, problems).
+__global__ __launch_bounds__(256) void k_cg_finish(const ProbDev *__restrict__ P, int n) {
+    const ProbDev &pr = P[blockIdx.y];
     const TemplateDev &T = pr.T;
-    const int nn = T.nn, n6 = 6 * nn;
-    if (!update_only && n6 <= kItems * kNodeThreads) {
-        // every load of the iteration up front (p, x, r, 1/diag, the node's
-        // partial range, r.z and the stop flag), then the partial sums
-        float pp[kItems], xx[kItems], rr[kItems], di[kItems];
-        int pb[kItems], pe[kItems];
+    const int nn = T.nn, nt = T.ntiles, lv = threadIdx.x;
+    if (int(blockIdx.x) * 256 >= nn) return;
+    if (pr.scal[2] != 0.0) return;                  // stopped at the target energy: no update
+    const int k = blockIdx.x * 256 + lv;
+    const int gl = (n - 1) & 1;
+    double ts[3] = {0.0, 0.0, 0.0};
+    const bool stopped = n == 0 || pr.scal[1] != 0.0;
+    if (!stopped) {
+        wave_sum_n<3>(pr.dots.g() + size_t(gl) * 3 * nt, nt, nt, ts);
+    }
+    double xu[6], xo[6], po[6];
+    if (k < nn) {
+        const int xb = stopped ? (n == 0 ? 0 : int(pr.cg[4]) & 1) : gl;
 #pragma unroll
-        for (int j = 0; j < kItems; ++j) {
-            const int i = threadIdx.x + j * kNodeThreads;
-            pp[j] = xx[j] = rr[j] = di[j] = 0.0f;
-            pb[j] = pe[j] = 0;
-            if (i < n6) {
-                const int k = i % nn;
-                pp[j] = pr.p[i]; xx[j] = pr.x[i]; rr[j] = pr.r[i]; di[j] = pr.dinv[i];
-                pb[j] = T.node_pbeg[k]; pe[j] = T.node_pbeg[k + 1];
-            }
+        for (int c = 0; c < 6; ++c) {
+            xo[c] = pr.vx[xb][size_t(c) * nn + k];
+            xu[c] = pr.vu[gl][size_t(c) * nn + k];
+            po[c] = n >= 2 ? pr.vp[n & 1][size_t(c) * nn + k] : 0.0;
         }
-        const double rz = pr.scal[0];
-        if (pr.scal[1] == 0.0) {
-            float ap[kItems];
-            double pap = 0.0;
-#pragma unroll
-            for (int j = 0; j < kItems; ++j) {
-                const int c = (threadIdx.x + j * kNodeThreads) / nn;
-                ap[j] = sum_parts(pr.partial, T.nslots, c, pb[j], pe[j]);
-                pap += double(pp[j]) * double(ap[j]);
-            }
-            pap = block_sum<kNodeThreads>(pap, red);
-            if (pap <= 0.0) {
-                if (threadIdx.x == 0) pr.scal[1] = 1.0;
-            } else {
-                const double alpha = rz / pap;
-                double rz2 = 0.0;
-                float zz[kItems];
-#pragma unroll
-                for (int j = 0; j < kItems; ++j) {
-                    const int i = threadIdx.x + j * kNodeThreads;
-                    zz[j] = 0.0f;
-                    if (i < n6) {
-                        pr.x[i] = float(fma(alpha, double(pp[j]), double(xx[j])));
-                        const float r = float(fma(-alpha, double(ap[j]), double(rr[j])));
-                        const float z = di[j] * r;
-                        pr.r[i] = r;
-                        zz[j] = z;
-                        rz2 += double(r) * double(z);
-                    }
-                }
-                rz2 = block_sum<kNodeThreads>(rz2, red);
-                const double beta = rz2 / rz;
-#pragma unroll
-                for (int j = 0; j < kItems; ++j) {
-                    const int i = threadIdx.x + j * kNodeThreads;
-                    if (i < n6) pr.p[i] = float(fma(beta, double(pp[j]), double(zz[j])));
-                }
-                if (threadIdx.x == 0) {
-                    pr.scal[0] = rz2;
-                    if (rz2 == 0.0) pr.scal[1] = 1.0;
-                }
-            }
+    }
+    bool step = false;
+    double alpha = 0.0, beta = 0.0;
+    if (!stopped) {
+        const double gamma = n == 1 ? pr.scal[0] : ts[0], delta = ts[1];
+        const double bb = pr.cg[5], rho = n == 1 ? bb : ts[2];
+        double den = delta;
+        if (n >= 2) {
+            const CAP_GLOBAL double *cg = pr.cg.g() + 2 * gl;
+            beta = gamma / cg[0];
+            den = delta - beta * gamma / cg[1];
         }
-    } else if (!update_only && pr.scal[1] == 0.0) {      // more items than registers
-        double pap = 0.0;
-        for (int i = threadIdx.x; i < n6; i += kNodeThreads) {
-            const int c = i / nn, k = i - c * nn;
-            const float a = gather_node(T, pr.partial, T.nslots, k, c);
-            pr.Ap[i] = a;
-            pap += double(pr.p[i]) * double(a);
-        }
-        pap = block_sum<kNodeThreads>(pap, red);
-        const double rz = pr.scal[0];
-        if (pap <= 0.0) {
-            if (threadIdx.x == 0) pr.scal[1] = 1.0;
+        step = !(den <= 0.0 || gamma == 0.0 || (pr.pcg_tol2 > 0.0 && rho <= pr.pcg_tol2 * bb));
+        if (step) alpha = gamma / den;
+    }
+    if (k >= nn) return;
+    float x[6];
+#pragma unroll
+    for (int c = 0; c < 6; ++c) {
+        if (step) {
+            const double pn = n >= 2 ? fma(beta, po[c], xu[c]) : xu[c];
+            x[c] = float(fma(alpha, pn, xo[c]));
         } else {
-            const double alpha = rz / pap;
-            double rz2 = 0.0;
-            for (int i = threadIdx.x; i < n6; i += kNodeThreads) {
-                pr.x[i] = float(fma(alpha, double(pr.p[i]), double(pr.x[i])));
-                const float r = float(fma(-alpha, double(pr.Ap[i]), double(pr.r[i])));
-                const float z = pr.dinv[i] * r;
-                pr.r[i] = r;
-                pr.z[i] = z;
-                rz2 += double(r) * double(z);
-            }
-            rz2 = block_sum<kNodeThreads>(rz2, red);
-            const double beta = rz2 / rz;
-            for (int i = threadIdx.x; i < n6; i += kNodeThreads) pr.p[i] = float(fma(beta, double(pr.p[i]), double(pr.z[i])));
-            if (threadIdx.x == 0) {
-                pr.scal[0] = rz2;
-                if (rz2 == 0.0) pr.scal[1] = 1.0;
-            }
+            x[c] = float(xo[c]);
         }
     }
-    if (last || update_only) {
-        __syncthreads();
-        for (int k = threadIdx.x; k < nn; k += blockDim.x) node_update(pr, k);
-    }
+    node_update_from(pr, k, x, x + 3);
 }
 
-// ----------------------------------------------------------------------------
-// PCG iteration for large node counts, split over several workgroups per
-// problem (blockIdx.x = item block of kSplitItems (component, node) items).
-// Dot products are summed per workgroup, then every workgroup adds the
-// workgroup sums in block order, so all of them see the same value.  r.z
-// alternates between scal[0] (even iterations) and scal[7] (odd), so the
-// workgroup that stores the next value never races a reader of the current.
-// ----------------------------------------------------------------------------
-__device__ inline int split_blocks(int nn) { return (6 * nn + kSplitItems - 1) / kSplitItems; }
-
-// A p from the tile partials, and the workgroup's share of p.Ap.
-__global__ __launch_bounds__(kSplitThreads) void k_pcg_split_a(const ProbDev *__restrict__ P) {
-    __shared__ double red[kSplitThreads / 64];
+// The standard arrangement's node step after product launch j (k_cg with
+// kCgStandard): alpha_j = r_j.u_j / p_j.Ap_j (p.Ap from the tile sums, r.u
+// from the node blocks of step j - 1), then per node x_{j+1} = x_j + alpha p_j,
+// r_{j+1} = r_j - alpha A p_j, u_{j+1} = M r_{j+1}, with the block's r.u and
+// r.r for the next product launch; stops (x stays x_j) if p.Ap <= 0.  `last`:
+// the node update R <- Exp(dw) R, t <- t + dt from the final x follows.  Grid:
+// (node blocks of 256, problems); one thread per node.
+__global__ __launch_bounds__(256) void k_pcg_node(const ProbDev *__restrict__ P, int j, int last) {
+    __shared__ double red[256 / 64][2];
     const ProbDev &pr = P[blockIdx.y];
     const TemplateDev &T = pr.T;
-    const int nn = T.nn, n6 = 6 * nn;
-    if (pr.scal[1] != 0.0 || int(blockIdx.x) >= split_blocks(nn)) return;
-    double pap = 0.0;
-    for (int u = 0; u < kSplitItems / kSplitThreads; ++u) {
-        const int i = blockIdx.x * kSplitItems + u * kSplitThreads + threadIdx.x;
-        if (i < n6) {
-            const int c = i / nn, k = i - c * nn;
-            const float a = gather_node(T, pr.partial, T.nslots, k, c);
-            pr.Ap[i] = a;
-            pap += double(pr.p[i]) * double(a);
-        }
+    const int nn = T.nn, nt = T.ntiles, nb = (nn + 255) / 256, lv = threadIdx.x;
+    if (int(blockIdx.x) >= nb) return;
+    const int k = blockIdx.x * 256 + lv, kc = min(k, nn - 1);
+    // every load up front: the flags, the sums, the node's vectors and partials
+    const double target_stop = pr.scal[2], pcg_stopped = pr.scal[1];
+    double pap1[1], rz1[1];
+    wave_sum_n<1>(pr.dots.g() + nt, nt, nt, pap1);
+    wave_sum_n<1>(pr.nsum.g() + size_t((j + 1) & 1) * 2 * nb, nb, nb, rz1);   // (j - 1) & 1; unused at j = 0
+    const double pap = pap1[0], rz = j == 0 ? pr.scal[0] : rz1[0];
+    const int pb = T.node_pbeg[kc], pe = T.node_pbeg[kc + 1], qmax = max(pe - 1, 0);
+    double xo[6], ro[6], po[6];
+    float di[6], part[6][kParts];
+#pragma unroll
+    for (int c = 0; c < 6; ++c) {
+        const size_t o = size_t(c) * nn + kc;
+        xo[c] = pr.vx[j & 1][o];
+        ro[c] = pr.vr[j & 1][o];
+        po[c] = pr.vp[j & 1][o];
+        di[c] = pr.dinv[o];
+#pragma unroll
+        for (int q = 0; q < kParts; ++q) part[c][q] = pr.partial[size_t(c) * T.nslots + min(pb + q, qmax)];
     }
-    pap = block_sum<kSplitThreads>(pap, red);
-    if (threadIdx.x == 0) pr.dots[blockIdx.x] = pap;
-}
-
-// alpha = r.z / p.Ap; x, r, z updates; the workgroup's share of the new r.z.
-__global__ __launch_bounds__(kSplitThreads) void k_pcg_split_b(const ProbDev *__restrict__ P, int it) {
-    __shared__ double red[kSplitThreads / 64];
-    const ProbDev &pr = P[blockIdx.y];
-    const int nn = pr.T.nn, n6 = 6 * nn, G = split_blocks(nn);
-    if (pr.scal[1] != 0.0 || int(blockIdx.x) >= G) return;
-    double pap = 0.0;
-    for (int w = 0; w < G; ++w) pap += pr.dots[w];
-    if (pap <= 0.0) {
-        if (blockIdx.x == 0 && threadIdx.x == 0) pr.scal[1] = 1.0;
+    if (target_stop != 0.0) return;          // stopped at the target energy: no update
+    float xn[6];
+    if (pcg_stopped != 0.0) {                // stopped earlier: only the final node update
+        if (last && k < nn) {
+            const int xb = int(pr.cg[4]) & 1;
+#pragma unroll
+            for (int c = 0; c < 6; ++c) xn[c] = float(pr.vx[xb][size_t(c) * nn + k]);
+            node_update_from(pr, k, xn, xn + 3);
+        }
         return;
     }
-    const double alpha = pr.scal[(it & 1) ? 7 : 0] / pap;
-    double rz2 = 0.0;
-    for (int u = 0; u < kSplitItems / kSplitThreads; ++u) {
-        const int i = blockIdx.x * kSplitItems + u * kSplitThreads + threadIdx.x;
-        if (i < n6) {
-            pr.x[i] = float(fma(alpha, double(pr.p[i]), double(pr.x[i])));
-            const float r = float(fma(-alpha, double(pr.Ap[i]), double(pr.r[i])));
-            const float z = pr.dinv[i] * r;
-            pr.r[i] = r;
-            pr.z[i] = z;
-            rz2 += double(r) * double(z);
+    if (pap <= 0.0) {                        // x stays x_j
+        if (blockIdx.x == 0 && lv == 0) {
+            pr.scal[1] = 1.0;
+            pr.cg[4] = double(j);
         }
+        if (last && k < nn) {
+#pragma unroll
+            for (int c = 0; c < 6; ++c) xn[c] = float(xo[c]);
+            node_update_from(pr, k, xn, xn + 3);
+        }
+        return;
     }
-    rz2 = block_sum<kSplitThreads>(rz2, red);
-    if (threadIdx.x == 0) pr.dots[G + blockIdx.x] = rz2;
-}
-
-// beta = r.z' / r.z; p = z + beta p; the next r.z into the other slot.  With
-// `last`, the node update follows for this workgroup's share of the nodes.
-__global__ __launch_bounds__(kSplitThreads) void k_pcg_split_c(const ProbDev *__restrict__ P, int it, int last) {
-    const ProbDev &pr = P[blockIdx.y];
-    const int nn = pr.T.nn, n6 = 6 * nn, G = split_blocks(nn);
-    if (int(blockIdx.x) >= G) return;
-    if (pr.scal[1] == 0.0) {
-        double rz2 = 0.0;
-        for (int w = 0; w < G; ++w) rz2 += pr.dots[G + w];
-        const double beta = rz2 / pr.scal[(it & 1) ? 7 : 0];
-        for (int u = 0; u < kSplitItems / kSplitThreads; ++u) {
-            const int i = blockIdx.x * kSplitItems + u * kSplitThreads + threadIdx.x;
-            if (i < n6) pr.p[i] = float(fma(beta, double(pr.p[i]), double(pr.z[i])));
-        }
-        __syncthreads();
-        if (blockIdx.x == 0 && threadIdx.x == 0) {
-            pr.scal[(it & 1) ? 0 : 7] = rz2;
-            if (rz2 == 0.0) pr.scal[1] = 1.0;
+    const double alpha = rz / pap;
+    double g = 0.0, r2 = 0.0;
+    if (k < nn) {
+#pragma unroll
+        for (int c = 0; c < 6; ++c) {
+            float ap = 0.0f;               // A p_j of the node: its partials in order
+#pragma unroll
+            for (int q = 0; q < kParts; ++q)
+                if (pb + q < pe) ap += part[c][q];
+            for (int q = pb + kParts; q < pe; ++q) ap += pr.partial[size_t(c) * T.nslots + q];
+            const size_t o = size_t(c) * nn + k;
+            const double x1 = fma(alpha, po[c], xo[c]);
+            const double r1 = fma(-alpha, double(ap), ro[c]);
+            const double u1 = double(float(double(di[c]) * r1));   // float32, as multiplied
+            xn[c] = float(x1);
+            if (!last) {
+                pr.vx[(j + 1) & 1][o] = x1;
+                pr.vr[(j + 1) & 1][o] = r1;
+                pr.vu[(j + 1) & 1][o] = u1;
+                g += r1 * u1;
+                r2 += r1 * r1;
+            }
         }
     }
     if (last) {
-        const int per = (nn + G - 1) / G;
-        for (int k = blockIdx.x * per + threadIdx.x; k < min(nn, int(blockIdx.x + 1) * per); k += blockDim.x)
-            node_update(pr, k);
+        if (k < nn) node_update_from(pr, k, xn, xn + 3);
+        return;
+    }
+    double s2[2] = {g, r2};
+    block_sum_n<256, 2>(s2, red);
+    if (lv == 0) {
+        CAP_GLOBAL double *np = pr.nsum.g() + size_t(j & 1) * 2 * nb;
+        np[blockIdx.x] = s2[0];
+        np[nb + blockIdx.x] = s2[1];
+        if (blockIdx.x == 0) pr.cg[2 * (j & 1)] = rz;
     }
 }
 

@@ -124,8 +124,12 @@ def params_of(state):
     return so3.log_all(st), st[9:12]
 
 
+@pytest.mark.parametrize("standard", [False, True])
 @pytest.mark.parametrize("name,gn,pcg", [("small0", 5, 10), ("small1", 5, 10), ("mid", 3, 8)])
-def test_solve_matches_schedule_matched_oracle(ctx, frames, name, gn, pcg):
+def test_solve_matches_schedule_matched_oracle(ctx, frames, name, gn, pcg, standard):
+    """Both arrangements of the PCG iteration (one launch per iteration in the
+    Chronopoulos-Gear form, and the standard recurrence) against the oracle's
+    PCG with the same schedule."""
     import paper_1810_02648_amd as cap
     from gpu_util import make_frame
     f = frames[name]
@@ -134,7 +138,7 @@ def test_solve_matches_schedule_matched_oracle(ctx, frames, name, gn, pcg):
     P = onr.Problem(f["xyz"], f["tri"], f["rgb"], g, f["cam"], f["mask"], f["image"], f["weights"])
     ref = onr.solve(P, gn, "pcg", pcg)
     fr = make_frame(ctx, f, g)
-    rep = cap.nonrigid_solve(ctx, fr, cap.params(*f["weights"], gn_iters=gn, pcg_iters=pcg))
+    rep = cap.nonrigid_solve(ctx, fr, cap.params(*f["weights"], gn_iters=gn, pcg_iters=pcg, pcg_standard=standard))
     assert rep["status"] == 0
     assert rep["n_visible"] == ref["n_visible"] and rep["n_boundary"] == ref["n_boundary"]
     r_gpu, t_gpu = params_of(fr.node_state.cpu().numpy())
@@ -209,11 +213,12 @@ def test_batch_equals_single_solves(ctx, frames):
 
 def test_large_tile_grid_equals_single_solves(ctx, frames):
     """A batch whose tile grid exceeds what the chip holds at once (16-vertex
-    tiles, over 1024 tiles in total) takes the two-pass J^T J p reduction; its
-    frames equal their single solves (one-pass reduction) bit for bit."""
+    tiles, over 1024 tiles in total) takes the two-pass J^T J p reduction and
+    the standard PCG recurrence; its frames equal their single solves with the
+    standard recurrence forced (one-pass reduction) bit for bit."""
     import paper_1810_02648_amd as cap
     from gpu_util import make_frame
-    prm = cap.params(1.0, 0.1, 10.0, gn_iters=2, pcg_iters=5)
+    prm = cap.params(1.0, 0.1, 10.0, gn_iters=2, pcg_iters=5, pcg_standard=True)
     singles, batch = [], []
     for name, nn in (("mid", 203), ("small0", 64), ("mid", 203), ("small1", 64), ("mid", 203)):
         f = frames[name]
@@ -237,7 +242,7 @@ def test_wide_batch_equals_single_solves(ctx, frames):
     for bit."""
     import paper_1810_02648_amd as cap
     from gpu_util import make_frame
-    prm = cap.params(1.0, 0.1, 10.0, gn_iters=1, pcg_iters=2)
+    prm = cap.params(1.0, 0.1, 10.0, gn_iters=1, pcg_iters=2, pcg_standard=True)   # 32 frames: over 1024 tiles
     f = frames["mid"]
     g = og.build_graph(f["xyz"], 203)
     a = make_frame(ctx, f, g)
@@ -376,7 +381,9 @@ def test_tile_size_autotuner_and_tile_independence(ctx, frames):
 
 
 def test_large_graph_split_pcg_matches_oracle(ctx):
-    """More than 1365 nodes: the PCG iteration runs split over workgroups."""
+    """More than 1365 nodes (more (component, node) pairs than one workgroup
+    holds in registers): the PCG vector updates run distributed over the tiles
+    like every other size; the solve matches the oracle."""
     import paper_1810_02648_amd as cap
     from gpu_util import make_frame
     f = synth.make_nonrigid_frame("small", 5, n_vertices=12001, n_nodes=1500, side=400)
