@@ -368,14 +368,42 @@ def bench_frame(args, cap, torch):
     }, f
 
 
-def bench_batch(args, cap, torch):
-    """Many independent frames of uneven size (log-uniform vertices, nodes and image
-    sides) solved together by one batched call per step."""
+def _distinct_frame(spec):
     import synth
-    n = args.batch if args.batch > 1 else 64
-    log("generating %d frames" % n)
-    frames_h = synth.make_batch(n, 0, workers=min(8, len(os.sched_getaffinity(0))))
-    gn, pcg, weights = 5, 10, (1.0, 0.1, 10.0)      # the small configuration's schedule and weights
+    return synth.make_nonrigid_frame(spec["workload"], spec["seed"], n_vertices=spec["n_vertices"])
+
+
+def make_distinct(workload, n, workers):
+    """n captures of one configuration that share no data: capture i has seed i
+    and a template of (configured vertex count - i) vertices, so templates,
+    graphs, colours, deformations and targets all differ."""
+    import multiprocessing as mp
+    from concurrent.futures import ProcessPoolExecutor
+
+    import synth
+    nv0 = synth.CONFIGS[workload]["n_vertices"]
+    specs = [dict(workload=workload, seed=i, n_vertices=nv0 - i) for i in range(n)]
+    with ProcessPoolExecutor(max_workers=workers, mp_context=mp.get_context("spawn")) as ex:
+        return list(ex.map(_distinct_frame, specs))
+
+
+def bench_batch(args, cap, torch):
+    """Many independent frames solved together by one batched call per step:
+    batch mode, frames of uneven size (log-uniform vertices, nodes and image
+    sides); frame mode with --distinct, captures of one configuration that
+    share no data (distinct templates and inputs)."""
+    import synth
+    workers = min(16, len(os.sched_getaffinity(0)))
+    if args.mode == "batch":
+        n = args.batch if args.batch > 1 else 64
+        log("generating %d frames" % n)
+        frames_h = synth.make_batch(n, 0, workers=min(8, workers))
+        gn, pcg, weights = 5, 10, (1.0, 0.1, 10.0)      # the small configuration's schedule and weights
+    else:
+        n = args.batch
+        log("generating %d distinct %s captures" % (n, args.workload))
+        frames_h = make_distinct(args.workload, n, workers)
+        gn, pcg, weights = frames_h[0]["gn"], frames_h[0]["pcg"], frames_h[0]["weights"]
     ctx = cap.Context(0)
     cap.set_graphs(ctx, not args.no_graphs)
     prm = cap.params(*weights, gn_iters=gn, pcg_iters=pcg)
@@ -439,7 +467,7 @@ def bench_batch(args, cap, torch):
     avg_s = prof[dom][0] / 1000.0 / prof[dom][1]
     achieved = total_bytes(dom) / avg_s / 1e9
     apply_s = prof["cg"][0] / 1000.0 / max(prof["cg"][1], 1)
-    key = "batch%d/tile%d" % (n, tile)
+    key = ("batch%d/tile%d" % (n, tile)) if args.mode == "batch" else ("%sx%d-distinct/tile%d" % (args.workload, n, tile))
     roof = {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(dom, key), "traffic_key": key,
             "avg_us": avg_s * 1e6,
@@ -461,9 +489,13 @@ def bench_batch(args, cap, torch):
         "data": "synthetic",
         "config": {
             "launch": "eager" if args.no_graphs else "HIP graph replay",
-            "workload": "batch of %d independent frames, log-uniform 4k-40k vertices, 128-1000 nodes, 512-1080 px "
-                        "square images (%d vertices, %.1f Mpx in total), %d GN x %d PCG, plain start, one batched "
-                        "call per step" % (n, sum(nv), sum(f["cam"].width ** 2 for f in frames_h) / 1e6, gn, pcg),
+            "workload": ("batch of %d independent frames, log-uniform 4k-40k vertices, 128-1000 nodes, 512-1080 px "
+                         "square images" % n if args.mode == "batch" else
+                         "%d distinct %s captures (seeds 0-%d, templates of %d..%d vertices, %d nodes, %d px images)"
+                         % (n, args.workload, n - 1, max(nv), min(nv), frames_h[0]["n_nodes"],
+                            frames_h[0]["cam"].width))
+                        + " (%d vertices, %.1f Mpx in total), %d GN x %d PCG, plain start, one batched call per step"
+                        % (sum(nv), sum(f["cam"].width ** 2 for f in frames_h) / 1e6, gn, pcg),
             "batch": n,
             "vertices_per_tile": tile,
             "autotune_ms": None if tune is None else {str(k): round(v, 3) for k, v in tune.items()},
@@ -494,6 +526,9 @@ def main():
     ap.add_argument("--no-graphs", action="store_true",
                     help="launch every kernel eagerly instead of replaying captured HIP graphs")
     ap.add_argument("--tile", type=int, default=0, help="frame/batch mode: vertices per tile (0 = library default)")
+    ap.add_argument("--distinct", action="store_true",
+                    help="frame mode: the --batch captures share no data (capture i: seed i, template of N - i "
+                         "vertices) instead of repeating one capture")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the solver has no multi-GPU path "
@@ -518,11 +553,13 @@ def main():
         return
     if args.mode == "sequence":
         result, data = bench_sequence(args, cap, torch)
-    elif args.mode == "batch":
+    elif args.mode == "batch" or args.distinct:
         result, data = bench_batch(args, cap, torch)
     else:
         result, data = bench_frame(args, cap, torch)
-    if not args.no_cpu_baseline:
+    if args.distinct and not args.no_cpu_baseline:
+        log("no cpu baseline for distinct captures (pass --no-cpu-baseline)")
+    elif not args.no_cpu_baseline:
         log("cpu baseline (oracle)")
         if args.mode == "batch":
             # frames at the 25th, 50th and 75th percentile of vertex count; rate = 1 / mean time

@@ -16,6 +16,9 @@ It is a plain, slow, readable restatement of what the solvers compute:
                    bit for bit.
 * ``nonrigid``  -- residuals, explicit sparse Jacobian, normal equations,
                    Cholesky or Jacobi-PCG solve, Gauss-Newton loop (float64).
+* ``vertex``    -- the paper's own per-vertex non-rigid stage: data terms,
+                   spatial smoothness, edge length, velocity and acceleration
+                   priors with Table 1 material weights; Gauss-Newton (float64).
 * ``so3``       -- rotation exponential / logarithm.
 
 Every result the paper pins only qualitatively is pinned in ``tests/`` by

@@ -1,0 +1,244 @@
+"""Non-rigid stage with per-vertex unknowns, float64 Gauss-Newton (oracle).
+
+Test infrastructure only (tests, the smoke check and the benchmark's CPU
+baseline may use it; the product library never does).
+
+This is the paper's own parameterisation of Stage II (Sec. 3.4): the unknowns
+are the vertex positions V in R^{3N}, started from the skinned pose result
+V^S (or any start V0 the caller passes, e.g. the displacement-warped start),
+and
+
+    E(V) = E_photo + E_silhouette + E_smooth + E_edge + E_velocity + E_acceleration
+
+    photo:   w_photo sum_{i in visible} ||sigma_c(I_Gauss(pi(V_i)) - C_i)||^2
+    sil:     w_sil   sum_{i in B} b_i I_DT(pi(V_i))^2
+    smooth:  w_smooth sum_i sum_{j in N_i} s_ij/|N_i| ||(V_i - V_j) - (V^S_i - V^S_j)||^2
+    edge:    w_edge   sum_i sum_{j in N_i} s_ij/|N_i| (||V_i - V_j|| - ||Vhat_i - Vhat_j||)^2
+    velocity:     w_vel sum_i ||V_i - V^{t-1}_i||^2
+    acceleration: w_acc sum_i ||V_i - 2 V^{t-1}_i + V^{t-2}_i||^2
+
+(Sec. 3.4, the equations of the dense photometric and silhouette alignment and
+of the spatial and temporal regularisers).  N_i is the one-ring of vertex i
+(the vertices that share a mesh edge with it), Vhat the template's rest pose,
+s_ij = (s_i + s_j)/2 with s_i the Table 1 non-rigidity weight of vertex i's
+material class (Sec. 3.1).  The robust kernel sigma_c zeroes a vertex's whole
+colour residual when ||I_Gauss - C_i||_2 > tau_c (tau_c = inf: off).  The
+acceleration term needs V^{t-2}; without it the term is absent.
+
+Decisions (visible set, contour set B, signs b_i) are taken once per frame
+at the float32 start positions by the recipe of ``decisions`` (the paper takes
+visibility from the skinned mesh after the pose step and updates B after
+Stage I).  A vertex whose edge vector has zero length contributes no edge-term
+derivative (its unit direction is taken as 0).
+
+Gauss-Newton (Sec. 4, Eq. gaussnewton) solves (J^T |B| J) delta = -J^T B F and
+sets V <- V + delta; the linear solve is the exact sparse Cholesky of
+``nonrigid.solve_cholesky`` or exactly ``pcg_iters`` Jacobi-PCG iterations of
+``nonrigid.solve_pcg`` (diagonal preconditioner, Sec. 4 non-rigid paragraph).
+"""
+import numpy as np
+import scipy.sparse as sp
+
+from .decisions import frame_decisions_from_positions, mesh_edges
+from .image import blur, distance_transform, sample
+from .nonrigid import projection_jacobian, solve_cholesky, solve_pcg
+
+# Table 1: non-rigidity weight of each material class (class ids 1..7).
+CLASS_WEIGHTS = np.array([1.0, 2.0, 2.5, 3.0, 50.0, 100.0, 200.0])
+
+
+def vertex_weights(classes):
+    """Per-vertex smoothness weight s_i from class ids in 1..7 (Table 1)."""
+    c = np.asarray(classes, dtype=np.int64)
+    if c.min() < 1 or c.max() > 7:
+        raise ValueError("material classes are 1..7")
+    return CLASS_WEIGHTS[c - 1]
+
+
+def one_ring(tri, nv):
+    """Sorted neighbour list of every vertex (vertices sharing a mesh edge)."""
+    nb = [set() for _ in range(nv)]
+    for a, b, _, _ in mesh_edges(tri):
+        nb[a].add(b)
+        nb[b].add(a)
+    return [np.array(sorted(s), dtype=np.int64) for s in nb]
+
+
+class VertexProblem:
+    """One frame of the per-vertex non-rigid stage with its frozen decisions."""
+
+    def __init__(self, rest, posed, tri, rgb, classes, cam, mask, image, weights, start=None,
+                 prev=None, prev2=None, tau_c=np.inf, case2="push", outline=False, blur_k=3):
+        """rest: Vhat [3][N]; posed: V^S [3][N]; weights: dict with w_photo, w_sil,
+        w_smooth, w_edge, w_vel, w_acc; start: V0 (default V^S); prev, prev2:
+        V^{t-1}, V^{t-2} (None: the velocity / acceleration term is absent)."""
+        self.rest = rest.astype(np.float64)
+        self.posed = posed.astype(np.float64)
+        self.tri, self.rgb, self.cam = tri, rgb, cam
+        self.nv = rest.shape[1]
+        w = dict(w_photo=0.0, w_sil=0.0, w_smooth=0.0, w_edge=0.0, w_vel=0.0, w_acc=0.0)
+        w.update(weights)
+        self.w = {k: float(v) for k, v in w.items()}
+        self.tau_c = float(tau_c)
+        self.s = vertex_weights(classes)
+        self.nbr = one_ring(tri, self.nv)
+        start = self.posed if start is None else start
+        self.start = start.astype(np.float32)
+        self.prev = None if prev is None else prev.astype(np.float64)
+        self.prev2 = None if prev2 is None else prev2.astype(np.float64)
+        if self.prev is None and self.w["w_vel"] > 0:
+            raise ValueError("velocity term without V^{t-1}")
+        if (self.prev is None or self.prev2 is None) and self.w["w_acc"] > 0:
+            raise ValueError("acceleration term without V^{t-1} and V^{t-2}")
+        self.dt, _ = distance_transform(mask)
+        self.img = blur(image, blur_k)
+        X, Y, Z = self.start
+        self.dec = frame_decisions_from_positions(X, Y, Z, tri, cam, mask, self.dt, outline=outline)
+        self.vis_idx = np.nonzero(self.dec["visible"])[0]
+        self.bnd_idx = np.nonzero(self.dec["boundary"])[0]
+        self.bsign = self.dec["bsign"][self.bnd_idx].astype(np.float64)
+        if case2 == "exclude":
+            keep = self.bsign > 0
+            self.bnd_idx, self.bsign = self.bnd_idx[keep], self.bsign[keep]
+        # directed edges (i, j), j in N_i, with weight s_ij / |N_i|
+        src = np.concatenate([np.full(len(n), i) for i, n in enumerate(self.nbr)]).astype(np.int64)
+        dst = np.concatenate(self.nbr).astype(np.int64)
+        deg = np.array([len(n) for n in self.nbr], dtype=np.float64)
+        self.e_src, self.e_dst = src, dst
+        self.e_w = 0.5 * (self.s[src] + self.s[dst]) / deg[src]
+        d = self.rest[:, src] - self.rest[:, dst]
+        self.e_rest = np.sqrt((d * d).sum(axis=0))
+
+    def linearize(self, V, need_jacobian=True):
+        """Residuals F, row weights b, Jacobian J (csr, 3N columns), per-term energies."""
+        V = np.asarray(V, dtype=np.float64)
+        cam, nv = self.cam, self.nv
+        X, Y, Z = V
+        u = cam.fx * X / Z + cam.cx
+        v = cam.fy * Y / Z + cam.cy
+        P = projection_jacobian(V, cam)
+        Fs, bs, trip = [], [], []
+        row0 = 0
+        e = dict(photo=0.0, sil=0.0, sil_abs=0.0, smooth=0.0, edge=0.0, vel=0.0, acc=0.0)
+
+        def add_block(rows, cols_vertex, M):
+            """Rows `rows` (n) get the 1x3 blocks M (n x 3) at columns of the vertices."""
+            for a in range(3):
+                trip.append((rows, 3 * cols_vertex + a, M[:, a]))
+
+        # photometric rows: 3 per visible vertex
+        vid = self.vis_idx[Z[self.vis_idx] > 0]
+        val, gu, gv = sample(self.img, u[vid], v[vid])
+        res = val - self.rgb[:, vid].astype(np.float64)
+        keep = np.sqrt((res * res).sum(axis=0)) <= self.tau_c
+        sw = np.sqrt(self.w["w_photo"])
+        r_ph = sw * res * keep
+        e["photo"] = float((r_ph ** 2).sum())
+        for c in range(3):
+            Fs.append(r_ph[c])
+            bs.append(np.ones(vid.size))
+            if need_jacobian:
+                G = (sw * keep)[:, None] * (gu[c][:, None] * P[vid, 0, :] + gv[c][:, None] * P[vid, 1, :])
+                add_block(row0 + np.arange(vid.size), vid, G)
+            row0 += vid.size
+
+        # silhouette rows: 1 per contour vertex
+        vid = self.bnd_idx
+        okz = Z[vid] > 0
+        vid, bsg = vid[okz], self.bsign[okz]
+        d, du, dv = sample(self.dt, u[vid], v[vid])
+        sw = np.sqrt(self.w["w_sil"])
+        r_s = sw * d
+        e["sil"] = float((bsg * r_s * r_s).sum())
+        e["sil_abs"] = float((r_s * r_s).sum())
+        Fs.append(r_s)
+        bs.append(bsg)
+        if need_jacobian:
+            G = sw * (du[:, None] * P[vid, 0, :] + dv[:, None] * P[vid, 1, :])
+            add_block(row0 + np.arange(vid.size), vid, G)
+        row0 += vid.size
+
+        # spatial smoothness: 3 rows per directed edge
+        i, j = self.e_src, self.e_dst
+        ne = i.size
+        sw = np.sqrt(self.w["w_smooth"] * self.e_w)
+        r_sm = sw * ((V[:, i] - V[:, j]) - (self.posed[:, i] - self.posed[:, j]))
+        e["smooth"] = float((r_sm ** 2).sum())
+        for c in range(3):
+            Fs.append(r_sm[c])
+            bs.append(np.ones(ne))
+            if need_jacobian:
+                rr = row0 + np.arange(ne)
+                trip.append((rr, 3 * i + c, sw))
+                trip.append((rr, 3 * j + c, -sw))
+            row0 += ne
+
+        # edge length: 1 row per directed edge
+        dvec = V[:, i] - V[:, j]
+        ell = np.sqrt((dvec * dvec).sum(axis=0))
+        sw = np.sqrt(self.w["w_edge"] * self.e_w)
+        r_ed = sw * (ell - self.e_rest)
+        e["edge"] = float((r_ed ** 2).sum())
+        Fs.append(r_ed)
+        bs.append(np.ones(ne))
+        if need_jacobian:
+            with np.errstate(invalid="ignore", divide="ignore"):
+                unit = np.where(ell > 0, dvec / ell, 0.0)
+            rr = row0 + np.arange(ne)
+            add_block(rr, i, (sw * unit).T)
+            add_block(rr, j, (-sw * unit).T)
+        row0 += ne
+
+        # temporal priors: 3 rows per vertex each
+        allv = np.arange(nv)
+        for name, wkey, target in (("vel", "w_vel", None), ("acc", "w_acc", None)):
+            wt = self.w[wkey]
+            if wt <= 0:
+                continue
+            if name == "vel":
+                ref = self.prev
+            else:
+                ref = 2.0 * self.prev - self.prev2
+            sw = np.sqrt(wt)
+            r_t = sw * (V - ref)
+            e[name] = float((r_t ** 2).sum())
+            for c in range(3):
+                Fs.append(r_t[c])
+                bs.append(np.ones(nv))
+                if need_jacobian:
+                    trip.append((row0 + allv, 3 * allv + c, np.full(nv, sw)))
+                row0 += nv
+
+        F = np.concatenate(Fs)
+        b = np.concatenate(bs)
+        e["total"] = e["photo"] + e["sil"] + e["smooth"] + e["edge"] + e["vel"] + e["acc"]
+        J = None
+        if need_jacobian:
+            r = np.concatenate([t[0] for t in trip])
+            cidx = np.concatenate([t[1] for t in trip])
+            vals = np.concatenate([np.broadcast_to(t[2], t[0].shape) for t in trip])
+            J = sp.csr_matrix((vals, (r, cidx)), shape=(row0, 3 * nv))
+        return F, b, J, e
+
+    def energy(self, V):
+        return self.linearize(V, need_jacobian=False)[3]
+
+    def normal_equations(self, V):
+        """System J^T |B| J, right-hand side -J^T B F (unknowns vertex-major: 3i + a)."""
+        F, b, J, e = self.linearize(V)
+        A = (J.T @ sp.diags(np.abs(b)) @ J).tocsr()
+        rhs = -(J.T @ (b * F))
+        return A, rhs, e
+
+
+def solve(problem, gn_iters, mode="chol", pcg_iters=10, start=None):
+    """Gauss-Newton schedule from the frame's start (or `start`); V [3][N] float64."""
+    V = (problem.start if start is None else start).astype(np.float64).copy()
+    energies = []
+    for _ in range(gn_iters):
+        A, rhs, e = problem.normal_equations(V)
+        energies.append(e)
+        delta = solve_cholesky(A, rhs) if mode == "chol" else solve_pcg(A, rhs, pcg_iters)
+        V = V + delta.reshape(problem.nv, 3).T
+    energies.append(problem.energy(V))
+    return dict(V=V, energies=energies, n_visible=int(problem.vis_idx.size), n_boundary=int(problem.bnd_idx.size))

@@ -48,6 +48,13 @@ _PARTS = [(0, 2, 0.16), (2, 3, 0.10), (4, "e4", 0.11), (6, 7, 0.055), (7, 8, 0.0
           (22, "e22", 0.04), (5, 6, 0.05), (10, 11, 0.05)]
 
 
+# material class (Table 1 class id) of each part: a synthetic stand-in for the
+# per-vertex semantic labels of the paper's template (Sec. 3.1): pelvis part
+# loose (1, dress/skirt), chest, neck and clavicles upper clothes (2), head
+# face/hair (7), arms (5), hands gloves (6), legs pants (3), feet shoes (6)
+PART_CLASS = np.array([1, 2, 7, 5, 5, 6, 5, 5, 6, 3, 3, 6, 6, 3, 3, 6, 6, 2, 2], np.int32)
+
+
 def dof_joints():
     """Joints that carry 3 axis-angle unknowns, in unknown order (pelvis first)."""
     return [j for j in range(len(JOINTS)) if j not in NO_DOF]
@@ -89,6 +96,7 @@ def make_body(n_vertices, root=(0.0, 0.0, 4.0)):
         off += int(n)
     xyz = np.concatenate(xyz)
     tri = np.concatenate(tri)
+    part = np.repeat(np.arange(len(_PARTS)), counts)
     # binding: 4 nearest bones (segment distance), a bone moves with its start joint
     bones = [(PARENTS[j], J[PARENTS[j]], J[j]) for j in range(1, len(JOINTS))]
     bones += [(j, J[j], _ENDS[j] + np.asarray(root)) for j in sorted(_ENDS)]
@@ -108,7 +116,9 @@ def make_body(n_vertices, root=(0.0, 0.0, 4.0)):
                 joints=np.ascontiguousarray(J.T.astype(np.float64)),
                 parents=PARENTS.copy(),
                 bind_idx=np.ascontiguousarray(bind_joint.T.astype(np.int32)),
-                bind_w=np.ascontiguousarray(w.T.astype(np.float32)))
+                bind_w=np.ascontiguousarray(w.T.astype(np.float32)),
+                part=part.astype(np.int32),
+                classes=PART_CLASS[part].astype(np.int32))
 
 
 def _rodrigues(w):

@@ -183,12 +183,14 @@ def make_sequence(name="seq20k", seed=0, n_frames=None, workers=None):
         from .body import make_body
         body = make_body(cfg["n_vertices"], root=(0.0, 0.0, 4.5))
         xyz, tri = body["xyz"], body["tri"]
+        classes = body["classes"]
         rgb = smooth_colours(xyz, rng)
         m = _body_motion(body, rng, 64)
         jobs = [(tri, rgb, cam, m, f / 30.0) for f in range(cfg["n_frames"])]
         render = _render_body_frame
     else:
         xyz, tri = template_mesh(cfg["mesh"], cfg["n_vertices"])
+        classes = np.full(xyz.shape[1], 2, np.int32)      # one material: upper clothes
         rgb = smooth_colours(xyz, rng)
         m = _motion(xyz, rng, 24)
         jobs = [(xyz, tri, rgb, cam, m, f / 30.0) for f in range(cfg["n_frames"])]
@@ -201,8 +203,40 @@ def make_sequence(name="seq20k", seed=0, n_frames=None, workers=None):
             frames = list(ex.map(render, jobs, chunksize=4))
     else:
         frames = [render(j) for j in jobs]
-    return dict(name=name, seed=seed, xyz=xyz, tri=tri, rgb=rgb, cam=cam,
+    return dict(name=name, seed=seed, xyz=xyz, tri=tri, rgb=rgb, cam=cam, classes=classes,
                 posed=[f[0] for f in frames], gt=[f[1] for f in frames], masks=[f[2] for f in frames],
                 images=[f[3] for f in frames],
                 n_nodes=cfg["n_nodes"], n_train=cfg["n_train"], gn=cfg["gn"], pcg=cfg["pcg"],
                 weights=cfg["weights"], w_vel=cfg["w_vel"], outline=cfg.get("outline", False))
+
+
+def vertex_weights_for(side):
+    """Term weights of the per-vertex non-rigid stage for a square image of
+    `side` pixels (positions in metres, colours in [0, 1], the silhouette
+    residual in pixels).  The paper's values (Sec. 5: photo 10000,
+    silhouette 600, smooth 10, edge 30, velocity 0.25, acceleration 0.1)
+    keep their ratios within the data terms (photo / silhouette) and within
+    the regularisers; the regularisers are scaled by k = 1e4 (side / 1080)^2
+    against w_sil = 1 (a pixel residual's weight grows with the image side
+    squared at a fixed field of view), the value of a sweep over k on the
+    small body sequence."""
+    k = 1.0e4 * (side / 1080.0) ** 2
+    return dict(w_photo=10000.0 / 600.0, w_sil=1.0, w_smooth=10.0 * k, w_edge=30.0 * k, w_vel=0.25 * k,
+                w_acc=0.1 * k)
+
+
+def vertex_frame(seq, t, weights=None):
+    """Inputs of the per-vertex non-rigid stage at frame t >= 2 of a sequence:
+    rest template, posed mesh V^S_t (the pose stage's result), targets, the
+    previous two frames' ground truth as V^{t-1}, V^{t-2}, and the start
+    V^S_t + (V^{t-1} - V^S_{t-1}) (the previous displacement carried over)."""
+    if t < 2:
+        raise ValueError("t >= 2")
+    side = seq["cam"].width
+    prev, prev2 = seq["gt"][t - 1], seq["gt"][t - 2]
+    start = (seq["posed"][t] + (prev - seq["posed"][t - 1])).astype(np.float32)
+    return dict(rest=seq["xyz"], posed=seq["posed"][t], tri=seq["tri"], rgb=seq["rgb"], classes=seq["classes"],
+                cam=seq["cam"], mask=seq["masks"][t], image=seq["images"][t], prev=prev, prev2=prev2,
+                start=np.ascontiguousarray(start), gt=seq["gt"][t],
+                weights=vertex_weights_for(side) if weights is None else weights,
+                outline=seq.get("outline", False))

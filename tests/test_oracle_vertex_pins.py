@@ -1,0 +1,214 @@
+"""Pins for the per-vertex non-rigid oracle (paper Sec. 3.4 regularisers, Sec. 3.1 Table 1).
+
+Each test checks the oracle against something the paper or the mathematics
+fixes independently of the oracle's own formulas: the printed Table 1, the
+topology of a mesh whose neighbourhoods are known, energies that vanish by
+invariance, closed-form energies and minimisers, finite differences, and the
+chain rule against the (separately pinned) embedded-deformation oracle.
+"""
+import os
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import decisions as od
+from oracle import graph as og
+from oracle import nonrigid as onr
+from oracle import so3
+from oracle import vertex as ov
+from synth.meshes import ellipsoid_icosphere
+from synth.render import render_targets
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def octahedron():
+    xyz = np.array([[1, 0, 0], [-1, 0, 0], [0, 1, 0], [0, -1, 0], [0, 0, 1], [0, 0, -1]], float).T
+    tri = np.array([[0, 2, 4], [2, 1, 4], [1, 3, 4], [3, 0, 4], [2, 0, 5], [1, 2, 5], [3, 1, 5], [0, 3, 5]]).T
+    return xyz, tri.astype(np.int32)
+
+
+@pytest.fixture(scope="module")
+def mini():
+    """A 162-vertex ellipsoid seen by a 64-pixel camera, rendered after a small deformation."""
+    xyz, tri = ellipsoid_icosphere(2, (0.15, 0.5, 0.15), (0.0, 0.0, 2.5))
+    cam = synth.Camera.square(64)
+    rng = np.random.default_rng(3)
+    rgb = rng.uniform(0, 1, (3, xyz.shape[1])).astype(np.float32)
+    gt = (xyz + rng.normal(0, 0.005, xyz.shape)).astype(np.float32)
+    mask, image = render_targets(gt, tri, rgb, cam)
+    classes = rng.integers(1, 8, xyz.shape[1])
+    return dict(xyz=xyz, tri=tri, cam=cam, rgb=rgb, mask=mask, image=image, classes=classes, gt=gt)
+
+
+def problem(m, weights, posed=None, start=None, prev=None, prev2=None, rest=None, **kw):
+    rest = m["xyz"] if rest is None else rest
+    posed = m["xyz"] if posed is None else posed
+    return ov.VertexProblem(rest, posed, m["tri"], m["rgb"], m["classes"], m["cam"], m["mask"], m["image"],
+                            weights, start=start, prev=prev, prev2=prev2, **kw)
+
+
+# ---------------------------------------------------------------- Table 1 and the one-ring
+def test_class_weights_are_table1():
+    rows = [l.split() for l in open(os.path.join(GOLDEN, "table1_nonrigidity_weights.txt")) if not l.startswith("#")]
+    ids = np.array([int(r[0]) for r in rows])
+    w = np.array([float(r[1]) for r in rows])
+    assert np.array_equal(ov.vertex_weights(ids), w)
+    with pytest.raises(ValueError):
+        ov.vertex_weights([0])
+
+
+def test_one_ring_of_octahedron():
+    xyz, tri = octahedron()
+    nb = ov.one_ring(tri, 6)
+    for i in range(6):
+        antipode = i ^ 1
+        assert sorted(nb[i].tolist()) == [j for j in range(6) if j not in (i, antipode)]
+
+
+def test_edge_weight_averages_the_two_classes_over_the_degree(mini):
+    P = problem(mini, dict(w_smooth=1.0))
+    s = ov.CLASS_WEIGHTS[mini["classes"] - 1]
+    for e in np.random.default_rng(0).integers(0, P.e_src.size, 20):
+        i, j = P.e_src[e], P.e_dst[e]
+        deg = sum(1 for a, b in zip(P.e_src, P.e_dst) if a == i)
+        assert P.e_w[e] == pytest.approx((s[i] + s[j]) / 2.0 / deg, rel=1e-15)
+
+
+# ---------------------------------------------------------------- regulariser closed forms
+def test_smooth_vanishes_at_posed_and_under_translation(mini):
+    rng = np.random.default_rng(1)
+    posed = mini["xyz"] + rng.normal(0, 0.01, mini["xyz"].shape)
+    P = problem(mini, dict(w_smooth=10.0), posed=posed)
+    assert P.energy(posed)["smooth"] < 1e-24
+    assert P.energy(posed + np.array([[0.3], [-0.1], [0.2]]))["smooth"] < 1e-20
+    _, rhs, _ = P.normal_equations(posed)
+    assert np.abs(rhs).max() < 1e-12
+
+
+def test_smooth_single_vertex_displacement(mini):
+    """Moving one vertex k by d changes 2 |N_k| directed edge differences by d:
+    E = w |d|^2 sum_{j in N_k} (s_kj / |N_k| + s_jk / |N_j|)."""
+    P = problem(mini, dict(w_smooth=3.0))
+    s = ov.CLASS_WEIGHTS[mini["classes"] - 1]
+    nb = ov.one_ring(mini["tri"], mini["xyz"].shape[1])
+    d = np.array([0.01, -0.02, 0.005])
+    for k in (0, 17, 100):
+        V = mini["xyz"].astype(np.float64).copy()
+        V[:, k] += d
+        expect = 3.0 * (d @ d) * sum((s[k] + s[j]) / 2 * (1 / len(nb[k]) + 1 / len(nb[j])) for j in nb[k])
+        assert P.energy(V)["smooth"] == pytest.approx(expect, rel=1e-12)
+
+
+def test_edge_vanishes_under_rigid_motion_and_scales_quadratically(mini):
+    P = problem(mini, dict(w_edge=2.0))
+    rest = mini["xyz"].astype(np.float64)
+    R = so3.exp([0.3, -0.2, 0.5])
+    assert P.energy(R @ rest + np.array([[0.1], [0.2], [-0.3]]))["edge"] < 1e-22
+    s = ov.CLASS_WEIGHTS[mini["classes"] - 1]
+    nb = ov.one_ring(mini["tri"], rest.shape[1])
+    c = 1.07
+    expect = 0.0
+    for i in range(rest.shape[1]):
+        for j in nb[i]:
+            L = np.linalg.norm(rest[:, i] - rest[:, j])
+            expect += (s[i] + s[j]) / 2 / len(nb[i]) * ((c - 1.0) * L) ** 2
+    assert P.energy(c * rest)["edge"] == pytest.approx(2.0 * expect, rel=1e-10)
+
+
+def test_temporal_terms_minimiser_is_the_closed_form_translation(mini):
+    """With smooth, edge (rigid posed mesh), velocity and acceleration only and
+    V^{t-1} = V^S + c1, V^{t-2} = V^S + c2, the minimiser is the translation
+    V^S + lam, lam = (w_v c1 + w_a (2 c1 - c2)) / (w_v + w_a): smooth and edge
+    vanish for every translation, and the temporal terms are then a 1-D
+    least-squares problem per coordinate."""
+    rest = mini["xyz"].astype(np.float64)
+    posed = so3.exp([0.1, 0.2, -0.1]) @ rest + np.array([[0.02], [0.0], [0.05]])
+    c1, c2 = np.array([0.01, -0.02, 0.03]), np.array([0.03, 0.01, -0.02])
+    for wv, wa in ((2.0, 0.0), (0.0, 1.5), (0.7, 0.3)):
+        w = dict(w_smooth=5.0, w_edge=3.0, w_vel=wv, w_acc=wa)
+        P = problem(mini, w, posed=posed, start=posed, prev=posed + c1[:, None], prev2=posed + c2[:, None])
+        out = ov.solve(P, 3, "chol")
+        lam = (wv * c1 + wa * (2 * c1 - c2)) / (wv + wa)
+        assert np.abs(out["V"] - (posed + lam[:, None])).max() < 1e-10
+
+
+def test_missing_temporal_inputs_are_rejected(mini):
+    with pytest.raises(ValueError):
+        problem(mini, dict(w_vel=1.0))
+    with pytest.raises(ValueError):
+        problem(mini, dict(w_acc=1.0), prev=mini["xyz"])
+
+
+# ---------------------------------------------------------------- derivatives
+def test_jacobian_matches_central_differences(mini):
+    rng = np.random.default_rng(5)
+    rest = mini["xyz"].astype(np.float64)
+    posed = rest + rng.normal(0, 0.004, rest.shape)
+    w = dict(w_photo=2.0, w_sil=0.5, w_smooth=7.0, w_edge=11.0, w_vel=0.3, w_acc=0.2)
+    P = problem(mini, w, posed=posed, start=posed.astype(np.float32), prev=posed + 0.003, prev2=posed - 0.002)
+    assert P.vis_idx.size > 20 and P.bnd_idx.size > 5
+    V = posed + rng.normal(0, 0.002, rest.shape)
+    F, b, J, _ = P.linearize(V)
+    J = J.toarray()
+    h = 1e-6
+    for col in rng.choice(J.shape[1], 60, replace=False):
+        i, a = divmod(col, 3)
+        Vp, Vm = V.copy(), V.copy()
+        Vp[a, i] += h
+        Vm[a, i] -= h
+        fd = (P.linearize(Vp, False)[0] - P.linearize(Vm, False)[0]) / (2 * h)
+        assert np.abs(fd - J[:, col]).max() <= 2e-4 * max(1.0, np.abs(J[:, col]).max()), col
+    # energy = sum b F^2 per term, and the system's gradient is the energy's
+    e = P.energy(V)
+    assert e["total"] == pytest.approx(float((b * F * F).sum()), rel=1e-12)
+
+
+def test_data_rows_agree_with_the_deformation_graph_oracle_by_the_chain_rule(small_frame):
+    """At the same decisions, the ED oracle's photometric and silhouette rows are
+    the per-vertex rows composed with dV/d(node unknowns)."""
+    f = small_frame
+    g = og.build_graph(f["xyz"], f["n_nodes"])
+    nn = f["n_nodes"]
+    rng = np.random.default_rng(2)
+    st = onr.identity_state(nn).astype(np.float64)
+    for k in range(nn):
+        st[:9, k] = (so3.exp(rng.normal(0, 0.02, 3))).ravel()
+    st[9:] = rng.normal(0, 0.004, (3, nn))
+    st = st.astype(np.float32)
+    E = onr.Problem(f["xyz"], f["tri"], f["rgb"], g, f["cam"], f["mask"], f["image"], (1.3, 0.7, 0.0), state0=st)
+    start = np.stack([E.dec["X"], E.dec["Y"], E.dec["Z"]])
+    P = ov.VertexProblem(f["xyz"], f["xyz"], f["tri"], f["rgb"], np.full(f["xyz"].shape[1], 2), f["cam"], f["mask"],
+                         f["image"], dict(w_sil=1.3, w_photo=0.7), start=start)
+    assert np.array_equal(P.vis_idx, E.vis_idx) and np.array_equal(P.bnd_idx, E.bnd_idx)
+    V, q = onr.ed_deform(f["xyz"], g, st)
+    Fe, be, Je, _ = E.linearize(st)
+    Fv, bv, Jv, _ = P.linearize(V)
+    nd = 3 * P.vis_idx.size + P.bnd_idx.size           # data rows come first in both
+    assert np.allclose(Fe[:nd], Fv[:nd], rtol=0, atol=1e-12)
+    assert np.array_equal(be[:nd], bv[:nd])
+    # dV/dx: 3N x 6nn
+    nv = f["xyz"].shape[1]
+    M = np.zeros((3 * nv, 6 * nn))
+    for k, blk in onr._vertex_cols(g, q, np.arange(nv)):
+        for a in range(3):
+            for c in range(6):
+                M[3 * np.arange(nv) + a, 6 * k + c] += blk[:, a, c]
+    lhs = Je.toarray()[:nd]
+    rhs = Jv.toarray()[:nd] @ M
+    assert np.abs(lhs - rhs).max() <= 1e-9 * max(1.0, np.abs(lhs).max())
+
+
+def test_gauss_newton_lowers_the_energy_on_a_body_frame():
+    import synth.sequence as ss
+    seq = ss.make_sequence("body_small", 0, n_frames=4, workers=1)
+    f = ss.vertex_frame(seq, 3)
+    P = ov.VertexProblem(f["rest"], f["posed"], f["tri"], f["rgb"], f["classes"], f["cam"], f["mask"], f["image"],
+                         f["weights"], start=f["start"], prev=f["prev"], prev2=f["prev2"], case2="exclude",
+                         outline=True)
+    out = ov.solve(P, 3, "pcg", 4)
+    e = [x["total"] for x in out["energies"]]
+    assert e[-1] < 0.5 * e[0]
+    exact = ov.solve(P, 3, "chol")
+    assert exact["energies"][-1]["total"] <= e[-1] * 1.0001
