@@ -421,8 +421,108 @@ CAPTURE_API int capture_pose_linearize(capture_ctx *ctx, const capture_pose_fram
                                        const capture_pose_params *params, double *system, double *energy,
                                        uint8_t *vflags, void *workspace, size_t workspace_bytes, void *stream);
 
+/* --------------------------------------------------------------------------
+ * Per-vertex non-rigid stage: the paper's own Stage II parameterisation
+ * (Sec. 3.4): the unknowns are the vertex positions V (3 per vertex),
+ *   E(V) = w_photo sum_{i visible} ||sigma_c(I_Gauss(pi(V_i)) - C_i)||^2
+ *        + w_sil sum_{i in B} b_i I_DT(pi(V_i))^2
+ *        + w_smooth sum_i sum_{j in N_i} s_ij/|N_i| ||(V_i - V_j) - (V^S_i - V^S_j)||^2
+ *        + w_edge sum_i sum_{j in N_i} s_ij/|N_i| (||V_i - V_j|| - ||Vhat_i - Vhat_j||)^2
+ *        + w_vel sum_i ||V_i - V^{t-1}_i||^2 + w_acc sum_i ||V_i - 2 V^{t-1}_i + V^{t-2}_i||^2
+ * (Sec. 3.4: dense photometric and silhouette alignment, spatial smoothness,
+ * edge length, velocity and acceleration priors).  N_i is the one-ring of
+ * vertex i, Vhat the rest pose, V^S the skinned pose result, and
+ * s_ij = (s_i + s_j) / 2 with s_i the Table 1 non-rigidity weight of vertex
+ * i's material class (Sec. 3.1: class 1..7 -> 1, 2, 2.5, 3, 50, 100, 200).
+ * Decisions (visible set, contour set B, signs b_i) are taken once at the
+ * start positions with the rules of the embedded-deformation stage.  Each
+ * Gauss-Newton step solves J^T |B| J delta = -J^T B F by Jacobi-preconditioned
+ * CG (Sec. 4, non-rigid paragraph: rows parallelised per vertex block row,
+ * diagonal preconditioner, a fixed number of iterations; the product is
+ * applied matrix-free by gathering each vertex's one-ring) and sets
+ * V <- V + delta.  The iterate and the CG vectors are float64; residuals,
+ * Jacobians and the per-vertex data blocks float32.
+ * ------------------------------------------------------------------------ */
+#define CAPTURE_VERTEX_MAX_RING 32     /* largest one-ring size a template may have */
+
+typedef struct capture_vertex_template capture_vertex_template;
+
+typedef struct {
+    int32_t n_vertices, n_triangles;
+    const int32_t *tri;          /* [3][n_triangles] device, counter-clockwise seen from outside; closed
+                                    parts may overlap; every edge in one or two faces */
+    const float *rest;           /* [3][n_vertices] device: rest pose Vhat (edge rest lengths) */
+    const int32_t *classes;      /* [n_vertices] device: material class 1..7 of Table 1 */
+} capture_vertex_template_desc;
+
+/* Copies the topology, builds the one-ring table (ELL layout, neighbours in
+ * ascending order) with each directed edge's s_ij/|N_i|, the undirected
+ * weight s_ij/|N_i| + s_ij/|N_j| and the rest length, and keeps them in
+ * library-owned device memory.  CAPTURE_EINVAL for indices or classes out of
+ * range or a non-manifold mesh, CAPTURE_EUNSUPPORTED for a one-ring larger
+ * than CAPTURE_VERTEX_MAX_RING.  Synchronous. */
+CAPTURE_API int capture_vertex_template_create(capture_ctx *ctx, const capture_vertex_template_desc *desc,
+                                               capture_vertex_template **out);
+CAPTURE_API void capture_vertex_template_destroy(capture_vertex_template *tmpl);
+
+typedef struct {
+    const capture_vertex_template *tmpl;
+    const float *posed;        /* [3][n_vertices] V^S: the skinned mesh of the pose result */
+    const float *prev;         /* [3][n_vertices] V^{t-1}, or NULL (then w_vel and w_acc must be 0) */
+    const float *prev2;        /* [3][n_vertices] V^{t-2}, or NULL (then w_acc must be 0) */
+    const float *rgb;          /* [3][n_vertices] template vertex colours C, in [0, 1] */
+    capture_camera camera;
+    const uint8_t *mask;       /* [H][W] foreground silhouette, 0 = background */
+    const float *image;        /* [3][H][W] colour frame in [0, 1] */
+    float *V;                  /* [3][n_vertices] in: start positions, out: solution */
+} capture_vertex_frame;
+
+/* blur_kernel[g]: odd size k in 1..15 of the Gaussian I_Gauss used by
+ * Gauss-Newton step g (sigma = 0.3 ((k - 1) / 2 - 1) + 0.8, separable,
+ * clamp-to-edge; 0 means 3).  The paper's photometric pyramid (Sec. 3.4: one
+ * Gauss-Newton step per level, kernels 15, 9, 3) is {15, 9, 3} with
+ * gn_iters = 3; at most 3 distinct sizes per solve.  The final energy uses
+ * the last step's image.  flags: CAPTURE_FLAG_EXCLUDE_CASE2,
+ * CAPTURE_FLAG_OUTLINE_ONLY as for the other stages. */
+typedef struct {
+    float w_photo, w_sil, w_smooth, w_edge, w_vel, w_acc, tau_color;
+    int32_t gn_iters;          /* 1..CAPTURE_MAX_GN */
+    int32_t pcg_iters;         /* >= 0 Jacobi-PCG iterations per Gauss-Newton step */
+    uint32_t flags;
+    int32_t blur_kernel[CAPTURE_MAX_GN];
+} capture_vertex_params;
+
+typedef struct {
+    double energy[CAPTURE_MAX_GN + 1];    /* E at the start of each step (with that step's image), then the final E */
+    double e_photo, e_sil, e_sil_abs, e_smooth, e_edge, e_vel, e_acc;   /* final per-term energies */
+    int32_t n_visible, n_boundary, gn_done;
+    int32_t status;                       /* CAPTURE_OK or CAPTURE_ENONFINITE (a non-finite energy) */
+} capture_vertex_report;
+
+/* Workspace bytes of one frame (a host struct; its arrays are not read). */
+CAPTURE_API int capture_vertex_workspace_size(capture_ctx *ctx, const capture_vertex_frame *frame,
+                                              const capture_vertex_params *params, size_t *bytes);
+
+/* Gauss-Newton solve of one frame.  frame->V is overwritten with the result
+ * (also when the report's status is CAPTURE_ENONFINITE, which is returned). */
+CAPTURE_API int capture_vertex_solve(capture_ctx *ctx, const capture_vertex_frame *frame,
+                                     const capture_vertex_params *params, capture_vertex_report *report,
+                                     void *workspace, size_t workspace_bytes, void *stream);
+
+/* Decisions and one linearisation at frame->V (not modified), with the image
+ * of step 0, then the matrix-free product:
+ *   rhs   [3][n_vertices] -J^T B F        diag [3][n_vertices] diagonal of J^T |B| J
+ *   p     [3][n_vertices] input direction (may be NULL)   Ap [3][n_vertices] out: J^T |B| J p
+ *   energy (host, 7 doubles): photo, sil, sil with |b_i|, smooth, edge, velocity, acceleration
+ *   vflags [n_vertices] (may be NULL): bit0 visible, bit1 in B, bit2 b_i = -1
+ * float64 rhs, diag, p and Ap; any output may be NULL. */
+CAPTURE_API int capture_vertex_linearize(capture_ctx *ctx, const capture_vertex_frame *frame,
+                                         const capture_vertex_params *params, double *rhs, double *diag,
+                                         const double *p, double *Ap, double *energy, uint8_t *vflags,
+                                         void *workspace, size_t workspace_bytes, void *stream);
+
 /* Launch mode of capture_batch_solve / capture_nonrigid_solve /
- * capture_nonrigid_solve_warm.  With `on`, the per-frame launch sequence
+ * capture_nonrigid_solve_warm / capture_vertex_solve.  With `on`, the per-frame launch sequence
  * (preprocessing, decisions, the warm-start prediction and selection, and the
  * full Gauss-Newton/PCG schedule) is captured into a HIP graph the first time
  * a launch shape (frame count, sizes, workspace address, schedule; for the

@@ -18,7 +18,10 @@ and
     acceleration: w_acc sum_i ||V_i - 2 V^{t-1}_i + V^{t-2}_i||^2
 
 (Sec. 3.4, the equations of the dense photometric and silhouette alignment and
-of the spatial and temporal regularisers).  N_i is the one-ring of vertex i
+of the spatial and temporal regularisers).  I_Gauss is the frame blurred by a
+Gaussian of odd kernel size k (``image.blur``); the paper's photometric pyramid
+takes one Gauss-Newton step per level with k = 15, 9, 3 (read as three blur
+levels at full resolution; ``solve(..., blur_schedule=(15, 9, 3))``).  N_i is the one-ring of vertex i
 (the vertices that share a mesh edge with it), Vhat the template's rest pose,
 s_ij = (s_i + s_j)/2 with s_i the Table 1 non-rigidity weight of vertex i's
 material class (Sec. 3.1).  The robust kernel sigma_c zeroes a vertex's whole
@@ -91,7 +94,9 @@ class VertexProblem:
         if (self.prev is None or self.prev2 is None) and self.w["w_acc"] > 0:
             raise ValueError("acceleration term without V^{t-1} and V^{t-2}")
         self.dt, _ = distance_transform(mask)
-        self.img = blur(image, blur_k)
+        self.image_in = image
+        self.blur_k = int(blur_k)
+        self._blurred = {}
         X, Y, Z = self.start
         self.dec = frame_decisions_from_positions(X, Y, Z, tri, cam, mask, self.dt, outline=outline)
         self.vis_idx = np.nonzero(self.dec["visible"])[0]
@@ -109,9 +114,18 @@ class VertexProblem:
         d = self.rest[:, src] - self.rest[:, dst]
         self.e_rest = np.sqrt((d * d).sum(axis=0))
 
-    def linearize(self, V, need_jacobian=True):
-        """Residuals F, row weights b, Jacobian J (csr, 3N columns), per-term energies."""
+    def image(self, k=None):
+        """I_Gauss of the frame with Gaussian kernel size k (default: the problem's)."""
+        k = self.blur_k if k is None else int(k)
+        if k not in self._blurred:
+            self._blurred[k] = blur(self.image_in, k)
+        return self._blurred[k]
+
+    def linearize(self, V, need_jacobian=True, blur_k=None):
+        """Residuals F, row weights b, Jacobian J (csr, 3N columns), per-term energies;
+        the photometric term samples I_Gauss of kernel size blur_k."""
         V = np.asarray(V, dtype=np.float64)
+        img = self.image(blur_k)
         cam, nv = self.cam, self.nv
         X, Y, Z = V
         u = cam.fx * X / Z + cam.cx
@@ -128,7 +142,7 @@ class VertexProblem:
 
         # photometric rows: 3 per visible vertex
         vid = self.vis_idx[Z[self.vis_idx] > 0]
-        val, gu, gv = sample(self.img, u[vid], v[vid])
+        val, gu, gv = sample(img, u[vid], v[vid])
         res = val - self.rgb[:, vid].astype(np.float64)
         keep = np.sqrt((res * res).sum(axis=0)) <= self.tau_c
         sw = np.sqrt(self.w["w_photo"])
@@ -220,25 +234,32 @@ class VertexProblem:
             J = sp.csr_matrix((vals, (r, cidx)), shape=(row0, 3 * nv))
         return F, b, J, e
 
-    def energy(self, V):
-        return self.linearize(V, need_jacobian=False)[3]
+    def energy(self, V, blur_k=None):
+        return self.linearize(V, need_jacobian=False, blur_k=blur_k)[3]
 
-    def normal_equations(self, V):
+    def normal_equations(self, V, blur_k=None):
         """System J^T |B| J, right-hand side -J^T B F (unknowns vertex-major: 3i + a)."""
-        F, b, J, e = self.linearize(V)
+        F, b, J, e = self.linearize(V, blur_k=blur_k)
         A = (J.T @ sp.diags(np.abs(b)) @ J).tocsr()
         rhs = -(J.T @ (b * F))
         return A, rhs, e
 
 
-def solve(problem, gn_iters, mode="chol", pcg_iters=10, start=None):
-    """Gauss-Newton schedule from the frame's start (or `start`); V [3][N] float64."""
+def solve(problem, gn_iters, mode="chol", pcg_iters=10, start=None, blur_schedule=None):
+    """Gauss-Newton schedule from the frame's start (or `start`); V [3][N] float64.
+
+    blur_schedule: Gaussian kernel size of I_Gauss per Gauss-Newton step (the
+    photometric pyramid of Sec. 3.4 is (15, 9, 3): one step per level); the
+    final energy uses the last step's kernel.  Default: the problem's kernel."""
     V = (problem.start if start is None else start).astype(np.float64).copy()
+    ks = [problem.blur_k] * gn_iters if blur_schedule is None else [int(k) for k in blur_schedule]
+    if len(ks) != gn_iters:
+        raise ValueError("one blur kernel per Gauss-Newton step")
     energies = []
-    for _ in range(gn_iters):
-        A, rhs, e = problem.normal_equations(V)
+    for g in range(gn_iters):
+        A, rhs, e = problem.normal_equations(V, blur_k=ks[g])
         energies.append(e)
         delta = solve_cholesky(A, rhs) if mode == "chol" else solve_pcg(A, rhs, pcg_iters)
         V = V + delta.reshape(problem.nv, 3).T
-    energies.append(problem.energy(V))
+    energies.append(problem.energy(V, blur_k=ks[-1]))
     return dict(V=V, energies=energies, n_visible=int(problem.vis_idx.size), n_boundary=int(problem.bnd_idx.size))

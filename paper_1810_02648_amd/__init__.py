@@ -14,7 +14,8 @@ from . import capi
 from .capi import CaptureError  # noqa: F401
 
 __all__ = ["Context", "Template", "FrameInputs", "graph_build", "CaptureError", "Body", "PoseInputs",
-           "pose_params", "pose_solve", "pose_linearize", "autotune_tiles"]
+           "pose_params", "pose_solve", "pose_linearize", "autotune_tiles", "VertexTemplate", "VertexInputs",
+           "vertex_params", "vertex_solve", "vertex_linearize"]
 
 
 def _ptr(t):
@@ -436,3 +437,97 @@ def pose_linearize(ctx, frame, prm):
     capi.check(ctx.lib.capture_pose_linearize(ctx.h, C.byref(fr), C.byref(prm), _ptr(system), e, _ptr(vflags),
                                               _ptr(ws), ws.numel(), _stream()))
     return dict(system=system, energy=list(e), vflags=vflags)
+
+
+# ---------------------------------------------------------------- per-vertex non-rigid stage
+class VertexTemplate:
+    """Mesh, rest pose and material classes (Table 1) of the per-vertex stage."""
+
+    def __init__(self, ctx, tri, rest, classes):
+        nf, nv = tri.shape[1], rest.shape[1]
+        _need(tri, torch.int32, (3, nf), "tri")
+        _need(rest, torch.float32, (3, nv), "rest")
+        _need(classes, torch.int32, (nv,), "classes")
+        self.ctx, self.nv, self.nf = ctx, nv, nf
+        d = capi.VertexTemplateDesc(nv, nf, _ptr(tri), _ptr(rest), _ptr(classes))
+        h = C.c_void_p()
+        capi.check(ctx.lib.capture_vertex_template_create(ctx.h, C.byref(d), C.byref(h)))
+        self.h = h
+
+    def __del__(self):
+        try:
+            if self.h:
+                self.ctx.lib.capture_vertex_template_destroy(self.h)
+                self.h = None
+        except Exception:
+            pass
+
+
+class VertexInputs:
+    """Device tensors of one per-vertex frame (see capture_vertex_frame); V is updated in place."""
+
+    def __init__(self, template, posed, rgb, camera, mask, image, V, prev=None, prev2=None):
+        nv = template.nv
+        W, H = int(camera.width), int(camera.height)
+        for t, name in ((posed, "posed"), (rgb, "rgb"), (V, "V")):
+            _need(t, torch.float32, (3, nv), name)
+        for t, name in ((prev, "prev"), (prev2, "prev2")):
+            if t is not None:
+                _need(t, torch.float32, (3, nv), name)
+        _need(mask, torch.uint8, (H, W), "mask")
+        _need(image, torch.float32, (3, H, W), "image")
+        self.template, self.posed, self.rgb, self.mask, self.image, self.V = template, posed, rgb, mask, image, V
+        self.prev, self.prev2 = prev, prev2
+        self.camera = capi.Camera(W, H, float(camera.fx), float(camera.fy), float(camera.cx), float(camera.cy))
+
+    def struct(self):
+        return capi.VertexFrame(self.template.h, _ptr(self.posed), _ptr(self.prev), _ptr(self.prev2), _ptr(self.rgb),
+                                self.camera, _ptr(self.mask), _ptr(self.image), _ptr(self.V))
+
+
+def vertex_params(w_photo, w_sil, w_smooth, w_edge, w_vel=0.0, w_acc=0.0, gn_iters=3, pcg_iters=4,
+                  tau_color=math.inf, exclude_case2=False, outline_only=False, blur_kernels=None):
+    flags = (capi.FLAG_EXCLUDE_CASE2 if exclude_case2 else 0) | (capi.FLAG_OUTLINE_ONLY if outline_only else 0)
+    bk = (C.c_int32 * capi.MAX_GN)()
+    for g, k in enumerate(blur_kernels or ()):
+        bk[g] = int(k)
+    return capi.VertexParams(w_photo, w_sil, w_smooth, w_edge, w_vel, w_acc, tau_color, gn_iters, pcg_iters, flags,
+                             bk)
+
+
+def _vertex_ws(ctx, fr, prm):
+    n = C.c_size_t()
+    capi.check(ctx.lib.capture_vertex_workspace_size(ctx.h, C.byref(fr), C.byref(prm), C.byref(n)))
+    return ctx.workspace(n.value)
+
+
+def vertex_solve(ctx, frame, prm):
+    """Gauss-Newton solve of one per-vertex frame; frame.V holds the result."""
+    fr = frame.struct()
+    ws = _vertex_ws(ctx, fr, prm)
+    rep = capi.VertexReport()
+    capi.check(ctx.lib.capture_vertex_solve(ctx.h, C.byref(fr), C.byref(prm), C.byref(rep), _ptr(ws), ws.numel(),
+                                            _stream()))
+    g = rep.gn_done
+    out = {name: getattr(rep, name) for name, _ in capi.VertexReport._fields_ if name != "energy"}
+    out["energy"] = [rep.energy[k] for k in range(g + 1)]
+    return out
+
+
+def vertex_linearize(ctx, frame, prm, p=None):
+    """Decisions and one linearisation at frame.V: rhs, diag (float64 [3][nv]),
+    J^T |B| J p if p is given, the 7 energy terms and the vertex flags."""
+    nv = frame.template.nv
+    fr = frame.struct()
+    ws = _vertex_ws(ctx, fr, prm)
+    dev = frame.V.device
+    rhs = torch.empty((3, nv), dtype=torch.float64, device=dev)
+    diag = torch.empty_like(rhs)
+    Ap = torch.empty_like(rhs) if p is not None else None
+    if p is not None:
+        _need(p, torch.float64, (3, nv), "p")
+    flags = torch.empty(nv, dtype=torch.uint8, device=dev)
+    en = (C.c_double * 7)()
+    capi.check(ctx.lib.capture_vertex_linearize(ctx.h, C.byref(fr), C.byref(prm), _ptr(rhs), _ptr(diag), _ptr(p),
+                                                _ptr(Ap), en, _ptr(flags), _ptr(ws), ws.numel(), _stream()))
+    return dict(rhs=rhs, diag=diag, Ap=Ap, energy=list(en), vflags=flags)

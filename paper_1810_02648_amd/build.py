@@ -10,7 +10,7 @@ SRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libcapture.so")
 SOURCES = ["plan.cpp", "frame_kernels.hip", "solve_kernels.hip", "warmstart.hip", "pose_kernels.hip",
-           "capi.hip", "pose_capi.hip"]
+           "capi.hip", "pose_capi.hip", "vertex.hip"]
 
 FLAGS = [
     "-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",

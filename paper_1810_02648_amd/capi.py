@@ -74,6 +74,33 @@ class PoseReport(C.Structure):
                 ("n_boundary", C.c_int32), ("gn_done", C.c_int32), ("status", C.c_int32)]
 
 
+VERTEX_MAX_RING = 32
+
+
+class VertexTemplateDesc(C.Structure):
+    _fields_ = [("n_vertices", C.c_int32), ("n_triangles", C.c_int32), ("tri", C.c_void_p), ("rest", C.c_void_p),
+                ("classes", C.c_void_p)]
+
+
+class VertexFrame(C.Structure):
+    _fields_ = [("tmpl", C.c_void_p), ("posed", C.c_void_p), ("prev", C.c_void_p), ("prev2", C.c_void_p),
+                ("rgb", C.c_void_p), ("camera", Camera), ("mask", C.c_void_p), ("image", C.c_void_p),
+                ("V", C.c_void_p)]
+
+
+class VertexParams(C.Structure):
+    _fields_ = [("w_photo", C.c_float), ("w_sil", C.c_float), ("w_smooth", C.c_float), ("w_edge", C.c_float),
+                ("w_vel", C.c_float), ("w_acc", C.c_float), ("tau_color", C.c_float), ("gn_iters", C.c_int32),
+                ("pcg_iters", C.c_int32), ("flags", C.c_uint32), ("blur_kernel", C.c_int32 * MAX_GN)]
+
+
+class VertexReport(C.Structure):
+    _fields_ = [("energy", C.c_double * (MAX_GN + 1)), ("e_photo", C.c_double), ("e_sil", C.c_double),
+                ("e_sil_abs", C.c_double), ("e_smooth", C.c_double), ("e_edge", C.c_double), ("e_vel", C.c_double),
+                ("e_acc", C.c_double), ("n_visible", C.c_int32), ("n_boundary", C.c_int32), ("gn_done", C.c_int32),
+                ("status", C.c_int32)]
+
+
 _P = C.c_void_p
 SIGNATURES = {
     "capture_create": (C.c_int, [C.POINTER(C.c_void_p), C.c_int]),
@@ -117,6 +144,14 @@ SIGNATURES = {
     "capture_autotune_tiles": (C.c_int, [_P, C.c_int32, C.POINTER(TemplateDesc), C.POINTER(Frame),
                                          C.POINTER(NonrigidParams), C.POINTER(C.c_int32), C.c_int32,
                                          C.POINTER(C.c_int32), C.POINTER(C.c_double), _P]),
+    "capture_vertex_template_create": (C.c_int, [_P, C.POINTER(VertexTemplateDesc), C.POINTER(C.c_void_p)]),
+    "capture_vertex_template_destroy": (None, [_P]),
+    "capture_vertex_workspace_size": (C.c_int, [_P, C.POINTER(VertexFrame), C.POINTER(VertexParams),
+                                                C.POINTER(C.c_size_t)]),
+    "capture_vertex_solve": (C.c_int, [_P, C.POINTER(VertexFrame), C.POINTER(VertexParams),
+                                       C.POINTER(VertexReport), _P, C.c_size_t, _P]),
+    "capture_vertex_linearize": (C.c_int, [_P, C.POINTER(VertexFrame), C.POINTER(VertexParams), _P, _P, _P, _P,
+                                           C.POINTER(C.c_double), _P, _P, C.c_size_t, _P]),
     "capture_set_graphs": (C.c_int, [_P, C.c_int]),
     "capture_profile_enable": (C.c_int, [_P, C.c_int]),
     "capture_profile_read": (C.c_int, [_P, C.c_char_p, C.POINTER(C.c_double), C.POINTER(C.c_int64)]),
@@ -124,7 +159,8 @@ SIGNATURES = {
 
 KERNELS = ("blur", "contour", "dt_cols", "dt_rows", "deform_start", "raster", "contour_edges", "decide",
            "linearize", "node_init", "cg", "cg_node", "ws_features", "ws_mlp", "pose_lbs", "pose_rows",
-           "pose_jtj", "pose_step", "prep_image", "prep_geom", "prep_raster", "prep_cols")
+           "pose_jtj", "pose_step", "prep_image", "prep_geom", "prep_raster", "prep_cols", "v_blur", "v_lin",
+           "v_apply", "v_update")
 WS_PARAMS = 38662
 
 _lib = None

@@ -296,7 +296,8 @@ const char *kKernelNames[K_COUNT] = {"blur", "contour", "dt_cols", "dt_rows", "d
                                      "contour_edges", "decide", "linearize", "node_init", "cg", "cg_node",
                                      "ws_features", "ws_mlp", "pose_lbs", "pose_rows", "pose_jtj",
                                      "pose_step", "prep_image", "prep_geom", "prep_raster",
-                                     "prep_cols"};
+                                     "prep_cols",
+                                     "v_blur", "v_lin", "v_apply", "v_update"};
 
 int setup(Run &R, capture_ctx *ctx, int n, const capture_frame *frames, const capture_nonrigid_params *params,
           void *ws, size_t ws_bytes, void *stream) {
@@ -488,44 +489,6 @@ std::string shape_key(const Run &R, const capture_nonrigid_params *prm) {
                   R.max_nf, R.max_nn, R.max_hw, R.max_w, R.max_h, R.max_tiles, R.total_tiles, R.max_me, R.lds_lin,
                   R.lds_apply, prm->gn_iters, prm->pcg_iters);
     return key;
-}
-
-template <class F>
-int launch_graph(Run &R, const std::string &key, F &&sequence) {
-    capture_ctx *ctx = R.ctx;
-    auto &cache = ctx->graph_cache;
-    hipGraphExec_t exec = nullptr;
-    for (size_t i = 0; i < cache.size(); ++i)
-        if (cache[i].key == key) {
-            exec = cache[i].exec;
-            std::rotate(cache.begin() + i, cache.begin() + i + 1, cache.end());     // most recent last
-            break;
-        }
-    if (!exec) {
-        if (!ctx->capture_stream) CAP_HIP(hipStreamCreateWithFlags(&ctx->capture_stream, hipStreamNonBlocking));
-        Run C = R;
-        C.s = ctx->capture_stream;
-        C.prof = nullptr;
-        CAP_HIP(hipStreamBeginCapture(C.s, hipStreamCaptureModeThreadLocal));
-        const int rc = sequence(C);
-        hipGraph_t graph = nullptr;
-        const hipError_t e = hipStreamEndCapture(C.s, &graph);
-        if (rc) {
-            if (graph) (void)hipGraphDestroy(graph);
-            return rc;
-        }
-        if (e != hipSuccess || !graph) return fail(CAPTURE_EHIP, "graph capture failed");
-        const hipError_t ei = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
-        (void)hipGraphDestroy(graph);
-        if (ei != hipSuccess) return fail(CAPTURE_EHIP, "graph instantiation failed");
-        if (cache.size() >= size_t(kGraphCache)) {
-            (void)hipGraphExecDestroy(cache.front().exec);
-            cache.erase(cache.begin());
-        }
-        cache.push_back({key, exec});
-    }
-    CAP_HIP(hipGraphLaunch(exec, R.s));
-    return CAPTURE_OK;
 }
 
 // Every problem's scalars and counters, copied to pinned host memory in one

@@ -1,5 +1,7 @@
 // Host-side launch helpers shared by the entry points (internal).
 #pragma once
+#include <algorithm>
+#include <string>
 #include <vector>
 
 #include "common.hpp"
@@ -111,6 +113,47 @@ inline void settle(Run &R) {
     }
     P->pending.clear();
     P->used = 0;
+}
+
+// Replays the launches of `sequence` (a callable taking a Run whose stream
+// it launches on) from a HIP graph cached under `key` in the context,
+// capturing it on the context's capture stream the first time.
+template <class F>
+inline int launch_graph(Run &R, const std::string &key, F &&sequence) {
+    capture_ctx *ctx = R.ctx;
+    auto &cache = ctx->graph_cache;
+    hipGraphExec_t exec = nullptr;
+    for (size_t i = 0; i < cache.size(); ++i)
+        if (cache[i].key == key) {
+            exec = cache[i].exec;
+            std::rotate(cache.begin() + i, cache.begin() + i + 1, cache.end());     // most recent last
+            break;
+        }
+    if (!exec) {
+        if (!ctx->capture_stream) CAP_HIP(hipStreamCreateWithFlags(&ctx->capture_stream, hipStreamNonBlocking));
+        Run C = R;
+        C.s = ctx->capture_stream;
+        C.prof = nullptr;
+        CAP_HIP(hipStreamBeginCapture(C.s, hipStreamCaptureModeThreadLocal));
+        const int rc = sequence(C);
+        hipGraph_t graph = nullptr;
+        const hipError_t e = hipStreamEndCapture(C.s, &graph);
+        if (rc) {
+            if (graph) (void)hipGraphDestroy(graph);
+            return rc;
+        }
+        if (e != hipSuccess || !graph) return fail(CAPTURE_EHIP, "graph capture failed");
+        const hipError_t ei = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        if (ei != hipSuccess) return fail(CAPTURE_EHIP, "graph instantiation failed");
+        if (cache.size() >= size_t(kGraphCache)) {
+            (void)hipGraphExecDestroy(cache.front().exec);
+            cache.erase(cache.begin());
+        }
+        cache.push_back({key, exec});
+    }
+    CAP_HIP(hipGraphLaunch(exec, R.s));
+    return CAPTURE_OK;
 }
 
 inline unsigned blocks(size_t n, unsigned t) { return unsigned((n + t - 1) / t); }
