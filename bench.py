@@ -56,6 +56,12 @@ def algorithmic_bytes(kernel, n_act, n_nodes, n_edges, n_pix, n_faces, n_verts):
         return 13 * n_pix
     if kernel in ("contour", "decide", "deform_start", "contour_edges"):
         return 5 * n_pix if kernel == "contour" else 64 * n_verts
+    if kernel in ("v_apply", "v_update"):   # per-vertex PCG: float64 vectors in and out, data block, one-ring table
+        return 192 * n_verts
+    if kernel == "v_lin":          # per-vertex linearisation: point, inputs, texel gathers, one-ring, PCG start
+        return 570 * n_verts
+    if kernel == "v_blur":         # the three blur levels: two passes each, 3 channels read + written per pass
+        return 3 * 48 * n_pix
     if kernel == "pose_step":      # the 69 x 70 float64 system in, the pose out
         return 8 * 69 * 70 + 8 * 69
     if kernel == "pose_jtj":       # the Jacobian (about 115 + 400 rows x 80 float64) in, the system out
@@ -387,6 +393,119 @@ def make_distinct(workload, n, workers):
         return list(ex.map(_distinct_frame, specs))
 
 
+def bench_vertex(args, cap, torch):
+    """The per-vertex non-rigid stage (the paper's own Stage II) on frames of the
+    articulated sequence: the paper's schedule (3 Gauss-Newton steps, one per
+    photometric pyramid level 15/9/3, 4 PCG iterations each)."""
+    import numpy as np
+
+    import synth.sequence as ss
+    n_frames = 2 + args.frames
+    log("generating %d frames of %s" % (n_frames, args.workload))
+    seq = ss.make_sequence(args.workload, 0, n_frames=n_frames, workers=min(16, len(os.sched_getaffinity(0))))
+    ctx = cap.Context(0)
+    cap.set_graphs(ctx, not args.no_graphs)
+    d = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    tmpl = cap.VertexTemplate(ctx, d(seq["tri"]), d(seq["xyz"]), d(seq["classes"].astype(np.int32)))
+    fs = [ss.vertex_frame(seq, t) for t in range(2, n_frames)]
+    w = fs[0]["weights"]
+    gn, pcg, blur = 3, 4, (15, 9, 3)
+    prm = cap.vertex_params(w["w_photo"], w["w_sil"], w["w_smooth"], w["w_edge"], w["w_vel"], w["w_acc"],
+                            gn_iters=gn, pcg_iters=pcg, exclude_case2=True, outline_only=True, blur_kernels=blur)
+    rgb = d(seq["rgb"])
+    frames, starts = [], []
+    for f in fs:
+        st = d(f["start"])
+        starts.append(st)
+        frames.append(cap.VertexInputs(tmpl, d(f["posed"]), rgb, f["cam"], d(f["mask"]), d(f["image"]), st.clone(),
+                                       prev=d(f["prev"]), prev2=d(f["prev2"])))
+
+    def step():
+        reps = []
+        for fr, st in zip(frames, starts):
+            fr.V.copy_(st)
+            reps.append(cap.vertex_solve(ctx, fr, prm))
+        return reps
+
+    tw = time.perf_counter()
+    k = 0
+    while k < args.warmup or time.perf_counter() - tw < 0.5:
+        reps = step()
+        torch.cuda.synchronize()
+        k += 1
+    log("timing", args.steps, "steps of", len(frames), "frames")
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        reps = step()
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    cap.profile_enable(ctx, True)
+    cap.profile_read(ctx)
+    step()
+    torch.cuda.synchronize()
+    prof = cap.profile_read(ctx)
+    cap.profile_enable(ctx, False)
+    nv = seq["xyz"].shape[1]
+    W, H = seq["cam"].width, seq["cam"].height
+    vk = {k: v for k, v in prof.items() if k.startswith("v_") and v[1]}
+    dom = max(vk, key=lambda k: vk[k][0])
+    avg_s = vk[dom][0] / 1000.0 / vk[dom][1]
+    bytes_launch = algorithmic_bytes(dom, 0, 0, 0, W * H, 0, nv)
+    achieved = bytes_launch / avg_s / 1e9
+    errs = [float(np.sqrt(((fr.V.cpu().numpy() - f["gt"]) ** 2).sum(0)).mean()) for fr, f in zip(frames, fs)]
+    errs0 = [float(np.sqrt(((f["start"] - f["gt"]) ** 2).sum(0)).mean()) for f in fs]
+    n = args.steps * len(frames)
+    return {
+        "metric": "per-vertex non-rigid GN frames/s",
+        "value": n / elapsed,
+        "unit": "frames/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1000.0 * elapsed / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {
+            "launch": "eager" if args.no_graphs else "HIP graph replay",
+            "workload": "%s per-vertex stage: %d frames (t = 2..%d) of the %d-vertex articulated body sequence, "
+                        "%dx%d targets, %d GN x %d PCG, photometric pyramid %s, smooth/edge/velocity/acceleration "
+                        "with Table 1 material weights; start = pose result + previous displacement"
+                        % (args.workload, len(frames), n_frames - 1, nv, W, H, gn, pcg, "/".join(map(str, blur))),
+            "mean_energy_start_final": [float(np.mean([r["energy"][0] for r in reps])),
+                                        float(np.mean([r["energy"][-1] for r in reps]))],
+            "mean_vertex_error_mm_start_final": [1000 * float(np.mean(errs0)), 1000 * float(np.mean(errs))],
+        },
+        "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None, "avg_us": avg_s * 1e6,
+                     "algorithmic_bytes_per_launch": bytes_launch},
+        "kernel_avg_us": {k: round(1000.0 * ms / c, 3) for k, (ms, c) in prof.items() if c},
+    }, (seq, fs, w, gn, pcg, blur)
+
+
+def cpu_baseline_vertex(data, n=3):
+    """The FP64 oracle on the first n frames of the GPU leg's problem (same
+    starts, inputs, weights, schedule and pyramid)."""
+    from threadpoolctl import threadpool_limits
+
+    from oracle import vertex as ov
+    seq, fs, w, gn, pcg, blur = data
+    cores = len(os.sched_getaffinity(0))
+    with threadpool_limits(limits=cores):
+        t0 = time.perf_counter()
+        for f in fs[:n]:
+            P = ov.VertexProblem(f["rest"], f["posed"], f["tri"], f["rgb"], f["classes"], f["cam"], f["mask"],
+                                 f["image"], w, start=f["start"], prev=f["prev"], prev2=f["prev2"], case2="exclude",
+                                 outline=True)
+            out = ov.solve(P, gn, "pcg", pcg, blur_schedule=blur)
+        dt = time.perf_counter() - t0
+    return dict(value=n / dt, unit="frames/s", cores=cores, kind="oracle",
+                sample="%d frames of the same workload (decisions, pyramid blur and %d GN x %d Jacobi-PCG in float64 "
+                       "each), %.1f s; last final energy %.4f" % (n, gn, pcg, dt, out["energies"][-1]["total"]))
+
+
 def bench_batch(args, cap, torch):
     """Many independent frames solved together by one batched call per step:
     batch mode, frames of uneven size (log-uniform vertices, nodes and image
@@ -513,7 +632,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--mode", default="sequence", choices=["sequence", "frame", "batch", "copy"],
+    ap.add_argument("--mode", default="sequence", choices=["sequence", "frame", "batch", "vertex", "copy"],
                     help="copy: a plain device copy of known size (calibrates the profiler's byte counters)")
     ap.add_argument("--workload", default=None,
                     help="sequence: body20k (default: articulated body), seq20k (ellipsoid), body_small, seq_small; "
@@ -526,6 +645,7 @@ def main():
     ap.add_argument("--no-graphs", action="store_true",
                     help="launch every kernel eagerly instead of replaying captured HIP graphs")
     ap.add_argument("--tile", type=int, default=0, help="frame/batch mode: vertices per tile (0 = library default)")
+    ap.add_argument("--frames", type=int, default=40, help="vertex mode: frames solved per step")
     ap.add_argument("--distinct", action="store_true",
                     help="frame mode: the --batch captures share no data (capture i: seed i, template of N - i "
                          "vertices) instead of repeating one capture")
@@ -535,7 +655,7 @@ def main():
               "(independent captures would shard one per GPU with no communication)", file=sys.stderr)
         sys.exit(2)
     if args.workload is None:
-        args.workload = "body20k" if args.mode == "sequence" else "frame20k"
+        args.workload = "body20k" if args.mode in ("sequence", "vertex") else "frame20k"
 
     import torch
 
@@ -553,6 +673,8 @@ def main():
         return
     if args.mode == "sequence":
         result, data = bench_sequence(args, cap, torch)
+    elif args.mode == "vertex":
+        result, data = bench_vertex(args, cap, torch)
     elif args.mode == "batch" or args.distinct:
         result, data = bench_batch(args, cap, torch)
     else:
@@ -574,6 +696,8 @@ def main():
             result["cpu_baseline"] = cb
         elif args.mode == "sequence":
             result["cpu_baseline"] = cpu_baseline_sequence(data)
+        elif args.mode == "vertex":
+            result["cpu_baseline"] = cpu_baseline_vertex(data)
         else:
             result["cpu_baseline"] = cpu_baseline(data, data["n_nodes"], data["gn"], data["pcg"], data["weights"])
     print(json.dumps(result), flush=True)
