@@ -485,6 +485,73 @@ def bench_vertex(args, cap, torch):
     }, (seq, fs, w, gn, pcg, blur)
 
 
+def bench_track(args, cap, torch):
+    """Two-stage tracking (pose stage with Euler start, skinning, warped
+    per-vertex stage) of the articulated sequence: stages of consecutive
+    frames on two streams against both stages in order on one stream."""
+    import numpy as np
+
+    import synth.sequence as ss
+    from paper_1810_02648_amd.pipeline import Tracker
+    from synth import body as sb
+    n = args.frames
+    log("generating %d frames of %s" % (n, args.workload))
+    seq = ss.make_sequence(args.workload, 0, n_frames=n, workers=min(16, len(os.sched_getaffinity(0))))
+    ctx = cap.Context(0)
+    d = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    b = seq["body"]
+    body = cap.Body(ctx, d(b["tri"]), d(b["xyz"]), d(b["bind_idx"]), d(b["bind_w"]), b["parents"], b["joints"],
+                    [j not in sb.NO_DOF for j in range(len(sb.JOINTS))])
+    vt = cap.VertexTemplate(ctx, d(b["tri"]), d(b["xyz"]), d(b["classes"]))
+    frames = []
+    for t in range(n):
+        p2d, p3d, lam = ss.pose_detections(seq, t)
+        frames.append(dict(mask=d(seq["masks"][t]), image=d(seq["images"][t]), p2d=d(p2d), p3d=d(p3d), lam=d(lam)))
+    prm = cap.pose_params(gn_iters=3, **ss.tracking_pose_params(seq["cam"].width, 3 * len(sb.dof_joints())))
+    T = Tracker(body, vt, d(seq["rgb"]), seq["cam"], frames, d(seq["poses"][0]), prm,
+                ss.vertex_weights_for(seq["cam"].width))
+    for c in (T.ctx_pose, T.ctx_nr):
+        cap.set_graphs(c, not args.no_graphs)
+    times = {}
+    for mode, run in (("sequential", T.run_sequential), ("pipelined", T.run_pipelined)):
+        for _ in range(max(args.warmup, 1)):
+            run()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            run()
+        torch.cuda.synchronize()
+        times[mode] = time.perf_counter() - t0
+        log(mode, "%.1f frames/s" % (args.steps * n / times[mode]))
+    err = [1000 * float(np.sqrt(((T.V[t].cpu().numpy() - seq["gt"][t]) ** 2).sum(0)).mean()) for t in range(n)]
+    err_s = [1000 * float(np.sqrt(((T.posed[t].cpu().numpy() - seq["gt"][t]) ** 2).sum(0)).mean())
+             for t in range(n)]
+    return {
+        "metric": "two-stage tracking frames/s (pose + per-vertex non-rigid)",
+        "value": args.steps * n / times["pipelined"],
+        "unit": "frames/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1000.0 * times["pipelined"] / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {
+            "launch": "eager" if args.no_graphs else "HIP graph replay",
+            "workload": "%s: %d frames, %d-vertex articulated body for both stages, %dx%d; pose stage 3 GN (69 "
+                        "unknowns, Euler start), skinning, displacement-warped per-vertex stage 3 GN x 4 PCG with the "
+                        "15/9/3 pyramid; one step = the whole sequence" % (args.workload, n, body.nv,
+                                                                           seq["cam"].width, seq["cam"].height),
+            "sequential_frames_per_s": args.steps * n / times["sequential"],
+            "pipelined_speedup": times["sequential"] / times["pipelined"],
+            "mean_vertex_error_mm_skinned_tracked": [float(np.mean(err_s)), float(np.mean(err))],
+        },
+    }, None
+
+
 def cpu_baseline_vertex(data, n=3):
     """The FP64 oracle on the first n frames of the GPU leg's problem (same
     starts, inputs, weights, schedule and pyramid)."""
@@ -632,7 +699,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--mode", default="sequence", choices=["sequence", "frame", "batch", "vertex", "copy"],
+    ap.add_argument("--mode", default="sequence", choices=["sequence", "frame", "batch", "vertex", "track", "copy"],
                     help="copy: a plain device copy of known size (calibrates the profiler's byte counters)")
     ap.add_argument("--workload", default=None,
                     help="sequence: body20k (default: articulated body), seq20k (ellipsoid), body_small, seq_small; "
@@ -645,7 +712,7 @@ def main():
     ap.add_argument("--no-graphs", action="store_true",
                     help="launch every kernel eagerly instead of replaying captured HIP graphs")
     ap.add_argument("--tile", type=int, default=0, help="frame/batch mode: vertices per tile (0 = library default)")
-    ap.add_argument("--frames", type=int, default=40, help="vertex mode: frames solved per step")
+    ap.add_argument("--frames", type=int, default=40, help="vertex / track modes: frames per step")
     ap.add_argument("--distinct", action="store_true",
                     help="frame mode: the --batch captures share no data (capture i: seed i, template of N - i "
                          "vertices) instead of repeating one capture")
@@ -655,7 +722,7 @@ def main():
               "(independent captures would shard one per GPU with no communication)", file=sys.stderr)
         sys.exit(2)
     if args.workload is None:
-        args.workload = "body20k" if args.mode in ("sequence", "vertex") else "frame20k"
+        args.workload = "body20k" if args.mode in ("sequence", "vertex", "track") else "frame20k"
 
     import torch
 
@@ -675,6 +742,9 @@ def main():
         result, data = bench_sequence(args, cap, torch)
     elif args.mode == "vertex":
         result, data = bench_vertex(args, cap, torch)
+    elif args.mode == "track":
+        result, data = bench_track(args, cap, torch)
+        args.no_cpu_baseline = True
     elif args.mode == "batch" or args.distinct:
         result, data = bench_batch(args, cap, torch)
     else:

@@ -344,7 +344,8 @@ CAPTURE_API int capture_nonrigid_solve_warm(capture_ctx *ctx, const capture_fram
  * paper skins with dual quaternions; this library uses LBS) with 4
  * influences per vertex: V_i = sum_s w_s (R_j (v_i - J_j) + p_j).
  * Energy: E = l2d sum_j lambda_j ||pi(p_j) - P2D_j||^2
- *           + l3d sum_j ||p_j - (P3D_j + t')||^2 + lsil sum_{i in B} b_i I_DT(pi(V_i))^2,
+ *           + l3d sum_j ||p_j - (P3D_j + t')||^2 + lsil sum_{i in B} b_i I_DT(pi(V_i))^2
+ *           + E_temporal + E_anatomic (see capture_pose_params),
  * decisions (visible set, contour set B, signs b_i) taken once per solve at
  * the start pose with the same raster and decision rules as the non-rigid
  * stage.  Each Gauss-Newton step solves (J^T J + mu I) delta = -J^T B F with
@@ -382,6 +383,7 @@ typedef struct {
     const double *p3d;            /* [3][n_joints] root-relative 3D joint detections (metres) */
     const double *lambda;         /* [n_joints] per-joint 2D confidences, >= 0 */
     double *pose;                 /* [n_unknowns] in: start pose, out: solution */
+    const double *prev_joints;    /* [3][n_joints] joint positions of the previous frame (E_temporal), or NULL */
 } capture_pose_frame;
 
 /* CAPTURE_FLAG_OUTLINE_ONLY: B keeps only contour vertices on the outline of
@@ -389,15 +391,26 @@ typedef struct {
  * pixel); contours of parts seen in front of other parts are dropped.  Also
  * CAPTURE_FLAG_EXCLUDE_CASE2 as for the non-rigid stage. */
 #define CAPTURE_FLAG_OUTLINE_ONLY 2u
+/* E_temporal = sum_j l_temporal[j] ||p_j - p_j^{t-1}|| ^2 (Sec. 3.3, temporal
+ * stabilisation: l_temporal[j] = lambda_temporal * lambda_j) needs
+ * frame->prev_joints when any weight is > 0.  E_anatomic = l_anatomic *
+ * sum_q Psi(theta_q) over the rotational unknowns q < 3 * (rotating joints)
+ * (Sec. 3.3, joint angle limits: the quadratic barrier outside
+ * [theta_min[q], theta_max[q]]; +-inf for an unlimited unknown).  Zero
+ * weights leave the terms out. */
 typedef struct {
     double l2d, l3d, lsil;        /* term weights, finite and >= 0 */
     int32_t gn_iters;             /* 1..CAPTURE_MAX_GN */
     uint32_t flags;               /* CAPTURE_FLAG_EXCLUDE_CASE2 | CAPTURE_FLAG_OUTLINE_ONLY */
+    double l_temporal[CAPTURE_MAX_JOINTS];
+    double l_anatomic;
+    double theta_min[CAPTURE_MAX_POSE_UNKNOWNS], theta_max[CAPTURE_MAX_POSE_UNKNOWNS];
 } capture_pose_params;
 
 typedef struct {
     double energy[CAPTURE_MAX_GN + 1];    /* E at the start of each step, then the final E */
     double e2d, e3d, e_sil, e_sil_abs;    /* final per-term energies (e_sil_abs: with |b_i|) */
+    double e_temporal, e_anatomic;
     int32_t n_visible, n_boundary, gn_done;
     int32_t status;                       /* CAPTURE_OK or a device-detected error */
 } capture_pose_report;
@@ -415,7 +428,7 @@ CAPTURE_API int capture_pose_solve(capture_ctx *ctx, const capture_pose_frame *f
 /* Decisions and one linearisation at frame->pose (not modified):
  *   system  [n_unknowns][n_unknowns + 1] (device, may be NULL): J^T J (undamped)
  *           with -J^T B F as the last column
- *   energy  host [4]: 2D, 3D, silhouette (with b_i), silhouette with |b_i|
+ *   energy  host [6]: 2D, 3D, silhouette (with b_i), silhouette with |b_i|, temporal, joint limits
  *   vflags  [n_vertices] (device, may be NULL): bit0 visible, bit1 in B, bit2 b_i = -1 */
 CAPTURE_API int capture_pose_linearize(capture_ctx *ctx, const capture_pose_frame *frame,
                                        const capture_pose_params *params, double *system, double *energy,
@@ -520,6 +533,42 @@ CAPTURE_API int capture_vertex_linearize(capture_ctx *ctx, const capture_vertex_
                                          const capture_vertex_params *params, double *rhs, double *diag,
                                          const double *p, double *Ap, double *energy, uint8_t *vflags,
                                          void *workspace, size_t workspace_bytes, void *stream);
+
+/* --------------------------------------------------------------------------
+ * Between the stages and between frames.  These calls only enqueue work on
+ * `stream` (no host synchronisation, no workspace), so that the stages of
+ * consecutive frames can run concurrently on different streams.
+ * ------------------------------------------------------------------------ */
+/* The skinned mesh V^S of a body at a pose (Sec. 3.1 skinning, with the
+ * library's linear blend and the float32 recipe of the pose stage's start
+ * positions): pose [n_unknowns] device float64, xyz [3][n_vertices] device out. */
+CAPTURE_API int capture_body_skin(capture_ctx *ctx, const capture_body *body, const double *pose, float *xyz,
+                                  void *stream);
+
+/* Displacement warping (Sec. 3.4): the previous frame's non-rigid
+ * displacement d = V^{t-1} - V^{S,t-1} is taken back to the rest pose by the
+ * inverse skinning rotation of the previous pose and carried forward by the
+ * current pose's, start = V^{S,t} + M_t M_{t-1}^T d, where M is the rotation
+ * of dual-quaternion skinning at the vertex (the unit quaternions of its
+ * influencing joints' global rotations, flipped into the first influence's
+ * hemisphere, blended by the skinning weights and normalised).  Poses device
+ * float64 [n_unknowns]; meshes device [3][n_vertices] float32 (the body's
+ * vertex count); start may alias none of the inputs.  Arithmetic in float64. */
+CAPTURE_API int capture_body_warp(capture_ctx *ctx, const capture_body *body, const double *pose_prev,
+                                  const double *pose_cur, const float *V_prev, const float *posed_prev,
+                                  const float *posed_cur, float *start, void *stream);
+
+/* Joint positions p_j at a pose (forward kinematics of the pose stage):
+ * pose [n_unknowns] device float64, joints [3][n_joints] device float64 out
+ * (e.g. the next frame's capture_pose_frame.prev_joints). */
+CAPTURE_API int capture_body_joints(capture_ctx *ctx, const capture_body *body, const double *pose, double *joints,
+                                    void *stream);
+
+/* Start pose of the next frame (Sec. 3.3): an explicit Euler step in joint
+ * angle space, pose_out = pose_prev + (pose_prev - pose_prev2); device float64
+ * [n_unknowns] each. */
+CAPTURE_API int capture_pose_extrapolate(capture_ctx *ctx, const capture_body *body, const double *pose_prev,
+                                         const double *pose_prev2, double *pose_out, void *stream);
 
 /* Launch mode of capture_batch_solve / capture_nonrigid_solve /
  * capture_nonrigid_solve_warm / capture_vertex_solve.  With `on`, the per-frame launch sequence

@@ -158,9 +158,18 @@ class PoseProblem:
     """One frame of the pose stage with frozen start-pose decisions."""
 
     def __init__(self, skel, xyz, tri, bind_idx, bind_w, cam, mask, p2d, p3d, lam, weights, pose0,
-                 case2="push", outline=True):
+                 case2="push", outline=True, prev_joints=None, lam_temporal=None, limits=None, l_anat=0.0):
+        """prev_joints [3][nj]: the previous frame's joint positions p^{t-1} and
+        lam_temporal [nj]: lambda_temporal * lambda_i per joint (E_temporal,
+        Sec. 3.3); limits (theta_min, theta_max) [it] over the rotational
+        unknowns (+-inf: none) with weight l_anat (E_anatomic, Sec. 3.3)."""
         from .image import distance_transform
         self.skel, self.xyz, self.tri, self.cam = skel, xyz, tri, cam
+        self.prev_joints = None if prev_joints is None else np.asarray(prev_joints, np.float64)
+        self.lam_t = None if lam_temporal is None else np.asarray(lam_temporal, np.float64)
+        self.limits = None if limits is None else (np.asarray(limits[0], np.float64),
+                                                   np.asarray(limits[1], np.float64))
+        self.l_anat = float(l_anat)
         self.bind_idx, self.bind_w = bind_idx, bind_w
         self.p2d, self.p3d, self.lam = np.asarray(p2d, np.float64), np.asarray(p3d, np.float64), np.asarray(lam)
         self.l2d, self.l3d, self.lsil = (float(w) for w in weights)
@@ -180,7 +189,7 @@ class PoseProblem:
         sk, cam = self.skel, self.cam
         R, p, Ax = sk.fk(pose)
         rows_F, rows_b, rows_J = [], [], []
-        e = dict(e2d=0.0, e3d=0.0, sil=0.0, sil_abs=0.0)
+        e = dict(e2d=0.0, e3d=0.0, sil=0.0, sil_abs=0.0, temporal=0.0, anatomic=0.0)
 
         def dpoint(y, chain):
             """d y / d unknowns for a point y carried by the joints in `chain` (j first)."""
@@ -249,9 +258,33 @@ class PoseProblem:
                                    [0, cam.fy / Z[n], -cam.fy * Y[n] / Z[n] ** 2]])
                     g = ss * np.array([du[n], dv[n]]) @ Pn
                     rows_J.append((g @ Js[n])[None, :])
+        # temporal stabilisation: sqrt(lambda_T lambda_j) (p_j - p_j^{t-1})
+        if self.prev_joints is not None:
+            for j in range(sk.nj):
+                st = np.sqrt(self.lam_t[j])
+                r = st * (p[j] - self.prev_joints[:, j])
+                e["temporal"] += float(r @ r)
+                rows_F.append(r)
+                rows_b.append(np.ones(3))
+                if need_jacobian:
+                    rows_J.append(st * dpoint(p[j], sk.anc[j][1:]))
+        # joint limits: quadratic barrier on every rotational unknown outside its range
+        if self.limits is not None and self.l_anat > 0:
+            lo, hi = self.limits
+            th = pose[:sk.it]
+            sa = np.sqrt(self.l_anat)
+            over, under = th > hi, th < lo
+            r = sa * np.where(over, th - hi, np.where(under, lo - th, 0.0))
+            e["anatomic"] = float(r @ r)
+            rows_F.append(r)
+            rows_b.append(np.ones(sk.it))
+            if need_jacobian:
+                Ja = np.zeros((sk.it, sk.nu))
+                Ja[np.arange(sk.it), np.arange(sk.it)] = sa * np.where(over, 1.0, np.where(under, -1.0, 0.0))
+                rows_J.append(Ja)
         F = np.concatenate(rows_F)
         b = np.concatenate(rows_b)
-        e["total"] = e["e2d"] + e["e3d"] + e["sil"]
+        e["total"] = e["e2d"] + e["e3d"] + e["sil"] + e["temporal"] + e["anatomic"]
         Jm = np.concatenate(rows_J, axis=0) if need_jacobian else None
         return F, b, Jm, e
 
@@ -274,3 +307,45 @@ def solve(problem, gn_iters):
     energies.append(problem.energy(pose))
     return dict(pose=pose, energies=energies, n_boundary=int(problem.bnd.size),
                 n_visible=int(problem.dec["visible"].sum()))
+
+
+def blended_rotations(skel, bind_idx, bind_w, pose):
+    """Per-vertex rotation of dual-quaternion skinning (its rotation part):
+    the unit quaternions of the influencing joints' global rotations, each
+    flipped into the hemisphere of the first influence's, blended by the
+    skinning weights and normalised (Sec. 3.1: the template is rigged with
+    dual quaternion skinning).  Returns [nv][3][3] (float64)."""
+    from scipy.spatial.transform import Rotation
+    R, _, _ = skel.fk(np.asarray(pose, np.float64))
+    q = Rotation.from_matrix(R).as_quat()                      # [nj][4] (x, y, z, w), library conversion
+    nv = bind_idx.shape[1]
+    acc = np.zeros((nv, 4))
+    q0 = q[bind_idx[0]]
+    for s in range(bind_idx.shape[0]):
+        qs = q[bind_idx[s]]
+        sign = np.where((qs * q0).sum(axis=1) < 0.0, -1.0, 1.0)
+        acc += (bind_w[s].astype(np.float64) * sign)[:, None] * qs
+    acc /= np.linalg.norm(acc, axis=1, keepdims=True)
+    return Rotation.from_quat(acc).as_matrix()
+
+
+def warp_displacements(skel, bind_idx, bind_w, pose_prev, pose_cur, V_prev, S_prev, S_cur):
+    """Displacement warping (Sec. 3.4): the non-rigid displacement of the
+    previous frame d = V^{t-1} - V^{S,t-1} is taken back to the rest pose by
+    the inverse of the previous pose's skinning rotation, carried forward by
+    the current pose's, and added to the current skinned mesh:
+        V^t_start = V^{S,t} + M_t M_{t-1}^T d,  M = blended_rotations(...).
+    Arrays [3][nv]; result float64."""
+    Mp = blended_rotations(skel, bind_idx, bind_w, pose_prev)
+    Mc = blended_rotations(skel, bind_idx, bind_w, pose_cur)
+    d = (np.asarray(V_prev, np.float64) - np.asarray(S_prev, np.float64)).T     # [nv][3]
+    rest = np.einsum("nba,nb->na", Mp, d)                                       # M_{t-1}^T d
+    return np.asarray(S_cur, np.float64) + np.einsum("nab,nb->na", Mc, rest).T
+
+
+def extrapolate_pose(pose_prev, pose_prev2):
+    """Start pose of the next frame (Sec. 3.3): an explicit Euler step in
+    joint-angle space from the last two frames' poses, p + (p - p_prev)."""
+    p1 = np.asarray(pose_prev, np.float64)
+    return p1 + (p1 - np.asarray(pose_prev2, np.float64))
+

@@ -15,7 +15,8 @@ from .capi import CaptureError  # noqa: F401
 
 __all__ = ["Context", "Template", "FrameInputs", "graph_build", "CaptureError", "Body", "PoseInputs",
            "pose_params", "pose_solve", "pose_linearize", "autotune_tiles", "VertexTemplate", "VertexInputs",
-           "vertex_params", "vertex_solve", "vertex_linearize"]
+           "vertex_params", "vertex_solve", "vertex_linearize", "body_skin", "body_warp", "pose_extrapolate",
+           "body_joints"]
 
 
 def _ptr(t):
@@ -385,7 +386,7 @@ class Body:
 class PoseInputs:
     """Device tensors of one pose frame (see capture_pose_frame)."""
 
-    def __init__(self, body, camera, mask, p2d, p3d, lam, pose):
+    def __init__(self, body, camera, mask, p2d, p3d, lam, pose, prev_joints=None):
         W, H = int(camera.width), int(camera.height)
         nj = body.nj
         _need(mask, torch.uint8, (H, W), "mask")
@@ -393,17 +394,30 @@ class PoseInputs:
         _need(p3d, torch.float64, (3, nj), "p3d")
         _need(lam, torch.float64, (nj,), "lambda")
         _need(pose, torch.float64, (body.nu,), "pose")
+        if prev_joints is not None:
+            _need(prev_joints, torch.float64, (3, nj), "prev_joints")
         self.body, self.mask, self.p2d, self.p3d, self.lam, self.pose = body, mask, p2d, p3d, lam, pose
+        self.prev_joints = prev_joints
         self.camera = capi.Camera(W, H, float(camera.fx), float(camera.fy), float(camera.cx), float(camera.cy))
 
     def struct(self):
         return capi.PoseFrame(self.body.h, self.camera, _ptr(self.mask), _ptr(self.p2d), _ptr(self.p3d),
-                              _ptr(self.lam), _ptr(self.pose))
+                              _ptr(self.lam), _ptr(self.pose), _ptr(self.prev_joints))
 
 
-def pose_params(l2d=1.0 / 9.0, l3d=2500.0, lsil=0.05, gn_iters=3, exclude_case2=True, outline_only=True):
+def pose_params(l2d=1.0 / 9.0, l3d=2500.0, lsil=0.05, gn_iters=3, exclude_case2=True, outline_only=True,
+                l_temporal=None, l_anatomic=0.0, theta_min=None, theta_max=None):
+    """l_temporal: per-joint temporal weights (lambda_temporal * lambda_j);
+    theta_min / theta_max: limits of the rotational unknowns (default unlimited)."""
     flags = (capi.FLAG_EXCLUDE_CASE2 if exclude_case2 else 0) | (capi.FLAG_OUTLINE_ONLY if outline_only else 0)
-    return capi.PoseParams(l2d, l3d, lsil, gn_iters, flags)
+    lt = (C.c_double * capi.MAX_JOINTS)(*([float(x) for x in l_temporal] if l_temporal is not None else []))
+    lo = (C.c_double * capi.MAX_POSE_UNKNOWNS)(*([-math.inf] * capi.MAX_POSE_UNKNOWNS))
+    hi = (C.c_double * capi.MAX_POSE_UNKNOWNS)(*([math.inf] * capi.MAX_POSE_UNKNOWNS))
+    for q, x in enumerate(theta_min if theta_min is not None else []):
+        lo[q] = float(x)
+    for q, x in enumerate(theta_max if theta_max is not None else []):
+        hi[q] = float(x)
+    return capi.PoseParams(l2d, l3d, lsil, gn_iters, flags, lt, l_anatomic, lo, hi)
 
 
 def _pose_ws(ctx, fr):
@@ -420,20 +434,21 @@ def pose_solve(ctx, frame, prm):
     capi.check(ctx.lib.capture_pose_solve(ctx.h, C.byref(fr), C.byref(prm), C.byref(rep), _ptr(ws), ws.numel(),
                                           _stream()))
     return dict(energy=[rep.energy[k] for k in range(rep.gn_done + 1)], e2d=rep.e2d, e3d=rep.e3d,
-                e_sil=rep.e_sil, e_sil_abs=rep.e_sil_abs, n_visible=rep.n_visible, n_boundary=rep.n_boundary,
+                e_sil=rep.e_sil, e_sil_abs=rep.e_sil_abs, e_temporal=rep.e_temporal, e_anatomic=rep.e_anatomic,
+                n_visible=rep.n_visible, n_boundary=rep.n_boundary,
                 gn_done=rep.gn_done, status=rep.status)
 
 
 def pose_linearize(ctx, frame, prm):
     """Decisions and normal equations at frame.pose: system [nu][nu+1] (J^T J | -J^T B F),
-    the 4 energy terms and the vertex flags."""
+    the 6 energy terms (2D, 3D, silhouette, silhouette with |b|, temporal, limits) and the vertex flags."""
     fr = frame.struct()
     ws = _pose_ws(ctx, fr)
     nu = frame.body.nu
     dev = frame.pose.device
     system = torch.empty((nu, nu + 1), dtype=torch.float64, device=dev)
     vflags = torch.empty(frame.body.nv, dtype=torch.uint8, device=dev)
-    e = (C.c_double * 4)()
+    e = (C.c_double * 6)()
     capi.check(ctx.lib.capture_pose_linearize(ctx.h, C.byref(fr), C.byref(prm), _ptr(system), e, _ptr(vflags),
                                               _ptr(ws), ws.numel(), _stream()))
     return dict(system=system, energy=list(e), vflags=vflags)
@@ -531,3 +546,40 @@ def vertex_linearize(ctx, frame, prm, p=None):
     capi.check(ctx.lib.capture_vertex_linearize(ctx.h, C.byref(fr), C.byref(prm), _ptr(rhs), _ptr(diag), _ptr(p),
                                                 _ptr(Ap), en, _ptr(flags), _ptr(ws), ws.numel(), _stream()))
     return dict(rhs=rhs, diag=diag, Ap=Ap, energy=list(en), vflags=flags)
+
+
+# ---------------------------------------------------------------- between stages and frames (enqueue only)
+def body_skin(ctx, body, pose, out):
+    """out [3][nv] float32 <- skinned mesh of `body` at `pose` (float64 [nu])."""
+    _need(pose, torch.float64, (body.nu,), "pose")
+    _need(out, torch.float32, (3, body.nv), "out")
+    capi.check(ctx.lib.capture_body_skin(ctx.h, body.h, _ptr(pose), _ptr(out), _stream()))
+    return out
+
+
+def body_warp(ctx, body, pose_prev, pose_cur, V_prev, posed_prev, posed_cur, out):
+    """out <- posed_cur + M_cur M_prev^T (V_prev - posed_prev) (displacement warping)."""
+    for t, name in ((pose_prev, "pose_prev"), (pose_cur, "pose_cur")):
+        _need(t, torch.float64, (body.nu,), name)
+    for t, name in ((V_prev, "V_prev"), (posed_prev, "posed_prev"), (posed_cur, "posed_cur"), (out, "out")):
+        _need(t, torch.float32, (3, body.nv), name)
+    capi.check(ctx.lib.capture_body_warp(ctx.h, body.h, _ptr(pose_prev), _ptr(pose_cur), _ptr(V_prev),
+                                         _ptr(posed_prev), _ptr(posed_cur), _ptr(out), _stream()))
+    return out
+
+
+def pose_extrapolate(ctx, body, pose_prev, pose_prev2, out):
+    """out <- pose_prev + (pose_prev - pose_prev2) (explicit Euler step)."""
+    for t, name in ((pose_prev, "pose_prev"), (pose_prev2, "pose_prev2"), (out, "out")):
+        _need(t, torch.float64, (body.nu,), name)
+    capi.check(ctx.lib.capture_pose_extrapolate(ctx.h, body.h, _ptr(pose_prev), _ptr(pose_prev2), _ptr(out),
+                                                _stream()))
+    return out
+
+
+def body_joints(ctx, body, pose, out):
+    """out [3][nj] float64 <- joint positions at `pose`."""
+    _need(pose, torch.float64, (body.nu,), "pose")
+    _need(out, torch.float64, (3, body.nj), "out")
+    capi.check(ctx.lib.capture_body_joints(ctx.h, body.h, _ptr(pose), _ptr(out), _stream()))
+    return out

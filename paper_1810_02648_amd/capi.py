@@ -60,17 +60,19 @@ class BodyDesc(C.Structure):
 
 class PoseFrame(C.Structure):
     _fields_ = [("body", C.c_void_p), ("camera", Camera), ("mask", C.c_void_p), ("p2d", C.c_void_p),
-                ("p3d", C.c_void_p), ("lambda_", C.c_void_p), ("pose", C.c_void_p)]
+                ("p3d", C.c_void_p), ("lambda_", C.c_void_p), ("pose", C.c_void_p), ("prev_joints", C.c_void_p)]
 
 
 class PoseParams(C.Structure):
     _fields_ = [("l2d", C.c_double), ("l3d", C.c_double), ("lsil", C.c_double), ("gn_iters", C.c_int32),
-                ("flags", C.c_uint32)]
+                ("flags", C.c_uint32), ("l_temporal", C.c_double * MAX_JOINTS), ("l_anatomic", C.c_double),
+                ("theta_min", C.c_double * MAX_POSE_UNKNOWNS), ("theta_max", C.c_double * MAX_POSE_UNKNOWNS)]
 
 
 class PoseReport(C.Structure):
     _fields_ = [("energy", C.c_double * (MAX_GN + 1)), ("e2d", C.c_double), ("e3d", C.c_double),
-                ("e_sil", C.c_double), ("e_sil_abs", C.c_double), ("n_visible", C.c_int32),
+                ("e_sil", C.c_double), ("e_sil_abs", C.c_double), ("e_temporal", C.c_double),
+                ("e_anatomic", C.c_double), ("n_visible", C.c_int32),
                 ("n_boundary", C.c_int32), ("gn_done", C.c_int32), ("status", C.c_int32)]
 
 
@@ -152,6 +154,10 @@ SIGNATURES = {
                                        C.POINTER(VertexReport), _P, C.c_size_t, _P]),
     "capture_vertex_linearize": (C.c_int, [_P, C.POINTER(VertexFrame), C.POINTER(VertexParams), _P, _P, _P, _P,
                                            C.POINTER(C.c_double), _P, _P, C.c_size_t, _P]),
+    "capture_body_skin": (C.c_int, [_P, _P, _P, _P, _P]),
+    "capture_body_warp": (C.c_int, [_P, _P, _P, _P, _P, _P, _P, _P, _P]),
+    "capture_pose_extrapolate": (C.c_int, [_P, _P, _P, _P, _P, _P]),
+    "capture_body_joints": (C.c_int, [_P, _P, _P, _P, _P]),
     "capture_set_graphs": (C.c_int, [_P, C.c_int]),
     "capture_profile_enable": (C.c_int, [_P, C.c_int]),
     "capture_profile_read": (C.c_int, [_P, C.c_char_p, C.POINTER(C.c_double), C.POINTER(C.c_int64)]),

@@ -193,6 +193,10 @@ constexpr int kMaxPoseUnknowns = 81;     // 3 per rotating joint + root t (3) + 
 constexpr int kPoseTile = 16;            // MFMA f64 16x16x4 tiles of J^T J
 constexpr int kPoseMaxCols = 96;         // unknowns + the b*F column, padded to 16
 constexpr int kPoseRowThreads = 256;
+constexpr int kPoseTerms = 6;            // energy terms: 2D, 3D, silhouette (b), silhouette (|b|), temporal, limits
+// Rows of the pose Jacobian before the contour rows: 2D (2 per joint), 3D and
+// temporal (3 per joint each), joint limits (one per rotational unknown).
+__host__ __device__ inline int pose_fixed_rows(int nj, int it) { return 8 * nj + it; }
 
 // Skeleton and skinning of a body (device copy of the static part).
 struct BodyDev {
@@ -213,6 +217,10 @@ struct PoseDev {
     double s3d, ssil;                // square roots of the 3D and silhouette weights
     double l2d;
     gptr<const double> p2d, p3d, lam;   // [2][nj], [3][nj], [nj]
+    gptr<const double> prev_joints;       // [3][nj] joint positions of the previous frame (temporal term), or null
+    double stemp[kMaxJoints];             // square roots of the per-joint temporal weights
+    double sanat;                         // square root of the joint-limit weight (0: no term)
+    double lim_lo[kMaxPoseUnknowns], lim_hi[kMaxPoseUnknowns];   // limits of the rotational unknowns
     gptr<double> pose;                    // caller's [nu]
     gptr<const float> dt;                 // [H][W]
     gptr<const uint8_t> vflags;           // [nv] decision flags
@@ -223,8 +231,8 @@ struct PoseDev {
     gptr<double> rows;                    // [np][ldr] Jacobian, column-major (row r, column c at c * ldr + r);
                                      // column nu holds b*F
     int ldr;                         // max_rows rounded up to 64
-    gptr<double> epart;                   // [row blocks][4] energy partials: 2D, 3D, sil, sil with |b|
-    gptr<double> energy;                  // [MAX_GN + 1][4]
+    gptr<double> epart;                   // [row blocks][kPoseTerms] energy partials
+    gptr<double> energy;                  // [MAX_GN + 1][kPoseTerms]
     gptr<double> sys;                     // [nu][nu + 1] system of the current step (J^T J | -J^T B F), undamped
     gptr<int> status;                     // [1]
 };

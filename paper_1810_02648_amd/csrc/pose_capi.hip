@@ -29,6 +29,11 @@ __global__ void k_pose_list(const PoseDev *P);
 __global__ void k_pose_rows(const PoseDev *P, int energy_only);
 __global__ void k_pose_jtj(const PoseDev *P);
 __global__ void k_pose_step(const PoseDev *P, int gn, int nblk, int mode);
+__global__ void k_body_skin(BodyDev B, const double *pose, float *out);
+__global__ void k_body_warp(BodyDev B, const double *pose_prev, const double *pose_cur, const float *Vp,
+                            const float *Sp, const float *Sc, float *out);
+__global__ void k_pose_extrapolate(int nu, const double *p, const double *p2, double *out);
+__global__ void k_body_joints(BodyDev B, const double *pose, double *out);
 
 namespace {
 
@@ -66,7 +71,7 @@ size_t carve_pose(uint8_t *base, const capture_pose_frame &f, ProbDev &pr, PoseD
     pr.vcode = L.take<uint8_t>(base, nv);
     pr.pva = L.take<float>(base, 3 * nv);
     pr.counts = L.take<int>(base, 3);
-    max_rows = 5 * B.nj + int(nv);
+    max_rows = pose_fixed_rows(B.nj, B.it) + int(nv);
     pd.jR = L.take<double>(base, size_t(9) * B.nj);
     pd.jp = L.take<double>(base, size_t(3) * B.nj);
     pd.jA = L.take<double>(base, size_t(9) * B.nj);
@@ -75,8 +80,8 @@ size_t carve_pose(uint8_t *base, const capture_pose_frame &f, ProbDev &pr, PoseD
     pd.nb = L.take<int>(base, 1);
     pd.ldr = (max_rows + 63) & ~63;
     pd.rows = L.take<double>(base, size_t(pd.ldr) * B.np);
-    pd.epart = L.take<double>(base, size_t(blocks(max_rows, kPoseRowThreads)) * 4);
-    pd.energy = L.take<double>(base, size_t(CAPTURE_MAX_GN + 1) * 4);
+    pd.epart = L.take<double>(base, size_t(blocks(max_rows, kPoseRowThreads)) * kPoseTerms);
+    pd.energy = L.take<double>(base, size_t(CAPTURE_MAX_GN + 1) * kPoseTerms);
     pd.sys = L.take<double>(base, size_t(B.nu) * (B.nu + 1));
     pd.status = L.take<int>(base, 1);
     return L.off;
@@ -102,6 +107,14 @@ int check_pose_params(const capture_pose_params *p) {
         return fail(CAPTURE_EINVAL, "weights must be finite and non-negative");
     if (p->flags & ~uint32_t(CAPTURE_FLAG_EXCLUDE_CASE2 | CAPTURE_FLAG_OUTLINE_ONLY))
         return fail(CAPTURE_EINVAL, "unknown flag bits");
+    for (int j = 0; j < CAPTURE_MAX_JOINTS; ++j)
+        if (!std::isfinite(p->l_temporal[j]) || p->l_temporal[j] < 0)
+            return fail(CAPTURE_EINVAL, "temporal weights must be finite and non-negative");
+    if (!std::isfinite(p->l_anatomic) || p->l_anatomic < 0)
+        return fail(CAPTURE_EINVAL, "the joint-limit weight must be finite and non-negative");
+    for (int q = 0; q < CAPTURE_MAX_POSE_UNKNOWNS; ++q)
+        if (std::isnan(p->theta_min[q]) || std::isnan(p->theta_max[q]) || p->theta_min[q] > p->theta_max[q])
+            return fail(CAPTURE_EINVAL, "joint limits: theta_min <= theta_max, no NaN");
     return CAPTURE_OK;
 }
 
@@ -137,6 +150,18 @@ int pose_setup(PoseRun &P, capture_ctx *ctx, const capture_pose_frame *f, const 
     pd.s3d = std::sqrt(prm->l3d);
     pd.ssil = std::sqrt(prm->lsil);
     pd.p2d = f->p2d; pd.p3d = f->p3d; pd.lam = f->lambda;
+    bool temporal = false;
+    for (int j = 0; j < body.dev.nj; ++j) {
+        pd.stemp[j] = std::sqrt(prm->l_temporal[j]);
+        temporal = temporal || prm->l_temporal[j] > 0.0;
+    }
+    if (temporal && !f->prev_joints) return fail(CAPTURE_EINVAL, "temporal weights without prev_joints");
+    pd.prev_joints = temporal ? f->prev_joints : nullptr;
+    pd.sanat = std::sqrt(prm->l_anatomic);
+    for (int q = 0; q < kMaxPoseUnknowns; ++q) {
+        pd.lim_lo[q] = prm->theta_min[q];
+        pd.lim_hi[q] = prm->theta_max[q];
+    }
     pd.pose = f->pose;
     pd.dt = pr.dt;
     pd.vflags = pr.vflags;
@@ -334,20 +359,26 @@ int capture_pose_solve(capture_ctx *ctx, const capture_pose_frame *f, const capt
     for (int g = 0; g < G; ++g)
         if ((rc = launch_pose_step(P, g, 0))) return rc;
     if ((rc = launch_pose_step(P, G, 1))) return rc;
-    double en[4 * (CAPTURE_MAX_GN + 1)];
+    double en[kPoseTerms * (CAPTURE_MAX_GN + 1)];
     int st = 0, counts[2] = {0, 0};
     hipStream_t s = P.R.s;
-    CAP_HIP(hipMemcpyAsync(en, P.pd.energy, sizeof(double) * 4 * (G + 1), hipMemcpyDeviceToHost, s));
+    CAP_HIP(hipMemcpyAsync(en, P.pd.energy, sizeof(double) * kPoseTerms * (G + 1), hipMemcpyDeviceToHost, s));
     CAP_HIP(hipMemcpyAsync(&st, P.pd.status, sizeof(int), hipMemcpyDeviceToHost, s));
     CAP_HIP(hipMemcpyAsync(counts, P.R.probs[0].counts, sizeof(int) * 2, hipMemcpyDeviceToHost, s));
     CAP_HIP(hipStreamSynchronize(s));
     settle(P.R);
     *rep = capture_pose_report{};
-    for (int g = 0; g <= G; ++g) rep->energy[g] = (en[4 * g] + en[4 * g + 1]) + en[4 * g + 2];
-    rep->e2d = en[4 * G];
-    rep->e3d = en[4 * G + 1];
-    rep->e_sil = en[4 * G + 2];
-    rep->e_sil_abs = en[4 * G + 3];
+    for (int g = 0; g <= G; ++g) {
+        const double *e = en + kPoseTerms * g;
+        rep->energy[g] = (((e[0] + e[1]) + e[2]) + e[4]) + e[5];
+    }
+    const double *e = en + kPoseTerms * G;
+    rep->e2d = e[0];
+    rep->e3d = e[1];
+    rep->e_sil = e[2];
+    rep->e_sil_abs = e[3];
+    rep->e_temporal = e[4];
+    rep->e_anatomic = e[5];
     rep->n_visible = counts[0];
     rep->n_boundary = counts[1];
     rep->gn_done = G;
@@ -368,14 +399,56 @@ int capture_pose_linearize(capture_ctx *ctx, const capture_pose_frame *f, const 
     if ((rc = launch_pose_step(P, 0, 2))) return rc;
     hipStream_t s = P.R.s;
     const int nu = P.pd.B.nu;
-    double en[4];
+    double en[kPoseTerms];
     if (system) CAP_HIP(hipMemcpyAsync(system, P.pd.sys, sizeof(double) * nu * (nu + 1), hipMemcpyDeviceToDevice, s));
     if (vflags) CAP_HIP(hipMemcpyAsync(vflags, P.R.probs[0].vflags, P.pd.B.nv, hipMemcpyDeviceToDevice, s));
     CAP_HIP(hipMemcpyAsync(en, P.pd.energy, sizeof(en), hipMemcpyDeviceToHost, s));
     CAP_HIP(hipStreamSynchronize(s));
     settle(P.R);
     if (energy)
-        for (int q = 0; q < 4; ++q) energy[q] = en[q];
+        for (int q = 0; q < kPoseTerms; ++q) energy[q] = en[q];
+    return CAPTURE_OK;
+}
+
+int capture_body_skin(capture_ctx *ctx, const capture_body *b, const double *pose, float *xyz, void *stream) {
+    if (!ctx || !b || !pose || !xyz) return fail(CAPTURE_EINVAL, "null argument");
+    if (b->device != ctx->device) return fail(CAPTURE_EINVAL, "body belongs to another device");
+    CAP_HIP(hipSetDevice(ctx->device));
+    hipLaunchKernelGGL(k_body_skin, dim3(blocks(b->dev.nv, 256)), dim3(256), 0, static_cast<hipStream_t>(stream),
+                       b->dev, pose, xyz);
+    CAP_HIP(hipGetLastError());
+    return CAPTURE_OK;
+}
+
+int capture_body_warp(capture_ctx *ctx, const capture_body *b, const double *pose_prev, const double *pose_cur,
+                      const float *V_prev, const float *posed_prev, const float *posed_cur, float *start,
+                      void *stream) {
+    if (!ctx || !b || !pose_prev || !pose_cur || !V_prev || !posed_prev || !posed_cur || !start)
+        return fail(CAPTURE_EINVAL, "null argument");
+    if (b->device != ctx->device) return fail(CAPTURE_EINVAL, "body belongs to another device");
+    CAP_HIP(hipSetDevice(ctx->device));
+    hipLaunchKernelGGL(k_body_warp, dim3(blocks(b->dev.nv, 256)), dim3(256), 0, static_cast<hipStream_t>(stream),
+                       b->dev, pose_prev, pose_cur, V_prev, posed_prev, posed_cur, start);
+    CAP_HIP(hipGetLastError());
+    return CAPTURE_OK;
+}
+
+int capture_body_joints(capture_ctx *ctx, const capture_body *b, const double *pose, double *joints, void *stream) {
+    if (!ctx || !b || !pose || !joints) return fail(CAPTURE_EINVAL, "null argument");
+    if (b->device != ctx->device) return fail(CAPTURE_EINVAL, "body belongs to another device");
+    CAP_HIP(hipSetDevice(ctx->device));
+    hipLaunchKernelGGL(k_body_joints, dim3(1), dim3(64), 0, static_cast<hipStream_t>(stream), b->dev, pose, joints);
+    CAP_HIP(hipGetLastError());
+    return CAPTURE_OK;
+}
+
+int capture_pose_extrapolate(capture_ctx *ctx, const capture_body *b, const double *pose_prev,
+                             const double *pose_prev2, double *pose_out, void *stream) {
+    if (!ctx || !b || !pose_prev || !pose_prev2 || !pose_out) return fail(CAPTURE_EINVAL, "null argument");
+    CAP_HIP(hipSetDevice(ctx->device));
+    hipLaunchKernelGGL(k_pose_extrapolate, dim3(1), dim3(128), 0, static_cast<hipStream_t>(stream), b->dev.nu,
+                       pose_prev, pose_prev2, pose_out);
+    CAP_HIP(hipGetLastError());
     return CAPTURE_OK;
 }
 

@@ -254,7 +254,8 @@ __device__ inline void rotation_entries(const BodyDev &B, CAP_GLOBAL double *row
     }
 }
 
-// One Jacobian row per thread: 2 per joint (2D), 3 per joint (3D), one per
+// One Jacobian row per thread: 2 per joint (2D), 3 per joint (3D), 3 per joint
+// (temporal stabilisation), one per rotational unknown (joint limits), one per
 // contour vertex (silhouette).  Column nu holds b * F.  With energy_only the
 // rows are not written.  Per-block energy partials go to epart.
 __global__ __launch_bounds__(kPoseRowThreads) void k_pose_rows(const PoseDev *__restrict__ PP, int energy_only) {
@@ -270,10 +271,22 @@ __global__ __launch_bounds__(kPoseRowThreads) void k_pose_rows(const PoseDev *__
     __syncthreads();
     const int nj = B.nj, nu = B.nu, np_ = B.np;
     const size_t ldr = P.ldr;
-    const int M = 5 * nj + P.nb[0];
+    const int nfix = pose_fixed_rows(nj, B.it);
+    const int M = nfix + P.nb[0];
     const int r = blockIdx.x * blockDim.x + threadIdx.x;
-    double en[4] = {0.0, 0.0, 0.0, 0.0};
-    if (r < M) {
+    double en[kPoseTerms] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    if (r >= 8 * nj && r < nfix) {
+        // joint-limit barrier on rotational unknown q: one entry in the row
+        const int q = r - 8 * nj;
+        const double th = P.pose[q], lo = P.lim_lo[q], hi = P.lim_hi[q];
+        const double jq = th > hi ? P.sanat : (th < lo ? -P.sanat : 0.0);
+        const double F = th > hi ? P.sanat * (th - hi) : (th < lo ? P.sanat * (lo - th) : 0.0);
+        en[5] = F * F;
+        if (!energy_only) {
+            CAP_GLOBAL double *row = P.rows.g() + r;
+            for (int c = 0; c < np_; ++c) row[c * ldr] = c == q ? jq : (c == nu ? F : 0.0);
+        }
+    } else if (r < M) {
         CAP_GLOBAL double *row = P.rows.g() + r;      // column-major: entry c at row[c * ldr]
         double g[3], F;
         double ys[4][3], ws[4];
@@ -282,10 +295,10 @@ __global__ __launch_bounds__(kPoseRowThreads) void k_pose_rows(const PoseDev *__
         double tw;                    // weight of the root translation columns
         bool has_tp = false;
         int tpc = 0;
-        if (r < 5 * nj) {
-            const bool is2d = r < 2 * nj;
-            const int j = is2d ? r >> 1 : (r - 2 * nj) / 3;
-            const int c = is2d ? r & 1 : (r - 2 * nj) % 3;
+        if (r < 8 * nj) {
+            const bool is2d = r < 2 * nj, istemp = r >= 5 * nj;
+            const int j = is2d ? r >> 1 : (istemp ? (r - 5 * nj) / 3 : (r - 2 * nj) / 3);
+            const int c = is2d ? r & 1 : (istemp ? (r - 5 * nj) % 3 : (r - 2 * nj) % 3);
             const double X = sp[3 * j], Y = sp[3 * j + 1], Z = sp[3 * j + 2];
             if (is2d) {
                 const double s = sqrt(P.l2d * P.lam[j]);
@@ -299,20 +312,26 @@ __global__ __launch_bounds__(kPoseRowThreads) void k_pose_rows(const PoseDev *__
                     g[0] = 0.0; g[1] = s * (P.fy / Z); g[2] = s * (-(P.fy * Y) / (Z * Z));
                 }
                 en[0] = F * F;
-            } else {
+            } else if (!istemp) {
                 F = P.s3d * ((sp[3 * j + c] - P.p3d[c * nj + j]) - P.pose[B.itp + c]);
                 g[0] = g[1] = g[2] = 0.0;
                 g[c] = P.s3d;
                 has_tp = true;
                 tpc = c;
                 en[1] = F * F;
+            } else {        // temporal stabilisation: sqrt(w_j) (p_j - p_j^{t-1})
+                const double st = P.prev_joints ? P.stemp[j] : 0.0;
+                F = P.prev_joints ? st * (sp[3 * j + c] - P.prev_joints[c * nj + j]) : 0.0;
+                g[0] = g[1] = g[2] = 0.0;
+                g[c] = st;
+                en[4] = F * F;
             }
             ys[0][0] = X; ys[0][1] = Y; ys[0][2] = Z;
             ws[0] = 1.0;
             masks[0] = B.anc[j] & ~(1u << j);     // a joint does not move with its own rotation
             tw = 1.0;
         } else {
-            const int e = P.blist[r - 5 * nj];
+            const int e = P.blist[r - nfix];
             const int i = e >> 1;
             const double bs = (e & 1) ? -1.0 : 1.0;
             const int nv = B.nv;
@@ -355,9 +374,9 @@ __global__ __launch_bounds__(kPoseRowThreads) void k_pose_rows(const PoseDev *__
             for (int c = nu + 1; c < np_; ++c) row[c * ldr] = 0.0;
         }
     }
-    for (int q = 0; q < 4; ++q) {
+    for (int q = 0; q < kPoseTerms; ++q) {
         const double s = block_sum<kPoseRowThreads>(en[q], red);
-        if (threadIdx.x == 0) P.epart[size_t(blockIdx.x) * 4 + q] = s;
+        if (threadIdx.x == 0) P.epart[size_t(blockIdx.x) * kPoseTerms + q] = s;
     }
 }
 
@@ -380,7 +399,7 @@ __global__ __launch_bounds__(64 * kJtjWaves) void k_pose_jtj(const PoseDev *__re
     int I = 0, rem = blockIdx.x;
     while (rem >= nt - I) { rem -= nt - I; ++I; }
     const int Jt = I + rem;
-    const int M = 5 * P.B.nj + P.nb[0];
+    const int M = pose_fixed_rows(P.B.nj, P.B.it) + P.nb[0];
     const int wv = threadIdx.x >> 6, l = threadIdx.x & 63, li = l & 15, lk = l >> 4;
     dbl4 acc = {0.0, 0.0, 0.0, 0.0};
     const CAP_GLOBAL double *col_a = P.rows.g() + size_t(I * kPoseTile + li) * P.ldr;     // column-major rows
@@ -435,7 +454,7 @@ __global__ __launch_bounds__(kStepThreads) void k_pose_step(const PoseDev *__res
     const int t = threadIdx.x;
     __shared__ double A[kMaxPoseUnknowns * (kMaxPoseUnknowns + 1)];
     __shared__ double pn[kMaxPoseUnknowns];
-    __shared__ double ep[64 * 4];
+    __shared__ double ep[64 * kPoseTerms];
     __shared__ double red[kStepThreads / 64];
     __shared__ int bad;
     // energies of the rows kernel's blocks (4 terms each), summed in block
@@ -444,13 +463,13 @@ __global__ __launch_bounds__(kStepThreads) void k_pose_step(const PoseDev *__res
     double es = 0.0;
     for (int b0 = 0; b0 < nblk; b0 += 64) {
         __syncthreads();
-        if (t < 256) ep[t] = b0 + (t >> 2) < nblk ? P.epart[size_t(b0) * 4 + t] : 0.0;
+        if (t < 64 * kPoseTerms) ep[t] = b0 + t / kPoseTerms < nblk ? P.epart[size_t(b0) * kPoseTerms + t] : 0.0;
         __syncthreads();
-        if (t < 4)
-            for (int b = 0; b < 64 && b0 + b < nblk; ++b) es += ep[b * 4 + t];
+        if (t < kPoseTerms)
+            for (int b = 0; b < 64 && b0 + b < nblk; ++b) es += ep[b * kPoseTerms + t];
     }
-    if (t < 4) {
-        P.energy[gn * 4 + t] = es;
+    if (t < kPoseTerms) {
+        P.energy[gn * kPoseTerms + t] = es;
         if (!isfinite(es)) bad = 1;
     }
     __syncthreads();
@@ -594,6 +613,119 @@ __global__ __launch_bounds__(kStepThreads) void k_pose_step(const PoseDev *__res
            *sJ = sL + 9 * kMaxJoints;
     fk_block(B, pn, sR, sp, sA, sL, sJ);
     fk_store(P, sR, sp, sA);
+}
+
+// ---------------------------------------------------------------- skinning, warping, extrapolation
+// Skinned mesh at a pose: kinematics per workgroup (in LDS), then the float32
+// linear-blend recipe of k_pose_lbs for the workgroup's vertices.
+__global__ __launch_bounds__(256) void k_body_skin(BodyDev B, const double *__restrict__ pose, float *__restrict__ out) {
+    __shared__ double sR[9 * kMaxJoints], sp[3 * kMaxJoints], sA[9 * kMaxJoints], sL[9 * kMaxJoints],
+        sJ[9 * kMaxJoints];
+    __shared__ float fR[9 * kMaxJoints], fp[3 * kMaxJoints], fJ[3 * kMaxJoints];
+    fk_block(B, pose, sR, sp, sA, sL, sJ);
+    for (int e = threadIdx.x; e < 9 * B.nj; e += blockDim.x) fR[e] = float(sR[e]);
+    for (int e = threadIdx.x; e < 3 * B.nj; e += blockDim.x) {
+        fp[e] = float(sp[e]);
+        fJ[e] = float(B.rest[e % 3][e / 3]);
+    }
+    __syncthreads();
+    const int nv = B.nv, i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nv) return;
+    const float v[3] = {B.xyz[i], B.xyz[nv + i], B.xyz[2 * nv + i]};
+    float acc[3] = {0.0f, 0.0f, 0.0f};
+    for (int s = 0; s < 4; ++s) {
+        const int j = B.bind_joint[size_t(s) * nv + i];
+        const float w = B.bind_w[size_t(s) * nv + i];
+        const float d[3] = {v[0] - fJ[3 * j], v[1] - fJ[3 * j + 1], v[2] - fJ[3 * j + 2]};
+        for (int a = 0; a < 3; ++a) {
+            const float *R = fR + 9 * j + 3 * a;
+            const float q = (R[0] * d[0] + R[1] * d[1]) + R[2] * d[2];
+            acc[a] = acc[a] + w * (q + fp[3 * j + a]);
+        }
+    }
+    for (int a = 0; a < 3; ++a) out[size_t(a) * nv + i] = acc[a];
+}
+
+// Unit quaternion (w, x, y, z) of a rotation matrix (row-major), from the
+// largest of the trace and the diagonal entries (Shepperd's method).
+__device__ inline void quat_of(const double *R, double *q) {
+    const double tr = (R[0] + R[4]) + R[8];
+    if (tr > 0.0) {
+        const double s = 2.0 * sqrt(tr + 1.0);
+        q[0] = 0.25 * s; q[1] = (R[7] - R[5]) / s; q[2] = (R[2] - R[6]) / s; q[3] = (R[3] - R[1]) / s;
+    } else if (R[0] > R[4] && R[0] > R[8]) {
+        const double s = 2.0 * sqrt(((1.0 + R[0]) - R[4]) - R[8]);
+        q[0] = (R[7] - R[5]) / s; q[1] = 0.25 * s; q[2] = (R[1] + R[3]) / s; q[3] = (R[2] + R[6]) / s;
+    } else if (R[4] > R[8]) {
+        const double s = 2.0 * sqrt(((1.0 + R[4]) - R[0]) - R[8]);
+        q[0] = (R[2] - R[6]) / s; q[1] = (R[1] + R[3]) / s; q[2] = 0.25 * s; q[3] = (R[5] + R[7]) / s;
+    } else {
+        const double s = 2.0 * sqrt(((1.0 + R[8]) - R[0]) - R[4]);
+        q[0] = (R[3] - R[1]) / s; q[1] = (R[2] + R[6]) / s; q[2] = (R[5] + R[7]) / s; q[3] = 0.25 * s;
+    }
+}
+
+// Rotation of a vertex under dual-quaternion skinning: its influences'
+// quaternions flipped into the first one's hemisphere, blended, normalised.
+__device__ inline void blend_rotation(const BodyDev &B, const double *qj, int i, double M[9]) {
+    const int nv = B.nv;
+    double q[4] = {0.0, 0.0, 0.0, 0.0};
+    const int j0 = B.bind_joint[i];
+    for (int s = 0; s < 4; ++s) {
+        const int j = B.bind_joint[size_t(s) * nv + i];
+        const double w = B.bind_w[size_t(s) * nv + i];
+        const double dot = ((qj[4 * j] * qj[4 * j0] + qj[4 * j + 1] * qj[4 * j0 + 1]) + qj[4 * j + 2] * qj[4 * j0 + 2]) +
+                           qj[4 * j + 3] * qj[4 * j0 + 3];
+        const double ws = dot < 0.0 ? -w : w;
+        for (int c = 0; c < 4; ++c) q[c] += ws * qj[4 * j + c];
+    }
+    const double n = sqrt(((q[0] * q[0] + q[1] * q[1]) + q[2] * q[2]) + q[3] * q[3]);
+    const double w = q[0] / n, x = q[1] / n, y = q[2] / n, z = q[3] / n;
+    M[0] = 1.0 - 2.0 * (y * y + z * z); M[1] = 2.0 * (x * y - w * z); M[2] = 2.0 * (x * z + w * y);
+    M[3] = 2.0 * (x * y + w * z); M[4] = 1.0 - 2.0 * (x * x + z * z); M[5] = 2.0 * (y * z - w * x);
+    M[6] = 2.0 * (x * z - w * y); M[7] = 2.0 * (y * z + w * x); M[8] = 1.0 - 2.0 * (x * x + y * y);
+}
+
+// Displacement warping: start = S_cur + M_cur M_prev^T (V_prev - S_prev).
+__global__ __launch_bounds__(256) void k_body_warp(BodyDev B, const double *__restrict__ pose_prev,
+                                                   const double *__restrict__ pose_cur, const float *__restrict__ Vp,
+                                                   const float *__restrict__ Sp, const float *__restrict__ Sc,
+                                                   float *__restrict__ out) {
+    __shared__ double sR[9 * kMaxJoints], sp[3 * kMaxJoints], sA[9 * kMaxJoints], sL[9 * kMaxJoints],
+        sJ[9 * kMaxJoints];
+    __shared__ double qp[4 * kMaxJoints], qc[4 * kMaxJoints];
+    const int nj = B.nj, t = threadIdx.x;
+    fk_block(B, pose_prev, sR, sp, sA, sL, sJ);
+    if (t < nj) quat_of(sR + 9 * t, qp + 4 * t);
+    __syncthreads();
+    fk_block(B, pose_cur, sR, sp, sA, sL, sJ);
+    if (t < nj) quat_of(sR + 9 * t, qc + 4 * t);
+    __syncthreads();
+    const int nv = B.nv, i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nv) return;
+    double Mp[9], Mc[9], d[3], r[3];
+    blend_rotation(B, qp, i, Mp);
+    blend_rotation(B, qc, i, Mc);
+    for (int a = 0; a < 3; ++a) d[a] = double(Vp[size_t(a) * nv + i]) - double(Sp[size_t(a) * nv + i]);
+    for (int a = 0; a < 3; ++a) r[a] = (Mp[a] * d[0] + Mp[3 + a] * d[1]) + Mp[6 + a] * d[2];       // M_prev^T d
+    for (int a = 0; a < 3; ++a)
+        out[size_t(a) * nv + i] =
+            float(double(Sc[size_t(a) * nv + i]) + ((Mc[3 * a] * r[0] + Mc[3 * a + 1] * r[1]) + Mc[3 * a + 2] * r[2]));
+}
+
+// Joint positions at a pose, out [3][nj].
+__global__ __launch_bounds__(64) void k_body_joints(BodyDev B, const double *__restrict__ pose, double *__restrict__ out) {
+    __shared__ double sR[9 * kMaxJoints], sp[3 * kMaxJoints], sA[9 * kMaxJoints], sL[9 * kMaxJoints],
+        sJ[9 * kMaxJoints];
+    fk_block(B, pose, sR, sp, sA, sL, sJ);
+    for (int e = threadIdx.x; e < 3 * B.nj; e += blockDim.x) out[(e % 3) * B.nj + e / 3] = sp[e];
+}
+
+// Explicit Euler step of the pose: out = p + (p - p2).
+__global__ void k_pose_extrapolate(int nu, const double *__restrict__ p, const double *__restrict__ p2,
+                                   double *__restrict__ out) {
+    const int e = threadIdx.x;
+    if (e < nu) out[e] = p[e] + (p[e] - p2[e]);
 }
 
 }  // namespace cap

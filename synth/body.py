@@ -55,6 +55,17 @@ _PARTS = [(0, 2, 0.16), (2, 3, 0.10), (4, "e4", 0.11), (6, 7, 0.055), (7, 8, 0.0
 PART_CLASS = np.array([1, 2, 7, 5, 5, 6, 5, 5, 6, 3, 3, 6, 6, 3, 3, 6, 6, 2, 2], np.int32)
 
 
+# Per-joint temporal smoothness weights lambda_i of the pose stage (Sec. 3.3:
+# 2.5 torso and head, 2.0 shoulders, 1.5 knees and elbows, 1.0 hands and
+# feet), mapped onto this skeleton: clavicles count as shoulders, hips as
+# torso, wrists and hand ends as hands, ankles and toes as feet.
+TEMPORAL_JOINT_WEIGHTS = np.array([2.5, 2.5, 2.5, 2.5, 2.5,
+                                   2.0, 2.0, 1.5, 1.0, 1.0,
+                                   2.0, 2.0, 1.5, 1.0, 1.0,
+                                   2.5, 1.5, 1.0, 1.0,
+                                   2.5, 1.5, 1.0, 1.0])
+
+
 def dof_joints():
     """Joints that carry 3 axis-angle unknowns, in unknown order (pelvis first)."""
     return [j for j in range(len(JOINTS)) if j not in NO_DOF]

@@ -157,18 +157,19 @@ def _body_pose_at(m, t):
     from .body import pose_mesh
     pose = np.zeros(69)
     pose[:m["amp"].size] = m["amp"] * np.sin(2.0 * np.pi * m["freq"] * t + m["phase"])
-    posed, _ = pose_mesh(m["body"], pose)
+    posed, P = pose_mesh(m["body"], pose)
+    pose[66:69] = P[0]                    # t' maps root-relative 3D joints to the camera frame
     c = m["cloth"]
     off = (c["A"] * np.cos(c["w"] * t)[:, None, None] + c["B"] * np.sin(c["w"] * t)[:, None, None]).sum(0) / 2.0
     gt = posed.T.astype(np.float64) + c["wts"] @ off
-    return posed, np.ascontiguousarray(gt.T.astype(np.float32))
+    return posed, np.ascontiguousarray(gt.T.astype(np.float32)), pose, P
 
 
 def _render_body_frame(args):
     tri, rgb, cam, m, t = args
-    posed, gt = _body_pose_at(m, t)
+    posed, gt, pose, P = _body_pose_at(m, t)
     mask, image = render_targets(gt, tri, rgb, cam)
-    return posed, gt, mask, image
+    return posed, gt, mask, image, pose, P
 
 
 def make_sequence(name="seq20k", seed=0, n_frames=None, workers=None):
@@ -203,9 +204,12 @@ def make_sequence(name="seq20k", seed=0, n_frames=None, workers=None):
             frames = list(ex.map(render, jobs, chunksize=4))
     else:
         frames = [render(j) for j in jobs]
+    extra = {}
+    if cfg["mesh"] == "body":
+        extra = dict(body=body, poses=[f[4] for f in frames], joints=[f[5] for f in frames])
     return dict(name=name, seed=seed, xyz=xyz, tri=tri, rgb=rgb, cam=cam, classes=classes,
                 posed=[f[0] for f in frames], gt=[f[1] for f in frames], masks=[f[2] for f in frames],
-                images=[f[3] for f in frames],
+                images=[f[3] for f in frames], **extra,
                 n_nodes=cfg["n_nodes"], n_train=cfg["n_train"], gn=cfg["gn"], pcg=cfg["pcg"],
                 weights=cfg["weights"], w_vel=cfg["w_vel"], outline=cfg.get("outline", False))
 
@@ -240,3 +244,37 @@ def vertex_frame(seq, t, weights=None):
                 start=np.ascontiguousarray(start), gt=seq["gt"][t],
                 weights=vertex_weights_for(side) if weights is None else weights,
                 outline=seq.get("outline", False))
+
+
+def pose_detections(seq, t, px_sigma=None, m_sigma=0.02):
+    """Noisy 2D and 3D joint detections of frame t of a body sequence (the
+    stand-in for the CNN detections of Sec. 3.3): 2D = projected ground-truth
+    joints + N(0, px_sigma^2) px (default 3 px at 1080 px, scaled with the
+    image side), 3D = root-relative ground truth + N(0, m_sigma^2) m,
+    confidences 1; seeded by the frame index."""
+    rng = np.random.Generator(np.random.PCG64(1000 + t))
+    cam, P = seq["cam"], seq["joints"][t]
+    if px_sigma is None:
+        px_sigma = 3.0 * cam.width / 1080.0
+    u = cam.fx * P[:, 0] / P[:, 2] + cam.cx
+    v = cam.fy * P[:, 1] / P[:, 2] + cam.cy
+    p2d = np.stack([u, v], axis=1) + rng.normal(0.0, px_sigma, (P.shape[0], 2))
+    p3d = (P - P[0]) + rng.normal(0.0, m_sigma, P.shape)
+    return np.ascontiguousarray(p2d.T), np.ascontiguousarray(p3d.T), np.ones(P.shape[0])
+
+
+def tracking_pose_params(side, n_rot):
+    """Pose-stage weights for tracking a body sequence (a reading; Sec. 3.3 and
+    Sec. 5 give the terms, not weights in these units): 2D weight 1 / sigma^2
+    of the detection noise (pixels), 3D 1 / 0.02^2 (metres), temporal
+    stabilisation 100 lambda_i (metres), joint limits 1e6 outside +-1 rad on
+    every rotational unknown but the root's, no silhouette term (on these
+    synthetic frames it pulled the pose off the joints; the non-rigid stage
+    aligns the silhouette)."""
+    from .body import TEMPORAL_JOINT_WEIGHTS
+    sigma = 3.0 * side / 1080.0
+    lo = np.full(n_rot, -1.0)
+    hi = np.full(n_rot, 1.0)
+    lo[:3], hi[:3] = -np.inf, np.inf
+    return dict(l2d=1.0 / sigma ** 2, l3d=2500.0, lsil=0.0, l_temporal=100.0 * TEMPORAL_JOINT_WEIGHTS,
+                l_anatomic=1e6, theta_min=lo, theta_max=hi)

@@ -183,3 +183,52 @@ def test_pose_solve_is_deterministic(ctx, frames):
         rep = cap.pose_solve(ctx, fr, cap.pose_params(*WEIGHTS, gn_iters=3))
         outs.append((fr.pose.cpu().numpy(), rep["energy"]))
     assert np.array_equal(outs[0][0], outs[1][0]) and outs[0][1] == outs[1][1]
+
+
+@pytest.mark.parametrize("name", ["small", "full"])
+def test_temporal_and_joint_limit_terms_match_oracle(ctx, frames, name):
+    """E_temporal (previous joint positions, per-joint weights) and E_anatomic
+    (quadratic barrier outside the limits, Sec. 3.3): normal equations and a
+    3-step solve against the oracle; the limits are set so that several
+    unknowns start outside them."""
+    import paper_1810_02648_amd as cap
+    from gpu_util import dev
+    f = frames[name]
+    b = f["body"]
+    sk = op.Skeleton(b["parents"], b["joints"], sb.NO_DOF)
+    pose0 = start_pose(f, seed=5)
+    prev = start_pose(f, sigma=0.08, seed=9)
+    _, pj, _ = sk.fk(prev)
+    prevj = np.ascontiguousarray(pj.T)
+    lt = 300.0 * sb.TEMPORAL_JOINT_WEIGHTS
+    lo = np.full(sk.it, -0.25)
+    hi = np.full(sk.it, 0.25)
+    lo[:3], hi[:3] = -np.inf, np.inf
+    assert ((pose0[:sk.it] > hi) | (pose0[:sk.it] < lo)).sum() >= 3
+    P = op.PoseProblem(sk, b["xyz"], b["tri"], b["bind_idx"], b["bind_w"], f["cam"], f["mask"], f["p2d"], f["p3d"],
+                       f["lam"], WEIGHTS, pose0, case2="exclude", outline=True, prev_joints=prevj, lam_temporal=lt,
+                       limits=(lo, hi), l_anat=1e4)
+    body = body_on_device(ctx, f)
+    prm = cap.pose_params(*WEIGHTS, gn_iters=3, l_temporal=lt, l_anatomic=1e4, theta_min=lo, theta_max=hi)
+    fr = cap.PoseInputs(body, f["cam"], dev(f["mask"]), dev(f["p2d"], torch.float64), dev(f["p3d"], torch.float64),
+                        dev(f["lam"], torch.float64), dev(pose0, torch.float64), prev_joints=dev(prevj))
+    out = cap.pose_linearize(ctx, fr, prm)
+    F, bb, J, e = P.linearize(pose0)
+    A = J.T @ (np.abs(bb)[:, None] * J)
+    rhs = -(J.T @ (bb * F))
+    S = out["system"].cpu().numpy()
+    assert np.abs(S[:, :-1] - A).max() <= 1e-9 * np.abs(A).max()
+    assert np.abs(S[:, -1] - rhs).max() <= 1e-9 * np.abs(rhs).max()
+    for k, key in enumerate(("e2d", "e3d", "sil", "sil_abs", "temporal", "anatomic")):
+        assert abs(out["energy"][k] - e[key]) <= 1e-10 * max(1.0, abs(e["total"])), (key, out["energy"][k], e[key])
+    assert e["temporal"] > 0 and e["anatomic"] > 0
+    ref = op.solve(P, 3)
+    rep = cap.pose_solve(ctx, fr, prm)
+    got = fr.pose.cpu().numpy()
+    step = np.linalg.norm(ref["pose"] - pose0)
+    assert np.linalg.norm(got - ref["pose"]) <= 1e-4 * step
+    E_ref = [x["total"] for x in ref["energies"]]
+    for a, r in zip(rep["energy"], E_ref):
+        assert abs(a - r) <= 1e-5 * E_ref[0]
+    assert abs(rep["e_temporal"] - ref["energies"][-1]["temporal"]) <= 1e-5 * E_ref[0]
+    assert abs(rep["e_anatomic"] - ref["energies"][-1]["anatomic"]) <= 1e-5 * E_ref[0]

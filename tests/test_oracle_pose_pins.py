@@ -10,6 +10,7 @@ import pytest
 from scipy.spatial.transform import Rotation
 
 from oracle import pose as op
+from oracle import so3
 from synth import body as sb
 
 
@@ -176,3 +177,95 @@ def test_gauss_newton_step_matches_dense_least_squares(small_pose):
     step = np.linalg.lstsq(Js, -Fs, rcond=None)[0]
     out = op.solve(P, 1)
     assert np.abs(out["pose"] - P.pose0 - step).max() < 1e-9 * max(1.0, np.abs(step).max())
+
+
+# ---------------------------------------------------------------- displacement warping (Sec. 3.4)
+def _warp_setup():
+    from synth import body as sb
+    b = sb.make_body(2000)
+    skel = op.Skeleton(b["parents"], b["joints"])
+    rng = np.random.default_rng(7)
+    p0 = np.zeros(skel.nu)
+    p0[:skel.it] = rng.normal(0, 0.3, skel.it)
+    p1 = p0.copy()
+    p1[:skel.it] += rng.normal(0, 0.2, skel.it)
+    p1[skel.it:skel.it + 3] += [0.05, -0.02, 0.03]
+    d = rng.normal(0, 0.01, b["xyz"].shape)
+    S0 = rng.normal(0, 1, b["xyz"].shape)
+    S1 = rng.normal(0, 1, b["xyz"].shape)
+    return b, skel, p0, p1, d, S0, S1
+
+
+def test_warp_is_a_plain_carry_when_the_pose_does_not_change():
+    b, skel, p0, _, d, S0, S1 = _warp_setup()
+    out = op.warp_displacements(skel, b["bind_idx"], b["bind_w"], p0, p0, S0 + d, S0, S1)
+    assert np.abs(out - (S1 + d)).max() < 1e-12
+
+
+def test_warp_under_a_global_rotation_rotates_the_displacement():
+    """Every joint turned by the same root rotation G: M_t M_{t-1}^T = G_t G_{t-1}^T."""
+    b, skel, _, _, d, S0, S1 = _warp_setup()
+    pa, pb = np.zeros(skel.nu), np.zeros(skel.nu)
+    wa, wb = np.array([0.2, -0.4, 0.1]), np.array([-0.5, 0.3, 0.7])
+    pa[0:3], pb[0:3] = wa, wb                             # joint 0 (the root) carries the global rotation
+    Ga, Gb = so3.exp(wa), so3.exp(wb)
+    out = op.warp_displacements(skel, b["bind_idx"], b["bind_w"], pa, pb, S0 + d, S0, S1)
+    assert np.abs(out - (S1 + Gb @ Ga.T @ d)).max() < 1e-12
+
+
+def test_warp_with_one_influence_follows_that_joint():
+    b, skel, p0, p1, d, S0, S1 = _warp_setup()
+    bi = b["bind_idx"].copy()
+    bw = np.zeros_like(b["bind_w"])
+    bw[0] = 1.0
+    R0, _, _ = skel.fk(p0)
+    R1, _, _ = skel.fk(p1)
+    out = op.warp_displacements(skel, bi, bw, p0, p1, S0 + d, S0, S1)
+    j = bi[0]
+    expect = S1 + np.einsum("nab,nb->na", R1[j] @ np.transpose(R0[j], (0, 2, 1)), d.T).T
+    assert np.abs(out - expect).max() < 1e-12
+    # blended rotations are rotations, and the blend of two equal rotations is that rotation
+    M = op.blended_rotations(skel, b["bind_idx"], b["bind_w"], p1)
+    assert np.abs(np.einsum("nab,ncb->nac", M, M) - np.eye(3)).max() < 1e-12
+    assert np.abs(np.linalg.det(M) - 1).max() < 1e-12
+
+
+def test_euler_extrapolation_is_exact_for_constant_velocity():
+    p2 = np.linspace(-0.3, 0.4, 69)
+    v = np.linspace(0.01, -0.02, 69)
+    assert np.allclose(op.extrapolate_pose(p2 + v, p2), p2 + 2 * v, rtol=0, atol=1e-15)
+
+
+def test_temporal_and_limit_rows_match_finite_differences_and_vanish_where_they_should():
+    """E_temporal vanishes at the previous joints and E_anatomic inside the
+    limits; their Jacobian rows match central differences (Sec. 3.3)."""
+    f = sb.make_pose_frame(n_vertices=2000, side=320, seed=3)
+    b = f["body"]
+    sk = op.Skeleton(b["parents"], b["joints"], sb.NO_DOF)
+    rng = np.random.default_rng(4)
+    pose = f["gt_pose"].copy()
+    pose[:sk.it] += rng.normal(0, 0.1, sk.it)
+    _, pj, _ = sk.fk(pose)
+    lo, hi = np.full(sk.it, -5.0), np.full(sk.it, 5.0)
+    P = op.PoseProblem(sk, b["xyz"], b["tri"], b["bind_idx"], b["bind_w"], f["cam"], f["mask"], f["p2d"], f["p3d"],
+                       f["lam"], (0.0, 0.0, 0.0), pose, prev_joints=pj.T, lam_temporal=np.full(sk.nj, 7.0),
+                       limits=(lo, hi), l_anat=3.0)
+    e = P.energy(pose)
+    assert e["temporal"] < 1e-24 and e["anatomic"] == 0.0
+    # a translation of the root moves every joint by it: E_temporal = sum_j w_j |d|^2
+    d = np.array([0.01, -0.02, 0.03])
+    moved = pose.copy()
+    moved[sk.it:sk.it + 3] += d
+    assert P.energy(moved)["temporal"] == pytest.approx(7.0 * sk.nj * (d @ d), rel=1e-10)
+    # one unknown 0.5 over its upper limit and one 0.25 under its lower limit
+    out = pose.copy()
+    out[4], out[10] = 5.5, -5.25
+    assert P.energy(out)["anatomic"] == pytest.approx(3.0 * (0.5 ** 2 + 0.25 ** 2), rel=1e-12)
+    F, bb, J, _ = P.linearize(out)
+    h = 1e-6
+    for c in (0, 4, 10, 20, sk.it, sk.it + 1, sk.it + 4):
+        pp, pm = out.copy(), out.copy()
+        pp[c] += h
+        pm[c] -= h
+        fd = (P.linearize(pp, False)[0] - P.linearize(pm, False)[0]) / (2 * h)
+        assert np.abs(fd - J[:, c]).max() <= 1e-5 * max(1.0, np.abs(J[:, c]).max()), c
