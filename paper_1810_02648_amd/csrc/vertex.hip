@@ -36,7 +36,8 @@ __global__ void k_raster_big(const ProbDev *P);
 __global__ void k_contour_edges(const ProbDev *P);
 __global__ void k_decide(const ProbDev *P);
 
-constexpr int kVThreads = 256;
+constexpr int kVThreads = 128;
+constexpr int kRingChunk = 4;       // one-ring neighbours whose gathers are issued together
 constexpr int kVTerms = 7;          // photo, sil (with b), sil (with |b|), smooth, edge, velocity, acceleration
 constexpr int kVLevels = 3;         // distinct Gaussian kernels per solve
 constexpr int kVMaxBlur = 15;
@@ -80,6 +81,13 @@ struct BlurW {
     int r;
 };
 
+// The blur levels of a solve: kernel radii and weights.
+struct BlurSet {
+    int n;
+    int r[kVLevels];
+    float w[kVLevels][kVMaxBlur];
+};
+
 }  // namespace cap
 
 struct capture_vertex_template {
@@ -107,26 +115,62 @@ __global__ __launch_bounds__(kVThreads) void k_vstart(const VertexDev *__restric
     for (int a = 0; a < 3; ++a) pr.x[1][a * size_t(nv) + i] = 0.0;
 }
 
-// One pass of the separable Gaussian (clamp-to-edge) over a [3][H][W]
-// image, taps added from -r to r.  A null src reads the frame's image (its
-// address comes from the problem descriptor, so a replayed graph reads the
-// current frame).
-__global__ __launch_bounds__(256) void k_vblur(const ProbDev *__restrict__ R, const float *__restrict__ src,
-                                               float *__restrict__ dst, int W, int H, int horizontal, BlurW bw) {
-    const int i = blockIdx.x * 256 + threadIdx.x;
-    if (i >= W * H) return;
-    if (!src) src = R->image;
-    const int y = i / W, x = i - y * W;
+// Horizontal passes of every blur level: a row segment of 256 pixels and its
+// clamped margins staged in LDS once for the three channels, then each pixel's
+// taps (added from -r to r) for each level; out: tmp[level][c][H][W].
+constexpr int kBlurMargin = (kVMaxBlur - 1) / 2;
+__global__ __launch_bounds__(256) void k_vblur_h(const ProbDev *__restrict__ R, float *__restrict__ tmp, int W, int H,
+                                                 BlurSet bs) {
+    __shared__ float sh[3][256 + 2 * kBlurMargin];
+    const int x0 = blockIdx.x * 256, y = blockIdx.y, t = threadIdx.x;
     const size_t plane = size_t(W) * H;
-    for (int c = 0; c < 3; ++c) {
-        const float *s = src + c * plane;
-        float acc = 0.0f;
-        for (int d = -bw.r; d <= bw.r; ++d) {
-            const float t = horizontal ? s[size_t(y) * W + min(max(x + d, 0), W - 1)]
-                                       : s[size_t(min(max(y + d, 0), H - 1)) * W + x];
-            acc = acc + bw.w[d + bw.r] * t;
+    const float *img = R->image;
+    for (int q = t; q < 256 + 2 * kBlurMargin; q += 256) {
+        const int x = min(max(x0 - kBlurMargin + q, 0), W - 1);
+        for (int c = 0; c < 3; ++c) sh[c][q] = img[c * plane + size_t(y) * W + x];
+    }
+    __syncthreads();
+    const int x = x0 + t;
+    if (x >= W) return;
+    for (int l = 0; l < bs.n; ++l) {
+        const int r = bs.r[l];
+        for (int c = 0; c < 3; ++c) {
+            float acc = 0.0f;
+            for (int d = -r; d <= r; ++d) acc = acc + bs.w[l][d + r] * sh[c][t + kBlurMargin + d];
+            tmp[(size_t(l) * 3 + c) * plane + size_t(y) * W + x] = acc;
         }
-        dst[c * plane + i] = acc;
+    }
+}
+
+// Vertical passes: level blockIdx.z, a tile of 64 columns x 16 rows with its
+// clamped margin rows staged in LDS per channel, taps added from -r to r.
+constexpr int kBlurTileW = 64, kBlurTileH = 16;
+struct BlurOut {
+    float *p[kVLevels];
+};
+__global__ __launch_bounds__(256) void k_vblur_v(const float *__restrict__ tmp, BlurOut out, int W, int H, BlurSet bs) {
+    __shared__ float sh[kBlurTileH + 2 * kBlurMargin][kBlurTileW];
+    const int l = blockIdx.z, r = bs.r[l];
+    const int x0 = blockIdx.x * kBlurTileW, y0 = blockIdx.y * kBlurTileH, t = threadIdx.x;
+    const int tx = t & (kBlurTileW - 1), ty = t / kBlurTileW;        // 4 row groups of 4 rows
+    const size_t plane = size_t(W) * H;
+    const int x = min(x0 + tx, W - 1);
+    for (int c = 0; c < 3; ++c) {
+        const float *src = tmp + (size_t(l) * 3 + c) * plane;
+        __syncthreads();
+        for (int q = ty; q < kBlurTileH + 2 * r; q += 256 / kBlurTileW) {
+            const int y = min(max(y0 - r + q, 0), H - 1);
+            sh[q][tx] = src[size_t(y) * W + x];
+        }
+        __syncthreads();
+        if (x0 + tx < W)
+            for (int k = 0; k < kBlurTileH / (256 / kBlurTileW); ++k) {
+                const int row = ty + k * (256 / kBlurTileW), y = y0 + row;
+                if (y >= H) break;
+                float acc = 0.0f;
+                for (int d = -r; d <= r; ++d) acc = acc + bs.w[l][d + r] * sh[row + r + d][tx];
+                out.p[l][c * plane + size_t(y) * W + x0 + tx] = acc;
+            }
     }
 }
 
@@ -230,36 +274,56 @@ __global__ __launch_bounds__(kVThreads) void k_vlin(const VertexDev *__restrict_
         if (pr.w_smooth > 0.0 || pr.w_edge > 0.0) {
             double S[3];
             for (int a = 0; a < 3; ++a) S[a] = pr.posed[size_t(a) * nv + i];
-            for (int k = 0; k < T.K; ++k) {
-                const int j = T.nbr[size_t(k) * nv + i];
-                if (j < 0) break;
-                const double ek = T.ek[size_t(k) * nv + i], ea = T.ea[size_t(k) * nv + i];
-                double Vj[3], xj[3], d[3], sm[3];
-                load3(pr.V[gp], nv, j, Vj);
-                load3(pr.x[gp], nv, j, xj);
-                for (int a = 0; a < 3; ++a) {
-                    Vj[a] += xj[a];
-                    d[a] = V[a] - Vj[a];
-                    sm[a] = d[a] - (S[a] - double(pr.posed[size_t(a) * nv + j]));
+            // the one-ring in chunks, each chunk's gathers in flight together
+            for (int k0 = 0; k0 < T.K; k0 += kRingChunk) {
+                int jn[kRingChunk];
+                double ek[kRingChunk], ea[kRingChunk], el[kRingChunk], Vj[kRingChunk][3], xj[kRingChunk][3];
+                float Sj[kRingChunk][3];
+#pragma unroll
+                for (int u = 0; u < kRingChunk; ++u) {
+                    const int k = min(k0 + u, T.K - 1);
+                    const size_t o = size_t(k) * nv + i;
+                    jn[u] = k0 + u < T.K ? T.nbr[o] : -1;
+                    ek[u] = T.ek[o];
+                    ea[u] = T.ea[o];
+                    el[u] = T.elen[o];
                 }
-                if (pr.w_smooth > 0.0) {
-                    es[3] += pr.w_smooth * ek * ((sm[0] * sm[0] + sm[1] * sm[1]) + sm[2] * sm[2]);
+#pragma unroll
+                for (int u = 0; u < kRingChunk; ++u) {
+                    const int q = jn[u] < 0 ? i : jn[u];
+                    load3(pr.V[gp], nv, q, Vj[u]);
+                    load3(pr.x[gp], nv, q, xj[u]);
+                    for (int a = 0; a < 3; ++a) Sj[u][a] = pr.posed[size_t(a) * nv + q];
+                }
+#pragma unroll
+                for (int u = 0; u < kRingChunk; ++u) {
+                    if (jn[u] < 0) continue;
+                    double d[3], sm[3];
                     for (int a = 0; a < 3; ++a) {
-                        gr[a] += pr.w_smooth * ea * sm[a];
-                        dg[a] += pr.w_smooth * ea;
+                        const double v = Vj[u][a] + xj[u][a];
+                        d[a] = V[a] - v;
+                        sm[a] = d[a] - (S[a] - double(Sj[u][a]));
+                    }
+                    if (pr.w_smooth > 0.0) {
+                        es[3] += pr.w_smooth * ek[u] * ((sm[0] * sm[0] + sm[1] * sm[1]) + sm[2] * sm[2]);
+                        for (int a = 0; a < 3; ++a) {
+                            gr[a] += pr.w_smooth * ea[u] * sm[a];
+                            dg[a] += pr.w_smooth * ea[u];
+                        }
+                    }
+                    if (pr.w_edge > 0.0) {
+                        const double len = sqrt((d[0] * d[0] + d[1] * d[1]) + d[2] * d[2]);
+                        const double dl = len - el[u];
+                        es[4] += pr.w_edge * ek[u] * dl * dl;
+                        if (len > 0.0)
+                            for (int a = 0; a < 3; ++a) {
+                                const double ua = d[a] / len;
+                                gr[a] += pr.w_edge * ea[u] * dl * ua;
+                                dg[a] += pr.w_edge * ea[u] * ua * ua;
+                            }
                     }
                 }
-                if (pr.w_edge > 0.0) {
-                    const double len = sqrt((d[0] * d[0] + d[1] * d[1]) + d[2] * d[2]);
-                    const double dl = len - double(T.elen[size_t(k) * nv + i]);
-                    es[4] += pr.w_edge * ek * dl * dl;
-                    if (len > 0.0)
-                        for (int a = 0; a < 3; ++a) {
-                            const double ua = d[a] / len;
-                            gr[a] += pr.w_edge * ea * dl * ua;
-                            dg[a] += pr.w_edge * ea * ua * ua;
-                        }
-                }
+                if (jn[kRingChunk - 1] < 0) break;
             }
         }
         if (mode == 1) {
@@ -331,27 +395,43 @@ __global__ __launch_bounds__(kVThreads) void k_vapply(const VertexDev *__restric
         out[1] = ((H1 * pi[0] + H3 * pi[1]) + H4 * pi[2]) + wt * pi[1];
         out[2] = ((H2 * pi[0] + H4 * pi[1]) + H5 * pi[2]) + wt * pi[2];
         if (pr.w_smooth > 0.0 || pr.w_edge > 0.0)
-            for (int k = 0; k < T.K; ++k) {
-                const int jn = T.nbr[size_t(k) * nv + i];
-                if (jn < 0) break;
-                const double ea = T.ea[size_t(k) * nv + i];
-                double pj[3], Vj[3], dp[3], d[3];
-                pval(jn, pj);
-                load3(Vg, nv, jn, Vj);
-                for (int a = 0; a < 3; ++a) {
-                    dp[a] = pi[a] - pj[a];
-                    d[a] = V[a] - Vj[a];
+            // the one-ring in chunks: a chunk's indices, then all its gathers in
+            // flight together (positions past the row's end re-read the vertex itself)
+            for (int k0 = 0; k0 < T.K; k0 += kRingChunk) {
+                int jn[kRingChunk];
+                double ea[kRingChunk], pj[kRingChunk][3], Vj[kRingChunk][3];
+#pragma unroll
+                for (int u = 0; u < kRingChunk; ++u) {
+                    const int k = min(k0 + u, T.K - 1);
+                    jn[u] = k0 + u < T.K ? T.nbr[size_t(k) * nv + i] : -1;
+                    ea[u] = T.ea[size_t(k) * nv + i];
                 }
-                if (pr.w_smooth > 0.0)
-                    for (int a = 0; a < 3; ++a) out[a] += pr.w_smooth * ea * dp[a];
-                if (pr.w_edge > 0.0) {
-                    const double len = sqrt((d[0] * d[0] + d[1] * d[1]) + d[2] * d[2]);
-                    if (len > 0.0) {
-                        const double ua[3] = {d[0] / len, d[1] / len, d[2] / len};
-                        const double s = pr.w_edge * ea * ((ua[0] * dp[0] + ua[1] * dp[1]) + ua[2] * dp[2]);
-                        for (int a = 0; a < 3; ++a) out[a] += s * ua[a];
+#pragma unroll
+                for (int u = 0; u < kRingChunk; ++u) {
+                    const int q = jn[u] < 0 ? i : jn[u];
+                    pval(q, pj[u]);
+                    load3(Vg, nv, q, Vj[u]);
+                }
+#pragma unroll
+                for (int u = 0; u < kRingChunk; ++u) {
+                    if (jn[u] < 0) continue;
+                    double dp[3], d[3];
+                    for (int a = 0; a < 3; ++a) {
+                        dp[a] = pi[a] - pj[u][a];
+                        d[a] = V[a] - Vj[u][a];
+                    }
+                    if (pr.w_smooth > 0.0)
+                        for (int a = 0; a < 3; ++a) out[a] += pr.w_smooth * ea[u] * dp[a];
+                    if (pr.w_edge > 0.0) {
+                        const double len = sqrt((d[0] * d[0] + d[1] * d[1]) + d[2] * d[2]);
+                        if (len > 0.0) {
+                            const double ua[3] = {d[0] / len, d[1] / len, d[2] / len};
+                            const double s = pr.w_edge * ea[u] * ((ua[0] * dp[0] + ua[1] * dp[1]) + ua[2] * dp[2]);
+                            for (int a = 0; a < 3; ++a) out[a] += s * ua[a];
+                        }
                     }
                 }
+                if (jn[kRingChunk - 1] < 0) break;
             }
         for (int a = 0; a < 3; ++a) {
             const size_t o = size_t(a) * nv + i;
@@ -465,7 +545,7 @@ size_t carve_vertex(uint8_t *base, const capture_vertex_frame &f, int nlev, Prob
     pr.pva = L.take<float>(base, 3 * nv);
     pr.counts = L.take<int>(base, 3);
     for (int l = 0; l < nlev; ++l) blurred[l] = L.take<float>(base, 3 * hw);
-    *tmp = L.take<float>(base, 3 * hw);
+    *tmp = L.take<float>(base, 3 * hw * size_t(nlev));       // horizontal passes of every level
     for (int q = 0; q < 2; ++q) {
         vd.V[q] = L.take<double>(base, 3 * nv);
         vd.x[q] = L.take<double>(base, 3 * nv);
@@ -611,13 +691,18 @@ int launch_vertex_decisions(VRun &P) {
         hipLaunchKernelGGL(k_dt_rows, dim3(pr.H), dim3(256), dt_rows_lds(pr.W), s, R.dprobs);
     });
     timed(R, K_V_BLUR, [&] {
+        BlurSet bs{};
+        BlurOut bo{};
+        bs.n = P.nlev;
         for (int l = 0; l < P.nlev; ++l) {
             const BlurW bw = blur_weights(P.levels[l]);
-            hipLaunchKernelGGL(k_vblur, gpx, dim3(256), 0, s, R.dprobs, static_cast<const float *>(nullptr), P.tmp,
-                               pr.W, pr.H, 1, bw);
-            hipLaunchKernelGGL(k_vblur, gpx, dim3(256), 0, s, R.dprobs, static_cast<const float *>(P.tmp),
-                               P.blurred[l], pr.W, pr.H, 0, bw);
+            bs.r[l] = bw.r;
+            for (int q = 0; q < kVMaxBlur; ++q) bs.w[l][q] = bw.w[q];
+            bo.p[l] = P.blurred[l];
         }
+        hipLaunchKernelGGL(k_vblur_h, dim3(blocks(pr.W, 256), pr.H), dim3(256), 0, s, R.dprobs, P.tmp, pr.W, pr.H, bs);
+        hipLaunchKernelGGL(k_vblur_v, dim3(blocks(pr.W, kBlurTileW), blocks(pr.H, kBlurTileH), P.nlev), dim3(256), 0,
+                           s, static_cast<const float *>(P.tmp), bo, pr.W, pr.H, bs);
     });
     timed(R, K_RASTER, [&] {
         hipLaunchKernelGGL(k_raster, dim3(blocks(pr.T.nf, 256)), dim3(256), 0, s, R.dprobs);
