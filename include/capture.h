@@ -503,12 +503,25 @@ typedef struct {
     int32_t pcg_iters;         /* >= 0 Jacobi-PCG iterations per Gauss-Newton step */
     uint32_t flags;
     int32_t blur_kernel[CAPTURE_MAX_GN];
+    /* Vertex snapping after the solve (Sec. 3.4), off when snap_max_px = 0:
+     * contour vertices with b_i = +1 whose distance-transform value at the
+     * final projection is at most snap_max_px pixels walk along the negative
+     * distance-transform gradient, u <- u - I_DT(u) grad / |grad|, at most
+     * snap_steps times (stopping below 0.05 px or where the gradient
+     * vanishes), and are lifted back at their depth; vertices within
+     * snap_rings one-ring steps of a snapped vertex follow a Laplacian warp:
+     * snap_iters Jacobi sweeps of d_i <- mean of the neighbours' d, snapped
+     * vertices held at their displacement and vertices farther away at 0.
+     * The report's energies are those before snapping. */
+    float snap_max_px;
+    int32_t snap_steps, snap_rings, snap_iters;
 } capture_vertex_params;
 
 typedef struct {
     double energy[CAPTURE_MAX_GN + 1];    /* E at the start of each step (with that step's image), then the final E */
     double e_photo, e_sil, e_sil_abs, e_smooth, e_edge, e_vel, e_acc;   /* final per-term energies */
     int32_t n_visible, n_boundary, gn_done;
+    int32_t n_snapped;                    /* contour vertices moved by vertex snapping */
     int32_t status;                       /* CAPTURE_OK or CAPTURE_ENONFINITE (a non-finite energy) */
 } capture_vertex_report;
 

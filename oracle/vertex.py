@@ -263,3 +263,55 @@ def solve(problem, gn_iters, mode="chol", pcg_iters=10, start=None, blur_schedul
         V = V + delta.reshape(problem.nv, 3).T
     energies.append(problem.energy(V, blur_k=ks[-1]))
     return dict(V=V, energies=energies, n_visible=int(problem.vis_idx.size), n_boundary=int(problem.bnd_idx.size))
+
+
+def snap_vertices(problem, V, max_px=3.0, steps=4, rings=2, iters=8, tol_px=0.05):
+    """Vertex snapping (Sec. 3.4) after the non-rigid stage, float64.
+
+    Contour vertices of the frame's set B with b_i = +1 walk on the distance
+    transform along its negative gradient: u <- u - I_DT(u) grad/|grad|, at
+    most `steps` times, stopping once I_DT(u) <= tol_px or the gradient
+    vanishes (|grad| < 1e-6); a vertex whose distance at the start exceeds
+    max_px is not snapped.  The snapped pixel is lifted back at the vertex's
+    depth: X = (u - cx) Z / fx, Y = (v - cy) Z / fy.  The other vertices within
+    `rings` one-ring steps of a snapped vertex follow a Laplacian warp: their
+    displacement starts at 0 and takes `iters` Jacobi sweeps
+    d_i <- mean_{j in N_i} d_j, with snapped vertices held at their snap
+    displacement and vertices farther away held at 0.  Returns (V', snapped
+    mask)."""
+    V = np.asarray(V, np.float64)
+    cam, nv = problem.cam, problem.nv
+    disp = np.zeros((3, nv))
+    snapped = np.zeros(nv, bool)
+    for i, b in zip(problem.bnd_idx, problem.bsign):
+        if b < 0:
+            continue
+        X, Y, Z = V[:, i]
+        if Z <= 0:
+            continue
+        u = cam.fx * X / Z + cam.cx
+        v = cam.fy * Y / Z + cam.cy
+        d0 = sample(problem.dt, np.array([u]), np.array([v]))[0][0]
+        if d0 > max_px:
+            continue
+        for _ in range(steps):
+            d, gu, gv = (a[0] for a in sample(problem.dt, np.array([u]), np.array([v])))
+            g = np.hypot(gu, gv)
+            if d <= tol_px or g < 1e-6:
+                break
+            u, v = u - d * gu / g, v - d * gv / g
+        disp[:, i] = [(u - cam.cx) * Z / cam.fx - X, (v - cam.cy) * Z / cam.fy - Y, 0.0]
+        snapped[i] = True
+    # ring distance from the snapped vertices
+    dist = np.where(snapped, 0, rings + 1)
+    for r in range(1, rings + 1):
+        for i in range(nv):
+            if dist[i] > r and any(dist[j] == r - 1 for j in problem.nbr[i]):
+                dist[i] = r
+    band = (dist >= 1) & (dist <= rings)
+    for _ in range(iters):
+        new = disp.copy()
+        for i in np.nonzero(band)[0]:
+            new[:, i] = disp[:, problem.nbr[i]].mean(axis=1)
+        disp = new
+    return V + disp, snapped

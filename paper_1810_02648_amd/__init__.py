@@ -501,13 +501,14 @@ class VertexInputs:
 
 
 def vertex_params(w_photo, w_sil, w_smooth, w_edge, w_vel=0.0, w_acc=0.0, gn_iters=3, pcg_iters=4,
-                  tau_color=math.inf, exclude_case2=False, outline_only=False, blur_kernels=None):
+                  tau_color=math.inf, exclude_case2=False, outline_only=False, blur_kernels=None, snap_max_px=0.0,
+                  snap_steps=4, snap_rings=2, snap_iters=8):
     flags = (capi.FLAG_EXCLUDE_CASE2 if exclude_case2 else 0) | (capi.FLAG_OUTLINE_ONLY if outline_only else 0)
     bk = (C.c_int32 * capi.MAX_GN)()
     for g, k in enumerate(blur_kernels or ()):
         bk[g] = int(k)
     return capi.VertexParams(w_photo, w_sil, w_smooth, w_edge, w_vel, w_acc, tau_color, gn_iters, pcg_iters, flags,
-                             bk)
+                             bk, snap_max_px, snap_steps, snap_rings, snap_iters)
 
 
 def _vertex_ws(ctx, fr, prm):

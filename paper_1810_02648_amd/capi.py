@@ -93,14 +93,16 @@ class VertexFrame(C.Structure):
 class VertexParams(C.Structure):
     _fields_ = [("w_photo", C.c_float), ("w_sil", C.c_float), ("w_smooth", C.c_float), ("w_edge", C.c_float),
                 ("w_vel", C.c_float), ("w_acc", C.c_float), ("tau_color", C.c_float), ("gn_iters", C.c_int32),
-                ("pcg_iters", C.c_int32), ("flags", C.c_uint32), ("blur_kernel", C.c_int32 * MAX_GN)]
+                ("pcg_iters", C.c_int32), ("flags", C.c_uint32), ("blur_kernel", C.c_int32 * MAX_GN),
+                ("snap_max_px", C.c_float), ("snap_steps", C.c_int32), ("snap_rings", C.c_int32),
+                ("snap_iters", C.c_int32)]
 
 
 class VertexReport(C.Structure):
     _fields_ = [("energy", C.c_double * (MAX_GN + 1)), ("e_photo", C.c_double), ("e_sil", C.c_double),
                 ("e_sil_abs", C.c_double), ("e_smooth", C.c_double), ("e_edge", C.c_double), ("e_vel", C.c_double),
                 ("e_acc", C.c_double), ("n_visible", C.c_int32), ("n_boundary", C.c_int32), ("gn_done", C.c_int32),
-                ("status", C.c_int32)]
+                ("n_snapped", C.c_int32), ("status", C.c_int32)]
 
 
 _P = C.c_void_p
@@ -166,7 +168,7 @@ SIGNATURES = {
 KERNELS = ("blur", "contour", "dt_cols", "dt_rows", "deform_start", "raster", "contour_edges", "decide",
            "linearize", "node_init", "cg", "cg_node", "ws_features", "ws_mlp", "pose_lbs", "pose_rows",
            "pose_jtj", "pose_step", "prep_image", "prep_geom", "prep_raster", "prep_cols", "v_blur", "v_lin",
-           "v_apply", "v_update")
+           "v_apply", "v_update", "v_snap")
 WS_PARAMS = 38662
 
 _lib = None

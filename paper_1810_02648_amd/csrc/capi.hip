@@ -297,7 +297,7 @@ const char *kKernelNames[K_COUNT] = {"blur", "contour", "dt_cols", "dt_rows", "d
                                      "ws_features", "ws_mlp", "pose_lbs", "pose_rows", "pose_jtj",
                                      "pose_step", "prep_image", "prep_geom", "prep_raster",
                                      "prep_cols",
-                                     "v_blur", "v_lin", "v_apply", "v_update"};
+                                     "v_blur", "v_lin", "v_apply", "v_update", "v_snap"};
 
 int setup(Run &R, capture_ctx *ctx, int n, const capture_frame *frames, const capture_nonrigid_params *params,
           void *ws, size_t ws_bytes, void *stream) {

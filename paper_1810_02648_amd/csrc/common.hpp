@@ -242,7 +242,7 @@ enum KernelId {
     K_BLUR, K_CONTOUR, K_DT_COLS, K_DT_ROWS, K_DEFORM, K_RASTER, K_CEDGES, K_DECIDE,
     K_LIN, K_NODE_INIT, K_APPLY, K_NODE_PCG, K_WS_FEAT, K_WS_MLP,
     K_POSE_LBS, K_POSE_ROWS, K_POSE_JTJ, K_POSE_STEP, K_PREP_IMAGE, K_PREP_GEOM, K_PREP_RASTER, K_PREP_COLS,
-    K_V_BLUR, K_V_LIN, K_V_APPLY, K_V_UPDATE,
+    K_V_BLUR, K_V_LIN, K_V_APPLY, K_V_UPDATE, K_V_SNAP,
     K_COUNT
 };
 

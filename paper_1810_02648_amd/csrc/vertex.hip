@@ -74,6 +74,8 @@ struct VertexDev {
     gptr<double> epart;              // [MAX_GN + 1][kVTerms][nb] per-workgroup energies
     gptr<double> scal;               // [MAX_GN] PCG stopped in step g, then [MAX_GN + 1][kVTerms] energies
     gptr<double> rhs_out, diag_out;  // capture_vertex_linearize outputs (or null)
+    gptr<int> ring;                  // [nv] one-ring distance from a snapped vertex (vertex snapping)
+    gptr<int> nsnap;                 // [1] snapped vertices
 };
 
 struct BlurW {
@@ -487,6 +489,104 @@ __global__ __launch_bounds__(256) void k_vreport(const VertexDev *__restrict__ P
     }
 }
 
+// ---------------------------------------------------------------- vertex snapping
+// Contour vertices with b_i = +1 walk on the distance transform from their
+// final projection along the negative gradient, u <- u - I_DT(u) g/|g| (at most
+// `steps` times, stopping once I_DT <= tol or |g| < 1e-6), if their starting
+// distance is at most max_px; the pixel is lifted back at the vertex's depth.
+// Out: displacement (0 for the others) and ring 0 / rings + 1.
+__global__ __launch_bounds__(kVThreads) void k_vsnap(const VertexDev *__restrict__ P, int G, int steps, float max_px,
+                                                     float tol, int rings) {
+    const VertexDev &pr = *P;
+    const int nv = pr.nv, i = blockIdx.x * kVThreads + threadIdx.x;
+    if (i >= nv) return;
+    double V[3], xo[3], d[3] = {0.0, 0.0, 0.0};
+    load3(pr.V[(G + 1) & 1], nv, i, V);
+    load3(pr.x[(G + 1) & 1], nv, i, xo);
+    for (int a = 0; a < 3; ++a) V[a] += xo[a];
+    const uint8_t code = pr.vflags[i];
+    bool snap = false;
+    if ((code & 2) && !(code & 4) && V[2] > 0.0) {
+        double u = double(pr.fx) * V[0] / V[2] + pr.cx, v = double(pr.fy) * V[1] / V[2] + pr.cy;
+        float gu, gv;
+        int cu, cv;
+        float fu, fv;
+        cell_of(u, cu, fu);
+        cell_of(v, cv, fv);
+        const float d0 = sample_cubic_cell(pr.dt.g(), pr.W, pr.H, cu, fu, cv, fv, gu, gv);
+        if (d0 <= max_px) {
+            snap = true;
+            for (int k = 0; k < steps; ++k) {
+                cell_of(u, cu, fu);
+                cell_of(v, cv, fv);
+                const float dist = sample_cubic_cell(pr.dt.g(), pr.W, pr.H, cu, fu, cv, fv, gu, gv);
+                const double g = sqrt(double(gu) * gu + double(gv) * gv);
+                if (dist <= tol || g < 1e-6) break;
+                u = u - double(dist) * gu / g;
+                v = v - double(dist) * gv / g;
+            }
+            d[0] = (u - pr.cx) * V[2] / pr.fx - V[0];
+            d[1] = (v - pr.cy) * V[2] / pr.fy - V[1];
+        }
+    }
+    for (int a = 0; a < 3; ++a) pr.p[0][size_t(a) * nv + i] = d[a];
+    pr.ring[i] = snap ? 0 : rings + 1;
+    if (snap) atomicAdd(pr.nsnap.ptr, 1);
+}
+
+// Ring distance r: a vertex farther than r with a neighbour at r - 1.
+__global__ __launch_bounds__(kVThreads) void k_vring(const VertexDev *__restrict__ P, int r) {
+    const VertexDev &pr = *P;
+    const VTemplateDev &T = pr.T;
+    const int nv = pr.nv, i = blockIdx.x * kVThreads + threadIdx.x;
+    if (i >= nv || pr.ring[i] <= r) return;
+    for (int k = 0; k < T.K; ++k) {
+        const int j = T.nbr[size_t(k) * nv + i];
+        if (j < 0) break;
+        if (pr.ring[j] == r - 1) {
+            pr.ring[i] = r;
+            return;
+        }
+    }
+}
+
+// One Jacobi sweep of the Laplacian warp: vertices of the band (ring 1..rings)
+// take the mean of their neighbours' displacements; the others keep theirs.
+__global__ __launch_bounds__(kVThreads) void k_vwarp(const VertexDev *__restrict__ P, int src, int rings) {
+    const VertexDev &pr = *P;
+    const VTemplateDev &T = pr.T;
+    const int nv = pr.nv, i = blockIdx.x * kVThreads + threadIdx.x;
+    if (i >= nv) return;
+    const gptr<double> a = pr.p[src], b = pr.p[src ^ 1];
+    const int rg = pr.ring[i];
+    double m[3];
+    if (rg >= 1 && rg <= rings) {
+        double s[3] = {0.0, 0.0, 0.0};
+        int n = 0;
+        for (int k = 0; k < T.K; ++k) {
+            const int j = T.nbr[size_t(k) * nv + i];
+            if (j < 0) break;
+            for (int c = 0; c < 3; ++c) s[c] += a[size_t(c) * nv + j];
+            ++n;
+        }
+        for (int c = 0; c < 3; ++c) m[c] = s[c] / n;
+    } else {
+        for (int c = 0; c < 3; ++c) m[c] = a[size_t(c) * nv + i];
+    }
+    for (int c = 0; c < 3; ++c) b[size_t(c) * nv + i] = m[c];
+}
+
+// The caller's positions: the final point plus the displacement in buffer src.
+__global__ __launch_bounds__(kVThreads) void k_vsnap_apply(const VertexDev *__restrict__ P, int G, int src) {
+    const VertexDev &pr = *P;
+    const int nv = pr.nv, i = blockIdx.x * kVThreads + threadIdx.x;
+    if (i >= nv) return;
+    double V[3], xo[3];
+    load3(pr.V[(G + 1) & 1], nv, i, V);
+    load3(pr.x[(G + 1) & 1], nv, i, xo);
+    for (int a = 0; a < 3; ++a) pr.Vout[size_t(a) * nv + i] = float((V[a] + xo[a]) + pr.p[src][size_t(a) * nv + i]);
+}
+
 namespace {
 
 // Blur weights of kernel size k (odd, 1..15): sigma = 0.3 ((k - 1) / 2 - 1) + 0.8,
@@ -560,6 +660,8 @@ size_t carve_vertex(uint8_t *base, const capture_vertex_frame &f, int nlev, Prob
     vd.pap = L.take<double>(base, nb);
     vd.epart = L.take<double>(base, size_t(CAPTURE_MAX_GN + 1) * kVTerms * nb);
     vd.scal = L.take<double>(base, CAPTURE_MAX_GN + size_t(CAPTURE_MAX_GN + 1) * kVTerms);
+    vd.ring = L.take<int>(base, nv);
+    vd.nsnap = L.take<int>(base, 1);
     return L.off;
 }
 
@@ -604,6 +706,9 @@ int check_vertex_params(const capture_vertex_params *p, const capture_vertex_fra
         return fail(CAPTURE_EINVAL, "unknown flag bits");
     if ((p->w_vel > 0.0f || p->w_acc > 0.0f) && !f->prev) return fail(CAPTURE_EINVAL, "temporal terms need prev");
     if (p->w_acc > 0.0f && !f->prev2) return fail(CAPTURE_EINVAL, "the acceleration term needs prev2");
+    if (std::isnan(p->snap_max_px) || p->snap_max_px < 0.0f || p->snap_steps < 0 || p->snap_steps > 64 ||
+        p->snap_rings < 0 || p->snap_rings > 16 || p->snap_iters < 0 || p->snap_iters > 1024)
+        return fail(CAPTURE_EINVAL, "snapping: max_px >= 0, steps 0..64, rings 0..16, iters 0..1024");
     return CAPTURE_OK;
 }
 
@@ -740,6 +845,20 @@ int launch_vertex_solve(VRun &P, const capture_vertex_params *prm) {
     }
     launch_vlin(P, G, P.step_level[G - 1], 1);
     hipLaunchKernelGGL(k_vreport, dim3(1), dim3(256), 0, R.s, P.dv, G);
+    hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, R.s, reinterpret_cast<uint32_t *>(P.vd.nsnap.ptr), size_t(1),
+                       0u);
+    if (prm->snap_max_px > 0.0f) {
+        const float tol = 0.05f;
+        timed(R, K_V_SNAP, [&] {
+            hipLaunchKernelGGL(k_vsnap, dim3(nb), dim3(kVThreads), 0, R.s, P.dv, G, prm->snap_steps, prm->snap_max_px,
+                               tol, prm->snap_rings);
+            for (int r = 1; r <= prm->snap_rings; ++r)
+                hipLaunchKernelGGL(k_vring, dim3(nb), dim3(kVThreads), 0, R.s, P.dv, r);
+            for (int it = 0; it < prm->snap_iters; ++it)
+                hipLaunchKernelGGL(k_vwarp, dim3(nb), dim3(kVThreads), 0, R.s, P.dv, it & 1, prm->snap_rings);
+            hipLaunchKernelGGL(k_vsnap_apply, dim3(nb), dim3(kVThreads), 0, R.s, P.dv, G, prm->snap_iters & 1);
+        });
+    }
     CAP_HIP(hipGetLastError());
     return CAPTURE_OK;
 }
@@ -894,6 +1013,9 @@ int capture_vertex_solve(capture_ctx *ctx, const capture_vertex_frame *f, const 
                       f->camera.width, f->camera.height, prm->gn_iters, prm->pcg_iters);
         key += buf;
         for (int g = 0; g < prm->gn_iters; ++g) key += std::to_string(kernel_of(prm, g)) + ",";
+        std::snprintf(buf, sizeof buf, "|%a %d %d %d", double(prm->snap_max_px), prm->snap_steps, prm->snap_rings,
+                      prm->snap_iters);
+        key += buf;
         rc = launch_graph(P.R, key, [&](Run &C) {
             VRun Q = P;
             Q.R = C;
@@ -905,11 +1027,12 @@ int capture_vertex_solve(capture_ctx *ctx, const capture_vertex_frame *f, const 
     if (rc) return rc;
     const int G = prm->gn_iters;
     double en[(CAPTURE_MAX_GN + 1) * kVTerms];
-    int counts[2] = {0, 0};
+    int counts[2] = {0, 0}, nsnap = 0;
     hipStream_t s = P.R.s;
     CAP_HIP(hipMemcpyAsync(en, P.vd.scal.ptr + CAPTURE_MAX_GN, sizeof(double) * kVTerms * (G + 1),
                            hipMemcpyDeviceToHost, s));
     CAP_HIP(hipMemcpyAsync(counts, P.R.probs[0].counts, sizeof(int) * 2, hipMemcpyDeviceToHost, s));
+    CAP_HIP(hipMemcpyAsync(&nsnap, P.vd.nsnap.ptr, sizeof(int), hipMemcpyDeviceToHost, s));
     CAP_HIP(hipStreamSynchronize(s));
     settle(P.R);
     *rep = capture_vertex_report{};
@@ -930,6 +1053,7 @@ int capture_vertex_solve(capture_ctx *ctx, const capture_vertex_frame *f, const 
     rep->n_visible = counts[0];
     rep->n_boundary = counts[1];
     rep->gn_done = G;
+    rep->n_snapped = nsnap;
     rep->status = finite ? CAPTURE_OK : CAPTURE_ENONFINITE;
     if (!finite) return fail(CAPTURE_ENONFINITE, "non-finite energy in the per-vertex solve");
     return CAPTURE_OK;

@@ -213,3 +213,26 @@ def test_graph_replay_equals_eager(ctx, seq_small):
             assert torch.equal(fr.V, V)
     finally:
         cap.set_graphs(ctx, False)
+
+
+def test_vertex_snapping_matches_the_oracle(ctx, seq_small):
+    """Snapping after the solve (Sec. 3.4): contour walk on the distance
+    transform and the band's Laplacian warp, against the oracle applied to the
+    oracle's own solution."""
+    import paper_1810_02648_amd as cap
+    f = ss.vertex_frame(seq_small, 4)
+    w = weights_of(f)
+    P = oracle_problem(f, w)
+    ref = ov.solve(P, 3, "pcg", 4)
+    snapped, mask = ov.snap_vertices(P, ref["V"], max_px=3.0, steps=4, rings=2, iters=8)
+    fr = gpu_frame(ctx, f)
+    prm = gpu_params(w, 3, 4)
+    prm.snap_max_px, prm.snap_steps, prm.snap_rings, prm.snap_iters = 3.0, 4, 2, 8
+    rep = cap.vertex_solve(ctx, fr, prm)
+    got = fr.V.cpu().numpy().astype(np.float64)
+    print("snapped %d (oracle %d), max difference %.3e m, largest snap %.3e m"
+          % (rep["n_snapped"], mask.sum(), np.abs(got - snapped).max(), np.abs(snapped - ref["V"]).max()))
+    assert abs(rep["n_snapped"] - int(mask.sum())) <= 1 and mask.sum() > 20
+    assert np.abs(got - snapped).max() <= 1e-4
+    assert np.abs(snapped - ref["V"]).max() > 1e-3          # snapping moved something
+    assert_energies(rep, ref)                                # the report's energies are those before snapping

@@ -212,3 +212,73 @@ def test_gauss_newton_lowers_the_energy_on_a_body_frame():
     assert e[-1] < 0.5 * e[0]
     exact = ov.solve(P, 3, "chol")
     assert exact["energies"][-1]["total"] <= e[-1] * 1.0001
+
+
+# ---------------------------------------------------------------- vertex snapping (Sec. 3.4)
+def test_snapping_lands_contour_vertices_on_the_silhouette_and_warps_the_band(mini):
+    """Moved off the silhouette by less than max_px, contour vertices walk back
+    onto it (I_DT at the snapped projection below tol); the band's warp is the
+    given number of Jacobi sweeps of the mean-value rule; vertices outside the
+    band do not move."""
+    P = problem(mini, dict(w_sil=1.0), start=mini["gt"])
+    V0 = mini["gt"].astype(np.float64)
+    rng = np.random.default_rng(8)
+    V = V0 + rng.normal(0, 0.002, V0.shape)
+    out, snapped = ov.snap_vertices(P, V, max_px=3.0, steps=6, rings=2, iters=8)
+    assert snapped.sum() > 10
+    cam = mini["cam"]
+    from oracle.image import sample
+    X, Y, Z = out[:, snapped]
+    d, _, _ = sample(P.dt, cam.fx * X / Z + cam.cx, cam.fy * Y / Z + cam.cy)
+    assert np.median(d) < 0.1
+    assert np.allclose(out[2], V[2])                  # depth is kept
+    # band and outside
+    nb = ov.one_ring(mini["tri"], V.shape[1])
+    ring1 = np.zeros(V.shape[1], bool)
+    for i in np.nonzero(snapped)[0]:
+        ring1[nb[i]] = True
+    ring1 &= ~snapped
+    ring2 = np.zeros_like(ring1)
+    for i in np.nonzero(ring1)[0]:
+        ring2[nb[i]] = True
+    ring2 &= ~snapped & ~ring1
+    outside = ~(snapped | ring1 | ring2)
+    assert np.array_equal(out[:, outside], V[:, outside])
+    assert np.abs(out[:, ring1] - V[:, ring1]).max() > 0
+    # one sweep: a ring-1 vertex gets the mean of its neighbours' starting displacements
+    out1, _ = ov.snap_vertices(P, V, max_px=3.0, steps=6, rings=2, iters=1)
+    d_snap = out - V
+    i = np.nonzero(ring1)[0][0]
+    expect = np.mean([d_snap[:, j] if snapped[j] else np.zeros(3) for j in nb[i]], axis=0)
+    assert np.allclose(out1[:, i] - V[:, i], expect, rtol=0, atol=1e-15)
+
+
+def test_laplacian_warp_converges_to_the_harmonic_interpolant(mini):
+    """Many sweeps of the warp reach the harmonic displacement field of the band
+    (Dirichlet data: snap displacements, 0 beyond the band), solved directly."""
+    import scipy.sparse as sps
+    import scipy.sparse.linalg as spl
+    P = problem(mini, dict(w_sil=1.0), start=mini["gt"])
+    V = mini["gt"].astype(np.float64) + np.random.default_rng(9).normal(0, 0.002, mini["gt"].shape)
+    out, snapped = ov.snap_vertices(P, V, iters=4000)
+    d = out - V
+    nb = ov.one_ring(mini["tri"], V.shape[1])
+    nv = V.shape[1]
+    dist = np.where(snapped, 0, 3)
+    for r in (1, 2):
+        for i in range(nv):
+            if dist[i] > r and any(dist[j] == r - 1 for j in nb[i]):
+                dist[i] = r
+    band = np.nonzero((dist >= 1) & (dist <= 2))[0]
+    idx = {v: k for k, v in enumerate(band)}
+    A = sps.lil_matrix((band.size, band.size))
+    rhs = np.zeros((band.size, 3))
+    for k, i in enumerate(band):
+        A[k, k] = 1.0
+        for j in nb[i]:
+            if j in idx:
+                A[k, idx[j]] -= 1.0 / len(nb[i])
+            elif snapped[j]:
+                rhs[k] += d[:, j] / len(nb[i])
+    x = spl.spsolve(A.tocsc(), rhs)
+    assert np.abs(x.T - d[:, band]).max() < 1e-9
