@@ -391,6 +391,8 @@ typedef struct {
  * pixel); contours of parts seen in front of other parts are dropped.  Also
  * CAPTURE_FLAG_EXCLUDE_CASE2 as for the non-rigid stage. */
 #define CAPTURE_FLAG_OUTLINE_ONLY 2u
+/* Body-part mask of the per-vertex stage's silhouette term (capture_vertex_params). */
+#define CAPTURE_FLAG_PART_MASK 8u
 /* E_temporal = sum_j l_temporal[j] ||p_j - p_j^{t-1}|| ^2 (Sec. 3.3, temporal
  * stabilisation: l_temporal[j] = lambda_temporal * lambda_j) needs
  * frame->prev_joints when any weight is > 0.  E_anatomic = l_anatomic *
@@ -466,6 +468,8 @@ typedef struct {
                                     parts may overlap; every edge in one or two faces */
     const float *rest;           /* [3][n_vertices] device: rest pose Vhat (edge rest lengths) */
     const int32_t *classes;      /* [n_vertices] device: material class 1..7 of Table 1 */
+    const int32_t *parts;        /* [n_vertices] device: body-part label (0 = torso, < 2^20), or NULL
+                                    (needed by CAPTURE_FLAG_PART_MASK) */
 } capture_vertex_template_desc;
 
 /* Copies the topology, builds the one-ring table (ELL layout, neighbours in
@@ -515,6 +519,15 @@ typedef struct {
      * The report's energies are those before snapping. */
     float snap_max_px;
     int32_t snap_steps, snap_rings, snap_iters;
+    /* Body-part mask (Sec. 3.4, dense silhouette alignment; flag
+     * CAPTURE_FLAG_PART_MASK): the model at the start positions is rendered with
+     * per-face part labels (a face takes its first vertex's label; a pixel the
+     * label of the face that sets its depth-buffer value, the smallest on
+     * ties), grown part_dilation times over 3x3 neighbourhoods with the torso
+     * (label 0) taking precedence (a background pixel otherwise takes its
+     * smallest neighbouring label), and a contour vertex whose pixel carries
+     * another part's label gets b_i = 0 (no silhouette residual). */
+    int32_t part_dilation;
 } capture_vertex_params;
 
 typedef struct {

@@ -31,7 +31,10 @@ acceleration term needs V^{t-2}; without it the term is absent.
 Decisions (visible set, contour set B, signs b_i) are taken once per frame
 at the float32 start positions by the recipe of ``decisions`` (the paper takes
 visibility from the skinned mesh after the pose step and updates B after
-Stage I).  A vertex whose edge vector has zero length contributes no edge-term
+Stage I).  With per-vertex body-part labels, a contour vertex whose pixel
+lies in another part's region of the dilated part mask loses its silhouette
+residual (b_i = 0; ``part_label_image``; the mask is rendered from the start
+positions, the posed model carried into the frame).  A vertex whose edge vector has zero length contributes no edge-term
 derivative (its unit direction is taken as 0).
 
 Gauss-Newton (Sec. 4, Eq. gaussnewton) solves (J^T |B| J) delta = -J^T B F and
@@ -42,7 +45,7 @@ sets V <- V + delta; the linear solve is the exact sparse Cholesky of
 import numpy as np
 import scipy.sparse as sp
 
-from .decisions import frame_decisions_from_positions, mesh_edges
+from .decisions import frame_decisions_from_positions, mesh_edges, triangle_coverage
 from .image import blur, distance_transform, sample
 from .nonrigid import projection_jacobian, solve_cholesky, solve_pcg
 
@@ -71,7 +74,8 @@ class VertexProblem:
     """One frame of the per-vertex non-rigid stage with its frozen decisions."""
 
     def __init__(self, rest, posed, tri, rgb, classes, cam, mask, image, weights, start=None,
-                 prev=None, prev2=None, tau_c=np.inf, case2="push", outline=False, blur_k=3):
+                 prev=None, prev2=None, tau_c=np.inf, case2="push", outline=False, blur_k=3, parts=None,
+                 part_dilation=10):
         """rest: Vhat [3][N]; posed: V^S [3][N]; weights: dict with w_photo, w_sil,
         w_smooth, w_edge, w_vel, w_acc; start: V0 (default V^S); prev, prev2:
         V^{t-1}, V^{t-2} (None: the velocity / acceleration term is absent)."""
@@ -104,6 +108,14 @@ class VertexProblem:
         self.bsign = self.dec["bsign"][self.bnd_idx].astype(np.float64)
         if case2 == "exclude":
             keep = self.bsign > 0
+            self.bnd_idx, self.bsign = self.bnd_idx[keep], self.bsign[keep]
+        self.part_image = None
+        if parts is not None:
+            self.part_image = part_label_image(self.dec, tri, parts, cam, part_dilation)
+            px = np.rint(self.dec["u"][self.bnd_idx]).astype(np.int64)
+            py = np.rint(self.dec["v"][self.bnd_idx]).astype(np.int64)
+            lab = self.part_image[py, px]
+            keep = (lab < 0) | (lab == np.asarray(parts)[self.bnd_idx])
             self.bnd_idx, self.bsign = self.bnd_idx[keep], self.bsign[keep]
         # directed edges (i, j), j in N_i, with weight s_ij / |N_i|
         src = np.concatenate([np.full(len(n), i) for i, n in enumerate(self.nbr)]).astype(np.int64)
@@ -243,6 +255,35 @@ class VertexProblem:
         A = (J.T @ sp.diags(np.abs(b)) @ J).tocsr()
         rhs = -(J.T @ (b * F))
         return A, rhs, e
+
+
+def part_label_image(dec, tri, parts, cam, dilation=10):
+    """Body-part mask (Sec. 3.4, dense silhouette alignment): the model at the
+    frame's start positions rendered with per-face part labels (a face takes
+    its first vertex's label; a pixel the label of the face that sets its
+    depth-buffer value, the smallest on ties; -1 for background), then
+    `dilation` growth steps over the 3x3 neighbourhood in which label 0 (the
+    torso) takes precedence: a pixel becomes torso when a neighbour is torso,
+    and a background pixel otherwise takes the smallest label among its
+    labelled neighbours.  Returns int [H][W]."""
+    W, H = cam.width, cam.height
+    zb = dec["zbuf"].reshape(-1)
+    lab = np.full(H * W, np.iinfo(np.int64).max, dtype=np.int64)
+    parts = np.asarray(parts, dtype=np.int64)
+    for f, _, pix, inv in triangle_coverage(dec["u"], dec["v"], dec["Z"], dec["valid"], tri, W, H):
+        top = inv.view(np.uint32) == zb[pix]
+        np.minimum.at(lab, pix[top], parts[tri[0, f]])
+    lab = np.where(lab == np.iinfo(np.int64).max, -1, lab).reshape(H, W)
+    for _ in range(dilation):
+        pad = np.pad(lab, 1, constant_values=-1)
+        nb = [pad[1 + dy:1 + dy + H, 1 + dx:1 + dx + W] for dy in (-1, 0, 1) for dx in (-1, 0, 1)]
+        nb = np.stack(nb)                                           # [9][H][W], the pixel itself included
+        torso = (nb == 0).any(axis=0)
+        big = np.iinfo(np.int64).max
+        smallest = np.where(nb >= 0, nb, big).min(axis=0)
+        new = np.where(torso, 0, np.where(lab >= 0, lab, np.where(smallest < big, smallest, -1)))
+        lab = new
+    return lab
 
 
 def solve(problem, gn_iters, mode="chol", pcg_iters=10, start=None, blur_schedule=None):

@@ -458,13 +458,15 @@ def pose_linearize(ctx, frame, prm):
 class VertexTemplate:
     """Mesh, rest pose and material classes (Table 1) of the per-vertex stage."""
 
-    def __init__(self, ctx, tri, rest, classes):
+    def __init__(self, ctx, tri, rest, classes, parts=None):
         nf, nv = tri.shape[1], rest.shape[1]
         _need(tri, torch.int32, (3, nf), "tri")
         _need(rest, torch.float32, (3, nv), "rest")
         _need(classes, torch.int32, (nv,), "classes")
+        if parts is not None:
+            _need(parts, torch.int32, (nv,), "parts")
         self.ctx, self.nv, self.nf = ctx, nv, nf
-        d = capi.VertexTemplateDesc(nv, nf, _ptr(tri), _ptr(rest), _ptr(classes))
+        d = capi.VertexTemplateDesc(nv, nf, _ptr(tri), _ptr(rest), _ptr(classes), _ptr(parts))
         h = C.c_void_p()
         capi.check(ctx.lib.capture_vertex_template_create(ctx.h, C.byref(d), C.byref(h)))
         self.h = h
@@ -502,13 +504,14 @@ class VertexInputs:
 
 def vertex_params(w_photo, w_sil, w_smooth, w_edge, w_vel=0.0, w_acc=0.0, gn_iters=3, pcg_iters=4,
                   tau_color=math.inf, exclude_case2=False, outline_only=False, blur_kernels=None, snap_max_px=0.0,
-                  snap_steps=4, snap_rings=2, snap_iters=8):
-    flags = (capi.FLAG_EXCLUDE_CASE2 if exclude_case2 else 0) | (capi.FLAG_OUTLINE_ONLY if outline_only else 0)
+                  snap_steps=4, snap_rings=2, snap_iters=8, part_mask=False, part_dilation=10):
+    flags = ((capi.FLAG_EXCLUDE_CASE2 if exclude_case2 else 0) | (capi.FLAG_OUTLINE_ONLY if outline_only else 0) |
+             (capi.FLAG_PART_MASK if part_mask else 0))
     bk = (C.c_int32 * capi.MAX_GN)()
     for g, k in enumerate(blur_kernels or ()):
         bk[g] = int(k)
     return capi.VertexParams(w_photo, w_sil, w_smooth, w_edge, w_vel, w_acc, tau_color, gn_iters, pcg_iters, flags,
-                             bk, snap_max_px, snap_steps, snap_rings, snap_iters)
+                             bk, snap_max_px, snap_steps, snap_rings, snap_iters, part_dilation)
 
 
 def _vertex_ws(ctx, fr, prm):

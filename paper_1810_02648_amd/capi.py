@@ -40,6 +40,7 @@ class NonrigidParams(C.Structure):
 FLAG_EXCLUDE_CASE2 = 1
 FLAG_OUTLINE_ONLY = 2
 FLAG_PCG_STANDARD = 4
+FLAG_PART_MASK = 8
 MAX_JOINTS = 32
 MAX_POSE_UNKNOWNS = 81
 
@@ -81,7 +82,7 @@ VERTEX_MAX_RING = 32
 
 class VertexTemplateDesc(C.Structure):
     _fields_ = [("n_vertices", C.c_int32), ("n_triangles", C.c_int32), ("tri", C.c_void_p), ("rest", C.c_void_p),
-                ("classes", C.c_void_p)]
+                ("classes", C.c_void_p), ("parts", C.c_void_p)]
 
 
 class VertexFrame(C.Structure):
@@ -95,7 +96,7 @@ class VertexParams(C.Structure):
                 ("w_vel", C.c_float), ("w_acc", C.c_float), ("tau_color", C.c_float), ("gn_iters", C.c_int32),
                 ("pcg_iters", C.c_int32), ("flags", C.c_uint32), ("blur_kernel", C.c_int32 * MAX_GN),
                 ("snap_max_px", C.c_float), ("snap_steps", C.c_int32), ("snap_rings", C.c_int32),
-                ("snap_iters", C.c_int32)]
+                ("snap_iters", C.c_int32), ("part_dilation", C.c_int32)]
 
 
 class VertexReport(C.Structure):

@@ -480,6 +480,50 @@ __device__ inline void raster_big_body(const ProbDev &pr, int bx, int nbx) {
     }
 }
 
+// Body-part labels of the rendered model: the pixels where a face sets the
+// depth-buffer value take the smaller of their label and the face's (its
+// first vertex's part).  Small faces one per thread; the queued large faces
+// (from the depth pass) one workgroup each.
+__device__ inline void label_pixel(const ProbDev &pr, const TriRaster &s, long long i, long long j, int lab,
+                                   int *__restrict__ img) {
+    const long long Pu = i * 256, Pv = j * 256;
+    const long long E0 = s.dU0 * (Pv - s.V1) - s.dV0 * (Pu - s.U1);
+    const long long E1 = s.dU1 * (Pv - s.V2) - s.dV1 * (Pu - s.U2);
+    const long long E2 = s.dU2 * (Pv - s.V0) - s.dV2 * (Pu - s.U0);
+    const bool in = (E0 > 0 || (E0 == 0 && s.o0)) && (E1 > 0 || (E1 == 0 && s.o1)) && (E2 > 0 || (E2 == 0 && s.o2));
+    if (!in) return;
+    const float inv = ((float(E0) * s.iz0 + float(E1) * s.iz1) + float(E2) * s.iz2) / s.Af;
+    const size_t q = size_t(j) * pr.W + i;
+    if (__float_as_uint(inv) == pr.zbuf[q]) atomicMin(img + q, lab);
+}
+
+__global__ void k_part_labels(const ProbDev *__restrict__ P, const int *__restrict__ parts, int *__restrict__ img) {
+    const ProbDev &pr = *P;
+    const TemplateDev &T = pr.T;
+    const int nf = T.nf, f = blockIdx.x * blockDim.x + threadIdx.x;
+    if (f >= nf) return;
+    TriRaster s;
+    if (!tri_setup(pr, f, s)) return;
+    if ((s.i1 - s.i0 + 1) * (s.j1 - s.j0 + 1) > kRasterSmall) return;      // queued by the depth pass
+    const int lab = parts[T.tri[f]];
+    for (long long j = s.j0; j <= s.j1; ++j)
+        for (long long i = s.i0; i <= s.i1; ++i) label_pixel(pr, s, i, j, lab, img);
+}
+
+__global__ __launch_bounds__(256) void k_part_labels_big(const ProbDev *__restrict__ P, const int *__restrict__ parts,
+                                                         int *__restrict__ img) {
+    const ProbDev &pr = *P;
+    const int nq = pr.counts[2];
+    for (int q = blockIdx.x; q < nq; q += gridDim.x) {
+        const int f = pr.bigq[q];
+        TriRaster s;
+        if (!tri_setup(pr, f, s)) continue;
+        const int lab = parts[pr.T.tri[f]];
+        const long long w = s.i1 - s.i0 + 1, area = w * (s.j1 - s.j0 + 1);
+        for (long long k = threadIdx.x; k < area; k += blockDim.x) label_pixel(pr, s, s.i0 + k % w, s.j0 + k / w, lab, img);
+    }
+}
+
 __global__ __launch_bounds__(256) void k_raster_big(const ProbDev *__restrict__ P) {
     raster_big_body(P[blockIdx.y], blockIdx.x, gridDim.x);
 }

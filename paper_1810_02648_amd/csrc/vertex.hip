@@ -35,6 +35,8 @@ __global__ void k_raster(const ProbDev *P);
 __global__ void k_raster_big(const ProbDev *P);
 __global__ void k_contour_edges(const ProbDev *P);
 __global__ void k_decide(const ProbDev *P);
+__global__ void k_part_labels(const ProbDev *P, const int *parts, int *img);
+__global__ void k_part_labels_big(const ProbDev *P, const int *parts, int *img);
 
 constexpr int kVThreads = 128;
 constexpr int kRingChunk = 4;       // one-ring neighbours whose gathers are issued together
@@ -52,6 +54,7 @@ struct VTemplateDev {
     gptr<const float> ek;     // s_ij / |N_i|: weight of the directed edge i -> j in the energy
     gptr<const float> ea;     // s_ij / |N_i| + s_ij / |N_j|: weight of the edge pair in the normal equations
     gptr<const float> elen;   // |Vhat_i - Vhat_j|
+    gptr<const int> parts;    // [nv] body-part label (0: torso), or null
 };
 
 // One frame: inputs, decisions and the solver's buffers (all [3][nv] planes).
@@ -75,6 +78,7 @@ struct VertexDev {
     gptr<double> scal;               // [MAX_GN] PCG stopped in step g, then [MAX_GN + 1][kVTerms] energies
     gptr<double> rhs_out, diag_out;  // capture_vertex_linearize outputs (or null)
     gptr<int> ring;                  // [nv] one-ring distance from a snapped vertex (vertex snapping)
+    gptr<int> plab[2];               // [H][W] body-part label images (ping-pong of the dilation)
     gptr<int> nsnap;                 // [1] snapped vertices
 };
 
@@ -489,6 +493,51 @@ __global__ __launch_bounds__(256) void k_vreport(const VertexDev *__restrict__ P
     }
 }
 
+// ---------------------------------------------------------------- body-part mask
+constexpr int kNoPart = 0x7fffffff;
+// One growth step of the part label image over the 3x3 neighbourhood (outside
+// the image: no label): torso (0) where any neighbour is torso, else the
+// pixel's own label, else the smallest neighbouring label.
+__global__ __launch_bounds__(256) void k_part_dilate(const int *__restrict__ src, int *__restrict__ dst, int W, int H) {
+    const int q = blockIdx.x * 256 + threadIdx.x;
+    if (q >= W * H) return;
+    const int y = q / W, x = q - y * W;
+    int v[9];
+#pragma unroll
+    for (int dy = -1; dy <= 1; ++dy)
+#pragma unroll
+        for (int dx = -1; dx <= 1; ++dx) {
+            const int yy = y + dy, xx = x + dx;
+            const bool in = yy >= 0 && yy < H && xx >= 0 && xx < W;
+            v[3 * (dy + 1) + dx + 1] = in ? src[size_t(min(max(yy, 0), H - 1)) * W + min(max(xx, 0), W - 1)] : kNoPart;
+        }
+    int mn = kNoPart;
+    bool torso = false;
+#pragma unroll
+    for (int k = 0; k < 9; ++k) {
+        torso = torso || v[k] == 0;
+        mn = min(mn, v[k]);
+    }
+    dst[q] = torso ? 0 : (v[4] != kNoPart ? v[4] : mn);
+}
+
+// Contour vertices whose pixel lies in another part's region lose their
+// silhouette residual (b_i = 0): flags cleared, contour count reduced.
+__global__ __launch_bounds__(kVThreads) void k_part_mask(const VertexDev *__restrict__ P, const ProbDev *__restrict__ R,
+                                                         const int *__restrict__ img) {
+    const VertexDev &pr = *P;
+    const int nv = pr.nv, i = blockIdx.x * kVThreads + threadIdx.x;
+    if (i >= nv) return;
+    const uint8_t code = R->vflags[i];
+    if (!(code & 2)) return;
+    const int px = int(rintf(R->duv[i])), py = int(rintf(R->duv[nv + i]));
+    const int lab = img[size_t(py) * R->W + px];
+    if (lab != kNoPart && lab != pr.T.parts[i]) {
+        R->vflags[i] = uint8_t(code & ~6);
+        atomicSub(R->counts.ptr + 1, 1);
+    }
+}
+
 // ---------------------------------------------------------------- vertex snapping
 // Contour vertices with b_i = +1 walk on the distance transform from their
 // final projection along the negative gradient, u <- u - I_DT(u) g/|g| (at most
@@ -612,6 +661,8 @@ struct VRun {
     int step_level[CAPTURE_MAX_GN] = {};
     float *blurred[kVLevels] = {nullptr, nullptr, nullptr};
     float *tmp = nullptr;
+    bool part_mask = false;
+    int part_dilation = 0;
 };
 
 int kernel_of(const capture_vertex_params *p, int g) { return p->blur_kernel[g] == 0 ? 3 : p->blur_kernel[g]; }
@@ -661,6 +712,8 @@ size_t carve_vertex(uint8_t *base, const capture_vertex_frame &f, int nlev, Prob
     vd.epart = L.take<double>(base, size_t(CAPTURE_MAX_GN + 1) * kVTerms * nb);
     vd.scal = L.take<double>(base, CAPTURE_MAX_GN + size_t(CAPTURE_MAX_GN + 1) * kVTerms);
     vd.ring = L.take<int>(base, nv);
+    vd.plab[0] = L.take<int>(base, hw);
+    vd.plab[1] = L.take<int>(base, hw);
     vd.nsnap = L.take<int>(base, 1);
     return L.off;
 }
@@ -702,8 +755,11 @@ int check_vertex_params(const capture_vertex_params *p, const capture_vertex_fra
     for (float x : w)
         if (!std::isfinite(x) || x < 0.0f) return fail(CAPTURE_EINVAL, "weights must be finite and non-negative");
     if (std::isnan(p->tau_color) || p->tau_color < 0.0f) return fail(CAPTURE_EINVAL, "tau_color must be >= 0");
-    if (p->flags & ~uint32_t(CAPTURE_FLAG_EXCLUDE_CASE2 | CAPTURE_FLAG_OUTLINE_ONLY))
+    if (p->flags & ~uint32_t(CAPTURE_FLAG_EXCLUDE_CASE2 | CAPTURE_FLAG_OUTLINE_ONLY | CAPTURE_FLAG_PART_MASK))
         return fail(CAPTURE_EINVAL, "unknown flag bits");
+    if ((p->flags & CAPTURE_FLAG_PART_MASK) && !f->tmpl->dev.parts)
+        return fail(CAPTURE_EINVAL, "the body-part mask needs a template with part labels");
+    if (p->part_dilation < 0 || p->part_dilation > 64) return fail(CAPTURE_EINVAL, "part_dilation must be in [0, 64]");
     if ((p->w_vel > 0.0f || p->w_acc > 0.0f) && !f->prev) return fail(CAPTURE_EINVAL, "temporal terms need prev");
     if (p->w_acc > 0.0f && !f->prev2) return fail(CAPTURE_EINVAL, "the acceleration term needs prev2");
     if (std::isnan(p->snap_max_px) || p->snap_max_px < 0.0f || p->snap_steps < 0 || p->snap_steps > 64 ||
@@ -757,6 +813,8 @@ int vertex_setup(VRun &P, capture_ctx *ctx, const capture_vertex_frame *f, const
     vd.dt = pr.dt;
     vd.vflags = pr.vflags;
     vd.Vout = f->V;
+    P.part_mask = (prm->flags & CAPTURE_FLAG_PART_MASK) != 0;
+    P.part_dilation = prm->part_dilation;
     Run &R = P.R;
     R.ctx = ctx;
     R.prof = &ctx->prof;
@@ -817,6 +875,21 @@ int launch_vertex_decisions(VRun &P) {
         hipLaunchKernelGGL(k_contour_edges, dim3(blocks(pr.T.nmedges, 256)), dim3(256), 0, s, R.dprobs);
     });
     timed(R, K_DECIDE, [&] { hipLaunchKernelGGL(k_decide, dim3(blocks(nv, 256)), dim3(256), 0, s, R.dprobs); });
+    if (P.part_mask) {
+        int *a = P.vd.plab[0].ptr, *b = P.vd.plab[1].ptr;
+        hipLaunchKernelGGL(k_fill_u32, dim3(blocks(hw, 256)), dim3(256), 0, s, reinterpret_cast<uint32_t *>(a), hw,
+                           uint32_t(kNoPart));
+        hipLaunchKernelGGL(k_part_labels, dim3(blocks(pr.T.nf, 256)), dim3(256), 0, s, R.dprobs,
+                           static_cast<const int *>(P.vd.T.parts.ptr), a);
+        hipLaunchKernelGGL(k_part_labels_big, dim3(kRasterBigBlocks), dim3(256), 0, s, R.dprobs,
+                           static_cast<const int *>(P.vd.T.parts.ptr), a);
+        for (int k = 0; k < P.part_dilation; ++k) {
+            hipLaunchKernelGGL(k_part_dilate, gpx, dim3(256), 0, s, static_cast<const int *>(a), b, pr.W, pr.H);
+            std::swap(a, b);
+        }
+        hipLaunchKernelGGL(k_part_mask, dim3(P.vd.nb), dim3(kVThreads), 0, s, P.dv, R.dprobs,
+                           static_cast<const int *>(a));
+    }
     CAP_HIP(hipGetLastError());
     return CAPTURE_OK;
 }
@@ -928,12 +1001,16 @@ int capture_vertex_template_create(capture_ctx *ctx, const capture_vertex_templa
     if (nv < 2 || nf < 1) return fail(CAPTURE_EINVAL, "vertex template: need n_vertices >= 2 and n_triangles >= 1");
     if (nv > (1 << 26)) return fail(CAPTURE_EUNSUPPORTED, "vertex template: too many vertices");
     if (!d->tri || !d->rest || !d->classes) return fail(CAPTURE_EINVAL, "vertex template: null array");
-    std::vector<int> tri, cls;
+    std::vector<int> tri, cls, parts;
     std::vector<float> rest;
     int rc;
     if ((rc = copy_down_v(tri, d->tri, size_t(3) * nf)) || (rc = copy_down_v(cls, d->classes, size_t(nv))) ||
         (rc = copy_down_v(rest, d->rest, size_t(3) * nv)))
         return rc;
+    if (d->parts) {
+        if ((rc = copy_down_v(parts, d->parts, size_t(nv)))) return rc;
+        for (int q : parts) if (q < 0 || q >= 1 << 20) return fail(CAPTURE_EINVAL, "vertex template: part labels 0..2^20-1");
+    }
     for (int v : tri) if (v < 0 || v >= nv) return fail(CAPTURE_EINVAL, "vertex template: triangle index out of range");
     for (int c : cls) if (c < 1 || c > 7) return fail(CAPTURE_EINVAL, "vertex template: material class outside 1..7");
     for (float x : rest) if (!std::isfinite(x)) return fail(CAPTURE_ENONFINITE, "vertex template: non-finite rest position");
@@ -946,9 +1023,9 @@ int capture_vertex_template_create(capture_ctx *ctx, const capture_vertex_templa
         capture_template_destroy(topo);
         return rc;
     }
-    const size_t b_n = sizeof(int) * nbr.size(), b_f = sizeof(float) * ek.size();
+    const size_t b_n = sizeof(int) * nbr.size(), b_f = sizeof(float) * ek.size(), b_p = sizeof(int) * parts.size();
     void *mem = nullptr;
-    if (hipMalloc(&mem, b_n + 3 * b_f) != hipSuccess) {
+    if (hipMalloc(&mem, b_n + 3 * b_f + b_p) != hipSuccess) {
         capture_template_destroy(topo);
         return fail(CAPTURE_ENOMEM, "vertex template: device allocation failed");
     }
@@ -956,7 +1033,8 @@ int capture_vertex_template_create(capture_ctx *ctx, const capture_vertex_templa
     if (hipMemcpy(m, nbr.data(), b_n, hipMemcpyHostToDevice) != hipSuccess ||
         hipMemcpy(m + b_n, ek.data(), b_f, hipMemcpyHostToDevice) != hipSuccess ||
         hipMemcpy(m + b_n + b_f, ea.data(), b_f, hipMemcpyHostToDevice) != hipSuccess ||
-        hipMemcpy(m + b_n + 2 * b_f, elen.data(), b_f, hipMemcpyHostToDevice) != hipSuccess) {
+        hipMemcpy(m + b_n + 2 * b_f, elen.data(), b_f, hipMemcpyHostToDevice) != hipSuccess ||
+        (b_p && hipMemcpy(m + b_n + 3 * b_f, parts.data(), b_p, hipMemcpyHostToDevice) != hipSuccess)) {
         (void)hipFree(mem);
         capture_template_destroy(topo);
         return fail(CAPTURE_EHIP, "vertex template: upload failed");
@@ -968,6 +1046,7 @@ int capture_vertex_template_create(capture_ctx *ctx, const capture_vertex_templa
     t->dev.ek = reinterpret_cast<const float *>(m + b_n);
     t->dev.ea = reinterpret_cast<const float *>(m + b_n + b_f);
     t->dev.elen = reinterpret_cast<const float *>(m + b_n + 2 * b_f);
+    t->dev.parts = b_p ? reinterpret_cast<const int *>(m + b_n + 3 * b_f) : nullptr;
     t->topo = topo;
     t->mem = mem;
     t->device = ctx->device;
@@ -1013,8 +1092,8 @@ int capture_vertex_solve(capture_ctx *ctx, const capture_vertex_frame *f, const 
                       f->camera.width, f->camera.height, prm->gn_iters, prm->pcg_iters);
         key += buf;
         for (int g = 0; g < prm->gn_iters; ++g) key += std::to_string(kernel_of(prm, g)) + ",";
-        std::snprintf(buf, sizeof buf, "|%a %d %d %d", double(prm->snap_max_px), prm->snap_steps, prm->snap_rings,
-                      prm->snap_iters);
+        std::snprintf(buf, sizeof buf, "|%a %d %d %d|%u %d", double(prm->snap_max_px), prm->snap_steps,
+                      prm->snap_rings, prm->snap_iters, prm->flags, prm->part_dilation);
         key += buf;
         rc = launch_graph(P.R, key, [&](Run &C) {
             VRun Q = P;

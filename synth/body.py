@@ -55,6 +55,11 @@ _PARTS = [(0, 2, 0.16), (2, 3, 0.10), (4, "e4", 0.11), (6, 7, 0.055), (7, 8, 0.0
 PART_CLASS = np.array([1, 2, 7, 5, 5, 6, 5, 5, 6, 3, 3, 6, 6, 3, 3, 6, 6, 2, 2], np.int32)
 
 
+# body-part label of each part for the silhouette term's part mask: 0 torso
+# (pelvis, chest, neck, clavicles), 1 head, 2 / 3 left / right arm (upper arm,
+# forearm, hand), 4 / 5 left / right leg (thigh, shin, foot, toe)
+PART_GROUP = np.array([0, 0, 1, 2, 2, 2, 3, 3, 3, 4, 4, 4, 4, 5, 5, 5, 5, 0, 0], np.int32)
+
 # Per-joint temporal smoothness weights lambda_i of the pose stage (Sec. 3.3:
 # 2.5 torso and head, 2.0 shoulders, 1.5 knees and elbows, 1.0 hands and
 # feet), mapped onto this skeleton: clavicles count as shoulders, hips as
@@ -129,7 +134,8 @@ def make_body(n_vertices, root=(0.0, 0.0, 4.0)):
                 bind_idx=np.ascontiguousarray(bind_joint.T.astype(np.int32)),
                 bind_w=np.ascontiguousarray(w.T.astype(np.float32)),
                 part=part.astype(np.int32),
-                classes=PART_CLASS[part].astype(np.int32))
+                classes=PART_CLASS[part].astype(np.int32),
+                parts=PART_GROUP[part].astype(np.int32))
 
 
 def _rodrigues(w):

@@ -185,6 +185,7 @@ def make_sequence(name="seq20k", seed=0, n_frames=None, workers=None):
         body = make_body(cfg["n_vertices"], root=(0.0, 0.0, 4.5))
         xyz, tri = body["xyz"], body["tri"]
         classes = body["classes"]
+        parts = body["parts"]
         rgb = smooth_colours(xyz, rng)
         m = _body_motion(body, rng, 64)
         jobs = [(tri, rgb, cam, m, f / 30.0) for f in range(cfg["n_frames"])]
@@ -192,6 +193,7 @@ def make_sequence(name="seq20k", seed=0, n_frames=None, workers=None):
     else:
         xyz, tri = template_mesh(cfg["mesh"], cfg["n_vertices"])
         classes = np.full(xyz.shape[1], 2, np.int32)      # one material: upper clothes
+        parts = np.zeros(xyz.shape[1], np.int32)          # one body part
         rgb = smooth_colours(xyz, rng)
         m = _motion(xyz, rng, 24)
         jobs = [(xyz, tri, rgb, cam, m, f / 30.0) for f in range(cfg["n_frames"])]
@@ -207,7 +209,7 @@ def make_sequence(name="seq20k", seed=0, n_frames=None, workers=None):
     extra = {}
     if cfg["mesh"] == "body":
         extra = dict(body=body, poses=[f[4] for f in frames], joints=[f[5] for f in frames])
-    return dict(name=name, seed=seed, xyz=xyz, tri=tri, rgb=rgb, cam=cam, classes=classes,
+    return dict(name=name, seed=seed, xyz=xyz, tri=tri, rgb=rgb, cam=cam, classes=classes, parts=parts,
                 posed=[f[0] for f in frames], gt=[f[1] for f in frames], masks=[f[2] for f in frames],
                 images=[f[3] for f in frames], **extra,
                 n_nodes=cfg["n_nodes"], n_train=cfg["n_train"], gn=cfg["gn"], pcg=cfg["pcg"],
@@ -240,6 +242,7 @@ def vertex_frame(seq, t, weights=None):
     prev, prev2 = seq["gt"][t - 1], seq["gt"][t - 2]
     start = (seq["posed"][t] + (prev - seq["posed"][t - 1])).astype(np.float32)
     return dict(rest=seq["xyz"], posed=seq["posed"][t], tri=seq["tri"], rgb=seq["rgb"], classes=seq["classes"],
+                parts=seq["parts"],
                 cam=seq["cam"], mask=seq["masks"][t], image=seq["images"][t], prev=prev, prev2=prev2,
                 start=np.ascontiguousarray(start), gt=seq["gt"][t],
                 weights=vertex_weights_for(side) if weights is None else weights,

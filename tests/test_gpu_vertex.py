@@ -236,3 +236,30 @@ def test_vertex_snapping_matches_the_oracle(ctx, seq_small):
     assert np.abs(got - snapped).max() <= 1e-4
     assert np.abs(snapped - ref["V"]).max() > 1e-3          # snapping moved something
     assert_energies(rep, ref)                                # the report's energies are those before snapping
+
+
+def test_body_part_mask_matches_the_oracle(ctx, seq_small):
+    """Body-part mask of the silhouette term (Sec. 3.4): the same contour
+    vertices lose their residual on both sides (bit-exact), and the solve
+    matches the oracle's."""
+    import paper_1810_02648_amd as cap
+    f = ss.vertex_frame(seq_small, 3)
+    w = weights_of(f)
+    P = ov.VertexProblem(f["rest"], f["posed"], f["tri"], f["rgb"], f["classes"], f["cam"], f["mask"], f["image"], w,
+                         start=f["start"], prev=f["prev"], prev2=f["prev2"], case2="exclude", outline=False,
+                         parts=f["parts"], part_dilation=10)
+    P0 = oracle_problem(f, w, outline=False)
+    assert 0 < P.bnd_idx.size < P0.bnd_idx.size
+    tmpl = cap.VertexTemplate(ctx, dev(f["tri"]), dev(f["rest"]), dev(f["classes"].astype(np.int32)),
+                              dev(f["parts"].astype(np.int32)))
+    fr = gpu_frame(ctx, f, tmpl=tmpl)
+    prm = gpu_params(w, 3, 4, outline=False)
+    prm.flags |= 8
+    prm.part_dilation = 10
+    out = cap.vertex_linearize(ctx, fr, prm)
+    assert np.array_equal(out["vflags"].cpu().numpy() & 3, vertex_flags(P))
+    ref = ov.solve(P, 3, "pcg", 4)
+    rep = cap.vertex_solve(ctx, fr, prm)
+    assert rep["n_boundary"] == P.bnd_idx.size
+    assert_solution(fr.V.cpu().numpy(), ref, f["start"])
+    assert_energies(rep, ref)

@@ -282,3 +282,40 @@ def test_laplacian_warp_converges_to_the_harmonic_interpolant(mini):
                 rhs[k] += d[:, j] / len(nb[i])
     x = spl.spsolve(A.tocsc(), rhs)
     assert np.abs(x.T - d[:, band]).max() < 1e-9
+
+
+# ---------------------------------------------------------------- body-part mask (Sec. 3.4)
+def test_part_mask_renders_labels_and_dilates_with_torso_precedence():
+    """Two labelled squares (torso 0 at left, part 3 at right) with a 4-pixel
+    gap: the rendered labels cover exactly each square's pixels; after 3
+    growth steps the torso holds the 3 gap pixels next to it (it takes
+    precedence where both grow) and part 3 the last one; the background
+    grows by 3 pixels."""
+    cam = synth.Camera(24, 12, 100.0, 100.0, 0.0, 0.0)
+    Z = 2.0
+    def square(x0, x1, y0, y1):      # pixel-corner rectangle as two triangles, counter-clockwise on screen
+        pts = [(x0, y0), (x1, y0), (x1, y1), (x0, y1)]
+        return [(p[0] * Z / 100.0, p[1] * Z / 100.0, Z) for p in pts]
+    P = square(1.5, 6.5, 2.5, 8.5) + square(10.5, 16.5, 2.5, 8.5)
+    xyz = np.array(P, np.float32).T
+    tri = np.array([[0, 2, 1], [0, 3, 2], [4, 6, 5], [4, 7, 6]], np.int32).T
+    from oracle.decisions import frame_decisions_from_positions
+    mask = np.zeros((12, 24), np.uint8)
+    dec = frame_decisions_from_positions(xyz[0], xyz[1], xyz[2], tri, cam, mask, np.zeros((12, 24), np.float32))
+    parts = np.array([0, 0, 0, 0, 3, 3, 3, 3])
+    lab0 = ov.part_label_image(dec, tri, parts, cam, dilation=0)
+    covered = dec["zbuf"] > 0
+    assert np.array_equal(lab0 >= 0, covered)
+    assert set(np.unique(lab0[:, :8])) <= {-1, 0} and set(np.unique(lab0[:, 9:])) <= {-1, 3}
+    lab = ov.part_label_image(dec, tri, parts, cam, dilation=3)
+    cols0 = np.nonzero((lab0 == 0).any(axis=0))[0]
+    cols3 = np.nonzero((lab0 == 3).any(axis=0))[0]
+    row = 5
+    assert (lab[row, cols0.max() + 1:cols0.max() + 4] == 0).all()          # torso grew by 3 into the gap
+    gap = cols3.min() - cols0.max() - 1
+    assert gap == 4
+    assert lab[row, cols3.min()] == 3 and (lab[row, cols3.max() + 1:cols3.max() + 4] == 3).all()
+    assert lab[row, cols0.max() + 4] == 3                                   # part 3 grew left into the remaining gap pixel
+    # the background grows by exactly 3 pixels around the union
+    from scipy.ndimage import binary_dilation
+    assert np.array_equal(lab >= 0, binary_dilation(covered, np.ones((3, 3), bool), iterations=3))
