@@ -187,7 +187,7 @@ def bench_sequence(args, cap, torch):
     seq = synth.sequence.make_sequence(args.workload, 0)
     ctx = cap.Context(0)
     cap.set_graphs(ctx, not args.no_graphs)
-    S = sq.DeviceSequence(ctx, seq)
+    S = sq.DeviceSequence(ctx, seq, vertices_per_tile=args.tile)
     log("plain tracking over %d frames" % S.n)
     states, _ = sq.track_plain(S)
     ntr = seq["n_train"]
@@ -219,7 +219,7 @@ def bench_sequence(args, cap, torch):
     n_edges = int((S.graph["edge_dst"] >= 0).sum().item())
     calls = 2 * len(test)    # one evaluate pass = one plain and one learned solve per frame
     roof = roofline_for(prof, calls, 1, n_act, S.nn, n_edges, W, H, seq["tri"].shape[1], seq["xyz"].shape[1],
-                        "%s/tile0" % args.workload)
+                        "%s/tile%d" % (args.workload, args.tile))
     return {
         "metric": METRIC,
         "value": n / tl,
@@ -711,7 +711,7 @@ def main():
     ap.add_argument("--no-pose", action="store_true", help="frame mode: leave out the pose stage")
     ap.add_argument("--no-graphs", action="store_true",
                     help="launch every kernel eagerly instead of replaying captured HIP graphs")
-    ap.add_argument("--tile", type=int, default=0, help="frame/batch mode: vertices per tile (0 = library default)")
+    ap.add_argument("--tile", type=int, default=0, help="sequence/frame/batch modes: vertices per tile (0 = library default; frame and batch modes autotune)")
     ap.add_argument("--frames", type=int, default=40, help="vertex / track modes: frames per step")
     ap.add_argument("--distinct", action="store_true",
                     help="frame mode: the --batch captures share no data (capture i: seed i, template of N - i "

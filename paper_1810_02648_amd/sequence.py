@@ -36,7 +36,7 @@ def identity_state(nn, device="cuda"):
 class DeviceSequence:
     """A synthetic sequence's inputs resident on the device, with its template."""
 
-    def __init__(self, ctx, seq, graph=None):
+    def __init__(self, ctx, seq, graph=None, vertices_per_tile=0):
         self.ctx = ctx
         self.seq = seq
         self.xyz = torch.from_numpy(seq["xyz"]).cuda()
@@ -46,7 +46,7 @@ class DeviceSequence:
         if graph is None:
             graph = graph_build(ctx, self.xyz, nn)
         self.graph = graph
-        self.template = Template(ctx, torch.from_numpy(seq["tri"]).cuda(), graph)
+        self.template = Template(ctx, torch.from_numpy(seq["tri"]).cuda(), graph, vertices_per_tile)
         self.masks = [torch.from_numpy(m).cuda() for m in seq["masks"]]
         self.images = [torch.from_numpy(i).cuda() for i in seq["images"]]
         self.nn = nn
