@@ -40,6 +40,8 @@ __global__ void k_part_labels_big(const ProbDev *P, const int *parts, int *img);
 
 constexpr int kVThreads = 128;
 constexpr int kRingChunk = 4;       // one-ring neighbours whose gathers are issued together
+constexpr int kRowLanes = 8;        // lanes per vertex row in the product
+constexpr int kApplyThreads = 1024;
 constexpr int kVTerms = 7;          // photo, sil (with b), sil (with |b|), smooth, edge, velocity, acceleration
 constexpr int kVLevels = 3;         // distinct Gaussian kernels per solve
 constexpr int kVMaxBlur = 15;
@@ -61,6 +63,7 @@ struct VTemplateDev {
 struct VertexDev {
     VTemplateDev T;
     int nv, nb;                      // vertices, workgroups of the per-vertex kernels
+    int nba;                         // workgroups of the product (kRowLanes lanes per vertex)
     int W, H;
     float fx, fy, cx, cy;
     float sw_photo, sw_sil, tau;
@@ -368,12 +371,18 @@ __global__ __launch_bounds__(kVThreads) void k_vlin(const VertexDev *__restrict_
 // sum_j a_ij [w_smooth (p_i - p_j) + w_edge u_ij u_ij^T (p_i - p_j)], and the
 // p.Ap sums.  Stops the step's PCG (flag in scal[g]) when r.u == 0.
 // product_only: multiply the vector in u (p = u), no stop test (capture_vertex_linearize).
-__global__ __launch_bounds__(kVThreads) void k_vapply(const VertexDev *__restrict__ P, int g, int j, int product_only) {
-    __shared__ double red[kVThreads / 64][1];
+// kRowLanes lanes per vertex row: lane l takes neighbours l, l + kRowLanes, ...
+// of the one-ring (their gathers in flight across the lanes), the lanes' sums
+// are added by a fixed butterfly, and the row's first lane adds the vertex's
+// own block and stores p_j and (J^T |B| J p_j)_i.
+__global__ __launch_bounds__(kApplyThreads) void k_vapply(const VertexDev *__restrict__ P, int g, int j,
+                                                          int product_only) {
+    __shared__ double red[kApplyThreads / 64][1];
     const VertexDev &pr = *P;
     if (pr.scal[g] != 0.0) return;
     const VTemplateDev &T = pr.T;
-    const int nv = pr.nv, nb = pr.nb, i = blockIdx.x * kVThreads + threadIdx.x;
+    const int nv = pr.nv, nb = pr.nb;
+    const int gt = blockIdx.x * kApplyThreads + threadIdx.x, i0 = gt / kRowLanes, l = gt % kRowLanes;
     double rz[1] = {1.0}, rzp[1] = {1.0};
     if (!product_only) wave_sum_n<1>(pr.ru.g() + size_t(j & 1) * nb, nb, nb, rz);
     if (rz[0] == 0.0) {
@@ -389,56 +398,46 @@ __global__ __launch_bounds__(kVThreads) void k_vapply(const VertexDev *__restric
             q[a] = j > 0 ? pr.u[o] + beta * pold[o] : double(pr.u[o]);
         }
     };
+    const int i = min(i0, nv - 1);          // lanes past the last row repeat it and store nothing
+    double pi[3], V[3], c[3] = {0.0, 0.0, 0.0};
+    pval(i, pi);
+    load3(Vg, nv, i, V);
+    if (pr.w_smooth > 0.0 || pr.w_edge > 0.0)
+        for (int k = l; k < T.K; k += kRowLanes) {
+            const int jn = T.nbr[size_t(k) * nv + i];
+            if (jn < 0) break;
+            const double ea = T.ea[size_t(k) * nv + i];
+            double pj[3], Vj[3], dp[3], d[3];
+            pval(jn, pj);
+            load3(Vg, nv, jn, Vj);
+            for (int a = 0; a < 3; ++a) {
+                dp[a] = pi[a] - pj[a];
+                d[a] = V[a] - Vj[a];
+            }
+            if (pr.w_smooth > 0.0)
+                for (int a = 0; a < 3; ++a) c[a] += pr.w_smooth * ea * dp[a];
+            if (pr.w_edge > 0.0) {
+                const double len = sqrt((d[0] * d[0] + d[1] * d[1]) + d[2] * d[2]);
+                if (len > 0.0) {
+                    const double ua[3] = {d[0] / len, d[1] / len, d[2] / len};
+                    const double s = pr.w_edge * ea * ((ua[0] * dp[0] + ua[1] * dp[1]) + ua[2] * dp[2]);
+                    for (int a = 0; a < 3; ++a) c[a] += s * ua[a];
+                }
+            }
+        }
+#pragma unroll
+    for (int o = kRowLanes / 2; o > 0; o >>= 1)
+#pragma unroll
+        for (int a = 0; a < 3; ++a) c[a] += __shfl_xor(c[a], o);
     double pap[1] = {0.0};
-    if (i < nv) {
-        double pi[3], V[3], out[3];
-        pval(i, pi);
-        load3(Vg, nv, i, V);
+    if (l == 0 && i0 < nv) {
         const double H0 = pr.Hm[i], H1 = pr.Hm[nv + i], H2 = pr.Hm[2 * size_t(nv) + i];
         const double H3 = pr.Hm[3 * size_t(nv) + i], H4 = pr.Hm[4 * size_t(nv) + i], H5 = pr.Hm[5 * size_t(nv) + i];
         const double wt = pr.w_vel + pr.w_acc;
-        out[0] = ((H0 * pi[0] + H1 * pi[1]) + H2 * pi[2]) + wt * pi[0];
-        out[1] = ((H1 * pi[0] + H3 * pi[1]) + H4 * pi[2]) + wt * pi[1];
-        out[2] = ((H2 * pi[0] + H4 * pi[1]) + H5 * pi[2]) + wt * pi[2];
-        if (pr.w_smooth > 0.0 || pr.w_edge > 0.0)
-            // the one-ring in chunks: a chunk's indices, then all its gathers in
-            // flight together (positions past the row's end re-read the vertex itself)
-            for (int k0 = 0; k0 < T.K; k0 += kRingChunk) {
-                int jn[kRingChunk];
-                double ea[kRingChunk], pj[kRingChunk][3], Vj[kRingChunk][3];
-#pragma unroll
-                for (int u = 0; u < kRingChunk; ++u) {
-                    const int k = min(k0 + u, T.K - 1);
-                    jn[u] = k0 + u < T.K ? T.nbr[size_t(k) * nv + i] : -1;
-                    ea[u] = T.ea[size_t(k) * nv + i];
-                }
-#pragma unroll
-                for (int u = 0; u < kRingChunk; ++u) {
-                    const int q = jn[u] < 0 ? i : jn[u];
-                    pval(q, pj[u]);
-                    load3(Vg, nv, q, Vj[u]);
-                }
-#pragma unroll
-                for (int u = 0; u < kRingChunk; ++u) {
-                    if (jn[u] < 0) continue;
-                    double dp[3], d[3];
-                    for (int a = 0; a < 3; ++a) {
-                        dp[a] = pi[a] - pj[u][a];
-                        d[a] = V[a] - Vj[u][a];
-                    }
-                    if (pr.w_smooth > 0.0)
-                        for (int a = 0; a < 3; ++a) out[a] += pr.w_smooth * ea[u] * dp[a];
-                    if (pr.w_edge > 0.0) {
-                        const double len = sqrt((d[0] * d[0] + d[1] * d[1]) + d[2] * d[2]);
-                        if (len > 0.0) {
-                            const double ua[3] = {d[0] / len, d[1] / len, d[2] / len};
-                            const double s = pr.w_edge * ea[u] * ((ua[0] * dp[0] + ua[1] * dp[1]) + ua[2] * dp[2]);
-                            for (int a = 0; a < 3; ++a) out[a] += s * ua[a];
-                        }
-                    }
-                }
-                if (jn[kRingChunk - 1] < 0) break;
-            }
+        double out[3];
+        out[0] = (((H0 * pi[0] + H1 * pi[1]) + H2 * pi[2]) + wt * pi[0]) + c[0];
+        out[1] = (((H1 * pi[0] + H3 * pi[1]) + H4 * pi[2]) + wt * pi[1]) + c[1];
+        out[2] = (((H2 * pi[0] + H4 * pi[1]) + H5 * pi[2]) + wt * pi[2]) + c[2];
         for (int a = 0; a < 3; ++a) {
             const size_t o = size_t(a) * nv + i;
             pnew[o] = pi[a];
@@ -446,7 +445,7 @@ __global__ __launch_bounds__(kVThreads) void k_vapply(const VertexDev *__restric
         }
         pap[0] = (pi[0] * out[0] + pi[1] * out[1]) + pi[2] * out[2];
     }
-    block_sum_n<kVThreads, 1>(pap, red);
+    block_sum_n<kApplyThreads, 1>(pap, red);
     if (threadIdx.x == 0) pr.pap[blockIdx.x] = pap[0];
 }
 
@@ -458,7 +457,7 @@ __global__ __launch_bounds__(kVThreads) void k_vupdate(const VertexDev *__restri
     if (pr.scal[g] != 0.0) return;
     const int nv = pr.nv, nb = pr.nb, i = blockIdx.x * kVThreads + threadIdx.x;
     double pAp[1], rz[1];
-    wave_sum_n<1>(pr.pap.g(), nb, nb, pAp);
+    wave_sum_n<1>(pr.pap.g(), pr.nba, pr.nba, pAp);
     wave_sum_n<1>(pr.ru.g() + size_t(j & 1) * nb, nb, nb, rz);
     if (!(pAp[0] > 0.0)) {
         if (blockIdx.x == 0 && threadIdx.x == 0) pr.scal[g] = 1.0;
@@ -708,7 +707,7 @@ size_t carve_vertex(uint8_t *base, const capture_vertex_frame &f, int nlev, Prob
     vd.dinv = L.take<double>(base, 3 * nv);
     vd.Hm = L.take<float>(base, 6 * nv);
     vd.ru = L.take<double>(base, 2 * size_t(nb));
-    vd.pap = L.take<double>(base, nb);
+    vd.pap = L.take<double>(base, blocks(nv * kRowLanes, kApplyThreads));
     vd.epart = L.take<double>(base, size_t(CAPTURE_MAX_GN + 1) * kVTerms * nb);
     vd.scal = L.take<double>(base, CAPTURE_MAX_GN + size_t(CAPTURE_MAX_GN + 1) * kVTerms);
     vd.ring = L.take<int>(base, nv);
@@ -797,6 +796,7 @@ int vertex_setup(VRun &P, capture_ctx *ctx, const capture_vertex_frame *f, const
     vd.T = vt.dev;
     vd.nv = vt.dev.nv;
     vd.nb = int(blocks(vd.nv, kVThreads));
+    vd.nba = int(blocks(size_t(vd.nv) * kRowLanes, kApplyThreads));
     vd.W = pr.W; vd.H = pr.H;
     vd.fx = pr.fx; vd.fy = pr.fy; vd.cx = pr.cx; vd.cy = pr.cy;
     vd.sw_photo = std::sqrt(prm->w_photo);
@@ -912,7 +912,9 @@ int launch_vertex_solve(VRun &P, const capture_vertex_params *prm) {
     for (int g = 0; g < G; ++g) {
         launch_vlin(P, g, P.step_level[g], 0);
         for (int j = 0; j < prm->pcg_iters; ++j) {
-            timed(R, K_V_APPLY, [&] { hipLaunchKernelGGL(k_vapply, dim3(nb), dim3(kVThreads), 0, R.s, P.dv, g, j, 0); });
+            timed(R, K_V_APPLY, [&] {
+                hipLaunchKernelGGL(k_vapply, dim3(P.vd.nba), dim3(kApplyThreads), 0, R.s, P.dv, g, j, 0);
+            });
             timed(R, K_V_UPDATE, [&] { hipLaunchKernelGGL(k_vupdate, dim3(nb), dim3(kVThreads), 0, R.s, P.dv, g, j); });
         }
     }
@@ -1157,7 +1159,7 @@ int capture_vertex_linearize(capture_ctx *ctx, const capture_vertex_frame *f, co
     if (p && Ap) {
         // the product of the given direction: p is copied into u (iteration 0 multiplies p = u)
         CAP_HIP(hipMemcpyAsync(P.vd.u.ptr, p, sizeof(double) * 3 * nv, hipMemcpyDeviceToDevice, s));
-        hipLaunchKernelGGL(k_vapply, dim3(P.vd.nb), dim3(kVThreads), 0, s, P.dv, 0, 0, 1);
+        hipLaunchKernelGGL(k_vapply, dim3(P.vd.nba), dim3(kApplyThreads), 0, s, P.dv, 0, 0, 1);
         CAP_HIP(hipMemcpyAsync(Ap, P.vd.Ap.ptr, sizeof(double) * 3 * nv, hipMemcpyDeviceToDevice, s));
     }
     hipLaunchKernelGGL(k_vreport, dim3(1), dim3(256), 0, s, P.dv, 0);
