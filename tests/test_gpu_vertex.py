@@ -263,3 +263,30 @@ def test_body_part_mask_matches_the_oracle(ctx, seq_small):
     assert rep["n_boundary"] == P.bnd_idx.size
     assert_solution(fr.V.cpu().numpy(), ref, f["start"])
     assert_energies(rep, ref)
+
+
+def test_empty_silhouette_and_no_regularisers(ctx, seq_small):
+    """Edge cases: an empty mask (no image contour: the distance transform is 0,
+    so the model's contour vertices carry zero silhouette residuals) and a
+    solve with only the data terms and the temporal priors (no one-ring
+    terms), both against the oracle."""
+    import paper_1810_02648_amd as cap
+    f = dict(ss.vertex_frame(seq_small, 3))
+    f["mask"] = np.zeros_like(f["mask"])
+    w = weights_of(f)
+    P = oracle_problem(f, w)
+    assert float(P.dt.max()) == 0.0
+    ref = ov.solve(P, 2, "pcg", 4)
+    fr = gpu_frame(ctx, f)
+    rep = cap.vertex_solve(ctx, fr, gpu_params(w, 2, 4))
+    assert rep["n_boundary"] == P.bnd_idx.size and rep["e_sil"] == 0.0
+    assert_solution(fr.V.cpu().numpy(), ref, f["start"])
+    assert_energies(rep, ref)
+    f = ss.vertex_frame(seq_small, 3)
+    w2 = dict(weights_of(f), w_smooth=0.0, w_edge=0.0)
+    ref = ov.solve(oracle_problem(f, w2), 2, "pcg", 4)
+    fr = gpu_frame(ctx, f)
+    rep = cap.vertex_solve(ctx, fr, gpu_params(w2, 2, 4))
+    assert rep["e_smooth"] == 0.0 and rep["e_edge"] == 0.0
+    assert_solution(fr.V.cpu().numpy(), ref, f["start"])
+    assert_energies(rep, ref)
