@@ -21,7 +21,8 @@ def test_header_declares_the_boundary():
     names = declared_functions()
     for required in ("capture_nonrigid_solve", "capture_batch_solve", "capture_graph_build",
                      "capture_workspace_size", "capture_template_create", "capture_last_error",
-                     "capture_pose_solve", "capture_body_create"):
+                     "capture_pose_solve", "capture_body_create", "capture_vertex_solve",
+                     "capture_vertex_template_create", "capture_body_warp", "capture_body_skin"):
         assert required in names
 
 
@@ -45,10 +46,11 @@ def test_struct_layouts_match_header():
 #include <stdio.h>
 #include "capture.h"
 int main(void) {
-  printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\n", sizeof(capture_camera), sizeof(capture_template_desc),
-         sizeof(capture_frame), sizeof(capture_nonrigid_params), sizeof(capture_report),
+  printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\n", sizeof(capture_camera),
+         sizeof(capture_template_desc), sizeof(capture_frame), sizeof(capture_nonrigid_params), sizeof(capture_report),
          sizeof(capture_body_desc), sizeof(capture_pose_frame), sizeof(capture_pose_params),
-         sizeof(capture_pose_report), sizeof(capture_template_info));
+         sizeof(capture_pose_report), sizeof(capture_template_info), sizeof(capture_vertex_template_desc),
+         sizeof(capture_vertex_frame), sizeof(capture_vertex_params), sizeof(capture_vertex_report));
   return 0;
 }
 """
@@ -61,4 +63,6 @@ int main(void) {
     assert sizes == [ctypes.sizeof(capi.Camera), ctypes.sizeof(capi.TemplateDesc), ctypes.sizeof(capi.Frame),
                      ctypes.sizeof(capi.NonrigidParams), ctypes.sizeof(capi.Report), ctypes.sizeof(capi.BodyDesc),
                      ctypes.sizeof(capi.PoseFrame), ctypes.sizeof(capi.PoseParams), ctypes.sizeof(capi.PoseReport),
-                     ctypes.sizeof(capi.TemplateInfo)]
+                     ctypes.sizeof(capi.TemplateInfo), ctypes.sizeof(capi.VertexTemplateDesc),
+                     ctypes.sizeof(capi.VertexFrame), ctypes.sizeof(capi.VertexParams),
+                     ctypes.sizeof(capi.VertexReport)]
