@@ -39,10 +39,6 @@ constexpr int kMaxImageSide = 4096;
 constexpr int kRasterSmall = 256;         // pixel-box size above which a face is rasterised by a workgroup
 constexpr int kRasterBigBlocks = 512;
 constexpr int kScanColsMin = 16384;      // image columns (all frames) from which the segment scan runs a thread per column
-#ifndef CAP_DT_CHUNKS
-#define CAP_DT_CHUNKS 32
-#endif
-constexpr int kDtChunks = CAP_DT_CHUNKS; // column chunks of the exact distance transform's row pass
 // Dynamic LDS of the row pass for rows of W pixels: G (int).
 inline size_t dt_rows_lds(int W) { return sizeof(int) * size_t(W) + 16; }
 #ifndef CAP_APPLY_SPLIT_TILES

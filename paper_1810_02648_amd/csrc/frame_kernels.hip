@@ -219,21 +219,24 @@ __device__ inline void dt_cols_body(const ProbDev &pr, int bx) {
 __global__ void k_dt_cols(const ProbDev *__restrict__ P) { dt_cols_body(P[blockIdx.y], blockIdx.x); }
 
 // Phase 2: per row, D(x) = min over x' of (x - x')^2 + G(x'), G = g^2, exact.
-// The row's G is staged in LDS and cut into kDtChunks column chunks with their
-// smallest G.  Each pixel takes the minimum over its own chunk's columns
-// (every lane of a wave reads the same G values, so the LDS reads broadcast
-// and none depends on another), then visits the neighbouring chunks outwards
-// while their column distance can still beat the best value, and scans a
-// chunk only if its column distance^2 plus its smallest G can.  Integer
-// arithmetic throughout, so the result is exact.  One workgroup per row.
-#ifndef CAP_DT_UNROLL
-#define CAP_DT_UNROLL 8
-#endif
-constexpr int kDtUnroll = CAP_DT_UNROLL;
+// With H(x') = G(x') + x'^2 the value is x^2 + H(x') - 2 x x'.  The matrix of
+// H(x') - 2 x x' over (x, x') is Monge (its cross term is), so the smallest
+// minimising column of a pixel never decreases along the row.  kDtAnchors
+// anchor pixels (every s-th one and the last) take the minimum over the whole
+// row, eight lanes each, and keep their smallest minimising column; every
+// other pixel scans only the columns between the minimising columns of the
+// anchors on either side of it.  That is at most kDtAnchors W + s (W + kDtAnchors)
+// candidates per row, whatever the sites, and each costs a three-operand add
+// and a share of a three-operand min (the -2 x x' term steps by -2x along the
+// columns).  Integer arithmetic throughout (no term leaves 32 bits for rows up
+// to 4096 pixels), so the result is exact.  One 256-thread workgroup per row.
+constexpr int kDtAnchors = 32;
+constexpr int kDtLanes = 8;                  // lanes per anchor: kDtAnchors x kDtLanes = 256
+constexpr int kDtUnroll = 8;
 
 __device__ inline void dt_rows_body(const ProbDev &pr, int y) {
-    extern __shared__ int G[];
-    __shared__ int cmin[kDtChunks];
+    extern __shared__ int Hs[];
+    __shared__ int aq[kDtAnchors];
     const int W = pr.W, H = pr.H;
     if (y >= H) return;
     const int far2 = 1 << 30;
@@ -247,58 +250,60 @@ __device__ inline void dt_rows_body(const ProbDev &pr, int y) {
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
             const int x = x0 + u * int(blockDim.x);
-            if (x < W) G[x] = g[u] >= kFar ? far2 : g[u] * g[u];
+            if (x < W) Hs[x] = (g[u] >= kFar ? far2 : g[u] * g[u]) + x * x;
         }
     }
     __syncthreads();
-    const int cs = (W + kDtChunks - 1) / kDtChunks;
-    if (threadIdx.x < kDtChunks) {
-        const int a = threadIdx.x * cs, b = min(W, a + cs);
-        int m = far2;
-        for (int q = a; q < b; ++q) m = min(m, G[q]);
-        cmin[threadIdx.x] = m;
+    float *out = pr.dt + size_t(y) * W;
+    const int s = max(1, (W - 1 + kDtAnchors - 2) / (kDtAnchors - 1));     // anchor k at min(k s, W - 1)
+    {
+        const int k = threadIdx.x / kDtLanes, part = threadIdx.x % kDtLanes;
+        const int x = min(k * s, W - 1);
+        const int m2x = -2 * x;
+        int bv = INT_MAX, bq = INT_MAX;      // smallest value, then smallest column, of this lane's columns
+        int base = m2x * part;
+#pragma unroll 4
+        for (int q = part; q < W; q += kDtLanes, base += m2x * kDtLanes) {
+            const int v = Hs[q] + base;
+            if (v < bv) { bv = v; bq = q; }
+        }
+#pragma unroll
+        for (int o = 1; o < kDtLanes; o <<= 1) {
+            const int ov = __shfl_xor(bv, o, kDtLanes), oq = __shfl_xor(bq, o, kDtLanes);
+            if (ov < bv || (ov == bv && oq < bq)) { bv = ov; bq = oq; }
+        }
+        if (part == 0) {
+            aq[k] = bq;
+            if (k == 0 || x != min((k - 1) * s, W - 1)) {       // once per distinct anchor pixel
+                const int best = bv + x * x;
+                out[x] = best >= far2 ? 0.0f : sqrtf(float(best));
+            }
+        }
     }
     __syncthreads();
-    // min over the chunk's columns of (x - q)^2 + G(q); columns without a site
-    // have G = 2^30, so they never beat a site (and the sum stays below 2^31)
-    auto scan = [&](int c, int x, int best) {
-        const int a = c * cs, b = min(W, a + cs);
+    // every other pixel: its interval's column range, kDtUnroll reads in flight
+    for (int x = threadIdx.x; x < W; x += blockDim.x) {
+        const int k = x / s;
+        if ((x % s == 0 && k < kDtAnchors) || x == W - 1) continue;
+        const int a = aq[k], b = aq[k + 1] + 1;
+        const int m2x = -2 * x;
+        int step[kDtUnroll];                 // -2 x u
+#pragma unroll
+        for (int u = 0; u < kDtUnroll; ++u) step[u] = m2x * u;
+        int base = m2x * a;                  // -2 x q at the block's first column
+        int m = far2;                        // m + x^2 >= 2^30: no site in the range
         int q = a;
-        for (; q + kDtUnroll <= b; q += kDtUnroll) {      // kDtUnroll independent reads in flight
+        for (; q + kDtUnroll <= b; q += kDtUnroll) {
             int v[kDtUnroll];
 #pragma unroll
-            for (int u = 0; u < kDtUnroll; ++u) v[u] = (x - q - u) * (x - q - u) + G[q + u];
+            for (int u = 0; u < kDtUnroll; ++u) v[u] = Hs[q + u] + base + step[u];
 #pragma unroll
-            for (int u = 0; u < kDtUnroll; ++u) best = min(best, v[u]);
+            for (int u = 0; u < kDtUnroll; u += 2) m = min(m, min(v[u], v[u + 1]));
+            base += m2x * kDtUnroll;
         }
-        for (; q < b; ++q) best = min(best, (x - q) * (x - q) + G[q]);
-        return best;
-    };
-    for (int x = threadIdx.x; x < W; x += blockDim.x) {
-        const int c0 = x / cs;
-        int best = scan(c0, x, far2);
-        int l = c0 - 1, r = c0 + 1;
-        while (l >= 0 || r < kDtChunks) {
-            if (l >= 0) {
-                const int d = x - (min(W, l * cs + cs) - 1);
-                if (d * d < best) {
-                    if (d * d + cmin[l] < best) best = scan(l, x, best);
-                    --l;
-                } else {
-                    l = -1;
-                }
-            }
-            if (r < kDtChunks) {
-                const int d = r * cs - x;
-                if (r * cs < W && d * d < best) {
-                    if (d * d + cmin[r] < best) best = scan(r, x, best);
-                    ++r;
-                } else {
-                    r = kDtChunks;
-                }
-            }
-        }
-        pr.dt[size_t(y) * W + x] = best >= far2 ? 0.0f : sqrtf(float(best));
+        for (; q < b; ++q, base += m2x) m = min(m, Hs[q] + base);
+        const int best = m + x * x;
+        out[x] = best >= far2 ? 0.0f : sqrtf(float(best));
     }
 }
 
