@@ -71,46 +71,63 @@ __device__ inline float d2f(float ax, float ay, float az, float bx, float by, fl
     return (dx * dx + dy * dy) + dz * dz;
 }
 
-// Farthest-point sampling in one workgroup; argmax ties -> lowest index.
-__global__ __launch_bounds__(1024) void k_fps(const float *__restrict__ xyz, int nv, int nn, float *mind,
-                                              int *node_vertex) {
-    __shared__ float bv[1024];
-    __shared__ int bi[1024];
-    __shared__ float sel[3];
-    const float *X = xyz, *Y = xyz + nv, *Z = xyz + 2 * size_t(nv);
-    if (threadIdx.x == 0) { node_vertex[0] = 0; sel[0] = X[0]; sel[1] = Y[0]; sel[2] = Z[0]; }
+// Farthest-point sampling, one launch per node over the whole chip.  Launch n
+// (0 <= n < nn) learns node n: vertex 0 for n = 0, else the argmax of the
+// smallest squared distances to the nodes so far, with ties to the lowest
+// index.  Every workgroup takes that argmax from the previous launch's
+// per-workgroup partials (the order of (value desc, index asc) is total, so
+// every workgroup gets the same node, with no atomics and no waiting on other
+// workgroups); workgroup 0 stores it.  Then each workgroup lowers the
+// distances of its vertices (grid-stride) by the new node's and writes the
+// argmax of its vertices as its partial for launch n + 1 (partials alternate
+// between two buffers by launch parity).  The distances and the rule are
+// those of a one-workgroup loop over all vertices, so the nodes are too.
+constexpr int kFpsThreads = 256, kFpsMaxBlocks = 256;
+
+struct ArgMax {
+    float v;
+    int i;
+};
+__device__ inline ArgMax argmax_of(ArgMax a, ArgMax b) { return (b.v > a.v || (b.v == a.v && b.i < a.i)) ? b : a; }
+
+__device__ inline ArgMax block_argmax(ArgMax a, ArgMax *red) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) a = argmax_of(a, ArgMax{__shfl_xor(a.v, o), __shfl_xor(a.i, o)});
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = a;
     __syncthreads();
-    for (int v = threadIdx.x; v < nv; v += blockDim.x) mind[v] = d2f(X[v], Y[v], Z[v], sel[0], sel[1], sel[2]);
-    for (int n = 1; n < nn; ++n) {
-        float best = -1.0f;
-        int bidx = 0x7fffffff;
-        for (int v = threadIdx.x; v < nv; v += blockDim.x) {
-            float m = mind[v];
-            if (m > best) { best = m; bidx = v; }
-        }
-        bv[threadIdx.x] = best;
-        bi[threadIdx.x] = bidx;
-        __syncthreads();
-        for (int s = blockDim.x / 2; s > 0; s >>= 1) {
-            if (int(threadIdx.x) < s) {
-                float ov = bv[threadIdx.x + s];
-                int oi = bi[threadIdx.x + s];
-                if (ov > bv[threadIdx.x] || (ov == bv[threadIdx.x] && oi < bi[threadIdx.x])) {
-                    bv[threadIdx.x] = ov;
-                    bi[threadIdx.x] = oi;
-                }
-            }
-            __syncthreads();
-        }
-        const int s = bi[0];
-        if (threadIdx.x == 0) { node_vertex[n] = s; sel[0] = X[s]; sel[1] = Y[s]; sel[2] = Z[s]; }
-        __syncthreads();
-        const float sx = sel[0], sy = sel[1], sz = sel[2];
-        for (int v = threadIdx.x; v < nv; v += blockDim.x) {
-            float d = d2f(X[v], Y[v], Z[v], sx, sy, sz);
-            if (d < mind[v]) mind[v] = d;
-        }
-        __syncthreads();
+    ArgMax r = red[0];
+#pragma unroll
+    for (int w = 1; w < kFpsThreads / 64; ++w) r = argmax_of(r, red[w]);
+    __syncthreads();            // red free for the next use
+    return r;
+}
+
+__global__ __launch_bounds__(kFpsThreads) void k_fps_step(const float *__restrict__ xyz, int nv, int nn, int n,
+                                                          float *__restrict__ mind, float *__restrict__ pv,
+                                                          int *__restrict__ pi, int *__restrict__ node_vertex) {
+    __shared__ ArgMax red[kFpsThreads / 64];
+    const float *X = xyz, *Y = xyz + nv, *Z = xyz + 2 * size_t(nv);
+    const int nb = gridDim.x;
+    int sel = 0;
+    if (n > 0) {
+        const int t = threadIdx.x, q = ((n - 1) & 1) * kFpsMaxBlocks;
+        const ArgMax a = t < nb ? ArgMax{pv[q + t], pi[q + t]} : ArgMax{-1.0f, 0x7fffffff};
+        sel = min(block_argmax(a, red).i, nv - 1);     // (every workgroup has a vertex: the index is one)
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) node_vertex[n] = sel;
+    if (n == nn - 1) return;
+    const float sx = X[sel], sy = Y[sel], sz = Z[sel];
+    ArgMax best{-1.0f, 0x7fffffff};
+    for (int v = blockIdx.x * kFpsThreads + threadIdx.x; v < nv; v += nb * kFpsThreads) {
+        const float d = d2f(X[v], Y[v], Z[v], sx, sy, sz);
+        const float m = n == 0 ? d : (d < mind[v] ? d : mind[v]);
+        mind[v] = m;
+        if (m > best.v) best = ArgMax{m, v};
+    }
+    best = block_argmax(best, red);
+    if (threadIdx.x == 0) {
+        pv[(n & 1) * kFpsMaxBlocks + blockIdx.x] = best.v;
+        pi[(n & 1) * kFpsMaxBlocks + blockIdx.x] = best.i;
     }
 }
 
@@ -666,10 +683,18 @@ int capture_graph_build(capture_ctx *ctx, const float *xyz, int32_t n_vertices, 
         return fail(CAPTURE_EINVAL, "graph: need 4 <= n_nodes <= n_vertices and n_nodes <= 65536");
     CAP_HIP(hipSetDevice(ctx->device));
     hipStream_t s = static_cast<hipStream_t>(stream);
+    // scratch: the vertices' smallest squared distances, then two buffers of
+    // per-workgroup partials (value, index) of the farthest-point steps
     float *mind = nullptr;
-    if (hipMalloc(&mind, sizeof(float) * size_t(n_vertices)) != hipSuccess)
+    const size_t mbytes = (sizeof(float) * size_t(n_vertices) + 255) / 256 * 256;
+    if (hipMalloc(&mind, mbytes + 2 * kFpsMaxBlocks * (sizeof(float) + sizeof(int))) != hipSuccess)
         return fail(CAPTURE_ENOMEM, "graph: scratch allocation failed");
-    hipLaunchKernelGGL(k_fps, dim3(1), dim3(1024), 0, s, xyz, n_vertices, n_nodes, mind, node_vertex);
+    float *pv = reinterpret_cast<float *>(reinterpret_cast<char *>(mind) + mbytes);
+    int *pi = reinterpret_cast<int *>(pv + 2 * kFpsMaxBlocks);
+    const unsigned nb_fps = std::min(blocks(size_t(n_vertices), kFpsThreads), unsigned(kFpsMaxBlocks));
+    for (int n = 0; n < n_nodes; ++n)
+        hipLaunchKernelGGL(k_fps_step, dim3(nb_fps), dim3(kFpsThreads), 0, s, xyz, n_vertices, n_nodes, n, mind, pv, pi,
+                           node_vertex);
     hipLaunchKernelGGL(k_bind, dim3(blocks(n_vertices, 256)), dim3(256), 0, s, xyz, n_vertices, n_nodes, node_vertex,
                        bind_idx, bind_w);
     hipLaunchKernelGGL(k_node_edges, dim3(blocks(n_nodes, 256)), dim3(256), 0, s, xyz, n_vertices, n_nodes,

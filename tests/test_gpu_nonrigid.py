@@ -47,6 +47,21 @@ def test_graph_build_matches_oracle(ctx, frames):
         assert np.abs(g["bind_w"].cpu().numpy() - ref["bind_w64"]).max() < 2e-6, name
 
 
+def test_graph_build_many_vertices_per_thread(ctx):
+    """Farthest-point sampling on a cloud large enough that the grid is capped
+    (256 workgroups, several vertices per thread, a ragged tail), against the
+    oracle's sampling, binding and node edges."""
+    import paper_1810_02648_amd as cap
+    from gpu_util import dev
+    rng = np.random.default_rng(17)
+    xyz = (rng.standard_normal((3, 70001)) * np.array([[0.3], [0.8], [0.2]])).astype(np.float32)
+    ref = og.build_graph(xyz, 301)
+    g = cap.graph_build(ctx, dev(xyz), 301)
+    assert np.array_equal(g["node_vertex"].cpu().numpy(), ref["node_vertex"])
+    assert np.array_equal(g["bind_idx"].cpu().numpy(), ref["bind_idx"])
+    assert np.array_equal(g["edge_dst"].cpu().numpy(), ref["edge_dst"])
+
+
 @pytest.mark.parametrize("name", ["small0", "small1", "mid"])
 def test_frame_decisions_bit_exact(ctx, frames, name):
     import paper_1810_02648_amd as cap
