@@ -99,6 +99,33 @@ def test_distance_transform_edge_cases(ctx, frames):
         assert np.array_equal(out["dt"].cpu().numpy().view(np.uint32), ref.view(np.uint32))
 
 
+@pytest.mark.parametrize("W", [8, 17, 31, 32, 33, 64, 600])
+def test_distance_transform_row_widths(ctx, frames, W):
+    """Row pass at widths where its anchor pixels coincide (W <= 32: every
+    pixel an anchor, the last ones repeated), where the last anchors repeat
+    the last pixel (33) and where the intervals hold many pixels (600); masks of
+    random blobs with empty rows, bit-exact against the oracle."""
+    import dataclasses
+    import paper_1810_02648_amd as cap
+    from gpu_util import make_frame
+    f = dict(frames["small0"])
+    g = og.build_graph(f["xyz"], 64)
+    H = 48
+    rng = np.random.default_rng(W)
+    m = np.zeros((H, W), np.uint8)
+    for _ in range(max(1, W // 40)):
+        cy, cx, r = rng.integers(6, H - 6), rng.integers(0, W), rng.integers(1, 6)
+        yy, xx = np.mgrid[0:H, 0:W]
+        m[(yy - cy) ** 2 + (xx - cx) ** 2 <= r * r] = 1
+    m[:5] = 0                                   # rows with no site at all
+    f["mask"] = m
+    f["image"] = np.zeros((3, H, W), np.float32)
+    f["cam"] = dataclasses.replace(f["cam"], width=W, height=H, cx=(W - 1) / 2.0, cy=(H - 1) / 2.0)
+    out = cap.frame_decisions(ctx, make_frame(ctx, f, g))
+    ref, _ = oi.distance_transform(m)
+    assert np.array_equal(out["dt"].cpu().numpy().view(np.uint32), ref.view(np.uint32))
+
+
 def normal_equations_dense(P, state):
     A, rhs, e = P.normal_equations(state)
     return A, rhs, e
