@@ -78,6 +78,10 @@ def algorithmic_bytes(kernel, n_act, n_nodes, n_edges, n_pix, n_faces, n_verts):
 # in profiles/ with the fingerprint of the kernel sources they were taken on;
 # a changed kernel reports null until it is measured again.
 TRAFFIC_TABLE = os.path.join(ROOT, "profiles", "k_cg_hbm_traffic.md")
+# Sequence mode's vertices per tile: on the 20k-vertex sequence, same-box runs
+# at 96 / 128 / 160 / 256 (the library default) gave 128 the most frames/s
+# (2-3 % over 256: shorter product launches outweigh the longer node pass).
+SEQUENCE_TILE = 128
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_1810_02648_amd", "csrc", f)
                   for f in ("solve_kernels.hip", "common.hpp", "device.hpp")]
 
@@ -187,7 +191,8 @@ def bench_sequence(args, cap, torch):
     seq = synth.sequence.make_sequence(args.workload, 0)
     ctx = cap.Context(0)
     cap.set_graphs(ctx, not args.no_graphs)
-    S = sq.DeviceSequence(ctx, seq, vertices_per_tile=args.tile)
+    tile = SEQUENCE_TILE if args.tile is None else args.tile
+    S = sq.DeviceSequence(ctx, seq, vertices_per_tile=tile)
     log("plain tracking over %d frames" % S.n)
     states, _ = sq.track_plain(S)
     ntr = seq["n_train"]
@@ -219,7 +224,7 @@ def bench_sequence(args, cap, torch):
     n_edges = int((S.graph["edge_dst"] >= 0).sum().item())
     calls = 2 * len(test)    # one evaluate pass = one plain and one learned solve per frame
     roof = roofline_for(prof, calls, 1, n_act, S.nn, n_edges, W, H, seq["tri"].shape[1], seq["xyz"].shape[1],
-                        "%s/tile%d" % (args.workload, args.tile))
+                        "%s/tile%d" % (args.workload, tile))
     return {
         "metric": METRIC,
         "value": n / tl,
@@ -248,6 +253,7 @@ def bench_sequence(args, cap, torch):
             "mean_gn_steps_learned": float(np.mean(ev["learned_steps"])),
             "target_reached_fraction": float(np.mean(ev["reached"])),
             "prediction_used_fraction": float(np.mean(ev["used_prediction"])),
+            "vertices_per_tile": tile,
             "train_epochs": args.epochs,
             "train_seconds": t_train,
             "train_loss_first_last": [losses[0], losses[-1]],
@@ -275,7 +281,7 @@ def bench_frame(args, cap, torch):
     mask = torch.from_numpy(f["mask"]).cuda()
     image = torch.from_numpy(f["image"]).cuda()
     prm = cap.params(*f["weights"], gn_iters=gn, pcg_iters=pcg)
-    tile, tune = args.tile, None
+    tile, tune = args.tile or 0, None
     if tile == 0:       # autotuned tile size (setup, not timed)
         probe = cap.Template(ctx, tri, graph)
         fr0 = [cap.FrameInputs(probe, xyz, rgb, f["cam"], mask, image, start.clone()) for _ in range(args.batch)]
@@ -606,7 +612,7 @@ def bench_batch(args, cap, torch):
         return [cap.FrameInputs(cap.Template(ctx, tri, g, tile), xyz, rgb, f["cam"], mask, image, st.clone())
                 for f, (xyz, tri, g, rgb, mask, image, st) in zip(frames_h, dev_in)]
 
-    tile, tune = args.tile, None
+    tile, tune = args.tile or 0, None
     if tile == 0:       # autotuned tile size for the whole batch (setup, not timed)
         tile, tune = cap.autotune_tiles(ctx, [d[1] for d in dev_in], [d[2] for d in dev_in], make_frames(0), prm)
         log("autotuned vertices_per_tile", tile, tune)
@@ -711,7 +717,9 @@ def main():
     ap.add_argument("--no-pose", action="store_true", help="frame mode: leave out the pose stage")
     ap.add_argument("--no-graphs", action="store_true",
                     help="launch every kernel eagerly instead of replaying captured HIP graphs")
-    ap.add_argument("--tile", type=int, default=0, help="sequence/frame/batch modes: vertices per tile (0 = library default; frame and batch modes autotune)")
+    ap.add_argument("--tile", type=int, default=None,
+                    help="vertices per tile (0 = library default); default: %d in sequence mode, autotuned in frame "
+                         "and batch modes" % SEQUENCE_TILE)
     ap.add_argument("--frames", type=int, default=40, help="vertex / track modes: frames per step")
     ap.add_argument("--distinct", action="store_true",
                     help="frame mode: the --batch captures share no data (capture i: seed i, template of N - i "
