@@ -142,6 +142,38 @@ def test_missing_temporal_inputs_are_rejected(mini):
 
 
 # ---------------------------------------------------------------- derivatives
+def test_colour_kernel_prunes_photometric_rows_by_residual_norm(mini):
+    """Sec. 3.4 robust colour kernel in the per-vertex oracle: template colours
+    set to the blurred image's colour at each vertex plus an offset whose norm
+    is 0.49 or 0.51 (spread over the channels).  With tau_c = 0.5 exactly the
+    0.49 residuals remain, with their Jacobian rows, and the 0.51 rows vanish;
+    with tau_c = inf all remain.  The energy is the offsets' closed form."""
+    from oracle import image as oi
+    w = dict(w_photo=3.0, w_sil=0.0, w_smooth=0.0, w_edge=0.0, w_vel=0.0, w_acc=0.0)
+    V = mini["xyz"].astype(np.float64)
+    P0 = problem(mini, w)
+    cam = mini["cam"]
+    val, _, _ = oi.sample(P0.image(), cam.fx * V[0] / V[2] + cam.cx, cam.fy * V[1] / V[2] + cam.cy)
+    rng = np.random.default_rng(8)
+    dirs = rng.normal(size=(3, V.shape[1]))
+    dirs /= np.linalg.norm(dirs, axis=0)
+    small = rng.uniform(size=V.shape[1]) < 0.5
+    mag = np.where(small, 0.49, 0.51)
+    rgb = val + mag * dirs
+    vid = P0.vis_idx[V[2][P0.vis_idx] > 0]
+    assert vid.size > 20 and 0 < small[vid].sum() < vid.size
+    for tau, expect in ((0.5, 3.0 * 0.49 ** 2 * small[vid].sum()), (np.inf, 3.0 * (mag[vid] ** 2).sum())):
+        P = ov.VertexProblem(V, V, mini["tri"], rgb, mini["classes"], cam, mini["mask"], mini["image"], w, tau_c=tau)
+        F, b, J, e = P.linearize(V)
+        assert e["photo"] == pytest.approx(expect, rel=1e-9), tau
+        rows = np.abs(J[: 3 * vid.size]).sum(axis=1).A.ravel().reshape(3, vid.size).sum(axis=0)
+        if np.isfinite(tau):
+            assert (rows[~small[vid]] == 0).all() and (rows[small[vid]] > 0).all()
+            assert (F[: 3 * vid.size].reshape(3, vid.size)[:, ~small[vid]] == 0).all()
+        else:
+            assert (rows > 0).all()
+
+
 def test_jacobian_matches_central_differences(mini):
     rng = np.random.default_rng(5)
     rest = mini["xyz"].astype(np.float64)
