@@ -174,6 +174,37 @@ def test_colour_kernel_prunes_photometric_rows_by_residual_norm(mini):
             assert (rows > 0).all()
 
 
+def test_pyramid_takes_the_levels_in_order_and_touches_only_the_photometric_term(mini):
+    """Sec. 3.4 pyramid, one Gauss-Newton step per level (15, 9, 3): the first
+    step's energy is the photometric energy on the 15-tap image at the start
+    and the final energy the one on the 3-tap image at the result (each
+    computed here from the separately pinned blur and sampling); without the
+    photometric term the schedule changes nothing, bit for bit."""
+    from oracle import image as oi
+    rng = np.random.default_rng(21)
+    V0 = mini["xyz"].astype(np.float64) + rng.normal(0, 0.003, mini["xyz"].shape)
+    cam = mini["cam"]
+
+    def photo(P, V, k):
+        vid = P.vis_idx[V[2][P.vis_idx] > 0]
+        val, _, _ = oi.sample(oi.blur(mini["image"], k), cam.fx * V[0, vid] / V[2, vid] + cam.cx,
+                              cam.fy * V[1, vid] / V[2, vid] + cam.cy)
+        return 2.0 * float(((val - mini["rgb"][:, vid].astype(np.float64)) ** 2).sum())
+
+    w = dict(w_photo=2.0, w_sil=0.5, w_smooth=7.0, w_edge=11.0, w_vel=0.0, w_acc=0.0)
+    P = problem(mini, w, start=V0.astype(np.float32))
+    out = ov.solve(P, 3, "chol", blur_schedule=(15, 9, 3))
+    Vs = P.start.astype(np.float64)
+    assert out["energies"][0]["photo"] == pytest.approx(photo(P, Vs, 15), rel=1e-12)
+    assert out["energies"][-1]["photo"] == pytest.approx(photo(P, out["V"], 3), rel=1e-12)
+    assert photo(P, Vs, 15) != pytest.approx(photo(P, Vs, 3), rel=1e-3)     # the levels differ here
+    w0 = dict(w, w_photo=0.0)
+    P0 = problem(mini, w0, start=V0.astype(np.float32))
+    a = ov.solve(P0, 3, "chol", blur_schedule=(15, 9, 3))["V"]
+    b = ov.solve(P0, 3, "chol")["V"]
+    assert np.array_equal(a, b)
+
+
 def test_jacobian_matches_central_differences(mini):
     rng = np.random.default_rng(5)
     rest = mini["xyz"].astype(np.float64)
