@@ -143,9 +143,20 @@ __global__ __launch_bounds__(256) void k_vblur_h(const ProbDev *__restrict__ R, 
     if (x >= W) return;
     for (int l = 0; l < bs.n; ++l) {
         const int r = bs.r[l];
+        float w[kVMaxBlur];                  // the level's taps (uniform)
+#pragma unroll
+        for (int q = 0; q < kVMaxBlur; ++q) w[q] = bs.w[l][q];
         for (int c = 0; c < 3; ++c) {
+            // taps unrolled to the largest kernel, every read issued first
+            // (clamped into the level's window), then added from -r to r
+            const float *row = &sh[c][t + kBlurMargin - r];
+            float v[kVMaxBlur];
+#pragma unroll
+            for (int q = 0; q < kVMaxBlur; ++q) v[q] = row[min(q, 2 * r)];
             float acc = 0.0f;
-            for (int d = -r; d <= r; ++d) acc = acc + bs.w[l][d + r] * sh[c][t + kBlurMargin + d];
+#pragma unroll
+            for (int q = 0; q < kVMaxBlur; ++q)
+                if (q <= 2 * r) acc = acc + w[q] * v[q];
             tmp[(size_t(l) * 3 + c) * plane + size_t(y) * W + x] = acc;
         }
     }
@@ -160,6 +171,9 @@ struct BlurOut {
 __global__ __launch_bounds__(256) void k_vblur_v(const float *__restrict__ tmp, BlurOut out, int W, int H, BlurSet bs) {
     __shared__ float sh[kBlurTileH + 2 * kBlurMargin][kBlurTileW];
     const int l = blockIdx.z, r = bs.r[l];
+    float w[kVMaxBlur];                      // the level's taps (uniform)
+#pragma unroll
+    for (int q = 0; q < kVMaxBlur; ++q) w[q] = bs.w[l][q];
     const int x0 = blockIdx.x * kBlurTileW, y0 = blockIdx.y * kBlurTileH, t = threadIdx.x;
     const int tx = t & (kBlurTileW - 1), ty = t / kBlurTileW;        // 4 row groups of 4 rows
     const size_t plane = size_t(W) * H;
@@ -176,8 +190,13 @@ __global__ __launch_bounds__(256) void k_vblur_v(const float *__restrict__ tmp, 
             for (int k = 0; k < kBlurTileH / (256 / kBlurTileW); ++k) {
                 const int row = ty + k * (256 / kBlurTileW), y = y0 + row;
                 if (y >= H) break;
+                float v[kVMaxBlur];          // as in the horizontal pass: reads first, then the taps in order
+#pragma unroll
+                for (int q = 0; q < kVMaxBlur; ++q) v[q] = sh[row + min(q, 2 * r)][tx];
                 float acc = 0.0f;
-                for (int d = -r; d <= r; ++d) acc = acc + bs.w[l][d + r] * sh[row + r + d][tx];
+#pragma unroll
+                for (int q = 0; q < kVMaxBlur; ++q)
+                    if (q <= 2 * r) acc = acc + w[q] * v[q];
                 out.p[l][c * plane + size_t(y) * W + x0 + tx] = acc;
             }
     }
