@@ -3,6 +3,7 @@
 // steps of rows -> J^T J tiles -> Cholesky step).
 #include <algorithm>
 #include <cmath>
+#include <cstring>
 #include <vector>
 
 #include "device.hpp"
@@ -70,7 +71,6 @@ size_t carve_pose(uint8_t *base, const capture_pose_frame &f, ProbDev &pr, PoseD
     pr.px = L.take<float>(base, 3 * nv);
     pr.vcode = L.take<uint8_t>(base, nv);
     pr.pva = L.take<float>(base, 3 * nv);
-    pr.counts = L.take<int>(base, 3);
     max_rows = pose_fixed_rows(B.nj, B.it) + int(nv);
     pd.jR = L.take<double>(base, size_t(9) * B.nj);
     pd.jp = L.take<double>(base, size_t(3) * B.nj);
@@ -81,8 +81,10 @@ size_t carve_pose(uint8_t *base, const capture_pose_frame &f, ProbDev &pr, PoseD
     pd.ldr = (max_rows + 63) & ~63;
     pd.rows = L.take<double>(base, size_t(pd.ldr) * B.np);
     pd.epart = L.take<double>(base, size_t(blocks(max_rows, kPoseRowThreads)) * kPoseTerms);
-    pd.energy = L.take<double>(base, size_t(CAPTURE_MAX_GN + 1) * kPoseTerms);
     pd.sys = L.take<double>(base, size_t(B.nu) * (B.nu + 1));
+    // the report's items together, so that one read-back takes them
+    pd.energy = L.take<double>(base, size_t(CAPTURE_MAX_GN + 1) * kPoseTerms);
+    pr.counts = L.take<int>(base, 3);
     pd.status = L.take<int>(base, 1);
     return L.off;
 }
@@ -166,6 +168,7 @@ int pose_setup(PoseRun &P, capture_ctx *ctx, const capture_pose_frame *f, const 
     pd.dt = pr.dt;
     pd.vflags = pr.vflags;
     Run &R = P.R;
+    R.ctx = ctx;
     R.prof = &ctx->prof;
     R.n = 1;
     R.probs.resize(1);
@@ -180,8 +183,13 @@ int pose_setup(PoseRun &P, capture_ctx *ctx, const capture_pose_frame *f, const 
     P.row_blocks = int(blocks(max_rows, kPoseRowThreads));
     const int nt = pd.B.np / kPoseTile;
     P.ntp = nt * (nt + 1) / 2;
-    CAP_HIP(hipMemcpyAsync(R.dprobs, &R.probs[0], sizeof(ProbDev), hipMemcpyHostToDevice, R.s));
-    CAP_HIP(hipMemcpyAsync(P.dpose, &P.pd, sizeof(PoseDev), hipMemcpyHostToDevice, R.s));
+    // both descriptors in one upload from the context's pinned staging
+    const size_t poff = reinterpret_cast<uint8_t *>(P.dpose) - reinterpret_cast<uint8_t *>(R.dprobs);
+    uint8_t *stage = static_cast<uint8_t *>(run_staging(R, poff + sizeof(PoseDev)));
+    if (!stage) return fail(CAPTURE_ENOMEM, "host staging allocation failed");
+    std::memcpy(stage, &R.probs[0], sizeof(ProbDev));
+    std::memcpy(stage + poff, &P.pd, sizeof(PoseDev));
+    CAP_HIP(hipMemcpyAsync(R.dprobs, stage, poff + sizeof(PoseDev), hipMemcpyHostToDevice, R.s));
     return CAPTURE_OK;
 }
 
@@ -359,14 +367,22 @@ int capture_pose_solve(capture_ctx *ctx, const capture_pose_frame *f, const capt
     for (int g = 0; g < G; ++g)
         if ((rc = launch_pose_step(P, g, 0))) return rc;
     if ((rc = launch_pose_step(P, G, 1))) return rc;
-    double en[kPoseTerms * (CAPTURE_MAX_GN + 1)];
-    int st = 0, counts[2] = {0, 0};
+    // energies, counts and status (adjacent in the workspace) in one
+    // read-back into the context's pinned staging, after the descriptor
+    // upload from it on the stream
+    const uint8_t *d0 = reinterpret_cast<const uint8_t *>(P.pd.energy.ptr);
+    const size_t off_counts = reinterpret_cast<const uint8_t *>(P.R.probs[0].counts.ptr) - d0;
+    const size_t off_status = reinterpret_cast<const uint8_t *>(P.pd.status.ptr) - d0;
+    uint8_t *h = static_cast<uint8_t *>(run_staging(P.R, off_status + sizeof(int)));
+    if (!h) return fail(CAPTURE_ENOMEM, "host staging allocation failed");
     hipStream_t s = P.R.s;
-    CAP_HIP(hipMemcpyAsync(en, P.pd.energy, sizeof(double) * kPoseTerms * (G + 1), hipMemcpyDeviceToHost, s));
-    CAP_HIP(hipMemcpyAsync(&st, P.pd.status, sizeof(int), hipMemcpyDeviceToHost, s));
-    CAP_HIP(hipMemcpyAsync(counts, P.R.probs[0].counts, sizeof(int) * 2, hipMemcpyDeviceToHost, s));
+    CAP_HIP(hipMemcpyAsync(h, d0, off_status + sizeof(int), hipMemcpyDeviceToHost, s));
     CAP_HIP(hipStreamSynchronize(s));
     settle(P.R);
+    const double *en = reinterpret_cast<const double *>(h);
+    int st = 0, counts[2] = {0, 0};
+    std::memcpy(counts, h + off_counts, sizeof(counts));
+    std::memcpy(&st, h + off_status, sizeof(int));
     *rep = capture_pose_report{};
     for (int g = 0; g <= G; ++g) {
         const double *e = en + kPoseTerms * g;

@@ -15,6 +15,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstring>
 #include <string>
 #include <vector>
 
@@ -501,13 +502,20 @@ __global__ __launch_bounds__(kVThreads) void k_vupdate(const VertexDev *__restri
 
 // Energies of steps 0..G (one workgroup; each wave adds whole rows of
 // workgroup partials in a fixed order).
-__global__ __launch_bounds__(256) void k_vreport(const VertexDev *__restrict__ P, int G) {
+__global__ __launch_bounds__(256) void k_vreport(const VertexDev *__restrict__ P, const int *__restrict__ counts,
+                                                  int G) {
     const VertexDev &pr = *P;
     const int nb = pr.nb, wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     for (int item = wave; item < (G + 1) * kVTerms; item += 4) {
         double s[1];
         wave_sum_n<1>(pr.epart.g() + size_t(item) * nb, nb, nb, s);
         if (lane == 0) pr.scal[CAPTURE_MAX_GN + item] = s[0];
+    }
+    if (threadIdx.x == 0) {     // after the energies, so that one read-back takes the whole report
+        CAP_GLOBAL double *c = pr.scal.g() + CAPTURE_MAX_GN + (G + 1) * kVTerms;
+        c[0] = double(counts[0]);
+        c[1] = double(counts[1]);
+        c[2] = double(pr.nsnap[0]);
     }
 }
 
@@ -728,7 +736,7 @@ size_t carve_vertex(uint8_t *base, const capture_vertex_frame &f, int nlev, Prob
     vd.ru = L.take<double>(base, 2 * size_t(nb));
     vd.pap = L.take<double>(base, blocks(nv * kRowLanes, kApplyThreads));
     vd.epart = L.take<double>(base, size_t(CAPTURE_MAX_GN + 1) * kVTerms * nb);
-    vd.scal = L.take<double>(base, CAPTURE_MAX_GN + size_t(CAPTURE_MAX_GN + 1) * kVTerms);
+    vd.scal = L.take<double>(base, CAPTURE_MAX_GN + size_t(CAPTURE_MAX_GN + 1) * kVTerms + 3);
     vd.ring = L.take<int>(base, nv);
     vd.plab[0] = L.take<int>(base, hw);
     vd.plab[1] = L.take<int>(base, hw);
@@ -844,8 +852,13 @@ int vertex_setup(VRun &P, capture_ctx *ctx, const capture_vertex_frame *f, const
     R.s = static_cast<hipStream_t>(stream);
     P.vd = vd;
     P.dv = reinterpret_cast<VertexDev *>(base + ((sizeof(ProbDev) + 255) & ~size_t(255)));
-    CAP_HIP(hipMemcpyAsync(R.dprobs, &R.probs[0], sizeof(ProbDev), hipMemcpyHostToDevice, R.s));
-    CAP_HIP(hipMemcpyAsync(P.dv, &P.vd, sizeof(VertexDev), hipMemcpyHostToDevice, R.s));
+    // both descriptors in one upload from the context's pinned staging
+    const size_t voff = reinterpret_cast<uint8_t *>(P.dv) - reinterpret_cast<uint8_t *>(R.dprobs);
+    uint8_t *stage = static_cast<uint8_t *>(run_staging(R, voff + sizeof(VertexDev)));
+    if (!stage) return fail(CAPTURE_ENOMEM, "host staging allocation failed");
+    std::memcpy(stage, &R.probs[0], sizeof(ProbDev));
+    std::memcpy(stage + voff, &P.vd, sizeof(VertexDev));
+    CAP_HIP(hipMemcpyAsync(R.dprobs, stage, voff + sizeof(VertexDev), hipMemcpyHostToDevice, R.s));
     return CAPTURE_OK;
 }
 
@@ -938,7 +951,6 @@ int launch_vertex_solve(VRun &P, const capture_vertex_params *prm) {
         }
     }
     launch_vlin(P, G, P.step_level[G - 1], 1);
-    hipLaunchKernelGGL(k_vreport, dim3(1), dim3(256), 0, R.s, P.dv, G);
     hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, R.s, reinterpret_cast<uint32_t *>(P.vd.nsnap.ptr), size_t(1),
                        0u);
     if (prm->snap_max_px > 0.0f) {
@@ -953,6 +965,7 @@ int launch_vertex_solve(VRun &P, const capture_vertex_params *prm) {
             hipLaunchKernelGGL(k_vsnap_apply, dim3(nb), dim3(kVThreads), 0, R.s, P.dv, G, prm->snap_iters & 1);
         });
     }
+    hipLaunchKernelGGL(k_vreport, dim3(1), dim3(256), 0, R.s, P.dv, R.probs[0].counts.ptr, G);
     CAP_HIP(hipGetLastError());
     return CAPTURE_OK;
 }
@@ -1126,15 +1139,18 @@ int capture_vertex_solve(capture_ctx *ctx, const capture_vertex_frame *f, const 
     }
     if (rc) return rc;
     const int G = prm->gn_iters;
-    double en[(CAPTURE_MAX_GN + 1) * kVTerms];
-    int counts[2] = {0, 0}, nsnap = 0;
+    // the energies of every step, then the visible, contour and snapped
+    // counts, in one read-back into the context's pinned staging (the
+    // descriptor upload from it precedes this copy on the stream)
+    const size_t nrep = size_t(G + 1) * kVTerms + 3;
+    const double *en = static_cast<const double *>(run_staging(P.R, sizeof(double) * nrep));
+    if (!en) return fail(CAPTURE_ENOMEM, "host staging allocation failed");
     hipStream_t s = P.R.s;
-    CAP_HIP(hipMemcpyAsync(en, P.vd.scal.ptr + CAPTURE_MAX_GN, sizeof(double) * kVTerms * (G + 1),
+    CAP_HIP(hipMemcpyAsync(const_cast<double *>(en), P.vd.scal.ptr + CAPTURE_MAX_GN, sizeof(double) * nrep,
                            hipMemcpyDeviceToHost, s));
-    CAP_HIP(hipMemcpyAsync(counts, P.R.probs[0].counts, sizeof(int) * 2, hipMemcpyDeviceToHost, s));
-    CAP_HIP(hipMemcpyAsync(&nsnap, P.vd.nsnap.ptr, sizeof(int), hipMemcpyDeviceToHost, s));
     CAP_HIP(hipStreamSynchronize(s));
     settle(P.R);
+    const int counts[2] = {int(en[nrep - 3]), int(en[nrep - 2])}, nsnap = int(en[nrep - 1]);
     *rep = capture_vertex_report{};
     bool finite = true;
     for (int g = 0; g <= G; ++g) {
@@ -1181,7 +1197,7 @@ int capture_vertex_linearize(capture_ctx *ctx, const capture_vertex_frame *f, co
         hipLaunchKernelGGL(k_vapply, dim3(P.vd.nba), dim3(kApplyThreads), 0, s, P.dv, 0, 0, 1);
         CAP_HIP(hipMemcpyAsync(Ap, P.vd.Ap.ptr, sizeof(double) * 3 * nv, hipMemcpyDeviceToDevice, s));
     }
-    hipLaunchKernelGGL(k_vreport, dim3(1), dim3(256), 0, s, P.dv, 0);
+    hipLaunchKernelGGL(k_vreport, dim3(1), dim3(256), 0, s, P.dv, R.probs[0].counts.ptr, 0);
     if (vflags) CAP_HIP(hipMemcpyAsync(vflags, R.probs[0].vflags, nv, hipMemcpyDeviceToDevice, s));
     double en[kVTerms];
     CAP_HIP(hipMemcpyAsync(en, P.vd.scal.ptr + CAPTURE_MAX_GN, sizeof(en), hipMemcpyDeviceToHost, s));
