@@ -157,33 +157,50 @@ __global__ __launch_bounds__(256) void k_pose_lbs(const PoseDev *__restrict__ PP
     store_start_vertex(*PR, i, acc[0], acc[1], acc[2]);
 }
 
-// Contour set B as an ascending list, by one block (wave ballots, then wave
-// offsets): entry (vertex << 1) | (b_i == -1).
+// Contour set B as an ascending list, by one block: entry (vertex << 1) |
+// (b_i == -1).  The vertices go in rounds of kListBatch chunks of 1,024, each
+// round's flags loaded together; wave ballots count each chunk's entries per
+// wave, and after one barrier every thread adds the counts before its own
+// (earlier chunks, then earlier waves of its chunk) to place its entries.
+constexpr int kListBatch = 8;
 __global__ __launch_bounds__(1024) void k_pose_list(const PoseDev *__restrict__ PP) {
     const PoseDev &P = *PP;
     const int nv = P.B.nv;
-    __shared__ int wsum[16];
+    __shared__ int wsum[kListBatch][16];
     __shared__ int base;
     if (threadIdx.x == 0) base = 0;
-    __syncthreads();
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
-    for (int c0 = 0; c0 < nv; c0 += blockDim.x) {
-        const int i = c0 + threadIdx.x;
-        const uint8_t f = i < nv ? P.vflags[i] : 0;
-        const bool in = (f & 2) != 0;
-        const unsigned long long m = __ballot(in);
-        const int before = __popcll(m & ((1ull << lane) - 1ull));
-        if (lane == 0) wsum[wid] = __popcll(m);
-        __syncthreads();
-        int off = base;
-        for (int w = 0; w < wid; ++w) off += wsum[w];
-        if (in) P.blist[off + before] = (i << 1) | ((f & 4) ? 1 : 0);
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            int tot = 0;
-            for (int w = 0; w < nw; ++w) tot += wsum[w];
-            base += tot;
+    const int span = kListBatch * int(blockDim.x);
+    for (int c0 = 0; c0 < nv; c0 += span) {
+        uint8_t f[kListBatch];
+#pragma unroll
+        for (int u = 0; u < kListBatch; ++u) {
+            const int i = c0 + u * int(blockDim.x) + int(threadIdx.x);
+            f[u] = i < nv ? P.vflags[i] : 0;
         }
+        int before[kListBatch];
+#pragma unroll
+        for (int u = 0; u < kListBatch; ++u) {
+            const unsigned long long m = __ballot((f[u] & 2) != 0);
+            before[u] = __popcll(m & ((1ull << lane) - 1ull));
+            if (lane == 0) wsum[u][wid] = __popcll(m);
+        }
+        __syncthreads();          // (also orders base's first store before its reads)
+        int run = base;
+#pragma unroll
+        for (int u = 0; u < kListBatch; ++u) {
+            int cw = 0;
+            for (int w = 0; w < nw; ++w) {
+                if (w == wid) before[u] += run + cw;
+                cw += wsum[u][w];
+            }
+            run += cw;
+        }
+#pragma unroll
+        for (int u = 0; u < kListBatch; ++u)
+            if (f[u] & 2) P.blist[before[u]] = ((c0 + u * int(blockDim.x) + int(threadIdx.x)) << 1) | ((f[u] & 4) ? 1 : 0);
+        __syncthreads();          // every thread has read base and wsum
+        if (threadIdx.x == 0) base = run;
         __syncthreads();
     }
     if (threadIdx.x == 0) P.nb[0] = base;
