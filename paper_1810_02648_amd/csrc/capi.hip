@@ -25,7 +25,9 @@ __global__ void k_prep_rows(const ProbDev *P, int nb_rows);
 __global__ void k_linearize(const ProbDev *P, const TileDesc *D, int mode);
 template <int kSplit, int kMode>
 __global__ void k_cg(const ProbDev *P, const TileDesc *D, int j);
-__global__ void k_node_init(const ProbDev *P, int gn, int energy_only, int check_target, int slot_prev, int gn_iters);
+__global__ void k_node_init(const ProbDev *P, int check_target);
+__global__ void k_node_init_fin(const ProbDev *P, int gn, int energy_only, int check_target, int slot_prev, int gn_iters,
+                                int nparts);
 __global__ void k_node_gather(const ProbDev *P);
 __global__ void k_cg_finish(const ProbDev *P, int n);
 __global__ void k_pcg_node(const ProbDev *P, int j, int last);
@@ -452,8 +454,10 @@ void launch_linearize(Run &R, int gn, int energy_only, int check_target = 0, int
                            energy_only);
     });
     timed(R, K_NODE_INIT, [&] {
-        hipLaunchKernelGGL(k_node_init, dim3(R.n), dim3(kInitThreads), 0, R.s, R.dprobs, gn, energy_only,
-                           check_target, slot_prev, gn_iters);
+        if (!energy_only)
+            hipLaunchKernelGGL(k_node_init, dim3(kInitBlocks, R.n), dim3(kInitThreads), 0, R.s, R.dprobs, check_target);
+        hipLaunchKernelGGL(k_node_init_fin, dim3(R.n), dim3(kInitFinThreads), 0, R.s, R.dprobs, gn, energy_only,
+                           check_target, slot_prev, gn_iters, kInitBlocks);
     });
 }
 
@@ -1128,7 +1132,8 @@ int warm_sequence(Run &R, const capture_nonrigid_params *params, capture_warmsta
                            R.tiles, 2);
     });
     timed(R, K_NODE_INIT, [&] {
-        hipLaunchKernelGGL(k_node_init, dim3(R.n), dim3(kInitThreads), 0, R.s, R.dprobs, 0, 0, 3, 0, 0);
+        hipLaunchKernelGGL(k_node_init, dim3(kInitBlocks, R.n), dim3(kInitThreads), 0, R.s, R.dprobs, 3);
+        hipLaunchKernelGGL(k_node_init_fin, dim3(R.n), dim3(kInitFinThreads), 0, R.s, R.dprobs, 0, 0, 3, 0, 0, kInitBlocks);
     });
     if (!split) return launch_solve(R, params, 1, true);
     launch_steps(R, params, 1, true, 0, split);

@@ -34,7 +34,9 @@ constexpr int kMaxTileSlots = 200;    // distinct nodes touched by a tile
 #define CAP_NODE_THREADS 1024
 #endif
 constexpr int kNodeThreads = CAP_NODE_THREADS;    // threads of a per-problem node workgroup
-constexpr int kInitThreads = 512;     // threads of the post-linearisation node workgroup (k_node_init)
+constexpr int kInitThreads = 512;     // threads of a post-linearisation node workgroup (k_node_init)
+constexpr int kInitBlocks = 8;        // k_node_init workgroups per problem (then k_node_init_fin: one)
+constexpr int kInitFinThreads = 256;  // threads of k_node_init_fin
 constexpr int kMaxImageSide = 4096;
 constexpr int kRasterSmall = 256;         // pixel-box size above which a face is rasterised by a workgroup
 constexpr int kRasterBigBlocks = 512;
@@ -47,7 +49,8 @@ inline size_t dt_rows_lds(int W) { return sizeof(int) * size_t(W) + 16; }
 constexpr int kApplySplitTiles = CAP_APPLY_SPLIT_TILES;   // tile grids above this take the two-pass J^T J p reduction
 constexpr int kGraphCache = 16;          // captured solve graphs kept per context
 constexpr int kTerms = 5;   // energy terms per slot: photo, sil (with b), sil (with |b|), arap, velocity
-constexpr int kScalars = 8 + kTerms * (CAPTURE_MAX_GN + 2);   // slot MAX_GN + 1: predicted start
+constexpr int kInitPart = 8 + kTerms * (CAPTURE_MAX_GN + 2);  // energy slot MAX_GN + 1: predicted start
+constexpr int kScalars = kInitPart + 2 * kInitBlocks;         // then r.u and b.b per k_node_init workgroup
 
 // A pointer to device global memory.  Indexing it reads and writes through
 // the global address space (global_load / global_store): a plain pointer held

@@ -737,7 +737,7 @@ template __global__ void k_cg<1, kCgStandard>(const ProbDev *, const TileDesc *,
 // Node kernels: one workgroup per problem.
 // ----------------------------------------------------------------------------
 
-constexpr int kInitItems = 16;   // k_node_init (kInitThreads): the same 8192 items, 256 VGPRs per lane
+constexpr int kInitItems = 4;    // k_node_init: items per thread in registers (kInitBlocks x kInitThreads threads)
 
 
 __device__ inline float sum_parts(gptr<const float> partial, int stride, int c, int pb, int pe) {
@@ -788,109 +788,133 @@ __device__ inline float gather_node(const TemplateDev &T, gptr<const float> part
     return sum_parts(partial, stride, c, T.node_pbeg[k], T.node_pbeg[k + 1]);
 }
 
-// After a linearisation: b, diag, Jacobi preconditioner, PCG start vectors
-// (x_0 = 0, r_0 = b, u_0 = M^-1 r_0, generation 0), r.u, and the energy of GN step `gn`.
-// One thread per (component, node) item; every load is issued before the
-// stop tests, and r.z and the energy terms share one block reduction.
+// After a linearisation, in two launches.  k_node_init (kInitBlocks
+// workgroups per problem, blockIdx.y = problem): b, diag, Jacobi
+// preconditioner and PCG start vectors (x_0 = 0, r_0 = b, u_0 = M^-1 r_0,
+// generation 0) of its share of the (component, node) items, one item per
+// thread, every load issued before the stop tests; its r.u and b.b sums go
+// to scal[kInitPart + 2 blockIdx.x ..].  k_node_init_fin (one workgroup per
+// problem) adds those sums in workgroup order and the tiles' energy sums in
+// tile order, and takes the decisions: the energy of GN step `gn`, the
+// scalars of the first PCG iteration and the stops.
 // check_target bit 0: stop when the energy reaches the target; bit 1: the
 // conditional pass (see k_linearize); bit 2: the learned start's selection
 // after the linearisation at the prediction: keep the prediction only if
 // its energy is below the energy in scal slot `slot_prev` (that of the
 // previous frame's state), otherwise undo any stop (the schedule is again
 // gn_iters steps) and restore the start state from state0; scal[4] and
-// scal[6] receive the two energies, scal[5] the rejection.
-__global__ __launch_bounds__(kInitThreads) void k_node_init(const ProbDev *__restrict__ P, int gn, int energy_only,
-                                                          int check_target, int slot_prev, int gn_iters) {
-    __shared__ double red[kInitThreads / 64][2 + kTerms];
-    __shared__ int reject;
-    const ProbDev &pr = P[blockIdx.x];
+// scal[6] hold the two energies, scal[5] the rejection.  With energy_only
+// the first launch is left out.
+__global__ __launch_bounds__(kInitThreads) void k_node_init(const ProbDev *__restrict__ P, int check_target) {
+    __shared__ double red[kInitThreads / 64][2];
+    const ProbDev &pr = P[blockIdx.y];
     const TemplateDev &T = pr.T;
     const int nn = T.nn, n6 = 6 * nn;
-    double v[2 + kTerms] = {0, 0, 0, 0, 0, 0, 0};   // r.u, the energy terms, b.b
-    for (int t = threadIdx.x; t < T.ntiles; t += blockDim.x)
-        for (int q = 0; q < kTerms; ++q) v[1 + q] += pr.tile_e[size_t(t) * kTerms + q];
-    const bool regs = n6 <= kInitItems * kInitThreads;
+    const int gt = blockIdx.x * kInitThreads + threadIdx.x, stride = gridDim.x * kInitThreads;
+    const bool regs = n6 <= kInitItems * stride;
     int pb[kInitItems], pe[kInitItems];
-    if (!energy_only && regs) {     // unconditional loads at clamped positions, zeroed past the items
+    if (regs) {     // unconditional loads at clamped positions, zeroed past the items
 #pragma unroll
         for (int j = 0; j < kInitItems; ++j) {
-            const int k = min(int(threadIdx.x) + j * kInitThreads, n6 - 1) % nn;
+            const int k = min(gt + j * stride, n6 - 1) % nn;
             pb[j] = T.node_pbeg[k]; pe[j] = T.node_pbeg[k + 1];
         }
 #pragma unroll
         for (int j = 0; j < kInitItems; ++j)
-            if (int(threadIdx.x) + j * kInitThreads >= n6) pb[j] = pe[j] = 0;
+            if (gt + j * stride >= n6) pb[j] = pe[j] = 0;
     }
     // stopped at the target energy (never so at the selection, which follows
     // the frame set-up's cleared flags)
     if (pr.scal[2] != 0.0 && !(check_target & 4)) return;
     if ((check_target & 2) && pr.scal[5] == 0.0) return;   // conditional pass (see k_linearize)
-    if (!energy_only) {
-        if (regs) {
-            // items in groups of four, each group's loads (b and the diagonal,
-            // kParts parts each) in flight together
-            constexpr int G = 4;
-            static_assert(kInitItems % G == 0, "whole groups");
+    double v[2] = {0.0, 0.0};      // r.u, b.b
+    if (regs) {
+        // items in groups of four, each group's loads (b and the diagonal,
+        // kParts parts each) in flight together
+        constexpr int G = 4;
+        static_assert(kInitItems % G == 0, "whole groups");
 #pragma unroll
-            for (int g = 0; g < kInitItems; g += G) {
-                if (g * kInitThreads >= n6) break;           // (uniform) no thread has these items
-                int cb[G], cd[G], gb[G], ge[G];
-                float bb[G], dd[G];
+        for (int g = 0; g < kInitItems; g += G) {
+            if (g * stride >= n6) break;                 // (uniform) no thread has these items
+            int cb[G], cd[G], gb[G], ge[G];
+            float bb[G], dd[G];
 #pragma unroll
-                for (int h = 0; h < G; ++h) {
-                    cb[h] = min(int(threadIdx.x) + (g + h) * kInitThreads, n6 - 1) / nn;
-                    cd[h] = 6 + cb[h];
-                    gb[h] = pb[g + h];
-                    ge[h] = pe[g + h];
-                }
-                sum_parts_n<G>(pr.partial, T.nslots, cb, gb, ge, bb);
-                sum_parts_n<G>(pr.partial, T.nslots, cd, gb, ge, dd);
-#pragma unroll
-                for (int h = 0; h < G; ++h) {
-                    const int i = threadIdx.x + (g + h) * kInitThreads;
-                    if (i < n6) {
-                        const float b = bb[h], d = dd[h];
-                        const float mi = d > 0.0f ? 1.0f / d : 1.0f;
-                        const double u = double(mi * b);     // float32, as multiplied
-                        pr.b[i] = b; pr.diag[i] = d; pr.dinv[i] = mi;
-                        pr.vx[0][i] = 0.0; pr.vr[0][i] = double(b); pr.vu[0][i] = u;
-                        v[0] += double(b) * u;
-                        v[1 + kTerms] += double(b) * double(b);
-                    }
-                }
+            for (int h = 0; h < G; ++h) {
+                cb[h] = min(gt + (g + h) * stride, n6 - 1) / nn;
+                cd[h] = 6 + cb[h];
+                gb[h] = pb[g + h];
+                ge[h] = pe[g + h];
             }
-        } else {
-            for (int i = threadIdx.x; i < n6; i += blockDim.x) {
-                const int c = i / nn, k = i - c * nn;
-                const float b = gather_node(T, pr.partial, T.nslots, k, c);
-                const float d = gather_node(T, pr.partial, T.nslots, k, 6 + c);
-                const float mi = d > 0.0f ? 1.0f / d : 1.0f;
-                const double u = double(mi * b);     // float32, as multiplied
-                pr.b[i] = b; pr.diag[i] = d; pr.dinv[i] = mi;
-                pr.vx[0][i] = 0.0; pr.vr[0][i] = double(b); pr.vu[0][i] = u;
-                v[0] += double(b) * u;
-                v[1 + kTerms] += double(b) * double(b);
+            sum_parts_n<G>(pr.partial, T.nslots, cb, gb, ge, bb);
+            sum_parts_n<G>(pr.partial, T.nslots, cd, gb, ge, dd);
+#pragma unroll
+            for (int h = 0; h < G; ++h) {
+                const int i = gt + (g + h) * stride;
+                if (i < n6) {
+                    const float b = bb[h], d = dd[h];
+                    const float mi = d > 0.0f ? 1.0f / d : 1.0f;
+                    const double u = double(mi * b);     // float32, as multiplied
+                    pr.b[i] = b; pr.diag[i] = d; pr.dinv[i] = mi;
+                    pr.vx[0][i] = 0.0; pr.vr[0][i] = double(b); pr.vu[0][i] = u;
+                    v[0] += double(b) * u;
+                    v[1] += double(b) * double(b);
+                }
             }
         }
+    } else {
+        for (int i = gt; i < n6; i += stride) {
+            const int c = i / nn, k = i - c * nn;
+            const float b = gather_node(T, pr.partial, T.nslots, k, c);
+            const float d = gather_node(T, pr.partial, T.nslots, k, 6 + c);
+            const float mi = d > 0.0f ? 1.0f / d : 1.0f;
+            const double u = double(mi * b);     // float32, as multiplied
+            pr.b[i] = b; pr.diag[i] = d; pr.dinv[i] = mi;
+            pr.vx[0][i] = 0.0; pr.vr[0][i] = double(b); pr.vu[0][i] = u;
+            v[0] += double(b) * u;
+            v[1] += double(b) * double(b);
+        }
     }
-    block_sum_n<kInitThreads, 2 + kTerms>(v, red);
+    block_sum_n<kInitThreads, 2>(v, red);
     if (threadIdx.x == 0) {
-        const double rz = v[0];
+        pr.scal[kInitPart + 2 * blockIdx.x] = v[0];
+        pr.scal[kInitPart + 2 * blockIdx.x + 1] = v[1];
+    }
+}
+
+__global__ __launch_bounds__(kInitFinThreads) void k_node_init_fin(const ProbDev *__restrict__ P, int gn, int energy_only,
+                                                                   int check_target, int slot_prev, int gn_iters,
+                                                                   int nparts) {
+    __shared__ double red[kInitFinThreads / 64][kTerms];
+    __shared__ int reject;
+    const ProbDev &pr = P[blockIdx.x];
+    const TemplateDev &T = pr.T;
+    double v[kTerms] = {0, 0, 0, 0, 0};   // the energy terms
+    for (int t = threadIdx.x; t < T.ntiles; t += blockDim.x)
+        for (int q = 0; q < kTerms; ++q) v[q] += pr.tile_e[size_t(t) * kTerms + q];
+    if (pr.scal[2] != 0.0 && !(check_target & 4)) return;          // as in k_node_init
+    if ((check_target & 2) && pr.scal[5] == 0.0) return;
+    block_sum_n<kInitFinThreads, kTerms>(v, red);
+    if (threadIdx.x == 0) {
         if (!energy_only) {
+            double rz = 0.0, bb = 0.0;        // the workgroups' sums in workgroup order
+            for (int w = 0; w < nparts; ++w) {
+                rz += pr.scal[kInitPart + 2 * w];
+                bb += pr.scal[kInitPart + 2 * w + 1];
+            }
             pr.scal[0] = rz;
             pr.scal[1] = rz == 0.0 ? 1.0 : 0.0;
             pr.cg[4] = 0.0;        // the solution so far: x_0 = 0 (generation 0)
-            pr.cg[5] = v[1 + kTerms];
-            if ((check_target & 1) && v[1] + v[2] + v[4] + v[5] <= pr.target) {   // x = 0 above, so the step's update is void
+            pr.cg[5] = bb;
+            if ((check_target & 1) && v[0] + v[1] + v[3] + v[4] <= pr.target) {   // x = 0 above, so the step's update is void
                 pr.scal[1] = 1.0;
                 pr.scal[2] = 1.0;
                 pr.scal[3] = double(gn);
             }
         }
-        for (int q = 0; q < kTerms; ++q) pr.scal[8 + kTerms * gn + q] = v[1 + q];
+        for (int q = 0; q < kTerms; ++q) pr.scal[8 + kTerms * gn + q] = v[q];
         if (check_target & 4) {
             const CAP_GLOBAL double *e0 = pr.scal.g() + 8 + kTerms * slot_prev;
-            const double E0 = e0[0] + e0[1] + e0[3] + e0[4], E1 = v[1] + v[2] + v[4] + v[5];
+            const double E0 = e0[0] + e0[1] + e0[3] + e0[4], E1 = v[0] + v[1] + v[3] + v[4];
             reject = !(E1 < E0);
             pr.scal[4] = E1;
             pr.scal[5] = reject ? 1.0 : 0.0;
