@@ -471,23 +471,25 @@ __global__ __launch_bounds__(kStepThreads) void k_pose_step(const PoseDev *__res
     const int t = threadIdx.x;
     __shared__ double A[kMaxPoseUnknowns * (kMaxPoseUnknowns + 1)];
     __shared__ double pn[kMaxPoseUnknowns];
-    __shared__ double ep[64 * kPoseTerms];
     __shared__ double red[kStepThreads / 64];
     __shared__ int bad;
-    // energies of the rows kernel's blocks (4 terms each), summed in block
-    // order by four threads, 64 blocks' partials per round of loads
+    // energies of the rows kernel's blocks: wave q sums term q, each lane a
+    // strided share of the blocks (its loads in flight together), then a
+    // fixed butterfly over the lanes
     if (t == 0) bad = 0;
-    double es = 0.0;
-    for (int b0 = 0; b0 < nblk; b0 += 64) {
-        __syncthreads();
-        if (t < 64 * kPoseTerms) ep[t] = b0 + t / kPoseTerms < nblk ? P.epart[size_t(b0) * kPoseTerms + t] : 0.0;
-        __syncthreads();
-        if (t < kPoseTerms)
-            for (int b = 0; b < 64 && b0 + b < nblk; ++b) es += ep[b * kPoseTerms + t];
-    }
-    if (t < kPoseTerms) {
-        P.energy[gn * kPoseTerms + t] = es;
-        if (!isfinite(es)) bad = 1;
+    __syncthreads();
+    {
+        const int wq = t >> 6, lane = t & 63;
+        if (wq < kPoseTerms) {
+            double es = 0.0;
+            for (int b = lane; b < nblk; b += 64) es += P.epart[size_t(b) * kPoseTerms + wq];
+#pragma unroll
+            for (int o = 32; o > 0; o >>= 1) es += __shfl_xor(es, o);
+            if (lane == 0) {
+                P.energy[gn * kPoseTerms + wq] = es;
+                if (!isfinite(es)) bad = 1;
+            }
+        }
     }
     __syncthreads();
     if (bad) {
