@@ -737,7 +737,9 @@ template __global__ void k_cg<1, kCgStandard>(const ProbDev *, const TileDesc *,
 // Node kernels: one workgroup per problem.
 // ----------------------------------------------------------------------------
 
-constexpr int kInitItems = 4;    // k_node_init: items per thread in registers (kInitBlocks x kInitThreads threads)
+// k_node_init: items per thread held in registers (kInitBlocks x kInitThreads
+// threads: 8,192 items, 1,365 nodes); larger problems take the strided loop
+constexpr int kInitItems = 2;
 
 
 __device__ inline float sum_parts(gptr<const float> partial, int stride, int c, int pb, int pe) {
@@ -829,9 +831,9 @@ __global__ __launch_bounds__(kInitThreads) void k_node_init(const ProbDev *__res
     if ((check_target & 2) && pr.scal[5] == 0.0) return;   // conditional pass (see k_linearize)
     double v[2] = {0.0, 0.0};      // r.u, b.b
     if (regs) {
-        // items in groups of four, each group's loads (b and the diagonal,
+        // items in groups of two, each group's loads (b and the diagonal,
         // kParts parts each) in flight together
-        constexpr int G = 4;
+        constexpr int G = 2;
         static_assert(kInitItems % G == 0, "whole groups");
 #pragma unroll
         for (int g = 0; g < kInitItems; g += G) {
