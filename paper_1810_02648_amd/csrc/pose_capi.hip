@@ -16,13 +16,9 @@ int build_topology_template(const int *tri_dev, int nv, int nf, capture_template
 __global__ void k_fill_u32(uint32_t *p, size_t n, uint32_t v);
 __global__ void k_contour(const ProbDev *P);
 __global__ void k_dt_seg(const ProbDev *P);
-__global__ void k_dt_scan(const ProbDev *P);
-__global__ void k_dt_scan_cols(const ProbDev *P);
-__global__ void k_dt_cols(const ProbDev *P);
-__global__ void k_dt_rows(const ProbDev *P);
-__global__ void k_raster(const ProbDev *P);
-__global__ void k_raster_big(const ProbDev *P);
-__global__ void k_contour_edges(const ProbDev *P);
+__global__ void k_prep_raster(const ProbDev *P, int nb_f, int scan);
+__global__ void k_prep_cols(const ProbDev *P);
+__global__ void k_prep_rows(const ProbDev *P, int nb_rows);
 __global__ void k_decide(const ProbDev *P);
 __global__ void k_pose_fk(const PoseDev *P);
 __global__ void k_pose_lbs(const PoseDev *P, const ProbDev *R);
@@ -201,28 +197,26 @@ int launch_pose_decisions(PoseRun &P) {
     const ProbDev &pr = R.probs[0];
     const size_t hw = size_t(pr.W) * pr.H;
     hipLaunchKernelGGL(k_fill_u32, dim3(blocks(hw, 256)), dim3(256), 0, s, pr.zbuf, hw, 0u);
-    hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, s, reinterpret_cast<uint32_t *>(pr.counts.ptr), size_t(3), 0u);
-    timed(R, K_POSE_LBS, [&] {
+    timed(R, K_POSE_LBS, [&] {           // (the skinning also zeroes the counters)
         hipLaunchKernelGGL(k_pose_fk, dim3(1), dim3(64), 0, s, P.dpose);
         hipLaunchKernelGGL(k_pose_lbs, dim3(blocks(pr.T.nv, 256)), dim3(256), 0, s, P.dpose, R.dprobs);
     });
     const dim3 gpx(blocks(hw, 256));
     timed(R, K_CONTOUR, [&] { hipLaunchKernelGGL(k_contour, gpx, dim3(256), 0, s, R.dprobs); });
+    // steps with the same predecessors share a launch, as in the
+    // deformation-graph path: rasterisation + segment scan, large faces +
+    // column distances, row pass + contour edges
     const size_t nsegw = size_t(pr.W) * ((pr.H + 15) / 16);
-    timed(R, K_DT_COLS, [&] {
-        hipLaunchKernelGGL(k_dt_seg, dim3(blocks(nsegw, 256)), dim3(256), 0, s, R.dprobs);
-        hipLaunchKernelGGL(k_dt_scan, dim3(blocks(pr.W, 4)), dim3(256), 0, s, R.dprobs);
-        hipLaunchKernelGGL(k_dt_cols, dim3(blocks(nsegw, 256)), dim3(256), 0, s, R.dprobs);
+    const int nb_seg = int(blocks(nsegw, 256)), nb_f = int(blocks(pr.T.nf, 256)), nb_me = int(blocks(pr.T.nmedges, 256));
+    timed(R, K_DT_COLS, [&] { hipLaunchKernelGGL(k_dt_seg, dim3(nb_seg), dim3(256), 0, s, R.dprobs); });
+    timed(R, K_PREP_RASTER, [&] {
+        hipLaunchKernelGGL(k_prep_raster, dim3(nb_f + int(blocks(pr.W, 4))), dim3(256), 0, s, R.dprobs, nb_f, 1);
+    });
+    timed(R, K_PREP_COLS, [&] {
+        hipLaunchKernelGGL(k_prep_cols, dim3(kRasterBigBlocks + nb_seg), dim3(256), 0, s, R.dprobs);
     });
     timed(R, K_DT_ROWS, [&] {
-        hipLaunchKernelGGL(k_dt_rows, dim3(pr.H), dim3(256), dt_rows_lds(pr.W), s, R.dprobs);
-    });
-    timed(R, K_RASTER, [&] {
-        hipLaunchKernelGGL(k_raster, dim3(blocks(pr.T.nf, 256)), dim3(256), 0, s, R.dprobs);
-        hipLaunchKernelGGL(k_raster_big, dim3(kRasterBigBlocks), dim3(256), 0, s, R.dprobs);
-    });
-    timed(R, K_CEDGES, [&] {
-        hipLaunchKernelGGL(k_contour_edges, dim3(blocks(pr.T.nmedges, 256)), dim3(256), 0, s, R.dprobs);
+        hipLaunchKernelGGL(k_prep_rows, dim3(pr.H + nb_me), dim3(256), dt_rows_lds(pr.W), s, R.dprobs, pr.H);
     });
     timed(R, K_DECIDE, [&] {
         hipLaunchKernelGGL(k_decide, dim3(blocks(pr.T.nv, 256)), dim3(256), 0, s, R.dprobs);

@@ -132,6 +132,7 @@ __global__ __launch_bounds__(64) void k_pose_fk(const PoseDev *__restrict__ PP) 
 __global__ __launch_bounds__(256) void k_pose_lbs(const PoseDev *__restrict__ PP, const ProbDev *__restrict__ PR) {
     const PoseDev &P = *PP;
     const BodyDev &B = P.B;
+    if (blockIdx.x == 0 && threadIdx.x < 3) PR->counts[threadIdx.x] = 0;     // visible, contour, large-face queue
     __shared__ float sR[9 * kMaxJoints], sp[3 * kMaxJoints], sJ[3 * kMaxJoints];
     for (int e = threadIdx.x; e < 9 * B.nj; e += blockDim.x) sR[e] = float(P.jR[e]);
     for (int e = threadIdx.x; e < 3 * B.nj; e += blockDim.x) {
