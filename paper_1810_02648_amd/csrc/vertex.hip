@@ -109,7 +109,17 @@ namespace cap {
 // ---------------------------------------------------------------- kernels
 // Start positions: the decision recipe's float32 geometry, and the first
 // linearisation point (read by step 0 as "previous point + previous solution").
-__global__ __launch_bounds__(kVThreads) void k_vstart(const VertexDev *__restrict__ P, const ProbDev *__restrict__ R) {
+// Blocks from nbv on clear the depth buffer instead, 8 x kVThreads pixels each.
+constexpr int kZbufPerBlock = 8 * kVThreads;
+__global__ __launch_bounds__(kVThreads) void k_vstart(const VertexDev *__restrict__ P, const ProbDev *__restrict__ R,
+                                                      int nbv) {
+    if (int(blockIdx.x) >= nbv) {
+        const size_t hw = size_t(R->W) * R->H, q0 = size_t(blockIdx.x - nbv) * kZbufPerBlock + threadIdx.x;
+#pragma unroll
+        for (int u = 0; u < kZbufPerBlock / kVThreads; ++u)
+            if (q0 + size_t(u) * kVThreads < hw) R->zbuf[q0 + size_t(u) * kVThreads] = 0u;
+        return;
+    }
     const VertexDev &pr = *P;
     const int nv = pr.nv, i = blockIdx.x * kVThreads + threadIdx.x;
     if (blockIdx.x == 0 && threadIdx.x < CAPTURE_MAX_GN) pr.scal[threadIdx.x] = 0.0;
@@ -220,6 +230,7 @@ __global__ __launch_bounds__(kVThreads) void k_vlin(const VertexDev *__restrict_
     const VTemplateDev &T = pr.T;
     const int nv = pr.nv, i = blockIdx.x * kVThreads + threadIdx.x;
     const int gp = (g + 1) & 1, gc = g & 1;
+    if (mode != 0 && i == 0) pr.nsnap[0] = 0;      // the snapping that may follow counts from here
     double es[kVTerms + 1] = {0, 0, 0, 0, 0, 0, 0, 0};
     if (i < nv) {
         double V[3], xo[3];
@@ -867,14 +878,15 @@ int launch_vertex_decisions(VRun &P) {
     const ProbDev &pr = R.probs[0];
     const size_t hw = size_t(pr.W) * pr.H;
     const int nv = pr.T.nv;
-    // the depth buffer cleared; the start geometry (which also zeroes the
-    // counters); contour pixels and column segments; then, as in the
+    // the start geometry (which also zeroes the counters and, in blocks of
+    // its own, the depth buffer); contour pixels and column segments; then, as in the
     // deformation-graph path, steps with the same predecessors share a launch
     // (rasterisation + segment scan, large faces + column distances, row pass
     // + contour edges)
-    hipLaunchKernelGGL(k_fill_u32, dim3(blocks(hw, 256)), dim3(256), 0, s, pr.zbuf, hw, 0u);
     timed(R, K_DEFORM, [&] {
-        hipLaunchKernelGGL(k_vstart, dim3(blocks(nv, kVThreads)), dim3(kVThreads), 0, s, P.dv, R.dprobs);
+        const int nbv = int(blocks(nv, kVThreads));
+        hipLaunchKernelGGL(k_vstart, dim3(nbv + int(blocks(hw, kZbufPerBlock))), dim3(kVThreads), 0, s, P.dv, R.dprobs,
+                           nbv);
     });
     const dim3 gpx(blocks(hw, 256));
     timed(R, K_CONTOUR, [&] { hipLaunchKernelGGL(k_contour, gpx, dim3(256), 0, s, R.dprobs); });
@@ -948,9 +960,7 @@ int launch_vertex_solve(VRun &P, const capture_vertex_params *prm) {
             timed(R, K_V_UPDATE, [&] { hipLaunchKernelGGL(k_vupdate, dim3(nb), dim3(kVThreads), 0, R.s, P.dv, g, j); });
         }
     }
-    launch_vlin(P, G, P.step_level[G - 1], 1);
-    hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, R.s, reinterpret_cast<uint32_t *>(P.vd.nsnap.ptr), size_t(1),
-                       0u);
+    launch_vlin(P, G, P.step_level[G - 1], 1);      // (also zeroes the snapped count)
     if (prm->snap_max_px > 0.0f) {
         const float tol = 0.05f;
         timed(R, K_V_SNAP, [&] {
