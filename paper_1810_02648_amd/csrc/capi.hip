@@ -46,6 +46,8 @@ __global__ void k_mse_grad(const float *y, const float *t, int n, float *dy, uin
 __global__ void k_adam(float *w, const float *g, float *m, float *v, uint16_t *wb, int n, float lr, float c1, float c2);
 __global__ void k_to_bf16(const float *in, uint16_t *out, int n);
 __global__ void k_ws_features(const ProbDev *P, float *X);
+__global__ void k_ws_layer1_feat(const ProbDev *P, float *X, const float *mu, const float *sd, const uint16_t *W,
+                                 const float *bias, uint16_t *Xb, float *z, uint16_t *cat);
 __global__ void k_ws_layer1(const float *X, int nn, const float *mu, const float *sd, const uint16_t *W,
                             const float *bias, uint16_t *Xb, float *z, uint16_t *cat);
 template <int NT>
@@ -587,8 +589,9 @@ void ws_forward(capture_warmstart *net, const TemplateDev &T, const float *X, hi
                 const ProbDev *upd = nullptr) {
     const int nn = T.nn;
     const dim3 g(unsigned((nn + 15) / 16));
-    hipLaunchKernelGGL(k_ws_layer1, g, dim3(512), 0, s, X, nn, net->mu, net->sd, net->wb + kOffW1, net->w + kOffB1,
-                       net->Xb, net->z1, net->c1);
+    if (X)      // (else the first layer has run with its features formed in place: k_ws_layer1_feat)
+        hipLaunchKernelGGL(k_ws_layer1, g, dim3(512), 0, s, X, nn, net->mu, net->sd, net->wb + kOffW1, net->w + kOffB1,
+                           net->Xb, net->z1, net->c1);
     hipLaunchKernelGGL(k_ws_layer_mp<8>, g, dim3(512), 0, s, net->c1, net->z1, T.edge_dst, nn, net->wb + kOffW2,
                        net->w + kOffB2, 128, net->z2, net->c2, (float *)nullptr, (const ProbDev *)nullptr);
     hipLaunchKernelGGL(k_ws_layer_mp<1>, g, dim3(512), 0, s, net->c2, net->z2, T.edge_dst, nn, net->wb + kOffW3,
@@ -1120,11 +1123,10 @@ int warm_sequence(Run &R, const capture_nonrigid_params *params, capture_warmsta
     int rc = launch_frame(R, params->gn_iters);   // keeps the given state in state0
     if (rc) return rc;
     launch_linearize(R, prev_slot, 0);
-    timed(R, K_WS_FEAT, [&] {
-        hipLaunchKernelGGL(k_ws_features, dim3(blocks(pr.T.nn, 256), 1), dim3(256), 0, R.s, R.dprobs, net->X);
-    });
-    timed(R, K_WS_MLP, [&] {      // the prediction, applied to the node state by the last layer
-        ws_forward(net, pr.T, net->X, R.s, pr.x, R.dprobs);
+    timed(R, K_WS_MLP, [&] {      // features and the prediction, applied to the node state by the last layer
+        hipLaunchKernelGGL(k_ws_layer1_feat, dim3(unsigned((pr.T.nn + 15) / 16)), dim3(512), 0, R.s, R.dprobs, net->X,
+                           net->mu, net->sd, net->wb + kOffW1, net->w + kOffB1, net->Xb, net->z1, net->c1);
+        ws_forward(net, pr.T, nullptr, R.s, pr.x, R.dprobs);
     });
     launch_linearize(R, 0, 0, 1 | 4, prev_slot, params->gn_iters);      // energy test and selection
     timed(R, K_LIN, [&] {

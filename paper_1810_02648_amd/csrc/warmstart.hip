@@ -426,6 +426,80 @@ __global__ __launch_bounds__(256) void k_ws_features(const ProbDev *__restrict__
 }
 
 
+// The learned start's first layer with its features formed in place: one
+// 8-wave workgroup per 16 nodes.  The first 256 threads form the mean node
+// position exactly as k_ws_features does (the same strided sums and tree), 16
+// threads form their nodes' features (into LDS, and into X as k_ws_features
+// would), and the layer then proceeds as k_ws_layer1 on those values: the
+// same numbers as the two launches, with one launch and no round trip
+// through X.
+__global__ __launch_bounds__(kLayerThreads) void k_ws_layer1_feat(const ProbDev *__restrict__ P, float *__restrict__ X,
+                                                                  const float *__restrict__ mu,
+                                                                  const float *__restrict__ sd,
+                                                                  const uint16_t *__restrict__ W,
+                                                                  const float *__restrict__ bias,
+                                                                  uint16_t *__restrict__ Xb, float *__restrict__ z,
+                                                                  uint16_t *__restrict__ cat) {
+    static_assert(kLayerThreads / 64 == 8 && kLayerThreads >= 256, "one output tile per wave; 256 threads for the mean");
+    __shared__ float part[3][256];
+    __shared__ float mean[3];
+    __shared__ float Xs[16][32];
+    __shared__ uint16_t As[16][32 + 8];
+    const ProbDev &pr = *P;
+    const int nn = pr.T.nn;
+    const CAP_GLOBAL float *__restrict__ prev2 = pr.prev2.g();
+    const int i0 = blockIdx.x * 16, t = threadIdx.x;
+    const int wv = t >> 6, lane = t & 63, r = lane & 15;
+    s4v bw[2];
+    load_wfrag<32>(W, wv * 16 + r, 128, bw);
+    WsNodeIn in;
+    const int kn = i0 + t;
+    if (t < 16 && kn < nn) ws_node_load(pr, prev2, nn, kn, in);
+    {   // mean node position, as in k_ws_features
+        float sacc[3] = {0.0f, 0.0f, 0.0f};
+        if (t < 256)
+            for (int k = t; k < nn; k += 256)
+                for (int a = 0; a < 3; ++a) sacc[a] += pr.gpos[size_t(a) * nn + k];
+        if (t < 256)
+            for (int a = 0; a < 3; ++a) part[a][t] = sacc[a];
+        __syncthreads();
+        for (int h = 128; h > 0; h >>= 1) {
+            if (t < h)
+                for (int a = 0; a < 3; ++a) part[a][t] += part[a][t + h];
+            __syncthreads();
+        }
+        if (t < 3) mean[t] = part[t][0] / float(nn);
+        __syncthreads();
+    }
+    if (t < 16 && kn < nn) {
+        const float m[3] = {mean[0], mean[1], mean[2]};
+        ws_node_features(in, prev2 != nullptr, m, Xs[t]);
+#pragma unroll
+        for (int q = 0; q < 32; ++q) X[size_t(kn) * 32 + q] = Xs[t][q];
+    }
+    __syncthreads();
+    for (int idx = t; idx < 16 * 32; idx += blockDim.x) {      // standardised, as k_ws_layer1
+        const int rr = idx >> 5, k = idx & 31, i = i0 + rr;
+        uint16_t b = 0;
+        if (i < nn) {
+            b = f2bf(k < 27 ? (Xs[rr][k] - mu[k]) / sd[k] : 0.0f);
+            Xb[size_t(i) * 32 + k] = b;
+        }
+        As[rr][k] = b;
+    }
+    lds_barrier();
+    const f4v acc = tile_mfma<32>(As, bw);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int i = i0 + (lane >> 4) * 4 + q, j = wv * 16 + r;
+        if (i < nn) {
+            const float v = acc[q] + bias[j];
+            z[size_t(i) * 128 + j] = v;
+            cat[size_t(i) * 256 + j] = f2bf(v > 0.0f ? v : 0.0f);
+        }
+    }
+}
+
 // Training target: per node (dw, dt) with R_next = Exp(dw) R_prev and
 // t_next = t_prev + dt, divided by (0.05 rad, 0.01 m); layout [nn][6].
 __global__ void k_ws_target(const float *__restrict__ prev, const float *__restrict__ next, int nn,
