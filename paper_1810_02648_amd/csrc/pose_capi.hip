@@ -13,7 +13,6 @@ namespace cap {
 
 int build_topology_template(const int *tri_dev, int nv, int nf, capture_template **out, int device);
 
-__global__ void k_fill_u32(uint32_t *p, size_t n, uint32_t v);
 __global__ void k_contour(const ProbDev *P);
 __global__ void k_dt_seg(const ProbDev *P);
 __global__ void k_prep_raster(const ProbDev *P, int nb_f, int scan);
@@ -21,7 +20,7 @@ __global__ void k_prep_cols(const ProbDev *P);
 __global__ void k_prep_rows(const ProbDev *P, int nb_rows);
 __global__ void k_decide(const ProbDev *P);
 __global__ void k_pose_fk(const PoseDev *P);
-__global__ void k_pose_lbs(const PoseDev *P, const ProbDev *R);
+__global__ void k_pose_lbs(const PoseDev *P, const ProbDev *R, int nbv);
 __global__ void k_pose_list(const PoseDev *P);
 __global__ void k_pose_rows(const PoseDev *P, int energy_only);
 __global__ void k_pose_jtj(const PoseDev *P);
@@ -196,10 +195,10 @@ int launch_pose_decisions(PoseRun &P) {
     hipStream_t s = R.s;
     const ProbDev &pr = R.probs[0];
     const size_t hw = size_t(pr.W) * pr.H;
-    hipLaunchKernelGGL(k_fill_u32, dim3(blocks(hw, 256)), dim3(256), 0, s, pr.zbuf, hw, 0u);
-    timed(R, K_POSE_LBS, [&] {           // (the skinning also zeroes the counters)
+    timed(R, K_POSE_LBS, [&] {           // (the skinning also zeroes the counters and clears the depth buffer)
+        const int nbv = int(blocks(pr.T.nv, 256));
         hipLaunchKernelGGL(k_pose_fk, dim3(1), dim3(64), 0, s, P.dpose);
-        hipLaunchKernelGGL(k_pose_lbs, dim3(blocks(pr.T.nv, 256)), dim3(256), 0, s, P.dpose, R.dprobs);
+        hipLaunchKernelGGL(k_pose_lbs, dim3(nbv + int(blocks(hw, 2048))), dim3(256), 0, s, P.dpose, R.dprobs, nbv);
     });
     const dim3 gpx(blocks(hw, 256));
     timed(R, K_CONTOUR, [&] { hipLaunchKernelGGL(k_contour, gpx, dim3(256), 0, s, R.dprobs); });

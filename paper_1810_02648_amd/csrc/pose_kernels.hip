@@ -129,7 +129,16 @@ __global__ __launch_bounds__(64) void k_pose_fk(const PoseDev *__restrict__ PP) 
 
 // Linear blend skinning of the start pose, float32 recipe:
 // d = v - J_j; q_a = (R_a0 d0 + R_a1 d1) + R_a2 d2; acc_a = acc_a + w (q_a + p_j,a).
-__global__ __launch_bounds__(256) void k_pose_lbs(const PoseDev *__restrict__ PP, const ProbDev *__restrict__ PR) {
+// Blocks from nbv on clear the depth buffer instead (2,048 pixels each).
+__global__ __launch_bounds__(256) void k_pose_lbs(const PoseDev *__restrict__ PP, const ProbDev *__restrict__ PR,
+                                                  int nbv) {
+    if (int(blockIdx.x) >= nbv) {
+        const size_t hw = size_t(PR->W) * PR->H, q0 = size_t(blockIdx.x - nbv) * 2048 + threadIdx.x;
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+            if (q0 + size_t(u) * 256 < hw) PR->zbuf[q0 + size_t(u) * 256] = 0u;
+        return;
+    }
     const PoseDev &P = *PP;
     const BodyDev &B = P.B;
     if (blockIdx.x == 0 && threadIdx.x < 3) PR->counts[threadIdx.x] = 0;     // visible, contour, large-face queue
