@@ -80,8 +80,9 @@ CAPTURE_API const char *capture_last_error(void);
  *                                 index), -1 when fewer exist
  * Squared distances use one float32 recipe ((dx*dx + dy*dy) + dz*dz) so the
  * indices are reproducible bit for bit.  Requires 4 <= n_nodes <= n_vertices
- * and n_nodes <= 65536.  Synchronous.  Set-up, not per frame: the call allocates
- * and frees a device scratch of 4 * n_vertices bytes.
+ * and n_nodes <= 65536.  Synchronous (one kernel launch per node for the
+ * sampling).  Set-up, not per frame: the call allocates and frees a device
+ * scratch of about 4 * n_vertices bytes (plus 4 KiB of per-workgroup partials).
  * ------------------------------------------------------------------------ */
 CAPTURE_API int capture_graph_build(capture_ctx *ctx, const float *xyz, int32_t n_vertices, int32_t n_nodes,
                         int32_t *node_vertex, int32_t *bind_idx, float *bind_w, int32_t *edge_dst,
