@@ -99,12 +99,13 @@ def test_distance_transform_edge_cases(ctx, frames):
         assert np.array_equal(out["dt"].cpu().numpy().view(np.uint32), ref.view(np.uint32))
 
 
-@pytest.mark.parametrize("W", [8, 17, 31, 32, 33, 64, 600])
+@pytest.mark.parametrize("W", [8, 17, 31, 32, 33, 64, 600, 2048, 4096])
 def test_distance_transform_row_widths(ctx, frames, W):
     """Row pass at widths where its anchor pixels coincide (W <= 32: every
     pixel an anchor, the last ones repeated), where the last anchors repeat
-    the last pixel (33) and where the intervals hold many pixels (600); masks of
-    random blobs with empty rows, bit-exact against the oracle."""
+    the last pixel (33), where the intervals hold many pixels (600, 2048) and
+    at the largest image side (4096, where no integer term may leave 32 bits);
+    masks of random blobs with empty rows, bit-exact against the oracle."""
     import dataclasses
     import paper_1810_02648_amd as cap
     from gpu_util import make_frame
