@@ -62,6 +62,21 @@ def test_graph_build_many_vertices_per_thread(ctx):
     assert np.array_equal(g["edge_dst"].cpu().numpy(), ref["edge_dst"])
 
 
+@pytest.mark.parametrize("nv,nn", [(300, 4), (300, 300), (257, 257)])
+def test_graph_build_node_count_limits(ctx, nv, nn):
+    """Farthest-point sampling at the smallest node count and with every vertex a
+    node (the last selections decided by the lowest-index rule), against the oracle."""
+    import paper_1810_02648_amd as cap
+    from gpu_util import dev
+    rng = np.random.default_rng(nv + nn)
+    xyz = rng.standard_normal((3, nv)).astype(np.float32)
+    ref = og.build_graph(xyz, nn)
+    g = cap.graph_build(ctx, dev(xyz), nn)
+    assert np.array_equal(g["node_vertex"].cpu().numpy(), ref["node_vertex"])
+    assert np.array_equal(g["bind_idx"].cpu().numpy(), ref["bind_idx"])
+    assert np.array_equal(g["edge_dst"].cpu().numpy(), ref["edge_dst"])
+
+
 @pytest.mark.parametrize("name", ["small0", "small1", "mid"])
 def test_frame_decisions_bit_exact(ctx, frames, name):
     import paper_1810_02648_amd as cap
