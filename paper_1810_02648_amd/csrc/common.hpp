@@ -164,7 +164,7 @@ struct ProbDev {
     gptr<double> cg;       // [8]: (gamma, alpha) of two PCG launches, generation of the final x, b.b
     gptr<double> nsum;     // [2][2][node blocks] per-block r.u and r.r of two node steps (standard PCG)
     gptr<int> counts;      // [3] visible, contour set, queued large faces
-    gptr<int> bigq;        // [nf] faces rasterised by k_raster_big
+    gptr<int> bigq;        // [nf] faces left to the large-face pass
     gptr<float> state0;    // [12][nn] copy of the start state (restored on a device-detected error)
     double target;    // stop once the energy at the start of a GN step is <= target (-inf: never)
     gptr<const float> prev2;   // [12][nn] state two frames back (warm-start features), or null

@@ -148,8 +148,6 @@ __device__ inline void dt_scan_body(const ProbDev &pr, int bx) {
     }
 }
 
-__global__ __launch_bounds__(256) void k_dt_scan(const ProbDev *__restrict__ P) { dt_scan_body(P[blockIdx.y], blockIdx.x); }
-
 // The same with one thread per column (coalesced across columns), in one pass
 // down and one up; segments are read kScanBatch at a time into registers, so
 // the loads of a batch are in flight together.  Used when the frames have
@@ -215,8 +213,6 @@ __device__ inline void dt_cols_body(const ProbDev &pr, int bx) {
         if (y0 + k < y1) pr.colg[size_t(y0 + k) * W + x] = dd < d[k] ? dd : d[k];
     }
 }
-
-__global__ void k_dt_cols(const ProbDev *__restrict__ P) { dt_cols_body(P[blockIdx.y], blockIdx.x); }
 
 // Phase 2: per row, D(x) = min over x' of (x - x')^2 + G(x'), G = g^2, exact.
 // With H(x') = G(x') + x'^2 the value is x^2 + H(x') - 2 x x'.  The matrix of
@@ -306,8 +302,6 @@ __device__ inline void dt_rows_body(const ProbDev &pr, int y) {
         out[x] = best >= far2 ? 0.0f : sqrtf(float(best));
     }
 }
-
-__global__ __launch_bounds__(256) void k_dt_rows(const ProbDev *__restrict__ P) { dt_rows_body(P[blockIdx.y], blockIdx.x); }
 
 // ---------------------------------------------------------------- start-state geometry
 // Embedded deformation at the start state, float32 recipe, then projection
@@ -439,7 +433,7 @@ __device__ inline void tri_pixel(const ProbDev &pr, const TriRaster &s, long lon
 
 // Per face: cross product (for normals), then rasterise the inverse depth.
 // A face whose pixel box holds more than kRasterSmall pixels is queued for
-// k_raster_big instead, so one thread never walks a large box.
+// the large-face pass instead, so one thread never walks a large box.
 __device__ inline void raster_body(const ProbDev &pr, int bx) {
     const TemplateDev &T = pr.T;
     const int nv = T.nv, nf = T.nf;
@@ -471,8 +465,6 @@ __device__ inline void raster_body(const ProbDev &pr, int bx) {
     for (long long j = s.j0; j <= s.j1; ++j)
         for (long long i = s.i0; i <= s.i1; ++i) tri_pixel(pr, s, i, j);
 }
-
-__global__ void k_raster(const ProbDev *__restrict__ P) { raster_body(P[blockIdx.y], blockIdx.x); }
 
 // Queued large faces: one workgroup per face at a time, threads over its pixel box.
 __device__ inline void raster_big_body(const ProbDev &pr, int bx, int nbx) {
@@ -529,10 +521,6 @@ __global__ __launch_bounds__(256) void k_part_labels_big(const ProbDev *__restri
     }
 }
 
-__global__ __launch_bounds__(256) void k_raster_big(const ProbDev *__restrict__ P) {
-    raster_big_body(P[blockIdx.y], blockIdx.x, gridDim.x);
-}
-
 // Per mesh edge: contour edge when its faces' facing differs (a border edge
 // when its one face is front-facing); marks both endpoints.
 __device__ inline void contour_edges_body(const ProbDev &pr, int bx) {
@@ -557,8 +545,6 @@ __device__ inline void contour_edges_body(const ProbDev &pr, int bx) {
         pr.vcont[b] = 1;
     }
 }
-
-__global__ void k_contour_edges(const ProbDev *__restrict__ P) { contour_edges_body(P[blockIdx.y], blockIdx.x); }
 
 // ---------------------------------------------------------------- per-frame set-up
 // Scalars and counters (block 0), the start-state copy and the node positions
